@@ -1,0 +1,105 @@
+/*
+ * Plain FP64 CPU oracle of the electromagnetic PIC timestep (λPIC, arXiv 2607.13507).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP product path; only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant with the GPU library.
+ *
+ * What it computes follows the paper:
+ *   - Maxwell's equations in the Yee discretisation, each field advance split into two
+ *     half steps (Sec. 3.2, Eqs. 1-4), in normalised units c = eps0 = 1;
+ *   - the per-step order of Algorithm 1 (Sec. 3.3): E half, B half, per species
+ *     {position half push, interpolation, Boris momentum push, position half push,
+ *     Esirkepov deposit}, then B half, E half;
+ *   - the relativistic Boris push with u = gamma v (Sec. 3.1);
+ *   - staggering-aware interpolation with a B-spline shape of order 1 (CIC) or 2
+ *     (quadratic) (Sec. 3.1);
+ *   - Esirkepov's charge-conserving current deposition (Sec. 3.1, Esirkepov 2001).
+ * Positions are absolute FP64 coordinates.  Every boundary is periodic.
+ *
+ * Grid layout: one array per component, ncell = nx*ny*nz entries (nz = 1 in 2D), index
+ * (k*ny + j)*nx + i, no guard cells (periodicity by index wrap).  Staggering of the array
+ * entry [i,j,k] (in units of the cell size, 2D drops z):
+ *   Ex (i+1/2, j, k)   Ey (i, j+1/2, k)   Ez (i, j, k+1/2)   (Ez at (i,j) in 2D)
+ *   Bx (i, j+1/2, k+1/2)  By (i+1/2, j, k+1/2)  Bz (i+1/2, j+1/2, k)
+ *   Jx, Jy, Jz as Ex, Ey, Ez;  rho at (i, j, k).
+ */
+#ifndef LPIC_ORACLE_H
+#define LPIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t nx, ny, nz;    /* cells; nz = 1 when ndim == 2 */
+  double dx, dy, dz, dt;
+  double rho_bg;         /* fixed neutralising background charge density (added in Gauss) */
+} orc_grid;
+
+typedef struct {
+  double *ex, *ey, *ez, *bx, *by, *bz, *jx, *jy, *jz;
+  double *rho0, *rho1;   /* optional (NULL): charge at the start / end of the step */
+} orc_fields;
+
+typedef struct {
+  int64_t n;             /* number of particles */
+  double q, m;           /* charge and mass in units of e and m_e */
+  int32_t order;         /* 1 = CIC, 2 = quadratic */
+  double *x, *y, *z;     /* absolute positions; z unused (may be NULL) in 2D; x < 0 = dead */
+  double *ux, *uy, *uz;  /* u = gamma v / c */
+  double *w;             /* weight = density carried by the macro-particle */
+} orc_species;
+
+/* One-dimensional B-spline shape of the given order evaluated at xi (cell units). */
+double orc_shape(int32_t order, double xi);
+
+/* Relativistic Boris push of one momentum u[3] by dt in fields E, B (Sec. 3.1). */
+void orc_boris(double u[3], const double E[3], const double B[3], double q, double m, double dt);
+
+/* Interpolate the six field components at absolute position pos[] with shape `order`. */
+void orc_gather(const orc_grid *g, const orc_fields *f, int32_t order, const double pos[3],
+                double E[3], double B[3]);
+
+/* Half (or any fraction) field updates, Eqs. 3-4 in normalised units. */
+void orc_yee_e(const orc_grid *g, orc_fields *f, double frac);   /* E += frac*dt*(curl B - J) */
+void orc_yee_b(const orc_grid *g, orc_fields *f, double frac);   /* B -= frac*dt*curl E */
+
+/* Esirkepov deposit of one particle moving from p0 to p1 (absolute, unwrapped), adding
+ * J into f.  vz_bar is the mean z velocity used for Jz in 2D (ignored in 3D). */
+void orc_deposit_particle(const orc_grid *g, orc_fields *f, int32_t order, double q, double w,
+                          const double p0[3], const double p1[3], double vz_bar);
+
+/* Add q*w*S(pos - node) into rho at the integer nodes. */
+void orc_deposit_rho(const orc_grid *g, double *rho, int32_t order, double q, double w,
+                     const double pos[3]);
+
+/* Particle part of Algorithm 1 for one species: half position push, gather, Boris, half
+ * position push, Esirkepov deposit into J (J is NOT zeroed here), optional rho0/rho1
+ * deposits, periodic wrap.  If x0/y0/z0/vz0 are non-NULL they receive the start position
+ * and start z velocity of every particle (for separate deposit checks). */
+void orc_push_deposit(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
+                      double *x0, double *y0, double *z0, double *vz0);
+
+/* Gather + push only (no deposit); positions are wrapped. */
+void orc_gather_push(const orc_grid *g, const orc_fields *f, orc_species *s);
+
+/* One full timestep of Algorithm 1 over all species. */
+void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies);
+
+/* Diagnostics (all FP64).  dV is the cell volume (dx*dy or dx*dy*dz). */
+double orc_field_energy(const orc_grid *g, const orc_fields *f);
+double orc_kinetic_energy(const orc_grid *g, const orc_species *s);
+/* max |rho1 - rho0 + dt div J| / max |rho1| */
+double orc_continuity(const orc_grid *g, const orc_fields *f);
+/* G = div E - (rho0 + rho1)/2 - rho_bg at every node, written into out[ncell]. */
+void orc_gauss(const orc_grid *g, const orc_fields *f, double *out);
+/* div B at the cell centres (i+1/2, j+1/2, k+1/2), written into out[ncell]. */
+void orc_div_b(const orc_grid *g, const orc_fields *f, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,304 @@
+"""Seeded synthetic inputs for the PIC hot path.
+
+This module only draws random numbers and lays out particle lists and initial fields; it
+holds none of the method's arithmetic (no shape function, push, deposit or field solve), so
+both the HIP path and the FP64 oracle can take their inputs from it.
+
+Units are normalised (c = eps0 = m_e = e = 1); for laser workloads the reference frequency
+is the laser's, so the wavelength is 2*pi, the critical density is 1 and a0 is the peak
+field.  A macro-particle carries the weight w = n / ppc (a density), positions are absolute
+FP64 coordinates, momenta are u = gamma v.
+
+Recipes (configuration names follow the workloads they model):
+  thermal_2d      2D3V periodic uniform electron plasma on a fixed ion background,
+                  Gaussian momenta sigma = sqrt(T/m) per component, random in-cell positions
+  laser_slab_2d   2D3V fully ionised hydrogen slab (electrons + protons) with a linearly
+                  polarised Gaussian pulse initialised in the vacuum region in front of it
+  thermal_3d      3D3V periodic uniform electron plasma on a fixed ion background
+  ensemble_2d     many independent laser-slab runs of mixed sizes drawn from one seed
+  wakefield_2d    underdense electron plasma filling a long box, fixed ions, Gaussian pulse
+  cold_langmuir   cold electron lattice with a sinusoidal velocity perturbation
+  vacuum_mode     one Fourier mode of the vacuum field, no particles
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+M_PROTON = 1836.15267343
+LAMBDA = 2.0 * math.pi          # laser wavelength in units of c / omega_L
+T_1KEV = 1.0 / 510.99895        # 1 keV in units of m_e c^2
+
+
+@dataclass
+class SpeciesInit:
+    name: str
+    q: float
+    m: float
+    order: int                  # 1 = CIC, 2 = quadratic
+    x: np.ndarray
+    y: np.ndarray
+    z: Optional[np.ndarray]
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    w: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    ndim: int
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    dt: float
+    rho_bg: float
+    species: List[SpeciesInit]
+    fields: Dict[str, np.ndarray] = field(default_factory=dict)   # initial E, B (flat, x fastest)
+    steps: int = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * (self.nz if self.ndim == 3 else 1)
+
+    @property
+    def nparticles(self) -> int:
+        return sum(s.n for s in self.species)
+
+    def box(self):
+        return (self.nx * self.dx, self.ny * self.dy, self.nz * self.dz)
+
+
+def cfl_dt(eta: float, *h: float) -> float:
+    """Time step eta / (c sqrt(sum h^-2)), the CFL form stated in Sec. 3.2."""
+    return eta / math.sqrt(sum(1.0 / (v * v) for v in h))
+
+
+# ----------------------------------------------------------------------------------------
+# building blocks
+# ----------------------------------------------------------------------------------------
+def _random_in_cells(rng, cells_x, cells_y, cells_z, ppc, dx, dy, dz):
+    """ppc particles uniformly at random inside each listed cell (C-order cell lists)."""
+    nc = cells_x.shape[0]
+    ix = np.repeat(cells_x, ppc)
+    iy = np.repeat(cells_y, ppc)
+    x = (ix + rng.random(nc * ppc)) * dx
+    y = (iy + rng.random(nc * ppc)) * dy
+    z = None
+    if cells_z is not None:
+        iz = np.repeat(cells_z, ppc)
+        z = (iz + rng.random(nc * ppc)) * dz
+    # a draw of exactly 1.0 cannot happen (rng.random is in [0, 1)), but rounding of
+    # (i + r) * dx at the top cell can reach the box edge: fold it back
+    return x, y, z
+
+
+def _cell_lists_2d(x0, x1, y0, y1):
+    jj, ii = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+    return ii.reshape(-1), jj.reshape(-1)
+
+
+def _thermal_species(rng, name, q, m, order, x, y, z, T, density, ppc):
+    n = x.shape[0]
+    sig = math.sqrt(T / m) if T > 0 else 0.0
+    ux = rng.normal(0.0, sig, n) if sig > 0 else np.zeros(n)
+    uy = rng.normal(0.0, sig, n) if sig > 0 else np.zeros(n)
+    uz = rng.normal(0.0, sig, n) if sig > 0 else np.zeros(n)
+    w = np.full(n, density / ppc)
+    return SpeciesInit(name, q, m, order, x, y, z, ux, uy, uz, w)
+
+
+def _fold(a, L):
+    a = np.where(a >= L, a - L, a)
+    return np.where(a < 0, a + L, a)
+
+
+def gaussian_pulse_fields(nx, ny, dx, dy, a0, x_lo, x_hi, waist, y_centre):
+    """Linearly polarised (E along y) pulse moving in +x, laid out on the Yee stagger:
+    Ey(x,y) = a0 sin^2(pi (x - x_lo)/(x_hi - x_lo)) exp(-((y - yc)/waist)^2) sin(x), Bz = Ey
+    evaluated at Bz's own location; zero outside [x_lo, x_hi)."""
+    def profile(xs, ys):
+        inside = (xs >= x_lo) & (xs < x_hi)
+        env = np.where(inside, np.sin(math.pi * (xs - x_lo) / (x_hi - x_lo)) ** 2, 0.0)
+        return a0 * env * np.exp(-((ys - y_centre) / waist) ** 2) * np.sin(xs)
+
+    i = np.arange(nx)
+    j = np.arange(ny)
+    # Ey at (i, j+1/2), Bz at (i+1/2, j+1/2)
+    Y, X = np.meshgrid((j + 0.5) * dy, i * dx, indexing="ij")
+    ey = profile(X, Y)
+    Y, X = np.meshgrid((j + 0.5) * dy, (i + 0.5) * dx, indexing="ij")
+    bz = profile(X, Y)
+    return {"ey": ey.reshape(-1), "bz": bz.reshape(-1)}
+
+
+# ----------------------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------------------
+def thermal_2d(nx=64, ny=64, dx=0.05, ppc=16, T=0.01, density=1.0, order=1, seed=1,
+               eta=0.95, steps=100, name="thermal_2d") -> Workload:
+    """2D3V periodic uniform electrons on a fixed neutralising ion background (defaults:
+    64x64, dx = dy = 0.05 c/omega_p, 16 ppc, T = 0.01 m c^2, CIC, 100 steps)."""
+    rng = np.random.default_rng(seed)
+    cx, cy = _cell_lists_2d(0, nx, 0, ny)
+    x, y, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
+    x, y = _fold(x, nx * dx), _fold(y, ny * dx)
+    e = _thermal_species(rng, "electron", -1.0, 1.0, order, x, y, None, T, density, ppc)
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, +density, [e], {}, steps,
+                    dict(ppc=ppc, T=T, density=density, order=order, seed=seed))
+
+
+def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), density=20.0,
+                  ppc=32, T=T_1KEV, a0=10.0, order=2, seed=2, eta=0.95, steps=2000,
+                  pulse_cells=None, waist_lambda=6.25, name="laser_slab_2d") -> Workload:
+    """2D3V hydrogen slab (electrons + protons, `ppc` each) of `density` n_c in cells
+    [slab[0], slab[1]) over the whole y extent, with a Gaussian pulse of peak a0 in the
+    vacuum in front of it (x in [0, pulse_cells) cells, sin^2 envelope over that span)."""
+    rng = np.random.default_rng(seed)
+    dx = LAMBDA / cells_per_lambda
+    cx, cy = _cell_lists_2d(slab[0], slab[1], 0, ny)
+    xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
+    xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
+    e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
+    xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
+    xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
+    p = _thermal_species(rng, "proton", +1.0, M_PROTON, order, xs, ys, None, T, density, ppc)
+    if pulse_cells is None:
+        pulse_cells = min(slab[0], nx)
+    flds = {}
+    if a0 > 0 and pulse_cells > 0:
+        flds = gaussian_pulse_fields(nx, ny, dx, dx, a0, 0.0, pulse_cells * dx,
+                                     waist_lambda * LAMBDA, 0.5 * ny * dx)
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [e, p], flds, steps,
+                    dict(ppc=ppc, T=T, density=density, order=order, seed=seed, a0=a0,
+                         slab=slab, pulse_cells=pulse_cells))
+
+
+def thermal_3d(n=256, dx=0.1, ppc=8, T=0.05, density=1.0, order=2, seed=3, eta=0.95,
+               steps=200, name="thermal_3d") -> Workload:
+    """3D3V periodic uniform electrons on a fixed ion background (defaults 256^3, 8 ppc,
+    T = 0.05 m c^2, quadratic)."""
+    rng = np.random.default_rng(seed)
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    x, y, z = _random_in_cells(rng, ii.reshape(-1), jj.reshape(-1), kk.reshape(-1), ppc,
+                               dx, dx, dx)
+    L = n * dx
+    x, y, z = _fold(x, L), _fold(y, L), _fold(z, L)
+    e = _thermal_species(rng, "electron", -1.0, 1.0, order, x, y, z, T, density, ppc)
+    dt = cfl_dt(eta, dx, dx, dx)
+    return Workload(name, 3, n, n, n, dx, dx, dx, dt, +density, [e], {}, steps,
+                    dict(ppc=ppc, T=T, density=density, order=order, seed=seed))
+
+
+def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
+                sizes_y=(128, 256, 512), cells_per_lambda=32, eta=0.95, steps=20):
+    """Independent 2D3V laser-slab runs drawn from one seed: nx >= ny from the listed sizes,
+    ppc per species from {4, 8, 16, 32}, slab density log-uniform in [0.1, 10] n_c filling
+    the right half, a0 log-uniform in [0.5, 20], CIC or quadratic with probability 1/2.
+    All members share dx = lambda/32 and hence dt."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for r in range(members):
+        while True:
+            nx = int(rng.choice(sizes_x))
+            ny = int(rng.choice(sizes_y))
+            if nx >= ny:
+                break
+        nx //= max_scale
+        ny //= max_scale
+        ppc = int(rng.choice([4, 8, 16, 32]))
+        dens = float(10 ** rng.uniform(-1, 1))
+        a0 = float(10 ** rng.uniform(math.log10(0.5), math.log10(20)))
+        order = int(rng.choice([1, 2]))
+        sub = int(rng.integers(0, 2 ** 31 - 1))
+        wl = laser_slab_2d(nx=nx, ny=ny, cells_per_lambda=cells_per_lambda,
+                           slab=(nx // 2, nx), density=dens, ppc=ppc, a0=a0, order=order,
+                           seed=sub, eta=eta, steps=steps, pulse_cells=nx // 2,
+                           waist_lambda=min(6.25, 0.2 * ny / cells_per_lambda),
+                           name=f"ensemble_member_{r}")
+        runs.append(wl)
+    return runs
+
+
+def wakefield_2d(nx=8192, ny=512, cells_per_lambda=40, density=0.01, ppc=4, a0=2.0,
+                 waist_lambda=8.0, order=2, seed=5, eta=0.95, steps=20000, T=0.0,
+                 pulse_cells=None, name="wakefield_2d") -> Workload:
+    """Underdense electrons (fixed ions) filling the box behind an in-box Gaussian pulse."""
+    rng = np.random.default_rng(seed)
+    dx = LAMBDA / cells_per_lambda
+    if pulse_cells is None:
+        pulse_cells = min(nx // 4, 20 * cells_per_lambda)
+    cx, cy = _cell_lists_2d(pulse_cells, nx, 0, ny)
+    xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
+    xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
+    e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
+    flds = gaussian_pulse_fields(nx, ny, dx, dx, a0, 0.0, pulse_cells * dx,
+                                 waist_lambda * LAMBDA, 0.5 * ny * dx)
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, +density, [e], flds, steps,
+                    dict(ppc=ppc, density=density, order=order, seed=seed, a0=a0))
+
+
+def cold_langmuir(nx=64, ny=64, dx=0.05, lattice=4, amp=1e-3, order=1, eta=0.95, steps=1000,
+                  density=1.0, name="cold_langmuir") -> Workload:
+    """Cold electron lattice (lattice x lattice per cell, at sub-cell centres) on a fixed
+    ion background with u_x = amp sin(2 pi x / L)."""
+    cx, cy = _cell_lists_2d(0, nx, 0, ny)
+    sub = (np.arange(lattice) + 0.5) / lattice
+    oy, ox = np.meshgrid(sub, sub, indexing="ij")
+    ox = ox.reshape(-1)
+    oy = oy.reshape(-1)
+    ppc = lattice * lattice
+    x = (np.repeat(cx, ppc) + np.tile(ox, cx.shape[0])) * dx
+    y = (np.repeat(cy, ppc) + np.tile(oy, cy.shape[0])) * dx
+    L = nx * dx
+    n = x.shape[0]
+    ux = amp * np.sin(2 * math.pi * x / L)
+    e = SpeciesInit("electron", -1.0, 1.0, order, x, y, None, ux, np.zeros(n), np.zeros(n),
+                    np.full(n, density / ppc))
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, +density, [e], {}, steps,
+                    dict(amp=amp, lattice=lattice, order=order))
+
+
+def vacuum_mode(nx=64, ny=64, dx=0.05, mx=1, my=1, amp=1.0, eta=0.95, steps=1000,
+                name="vacuum_mode") -> Workload:
+    """Standing mode Ez = amp cos(kx x) cos(ky y), B = 0 (kx = 2 pi mx / Lx, same in y)."""
+    L = nx * dx
+    kx = 2 * math.pi * mx / L
+    ky = 2 * math.pi * my / (ny * dx)
+    Y, X = np.meshgrid(np.arange(ny) * dx, np.arange(nx) * dx, indexing="ij")
+    ez = amp * np.cos(kx * X) * np.cos(ky * Y)
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [], {"ez": ez.reshape(-1)},
+                    steps, dict(kx=kx, ky=ky, amp=amp))
+
+
+def gaussian_pulse_vacuum(nx=2048, ny=1024, cells_per_lambda=32, a0=10.0, steps=1000,
+                          eta=0.95, name="pulse_vacuum") -> Workload:
+    """Vacuum Gaussian pulse on the laser-slab grid (no particles)."""
+    dx = LAMBDA / cells_per_lambda
+    flds = gaussian_pulse_fields(nx, ny, dx, dx, a0, 0.0, min(nx, 16 * cells_per_lambda) * dx,
+                                 6.25 * LAMBDA, 0.5 * ny * dx)
+    dt = cfl_dt(eta, dx, dx)
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [], flds, steps, dict(a0=a0))
+
+
+def random_fields(ncell, seed, scale=1.0, names=("ex", "ey", "ez", "bx", "by", "bz")):
+    """Uniform random field values in [-scale, scale) for unit-level kernel checks."""
+    rng = np.random.default_rng(seed)
+    return {k: scale * (2 * rng.random(ncell) - 1) for k in names}
