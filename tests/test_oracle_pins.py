@@ -371,3 +371,102 @@ def test_p8_cold_plasma_oscillation_frequency():
     assert len(crossings) >= 4
     omega = math.pi * (len(crossings) - 1) / (crossings[-1] - crossings[0])
     assert omega == pytest.approx(1.0, rel=5e-3)
+
+
+# ------------------------------------------------------------- P1/P5 (general geometry)
+def _rodrigues(v, axis, ang):
+    k = axis / np.linalg.norm(axis)
+    return (v * math.cos(ang) + np.cross(k, v) * math.sin(ang) +
+            k * (k @ v) * (1 - math.cos(ang)))
+
+
+@pytest.mark.parametrize("q", [-1.0, 1.0])
+def test_p1_boris_rotation_about_oblique_field(q):
+    """Pure B along an arbitrary axis: u turns about B by 2 atan(|q| |B| dt / (2 m gamma))
+    per step, in the sense of -q B (right-handed rotation for negative charge)."""
+    B = np.array([0.3, -0.5, 0.8]) * 1.7
+    u0 = np.array([0.2, 0.4, -0.1])
+    dt, m = 0.03, 1.0
+    gam = math.sqrt(1 + u0 @ u0)
+    theta = 2 * math.atan(abs(q) * np.linalg.norm(B) * dt / (2 * m * gam))
+    u = u0.copy()
+    for n in range(1, 2001):
+        u = oracle.boris(u, [0, 0, 0], B, q, m, dt)
+    exp = _rodrigues(u0, -q * B, n * theta)
+    np.testing.assert_allclose(u, exp, atol=1e-11)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_p5_esirkepov_anisotropic_3d(order):
+    rng = np.random.default_rng(31)
+    sim = OracleSim(3, 7, 6, 5, 0.11, 0.07, 0.13, 0.03)
+    g = sim.grid
+    h = np.array([g.dx, g.dy, g.dz])
+    for _ in range(15):
+        sim.zero_currents()
+        p0 = rng.uniform(0, 1, 3) * np.array([7 * 0.11, 6 * 0.07, 5 * 0.13])
+        disp = rng.uniform(-0.5, 0.5, 3) * h
+        sim.deposit_particle(order, -1.0, 0.9, p0, p0 + disp, 0.0)
+        sim.deposit_rho(sim.rho0, order, -1.0, 0.9, p0)
+        sim.deposit_rho(sim.rho1, order, -1.0, 0.9, p0 + disp)
+        res = (sim.rho1 - sim.rho0).reshape(5, 6, 7) + g.dt * _divj(sim)
+        assert np.abs(res).max() <= 1e-13
+        for d, k in enumerate(("jx", "jy", "jz")):
+            assert sim.f[k].sum() == pytest.approx(-0.9 * disp[d] / g.dt, abs=1e-12)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_p5_2d_jz_matches_3d_push_in_uniform_fields(order):
+    """A full push in uniform fields: the 3D trapezoidal z displacement fixes the 2D Jz
+    (z-integrated 3D Jz equals the one-cell-thick 2D Jz)."""
+    dx, dt = 0.1, 0.04
+    E = {"ex": 0.2, "ey": -0.3, "ez": 0.9}
+    B = {"bx": 0.7, "by": 0.4, "bz": -0.5}
+    s2 = OracleSim(2, 8, 8, 1, dx, dx, 1.0, dt)
+    s3 = OracleSim(3, 8, 8, 8, dx, dx, dx, dt)
+    for s in (s2, s3):
+        for k, v in {**E, **B}.items():
+            s.f[k][:] = v
+    p = [0.41, 0.37, 0.43]
+    u = [0.3, -0.6, 0.8]
+    a2 = _single(-1.0, 1.0, order, p[:2], u, w=0.5)
+    a3 = _single(-1.0, 1.0, order, p, u, w=0.5)
+    s2.push_deposit(a2)
+    s3.push_deposit(a3)
+    np.testing.assert_allclose([a2.ux[0], a2.uy[0], a2.uz[0]], [a3.ux[0], a3.uy[0], a3.uz[0]],
+                               atol=1e-15)
+    jz3 = s3.f["jz"].reshape(8, 8, 8).sum(axis=0) * dx
+    jz2 = s2.f["jz"].reshape(8, 8) * dx
+    np.testing.assert_allclose(jz3, jz2, atol=1e-13)
+
+
+# ------------------------------------------------------------------ energy diagnostics
+def test_kinetic_energy_special_values():
+    sim = OracleSim(2, 4, 4, 1, 0.2, 0.3, 1.0, 0.05)
+    sim.species = [_single(1.0, W.M_PROTON, 1, [0.1, 0.1], [0.3, 0.0, 0.4], w=2.0),
+                   _single(-1.0, 1.0, 2, [0.1, 0.1], [0.0, 3.0, 0.0], w=0.5)]
+    exp = (2.0 * W.M_PROTON * (math.sqrt(1.25) - 1) + 0.5 * (math.sqrt(10.0) - 1)) * 0.2 * 0.3
+    assert sim.kinetic_energy() == pytest.approx(exp, rel=1e-14)
+    sim.f["ez"][:] = 2.0
+    sim.f["bx"][:] = 1.0
+    assert sim.field_energy() == pytest.approx(0.5 * 16 * 5.0 * 0.2 * 0.3, rel=1e-14)
+
+
+def test_cold_plasma_energy_growth_of_algorithm_1():
+    """For a cold plasma mode the step of Algorithm 1 (velocity at whole steps, E at half
+    steps, current from the trapezoidal path) is the linear map
+        v' = v + a dt F,   F' = F - b dt (v + v')/2          (a b = omega_p^2)
+    whose determinant is 1 + (omega_p dt)^2 / 2, so the oscillation energy grows by that
+    factor every step.  The measured growth rate must match it."""
+    wl = W.cold_langmuir(nx=32, ny=2, dx=0.05, lattice=2, amp=1e-2, order=2, steps=600)
+    sim = OracleSim.from_workload(wl)
+    k0 = sim.kinetic_energy()
+    tot, fe = [], []
+    for _ in range(wl.steps):
+        sim.step()
+        fe.append(sim.field_energy())
+        tot.append(fe[-1] + sim.kinetic_energy())
+    assert max(fe) > 0.9 * k0              # nearly all kinetic energy passes into the field
+    slope = np.polyfit(np.arange(1, wl.steps + 1), np.log(np.array(tot) / k0), 1)[0]
+    predicted = math.log(1 + 0.5 * wl.dt ** 2)
+    assert slope == pytest.approx(predicted, rel=0.1)
