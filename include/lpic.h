@@ -1,0 +1,287 @@
+/*
+ * lpic.h -- C ABI of the MI355X (gfx950) electromagnetic PIC hot path.
+ *
+ * The library advances the particle-in-cell timestep of lambda-PIC (arXiv 2607.13507):
+ * field half updates on the Yee grid, and per species a position half push, staggered
+ * field interpolation, a relativistic Boris momentum push, a second position half push and
+ * Esirkepov's charge-conserving current deposition (Sec. 3.1-3.3, Algorithm 1), with the
+ * per-tile particle sort that keeps the particle stream local to the field tiles.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units are normalised: c = eps0 = 1, charge in e, mass in m_e, u = gamma v / c, so the
+ * Maxwell system of Sec. 3.2 reads dE/dt = curl B - J, dB/dt = -curl E.  A macro-particle
+ * carries a weight w that is the density it contributes, so rho = sum q w S.
+ *
+ * Grid arrays: one array per component, ncell = nx*ny*nz entries (nz = 1 in 2D), index
+ * (k*ny + j)*nx + i, x fastest, NO guard cells: every boundary is periodic and is realised
+ * by wrapping indices inside the kernels (the guard fill after each field half and the
+ * guard fold of J after deposition of Algorithm 1 are therefore implicit).  Staggering of
+ * entry [i,j,k] in cell units: Ex (i+1/2,j,k), Ey (i,j+1/2,k), Ez (i,j,k+1/2) (2D: (i,j)),
+ * Bx (i,j+1/2,k+1/2), By (i+1/2,j,k+1/2), Bz (i+1/2,j+1/2,k); J as E; rho at (i,j,k).
+ *
+ * Precision:
+ *   LPIC_F32_CELLOFS  fields float; particles hold a packed int32 cell coordinate and FP32
+ *                     offsets in [0,1) inside that cell, FP32 momenta and weights.  Cell
+ *                     packing: 2D  cell = iy<<16 | ix          (nx <= 65536, ny <= 32768)
+ *                                 3D  cell = iz<<22 | iy<<11 | ix (nx, ny <= 2048, nz <= 512)
+ *                     A dead particle has cell = -1.
+ *   LPIC_F64_ABS      fields double; particles hold absolute FP64 positions (as the paper's
+ *                     particle arrays do, Sec. 2.1), FP64 momenta and weights.  A dead
+ *                     particle has x < 0.
+ * FP64 is also used, in both modes, for the global energy and continuity reductions.
+ *
+ * Memory: every pointer in the structs below is a DEVICE pointer owned by the caller
+ * (normally a PyTorch tensor); the library never frees it.  Entry points taking a
+ * hipStream_t only enqueue work on that stream and return; errors detectable on the host
+ * (bad sizes, null pointers, unsupported options) are reported before anything is
+ * enqueued.  Functions return an lpic_status; lpic_last_error() gives a thread-local
+ * message for the last failure.  No entry point aborts or throws.
+ */
+#ifndef LPIC_H
+#define LPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LPIC_OK = 0,
+  LPIC_EINVAL = -1,       /* invalid argument (null pointer, bad size, dt above CFL, ...) */
+  LPIC_EHIP = -2,         /* a HIP runtime call failed; lpic_last_error() has the text */
+  LPIC_ENOMEM = -3,       /* device allocation of library scratch failed */
+  LPIC_EUNSUPPORTED = -4, /* valid request the build does not support */
+  LPIC_EHOOK = -5,        /* a registered hook returned non-zero; the step stopped there */
+  LPIC_ENUMERIC = -6      /* NaN or Inf found by a diagnostic reduction */
+} lpic_status;
+
+typedef enum { LPIC_F32_CELLOFS = 0, LPIC_F64_ABS = 1 } lpic_precision;
+
+/* One simulation box (Sec. 3.2).  dt must satisfy the CFL bound
+ * dt <= 1 / sqrt(dx^-2 + dy^-2 [+ dz^-2]). */
+typedef struct {
+  int32_t ndim;              /* 2 or 3 */
+  int32_t nx, ny, nz;        /* cells; nz = 1 for ndim == 2 */
+  double dx, dy, dz, dt;     /* dz ignored in 2D */
+  double rho_bg;             /* fixed uniform background charge density (Gauss diagnostic) */
+} lpic_grid;
+
+/* Field arrays of one box, each ncell elements of float (F32) or double (F64). */
+typedef struct {
+  void *ex, *ey, *ez, *bx, *by, *bz;
+  void *jx, *jy, *jz;
+  void *rho0, *rho1;         /* optional charge at the start / end of the step (may be NULL
+                                unless a call asks for it) */
+} lpic_fields;
+
+/* Particle arrays of one species (Sec. 2.1, structure of arrays), n slots each. */
+typedef struct {
+  int64_t n;                 /* number of slots (alive + dead) */
+  double q, m;               /* charge [e] and mass [m_e] */
+  int32_t shape_order;       /* 1 = CIC (linear), 2 = quadratic spline */
+  int32_t reserved0;
+  int32_t *cell;             /* F32_CELLOFS: packed cell coordinate */
+  void *ox, *oy, *oz;        /* F32_CELLOFS: float offsets; oz unused in 2D */
+  void *x, *y, *z;           /* F64_ABS: double absolute positions; z unused in 2D */
+  void *ux, *uy, *uz, *w;    /* float (F32) or double (F64) */
+} lpic_species;
+
+/* Tiling used by the sort and the fused particle kernel.  Tile edges are powers of two;
+ * the field tile staged in on-chip memory is the tile plus `halo` cells on each side, and
+ * a tile's particles are processed in chunks of at most `chunk` particles per workgroup.
+ * halo must be >= 3; particles that drifted further than halo - 3 cells from their tile
+ * since the last sort are still handled correctly, through global memory. */
+typedef struct {
+  int32_t tx, ty, tz;        /* tz ignored in 2D */
+  int32_t halo;
+  int32_t chunk;
+  int32_t reserved0;
+} lpic_tiling;
+
+/* ---------------------------------------------------------------------------------------
+ * Field solver -- Sec. 3.2 Eqs. 3-4, split into halves as in Algorithm 1.
+ * which = 0: E += frac*dt*(curl B - J);  which = 1: B -= frac*dt*curl E.
+ * flags LPIC_YEE_ZERO_J (which = 0 only): after J has been read, set J (and rho0/rho1 when
+ * non-NULL) to zero, so that a following deposit starts from a clean array.
+ * ------------------------------------------------------------------------------------- */
+#define LPIC_YEE_ZERO_J 1
+lpic_status lpic_yee_update_EB(const lpic_grid *grid, const lpic_fields *fields,
+                               int32_t which, double frac, int32_t flags,
+                               lpic_precision prec, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Gather + push -- Sec. 3.1 and the particle part of Algorithm 1 up to (not including) the
+ * deposit: half position push, interpolation of E and B at the half position, Boris push
+ * of u by dt, second half position push, periodic wrap.  The start position and start
+ * z-velocity of every particle are written into `old_state` (lpic_old_state_bytes() bytes,
+ * caller-owned device memory, layout private to the library) for lpic_deposit_esirkepov.
+ * Fields are read from global memory; no sort is needed.
+ * ------------------------------------------------------------------------------------- */
+size_t lpic_old_state_bytes(int32_t ndim, int64_t n, lpic_precision prec);
+lpic_status lpic_gather_push(const lpic_grid *grid, const lpic_fields *fields,
+                             const lpic_species *sp, void *old_state, size_t old_bytes,
+                             lpic_precision prec, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Esirkepov deposit -- Sec. 3.1 (Esirkepov 2001): adds the current of every particle's
+ * straight path from its position in `old_state` to its present position into jx, jy, jz
+ * (which are NOT cleared).  with_rho != 0 also adds q w S at the start (rho0) and end
+ * (rho1) positions.  In 2D, Jz uses the mean of the start and end z-velocities.
+ * ------------------------------------------------------------------------------------- */
+lpic_status lpic_deposit_esirkepov(const lpic_grid *grid, const lpic_fields *fields,
+                                   const lpic_species *sp, const void *old_state,
+                                   size_t old_bytes, int32_t with_rho, lpic_precision prec,
+                                   hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Tile sort -- Algorithm 1 sorts particles by cell before the push; here particles are
+ * grouped by tile with a counting sort (histogram, scan, scatter) so that each workgroup
+ * of the fused kernel reads one field tile.  Order inside a tile is not specified.  Dead
+ * particles go to the end.  The sorted arrays are written into `alt` (same sizes as `sp`),
+ * then the array pointers of *sp and *alt are exchanged, so *sp describes the sorted data.
+ * tile_offsets (device, int32, ntiles + 2 entries): start of every tile, then the start of
+ * the dead block, then n.  ws: caller-owned device scratch of lpic_sort_ws_bytes() bytes.
+ * ------------------------------------------------------------------------------------- */
+size_t lpic_sort_ws_bytes(const lpic_grid *grid, const lpic_tiling *tiling, int64_t n);
+int64_t lpic_num_tiles(const lpic_grid *grid, const lpic_tiling *tiling);
+lpic_status lpic_sort_tiles(const lpic_grid *grid, lpic_species *sp, lpic_species *alt,
+                            const lpic_tiling *tiling, int32_t *tile_offsets, void *ws,
+                            size_t ws_bytes, lpic_precision prec, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Fused gather + push + deposit -- the unified pusher of Sec. 2.3 / Sec. 3.3: one pass
+ * over the particles of a species that does everything lpic_gather_push and
+ * lpic_deposit_esirkepov do, with the field tile staged on chip and the current of a tile
+ * accumulated on chip before one atomic flush.  Requires the particle order produced by
+ * lpic_sort_tiles with the same tiling (tile_offsets from that call); particles that have
+ * since left their tile are still handled exactly.  with_rho as in the deposit.
+ * kinetic (device double, may be NULL): adds sum w m u^2/(1+gamma) over the pushed
+ * particles (new momenta, not multiplied by the cell volume).
+ * ------------------------------------------------------------------------------------- */
+size_t lpic_fused_ws_bytes(const lpic_grid *grid, const lpic_tiling *tiling, int64_t n);
+lpic_status lpic_push_deposit_fused(const lpic_grid *grid, const lpic_fields *fields,
+                                    const lpic_species *sp, const lpic_tiling *tiling,
+                                    const int32_t *tile_offsets, void *ws, size_t ws_bytes,
+                                    int32_t with_rho, double *kinetic, lpic_precision prec,
+                                    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Position representation (input/output plumbing, not part of the step): convert absolute
+ * FP64 positions (device arrays x, y, z) into the species' representation and back.
+ * ------------------------------------------------------------------------------------- */
+lpic_status lpic_load_positions(const lpic_grid *grid, const lpic_species *sp,
+                                const double *x, const double *y, const double *z,
+                                lpic_precision prec, hipStream_t stream);
+lpic_status lpic_store_positions(const lpic_grid *grid, const lpic_species *sp, double *x,
+                                 double *y, double *z, lpic_precision prec,
+                                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * FP64 field diagnostics (energy of Sec. 4.1, continuity of Sec. 3.1).  Writes into
+ * out (device, 4 doubles, overwritten):
+ *   out[0] = sum (E^2 + B^2)/2 * dV                 field energy
+ *   out[1] = max |rho1 - rho0 + dt div J|           continuity residual (needs rho0, rho1)
+ *   out[2] = max |rho1|
+ *   out[3] = max |div E - (rho0 + rho1)/2 - rho_bg|  Gauss residual (needs rho0, rho1)
+ * Accumulation is FP64 whatever the field precision.
+ * ------------------------------------------------------------------------------------- */
+lpic_status lpic_reduce_fields(const lpic_grid *grid, const lpic_fields *fields,
+                               int32_t with_rho, double *out, lpic_precision prec,
+                               hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Orchestration: Algorithm 1 over one box (or an ensemble of independent boxes) with
+ * named-stage hooks (Sec. 2.2, Sec. 3.3).
+ * ------------------------------------------------------------------------------------- */
+typedef struct lpic_sim lpic_sim;
+
+typedef enum {
+  LPIC_STAGE_START = 0,             /* once, before the first step of a call */
+  LPIC_STAGE_LOOP_START = 1,        /* start of every step */
+  LPIC_STAGE_MAXWELL_1 = 2,         /* after the first field half update */
+  LPIC_STAGE_PUSH_POSITION_1 = 3,   /* intermediate particle stages: registering a hook at */
+  LPIC_STAGE_INTERPOLATOR = 4,      /* any of these four disables the fused kernel and   */
+  LPIC_STAGE_PUSH_MOMENTUM = 5,     /* graph capture (the unified-pusher rule of          */
+  LPIC_STAGE_PUSH_POSITION_2 = 6,   /* Sec. 2.3); they fire per species, between the      */
+                                    /* split gather-push and deposit calls                 */
+  LPIC_STAGE_CURRENT_DEPOSITION = 7,/* after all species deposited */
+  LPIC_STAGE_QED_CREATE = 8,        /* reserved (no QED in this library) */
+  LPIC_STAGE_MAXWELL_2 = 9,         /* after the second field half update */
+  LPIC_STAGE_LOOP_END = 10,         /* end of every step */
+  LPIC_STAGE_FINISH = 11,           /* once, after the last step of a call */
+  LPIC_NUM_STAGES = 12
+} lpic_stage;
+
+/* A hook runs on the host between enqueued kernels; it may enqueue its own work on the
+ * simulation's stream and may read or change any field or particle array.  Returning
+ * non-zero stops lpic_step with LPIC_EHOOK. */
+typedef int (*lpic_hook_fn)(lpic_sim *sim, int32_t stage, int64_t step, void *user);
+
+typedef struct {
+  lpic_tiling tiling;        /* tile shape, halo and chunk size (all runs) */
+  int32_t sort_interval;     /* re-sort every K steps (>= 1) */
+  int32_t diag_interval;     /* FP64 diagnostics every D steps (0 = never) */
+  int32_t use_graph;         /* capture hook-free steps in a HIP graph */
+  int32_t reserved0;
+} lpic_options;
+
+typedef struct {
+  int64_t steps;             /* steps completed */
+  int64_t sorts;             /* sorts performed */
+  int32_t fused;             /* 1 when the fused kernel is in use */
+  int32_t graph;             /* 1 when steps run as a captured graph */
+  double fused_ms;           /* summed fused-kernel time measured with HIP events, when
+                                timing is on (lpic_set_timing) */
+  int64_t fused_launches;    /* launches covered by fused_ms */
+  int64_t halo_escapes;      /* particle pushes that left their tile's on-chip halo and went
+                                through global memory (cumulative) */
+} lpic_stats;
+
+/* Create a simulation over nruns independent boxes.  species[s] belongs to box
+ * species_run[s]; species_alt[s] holds same-sized arrays used as the sort's second buffer.
+ * fields[r].rho0/rho1 must be non-NULL when diagnostics are on.  All arrays stay owned by
+ * the caller and must outlive the simulation; the library allocates only its own scratch
+ * (sort workspace, tile and chunk tables, diagnostics) and frees it in lpic_sim_destroy. */
+lpic_status lpic_sim_create(lpic_sim **out, int32_t nruns, const lpic_grid *grids,
+                            const lpic_fields *fields, int32_t nspecies,
+                            const lpic_species *species, const int32_t *species_run,
+                            const lpic_species *species_alt, lpic_precision prec,
+                            const lpic_options *opt, hipStream_t stream);
+void lpic_sim_destroy(lpic_sim *sim);
+
+/* Advance nsteps steps of Algorithm 1.  Returns after enqueueing (plus host hooks). */
+lpic_status lpic_step(lpic_sim *sim, int32_t nsteps);
+
+lpic_status lpic_register_hook(lpic_sim *sim, int32_t stage, lpic_hook_fn fn, void *user);
+lpic_status lpic_clear_hooks(lpic_sim *sim);
+
+/* Current arrays of species s (the sort exchanges the two buffers). */
+lpic_status lpic_get_species(lpic_sim *sim, int32_t s, lpic_species *out);
+lpic_status lpic_get_stats(lpic_sim *sim, lpic_stats *out);
+/* Latest diagnostics of box r, synchronous: out[0] field energy, out[1] kinetic energy,
+ * out[2] continuity residual / max|rho1|, out[3] Gauss residual max, out[4] the step they
+ * were taken at.  LPIC_ENUMERIC if any is NaN or Inf. */
+lpic_status lpic_get_diagnostics(lpic_sim *sim, int32_t r, double out[5]);
+/* Per-kernel timing of the fused kernel with HIP events on the simulation's stream
+ * (on = 1).  Timing forces eager launches (no graph). */
+lpic_status lpic_set_timing(lpic_sim *sim, int32_t on);
+/* Replace the options (tiling, intervals, graph) of an existing simulation, e.g. from an
+ * autotuner; the next step re-sorts. */
+lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
+/* Try the listed candidate options for `steps_each` steps each (the simulation really
+ * advances), keep the fastest; writes the winner into *best when non-NULL. */
+lpic_status lpic_autotune(lpic_sim *sim, const lpic_options *candidates, int32_t ncand,
+                          int32_t steps_each, lpic_options *best);
+
+const char *lpic_last_error(void);
+const char *lpic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPIC_H */

@@ -1,0 +1,973 @@
+// C ABI of the PIC hot path: argument validation, descriptor set-up, launch sequencing,
+// the Algorithm 1 step loop with named-stage hooks, HIP graph capture and the autotuner.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lpic.h"
+#include "lpic_internal.hpp"
+
+using namespace lpic;
+
+namespace {
+
+thread_local std::string g_err;
+
+lpic_status fail(lpic_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(LPIC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)                          \
+  do {                                     \
+    lpic_status s_ = (expr);               \
+    if (s_ != LPIC_OK) return s_;          \
+  } while (0)
+
+lpic_status last_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LPIC_EHIP, "%s launch: %s", what, hipGetErrorString(e));
+  return LPIC_OK;
+}
+
+int ilog2_exact(int v) {
+  if (v <= 0 || (v & (v - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+int64_t ncells(const lpic_grid* g) {
+  return (int64_t)g->nx * g->ny * (g->ndim == 3 ? g->nz : 1);
+}
+
+lpic_status check_grid(const lpic_grid* g, int prec) {
+  if (!g) return fail(LPIC_EINVAL, "grid is NULL");
+  if (g->ndim != 2 && g->ndim != 3) return fail(LPIC_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+  if (g->nx < 4 || g->ny < 4 || (g->ndim == 3 && g->nz < 4))
+    return fail(LPIC_EINVAL, "every grid dimension must be >= 4 cells");
+  if (g->ndim == 2 && g->nz != 1) return fail(LPIC_EINVAL, "nz must be 1 in 2D");
+  if (!(g->dx > 0) || !(g->dy > 0) || (g->ndim == 3 && !(g->dz > 0)) || !(g->dt > 0))
+    return fail(LPIC_EINVAL, "cell sizes and dt must be positive");
+  double s = 1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy);
+  if (g->ndim == 3) s += 1.0 / (g->dz * g->dz);
+  const double cfl = 1.0 / sqrt(s);
+  if (g->dt > cfl * (1.0 + 1e-12))
+    return fail(LPIC_EINVAL, "dt = %g exceeds the CFL limit %g", g->dt, cfl);
+  if (prec == LPIC_F32_CELLOFS) {
+    if (g->ndim == 2 && (g->nx > 65536 || g->ny > 32768))
+      return fail(LPIC_EINVAL, "2D cell packing needs nx <= 65536, ny <= 32768");
+    if (g->ndim == 3 && (g->nx > 2048 || g->ny > 2048 || g->nz > 512))
+      return fail(LPIC_EINVAL, "3D cell packing needs nx, ny <= 2048, nz <= 512");
+  }
+  if (ncells(g) >= (int64_t)1 << 31) return fail(LPIC_EINVAL, "grid has too many cells");
+  if (prec != LPIC_F32_CELLOFS && prec != LPIC_F64_ABS)
+    return fail(LPIC_EINVAL, "unknown precision %d", prec);
+  return LPIC_OK;
+}
+
+lpic_status check_fields(const lpic_fields* f, bool need_rho) {
+  if (!f) return fail(LPIC_EINVAL, "fields is NULL");
+  const void* p[9] = {f->ex, f->ey, f->ez, f->bx, f->by, f->bz, f->jx, f->jy, f->jz};
+  for (int i = 0; i < 9; ++i)
+    if (!p[i]) return fail(LPIC_EINVAL, "field array %d is NULL", i);
+  if (need_rho && (!f->rho0 || !f->rho1)) return fail(LPIC_EINVAL, "rho0/rho1 are required");
+  return LPIC_OK;
+}
+
+lpic_status check_species(const lpic_species* s, int ndim, int prec) {
+  if (!s) return fail(LPIC_EINVAL, "species is NULL");
+  if (s->n < 0) return fail(LPIC_EINVAL, "negative particle count");
+  if (s->n >= ((int64_t)1 << 31) - 1) return fail(LPIC_EINVAL, "too many particles");
+  if (s->shape_order != 1 && s->shape_order != 2)
+    return fail(LPIC_EINVAL, "shape_order must be 1 or 2 (got %d)", s->shape_order);
+  if (!(s->m > 0)) return fail(LPIC_EINVAL, "mass must be positive");
+  if (s->n == 0) return LPIC_OK;
+  if (!s->ux || !s->uy || !s->uz || !s->w) return fail(LPIC_EINVAL, "momentum/weight arrays are NULL");
+  if (prec == LPIC_F32_CELLOFS) {
+    if (!s->cell || !s->ox || !s->oy || (ndim == 3 && !s->oz))
+      return fail(LPIC_EINVAL, "cell/offset arrays are NULL");
+  } else {
+    if (!s->x || !s->y || (ndim == 3 && !s->z)) return fail(LPIC_EINVAL, "position arrays are NULL");
+  }
+  return LPIC_OK;
+}
+
+lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec) {
+  if (!t) return fail(LPIC_EINVAL, "tiling is NULL");
+  const int nd = g->ndim;
+  if (ilog2_exact(t->tx) < 0 || ilog2_exact(t->ty) < 0 || (nd == 3 && ilog2_exact(t->tz) < 0))
+    return fail(LPIC_EINVAL, "tile edges must be powers of two");
+  if (t->halo < 3) return fail(LPIC_EINVAL, "halo must be >= 3");
+  if (t->halo > g->nx || t->halo > g->ny || (nd == 3 && t->halo > g->nz))
+    return fail(LPIC_EINVAL, "halo larger than the grid");
+  if (t->chunk < 1) return fail(LPIC_EINVAL, "chunk must be >= 1");
+  const size_t smem = fused_smem_bytes(prec, nd, t->tx, t->ty, nd == 3 ? t->tz : 1, t->halo, 1);
+  if (smem > 160 * 1024)
+    return fail(LPIC_EINVAL, "tile + halo needs %zu bytes of LDS (limit 163840)", smem);
+  return LPIC_OK;
+}
+
+void tile_counts(const lpic_grid* g, const lpic_tiling* t, int& ntx, int& nty, int& ntz) {
+  ntx = (g->nx + t->tx - 1) / t->tx;
+  nty = (g->ny + t->ty - 1) / t->ty;
+  ntz = g->ndim == 3 ? (g->nz + t->tz - 1) / t->tz : 1;
+}
+
+RunDesc make_run(const lpic_grid* g, const lpic_fields* f, const lpic_tiling* t) {
+  RunDesc r;
+  memset(&r, 0, sizeof(r));
+  r.ndim = g->ndim;
+  r.nx = g->nx;
+  r.ny = g->ny;
+  r.nz = g->ndim == 3 ? g->nz : 1;
+  r.dx = g->dx;
+  r.dy = g->dy;
+  r.dz = g->ndim == 3 ? g->dz : 1.0;
+  r.dt = g->dt;
+  r.rho_bg = g->rho_bg;
+  if (t) {
+    tile_counts(g, t, r.ntx, r.nty, r.ntz);
+    r.ntiles = r.ntx * r.nty * r.ntz;
+  } else {
+    r.ntx = r.nty = r.ntz = 1;
+    r.ntiles = 1;
+  }
+  if (f) {
+    void* p[F_NUM] = {f->ex, f->ey, f->ez, f->bx, f->by, f->bz, f->jx, f->jy, f->jz,
+                      f->rho0, f->rho1};
+    for (int i = 0; i < F_NUM; ++i) r.f[i] = p[i];
+  }
+  r.diag = nullptr;
+  return r;
+}
+
+void species_ptrs(const lpic_species* s, int prec, void* out[P_NUM]) {
+  for (int i = 0; i < P_NUM; ++i) out[i] = nullptr;
+  if (!s) return;
+  if (prec == LPIC_F32_CELLOFS) {
+    out[P_CELL] = s->cell;
+    out[P_OX] = s->ox;
+    out[P_OY] = s->oy;
+    out[P_OZ] = s->oz;
+  } else {
+    out[P_X] = s->x;
+    out[P_Y] = s->y;
+    out[P_Z] = s->z;
+  }
+  out[P_UX] = s->ux;
+  out[P_UY] = s->uy;
+  out[P_UZ] = s->uz;
+  out[P_W] = s->w;
+}
+
+void set_species_ptrs(lpic_species* s, int prec, void* const in[P_NUM]) {
+  if (prec == LPIC_F32_CELLOFS) {
+    s->cell = (int32_t*)in[P_CELL];
+    s->ox = in[P_OX];
+    s->oy = in[P_OY];
+    s->oz = in[P_OZ];
+  } else {
+    s->x = in[P_X];
+    s->y = in[P_Y];
+    s->z = in[P_Z];
+  }
+  s->ux = in[P_UX];
+  s->uy = in[P_UY];
+  s->uz = in[P_UZ];
+  s->w = in[P_W];
+}
+
+SegDesc make_seg(const lpic_species* s, const lpic_species* alt, int run, const lpic_tiling* t,
+                 int bin_base, int64_t pbase, int prec) {
+  SegDesc d;
+  memset(&d, 0, sizeof(d));
+  d.run = run;
+  d.order = s->shape_order;
+  if (t) {
+    d.lx = ilog2_exact(t->tx);
+    d.ly = ilog2_exact(t->ty);
+    d.lz = ilog2_exact(t->tz > 0 ? t->tz : 1);
+    if (d.lz < 0) d.lz = 0;
+    d.halo = t->halo;
+  }
+  d.bin_base = bin_base;
+  d.n = s->n;
+  d.pbase = pbase;
+  d.q = s->q;
+  d.m = s->m;
+  species_ptrs(s, prec, d.p);
+  species_ptrs(alt, prec, d.alt);
+  return d;
+}
+
+Tables single_tables(const RunDesc& r, const SegDesc* s) {
+  Tables T;
+  memset(&T, 0, sizeof(T));
+  T.nruns = 1;
+  T.nsegs = 1;
+  T.run0 = r;
+  if (s) T.seg0 = *s;
+  return T;
+}
+
+size_t old_state_bytes(int ndim, int64_t n, int prec) {
+  if (prec == LPIC_F32_CELLOFS) return (size_t)n * (4 + 4 * ndim + (ndim == 2 ? 4 : 0));
+  return (size_t)n * (8 * ndim + (ndim == 2 ? 8 : 0));
+}
+
+int64_t max_chunks_of(int64_t ntiles, int64_t n, int chunk) {
+  return ntiles + (n + chunk - 1) / chunk;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// =======================================================================================
+// Stateless entry points
+// =======================================================================================
+extern "C" {
+
+const char* lpic_last_error(void) { return g_err.c_str(); }
+const char* lpic_version(void) { return "lpic-mi355x 0.1 (gfx950)"; }
+
+lpic_status lpic_yee_update_EB(const lpic_grid* grid, const lpic_fields* fields, int32_t which,
+                               double frac, int32_t flags, lpic_precision prec,
+                               hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, false));
+  if (which != 0 && which != 1) return fail(LPIC_EINVAL, "which must be 0 (E) or 1 (B)");
+  if (!(frac > 0) || frac > 1.0) return fail(LPIC_EINVAL, "frac must be in (0, 1]");
+  RunDesc r = make_run(grid, fields, nullptr);
+  Tables T = single_tables(r, nullptr);
+  const int64_t nb = (ncells(grid) + 255) / 256;
+  launch_yee(T, prec, grid->ndim, (int)nb, which, frac, (flags & LPIC_YEE_ZERO_J) ? 1 : 0, stream);
+  return last_launch("yee");
+}
+
+size_t lpic_old_state_bytes(int32_t ndim, int64_t n, lpic_precision prec) {
+  return old_state_bytes(ndim, n, prec);
+}
+
+lpic_status lpic_gather_push(const lpic_grid* grid, const lpic_fields* fields,
+                             const lpic_species* sp, void* old_state, size_t old_bytes,
+                             lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, false));
+  CHK(check_species(sp, grid->ndim, prec));
+  if (sp->n == 0) return LPIC_OK;
+  if (!old_state || old_bytes < old_state_bytes(grid->ndim, sp->n, prec))
+    return fail(LPIC_EINVAL, "old_state needs %zu bytes", old_state_bytes(grid->ndim, sp->n, prec));
+  RunDesc r = make_run(grid, fields, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  launch_gather_push(T, prec, grid->ndim, (int)((sp->n + 255) / 256), old_state, stream);
+  return last_launch("gather_push");
+}
+
+lpic_status lpic_deposit_esirkepov(const lpic_grid* grid, const lpic_fields* fields,
+                                   const lpic_species* sp, const void* old_state,
+                                   size_t old_bytes, int32_t with_rho, lpic_precision prec,
+                                   hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, with_rho != 0));
+  CHK(check_species(sp, grid->ndim, prec));
+  if (sp->n == 0) return LPIC_OK;
+  if (!old_state || old_bytes < old_state_bytes(grid->ndim, sp->n, prec))
+    return fail(LPIC_EINVAL, "old_state needs %zu bytes", old_state_bytes(grid->ndim, sp->n, prec));
+  RunDesc r = make_run(grid, fields, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  launch_deposit(T, prec, grid->ndim, (int)((sp->n + 255) / 256), old_state, with_rho, stream);
+  return last_launch("deposit");
+}
+
+int64_t lpic_num_tiles(const lpic_grid* grid, const lpic_tiling* tiling) {
+  if (!grid || !tiling || tiling->tx <= 0 || tiling->ty <= 0) return -1;
+  lpic_tiling t = *tiling;
+  if (grid->ndim != 3) t.tz = 1;
+  int a, b, c;
+  tile_counts(grid, &t, a, b, c);
+  return (int64_t)a * b * c;
+}
+
+size_t lpic_sort_ws_bytes(const lpic_grid* grid, const lpic_tiling* tiling, int64_t n) {
+  (void)n;
+  const int64_t nt = lpic_num_tiles(grid, tiling);
+  if (nt < 0) return 0;
+  return 2 * align256((size_t)(nt + 1) * 4);
+}
+
+lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_species* alt,
+                            const lpic_tiling* tiling, int32_t* tile_offsets, void* ws,
+                            size_t ws_bytes, lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_species(sp, grid->ndim, prec));
+  CHK(check_species(alt, grid->ndim, prec));
+  CHK(check_tiling(tiling, grid, prec));
+  if (alt->n != sp->n) return fail(LPIC_EINVAL, "alt must have as many slots as sp");
+  if (!tile_offsets) return fail(LPIC_EINVAL, "tile_offsets is NULL");
+  const size_t need = lpic_sort_ws_bytes(grid, tiling, sp->n);
+  if (!ws || ws_bytes < need) return fail(LPIC_EINVAL, "sort workspace needs %zu bytes", need);
+  lpic_tiling t = *tiling;
+  if (grid->ndim != 3) t.tz = 1;
+  RunDesc r = make_run(grid, nullptr, &t);
+  const int nbins = r.ntiles + 1;
+  int32_t* counts = (int32_t*)ws;
+  int32_t* cursor = (int32_t*)((char*)ws + align256((size_t)nbins * 4));
+  if (sp->n > 0) {
+    SegDesc s = make_seg(sp, alt, 0, &t, 0, 0, prec);
+    Tables T = single_tables(r, &s);
+    launch_zero_u32((uint32_t*)counts, nbins, stream);
+    CHK(last_launch("sort clear"));
+    launch_sort(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), counts,
+                tile_offsets, cursor, nbins, stream);
+    CHK(last_launch("sort"));
+  } else {
+    launch_zero_u32((uint32_t*)tile_offsets, nbins + 1, stream);
+    return last_launch("sort clear");
+  }
+  void* a[P_NUM];
+  void* b[P_NUM];
+  species_ptrs(sp, prec, a);
+  species_ptrs(alt, prec, b);
+  set_species_ptrs(sp, prec, b);
+  set_species_ptrs(alt, prec, a);
+  return LPIC_OK;
+}
+
+size_t lpic_fused_ws_bytes(const lpic_grid* grid, const lpic_tiling* tiling, int64_t n) {
+  if (!tiling || tiling->chunk < 1) return 0;
+  const int64_t nt = lpic_num_tiles(grid, tiling);
+  if (nt < 0) return 0;
+  return align256(sizeof(int32_t)) + (size_t)max_chunks_of(nt, n, tiling->chunk) * sizeof(Chunk);
+}
+
+lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fields,
+                                    const lpic_species* sp, const lpic_tiling* tiling,
+                                    const int32_t* tile_offsets, void* ws, size_t ws_bytes,
+                                    int32_t with_rho, double* kinetic, lpic_precision prec,
+                                    hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, with_rho != 0));
+  CHK(check_species(sp, grid->ndim, prec));
+  CHK(check_tiling(tiling, grid, prec));
+  if (!tile_offsets) return fail(LPIC_EINVAL, "tile_offsets is NULL");
+  if (sp->n == 0) return LPIC_OK;
+  const size_t need = lpic_fused_ws_bytes(grid, tiling, sp->n);
+  if (!ws || ws_bytes < need) return fail(LPIC_EINVAL, "fused workspace needs %zu bytes", need);
+  lpic_tiling t = *tiling;
+  if (grid->ndim != 3) t.tz = 1;
+  RunDesc r = make_run(grid, fields, &t);
+  SegDesc s = make_seg(sp, nullptr, 0, &t, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  int32_t* nchunks = (int32_t*)ws;
+  Chunk* chunks = (Chunk*)((char*)ws + align256(sizeof(int32_t)));
+  launch_build_chunks(T, tile_offsets, r.ntiles + 1, t.chunk, chunks, nchunks, stream);
+  CHK(last_launch("build chunks"));
+  const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
+  HIPCHK(prepare_fused(prec, grid->ndim, smem));
+  const int64_t maxch = max_chunks_of(r.ntiles, sp->n, t.chunk);
+  launch_fused(T, prec, grid->ndim, (int)maxch, smem, chunks, nchunks, with_rho, kinetic, 0,
+               nullptr, stream);
+  return last_launch("fused");
+}
+
+lpic_status lpic_load_positions(const lpic_grid* grid, const lpic_species* sp, const double* x,
+                                const double* y, const double* z, lpic_precision prec,
+                                hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_species(sp, grid->ndim, prec));
+  if (sp->n == 0) return LPIC_OK;
+  if (!x || !y || (grid->ndim == 3 && !z)) return fail(LPIC_EINVAL, "source arrays are NULL");
+  RunDesc r = make_run(grid, nullptr, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  launch_load_positions(T, prec, grid->ndim, (int)((sp->n + 255) / 256), x, y, z, stream);
+  return last_launch("load positions");
+}
+
+lpic_status lpic_store_positions(const lpic_grid* grid, const lpic_species* sp, double* x,
+                                 double* y, double* z, lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_species(sp, grid->ndim, prec));
+  if (sp->n == 0) return LPIC_OK;
+  if (!x || !y || (grid->ndim == 3 && !z)) return fail(LPIC_EINVAL, "destination arrays are NULL");
+  RunDesc r = make_run(grid, nullptr, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  launch_store_positions(T, prec, grid->ndim, (int)((sp->n + 255) / 256), x, y, z, stream);
+  return last_launch("store positions");
+}
+
+lpic_status lpic_reduce_fields(const lpic_grid* grid, const lpic_fields* fields,
+                               int32_t with_rho, double* out, lpic_precision prec,
+                               hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, with_rho != 0));
+  if (!out) return fail(LPIC_EINVAL, "out is NULL");
+  RunDesc r = make_run(grid, fields, nullptr);
+  Tables T = single_tables(r, nullptr);
+  launch_zero_doubles(out, 4, stream);
+  CHK(last_launch("reduce clear"));
+  launch_reduce_fields(T, prec, grid->ndim, (int)((ncells(grid) + 255) / 256), with_rho, out,
+                       stream);
+  return last_launch("reduce");
+}
+
+}  // extern "C"
+
+// =======================================================================================
+// Simulation object: Algorithm 1 over one box or an ensemble of boxes
+// =======================================================================================
+struct HookEntry {
+  lpic_hook_fn fn;
+  void* user;
+};
+
+struct lpic_sim {
+  int prec = 0, ndim = 2, nruns = 0, nsegs = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<lpic_grid> grids;
+  std::vector<lpic_fields> fields;
+  std::vector<lpic_species> sp, alt;          // host mirrors, current buffer in sp
+  std::vector<int32_t> species_run;
+  std::vector<RunDesc> runs_h;
+  std::vector<SegDesc> segs_h;
+  lpic_options opt{};
+  // device tables and scratch
+  RunDesc* runs_d = nullptr;
+  SegDesc* segs_d = nullptr;
+  int32_t* run_blk_d = nullptr;
+  int32_t* seg_blk256_d = nullptr;
+  int32_t* seg_blk_sort_d = nullptr;
+  int nblk_cells = 0, nblk_p256 = 0, nblk_sort = 0;
+  int32_t *counts = nullptr, *offsets = nullptr, *cursor = nullptr;
+  int nbins = 0;
+  Chunk* chunks = nullptr;
+  int32_t* nchunks = nullptr;
+  int64_t max_chunks = 0;
+  size_t smem = 0, smem_rho = 0;
+  double* diag = nullptr;
+  unsigned long long* escapes = nullptr;
+  void* old_state = nullptr;
+  std::vector<size_t> old_off;
+  std::vector<HookEntry> hooks[LPIC_NUM_STAGES];
+  // progress
+  int64_t step = 0, sorts = 0, diag_step = -1;
+  bool need_sort = true;
+  // graphs indexed by (sort, diag)
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool gparity[4] = {false, false, false, false};
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+  double fused_ms = 0.0;
+  int64_t fused_launches = 0;
+  bool last_fused = false, last_graph = false;
+};
+
+namespace {
+
+void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void drop_graphs(lpic_sim* s) {
+  for (int i = 0; i < 4; ++i) {
+    if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
+    s->gexec[i] = nullptr;
+  }
+}
+
+bool intermediate_hooks(const lpic_sim* s) {
+  for (int st = LPIC_STAGE_PUSH_POSITION_1; st <= LPIC_STAGE_PUSH_POSITION_2; ++st)
+    if (!s->hooks[st].empty()) return true;
+  return false;
+}
+
+bool inner_hooks(const lpic_sim* s) {
+  for (int st = LPIC_STAGE_MAXWELL_1; st <= LPIC_STAGE_MAXWELL_2; ++st)
+    if (!s->hooks[st].empty()) return true;
+  return false;
+}
+
+Tables sim_tables(const lpic_sim* s, const int32_t* seg_blk) {
+  Tables T;
+  memset(&T, 0, sizeof(T));
+  T.runs = s->runs_d;
+  T.segs = s->segs_d;
+  T.run_blk = s->run_blk_d;
+  T.seg_blk = seg_blk;
+  T.nruns = s->nruns;
+  T.nsegs = s->nsegs;
+  return T;
+}
+
+lpic_status run_hooks(lpic_sim* s, int stage) {
+  for (auto& h : s->hooks[stage]) {
+    const int rc = h.fn(s, stage, s->step, h.user);
+    if (rc != 0) return fail(LPIC_EHOOK, "hook at stage %d returned %d at step %lld", stage, rc,
+                             (long long)s->step);
+  }
+  return LPIC_OK;
+}
+
+// (Re)build everything that depends on the options: tiling, bins, chunk tables.
+lpic_status configure(lpic_sim* s) {
+  drop_graphs(s);
+  lpic_tiling t = s->opt.tiling;
+  if (s->ndim != 3) t.tz = 1;
+  for (int r = 0; r < s->nruns; ++r) {
+    CHK(check_tiling(&t, &s->grids[r], s->prec));
+    CHK(check_fields(&s->fields[r], s->opt.diag_interval > 0));
+  }
+  if (s->opt.sort_interval < 1) return fail(LPIC_EINVAL, "sort_interval must be >= 1");
+  if (s->opt.diag_interval < 0) return fail(LPIC_EINVAL, "diag_interval must be >= 0");
+  // runs
+  s->runs_h.clear();
+  std::vector<int32_t> run_blk(1, 0);
+  for (int r = 0; r < s->nruns; ++r) {
+    RunDesc d = make_run(&s->grids[r], &s->fields[r], &t);
+    d.diag = s->diag + (size_t)r * DIAG_NUM;
+    s->runs_h.push_back(d);
+    run_blk.push_back(run_blk.back() + (int32_t)((ncells(&s->grids[r]) + 255) / 256));
+  }
+  // segments (current buffers first)
+  s->segs_h.clear();
+  std::vector<int32_t> blk256(1, 0), blks(1, 0);
+  int bin = 0;
+  int64_t pbase = 0, maxch = 0;
+  for (int i = 0; i < s->nsegs; ++i) {
+    const int r = s->species_run[i];
+    SegDesc d = make_seg(&s->sp[i], &s->alt[i], r, &t, bin, pbase, s->prec);
+    s->segs_h.push_back(d);
+    bin += s->runs_h[r].ntiles + 1;
+    pbase += s->sp[i].n;
+    maxch += max_chunks_of(s->runs_h[r].ntiles, s->sp[i].n, t.chunk);
+    blk256.push_back(blk256.back() + (int32_t)((s->sp[i].n + 255) / 256));
+    blks.push_back(blks.back() + (int32_t)((s->sp[i].n + SORT_BLOCK - 1) / SORT_BLOCK));
+  }
+  if (pbase >= ((int64_t)1 << 31) - 1) return fail(LPIC_EINVAL, "too many particles in total");
+  s->nblk_cells = run_blk.back();
+  s->nblk_p256 = blk256.back();
+  s->nblk_sort = blks.back();
+  s->nbins = bin;
+  s->max_chunks = maxch;
+  // device tables
+  free_dev(s->runs_d); free_dev(s->segs_d); free_dev(s->run_blk_d);
+  free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
+  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor);
+  free_dev(s->chunks);
+  s->runs_d = nullptr; s->segs_d = nullptr; s->run_blk_d = nullptr;
+  s->seg_blk256_d = s->seg_blk_sort_d = nullptr;
+  s->counts = s->offsets = s->cursor = nullptr;
+  s->chunks = nullptr;
+#define ALLOC(ptr, bytes)                                                            \
+  do {                                                                               \
+    if (hipMalloc((void**)&(ptr), std::max<size_t>(bytes, 256)) != hipSuccess)        \
+      return fail(LPIC_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes)); \
+  } while (0)
+  ALLOC(s->runs_d, sizeof(RunDesc) * s->nruns);
+  ALLOC(s->segs_d, sizeof(SegDesc) * std::max(1, s->nsegs));
+  ALLOC(s->run_blk_d, sizeof(int32_t) * run_blk.size());
+  ALLOC(s->seg_blk256_d, sizeof(int32_t) * blk256.size());
+  ALLOC(s->seg_blk_sort_d, sizeof(int32_t) * blks.size());
+  ALLOC(s->counts, sizeof(int32_t) * (s->nbins + 1));
+  ALLOC(s->offsets, sizeof(int32_t) * (s->nbins + 1));
+  ALLOC(s->cursor, sizeof(int32_t) * (s->nbins + 1));
+  ALLOC(s->chunks, sizeof(Chunk) * std::max<int64_t>(1, maxch));
+  HIPCHK(hipMemcpy(s->runs_d, s->runs_h.data(), sizeof(RunDesc) * s->nruns, hipMemcpyHostToDevice));
+  if (s->nsegs)
+    HIPCHK(hipMemcpy(s->segs_d, s->segs_h.data(), sizeof(SegDesc) * s->nsegs, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->run_blk_d, run_blk.data(), sizeof(int32_t) * run_blk.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->seg_blk256_d, blk256.data(), sizeof(int32_t) * blk256.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->seg_blk_sort_d, blks.data(), sizeof(int32_t) * blks.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(s->counts, 0, sizeof(int32_t) * (s->nbins + 1)));
+  HIPCHK(hipMemset(s->nchunks, 0, sizeof(int32_t)));
+  s->smem = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 0);
+  s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1);
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->smem_rho));
+  s->need_sort = true;
+  return LPIC_OK;
+#undef ALLOC
+}
+
+void swap_host_buffers(lpic_sim* s) {
+  for (int i = 0; i < s->nsegs; ++i) {
+    std::swap(s->sp[i], s->alt[i]);
+    for (int q = 0; q < P_NUM; ++q) std::swap(s->segs_h[i].p[q], s->segs_h[i].alt[q]);
+  }
+}
+
+// The device work of one step between the LOOP_START and LOOP_END hooks.  With hooks at the
+// inner stages the host runs them in between (eager mode only).
+lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, bool eager_hooks,
+                         bool capturing) {
+  const Tables Tc = sim_tables(s, nullptr);
+  const Tables Ts = sim_tables(s, s->seg_blk_sort_d);
+  if (diag) {
+    launch_diag_clear(Tc, s->nruns, st);
+    CHK(last_launch("diag clear"));
+  }
+  // field half update t -> t + dt/2 (E first), clearing J for the deposit
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 1, st);
+  CHK(last_launch("yee E"));
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
+  CHK(last_launch("yee B"));
+  if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_1));
+  // sort particles (every sort_interval steps)
+  if (do_sort && s->nsegs > 0) {
+    launch_sort(Ts, s->prec, s->ndim, s->nblk_sort, s->counts, s->offsets, s->cursor, s->nbins, st);
+    CHK(last_launch("sort"));
+    launch_swap_segments(s->segs_d, s->nsegs, st);
+    CHK(last_launch("swap"));
+    launch_build_chunks(Tc, s->offsets, s->nbins, s->opt.tiling.chunk, s->chunks, s->nchunks, st);
+    CHK(last_launch("chunks"));
+    // the host mirror follows the device table at once, so that launches later in this
+    // step that take descriptors by value see the sorted buffers (not while capturing: a
+    // captured graph is replayed later and the caller swaps per replay)
+    if (!capturing) swap_host_buffers(s);
+  }
+  // particle loop
+  const bool fused = !intermediate_hooks(s);
+  s->last_fused = fused;
+  if (s->nsegs > 0) {
+    if (fused) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (s->timing) {
+        if (s->ev_free.empty()) {
+          HIPCHK(hipEventCreate(&e0));
+          HIPCHK(hipEventCreate(&e1));
+        } else {
+          e0 = s->ev_free.back().first;
+          e1 = s->ev_free.back().second;
+          s->ev_free.pop_back();
+        }
+        HIPCHK(hipEventRecord(e0, st));
+      }
+      launch_fused(Tc, s->prec, s->ndim, (int)s->max_chunks, diag ? s->smem_rho : s->smem,
+                   s->chunks, s->nchunks, diag ? 1 : 0, nullptr, diag ? 1 : 0, s->escapes, st);
+      CHK(last_launch("fused"));
+      if (s->timing) {
+        HIPCHK(hipEventRecord(e1, st));
+        s->ev_pending.push_back({e0, e1});
+      }
+    } else {
+      // split path, species by species, with the intermediate hooks in between
+      char* old = (char*)s->old_state;
+      for (int i = 0; i < s->nsegs; ++i) {
+        const int r = s->species_run[i];
+        RunDesc rd = s->runs_h[r];
+        Tables T1 = single_tables(rd, &s->segs_h[i]);
+        const int nb = (int)((s->sp[i].n + 255) / 256);
+        if (nb == 0) continue;
+        launch_gather_push(T1, s->prec, s->ndim, nb, old + s->old_off[i], st);
+        CHK(last_launch("gather_push"));
+        if (eager_hooks) {
+          CHK(run_hooks(s, LPIC_STAGE_PUSH_POSITION_1));
+          CHK(run_hooks(s, LPIC_STAGE_INTERPOLATOR));
+          CHK(run_hooks(s, LPIC_STAGE_PUSH_MOMENTUM));
+          CHK(run_hooks(s, LPIC_STAGE_PUSH_POSITION_2));
+        }
+        launch_deposit(T1, s->prec, s->ndim, nb, old + s->old_off[i], diag ? 1 : 0, st);
+        CHK(last_launch("deposit"));
+        if (diag) {
+          launch_kinetic(T1, s->prec, s->ndim, nb, rd.diag + DIAG_UKIN, st);
+          CHK(last_launch("kinetic"));
+        }
+      }
+    }
+  }
+  if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_CURRENT_DEPOSITION));
+  // field half update t + dt/2 -> t + dt (B first)
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
+  CHK(last_launch("yee B"));
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, st);
+  CHK(last_launch("yee E"));
+  if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_2));
+  if (diag) {
+    launch_reduce_fields(Tc, s->prec, s->ndim, s->nblk_cells, 1, nullptr, st);
+    CHK(last_launch("reduce"));
+  }
+  return LPIC_OK;
+}
+
+lpic_status ensure_old_state(lpic_sim* s) {
+  if (s->old_state) return LPIC_OK;
+  size_t tot = 0;
+  s->old_off.clear();
+  for (int i = 0; i < s->nsegs; ++i) {
+    s->old_off.push_back(tot);
+    tot += align256(old_state_bytes(s->ndim, s->sp[i].n, s->prec));
+  }
+  if (hipMalloc(&s->old_state, std::max<size_t>(tot, 256)) != hipSuccess)
+    return fail(LPIC_ENOMEM, "old-state allocation of %zu bytes failed", tot);
+  return LPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpic_status lpic_sim_create(lpic_sim** out, int32_t nruns, const lpic_grid* grids,
+                            const lpic_fields* fields, int32_t nspecies,
+                            const lpic_species* species, const int32_t* species_run,
+                            const lpic_species* species_alt, lpic_precision prec,
+                            const lpic_options* opt, hipStream_t stream) {
+  if (!out) return fail(LPIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nruns < 1 || !grids || !fields) return fail(LPIC_EINVAL, "need at least one box");
+  if (nspecies < 0 || (nspecies > 0 && (!species || !species_run || !species_alt)))
+    return fail(LPIC_EINVAL, "species arrays are NULL");
+  if (!opt) return fail(LPIC_EINVAL, "options are NULL");
+  for (int r = 0; r < nruns; ++r) {
+    CHK(check_grid(&grids[r], prec));
+    CHK(check_fields(&fields[r], opt->diag_interval > 0));
+    if (grids[r].ndim != grids[0].ndim) return fail(LPIC_EINVAL, "all boxes must have one ndim");
+  }
+  for (int i = 0; i < nspecies; ++i) {
+    if (species_run[i] < 0 || species_run[i] >= nruns)
+      return fail(LPIC_EINVAL, "species %d names box %d", i, species_run[i]);
+    if (i > 0 && species_run[i] < species_run[i - 1])
+      return fail(LPIC_EINVAL, "species must be listed in box order");
+    CHK(check_species(&species[i], grids[0].ndim, prec));
+    CHK(check_species(&species_alt[i], grids[0].ndim, prec));
+    if (species_alt[i].n != species[i].n) return fail(LPIC_EINVAL, "alt size mismatch");
+  }
+  lpic_sim* s = new lpic_sim();
+  s->prec = prec;
+  s->ndim = grids[0].ndim;
+  s->nruns = nruns;
+  s->nsegs = nspecies;
+  s->stream = stream;
+  s->grids.assign(grids, grids + nruns);
+  s->fields.assign(fields, fields + nruns);
+  if (nspecies) {
+    s->sp.assign(species, species + nspecies);
+    s->alt.assign(species_alt, species_alt + nspecies);
+    s->species_run.assign(species_run, species_run + nspecies);
+  }
+  s->opt = *opt;
+  if (hipMalloc((void**)&s->diag, sizeof(double) * DIAG_NUM * nruns) != hipSuccess ||
+      hipMalloc((void**)&s->nchunks, 256) != hipSuccess ||
+      hipMalloc((void**)&s->escapes, 256) != hipSuccess) {
+    lpic_sim_destroy(s);
+    return fail(LPIC_ENOMEM, "device allocation failed");
+  }
+  if (hipMemset(s->diag, 0, sizeof(double) * DIAG_NUM * nruns) != hipSuccess ||
+      hipMemset(s->escapes, 0, 256) != hipSuccess) {
+    lpic_sim_destroy(s);
+    return fail(LPIC_EHIP, "hipMemset failed");
+  }
+  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    lpic_sim_destroy(s);
+    return fail(LPIC_EHIP, "stream creation failed");
+  }
+  lpic_status st = configure(s);
+  if (st != LPIC_OK) {
+    std::string keep = g_err;
+    lpic_sim_destroy(s);
+    g_err = keep;
+    return st;
+  }
+  *out = s;
+  return LPIC_OK;
+}
+
+void lpic_sim_destroy(lpic_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  for (auto& e : s->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : s->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  free_dev(s->runs_d); free_dev(s->segs_d); free_dev(s->run_blk_d);
+  free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
+  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor);
+  free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
+  free_dev(s->old_state);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+lpic_status lpic_register_hook(lpic_sim* s, int32_t stage, lpic_hook_fn fn, void* user) {
+  if (!s || !fn) return fail(LPIC_EINVAL, "sim or hook is NULL");
+  if (stage < 0 || stage >= LPIC_NUM_STAGES) return fail(LPIC_EINVAL, "bad stage %d", stage);
+  if (stage == LPIC_STAGE_QED_CREATE) return fail(LPIC_EUNSUPPORTED, "no QED stage in this library");
+  s->hooks[stage].push_back({fn, user});
+  drop_graphs(s);
+  return LPIC_OK;
+}
+
+lpic_status lpic_clear_hooks(lpic_sim* s) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  for (auto& v : s->hooks) v.clear();
+  drop_graphs(s);
+  return LPIC_OK;
+}
+
+lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  if (nsteps < 0) return fail(LPIC_EINVAL, "nsteps must be >= 0");
+  const bool split = intermediate_hooks(s);
+  if (split) CHK(ensure_old_state(s));
+  const bool use_graph = s->opt.use_graph && !s->timing && !inner_hooks(s);
+  s->last_graph = use_graph;
+  CHK(run_hooks(s, LPIC_STAGE_START));
+  for (int n = 0; n < nsteps; ++n) {
+    CHK(run_hooks(s, LPIC_STAGE_LOOP_START));
+    const bool do_sort = s->need_sort || (s->step % s->opt.sort_interval) == 0;
+    const bool diag = s->opt.diag_interval > 0 && ((s->step + 1) % s->opt.diag_interval) == 0;
+    if (use_graph) {
+      const int gi = (do_sort ? 2 : 0) + (diag ? 1 : 0);
+      if (!s->gexec[gi]) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        lpic_status st = enqueue_step(s, s->cap_stream, do_sort, diag, false, true);
+        hipError_t ee = hipStreamEndCapture(s->cap_stream, &g);
+        if (st != LPIC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (ee != hipSuccess) return fail(LPIC_EHIP, "graph capture: %s", hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&s->gexec[gi], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(LPIC_EHIP, "graph instantiate: %s", hipGetErrorString(ie));
+      }
+      HIPCHK(hipGraphLaunch(s->gexec[gi], s->stream));
+      if (do_sort && s->nsegs > 0) swap_host_buffers(s);
+    } else {
+      CHK(enqueue_step(s, s->stream, do_sort, diag, true, false));
+    }
+    if (do_sort && s->nsegs > 0) {
+      ++s->sorts;
+      s->need_sort = false;
+    }
+    if (diag) s->diag_step = s->step + 1;
+    ++s->step;
+    CHK(run_hooks(s, LPIC_STAGE_LOOP_END));
+  }
+  CHK(run_hooks(s, LPIC_STAGE_FINISH));
+  return LPIC_OK;
+}
+
+lpic_status lpic_get_species(lpic_sim* s, int32_t i, lpic_species* out) {
+  if (!s || !out) return fail(LPIC_EINVAL, "NULL argument");
+  if (i < 0 || i >= s->nsegs) return fail(LPIC_EINVAL, "species index %d out of range", i);
+  *out = s->sp[i];
+  return LPIC_OK;
+}
+
+lpic_status lpic_get_stats(lpic_sim* s, lpic_stats* out) {
+  if (!s || !out) return fail(LPIC_EINVAL, "NULL argument");
+  for (auto& e : s->ev_pending) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+    s->fused_ms += ms;
+    ++s->fused_launches;
+    s->ev_free.push_back(e);
+  }
+  s->ev_pending.clear();
+  out->steps = s->step;
+  out->sorts = s->sorts;
+  out->fused = s->last_fused ? 1 : 0;
+  out->graph = s->last_graph ? 1 : 0;
+  out->fused_ms = s->fused_ms;
+  out->fused_launches = s->fused_launches;
+  unsigned long long esc = 0;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(&esc, s->escapes, sizeof(esc), hipMemcpyDeviceToHost));
+  out->halo_escapes = (int64_t)esc;
+  return LPIC_OK;
+}
+
+lpic_status lpic_get_diagnostics(lpic_sim* s, int32_t r, double out[5]) {
+  if (!s || !out) return fail(LPIC_EINVAL, "NULL argument");
+  if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "box index %d out of range", r);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  double d[DIAG_NUM];
+  HIPCHK(hipMemcpy(d, s->diag + (size_t)r * DIAG_NUM, sizeof(d), hipMemcpyDeviceToHost));
+  const lpic_grid& g = s->grids[r];
+  const double dV = g.dx * g.dy * (g.ndim == 3 ? g.dz : 1.0);
+  out[0] = d[DIAG_UFIELD];
+  out[1] = d[DIAG_UKIN] * dV;
+  out[2] = d[DIAG_RHOMAX] > 0 ? d[DIAG_RES] / d[DIAG_RHOMAX] : d[DIAG_RES];
+  out[3] = d[DIAG_GAUSS];
+  out[4] = (double)s->diag_step;
+  for (int i = 0; i < 4; ++i)
+    if (!isfinite(out[i])) return fail(LPIC_ENUMERIC, "diagnostic %d of box %d is not finite", i, r);
+  return LPIC_OK;
+}
+
+lpic_status lpic_set_timing(lpic_sim* s, int32_t on) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  s->timing = on != 0;
+  if (!s->timing) {
+    lpic_stats tmp;
+    CHK(lpic_get_stats(s, &tmp));
+  }
+  s->fused_ms = 0.0;
+  s->fused_launches = 0;
+  return LPIC_OK;
+}
+
+lpic_status lpic_set_options(lpic_sim* s, const lpic_options* opt) {
+  if (!s || !opt) return fail(LPIC_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  // the device segment table is rebuilt from the host mirror, which tracks the buffers
+  lpic_options keep = s->opt;
+  s->opt = *opt;
+  lpic_status st = configure(s);
+  if (st != LPIC_OK) {
+    s->opt = keep;
+    std::string err = g_err;
+    (void)configure(s);
+    g_err = err;
+  }
+  return st;
+}
+
+lpic_status lpic_autotune(lpic_sim* s, const lpic_options* cand, int32_t ncand,
+                          int32_t steps_each, lpic_options* best) {
+  if (!s || !cand || ncand < 1 || steps_each < 1) return fail(LPIC_EINVAL, "bad autotune arguments");
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best_ms = 1e300;
+  int best_i = -1;
+  for (int i = 0; i < ncand; ++i) {
+    if (lpic_set_options(s, &cand[i]) != LPIC_OK) continue;   // skip infeasible candidates
+    CHK(lpic_step(s, 1));                                      // warm-up, includes the sort
+    HIPCHK(hipEventRecord(a, s->stream));
+    CHK(lpic_step(s, steps_each));
+    HIPCHK(hipEventRecord(b, s->stream));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    if (ms < best_ms) { best_ms = ms; best_i = i; }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (best_i < 0) return fail(LPIC_EINVAL, "no feasible candidate");
+  CHK(lpic_set_options(s, &cand[best_i]));
+  if (best) *best = cand[best_i];
+  return LPIC_OK;
+}
+
+}  // extern "C"

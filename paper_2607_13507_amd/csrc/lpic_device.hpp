@@ -1,0 +1,608 @@
+// Device-side building blocks of the PIC hot path for gfx950.
+//
+// The particle math follows lambda-PIC (arXiv 2607.13507): Algorithm 1 (half position push,
+// interpolation, Boris momentum push, half position push, deposit), the relativistic Boris
+// scheme of Sec. 3.1, staggering-aware B-spline interpolation (Sec. 3.1) and Esirkepov's
+// charge-conserving deposition (Sec. 3.1, Esirkepov 2001).  Everything here is written for
+// 64-wide wavefronts: no warp-size assumptions other than wave64 ballots in the sort.
+//
+// Positions inside kernels are always (integer cell, offset in [0,1)) per axis, in cell
+// units.  In the FP32 mode this is the stored representation; in the FP64 mode it is
+// derived from the absolute coordinate on load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpic {
+
+enum FieldSlot { F_EX = 0, F_EY, F_EZ, F_BX, F_BY, F_BZ, F_JX, F_JY, F_JZ, F_R0, F_R1, F_NUM };
+
+// Particle array slots.  FP32: cell(int32) ox oy oz ux uy uz w;  FP64: x y z - ux uy uz w.
+enum PartSlot { P_CELL = 0, P_X = 0, P_OX = 1, P_Y = 1, P_OY = 2, P_Z = 2, P_OZ = 3,
+                P_UX = 4, P_UY = 5, P_UZ = 6, P_W = 7, P_NUM = 8 };
+
+enum { DIAG_UFIELD = 0, DIAG_UKIN = 1, DIAG_RES = 2, DIAG_RHOMAX = 3, DIAG_GAUSS = 4,
+       DIAG_NUM = 8 };
+
+// One simulation box.
+struct RunDesc {
+  int32_t ndim, nx, ny, nz;
+  int32_t ntx, nty, ntz, ntiles;   // tiles per axis of the current tiling
+  double dx, dy, dz, dt, rho_bg;
+  void* f[F_NUM];
+  double* diag;                    // DIAG_NUM device accumulators
+};
+
+// One species of one box (a "segment" of the global particle key space).
+struct SegDesc {
+  int32_t run, order;
+  int32_t lx, ly, lz, halo;        // log2 of the tile edges, halo cells
+  int32_t bin_base;                // global bin of tile 0; the dead bin is bin_base + ntiles
+  int32_t pad0;
+  int64_t n;                       // slots
+  int64_t pbase;                   // position of slot 0 in the concatenation of all segments
+  double q, m;
+  void* p[P_NUM];                  // current arrays
+  void* alt[P_NUM];                // second buffer of the sort
+};
+
+struct Chunk {
+  int32_t seg, tile, beg, end;     // particles [beg, end) of segment `seg`, home tile `tile`
+};
+
+// Descriptor access: either device tables (simulations, ensembles) or one run / one
+// segment passed by value (single-box entry points).
+struct Tables {
+  const RunDesc* runs;
+  const SegDesc* segs;
+  const int32_t* run_blk;          // nruns + 1 block prefix for cell kernels
+  const int32_t* seg_blk;          // nsegs + 1 block prefix for particle kernels
+  int32_t nruns, nsegs;
+  RunDesc run0;
+  SegDesc seg0;
+};
+
+__device__ __forceinline__ int find_owner(const int32_t* prefix, int count, int b) {
+  int lo = 0, hi = count - 1;  // largest i with prefix[i] <= b
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------------------
+// precision helpers
+// ---------------------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R rsq(R x);
+template <> __device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
+template <typename R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <typename R> __device__ __forceinline__ R ffloor(R x) { return floor(x); }
+template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
+
+__device__ __forceinline__ void atomic_add_lds(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void atomic_add_lds(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void atomic_add_global(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add_global(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// floor(x) limited to [lo, hi]; NaN maps to lo.  Every cell index derived from a particle
+// offset goes through this, so no input can produce an access outside the stencil window.
+template <typename R>
+__device__ __forceinline__ R floor_clamped(R x, R lo, R hi) {
+  return fmin(fmax(floor(x), lo), hi);
+}
+template <>
+__device__ __forceinline__ float floor_clamped<float>(float x, float lo, float hi) {
+  return fminf(fmaxf(floorf(x), lo), hi);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {  // |i| small compared to n
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// ---------------------------------------------------------------------------------------
+// Shape weights (Sec. 3.1).  For a particle at cell `c` with offset o in [0,1] the weights
+// of the ORDER+1 nodes that can be non-zero are returned with the index of the first one,
+// for the integer lattice (nodes at i) and the half lattice (nodes at i+1/2, index i).
+//   CIC       S(x) = 1 - |x|
+//   quadratic S(x) = 3/4 - x^2 (|x| <= 1/2),  (3/2 - |x|)^2 / 2 (1/2 < |x| < 3/2)
+// ---------------------------------------------------------------------------------------
+template <int ORDER, typename R>
+__device__ __forceinline__ void weights_int(R o, int c, int& base, R w[ORDER + 1]) {
+  if constexpr (ORDER == 1) {
+    base = c;
+    w[0] = R(1) - o;
+    w[1] = o;
+  } else {
+    const int up = o >= R(0.5);
+    const R d = o - R(up);                // offset from the nearest node, in [-1/2, 1/2)
+    base = c + up - 1;
+    const R a = R(0.5) - d, b = R(0.5) + d;
+    w[0] = R(0.5) * a * a;
+    w[1] = R(0.75) - d * d;
+    w[2] = R(0.5) * b * b;
+  }
+}
+
+template <int ORDER, typename R>
+__device__ __forceinline__ void weights_half(R o, int c, int& base, R w[ORDER + 1]) {
+  if constexpr (ORDER == 1) {
+    const int up = o >= R(0.5);
+    const R t = o + R(0.5) - R(up);       // distance past the half node at index base
+    base = c - 1 + up;
+    w[0] = R(1) - t;
+    w[1] = t;
+  } else {
+    const R d = o - R(0.5);               // the nearest half node is c + 1/2
+    base = c - 1;
+    const R a = R(0.5) - d, b = R(0.5) + d;
+    w[0] = R(0.5) * a * a;
+    w[1] = R(0.75) - d * d;
+    w[2] = R(0.5) * b * b;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Field / current accessors.  Coordinates are in the accessor's frame: global (wrapped)
+// for the global accessor, tile-local for the on-chip one.  xo/yo/zo turn a coordinate into
+// an element offset so a stencil's offsets are computed once and reused by every component.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+struct GlobalAcc {
+  R* f[F_NUM];
+  int nx, ny, nz;
+  __device__ __forceinline__ int xo(int x) const { return wrapi(x, nx); }
+  __device__ __forceinline__ int yo(int y) const { return wrapi(y, ny) * nx; }
+  __device__ __forceinline__ int zo(int z) const { return wrapi(z, nz) * nx * ny; }
+  __device__ __forceinline__ R get(int comp, int off) const { return f[comp][off]; }
+  __device__ __forceinline__ void add(int comp, int off, R v) const {
+    atomic_add_global(f[comp] + off, v);
+  }
+};
+
+template <typename R>
+struct LdsAcc {
+  R* base;        // planes: 6 field components, then jx jy jz, then rho0 rho1
+  int plane, sy, sz;
+  __device__ __forceinline__ int xo(int x) const { return x; }
+  __device__ __forceinline__ int yo(int y) const { return y * sy; }
+  __device__ __forceinline__ int zo(int z) const { return z * sz; }
+  __device__ __forceinline__ R get(int comp, int off) const { return base[comp * plane + off]; }
+  __device__ __forceinline__ void add(int comp, int off, R v) const {
+    atomic_add_lds(base + comp * plane + off, v);
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Interpolation (Sec. 3.1): every component from its own staggered nodes.
+// 2D:  Ex (h,i)  Ey (i,h)  Ez (i,i)  Bx (i,h)  By (h,i)  Bz (h,h)
+// 3D:  Ex (h,i,i) Ey (i,h,i) Ez (i,i,h) Bx (i,h,h) By (h,i,h) Bz (h,h,i)
+// ---------------------------------------------------------------------------------------
+template <int N, typename R, class Acc>
+__device__ __forceinline__ R interp2(const Acc& A, int comp, const int* xo, const R* wx,
+                                     const int* yo, const R* wy) {
+  R s = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    R r = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) r += wx[a] * A.get(comp, yo[b] + xo[a]);
+    s += wy[b] * r;
+  }
+  return s;
+}
+
+template <int N, typename R, class Acc>
+__device__ __forceinline__ R interp3(const Acc& A, int comp, const int* xo, const R* wx,
+                                     const int* yo, const R* wy, const int* zo, const R* wz) {
+  R s = R(0);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    R t = R(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      R r = R(0);
+#pragma unroll
+      for (int a = 0; a < N; ++a) r += wx[a] * A.get(comp, zo[c] + yo[b] + xo[a]);
+      t += wy[b] * r;
+    }
+    s += wz[c] * t;
+  }
+  return s;
+}
+
+template <int ORDER, typename R, class Acc>
+__device__ __forceinline__ void stencil_axis(const Acc& A, int axis, int c, R o, int* oi,
+                                             R* wi, int* oh, R* wh) {
+  constexpr int N = ORDER + 1;
+  int bi, bh;
+  weights_int<ORDER>(o, c, bi, wi);
+  weights_half<ORDER>(o, c, bh, wh);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    if (axis == 0) { oi[a] = A.xo(bi + a); oh[a] = A.xo(bh + a); }
+    else if (axis == 1) { oi[a] = A.yo(bi + a); oh[a] = A.yo(bh + a); }
+    else { oi[a] = A.zo(bi + a); oh[a] = A.zo(bh + a); }
+  }
+}
+
+template <int DIM, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void gather(const Acc& A, const int* c, const R* o, R E[3], R B[3]) {
+  constexpr int N = ORDER + 1;
+  int xi[N], xh[N], yi[N], yh[N];
+  R wxi[N], wxh[N], wyi[N], wyh[N];
+  stencil_axis<ORDER>(A, 0, c[0], o[0], xi, wxi, xh, wxh);
+  stencil_axis<ORDER>(A, 1, c[1], o[1], yi, wyi, yh, wyh);
+  if constexpr (DIM == 2) {
+    E[0] = interp2<N>(A, F_EX, xh, wxh, yi, wyi);
+    E[1] = interp2<N>(A, F_EY, xi, wxi, yh, wyh);
+    E[2] = interp2<N>(A, F_EZ, xi, wxi, yi, wyi);
+    B[0] = interp2<N>(A, F_BX, xi, wxi, yh, wyh);
+    B[1] = interp2<N>(A, F_BY, xh, wxh, yi, wyi);
+    B[2] = interp2<N>(A, F_BZ, xh, wxh, yh, wyh);
+  } else {
+    int zi[N], zh[N];
+    R wzi[N], wzh[N];
+    stencil_axis<ORDER>(A, 2, c[2], o[2], zi, wzi, zh, wzh);
+    E[0] = interp3<N>(A, F_EX, xh, wxh, yi, wyi, zi, wzi);
+    E[1] = interp3<N>(A, F_EY, xi, wxi, yh, wyh, zi, wzi);
+    E[2] = interp3<N>(A, F_EZ, xi, wxi, yi, wyi, zh, wzh);
+    B[0] = interp3<N>(A, F_BX, xi, wxi, yh, wyh, zh, wzh);
+    B[1] = interp3<N>(A, F_BY, xh, wxh, yi, wyi, zh, wzh);
+    B[2] = interp3<N>(A, F_BZ, xh, wxh, yh, wyh, zi, wzi);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Relativistic Boris push (Sec. 3.1): half electric kick, rotation, half electric kick.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void boris(R u[3], const R E[3], const R B[3], R qdt2m) {
+  const R umx = u[0] + qdt2m * E[0], umy = u[1] + qdt2m * E[1], umz = u[2] + qdt2m * E[2];
+  const R f = qdt2m * rsq<R>(R(1) + umx * umx + umy * umy + umz * umz);
+  const R tx = f * B[0], ty = f * B[1], tz = f * B[2];
+  const R s = R(2) * rcp<R>(R(1) + tx * tx + ty * ty + tz * tz);
+  const R sx = s * tx, sy = s * ty, sz = s * tz;
+  const R upx = umx + (umy * tz - umz * ty);
+  const R upy = umy + (umz * tx - umx * tz);
+  const R upz = umz + (umx * ty - umy * tx);
+  u[0] = umx + (upy * sz - upz * sy) + qdt2m * E[0];
+  u[1] = umy + (upz * sx - upx * sz) + qdt2m * E[1];
+  u[2] = umz + (upx * sy - upy * sx) + qdt2m * E[2];
+}
+
+// ---------------------------------------------------------------------------------------
+// Esirkepov window along one axis.  x0 in [0,1) is the start offset and x1 in (-1,2) the
+// end offset, both relative to the start cell.  Fills S0 and S1 on a window of W = ORDER+2
+// integer nodes starting at start_cell + base.
+// ---------------------------------------------------------------------------------------
+template <int ORDER, typename R>
+__device__ __forceinline__ void esk_axis(R x0, R x1, int& base, R S0[ORDER + 2], R S1[ORDER + 2]) {
+  if constexpr (ORDER == 1) {
+    const R f1 = floor_clamped<R>(x1, R(-1), R(1));
+    const int c1 = (int)f1;                      // -1, 0 or 1
+    const R d1 = x1 - f1;
+    base = c1 < 0 ? c1 : 0;
+    const int s0 = -base, s1 = c1 - base;        // 0 or 1 each
+    const R a0 = R(1) - x0, a1 = x0, b0 = R(1) - d1, b1 = d1;
+    S0[0] = s0 ? R(0) : a0;
+    S0[1] = s0 ? a0 : a1;
+    S0[2] = s0 ? a1 : R(0);
+    S1[0] = s1 ? R(0) : b0;
+    S1[1] = s1 ? b0 : b1;
+    S1[2] = s1 ? b1 : R(0);
+  } else {
+    const int c0 = x0 >= R(0.5);
+    const R fc1 = floor_clamped<R>(x1 + R(0.5), R(-1), R(2));
+    const int c1 = (int)fc1;                     // -1 .. 2
+    const R d0 = x0 - R(c0), d1 = x1 - fc1;
+    base = (c0 < c1 ? c0 : c1) - 1;
+    const int s0 = c0 - 1 - base, s1 = c1 - 1 - base;   // 0 or 1 each
+    R a[3], b[3];
+    {
+      const R p = R(0.5) - d0, q = R(0.5) + d0;
+      a[0] = R(0.5) * p * p; a[1] = R(0.75) - d0 * d0; a[2] = R(0.5) * q * q;
+    }
+    {
+      const R p = R(0.5) - d1, q = R(0.5) + d1;
+      b[0] = R(0.5) * p * p; b[1] = R(0.75) - d1 * d1; b[2] = R(0.5) * q * q;
+    }
+    S0[0] = s0 ? R(0) : a[0];
+    S0[1] = s0 ? a[0] : a[1];
+    S0[2] = s0 ? a[1] : a[2];
+    S0[3] = s0 ? a[2] : R(0);
+    S1[0] = s1 ? R(0) : b[0];
+    S1[1] = s1 ? b[0] : b[1];
+    S1[2] = s1 ? b[1] : b[2];
+    S1[3] = s1 ? b[2] : R(0);
+  }
+}
+
+// Per-segment constants in the kernel's precision.
+template <typename R>
+struct PushConst {
+  R hdx, hdy, hdz;      // dt / (2 h): half-step displacement in cells per unit velocity
+  R qdt2m;              // q dt / (2 m)
+  R jx, jy, jz;         // -q h / dt per axis (Esirkepov current factor, times w)
+  R q;                  // charge (2D Jz and rho, times w)
+};
+
+template <typename R>
+__device__ __forceinline__ PushConst<R> push_const(const RunDesc& r, const SegDesc& s) {
+  PushConst<R> c;
+  c.hdx = R(0.5 * r.dt / r.dx);
+  c.hdy = R(0.5 * r.dt / r.dy);
+  c.hdz = R(0.5 * r.dt / r.dz);
+  c.qdt2m = R(s.q * r.dt / (2.0 * s.m));
+  c.jx = R(-s.q * r.dx / r.dt);
+  c.jy = R(-s.q * r.dy / r.dt);
+  c.jz = R(-s.q * r.dz / r.dt);
+  c.q = R(s.q);
+  return c;
+}
+
+// Esirkepov deposit of one particle (2D3V or 3D3V) through accessor A, whose frame places
+// the start cell at c[] (accessor coordinates).  x0/x1 per axis as in esk_axis.
+//   2D: Wx = dSx (S0y + S1y)/2 summed along x, Wy likewise, and
+//       Wz = (S0x (2 S0y + S1y) + S1x (S0y + 2 S1y)) / 6   (= S0 S0 + dS S0/2 + S0 dS/2 + dS dS/3)
+//   3D: Wx = dSx (S0y (2 S0z + S1z) + S1y (S0z + 2 S1z)) / 6 summed along x, cyclic.
+template <int DIM, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0, const R* x1,
+                                        R w, R vz_bar, const PushConst<R>& k, bool with_rho) {
+  constexpr int W = ORDER + 2;
+  R S0x[W], S1x[W], S0y[W], S1y[W];
+  int bx, by;
+  esk_axis<ORDER>(x0[0], x1[0], bx, S0x, S1x);
+  esk_axis<ORDER>(x0[1], x1[1], by, S0y, S1y);
+  int xo[W], yo[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
+  const R cx = k.jx * w, cy = k.jy * w;
+  if constexpr (DIM == 2) {
+    const R cz = k.q * w * vz_bar * R(1.0 / 6.0);
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const R hy = cx * R(0.5) * (S0y[b] + S1y[b]);
+      R acc = R(0);
+#pragma unroll
+      for (int a = 0; a < W - 1; ++a) {
+        acc += (S1x[a] - S0x[a]) * hy;
+        A.add(F_JX, yo[b] + xo[a], acc);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const R hx = cy * R(0.5) * (S0x[a] + S1x[a]);
+      R acc = R(0);
+#pragma unroll
+      for (int b = 0; b < W - 1; ++b) {
+        acc += (S1y[b] - S0y[b]) * hx;
+        A.add(F_JY, yo[b] + xo[a], acc);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const R ay = R(2) * S0y[b] + S1y[b], by2 = S0y[b] + R(2) * S1y[b];
+#pragma unroll
+      for (int a = 0; a < W; ++a) A.add(F_JZ, yo[b] + xo[a], cz * (S0x[a] * ay + S1x[a] * by2));
+    }
+    if (with_rho) {
+      const R qw = k.q * w;
+#pragma unroll
+      for (int b = 0; b < W; ++b)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+          A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
+          A.add(F_R1, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
+        }
+    }
+  } else {
+    R S0z[W], S1z[W];
+    int bz;
+    esk_axis<ORDER>(x0[2], x1[2], bz, S0z, S1z);
+    int zo[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) zo[a] = A.zo(c[2] + bz + a);
+    const R cz = k.jz * w;
+    const R sixth = R(1.0 / 6.0);
+    // Jx: running sum along x of dSx * Ryz
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc)
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const R ryz = cx * sixth * (S0y[b] * (R(2) * S0z[cc] + S1z[cc]) +
+                                    S1y[b] * (S0z[cc] + R(2) * S1z[cc]));
+        R acc = R(0);
+#pragma unroll
+        for (int a = 0; a < W - 1; ++a) {
+          acc += (S1x[a] - S0x[a]) * ryz;
+          A.add(F_JX, zo[cc] + yo[b] + xo[a], acc);
+        }
+      }
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc)
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        const R rxz = cy * sixth * (S0x[a] * (R(2) * S0z[cc] + S1z[cc]) +
+                                    S1x[a] * (S0z[cc] + R(2) * S1z[cc]));
+        R acc = R(0);
+#pragma unroll
+        for (int b = 0; b < W - 1; ++b) {
+          acc += (S1y[b] - S0y[b]) * rxz;
+          A.add(F_JY, zo[cc] + yo[b] + xo[a], acc);
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        const R rxy = cz * sixth * (S0x[a] * (R(2) * S0y[b] + S1y[b]) +
+                                    S1x[a] * (S0y[b] + R(2) * S1y[b]));
+        R acc = R(0);
+#pragma unroll
+        for (int cc = 0; cc < W - 1; ++cc) {
+          acc += (S1z[cc] - S0z[cc]) * rxy;
+          A.add(F_JZ, zo[cc] + yo[b] + xo[a], acc);
+        }
+      }
+    if (with_rho) {
+      const R qw = k.q * w;
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc)
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            const int off = zo[cc] + yo[b] + xo[a];
+            A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
+            A.add(F_R1, off, qw * S1x[a] * S1y[b] * S1z[cc]);
+          }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Particle state in (cell, offset) form.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+struct PState {
+  int c[3];      // global cell
+  R o[3];        // offsets in [0,1)
+  R u[3];
+  R w;
+  bool alive;
+};
+
+__device__ __forceinline__ void unpack_cell(int32_t cell, int dim, int c[3]) {
+  if (dim == 2) {
+    c[0] = cell & 0xFFFF;
+    c[1] = cell >> 16;
+    c[2] = 0;
+  } else {
+    c[0] = cell & 0x7FF;
+    c[1] = (cell >> 11) & 0x7FF;
+    c[2] = cell >> 22;
+  }
+}
+__device__ __forceinline__ int32_t pack_cell(const int c[3], int dim) {
+  return dim == 2 ? (c[1] << 16) | c[0] : (c[2] << 22) | (c[1] << 11) | c[0];
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void load_particle(const SegDesc& s, const RunDesc& r, int64_t p,
+                                              PState<R>& ps) {
+  if constexpr (sizeof(R) == 4) {
+    const int32_t cell = ((const int32_t*)s.p[P_CELL])[p];
+    unpack_cell(cell < 0 ? 0 : cell, DIM, ps.c);
+    // a cell outside the box cannot come from the library; treat it like a dead slot
+    ps.alive = cell >= 0 && ps.c[0] < r.nx && ps.c[1] < r.ny && (DIM == 2 || ps.c[2] < r.nz);
+    ps.o[0] = ((const float*)s.p[P_OX])[p];
+    ps.o[1] = ((const float*)s.p[P_OY])[p];
+    ps.o[2] = DIM == 3 ? ((const float*)s.p[P_OZ])[p] : 0.f;
+  } else {
+    const double h[3] = {r.dx, r.dy, r.dz};
+    const int n[3] = {r.nx, r.ny, r.nz};
+    const double x = ((const double*)s.p[P_X])[p];
+    ps.alive = x >= 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d < DIM) {
+        const double X = ((const double*)s.p[P_X + d])[p] / h[d];
+        // positions outside [0, L] (or NaN) cannot come from the library: dead slot
+        if (!(X >= 0.0 && X <= (double)n[d])) ps.alive = false;
+        const double f = floor_clamped<double>(X, 0.0, (double)n[d]);
+        int ci = (int)f;
+        ps.o[d] = X - f;
+        ci = ci >= n[d] ? ci - n[d] : ci;
+        ps.c[d] = ci;
+      } else {
+        ps.c[d] = 0;
+        ps.o[d] = 0.0;
+      }
+    }
+  }
+  ps.u[0] = ((const R*)s.p[P_UX])[p];
+  ps.u[1] = ((const R*)s.p[P_UY])[p];
+  ps.u[2] = ((const R*)s.p[P_UZ])[p];
+  ps.w = ((const R*)s.p[P_W])[p];
+}
+
+// New cell and offset from the end offset x1 (relative to the start cell).  If the offset
+// rounds up to 1 (x1 a tiny negative number) the particle is put at the start of the cell
+// it came from instead; the error is below half an ulp of 1.
+template <typename R>
+__device__ __forceinline__ void advance_cell(int& c, R& o, R x1, int n) {
+  const R f = floor_clamped<R>(x1, R(-1), R(1));
+  int k = (int)f;
+  R on = x1 - f;
+  if (on >= R(1)) { on = R(0); k += 1; }
+  c = wrapi(c + k, n);
+  o = on;
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void store_particle(const SegDesc& s, const RunDesc& r, int64_t p,
+                                               const PState<R>& ps) {
+  if constexpr (sizeof(R) == 4) {
+    ((int32_t*)s.p[P_CELL])[p] = pack_cell(ps.c, DIM);
+    ((float*)s.p[P_OX])[p] = ps.o[0];
+    ((float*)s.p[P_OY])[p] = ps.o[1];
+    if (DIM == 3) ((float*)s.p[P_OZ])[p] = ps.o[2];
+  } else {
+    const double h[3] = {r.dx, r.dy, r.dz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ((double*)s.p[P_X + d])[p] = ((double)ps.c[d] + ps.o[d]) * h[d];
+  }
+  ((R*)s.p[P_UX])[p] = ps.u[0];
+  ((R*)s.p[P_UY])[p] = ps.u[1];
+  ((R*)s.p[P_UZ])[p] = ps.u[2];
+}
+
+// The particle part of Algorithm 1 for one particle: half push, gather at the half position,
+// Boris, second half push.  Fields come through accessor A whose frame has the particle's
+// start cell at a[].  On return x1 holds the end offsets relative to the start cell and
+// vz_bar the mean z velocity of the step (2D Jz).
+template <int DIM, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
+                                     const PushConst<R>& k, R x1[3], R& vz_bar, R& gamma1) {
+  const R ig0 = rsq<R>(R(1) + ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2]);
+  const R hd[3] = {k.hdx, k.hdy, k.hdz};
+  R xh[3];
+  int gc[3];
+  R go[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) {
+      xh[d] = ps.o[d] + hd[d] * ps.u[d] * ig0;
+      const R f = floor_clamped<R>(xh[d], R(-1), R(1));
+      gc[d] = a[d] + (int)f;
+      go[d] = xh[d] - f;
+    } else {
+      xh[d] = R(0); gc[d] = 0; go[d] = R(0);
+    }
+  }
+  R E[3], B[3];
+  gather<DIM, ORDER>(A, gc, go, E, B);
+  const R uz0 = ps.u[2];
+  boris<R>(ps.u, E, B, k.qdt2m);
+  const R u2 = ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2];
+  const R ig1 = rsq<R>(R(1) + u2);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x1[d] = d < DIM ? xh[d] + hd[d] * ps.u[d] * ig1 : R(0);
+  vz_bar = R(0.5) * (uz0 * ig0 + ps.u[2] * ig1);
+  gamma1 = R(1) / ig1;
+}
+
+}  // namespace lpic

@@ -1,0 +1,309 @@
+"""Python harness over the C ABI: device memory as torch tensors, named-stage hooks.
+
+``Simulation`` owns the field and particle tensors of one box or an ensemble of boxes and
+drives ``lpic_step`` (Algorithm 1 of the paper, Sec. 3.3).  Callbacks follow the paper's
+callback system (Sec. 2.2): a function attached to a named stage with an interval (whole
+steps, simulation time, or a predicate) that sees the full state, here as torch tensors on
+the GPU.  Every step of the hot path runs in the HIP library; this module only marshals.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Callable, Dict, List, Optional, Sequence, Union
+
+import numpy as np
+import torch
+
+from . import lpic as L
+from .workloads import Workload
+
+FIELD_NAMES = ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz")
+
+
+def torch_dtype(prec):
+    return torch.float32 if prec == L.F32_CELLOFS else torch.float64
+
+
+def grid_struct(wl: Workload) -> L.Grid:
+    return L.Grid(wl.ndim, wl.nx, wl.ny, wl.nz if wl.ndim == 3 else 1, wl.dx, wl.dy,
+                  wl.dz if wl.ndim == 3 else 1.0, wl.dt, wl.rho_bg)
+
+
+class DeviceFields:
+    """Yee arrays of one box (flat, x fastest) plus rho at the start / end of a step."""
+
+    def __init__(self, wl: Workload, prec, device="cuda", with_rho=True):
+        dt = torch_dtype(prec)
+        n = wl.ncell
+        self.t: Dict[str, torch.Tensor] = {k: torch.zeros(n, dtype=dt, device=device)
+                                           for k in FIELD_NAMES}
+        for k, v in wl.fields.items():
+            self.t[k].copy_(torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(dt))
+        self.rho0 = torch.zeros(n, dtype=dt, device=device) if with_rho else None
+        self.rho1 = torch.zeros(n, dtype=dt, device=device) if with_rho else None
+
+    def struct(self) -> L.Fields:
+        return L.Fields(*[L.ptr(self.t[k]) for k in FIELD_NAMES], L.ptr(self.rho0),
+                        L.ptr(self.rho1))
+
+    def numpy(self) -> Dict[str, np.ndarray]:
+        out = {k: v.detach().double().cpu().numpy() for k, v in self.t.items()}
+        if self.rho0 is not None:
+            out["rho0"] = self.rho0.double().cpu().numpy()
+            out["rho1"] = self.rho1.double().cpu().numpy()
+        return out
+
+
+class DeviceSpecies:
+    """Structure-of-arrays particle storage of one species on the GPU."""
+
+    def __init__(self, ndim, n, q, m, order, prec, device="cuda"):
+        self.ndim, self.n, self.q, self.m, self.order, self.prec = ndim, n, q, m, order, prec
+        dt = torch_dtype(prec)
+        e = lambda d: torch.empty(n, dtype=d, device=device)
+        self.a: Dict[str, torch.Tensor] = {}
+        if prec == L.F32_CELLOFS:
+            self.a["cell"] = e(torch.int32)
+            for k in ("ox", "oy", "oz")[:ndim]:
+                self.a[k] = e(torch.float32)
+        else:
+            for k in ("x", "y", "z")[:ndim]:
+                self.a[k] = e(torch.float64)
+        for k in ("ux", "uy", "uz", "w"):
+            self.a[k] = e(dt)
+
+    @classmethod
+    def from_init(cls, grid: L.Grid, s, prec, device="cuda", stream=None):
+        d = cls(grid.ndim, s.n, s.q, s.m, s.order, prec, device)
+        dt = torch_dtype(prec)
+        for k in ("ux", "uy", "uz", "w"):
+            d.a[k].copy_(torch.from_numpy(np.ascontiguousarray(getattr(s, k), dtype=np.float64)).to(dt))
+        d.load_positions(grid, s.x, s.y, s.z, stream)
+        return d
+
+    def like(self):
+        return DeviceSpecies(self.ndim, self.n, self.q, self.m, self.order, self.prec,
+                             next(iter(self.a.values())).device)
+
+    def struct(self) -> L.Species:
+        g = lambda k: L.ptr(self.a.get(k))
+        return L.Species(self.n, self.q, self.m, self.order, 0, g("cell"), g("ox"), g("oy"),
+                         g("oz"), g("x"), g("y"), g("z"), g("ux"), g("uy"), g("uz"), g("w"))
+
+    def load_positions(self, grid, x, y, z=None, stream=None):
+        if self.n == 0:
+            return
+        dev = next(iter(self.a.values())).device
+        t = [torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(dev)
+             if v is not None else None for v in (x, y, z)]
+        L.lpic_load_positions(grid, self.struct(), L.ptr(t[0]), L.ptr(t[1]), L.ptr(t[2]),
+                              self.prec, stream)
+        torch.cuda.current_stream().synchronize()
+
+    def positions(self, grid, stream=None) -> List[np.ndarray]:
+        """Absolute FP64 positions (dead particles: -1)."""
+        if self.n == 0:
+            return [np.zeros(0)] * self.ndim
+        dev = next(iter(self.a.values())).device
+        t = [torch.empty(self.n, dtype=torch.float64, device=dev) for _ in range(self.ndim)]
+        t3 = t + [None] * (3 - self.ndim)
+        L.lpic_store_positions(grid, self.struct(), L.ptr(t3[0]), L.ptr(t3[1]), L.ptr(t3[2]),
+                               self.prec, stream)
+        return [v.cpu().numpy() for v in t]
+
+    def numpy(self, k) -> np.ndarray:
+        return self.a[k].detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------------------------------
+# callbacks (Sec. 2.2)
+# ------------------------------------------------------------------------------------------
+class Callback:
+    """Stateful callback: subclass, set `stage` and `interval`, implement __call__(sim)."""
+
+    stage: str = "LOOP_END"
+    interval: Union[int, float, Callable, None] = 1
+
+    def __call__(self, sim: "Simulation"):
+        raise NotImplementedError
+
+    def due(self, sim: "Simulation") -> bool:
+        iv = self.interval
+        if iv is None:
+            return True
+        if callable(iv):
+            return bool(iv(sim))
+        if isinstance(iv, int):
+            return sim.nstep % iv == 0
+        # simulation-time interval: fire on the first step at or past each multiple
+        k = int(np.floor(sim.time / iv + 1e-9))
+        if k > getattr(self, "_last_k", -1):
+            self._last_k = k
+            return True
+        return False
+
+
+def callback(stage="LOOP_END", interval: Union[int, float, Callable, None] = 1):
+    """Decorator: attach a plain function f(sim) to a named stage with an interval."""
+
+    def wrap(fn):
+        class _Fn(Callback):
+            pass
+
+        cb = _Fn()
+        cb.stage = stage
+        cb.interval = interval
+        cb.__call__ = None
+        cb.fn = fn
+        cb.__name__ = getattr(fn, "__name__", "callback")
+        return cb
+
+    return wrap
+
+
+def _run_cb(cb, sim):
+    fn = getattr(cb, "fn", None)
+    return fn(sim) if fn is not None else cb(sim)
+
+
+# ------------------------------------------------------------------------------------------
+class Simulation:
+    """One box or an ensemble of independent boxes advanced by lpic_step."""
+
+    def __init__(self, workloads: Union[Workload, Sequence[Workload]], prec=L.F32_CELLOFS,
+                 tiling=(16, 16, 8), halo=4, chunk=2048, sort_interval=10, diag_interval=0,
+                 use_graph=True, device="cuda", with_rho=True, stream=None):
+        wls = [workloads] if isinstance(workloads, Workload) else list(workloads)
+        self.workloads = wls
+        self.prec = prec
+        self.ndim = wls[0].ndim
+        self.stream = stream
+        self.grids = [grid_struct(w) for w in wls]
+        self.fields = [DeviceFields(w, prec, device, with_rho) for w in wls]
+        self.species: List[DeviceSpecies] = []
+        self.alt: List[DeviceSpecies] = []
+        self.species_run: List[int] = []
+        for r, w in enumerate(wls):
+            for s in w.species:
+                d = DeviceSpecies.from_init(self.grids[r], s, prec, device, stream)
+                self.species.append(d)
+                self.alt.append(d.like())
+                self.species_run.append(r)
+        self.options = L.Options(L.Tiling(tiling[0], tiling[1], tiling[2] if self.ndim == 3 else 1,
+                                          halo, chunk, 0),
+                                 sort_interval, diag_interval, int(use_graph), 0)
+        self.h = L.lpic_sim_create(self.grids, [f.struct() for f in self.fields],
+                                   [s.struct() for s in self.species], self.species_run,
+                                   [a.struct() for a in self.alt], prec, self.options, stream)
+        self._hook_refs = []
+        self._callbacks: List[Callback] = []
+        self.nstep = 0
+        self.dt = wls[0].dt
+
+    # -- state ------------------------------------------------------------------------------
+    @property
+    def time(self):
+        return self.nstep * self.dt
+
+    def current(self, i) -> DeviceSpecies:
+        """The buffer that holds species i now (the sort alternates two buffers)."""
+        cur = L.lpic_get_species(self.h, i)
+        a = self.species[i]
+        key = "cell" if self.prec == L.F32_CELLOFS else "x"
+        if a.n == 0 or cur.ux == L.ptr(a.a["ux"]):
+            return a
+        b = self.alt[i]
+        assert cur.ux == L.ptr(b.a["ux"]) and (getattr(cur, key) == L.ptr(b.a[key]))
+        return b
+
+    def positions(self, i):
+        r = self.species_run[i]
+        return self.current(i).positions(self.grids[r], self.stream)
+
+    def step(self, n=1):
+        start = self.nstep
+        L.lpic_step(self.h, n)
+        self.nstep = start + n
+
+    def diagnostics(self, r=0):
+        d = L.lpic_get_diagnostics(self.h, r)
+        return dict(field_energy=d[0], kinetic_energy=d[1], continuity=d[2], gauss=d[3],
+                    step=int(d[4]))
+
+    def stats(self):
+        s = L.lpic_get_stats(self.h)
+        return dict(steps=s.steps, sorts=s.sorts, fused=bool(s.fused), graph=bool(s.graph),
+                    fused_ms=s.fused_ms, fused_launches=s.fused_launches,
+                    halo_escapes=s.halo_escapes)
+
+    def set_timing(self, on):
+        L.lpic_set_timing(self.h, on)
+
+    def set_options(self, **kw):
+        o = self.options
+        t = o.tiling
+        tiling = kw.get("tiling", (t.tx, t.ty, t.tz))
+        self.options = L.Options(L.Tiling(tiling[0], tiling[1], tiling[2] if self.ndim == 3 else 1,
+                                          kw.get("halo", t.halo), kw.get("chunk", t.chunk), 0),
+                                 kw.get("sort_interval", o.sort_interval),
+                                 kw.get("diag_interval", o.diag_interval),
+                                 int(kw.get("use_graph", o.use_graph)), 0)
+        L.lpic_set_options(self.h, self.options)
+
+    def autotune(self, candidates: Sequence[dict], steps_each=3):
+        opts = []
+        for c in candidates:
+            t = c.get("tiling", (16, 16, 8))
+            opts.append(L.Options(L.Tiling(t[0], t[1], t[2] if self.ndim == 3 else 1,
+                                           c.get("halo", 4), c.get("chunk", 2048), 0),
+                                  c.get("sort_interval", self.options.sort_interval),
+                                  c.get("diag_interval", self.options.diag_interval),
+                                  int(c.get("use_graph", self.options.use_graph)), 0))
+        before = L.lpic_get_stats(self.h).steps
+        best = L.lpic_autotune(self.h, opts, steps_each)
+        self.nstep += L.lpic_get_stats(self.h).steps - before
+        self.options = best
+        t = best.tiling
+        return dict(tiling=(t.tx, t.ty, t.tz), halo=t.halo, chunk=t.chunk,
+                    sort_interval=best.sort_interval, use_graph=bool(best.use_graph))
+
+    # -- hooks and callbacks --------------------------------------------------------------
+    def register_hook(self, stage: str, fn: Callable[["Simulation", str, int], Optional[int]]):
+        """Raw hook: fn(sim, stage_name, step) -> 0/None to continue, non-zero to stop."""
+        def c_hook(h, st, step, user):
+            try:
+                self.nstep = int(step)
+                rc = fn(self, L.STAGES[st], int(step))
+                return int(rc or 0)
+            except Exception:  # a Python error stops the step with LPIC_EHOOK
+                import traceback
+                traceback.print_exc()
+                return 1
+        cf = L.HOOK_FN(c_hook)
+        self._hook_refs.append(cf)
+        L.lpic_register_hook(self.h, L.STAGE[stage], cf, None)
+
+    def add_callback(self, cb: Callback):
+        self._callbacks.append(cb)
+
+        def hook(sim, stage, step):
+            if cb.due(sim):
+                return _run_cb(cb, sim)
+            return 0
+        self.register_hook(cb.stage, hook)
+
+    def clear_hooks(self):
+        L.lpic_clear_hooks(self.h)
+        self._hook_refs.clear()
+        self._callbacks.clear()
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lpic_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
