@@ -109,7 +109,8 @@ lpic_status check_species(const lpic_species* s, int ndim, int prec) {
   return LPIC_OK;
 }
 
-lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec) {
+lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec,
+                         bool need_lds = true) {
   if (!t) return fail(LPIC_EINVAL, "tiling is NULL");
   const int nd = g->ndim;
   if (ilog2_exact(t->tx) < 0 || ilog2_exact(t->ty) < 0 || (nd == 3 && ilog2_exact(t->tz) < 0))
@@ -119,7 +120,7 @@ lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec) {
     return fail(LPIC_EINVAL, "halo larger than the grid");
   if (t->chunk < 1) return fail(LPIC_EINVAL, "chunk must be >= 1");
   const size_t smem = fused_smem_bytes(prec, nd, t->tx, t->ty, nd == 3 ? t->tz : 1, t->halo, 1);
-  if (smem > 160 * 1024)
+  if (need_lds && smem > 160 * 1024)
     return fail(LPIC_EINVAL, "tile + halo needs %zu bytes of LDS (limit 163840)", smem);
   return LPIC_OK;
 }
@@ -238,6 +239,11 @@ int64_t max_chunks_of(int64_t ntiles, int64_t n, int chunk) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// The fused kernel gives XCD x (workgroups x, x+8, x+16, ...) the contiguous chunk range
+// [x*per, (x+1)*per) with per = ceil(nchunks/8); covering every chunk needs 8*per workgroups,
+// so the grid is the chunk bound rounded up to a multiple of 8.
+int64_t fused_grid(int64_t max_chunks) { return (max_chunks + 7) / 8 * 8; }
+
 }  // namespace
 
 // =======================================================================================
@@ -321,7 +327,7 @@ lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_specie
   CHK(check_grid(grid, prec));
   CHK(check_species(sp, grid->ndim, prec));
   CHK(check_species(alt, grid->ndim, prec));
-  CHK(check_tiling(tiling, grid, prec));
+  CHK(check_tiling(tiling, grid, prec, false));
   if (alt->n != sp->n) return fail(LPIC_EINVAL, "alt must have as many slots as sp");
   if (!tile_offsets) return fail(LPIC_EINVAL, "tile_offsets is NULL");
   const size_t need = lpic_sort_ws_bytes(grid, tiling, sp->n);
@@ -385,8 +391,8 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
   HIPCHK(prepare_fused(prec, grid->ndim, smem));
   const int64_t maxch = max_chunks_of(r.ntiles, sp->n, t.chunk);
-  launch_fused(T, prec, grid->ndim, (int)maxch, smem, chunks, nchunks, with_rho, kinetic, 0,
-               nullptr, stream);
+  launch_fused(T, prec, grid->ndim, (int)fused_grid(maxch), smem, chunks, nchunks, with_rho,
+               kinetic, 0, nullptr, stream);
   return last_launch("fused");
 }
 
@@ -664,7 +670,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, b
         }
         HIPCHK(hipEventRecord(e0, st));
       }
-      launch_fused(Tc, s->prec, s->ndim, (int)s->max_chunks, diag ? s->smem_rho : s->smem,
+      launch_fused(Tc, s->prec, s->ndim, (int)fused_grid(s->max_chunks), diag ? s->smem_rho : s->smem,
                    s->chunks, s->nchunks, diag ? 1 : 0, nullptr, diag ? 1 : 0, s->escapes, st);
       CHK(last_launch("fused"));
       if (s->timing) {

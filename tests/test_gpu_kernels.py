@@ -77,6 +77,15 @@ def test_gather_push_then_deposit(prec, ndim, order):
     compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"), what="deposit")
 
 
+def _tiling(prec, ndim, chunk):
+    """Tiles that span several tiles of the small boxes with a ragged edge, and fit LDS."""
+    if ndim == 2:
+        return L.Tiling(16, 8, 1, 4, chunk, 0)
+    if prec == L.F64_ABS:
+        return L.Tiling(8, 4, 4, 3, chunk, 0)
+    return L.Tiling(8, 8, 4, 3, chunk, 0)
+
+
 def _sorted_state(wl, prec, tiling):
     grid, F, S, orc = device_state(wl, prec, random_fields_seed=9, field_scale=0.5)
     d = S[0]
@@ -113,7 +122,7 @@ def test_sort_is_an_exact_tile_grouping(prec, ndim):
     # kill a few particles: they must end up after every tile
     dead = np.arange(0, n, 97)
     wl.species[0].x[dead] = -1.0
-    tiling = L.Tiling(16, 8, 4, 3, 64, 0)
+    tiling = _tiling(prec, ndim, chunk=64)
     grid, F, d0, alt, offs, orc = _sorted_state(wl, prec, tiling)
     # after the call the struct's pointers were exchanged: `alt` tensors hold the sorted data
     cur, before = alt, d0
@@ -142,7 +151,7 @@ def test_sort_is_an_exact_tile_grouping(prec, ndim):
 def test_fused_matches_oracle(prec, ndim, order, displaced):
     banner(f"fused prec={PNAME[prec]} ndim={ndim} order={order} displaced={displaced}")
     wl = small_2d(order) if ndim == 2 else small_3d(order)
-    tiling = L.Tiling(16, 8, 4, 4, 97, 0)     # odd chunk size: ragged chunks
+    tiling = _tiling(prec, ndim, chunk=97)    # odd chunk size: ragged chunks
     grid, F, d0, cur, offs, orc = _sorted_state(wl, prec, tiling)
     o = orc.species[0]
     # the oracle follows the sorted order
@@ -289,3 +298,31 @@ def test_offset_rounding_edge():
     pos = d.positions(grid)[0]
     exp = np.mod(sp.x - 1e-7 * 0.5 * wl.dt, 1.6)
     assert np.abs(periodic_diff(pos, sp.x, 1.6)).max() < 1e-7
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PNAME.get)
+@pytest.mark.parametrize("n", [540, 577, 1000])
+def test_fused_covers_every_chunk(prec, n):
+    """One tile holding every particle: the chunk count (9, 10, 16 for chunk 64) is close to
+    the launch bound, so each of the eight XCD ranges must still be covered by workgroups."""
+    banner(f"fused chunk coverage prec={PNAME[prec]} n={n}")
+    wl = W.thermal_2d(nx=16, ny=16, dx=0.1, ppc=4, T=0.1, order=2, seed=n)
+    sp = wl.species[0]
+    for k in ("x", "y", "ux", "uy", "uz", "w"):
+        setattr(sp, k, getattr(sp, k)[:n].copy())
+    tiling = L.Tiling(16, 16, 1, 4, 64, 0)
+    grid, F, d0, cur, offs, orc = _sorted_state(wl, prec, tiling)
+    o = orc.species[0]
+    pos = cur.positions(grid)
+    o.x[:], o.y[:] = pos[0], pos[1]
+    for k in ("ux", "uy", "uz", "w"):
+        getattr(o, k)[:] = cur.numpy(k)
+    wsb = L.lpic_fused_ws_bytes(grid, tiling, cur.n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    L.lpic_push_deposit_fused(grid, F.struct(), cur.struct(), tiling, offs.data_ptr(),
+                              ws.data_ptr(), wsb, 1, None, prec)
+    torch.cuda.synchronize()
+    orc.zero_currents()
+    orc.push_deposit(o)
+    compare_particles(grid, cur, o, prec, what="fused push")
+    compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"), what="fused deposit")

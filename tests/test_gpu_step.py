@@ -67,7 +67,8 @@ def test_fp64_steps_match_oracle(ndim, order, graph):
     wl = _wl(order) if ndim == 2 else W.thermal_3d(n=12, dx=0.1, ppc=2, T=0.05, order=order, seed=4)
     _tag_weights(wl)
     nsteps = 12
-    sim = Simulation(wl, prec=L.F64_ABS, tiling=(8, 8, 4), halo=4, chunk=128, sort_interval=5,
+    tiling, halo = ((8, 8, 1), 4) if ndim == 2 else ((8, 4, 4), 3)
+    sim = Simulation(wl, prec=L.F64_ABS, tiling=tiling, halo=halo, chunk=128, sort_interval=5,
                      diag_interval=3, use_graph=graph)
     orc = _oracle_like_gpu(sim, wl)
     sim.step(nsteps)
