@@ -72,7 +72,7 @@ def lib():
         L.orc_deposit_rho.argtypes = [ctypes.POINTER(Grid), _dp, ctypes.c_int32, ctypes.c_double,
                                       ctypes.c_double, _dp]
         L.orc_push_deposit.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
-                                       ctypes.POINTER(Species), ctypes.c_int32, _dp, _dp, _dp, _dp]
+                                       ctypes.POINTER(Species), ctypes.c_int32, _dp, _dp, _dp]
         L.orc_gather_push.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
                                       ctypes.POINTER(Species)]
         L.orc_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
@@ -170,14 +170,14 @@ class OracleSim:
         lib().orc_gather_push(ctypes.byref(self.grid), ctypes.byref(fs), ctypes.byref(st))
 
     def push_deposit(self, s: OracleSpecies, deposit=True):
-        """Push one species and deposit its current; returns start positions and vz."""
+        """Push one species and deposit its current; returns the deposit path starts."""
         n = s.n
-        x0, y0, z0, vz0 = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+        xs, ys, zs = np.zeros(n), np.zeros(n), np.zeros(n)
         fs = self.fields_struct()
         st = s.struct()
         lib().orc_push_deposit(ctypes.byref(self.grid), ctypes.byref(fs), ctypes.byref(st),
-                               int(deposit), _ptr(x0), _ptr(y0), _ptr(z0), _ptr(vz0))
-        return x0, y0, z0, vz0
+                               int(deposit), _ptr(xs), _ptr(ys), _ptr(zs))
+        return xs, ys, zs
 
     def deposit_particle(self, order, q, w, p0, p1, vz_bar=0.0):
         fs = self.fields_struct()

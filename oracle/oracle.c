@@ -261,10 +261,14 @@ static double wrap_pos(double p, double L) {
 }
 
 /* Algorithm 1, particle loop of one species: push positions by dt/2, interpolate E and B
- * there, Boris push of the momentum by dt, push positions by dt/2 with the new velocity,
- * deposit the current of the straight path from the start to the end position. */
+ * there, Boris push of the momentum by dt, push positions by dt/2 with the new velocity.
+ * The current follows Sec. 3.1 and Eq. 3: the deposit traces the trajectory over one dt
+ * centred on the end of the step, i.e. the straight path from the half-step position
+ * x^{n+1/2} to x^{n+1/2} + dt v^{n+1}, which gives J at the whole time level n+1 that
+ * Eq. 3 pairs with E^{n+1/2} -> E^{n+3/2}.  The stored position x^{n+1} is the midpoint of
+ * that path. */
 static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
-                            double *x0o, double *y0o, double *z0o, double *vz0o) {
+                            double *xso, double *yso, double *zso) {
   int nd = g->ndim;
   double dt = g->dt;
   double L[3] = {g->nx * g->dx, g->ny * g->dy, g->nz * g->dz};
@@ -273,7 +277,6 @@ static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, in
     double p0[3] = {s->x[p], s->y[p], (nd == 3) ? s->z[p] : 0.0};
     double u[3] = {s->ux[p], s->uy[p], s->uz[p]};
     double g0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    double vz0 = u[2] / g0;
     double ph[3] = {p0[0], p0[1], p0[2]};
     for (int d = 0; d < nd; ++d) ph[d] = p0[d] + 0.5 * dt * u[d] / g0;
     double E[3], B[3];
@@ -281,16 +284,18 @@ static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, in
     orc_boris(u, E, B, s->q, s->m, dt);
     double g1 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     double p1[3] = {ph[0], ph[1], ph[2]};
-    for (int d = 0; d < nd; ++d) p1[d] = ph[d] + 0.5 * dt * u[d] / g1;
-    if (x0o) x0o[p] = p0[0];
-    if (y0o) y0o[p] = p0[1];
-    if (z0o) z0o[p] = p0[2];
-    if (vz0o) vz0o[p] = vz0;
+    double pe[3] = {ph[0], ph[1], ph[2]};
+    for (int d = 0; d < nd; ++d) {
+      p1[d] = ph[d] + 0.5 * dt * u[d] / g1;
+      pe[d] = ph[d] + dt * u[d] / g1;
+    }
+    if (xso) xso[p] = ph[0];
+    if (yso) yso[p] = ph[1];
+    if (zso) zso[p] = ph[2];
     if (deposit) {
-      double vz_bar = 0.5 * (vz0 + u[2] / g1);
-      orc_deposit_particle(g, f, s->order, s->q, s->w[p], p0, p1, vz_bar);
-      if (f->rho0) orc_deposit_rho(g, f->rho0, s->order, s->q, s->w[p], p0);
-      if (f->rho1) orc_deposit_rho(g, f->rho1, s->order, s->q, s->w[p], p1);
+      orc_deposit_particle(g, f, s->order, s->q, s->w[p], ph, pe, u[2] / g1);
+      if (f->rho0) orc_deposit_rho(g, f->rho0, s->order, s->q, s->w[p], ph);
+      if (f->rho1) orc_deposit_rho(g, f->rho1, s->order, s->q, s->w[p], pe);
     }
     s->x[p] = wrap_pos(p1[0], L[0]);
     s->y[p] = wrap_pos(p1[1], L[1]);
@@ -302,16 +307,17 @@ static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, in
 }
 
 void orc_push_deposit(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
-                      double *x0, double *y0, double *z0, double *vz0) {
-  advance_species(g, f, s, deposit, x0, y0, z0, vz0);
+                      double *xs, double *ys, double *zs) {
+  advance_species(g, f, s, deposit, xs, ys, zs);
 }
 
 void orc_gather_push(const orc_grid *g, const orc_fields *f, orc_species *s) {
-  advance_species(g, (orc_fields *)f, s, 0, NULL, NULL, NULL, NULL);
+  advance_species(g, (orc_fields *)f, s, 0, NULL, NULL, NULL);
 }
 
 /* Algorithm 1: one timestep.  The first E half uses the current still held in J (the one
- * deposited by the previous step, zero before the first step). */
+ * deposited by the previous step, zero before the first step), so that together with the
+ * second half of the previous step E advances by a whole dt with that J, as in Eq. 3. */
 void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies) {
   int64_t n = ncell(g);
   orc_yee_e(g, f, 0.5);
@@ -321,7 +327,7 @@ void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecie
   memset(f->jz, 0, sizeof(double) * n);
   if (f->rho0) memset(f->rho0, 0, sizeof(double) * n);
   if (f->rho1) memset(f->rho1, 0, sizeof(double) * n);
-  for (int s = 0; s < nspecies; ++s) advance_species(g, f, &sp[s], 1, NULL, NULL, NULL, NULL);
+  for (int s = 0; s < nspecies; ++s) advance_species(g, f, &sp[s], 1, NULL, NULL, NULL);
   orc_yee_b(g, f, 0.5);
   orc_yee_e(g, f, 0.5);
 }
@@ -361,7 +367,8 @@ static double div_at_node(const orc_grid *g, const double *ax, const double *ay,
   return d;
 }
 
-/* Discrete continuity (Sec. 3.1): (rho1 - rho0)/dt + div J = 0 at every node. */
+/* Discrete continuity (Sec. 3.1): (rho1 - rho0)/dt + div J = 0 at every node, with rho0 and
+ * rho1 the charge at the two ends of the deposited paths. */
 double orc_continuity(const orc_grid *g, const orc_fields *f) {
   int nz = (g->ndim == 3) ? g->nz : 1;
   double rmax = 0.0, qmax = 0.0;

@@ -10,7 +10,8 @@
  *     half steps (Sec. 3.2, Eqs. 1-4), in normalised units c = eps0 = 1;
  *   - the per-step order of Algorithm 1 (Sec. 3.3): E half, B half, per species
  *     {position half push, interpolation, Boris momentum push, position half push,
- *     Esirkepov deposit}, then B half, E half;
+ *     Esirkepov deposit}, then B half, E half; the deposited path is the trajectory over
+ *     one dt centred on the end of the step (Sec. 3.1 and the time levels of Eq. 3);
  *   - the relativistic Boris push with u = gamma v (Sec. 3.1);
  *   - staggering-aware interpolation with a B-spline shape of order 1 (CIC) or 2
  *     (quadratic) (Sec. 3.1);
@@ -67,8 +68,9 @@ void orc_gather(const orc_grid *g, const orc_fields *f, int32_t order, const dou
 void orc_yee_e(const orc_grid *g, orc_fields *f, double frac);   /* E += frac*dt*(curl B - J) */
 void orc_yee_b(const orc_grid *g, orc_fields *f, double frac);   /* B -= frac*dt*curl E */
 
-/* Esirkepov deposit of one particle moving from p0 to p1 (absolute, unwrapped), adding
- * J into f.  vz_bar is the mean z velocity used for Jz in 2D (ignored in 3D). */
+/* Esirkepov deposit of one particle moving from p0 to p1 (absolute, unwrapped) during dt,
+ * adding J into f.  vz_bar is the z velocity along the path, used for Jz in 2D (ignored in
+ * 3D). */
 void orc_deposit_particle(const orc_grid *g, orc_fields *f, int32_t order, double q, double w,
                           const double p0[3], const double p1[3], double vz_bar);
 
@@ -77,11 +79,12 @@ void orc_deposit_rho(const orc_grid *g, double *rho, int32_t order, double q, do
                      const double pos[3]);
 
 /* Particle part of Algorithm 1 for one species: half position push, gather, Boris, half
- * position push, Esirkepov deposit into J (J is NOT zeroed here), optional rho0/rho1
- * deposits, periodic wrap.  If x0/y0/z0/vz0 are non-NULL they receive the start position
- * and start z velocity of every particle (for separate deposit checks). */
+ * position push; Esirkepov deposit into J (J is NOT zeroed here) of the path from the
+ * half-step position x^{n+1/2} to x^{n+1/2} + dt v^{n+1}; optional rho0/rho1 deposits at
+ * the two path ends; periodic wrap.  If xs/ys/zs are non-NULL they receive the path start
+ * x^{n+1/2} of every particle (unwrapped). */
 void orc_push_deposit(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
-                      double *x0, double *y0, double *z0, double *vz0);
+                      double *xs, double *ys, double *zs);
 
 /* Gather + push only (no deposit); positions are wrapped. */
 void orc_gather_push(const orc_grid *g, const orc_fields *f, orc_species *s);
