@@ -1,0 +1,236 @@
+"""Throughput of the PIC hot path on one MI355X: particle pushes per second.
+
+A step is one full pass of Algorithm 1 (Sec. 3.3) through lpic_step: field half updates,
+tile sort (every K steps), fused gather + Boris push + Esirkepov deposit over all species,
+field half updates, FP64 diagnostics every 10 steps.  A push is one alive macro-particle
+advanced through gather + push + deposit.
+
+Workload (default): 2D3V 2048x1024 Yee grid, dx = lambda/32, fully ionised hydrogen slab of
+20 n_c in cells x in [512, 768), electrons + protons at 32 ppc each (16,777,216 particles),
+T = 1 keV, quadratic shape, linearly polarised a0 = 10 Gaussian pulse initialised in the
+vacuum in front of the slab (periodic box), seeded synthetic data.  The FP32 cell+offset
+path is `value`; the plain FP64 path is reported beside it.
+
+Output: one JSON line (rank 0).  With --gpus > 1 the script exits: this build measures one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+KERNEL_SOURCES = ("paper_2607_13507_amd/csrc/lpic_device.hpp",
+                  "paper_2607_13507_amd/csrc/lpic_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_laser_slab_2048x1024_pmc.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_push(ndim, prec_f32, ppc_tot):
+    """Bytes the method must move per push (particle state in and out once; E, B read and J
+    written once per cell, amortised over the particles per cell)."""
+    if prec_f32:
+        part = 52 if ndim == 2 else 60
+        grid = 36
+    else:
+        part = 88 if ndim == 2 else 104
+        grid = 72
+    return part + grid / ppc_tot
+
+
+def read_traffic(launch_bytes_key="per_launch_bytes"):
+    """HBM bytes per fused launch from the committed PMC summary, if it was taken on the
+    current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[launch_bytes_key])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_workload(args):
+    from paper_2607_13507_amd import workloads as W
+    return W.laser_slab_2d(nx=args.nx, ny=args.ny, slab=(args.nx // 4, args.nx * 3 // 8),
+                           ppc=args.ppc, steps=args.steps)
+
+
+def run_gpu(wl, prec, args, steps, warmup, tune):
+    import torch
+    from paper_2607_13507_amd import lpic as L
+    from paper_2607_13507_amd.simulation import Simulation
+
+    sim = Simulation(wl, prec=prec, tiling=(args.tile, args.tile, 1), halo=args.halo,
+                     chunk=args.chunk, sort_interval=args.sort_interval, diag_interval=10,
+                     use_graph=True)
+    tuned = None
+    if tune:
+        cands = []
+        for t in (16, 32):
+            for ch in (1024, 2048, 4096, 8192):
+                cands.append(dict(tiling=(t, t, 1), halo=args.halo, chunk=ch,
+                                  sort_interval=args.sort_interval, use_graph=True))
+        tuned = sim.autotune(cands, steps_each=2)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    # timed region: eager launches with HIP events around every fused launch
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    sim.set_timing(False)
+    # the same number of steps again as captured graphs (no per-kernel events)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    diag = sim.diagnostics(0)
+    stg = sim.stats()
+    n = wl.nparticles
+    res = dict(ms_per_step=1e3 * (t1 - t0) / steps,
+               pushes_per_s=n * steps / (t1 - t0),
+               ms_per_step_graph=1e3 * (g1 - g0) / steps,
+               pushes_per_s_graph=n * steps / (g1 - g0),
+               fused_ms=st["fused_ms"] / max(1, st["fused_launches"]),
+               fused_launches=st["fused_launches"],
+               halo_escapes_per_push=stg["halo_escapes"] / max(1, n * stg["steps"]),
+               graph=stg["graph"], diagnostics=diag, tuned=tuned,
+               options=dict(tile=sim.options.tiling.tx, halo=sim.options.tiling.halo,
+                            chunk=sim.options.tiling.chunk,
+                            sort_interval=sim.options.sort_interval))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle (single thread) on one full step of the same workload."""
+    import oracle
+    orc = oracle.OracleSim.from_workload(wl)
+    t0 = time.perf_counter()
+    orc.step(1)
+    dt = time.perf_counter() - t0
+    return dict(value=wl.nparticles / dt, unit="particle-pushes/s", cores=1, kind="oracle",
+                sample=f"one full step (all {wl.nparticles} particles, {wl.nx}x{wl.ny} grid) "
+                       f"of the benchmark workload, FP64, single thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=2048)
+    ap.add_argument("--ny", type=int, default=1024)
+    ap.add_argument("--ppc", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--halo", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=2048)
+    ap.add_argument("--sort-interval", type=int, default=10)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2607_13507_amd import lpic as L
+    L.lib()   # the HIP library must be there; no fallback
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    wl = build_workload(args)
+    ppc_tot = 2 * args.ppc
+    f32 = run_gpu(wl, L.F32_CELLOFS, args, args.steps, args.warmup, args.autotune)
+    f64 = None
+    if not args.no_fp64:
+        s64 = max(5, args.steps // 5)
+        f64 = run_gpu(wl, L.F64_ABS, args, s64, max(2, args.warmup // 5), False)
+
+    bpp = algorithmic_bytes_per_push(2, True, ppc_tot)
+    launch_bytes = bpp * wl.nparticles
+    achieved = launch_bytes / (f32["fused_ms"] * 1e-3) / 1e9
+    traffic = read_traffic()
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="lpic::k_fused<float,2>", bytes_per_push=round(bpp, 3),
+                bytes_per_launch=int(launch_bytes), avg_launch_ms=round(f32["fused_ms"], 4),
+                launches=f32["fused_launches"], kernel_source_sha256=kernel_source_hash())
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl)
+    out = {
+        "metric": "particle-pushes/sec (gather+push+deposit) FP32 vs FP64, % HBM roofline",
+        "value": round(f32["pushes_per_s"], 1),
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c "
+                               f"cells x in [{args.nx // 4},{args.nx * 3 // 8}), e- + p+ "
+                               f"{args.ppc} ppc each ({wl.nparticles} particles), T=1 keV, "
+                               "quadratic, a0=10 pulse in-box (periodic stand-in for the "
+                               "boundary-injected laser), FP32 cell+offset",
+                   "particles": wl.nparticles, "grid": [args.nx, args.ny],
+                   "shape_order": 2, "sort_interval": f32["options"]["sort_interval"],
+                   "diag_interval": 10, "tiling": f32["options"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fused_pushes_per_s": round(wl.nparticles / (f32["fused_ms"] * 1e-3), 1),
+        "graph_mode": {"ms_per_step": round(f32["ms_per_step_graph"], 4),
+                       "pushes_per_s": round(f32["pushes_per_s_graph"], 1)},
+        "halo_escapes_per_push": f32["halo_escapes_per_push"],
+        "diagnostics_fp32": f32["diagnostics"],
+    }
+    if f64:
+        out["fp64"] = {"pushes_per_s": round(f64["pushes_per_s"], 1),
+                       "ms_per_step": round(f64["ms_per_step"], 4),
+                       "fused_avg_ms": round(f64["fused_ms"], 4),
+                       "fused_hbm_gbs": round(algorithmic_bytes_per_push(2, False, ppc_tot) *
+                                              wl.nparticles / (f64["fused_ms"] * 1e-3) / 1e9, 1),
+                       "graph_pushes_per_s": round(f64["pushes_per_s_graph"], 1),
+                       "fp32_over_fp64": round(f32["pushes_per_s"] / f64["pushes_per_s"], 3),
+                       "diagnostics": f64["diagnostics"]}
+    if f32["tuned"]:
+        out["autotuned"] = f32["tuned"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

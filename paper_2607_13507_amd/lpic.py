@@ -130,6 +130,9 @@ def lib():
     """Load liblpic.so (built in-tree by __graft_entry__.build()); no fallback."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime with the same soname as /opt/rocm's; importing it
+        # first makes liblpic.so bind to that one, so the process holds a single runtime
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)

@@ -21,6 +21,7 @@ def declared_functions():
 
 @pytest.fixture(scope="module")
 def lib():
+    import torch  # noqa: F401  (bind to torch's HIP runtime, as the binding does)
     if not os.path.exists(SO):
         from paper_2607_13507_amd import build
         build.build()
