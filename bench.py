@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--ppc", type=int, default=32)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--halo", type=int, default=4)
+    ap.add_argument("--halo", type=int, default=5)
     ap.add_argument("--chunk", type=int, default=2048)
     ap.add_argument("--sort-interval", type=int, default=10)
     ap.add_argument("--autotune", action="store_true")

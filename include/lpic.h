@@ -75,8 +75,8 @@ typedef struct {
 typedef struct {
   void *ex, *ey, *ez, *bx, *by, *bz;
   void *jx, *jy, *jz;
-  void *rho0, *rho1;         /* optional charge at the start / end of the step (may be NULL
-                                unless a call asks for it) */
+  void *rho0, *rho1;         /* optional charge at the start / end of the deposited paths
+                                (may be NULL unless a call asks for it) */
 } lpic_fields;
 
 /* Particle arrays of one species (Sec. 2.1, structure of arrays), n slots each. */
@@ -94,8 +94,10 @@ typedef struct {
 /* Tiling used by the sort and the fused particle kernel.  Tile edges are powers of two;
  * the field tile staged in on-chip memory is the tile plus `halo` cells on each side, and
  * a tile's particles are processed in chunks of at most `chunk` particles per workgroup.
- * halo must be >= 3; particles that drifted further than halo - 3 cells from their tile
- * since the last sort are still handled correctly, through global memory. */
+ * A particle's gather and deposit touch cells up to 3 below and 4 above its cell, so with
+ * halo h a particle may drift h - 3 cells below and h - 4 cells above its tile since the
+ * last sort and stay on chip; particles beyond that are still handled exactly, through
+ * global memory (counted in lpic_stats.halo_escapes).  halo must be >= 3. */
 typedef struct {
   int32_t tx, ty, tz;        /* tz ignored in 2D */
   int32_t halo;
@@ -116,11 +118,12 @@ lpic_status lpic_yee_update_EB(const lpic_grid *grid, const lpic_fields *fields,
 
 /* ---------------------------------------------------------------------------------------
  * Gather + push -- Sec. 3.1 and the particle part of Algorithm 1 up to (not including) the
- * deposit: half position push, interpolation of E and B at the half position, Boris push
- * of u by dt, second half position push, periodic wrap.  The start position and start
- * z-velocity of every particle are written into `old_state` (lpic_old_state_bytes() bytes,
- * caller-owned device memory, layout private to the library) for lpic_deposit_esirkepov.
- * Fields are read from global memory; no sort is needed.
+ * deposit: half position push to x^{n+1/2}, interpolation of E and B there, Boris push of
+ * u by dt, second half position push to x^{n+1}, periodic wrap.  The half-step position
+ * x^{n+1/2} of every particle -- the start of the path the deposit traces -- is written
+ * into `old_state` (lpic_old_state_bytes() bytes, caller-owned device memory, layout private
+ * to the library) for lpic_deposit_esirkepov.  Fields are read from global memory; no sort
+ * is needed.
  * ------------------------------------------------------------------------------------- */
 size_t lpic_old_state_bytes(int32_t ndim, int64_t n, lpic_precision prec);
 lpic_status lpic_gather_push(const lpic_grid *grid, const lpic_fields *fields,
@@ -128,10 +131,13 @@ lpic_status lpic_gather_push(const lpic_grid *grid, const lpic_fields *fields,
                              lpic_precision prec, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------
- * Esirkepov deposit -- Sec. 3.1 (Esirkepov 2001): adds the current of every particle's
- * straight path from its position in `old_state` to its present position into jx, jy, jz
- * (which are NOT cleared).  with_rho != 0 also adds q w S at the start (rho0) and end
- * (rho1) positions.  In 2D, Jz uses the mean of the start and end z-velocities.
+ * Esirkepov deposit -- Sec. 3.1 (Esirkepov 2001): adds into jx, jy, jz (NOT cleared) the
+ * current of every particle's straight path over one dt centred on the end of the step:
+ * from x^{n+1/2} (old_state) to x^{n+1/2} + dt v^{n+1} (v from the present momentum).  This
+ * is the trajectory "from t - dt/2 to t + dt/2" of Sec. 3.1 around the whole time level at
+ * which Eq. 3 applies J; x^{n+1} is the midpoint of the path.  In 2D, Jz uses v_z^{n+1}.
+ * with_rho != 0 also adds q w S at the path start (rho0) and end (rho1), so that
+ * rho1 - rho0 + dt div J = 0 holds node by node.
  * ------------------------------------------------------------------------------------- */
 lpic_status lpic_deposit_esirkepov(const lpic_grid *grid, const lpic_fields *fields,
                                    const lpic_species *sp, const void *old_state,

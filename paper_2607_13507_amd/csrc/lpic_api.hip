@@ -229,8 +229,8 @@ Tables single_tables(const RunDesc& r, const SegDesc* s) {
 }
 
 size_t old_state_bytes(int ndim, int64_t n, int prec) {
-  if (prec == LPIC_F32_CELLOFS) return (size_t)n * (4 + 4 * ndim + (ndim == 2 ? 4 : 0));
-  return (size_t)n * (8 * ndim + (ndim == 2 ? 8 : 0));
+  if (prec == LPIC_F32_CELLOFS) return (size_t)n * (4 + 4 * ndim);
+  return (size_t)n * 8 * ndim;
 }
 
 int64_t max_chunks_of(int64_t ntiles, int64_t n, int chunk) {

@@ -572,36 +572,43 @@ __device__ __forceinline__ void store_particle(const SegDesc& s, const RunDesc& 
 
 // The particle part of Algorithm 1 for one particle: half push, gather at the half position,
 // Boris, second half push.  Fields come through accessor A whose frame has the particle's
-// start cell at a[].  On return x1 holds the end offsets relative to the start cell and
-// vz_bar the mean z velocity of the step (2D Jz).
+// start cell at a[].  Outputs, per axis:
+//   pc, po  the half-step position x^{n+1/2} as (cell in A's frame, offset in [0,1)): the
+//           gather point and the start of the deposited path;
+//   pe      the path end x^{n+1/2} + dt v^{n+1}, as an offset relative to pc;
+//   x1      the new position x^{n+1} (the path midpoint), relative to the start cell.
+// The deposited path is the trajectory over one dt centred on the end of the step
+// (Sec. 3.1 with the time levels of Eq. 3), so vz1 = v_z^{n+1} is the 2D Jz velocity.
 template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
-                                     const PushConst<R>& k, R x1[3], R& vz_bar, R& gamma1) {
+                                     const PushConst<R>& k, int pc[3], R po[3], R pe[3],
+                                     R x1[3], R& vz1, R& gamma1) {
   const R ig0 = rsq<R>(R(1) + ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2]);
   const R hd[3] = {k.hdx, k.hdy, k.hdz};
   R xh[3];
-  int gc[3];
-  R go[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < DIM) {
       xh[d] = ps.o[d] + hd[d] * ps.u[d] * ig0;
       const R f = floor_clamped<R>(xh[d], R(-1), R(1));
-      gc[d] = a[d] + (int)f;
-      go[d] = xh[d] - f;
+      pc[d] = a[d] + (int)f;
+      po[d] = xh[d] - f;
     } else {
-      xh[d] = R(0); gc[d] = 0; go[d] = R(0);
+      xh[d] = R(0); pc[d] = 0; po[d] = R(0);
     }
   }
   R E[3], B[3];
-  gather<DIM, ORDER>(A, gc, go, E, B);
-  const R uz0 = ps.u[2];
+  gather<DIM, ORDER>(A, pc, po, E, B);
   boris<R>(ps.u, E, B, k.qdt2m);
   const R u2 = ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2];
   const R ig1 = rsq<R>(R(1) + u2);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) x1[d] = d < DIM ? xh[d] + hd[d] * ps.u[d] * ig1 : R(0);
-  vz_bar = R(0.5) * (uz0 * ig0 + ps.u[2] * ig1);
+  for (int d = 0; d < 3; ++d) {
+    const R half = d < DIM ? hd[d] * ps.u[d] * ig1 : R(0);
+    x1[d] = xh[d] + half;
+    pe[d] = po[d] + R(2) * half;
+  }
+  vz1 = ps.u[2] * ig1;
   gamma1 = R(1) / ig1;
 }
 

@@ -144,14 +144,13 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac) {
 
 // =======================================================================================
 // Split particle path: gather + push, then deposit (used when a hook sits between them).
-// Old-state layout: FP32  cell0[n] ox0[n] oy0[n] (oz0[n]) (vz0[n] in 2D)
-//                   FP64  x0[n] y0[n] (z0[n]) (vz0[n] in 2D)
+// The old state holds the start of each particle's deposit path, the half-step position:
+//   FP32  cell[n] (packed, wrapped) o0[n] o1[n] (o2[n])     FP64  x[n] y[n] (z[n]) (wrapped)
 // =======================================================================================
 template <typename R, int DIM>
 struct OldState {
   int32_t* cell;
   R* o[3];
-  R* vz;
   __device__ __forceinline__ OldState(void* base, int64_t n) {
     char* b = (char*)base;
     if (sizeof(R) == 4) {
@@ -163,7 +162,6 @@ struct OldState {
     for (int d = 0; d < 3; ++d) {
       if (d < DIM) { o[d] = (R*)b; b += sizeof(R) * n; } else { o[d] = nullptr; }
     }
-    vz = DIM == 2 ? (R*)b : nullptr;
   }
 };
 
@@ -187,22 +185,24 @@ __device__ __forceinline__ void gather_push_one(const SegDesc& s, const RunDesc&
     else os.o[0][p] = R(-1);
     return;
   }
-  if constexpr (sizeof(R) == 4) {
-    os.cell[p] = pack_cell(ps.c, DIM);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) os.o[d][p] = ps.o[d];
-  } else {
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) os.o[d][p] = ((const double*)s.p[P_X + d])[p];
-  }
   const GlobalAcc<R> A = global_acc<R>(r);
   const PushConst<R> k = push_const<R>(r, s);
-  R x1[3], vzb, g1;
-  const R uz0 = ps.u[2];
-  const R ig0 = rsq<R>(R(1) + ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2]);
-  push<DIM, ORDER>(A, ps.c, ps, k, x1, vzb, g1);
-  if (DIM == 2) os.vz[p] = uz0 * ig0;
+  int pc[3];
+  R po[3], pe[3], x1[3], vz1, g1;
+  push<DIM, ORDER>(A, ps.c, ps, k, pc, po, pe, x1, vz1, g1);
   const int n[3] = {r.nx, r.ny, r.nz};
+  int wc[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) wc[d] = wrapi(pc[d], n[d]);
+  if constexpr (sizeof(R) == 4) {
+    os.cell[p] = pack_cell(wc, DIM);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) os.o[d][p] = po[d];
+  } else {
+    const double h[3] = {r.dx, r.dy, r.dz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) os.o[d][p] = ((double)wc[d] + po[d]) * h[d];
+  }
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
   store_particle<R, DIM>(s, r, p, ps);
@@ -228,7 +228,7 @@ __device__ __forceinline__ void deposit_one(const SegDesc& s, const RunDesc& r, 
   if (!now.alive) return;
   const int n[3] = {r.nx, r.ny, r.nz};
   int c0[3];
-  R o0[3], x1[3];
+  R o0[3], pe[3];
   if constexpr (sizeof(R) == 4) {
     const int32_t cell0 = os.cell[p];
     if (cell0 < 0) return;
@@ -253,23 +253,14 @@ __device__ __forceinline__ void deposit_one(const SegDesc& s, const RunDesc& r, 
       }
     }
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (d < DIM) {
-      int k = now.c[d] - c0[d];
-      if (k > n[d] / 2) k -= n[d];
-      if (k < -n[d] / 2) k += n[d];
-      k = k < -1 ? -1 : (k > 1 ? 1 : k);
-      x1[d] = R(k) + now.o[d];
-    } else {
-      x1[d] = R(0);
-    }
-  }
-  const R ig1 = rsq<R>(R(1) + now.u[0] * now.u[0] + now.u[1] * now.u[1] + now.u[2] * now.u[2]);
-  const R vzb = DIM == 2 ? R(0.5) * (os.vz[p] + now.u[2] * ig1) : R(0);
-  const GlobalAcc<R> A = global_acc<R>(r);
+  // path end: the start plus dt v^{n+1}, from the momentum the push left behind
   const PushConst<R> k = push_const<R>(r, s);
-  deposit<DIM, ORDER>(A, c0, o0, x1, now.w, vzb, k, with_rho);
+  const R ig1 = rsq<R>(R(1) + now.u[0] * now.u[0] + now.u[1] * now.u[1] + now.u[2] * now.u[2]);
+  const R hd[3] = {k.hdx, k.hdy, k.hdz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) pe[d] = d < DIM ? o0[d] + R(2) * (hd[d] * now.u[d] * ig1) : R(0);
+  const GlobalAcc<R> A = global_acc<R>(r);
+  deposit<DIM, ORDER>(A, c0, o0, pe, now.w, now.u[2] * ig1, k, with_rho);
 }
 
 template <typename R, int DIM>
@@ -546,6 +537,8 @@ __device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s
     PState<R> ps;
     load_particle<R, DIM>(s, r, p, ps);
     if (!ps.alive) continue;
+    // local coordinates of the start cell; the gather and the deposit path touch cells
+    // [a-3, a+4] per axis, which must lie inside the staged region
     int a[3];
     bool inside = true;
 #pragma unroll
@@ -554,20 +547,20 @@ __device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s
         int v = ps.c[d] - r0[d];
         v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
         a[d] = v;
-        inside = inside && v >= 2 && v <= RWd[d] - 4;
+        inside = inside && v >= 3 && v <= RWd[d] - 5;
       } else {
         a[d] = 0;
       }
     }
-    R x1[3], vzb, g1;
-    const R o0[3] = {ps.o[0], ps.o[1], ps.o[2]};
+    int pc[3];
+    R po[3], pe[3], x1[3], vz1, g1;
     if (inside) {
-      push<DIM, ORDER>(L, a, ps, k, x1, vzb, g1);
-      deposit<DIM, ORDER>(L, a, o0, x1, ps.w, vzb, k, with_rho != 0);
+      push<DIM, ORDER>(L, a, ps, k, pc, po, pe, x1, vz1, g1);
+      deposit<DIM, ORDER>(L, pc, po, pe, ps.w, vz1, k, with_rho != 0);
     } else {
       ++escapes;
-      push<DIM, ORDER>(G, ps.c, ps, k, x1, vzb, g1);
-      deposit<DIM, ORDER>(G, ps.c, o0, x1, ps.w, vzb, k, with_rho != 0);
+      push<DIM, ORDER>(G, ps.c, ps, k, pc, po, pe, x1, vz1, g1);
+      deposit<DIM, ORDER>(G, pc, po, pe, ps.w, vz1, k, with_rho != 0);
     }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);

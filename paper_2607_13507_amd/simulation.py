@@ -171,7 +171,7 @@ class Simulation:
     """One box or an ensemble of independent boxes advanced by lpic_step."""
 
     def __init__(self, workloads: Union[Workload, Sequence[Workload]], prec=L.F32_CELLOFS,
-                 tiling=(16, 16, 8), halo=4, chunk=2048, sort_interval=10, diag_interval=0,
+                 tiling=(16, 16, 8), halo=5, chunk=2048, sort_interval=10, diag_interval=0,
                  use_graph=True, device="cuda", with_rho=True, stream=None):
         wls = [workloads] if isinstance(workloads, Workload) else list(workloads)
         self.workloads = wls
@@ -255,7 +255,7 @@ class Simulation:
         for c in candidates:
             t = c.get("tiling", (16, 16, 8))
             opts.append(L.Options(L.Tiling(t[0], t[1], t[2] if self.ndim == 3 else 1,
-                                           c.get("halo", 4), c.get("chunk", 2048), 0),
+                                           c.get("halo", 5), c.get("chunk", 2048), 0),
                                   c.get("sort_interval", self.options.sort_interval),
                                   c.get("diag_interval", self.options.diag_interval),
                                   int(c.get("use_graph", self.options.use_graph)), 0))
