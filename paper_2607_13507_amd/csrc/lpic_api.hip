@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lpic.h"
+#include "lpic.h"
 #include "lpic_internal.hpp"
 
 using namespace lpic;
@@ -318,7 +318,7 @@ size_t lpic_sort_ws_bytes(const lpic_grid* grid, const lpic_tiling* tiling, int6
   (void)n;
   const int64_t nt = lpic_num_tiles(grid, tiling);
   if (nt < 0) return 0;
-  return 2 * align256((size_t)(nt + 1) * 4);
+  return 3 * align256((size_t)(nt + 1) * 4);   // counts, cursor, placement multipliers
 }
 
 lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_species* alt,
@@ -338,13 +338,14 @@ lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_specie
   const int nbins = r.ntiles + 1;
   int32_t* counts = (int32_t*)ws;
   int32_t* cursor = (int32_t*)((char*)ws + align256((size_t)nbins * 4));
+  int32_t* mult = (int32_t*)((char*)ws + 2 * align256((size_t)nbins * 4));
   if (sp->n > 0) {
     SegDesc s = make_seg(sp, alt, 0, &t, 0, 0, prec);
     Tables T = single_tables(r, &s);
     launch_zero_u32((uint32_t*)counts, nbins, stream);
     CHK(last_launch("sort clear"));
     launch_sort(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), counts,
-                tile_offsets, cursor, nbins, stream);
+                tile_offsets, cursor, mult, nbins, stream);
     CHK(last_launch("sort"));
   } else {
     launch_zero_u32((uint32_t*)tile_offsets, nbins + 1, stream);
@@ -466,7 +467,7 @@ struct lpic_sim {
   int32_t* seg_blk256_d = nullptr;
   int32_t* seg_blk_sort_d = nullptr;
   int nblk_cells = 0, nblk_p256 = 0, nblk_sort = 0;
-  int32_t *counts = nullptr, *offsets = nullptr, *cursor = nullptr;
+  int32_t *counts = nullptr, *offsets = nullptr, *cursor = nullptr, *mult = nullptr;
   int nbins = 0;
   Chunk* chunks = nullptr;
   int32_t* nchunks = nullptr;
@@ -581,8 +582,9 @@ lpic_status configure(lpic_sim* s) {
   // device tables
   free_dev(s->runs_d); free_dev(s->segs_d); free_dev(s->run_blk_d);
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
-  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor);
+  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks);
+  s->mult = nullptr;
   s->runs_d = nullptr; s->segs_d = nullptr; s->run_blk_d = nullptr;
   s->seg_blk256_d = s->seg_blk_sort_d = nullptr;
   s->counts = s->offsets = s->cursor = nullptr;
@@ -600,6 +602,7 @@ lpic_status configure(lpic_sim* s) {
   ALLOC(s->counts, sizeof(int32_t) * (s->nbins + 1));
   ALLOC(s->offsets, sizeof(int32_t) * (s->nbins + 1));
   ALLOC(s->cursor, sizeof(int32_t) * (s->nbins + 1));
+  ALLOC(s->mult, sizeof(int32_t) * (s->nbins + 1));
   ALLOC(s->chunks, sizeof(Chunk) * std::max<int64_t>(1, maxch));
   HIPCHK(hipMemcpy(s->runs_d, s->runs_h.data(), sizeof(RunDesc) * s->nruns, hipMemcpyHostToDevice));
   if (s->nsegs)
@@ -642,7 +645,8 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, b
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_1));
   // sort particles (every sort_interval steps)
   if (do_sort && s->nsegs > 0) {
-    launch_sort(Ts, s->prec, s->ndim, s->nblk_sort, s->counts, s->offsets, s->cursor, s->nbins, st);
+    launch_sort(Ts, s->prec, s->ndim, s->nblk_sort, s->counts, s->offsets, s->cursor, s->mult,
+                s->nbins, st);
     CHK(last_launch("sort"));
     launch_swap_segments(s->segs_d, s->nsegs, st);
     CHK(last_launch("swap"));
@@ -807,7 +811,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   for (auto& e : s->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   free_dev(s->runs_d); free_dev(s->segs_d); free_dev(s->run_blk_d);
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
-  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor);
+  free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
   free_dev(s->old_state);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

@@ -172,16 +172,21 @@ struct GlobalAcc {
   }
 };
 
+// On-chip tile: the six field planes in the kernel's precision, and the current (and
+// charge) planes accumulated in FP64 whatever that precision: FP64 LDS atomic adds run at
+// full rate on gfx950, FP32 ones do not, and FP64 sums also keep the per-tile totals exact to
+// FP32 before the flush.
 template <typename R>
 struct LdsAcc {
-  R* base;        // planes: 6 field components, then jx jy jz, then rho0 rho1
+  R* fbase;       // planes Ex Ey Ez Bx By Bz
+  double* jbase;  // planes Jx Jy Jz, then rho0 rho1
   int plane, sy, sz;
   __device__ __forceinline__ int xo(int x) const { return x; }
   __device__ __forceinline__ int yo(int y) const { return y * sy; }
   __device__ __forceinline__ int zo(int z) const { return z * sz; }
-  __device__ __forceinline__ R get(int comp, int off) const { return base[comp * plane + off]; }
+  __device__ __forceinline__ R get(int comp, int off) const { return fbase[comp * plane + off]; }
   __device__ __forceinline__ void add(int comp, int off, R v) const {
-    atomic_add_lds(base + comp * plane + off, v);
+    atomic_add_lds(jbase + (comp - F_JX) * plane + off, (double)v);
   }
 };
 

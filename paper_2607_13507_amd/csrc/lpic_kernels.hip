@@ -338,9 +338,34 @@ __global__ __launch_bounds__(256) void k_sort_count(Tables T, int32_t* counts) {
   }
 }
 
-// Exclusive scan of the bin counts by one workgroup; clears the counts for the next sort.
+// Placement inside a bin: the particle of rank r (arrival order, roughly the previous
+// order, i.e. grouped by cell) goes to slot r*P mod N with P the inverse of Q mod N and
+// Q ~ N/64 coprime to N.  Slot s then holds rank s*Q mod N, so the 64 particles a wavefront
+// reads together come from 64 different stretches of the bin -- different cells -- and
+// their current goes to different LDS addresses.
+__device__ __forceinline__ int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { const int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+__device__ __forceinline__ int32_t spread_multiplier(int32_t n) {
+  if (n <= 64) return 1;
+  int64_t q = n >> 6;
+  while (gcd64(q, n) != 1) ++q;
+  // inverse of q modulo n (extended Euclid)
+  int64_t t0 = 0, t1 = 1, r0 = n, r1 = q;
+  while (r1) {
+    const int64_t k = r0 / r1;
+    int64_t t = t0 - k * t1; t0 = t1; t1 = t;
+    t = r0 - k * r1; r0 = r1; r1 = t;
+  }
+  if (t0 < 0) t0 += n;
+  return (int32_t)t0;
+}
+
+// Exclusive scan of the bin counts by one workgroup; clears the counts for the next sort
+// and records each bin's placement multiplier.
 __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* offsets,
-                                                    int32_t* cursor, int nbins) {
+                                                    int32_t* cursor, int32_t* mult, int nbins) {
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x;
   const int per = (nbins + 1023) / 1024;
@@ -373,6 +398,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
     const int32_t c = counts[b];
     offsets[b] = run;
     cursor[b] = run;
+    mult[b] = spread_multiplier(c);
     counts[b] = 0;
     run += c;
   }
@@ -380,7 +406,9 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
 }
 
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor) {
+__global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
+                                                      const int32_t* offsets,
+                                                      const int32_t* mult) {
   int blk;
   const SegDesc& s = seg_of(T, part_block(T, blk));
   const RunDesc& r = run_of(T, s.run);
@@ -394,7 +422,9 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor)
     if (wave_runs(key, valid, len, head)) base = atomicAdd(&cursor[key], len);
     base = __shfl(base, head, 64);
     if (!valid) continue;
-    const int64_t dst = (int64_t)base + (__lane_id() - head) - s.pbase;
+    const int32_t b0 = offsets[key], nb = offsets[key + 1] - b0;
+    const int64_t rank = (int64_t)base + (__lane_id() - head) - b0;
+    const int64_t dst = b0 + (rank * mult[key]) % nb - s.pbase;
     if constexpr (sizeof(R) == 4) {
       ((int32_t*)s.alt[P_CELL])[dst] = ((const int32_t*)s.p[P_CELL])[p];
       ((float*)s.alt[P_OX])[dst] = ((const float*)s.p[P_OX])[p];
@@ -510,8 +540,9 @@ __device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s
     else { r0[d] = 0; RWd[d] = 1; }
   }
   const int plane = RWd[0] * RWd[1] * RWd[2];
-  const int nplanes = 9 + (with_rho ? 2 : 0);
+  const int njplanes = 3 + (with_rho ? 2 : 0);
   R* const* F = (R* const*)r.f;
+  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
   // stage E, B; clear J (and rho)
   for (int e = threadIdx.x; e < plane; e += blockDim.x) {
     const int lx = e % RWd[0];
@@ -522,11 +553,12 @@ __device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s
                       wrapm(r0[0] + lx, n[0]);
 #pragma unroll
     for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][g];
-    for (int c = 6; c < nplanes; ++c) sm[c * plane + e] = R(0);
+    for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
   }
   __syncthreads();
   LdsAcc<R> L;
-  L.base = sm;
+  L.fbase = sm;
+  L.jbase = jm;
   L.plane = plane;
   L.sy = RWd[0];
   L.sz = RWd[0] * RWd[1];
@@ -578,9 +610,9 @@ __device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s
     const int lz = rest / RWd[1];
     const int64_t g = ((int64_t)wrapm(r0[2] + lz, n[2]) * n[1] + wrapm(r0[1] + ly, n[1])) * n[0] +
                       wrapm(r0[0] + lx, n[0]);
-    for (int c = 6; c < nplanes; ++c) {
-      const R v = sm[c * plane + e];
-      if (v != R(0)) atomic_add_global(F[c] + g, v);
+    for (int c = 0; c < njplanes; ++c) {
+      const double v = jm[c * plane + e];
+      if (v != 0.0) atomic_add_global(F[F_JX + c] + g, R(v));
     }
   }
   return ke * s.m;
@@ -809,10 +841,10 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
 }
 
 void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* counts,
-                 int32_t* offsets, int32_t* cursor, int nbins, hipStream_t st) {
+                 int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, hipStream_t st) {
   LPIC_PD(prec, dim, (k_sort_count<R, D><<<nblocks, 256, 0, st>>>(T, counts)));
-  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, nbins);
-  LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor)));
+  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins);
+  LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult)));
 }
 
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
@@ -896,7 +928,8 @@ void launch_store_positions(const Tables& T, int prec, int dim, int nblocks, dou
 
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
   const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
-  return plane * (9 + (with_rho ? 2 : 0)) * (prec == 0 ? 4 : 8);
+  // six field planes in the kernel precision (padded to 8 bytes), then FP64 current planes
+  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * (3 + (with_rho ? 2 : 0)) * 8;
 }
 
 }  // namespace lpic
