@@ -239,10 +239,22 @@ int64_t max_chunks_of(int64_t ntiles, int64_t n, int chunk) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// The fused kernel gives XCD x (workgroups x, x+8, x+16, ...) the contiguous chunk range
-// [x*per, (x+1)*per) with per = ceil(nchunks/8); covering every chunk needs 8*per workgroups,
-// so the grid is the chunk bound rounded up to a multiple of 8.
-int64_t fused_grid(int64_t max_chunks) { return (max_chunks + 7) / 8 * 8; }
+// The fused kernel is persistent: XCD x (workgroups x, x+8, x+16, ...) owns the contiguous
+// chunk range [x*per, (x+1)*per), per = ceil(nchunks/8), split into equal slices.  The grid
+// is a multiple of 8: as many workgroups as fit on the device at once, and never more than
+// there can be chunks.
+int fused_grid(int64_t max_chunks, int blocks_per_cu) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int64_t g = (int64_t)cus * std::max(1, blocks_per_cu);
+  g = std::min<int64_t>(g, std::max<int64_t>(max_chunks, 1));
+  return (int)((g + 7) / 8 * 8);
+}
 
 }  // namespace
 
@@ -364,7 +376,9 @@ size_t lpic_fused_ws_bytes(const lpic_grid* grid, const lpic_tiling* tiling, int
   if (!tiling || tiling->chunk < 1) return 0;
   const int64_t nt = lpic_num_tiles(grid, tiling);
   if (nt < 0) return 0;
-  return align256(sizeof(int32_t)) + (size_t)max_chunks_of(nt, n, tiling->chunk) * sizeof(Chunk);
+  // chunk count, escape counters and total, chunk table, escape list
+  return 256 + align256((size_t)max_chunks_of(nt, n, tiling->chunk) * sizeof(Chunk)) +
+         (size_t)std::max<int64_t>(n, 1) * 8;
 }
 
 lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fields,
@@ -385,15 +399,24 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   RunDesc r = make_run(grid, fields, &t);
   SegDesc s = make_seg(sp, nullptr, 0, &t, 0, 0, prec);
   Tables T = single_tables(r, &s);
+  const int64_t maxch = max_chunks_of(r.ntiles, sp->n, t.chunk);
   int32_t* nchunks = (int32_t*)ws;
-  Chunk* chunks = (Chunk*)((char*)ws + align256(sizeof(int32_t)));
+  EscapeList esc;
+  esc.count = (unsigned int*)((char*)ws + 64);
+  esc.total = (unsigned long long*)((char*)ws + 128);
+  Chunk* chunks = (Chunk*)((char*)ws + 256);
+  esc.items = (unsigned long long*)((char*)chunks + align256((size_t)maxch * sizeof(Chunk)));
+  esc.capacity = sp->n;
+  launch_zero_u32((uint32_t*)ws, 64, stream);          // chunk count, escape counters, total
+  CHK(last_launch("fused clear"));
   launch_build_chunks(T, tile_offsets, r.ntiles + 1, t.chunk, chunks, nchunks, stream);
   CHK(last_launch("build chunks"));
   const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
-  HIPCHK(prepare_fused(prec, grid->ndim, smem));
-  const int64_t maxch = max_chunks_of(r.ntiles, sp->n, t.chunk);
-  launch_fused(T, prec, grid->ndim, (int)fused_grid(maxch), smem, chunks, nchunks, with_rho,
-               kinetic, 0, nullptr, stream);
+  const int geo = fused_geometry(grid->ndim, t.tx, t.ty, t.tz, t.halo);
+  int bpc = 1;
+  HIPCHK(prepare_fused(prec, grid->ndim, geo, smem, &bpc));
+  launch_fused(T, prec, grid->ndim, geo, fused_grid(maxch, bpc), smem, chunks, nchunks, with_rho,
+               kinetic, 0, esc, stream);
   return last_launch("fused");
 }
 
@@ -473,8 +496,13 @@ struct lpic_sim {
   int32_t* nchunks = nullptr;
   int64_t max_chunks = 0;
   size_t smem = 0, smem_rho = 0;
+  int geo = 0;
   double* diag = nullptr;
-  unsigned long long* escapes = nullptr;
+  unsigned long long* escapes = nullptr;     // cumulative escape count
+  unsigned int* esc_count = nullptr;         // per-step escape counters
+  unsigned long long* esc_items = nullptr;   // escape list (capacity: all particles)
+  int64_t esc_capacity = 0;
+  int blocks_per_cu = 1;
   void* old_state = nullptr;
   std::vector<size_t> old_off;
   std::vector<HookEntry> hooks[LPIC_NUM_STAGES];
@@ -614,7 +642,14 @@ lpic_status configure(lpic_sim* s) {
   HIPCHK(hipMemset(s->nchunks, 0, sizeof(int32_t)));
   s->smem = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 0);
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1);
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->smem_rho));
+  s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, &s->blocks_per_cu));
+  if (!s->esc_items) {
+    s->esc_capacity = std::max<int64_t>(pbase, 1);
+    ALLOC(s->esc_items, sizeof(unsigned long long) * s->esc_capacity);
+    ALLOC(s->esc_count, 256);
+    HIPCHK(hipMemset(s->esc_count, 0, 256));
+  }
   s->need_sort = true;
   return LPIC_OK;
 #undef ALLOC
@@ -674,8 +709,14 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, b
         }
         HIPCHK(hipEventRecord(e0, st));
       }
-      launch_fused(Tc, s->prec, s->ndim, (int)fused_grid(s->max_chunks), diag ? s->smem_rho : s->smem,
-                   s->chunks, s->nchunks, diag ? 1 : 0, nullptr, diag ? 1 : 0, s->escapes, st);
+      EscapeList esc;
+      esc.items = s->esc_items;
+      esc.count = s->esc_count;
+      esc.total = s->escapes;
+      esc.capacity = s->esc_capacity;
+      launch_fused(Tc, s->prec, s->ndim, s->geo, fused_grid(s->max_chunks, s->blocks_per_cu),
+                   diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
+                   diag ? 1 : 0, esc, st);
       CHK(last_launch("fused"));
       if (s->timing) {
         HIPCHK(hipEventRecord(e1, st));
@@ -813,6 +854,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
+  free_dev(s->esc_items); free_dev(s->esc_count);
   free_dev(s->old_state);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;

@@ -84,6 +84,20 @@ template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0
 template <typename R> __device__ __forceinline__ R ffloor(R x) { return floor(x); }
 template <> __device__ __forceinline__ float ffloor<float>(float x) { return floorf(x); }
 
+// Global-memory pointers.  Arrays reached through descriptor tables would otherwise be
+// generic (flat) pointers: flat accesses count against the LDS wait counter too, so every
+// LDS wait would also wait for all in-flight particle loads.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {   // wavefront-uniform value (scalar register)
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ void atomic_add_lds(float* p, float v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -91,9 +105,15 @@ __device__ __forceinline__ void atomic_add_lds(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void atomic_add_global(float* p, float v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void atomic_add_global(double* p, double v) {
+  __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add_global(gptr<float> p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add_global(gptr<double> p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -161,32 +181,53 @@ __device__ __forceinline__ void weights_half(R o, int c, int& base, R w[ORDER + 
 // ---------------------------------------------------------------------------------------
 template <typename R>
 struct GlobalAcc {
-  R* f[F_NUM];
+  gptr<R> f[F_NUM];
   int nx, ny, nz;
   __device__ __forceinline__ int xo(int x) const { return wrapi(x, nx); }
   __device__ __forceinline__ int yo(int y) const { return wrapi(y, ny) * nx; }
   __device__ __forceinline__ int zo(int z) const { return wrapi(z, nz) * nx * ny; }
   __device__ __forceinline__ R get(int comp, int off) const { return f[comp][off]; }
   __device__ __forceinline__ void add(int comp, int off, R v) const {
-    atomic_add_global(f[comp] + off, v);
+    if (v != R(0)) atomic_add_global(f[comp] + off, v);
   }
+};
+
+// Strides of the staged region (tile + halo).  Fixed strides are compile-time constants, so
+// every stencil offset folds into the immediate offset of the LDS instruction; dynamic
+// strides serve any other tiling.
+template <int RW, int RH, int RD>
+struct FixStrides {
+  static constexpr int kSy = RW, kSz = RW * RH, kPlane = RW * RH * RD;
+  __device__ __forceinline__ constexpr int sy() const { return kSy; }
+  __device__ __forceinline__ constexpr int sz() const { return kSz; }
+  __device__ __forceinline__ constexpr int plane() const { return kPlane; }
+};
+struct DynStrides {
+  int sy_, sz_, plane_;
+  __device__ __forceinline__ int sy() const { return sy_; }
+  __device__ __forceinline__ int sz() const { return sz_; }
+  __device__ __forceinline__ int plane() const { return plane_; }
 };
 
 // On-chip tile: the six field planes in the kernel's precision, and the current (and
 // charge) planes accumulated in FP64 whatever that precision: FP64 LDS atomic adds run at
 // full rate on gfx950, FP32 ones do not, and FP64 sums also keep the per-tile totals exact to
 // FP32 before the flush.
-template <typename R>
+template <typename R, class S>
 struct LdsAcc {
   R* fbase;       // planes Ex Ey Ez Bx By Bz
   double* jbase;  // planes Jx Jy Jz, then rho0 rho1
-  int plane, sy, sz;
+  S st;
   __device__ __forceinline__ int xo(int x) const { return x; }
-  __device__ __forceinline__ int yo(int y) const { return y * sy; }
-  __device__ __forceinline__ int zo(int z) const { return z * sz; }
-  __device__ __forceinline__ R get(int comp, int off) const { return fbase[comp * plane + off]; }
+  __device__ __forceinline__ int yo(int y) const { return y * st.sy(); }
+  __device__ __forceinline__ int zo(int z) const { return z * st.sz(); }
+  __device__ __forceinline__ R get(int comp, int off) const {
+    return fbase[comp * st.plane() + off];
+  }
+  // Exact zeros are skipped: a particle that keeps its nearest node leaves a zero row and
+  // column in its window, and a lane masked off costs the LDS nothing.
   __device__ __forceinline__ void add(int comp, int off, R v) const {
-    atomic_add_lds(jbase + (comp - F_JX) * plane + off, (double)v);
+    if (v != R(0)) atomic_add_lds(jbase + (comp - F_JX) * st.plane() + off, (double)v);
   }
 };
 
@@ -505,26 +546,53 @@ __device__ __forceinline__ int32_t pack_cell(const int c[3], int dim) {
   return dim == 2 ? (c[1] << 16) | c[0] : (c[2] << 22) | (c[1] << 11) | c[0];
 }
 
+// The arrays of one species as global pointers, copied out of the descriptor once (they stay
+// in scalar registers instead of being re-read after every store).
+template <typename R>
+struct PartPtrs {
+  gptr<int32_t> cell;   // FP32: packed cells
+  gptr<R> pos[3];       // FP32: float offsets; FP64: absolute double positions
+  gptr<R> u[3];
+  gptr<R> w;
+  int nx, ny, nz;
+  double dx, dy, dz;
+};
+
+template <typename R>
+__device__ __forceinline__ PartPtrs<R> part_ptrs(const SegDesc& s, const RunDesc& r, bool alt = false) {
+  void* const* a = alt ? s.alt : s.p;
+  PartPtrs<R> q;
+  q.cell = gp((int32_t*)a[P_CELL]);
+  if (sizeof(R) == 4) {
+    for (int d = 0; d < 3; ++d) q.pos[d] = gp((R*)a[P_OX + d]);
+  } else {
+    for (int d = 0; d < 3; ++d) q.pos[d] = gp((R*)a[P_X + d]);
+  }
+  for (int d = 0; d < 3; ++d) q.u[d] = gp((R*)a[P_UX + d]);
+  q.w = gp((R*)a[P_W]);
+  q.nx = r.nx; q.ny = r.ny; q.nz = r.nz;
+  q.dx = r.dx; q.dy = r.dy; q.dz = r.dz;
+  return q;
+}
+
 template <typename R, int DIM>
-__device__ __forceinline__ void load_particle(const SegDesc& s, const RunDesc& r, int64_t p,
-                                              PState<R>& ps) {
+__device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, PState<R>& ps) {
   if constexpr (sizeof(R) == 4) {
-    const int32_t cell = ((const int32_t*)s.p[P_CELL])[p];
+    const int32_t cell = q.cell[p];
     unpack_cell(cell < 0 ? 0 : cell, DIM, ps.c);
     // a cell outside the box cannot come from the library; treat it like a dead slot
-    ps.alive = cell >= 0 && ps.c[0] < r.nx && ps.c[1] < r.ny && (DIM == 2 || ps.c[2] < r.nz);
-    ps.o[0] = ((const float*)s.p[P_OX])[p];
-    ps.o[1] = ((const float*)s.p[P_OY])[p];
-    ps.o[2] = DIM == 3 ? ((const float*)s.p[P_OZ])[p] : 0.f;
+    ps.alive = cell >= 0 && ps.c[0] < q.nx && ps.c[1] < q.ny && (DIM == 2 || ps.c[2] < q.nz);
+    ps.o[0] = q.pos[0][p];
+    ps.o[1] = q.pos[1][p];
+    ps.o[2] = DIM == 3 ? q.pos[2][p] : 0.f;
   } else {
-    const double h[3] = {r.dx, r.dy, r.dz};
-    const int n[3] = {r.nx, r.ny, r.nz};
-    const double x = ((const double*)s.p[P_X])[p];
-    ps.alive = x >= 0.0;
+    const double h[3] = {q.dx, q.dy, q.dz};
+    const int n[3] = {q.nx, q.ny, q.nz};
+    ps.alive = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d < DIM) {
-        const double X = ((const double*)s.p[P_X + d])[p] / h[d];
+        const double X = q.pos[d][p] / h[d];
         // positions outside [0, L] (or NaN) cannot come from the library: dead slot
         if (!(X >= 0.0 && X <= (double)n[d])) ps.alive = false;
         const double f = floor_clamped<double>(X, 0.0, (double)n[d]);
@@ -538,10 +606,16 @@ __device__ __forceinline__ void load_particle(const SegDesc& s, const RunDesc& r
       }
     }
   }
-  ps.u[0] = ((const R*)s.p[P_UX])[p];
-  ps.u[1] = ((const R*)s.p[P_UY])[p];
-  ps.u[2] = ((const R*)s.p[P_UZ])[p];
-  ps.w = ((const R*)s.p[P_W])[p];
+  ps.u[0] = q.u[0][p];
+  ps.u[1] = q.u[1][p];
+  ps.u[2] = q.u[2][p];
+  ps.w = q.w[p];
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void load_particle(const SegDesc& s, const RunDesc& r, int32_t p,
+                                              PState<R>& ps) {
+  load_particle<R, DIM>(part_ptrs<R>(s, r), p, ps);
 }
 
 // New cell and offset from the end offset x1 (relative to the start cell).  If the offset
@@ -558,21 +632,27 @@ __device__ __forceinline__ void advance_cell(int& c, R& o, R x1, int n) {
 }
 
 template <typename R, int DIM>
-__device__ __forceinline__ void store_particle(const SegDesc& s, const RunDesc& r, int64_t p,
+__device__ __forceinline__ void store_particle(const PartPtrs<R>& q, int32_t p,
                                                const PState<R>& ps) {
   if constexpr (sizeof(R) == 4) {
-    ((int32_t*)s.p[P_CELL])[p] = pack_cell(ps.c, DIM);
-    ((float*)s.p[P_OX])[p] = ps.o[0];
-    ((float*)s.p[P_OY])[p] = ps.o[1];
-    if (DIM == 3) ((float*)s.p[P_OZ])[p] = ps.o[2];
+    q.cell[p] = pack_cell(ps.c, DIM);
+    q.pos[0][p] = ps.o[0];
+    q.pos[1][p] = ps.o[1];
+    if (DIM == 3) q.pos[2][p] = ps.o[2];
   } else {
-    const double h[3] = {r.dx, r.dy, r.dz};
+    const double h[3] = {q.dx, q.dy, q.dz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) ((double*)s.p[P_X + d])[p] = ((double)ps.c[d] + ps.o[d]) * h[d];
+    for (int d = 0; d < DIM; ++d) q.pos[d][p] = ((double)ps.c[d] + ps.o[d]) * h[d];
   }
-  ((R*)s.p[P_UX])[p] = ps.u[0];
-  ((R*)s.p[P_UY])[p] = ps.u[1];
-  ((R*)s.p[P_UZ])[p] = ps.u[2];
+  q.u[0][p] = ps.u[0];
+  q.u[1][p] = ps.u[1];
+  q.u[2][p] = ps.u[2];
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void store_particle(const SegDesc& s, const RunDesc& r, int32_t p,
+                                               const PState<R>& ps) {
+  store_particle<R, DIM>(part_ptrs<R>(s, r), p, ps);
 }
 
 // The particle part of Algorithm 1 for one particle: half push, gather at the half position,

@@ -19,10 +19,26 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st);
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st);
-void launch_fused(const Tables& T, int prec, int dim, int nblocks, size_t smem,
+// Particles outside the on-chip margin of their home tile: the fused kernel records them
+// here and a second kernel pushes them through global memory; that kernel's last workgroup
+// clears the list (count[0] entries, count[1] workgroups done) for the next step.
+struct EscapeList {
+  unsigned long long* items;   // (segment << 32) | particle
+  unsigned int* count;         // two counters, zero between steps
+  unsigned long long* total;   // cumulative number of escapes
+  int64_t capacity;
+};
+constexpr int ESCAPE_BLOCKS = 512;
+
+// geometry: 0 = runtime strides, else a compiled (tile, halo) shape (fused_geometry()).
+int fused_geometry(int dim, int tx, int ty, int tz, int halo);
+// Launches the fused kernel (persistent grid of nblocks, a multiple of 8) and then the
+// escape kernel on the same stream.
+void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
                   const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
-                  int ke_to_diag, unsigned long long* escapes, hipStream_t st);
-hipError_t prepare_fused(int prec, int dim, size_t smem);
+                  int ke_to_diag, const EscapeList& esc, hipStream_t st);
+// Sets the dynamic LDS limit and returns how many workgroups of the kernel fit on a CU.
+hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu);
 void launch_reduce_fields(const Tables& T, int prec, int dim, int nblocks, int with_rho,
                           double* out, hipStream_t st);
 void launch_kinetic(const Tables& T, int prec, int dim, int nblocks, double* out,

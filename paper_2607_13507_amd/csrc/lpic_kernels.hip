@@ -20,16 +20,16 @@ __device__ __forceinline__ const SegDesc& seg_of(const Tables& T, int s) {
 __device__ __forceinline__ int cell_block(const Tables& T, int& blk) {
   blk = blockIdx.x;
   if (!T.runs) return 0;
-  const int r = find_owner(T.run_blk, T.nruns, blk);
-  blk -= T.run_blk[r];
+  const int r = uniform(find_owner(T.run_blk, T.nruns, blk));
+  blk = uniform(blk - T.run_blk[r]);
   return r;
 }
 // Block -> (segment, block within segment) for kernels over particles.
 __device__ __forceinline__ int part_block(const Tables& T, int& blk) {
   blk = blockIdx.x;
   if (!T.segs) return 0;
-  const int s = find_owner(T.seg_blk, T.nsegs, blk);
-  blk -= T.seg_blk[s];
+  const int s = uniform(find_owner(T.seg_blk, T.nsegs, blk));
+  blk = uniform(blk - T.seg_blk[s]);
   return s;
 }
 
@@ -96,7 +96,9 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   const RunDesc& r = run_of(T, cell_block(T, blk));
   CellIdx x;
   if (!cell_index(r, blk, DIM, x)) return;
-  R* const* f = (R* const*)r.f;
+  gptr<R> f[F_NUM];
+#pragma unroll
+  for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
   const double h = frac * r.dt;
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0), hh = R(h);
   const R bx = f[F_BX][x.c], by = f[F_BY][x.c], bz = f[F_BZ][x.c];
@@ -126,7 +128,9 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac) {
   const RunDesc& r = run_of(T, cell_block(T, blk));
   CellIdx x;
   if (!cell_index(r, blk, DIM, x)) return;
-  R* const* f = (R* const*)r.f;
+  gptr<R> f[F_NUM];
+#pragma unroll
+  for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
   const double h = frac * r.dt;
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0);
   const R ex = f[F_EX][x.c], ey = f[F_EY][x.c], ez = f[F_EZ][x.c];
@@ -169,7 +173,7 @@ template <typename R>
 __device__ __forceinline__ GlobalAcc<R> global_acc(const RunDesc& r) {
   GlobalAcc<R> A;
 #pragma unroll
-  for (int c = 0; c < F_NUM; ++c) A.f[c] = (R*)r.f[c];
+  for (int c = 0; c < F_NUM; ++c) A.f[c] = gp((R*)r.f[c]);
   A.nx = r.nx; A.ny = r.ny; A.nz = r.nz;
   return A;
 }
@@ -426,16 +430,15 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
     const int64_t rank = (int64_t)base + (__lane_id() - head) - b0;
     const int64_t dst = b0 + (rank * mult[key]) % nb - s.pbase;
     if constexpr (sizeof(R) == 4) {
-      ((int32_t*)s.alt[P_CELL])[dst] = ((const int32_t*)s.p[P_CELL])[p];
-      ((float*)s.alt[P_OX])[dst] = ((const float*)s.p[P_OX])[p];
-      ((float*)s.alt[P_OY])[dst] = ((const float*)s.p[P_OY])[p];
-      if (DIM == 3) ((float*)s.alt[P_OZ])[dst] = ((const float*)s.p[P_OZ])[p];
+      gp((int32_t*)s.alt[P_CELL])[dst] = gp((const int32_t*)s.p[P_CELL])[p];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) gp((float*)s.alt[P_OX + d])[dst] = gp((const float*)s.p[P_OX + d])[p];
     } else {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) ((double*)s.alt[P_X + d])[dst] = ((const double*)s.p[P_X + d])[p];
+      for (int d = 0; d < DIM; ++d) gp((double*)s.alt[P_X + d])[dst] = gp((const double*)s.p[P_X + d])[p];
     }
 #pragma unroll
-    for (int q = P_UX; q <= P_W; ++q) ((R*)s.alt[q])[dst] = ((const R*)s.p[q])[p];
+    for (int q = P_UX; q <= P_W; ++q) gp((R*)s.alt[q])[dst] = gp((const R*)s.p[q])[p];
   }
 }
 
@@ -521,136 +524,305 @@ __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* 
 // once.  Workgroups are mapped to chunks so that each XCD (every 8th workgroup) walks a
 // contiguous range of chunks: neighbouring tiles share that XCD's L2.
 // =======================================================================================
-template <typename R, int DIM, int ORDER>
-__device__ __forceinline__ double fused_chunk(const RunDesc& r, const SegDesc& s,
-                                              const Chunk& ch, R* sm, int with_rho,
-                                              int& escapes) {
-  const int n[3] = {r.nx, r.ny, r.nz};
+// Region geometries compiled with constant strides: (tile x, y, z, halo).  Geometry 0 is the
+// runtime-stride kernel used for every other tiling.
+struct GeoFix { int tx, ty, tz, halo; };
+__host__ __device__ constexpr GeoFix geo_table(int g) {
+  return g == 1 ? GeoFix{16, 16, 1, 5} : g == 2 ? GeoFix{8, 8, 1, 5} : g == 3 ? GeoFix{32, 32, 1, 5}
+       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 8, 8, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
+       : GeoFix{0, 0, 0, 0};
+}
+constexpr int NUM_GEO = 7;
+
+template <int DIM, int G>
+struct GeoStrides {
+  static constexpr GeoFix f = geo_table(G);
+  using type = FixStrides<f.tx + 2 * f.halo, f.ty + 2 * f.halo, DIM == 3 ? f.tz + 2 * f.halo : 1>;
+};
+template <int DIM>
+struct GeoStrides<DIM, 0> {
+  using type = DynStrides;
+};
+
+// One staged region: the home tile of a run plus `halo` cells, in LDS.
+struct Region {
+  int r0[3];     // global origin (may be negative: periodic)
+  int rw[3];     // extent
+};
+
+template <int DIM>
+__device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, int tile) {
+  Region g;
   const int TXs[3] = {1 << s.lx, 1 << s.ly, DIM == 3 ? (1 << s.lz) : 1};
-  const int halo = s.halo;
-  int t = ch.tile;
   int tc[3];
-  tc[0] = t % r.ntx; t /= r.ntx;
-  tc[1] = t % r.nty;
-  tc[2] = t / r.nty;
-  int r0[3], RWd[3];
+  tc[0] = tile % r.ntx; tile /= r.ntx;
+  tc[1] = tile % r.nty;
+  tc[2] = tile / r.nty;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (d < DIM) { r0[d] = tc[d] * TXs[d] - halo; RWd[d] = TXs[d] + 2 * halo; }
-    else { r0[d] = 0; RWd[d] = 1; }
+    if (d < DIM) { g.r0[d] = tc[d] * TXs[d] - s.halo; g.rw[d] = TXs[d] + 2 * s.halo; }
+    else { g.r0[d] = 0; g.rw[d] = 1; }
   }
-  const int plane = RWd[0] * RWd[1] * RWd[2];
-  const int njplanes = 3 + (with_rho ? 2 : 0);
-  R* const* F = (R* const*)r.f;
-  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
-  // stage E, B; clear J (and rho)
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int lx = e % RWd[0];
-    const int rest = e / RWd[0];
-    const int ly = rest % RWd[1];
-    const int lz = rest / RWd[1];
-    const int64_t g = ((int64_t)wrapm(r0[2] + lz, n[2]) * n[1] + wrapm(r0[1] + ly, n[1])) * n[0] +
-                      wrapm(r0[0] + lx, n[0]);
+  return g;
+}
+
+__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, int e) {
+  const int lx = e % g.rw[0];
+  const int rest = e / g.rw[0];
+  const int ly = rest % g.rw[1];
+  const int lz = rest / g.rw[1];
+  return ((int64_t)wrapm(g.r0[2] + lz, r.nz) * r.ny + wrapm(g.r0[1] + ly, r.ny)) * r.nx +
+         wrapm(g.r0[0] + lx, r.nx);
+}
+
+// Stage E and B of the region, clear its current (and charge) planes.
+template <typename R>
+__device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, int plane,
+                                             int njplanes, R* sm, double* jm) {
+  gptr<R> F[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][g];
+  for (int c = 0; c < 6; ++c) F[c] = gp((R*)r.f[c]);
+  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+    const int64_t gi = region_global(r, g, e);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
     for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
   }
-  __syncthreads();
-  LdsAcc<R> L;
-  L.fbase = sm;
-  L.jbase = jm;
-  L.plane = plane;
-  L.sy = RWd[0];
-  L.sz = RWd[0] * RWd[1];
-  const GlobalAcc<R> G = global_acc<R>(r);
-  const PushConst<R> k = push_const<R>(r, s);
-  double ke = 0.0;
-  for (int64_t p = ch.beg + threadIdx.x; p < ch.end; p += blockDim.x) {
-    PState<R> ps;
-    load_particle<R, DIM>(s, r, p, ps);
-    if (!ps.alive) continue;
-    // local coordinates of the start cell; the gather and the deposit path touch cells
-    // [a-3, a+4] per axis, which must lie inside the staged region
-    int a[3];
-    bool inside = true;
+}
+
+// Add the region's current (and charge) into the global arrays: one atomic per non-zero
+// entry, converted to the field precision.
+template <typename R>
+__device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, int plane,
+                                             int njplanes, const double* jm) {
+  gptr<R> F[5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (d < DIM) {
-        int v = ps.c[d] - r0[d];
-        v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
-        a[d] = v;
-        inside = inside && v >= 3 && v <= RWd[d] - 5;
-      } else {
-        a[d] = 0;
-      }
-    }
-    int pc[3];
-    R po[3], pe[3], x1[3], vz1, g1;
-    if (inside) {
-      push<DIM, ORDER>(L, a, ps, k, pc, po, pe, x1, vz1, g1);
-      deposit<DIM, ORDER>(L, pc, po, pe, ps.w, vz1, k, with_rho != 0);
-    } else {
-      ++escapes;
-      push<DIM, ORDER>(G, ps.c, ps, k, pc, po, pe, x1, vz1, g1);
-      deposit<DIM, ORDER>(G, pc, po, pe, ps.w, vz1, k, with_rho != 0);
-    }
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
-    store_particle<R, DIM>(s, r, p, ps);
-    const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] +
-                      (double)ps.u[2] * ps.u[2];
-    ke += (double)ps.w * u2 / (1.0 + (double)g1);
-  }
-  __syncthreads();
-  // flush the tile's current (and charge) with one atomic per non-zero cell
+  for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
   for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int lx = e % RWd[0];
-    const int rest = e / RWd[0];
-    const int ly = rest % RWd[1];
-    const int lz = rest / RWd[1];
-    const int64_t g = ((int64_t)wrapm(r0[2] + lz, n[2]) * n[1] + wrapm(r0[1] + ly, n[1])) * n[0] +
-                      wrapm(r0[0] + lx, n[0]);
+    const int64_t gi = region_global(r, g, e);
     for (int c = 0; c < njplanes; ++c) {
       const double v = jm[c * plane + e];
-      if (v != 0.0) atomic_add_global(F[F_JX + c] + g, R(v));
+      if (v != 0.0) atomic_add_global(F[c] + gi, R(v));
+    }
+  }
+}
+
+__device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, int seg,
+                                              int32_t p) {
+  const uint64_t mask = __ballot(want);
+  if (!mask) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(esc.count, (unsigned int)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (want) {
+    const unsigned int k = base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
+    if ((int64_t)k < esc.capacity) esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
+  }
+}
+
+// The particles of one chunk against the staged region, in rounds: each thread first
+// issues the loads of BATCH particles (256 apart, so every load instruction reads 64
+// consecutive particles) and then pushes them one by one, so HBM latency is paid once per
+// round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
+constexpr int BATCH = 4;
+
+template <typename R, int DIM, int ORDER, class ST>
+__device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
+                                                const Chunk& ch, const Region& g,
+                                                const LdsAcc<R, ST>& L, int with_rho,
+                                                bool want_ke, const EscapeList& esc) {
+  const int n[3] = {r.nx, r.ny, r.nz};
+  const PushConst<R> k = push_const<R>(r, s);
+  const PartPtrs<R> q = part_ptrs<R>(s, r);
+  double ke = 0.0;
+  const int32_t span = (int32_t)blockDim.x * BATCH;
+  for (int32_t base = ch.beg; base < ch.end; base += span) {
+    PState<R> ps[BATCH];
+    int32_t pi[BATCH];
+    bool ok[BATCH];
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      pi[b] = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+      ok[b] = pi[b] < ch.end;
+      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      bool inside = ok[b] && ps[b].alive;
+      int a[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d < DIM) {
+          // local start cell; gather and deposit touch cells [a-3, a+4] per axis
+          int v = ps[b].c[d] - g.r0[d];
+          v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
+          a[d] = v;
+          inside = inside && v >= 3 && v <= g.rw[d] - 5;
+        } else {
+          a[d] = 0;
+        }
+      }
+      escape_append(esc, ok[b] && ps[b].alive && !inside, seg, pi[b]);
+      if (!inside) continue;
+      int pcell[3];
+      R po[3], pe[3], x1[3], vz1, g1;
+      push<DIM, ORDER>(L, a, ps[b], k, pcell, po, pe, x1, vz1, g1);
+      deposit<DIM, ORDER>(L, pcell, po, pe, ps[b].w, vz1, k, with_rho != 0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps[b].c[d], ps[b].o[d], x1[d], n[d]);
+      store_particle<R, DIM>(q, pi[b], ps[b]);
+      if (want_ke) {   // diagnostic steps only
+        const double u2 = (double)ps[b].u[0] * ps[b].u[0] + (double)ps[b].u[1] * ps[b].u[1] +
+                          (double)ps[b].u[2] * ps[b].u[2];
+        ke += (double)ps[b].w * u2 / (1.0 + (double)g1);
+      }
     }
   }
   return ke * s.m;
 }
 
-template <typename R, int DIM>
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T t = T(0);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+// Fused gather + push + deposit over the chunk table, persistent: the grid is a multiple of
+// 8 and XCD x (workgroups x, x+8, ...) owns the contiguous chunk range [x*per, (x+1)*per),
+// split into equal contiguous slices per workgroup.  Consecutive chunks of one tile (and of
+// the other species of the same box, which follow in the table) reuse the staged region;
+// the region is flushed when the tile changes.
+template <typename R, int DIM, int G>
 __global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
-                                               unsigned long long* escapes_out) {
+                                               EscapeList esc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
   R* sm = (R*)smem_raw;
-  const int nch = *nchunks;
+  const int nch = uniform(*nchunks);
+  const int nb8 = gridDim.x >> 3;
   const int per = (nch + 7) >> 3;
-  const int loc = blockIdx.x >> 3;
-  if (loc >= per) return;
-  const int cid = (blockIdx.x & 7) * per + loc;
-  if (cid >= nch) return;
-  const Chunk ch = chunks[cid];
-  const SegDesc& s = seg_of(T, ch.seg);
-  const RunDesc& r = run_of(T, s.run);
-  int escapes = 0;
-  double ke = s.order == 1 ? fused_chunk<R, DIM, 1>(r, s, ch, sm, with_rho, escapes)
-                           : fused_chunk<R, DIM, 2>(r, s, ch, sm, with_rho, escapes);
-  if (kinetic || ke_to_diag || escapes_out) {
-    __shared__ double red[4];
-    __shared__ int redi[4];
-    ke = wave_sum(ke);
-    int esc = wave_sum(escapes);
-    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = ke; redi[threadIdx.x >> 6] = esc; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      int te = 0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { t += red[w]; te += redi[w]; }
-      double* kd = ke_to_diag ? r.diag + DIAG_UKIN : kinetic;
-      if (kd) atomic_add_global(kd, t);
-      if (escapes_out && te) atomicAdd(escapes_out, (unsigned long long)te);
+  const int q = (per + nb8 - 1) / nb8;
+  const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int lo = xcd * per + j * q;
+  const int hi = min(min(lo + q, (xcd + 1) * per), nch);
+  if (lo >= hi) return;
+
+  using ST = typename GeoStrides<DIM, G>::type;
+  const SegDesc& s0 = seg_of(T, uniform(chunks[lo].seg));
+  ST st;
+  if constexpr (G == 0) {
+    const int rw = (1 << s0.lx) + 2 * s0.halo, rh = (1 << s0.ly) + 2 * s0.halo;
+    const int rd = DIM == 3 ? (1 << s0.lz) + 2 * s0.halo : 1;
+    st.sy_ = rw;
+    st.sz_ = rw * rh;
+    st.plane_ = rw * rh * rd;
+  }
+  const int plane = st.plane();
+  const int njplanes = 3 + (with_rho ? 2 : 0);
+  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
+  LdsAcc<R, ST> L;
+  L.fbase = sm;
+  L.jbase = jm;
+  L.st = st;
+
+  int cur_run = -1, cur_tile = -1;
+  Region g;
+  double ke = 0.0;
+  for (int c = lo; c < hi; ++c) {
+    Chunk ch = chunks[c];
+    ch.seg = uniform(ch.seg);
+    ch.tile = uniform(ch.tile);
+    ch.beg = uniform(ch.beg);
+    ch.end = uniform(ch.end);
+    const SegDesc s = seg_of(T, ch.seg);
+    if (s.run != cur_run || ch.tile != cur_tile) {
+      if (cur_run >= 0) {
+        const RunDesc& rp = run_of(T, cur_run);
+        __syncthreads();
+        flush_region<R>(rp, g, plane, njplanes, jm);
+        if (kinetic || ke_to_diag) {
+          const double t = block_sum(ke, red);
+          if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rp.diag + DIAG_UKIN : kinetic, t);
+          ke = 0.0;
+        }
+      }
+      const RunDesc rn = run_of(T, s.run);
+      g = region_of<DIM>(rn, s, ch.tile);
+      __syncthreads();
+      stage_region<R>(rn, g, plane, njplanes, sm, jm);
+      __syncthreads();
+      cur_run = s.run;
+      cur_tile = ch.tile;
+    }
+    const RunDesc r = run_of(T, s.run);
+    const bool want_ke = kinetic || ke_to_diag;
+    ke += s.order == 1 ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc)
+                       : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc);
+  }
+  const RunDesc& rl = run_of(T, cur_run);
+  __syncthreads();
+  flush_region<R>(rl, g, plane, njplanes, jm);
+  if (kinetic || ke_to_diag) {
+    const double t = block_sum(ke, red);
+    if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rl.diag + DIAG_UKIN : kinetic, t);
+  }
+}
+
+// Escaped particles: the same push and deposit through global memory.  The last workgroup
+// to finish clears the list for the next step.
+template <typename R, int DIM, int ORDER>
+__device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s, int64_t p,
+                                             int with_rho) {
+  PState<R> ps;
+  load_particle<R, DIM>(s, r, p, ps);
+  if (!ps.alive) return 0.0;
+  const GlobalAcc<R> G = global_acc<R>(r);
+  const PushConst<R> k = push_const<R>(r, s);
+  int pcell[3];
+  R po[3], pe[3], x1[3], vz1, g1;
+  push<DIM, ORDER>(G, ps.c, ps, k, pcell, po, pe, x1, vz1, g1);
+  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+  const int n[3] = {r.nx, r.ny, r.nz};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
+  store_particle<R, DIM>(s, r, p, ps);
+  const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] + (double)ps.u[2] * ps.u[2];
+  return (double)ps.w * s.m * u2 / (1.0 + (double)g1);
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_escape(Tables T, int with_rho, double* kinetic,
+                                                int ke_to_diag, EscapeList esc) {
+  const unsigned int cnt = min((int64_t)esc.count[0], esc.capacity);
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += gridDim.x * blockDim.x) {
+    const unsigned long long v = esc.items[i];
+    const int seg = (int)(v >> 32);
+    const int64_t p = (int64_t)(v & 0xffffffffull);
+    const SegDesc& s = seg_of(T, seg);
+    const RunDesc& r = run_of(T, s.run);
+    const double ke = s.order == 1 ? escape_one<R, DIM, 1>(r, s, p, with_rho)
+                                   : escape_one<R, DIM, 2>(r, s, p, with_rho);
+    if (kinetic || ke_to_diag) atomic_add_global(ke_to_diag ? r.diag + DIAG_UKIN : kinetic, ke);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int done = atomicAdd(esc.count + 1, 1u);
+    if (done == gridDim.x - 1) {
+      atomicAdd(esc.total, (unsigned long long)esc.count[0]);
+      atomicExch(esc.count, 0u);
+      atomicExch(esc.count + 1, 0u);
     }
   }
 }
@@ -671,7 +843,9 @@ __global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int with_rho, d
   CellIdx x;
   double en = 0.0, res = 0.0, rm = 0.0, ga = 0.0;
   if (cell_index(r, blk, DIM, x)) {
-    R* const* f = (R* const*)r.f;
+    gptr<R> f[F_NUM];
+#pragma unroll
+    for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
     for (int c = 0; c < 6; ++c) {
       const double v = (double)f[c][x.c];
       en += v * v;
@@ -856,19 +1030,82 @@ void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int
   k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nbins, chunk, out, nchunks);
 }
 
-void launch_fused(const Tables& T, int prec, int dim, int nblocks, size_t smem,
-                  const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
-                  int ke_to_diag, unsigned long long* escapes, hipStream_t st) {
-  LPIC_PD(prec, dim,
-          (k_fused<R, D><<<nblocks, 256, smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
-                                                     ke_to_diag, escapes)));
+int fused_geometry(int dim, int tx, int ty, int tz, int halo) {
+  for (int g = 1; g < NUM_GEO; ++g) {
+    const GeoFix f = geo_table(g);
+    if (dim == 2 && f.tz == 1 && f.tx == tx && f.ty == ty && f.halo == halo) return g;
+    if (dim == 3 && f.tz > 1 && f.tx == tx && f.ty == ty && f.tz == tz && f.halo == halo) return g;
+  }
+  return 0;
 }
 
-hipError_t prepare_fused(int prec, int dim, size_t smem) {
+template <typename R, int D, int G>
+static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
+                           const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
+                           const EscapeList& esc, hipStream_t st) {
+  k_fused<R, D, G><<<nblocks, 256, smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
+                                               ke_to_diag, esc);
+}
+
+template <typename R, int D>
+static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
+                           const Chunk* chunks, const int32_t* nchunks, int with_rho,
+                           double* kinetic, int ke_to_diag, const EscapeList& esc,
+                           hipStream_t st) {
+#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, st)
+  if constexpr (D == 2) {
+    switch (geo) {
+      case 1: LPIC_GEO(1); return;
+      case 2: LPIC_GEO(2); return;
+      case 3: LPIC_GEO(3); return;
+      case 4: LPIC_GEO(4); return;
+      default: LPIC_GEO(0); return;
+    }
+  } else {
+    switch (geo) {
+      case 5: LPIC_GEO(5); return;
+      case 6: LPIC_GEO(6); return;
+      default: LPIC_GEO(0); return;
+    }
+  }
+#undef LPIC_GEO
+}
+
+void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
+                  const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
+                  int ke_to_diag, const EscapeList& esc, hipStream_t st) {
+  LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, chunks, nchunks, with_rho,
+                                           kinetic, ke_to_diag, esc, st)));
+  LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(T, with_rho, kinetic,
+                                                                    ke_to_diag, esc)));
+}
+
+template <typename R, int D, int G>
+static hipError_t set_smem(size_t smem, int* blocks_per_cu) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_fused<R, D, G>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256, smem);
+}
+
+hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu) {
   hipError_t e = hipSuccess;
-  LPIC_PD(prec, dim,
-          (e = hipFuncSetAttribute((const void*)k_fused<R, D>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)));
+  int* b = blocks_per_cu;
+  if (dim == 2) {
+    switch (geo) {
+      case 1: e = prec == 0 ? set_smem<float, 2, 1>(smem, b) : set_smem<double, 2, 1>(smem, b); break;
+      case 2: e = prec == 0 ? set_smem<float, 2, 2>(smem, b) : set_smem<double, 2, 2>(smem, b); break;
+      case 3: e = prec == 0 ? set_smem<float, 2, 3>(smem, b) : set_smem<double, 2, 3>(smem, b); break;
+      case 4: e = prec == 0 ? set_smem<float, 2, 4>(smem, b) : set_smem<double, 2, 4>(smem, b); break;
+      default: e = prec == 0 ? set_smem<float, 2, 0>(smem, b) : set_smem<double, 2, 0>(smem, b); break;
+    }
+  } else {
+    switch (geo) {
+      case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, b) : set_smem<double, 3, 5>(smem, b); break;
+      case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, b) : set_smem<double, 3, 6>(smem, b); break;
+      default: e = prec == 0 ? set_smem<float, 3, 0>(smem, b) : set_smem<double, 3, 0>(smem, b); break;
+    }
+  }
   return e;
 }
 
