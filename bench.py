@@ -84,7 +84,7 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
 
     sim = Simulation(wl, prec=prec, tiling=(args.tile, args.tile, 1), halo=args.halo,
                      chunk=args.chunk, sort_interval=args.sort_interval, diag_interval=10,
-                     use_graph=True)
+                     use_graph=not args.no_graph)
     tuned = None
     if tune:
         cands = []
@@ -107,7 +107,8 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     # the same number of steps again as captured graphs (no per-kernel events)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
-    sim.step(steps)
+    if not args.no_graph:
+        sim.step(steps)
     torch.cuda.synchronize()
     g1 = time.perf_counter()
     diag = sim.diagnostics(0)
@@ -115,8 +116,8 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     n = wl.nparticles
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps,
                pushes_per_s=n * steps / (t1 - t0),
-               ms_per_step_graph=1e3 * (g1 - g0) / steps,
-               pushes_per_s_graph=n * steps / (g1 - g0),
+               ms_per_step_graph=None if args.no_graph else 1e3 * (g1 - g0) / steps,
+               pushes_per_s_graph=None if args.no_graph else n * steps / (g1 - g0),
                fused_ms=st["fused_ms"] / max(1, st["fused_launches"]),
                fused_launches=st["fused_launches"],
                halo_escapes_per_push=stg["halo_escapes"] / max(1, n * stg["steps"]),
@@ -128,6 +129,20 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     del sim
     torch.cuda.empty_cache()
     return res
+
+
+def copy_calibration(mib):
+    """A plain elementwise copy of known size (read mib MiB, write mib MiB), launched three
+    times, against which the HBM byte counters of a profiler pass are scaled."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    return dict(kernel="elementwise mul by 1 (float32)", bytes_read=n * 4, bytes_written=n * 4,
+                launches=3)
 
 
 def cpu_baseline(wl):
@@ -157,6 +172,10 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="eager launches only (profiler passes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain copy of this many MiB (profiler byte calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -213,8 +232,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fused_pushes_per_s": round(wl.nparticles / (f32["fused_ms"] * 1e-3), 1),
-        "graph_mode": {"ms_per_step": round(f32["ms_per_step_graph"], 4),
-                       "pushes_per_s": round(f32["pushes_per_s_graph"], 1)},
+        "graph_mode": None if args.no_graph else {
+            "ms_per_step": round(f32["ms_per_step_graph"], 4),
+            "pushes_per_s": round(f32["pushes_per_s_graph"], 1)},
         "halo_escapes_per_push": f32["halo_escapes_per_push"],
         "diagnostics_fp32": f32["diagnostics"],
     }
@@ -224,11 +244,14 @@ def main():
                        "fused_avg_ms": round(f64["fused_ms"], 4),
                        "fused_hbm_gbs": round(algorithmic_bytes_per_push(2, False, ppc_tot) *
                                               wl.nparticles / (f64["fused_ms"] * 1e-3) / 1e9, 1),
-                       "graph_pushes_per_s": round(f64["pushes_per_s_graph"], 1),
+                       "graph_pushes_per_s": None if args.no_graph else
+                       round(f64["pushes_per_s_graph"], 1),
                        "fp32_over_fp64": round(f32["pushes_per_s"] / f64["pushes_per_s"], 3),
                        "diagnostics": f64["diagnostics"]}
     if f32["tuned"]:
         out["autotuned"] = f32["tuned"]
+    if args.copy_calibration > 0:
+        out["copy_calibration"] = copy_calibration(args.copy_calibration)
     print(json.dumps(out), flush=True)
 
 

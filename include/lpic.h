@@ -97,12 +97,16 @@ typedef struct {
  * A particle's gather and deposit touch cells up to 3 below and 4 above its cell, so with
  * halo h a particle may drift h - 3 cells below and h - 4 cells above its tile since the
  * last sort and stay on chip; particles beyond that are still handled exactly, through
- * global memory (counted in lpic_stats.halo_escapes).  halo must be >= 3. */
+ * global memory (counted in lpic_stats.halo_escapes).  halo must be >= 3.
+ * flags: LPIC_SORT_SPREAD makes every sort spread each tile's particles over the tile's
+ * range (see lpic_sort_tiles); without it only a simulation's first sort after particles
+ * are loaded does. */
+#define LPIC_SORT_SPREAD 1
 typedef struct {
   int32_t tx, ty, tz;        /* tz ignored in 2D */
   int32_t halo;
   int32_t chunk;
-  int32_t reserved0;
+  int32_t flags;             /* 0 or LPIC_SORT_SPREAD; other bits must be 0 */
 } lpic_tiling;
 
 /* ---------------------------------------------------------------------------------------
@@ -147,8 +151,13 @@ lpic_status lpic_deposit_esirkepov(const lpic_grid *grid, const lpic_fields *fie
 /* ---------------------------------------------------------------------------------------
  * Tile sort -- Algorithm 1 sorts particles by cell before the push; here particles are
  * grouped by tile with a counting sort (histogram, scan, scatter) so that each workgroup
- * of the fused kernel reads one field tile.  Order inside a tile is not specified.  Dead
- * particles go to the end.  The sorted arrays are written into `alt` (same sizes as `sp`),
+ * of the fused kernel reads one field tile.  Order inside a tile is not specified: by
+ * default a tile keeps roughly the order its particles had; with LPIC_SORT_SPREAD in
+ * tiling->flags the particle of rank r in a tile of N goes to slot r*P mod N (P coprime to
+ * N, about N/64 stretches apart), so that particles that sat together -- typically in one
+ * cell, as loaded -- end up in different wavefronts.  Spreading costs scattered writes
+ * (several times a plain sort); once spread, the order stays mixed under later plain
+ * sorts.  Dead particles go to the end.  The sorted arrays are written into `alt` (same sizes as `sp`),
  * then the array pointers of *sp and *alt are exchanged, so *sp describes the sorted data.
  * tile_offsets (device, int32, ntiles + 2 entries): start of every tile, then the start of
  * the dead block, then n.  ws: caller-owned device scratch of lpic_sort_ws_bytes() bytes.

@@ -119,6 +119,7 @@ lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec,
   if (t->halo > g->nx || t->halo > g->ny || (nd == 3 && t->halo > g->nz))
     return fail(LPIC_EINVAL, "halo larger than the grid");
   if (t->chunk < 1) return fail(LPIC_EINVAL, "chunk must be >= 1");
+  if (t->flags & ~LPIC_SORT_SPREAD) return fail(LPIC_EINVAL, "unknown tiling flags 0x%x", t->flags);
   const size_t smem = fused_smem_bytes(prec, nd, t->tx, t->ty, nd == 3 ? t->tz : 1, t->halo, 1);
   if (need_lds && smem > 160 * 1024)
     return fail(LPIC_EINVAL, "tile + halo needs %zu bytes of LDS (limit 163840)", smem);
@@ -357,7 +358,7 @@ lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_specie
     launch_zero_u32((uint32_t*)counts, nbins, stream);
     CHK(last_launch("sort clear"));
     launch_sort(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), counts,
-                tile_offsets, cursor, mult, nbins, stream);
+                tile_offsets, cursor, mult, nbins, (t.flags & LPIC_SORT_SPREAD) ? 1 : 0, stream);
     CHK(last_launch("sort"));
   } else {
     launch_zero_u32((uint32_t*)tile_offsets, nbins + 1, stream);
@@ -509,6 +510,7 @@ struct lpic_sim {
   // progress
   int64_t step = 0, sorts = 0, diag_step = -1;
   bool need_sort = true;
+  bool need_spread = true;   // the first sort after particles are loaded spreads tiles
   // graphs indexed by (sort, diag)
   hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   bool gparity[4] = {false, false, false, false};
@@ -664,8 +666,8 @@ void swap_host_buffers(lpic_sim* s) {
 
 // The device work of one step between the LOOP_START and LOOP_END hooks.  With hooks at the
 // inner stages the host runs them in between (eager mode only).
-lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, bool eager_hooks,
-                         bool capturing) {
+lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread, bool diag,
+                         bool eager_hooks, bool capturing) {
   const Tables Tc = sim_tables(s, nullptr);
   const Tables Ts = sim_tables(s, s->seg_blk_sort_d);
   if (diag) {
@@ -681,7 +683,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool diag, b
   // sort particles (every sort_interval steps)
   if (do_sort && s->nsegs > 0) {
     launch_sort(Ts, s->prec, s->ndim, s->nblk_sort, s->counts, s->offsets, s->cursor, s->mult,
-                s->nbins, st);
+                s->nbins, spread ? 1 : 0, st);
     CHK(last_launch("sort"));
     launch_swap_segments(s->segs_d, s->nsegs, st);
     CHK(last_launch("swap"));
@@ -887,13 +889,17 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
   for (int n = 0; n < nsteps; ++n) {
     CHK(run_hooks(s, LPIC_STAGE_LOOP_START));
     const bool do_sort = s->need_sort || (s->step % s->opt.sort_interval) == 0;
+    const bool always_spread = (s->opt.tiling.flags & LPIC_SORT_SPREAD) != 0;
+    const bool spread = do_sort && (s->need_spread || always_spread);
     const bool diag = s->opt.diag_interval > 0 && ((s->step + 1) % s->opt.diag_interval) == 0;
-    if (use_graph) {
+    // the one-off spreading sort runs eagerly; captured sort steps use the plain sort unless
+    // every sort spreads
+    if (use_graph && (!spread || always_spread)) {
       const int gi = (do_sort ? 2 : 0) + (diag ? 1 : 0);
       if (!s->gexec[gi]) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-        lpic_status st = enqueue_step(s, s->cap_stream, do_sort, diag, false, true);
+        lpic_status st = enqueue_step(s, s->cap_stream, do_sort, spread, diag, false, true);
         hipError_t ee = hipStreamEndCapture(s->cap_stream, &g);
         if (st != LPIC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
         if (ee != hipSuccess) return fail(LPIC_EHIP, "graph capture: %s", hipGetErrorString(ee));
@@ -904,11 +910,12 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
       HIPCHK(hipGraphLaunch(s->gexec[gi], s->stream));
       if (do_sort && s->nsegs > 0) swap_host_buffers(s);
     } else {
-      CHK(enqueue_step(s, s->stream, do_sort, diag, true, false));
+      CHK(enqueue_step(s, s->stream, do_sort, spread, diag, true, false));
     }
     if (do_sort && s->nsegs > 0) {
       ++s->sorts;
       s->need_sort = false;
+      s->need_spread = false;
     }
     if (diag) s->diag_step = s->step + 1;
     ++s->step;

@@ -15,7 +15,8 @@ void launch_deposit(const Tables& T, int prec, int dim, int nblocks, const void*
                     int with_rho, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* counts,
-                 int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, hipStream_t st);
+                 int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
+                 hipStream_t st);
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st);
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st);

@@ -327,26 +327,39 @@ __device__ __forceinline__ bool wave_runs(int key, bool valid, int& len, int& he
   return is_head;
 }
 
+// Keys of the SORT_ITEMS particles a thread handles (loads issued together); -1 past the end.
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_sort_count(Tables T, int32_t* counts) {
-  int blk;
-  const SegDesc& s = seg_of(T, part_block(T, blk));
-  const RunDesc& r = run_of(T, s.run);
+__device__ __forceinline__ void block_keys(const SegDesc& s, const RunDesc& r, int blk,
+                                           int key[SORT_ITEMS], int64_t p[SORT_ITEMS]) {
   const int64_t beg = (int64_t)blk * 256 * SORT_ITEMS;
+#pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    const int64_t p = beg + it * 256 + threadIdx.x;
-    const bool valid = p < s.n;
-    const int key = valid ? particle_bin<R, DIM>(s, r, p) : -1;
-    int len, head;
-    if (wave_runs(key, valid, len, head)) atomicAdd(&counts[key], len);
+    p[it] = beg + it * 256 + threadIdx.x;
+    key[it] = p[it] < s.n ? particle_bin<R, DIM>(s, r, p[it]) : -1;
   }
 }
 
-// Placement inside a bin: the particle of rank r (arrival order, roughly the previous
-// order, i.e. grouped by cell) goes to slot r*P mod N with P the inverse of Q mod N and
-// Q ~ N/64 coprime to N.  Slot s then holds rank s*Q mod N, so the 64 particles a wavefront
-// reads together come from 64 different stretches of the bin -- different cells -- and
-// their current goes to different LDS addresses.
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_sort_count(Tables T, int32_t* counts) {
+  int blk;
+  const SegDesc s = seg_of(T, part_block(T, blk));
+  const RunDesc r = run_of(T, s.run);
+  int key[SORT_ITEMS];
+  int64_t p[SORT_ITEMS];
+  block_keys<R, DIM>(s, r, blk, key, p);
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    int len, head;
+    if (wave_runs(key[it], key[it] >= 0, len, head)) atomicAdd(&counts[key[it]], len);
+  }
+}
+
+// Spread placement inside a bin (on request): the particle of rank r (arrival order,
+// roughly the previous order, e.g. grouped by cell as loaded) goes to slot r*P mod N with P
+// the inverse of Q mod N and Q ~ N/64 coprime to N.  Slot s then holds rank s*Q mod N, so
+// the 64 particles a wavefront reads together come from 64 different stretches of the bin
+// -- different cells -- and their current goes to different LDS addresses.  Without the
+// request P = 1: ranks are slots and writes stay contiguous.
 __device__ __forceinline__ int64_t gcd64(int64_t a, int64_t b) {
   while (b) { const int64_t t = a % b; a = b; b = t; }
   return a;
@@ -369,7 +382,8 @@ __device__ __forceinline__ int32_t spread_multiplier(int32_t n) {
 // Exclusive scan of the bin counts by one workgroup; clears the counts for the next sort
 // and records each bin's placement multiplier.
 __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* offsets,
-                                                    int32_t* cursor, int32_t* mult, int nbins) {
+                                                    int32_t* cursor, int32_t* mult, int nbins,
+                                                    int spread) {
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x;
   const int per = (nbins + 1023) / 1024;
@@ -402,44 +416,65 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
     const int32_t c = counts[b];
     offsets[b] = run;
     cursor[b] = run;
-    mult[b] = spread_multiplier(c);
+    mult[b] = spread ? spread_multiplier(c) : 1;
     counts[b] = 0;
     run += c;
   }
   if (tid == 1023) offsets[nbins] = run;
 }
 
+template <class V>
+__device__ __forceinline__ void move_items(const int64_t p[SORT_ITEMS],
+                                           const int64_t dst[SORT_ITEMS], const V* from, V* to) {
+  V v[SORT_ITEMS];
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it)
+    if (dst[it] >= 0) v[it] = gp(from)[p[it]];
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it)
+    if (dst[it] >= 0) gp(to)[dst[it]] = v[it];
+}
+
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
                                                       const int32_t* offsets,
-                                                      const int32_t* mult) {
+                                                      const int32_t* mult, int spread) {
   int blk;
-  const SegDesc& s = seg_of(T, part_block(T, blk));
-  const RunDesc& r = run_of(T, s.run);
-  const int64_t beg = (int64_t)blk * 256 * SORT_ITEMS;
+  const SegDesc s = seg_of(T, part_block(T, blk));
+  const RunDesc r = run_of(T, s.run);
+  int key[SORT_ITEMS];
+  int64_t p[SORT_ITEMS];
+  block_keys<R, DIM>(s, r, blk, key, p);
+  // destinations: one cursor atomic per run of equal keys in a wave
+  int64_t dst[SORT_ITEMS];
+#pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    const int64_t p = beg + it * 256 + threadIdx.x;
-    const bool valid = p < s.n;
-    const int key = valid ? particle_bin<R, DIM>(s, r, p) : -1;
     int len, head;
     int base = 0;
-    if (wave_runs(key, valid, len, head)) base = atomicAdd(&cursor[key], len);
+    if (wave_runs(key[it], key[it] >= 0, len, head)) base = atomicAdd(&cursor[key[it]], len);
     base = __shfl(base, head, 64);
-    if (!valid) continue;
-    const int32_t b0 = offsets[key], nb = offsets[key + 1] - b0;
-    const int64_t rank = (int64_t)base + (__lane_id() - head) - b0;
-    const int64_t dst = b0 + (rank * mult[key]) % nb - s.pbase;
-    if constexpr (sizeof(R) == 4) {
-      gp((int32_t*)s.alt[P_CELL])[dst] = gp((const int32_t*)s.p[P_CELL])[p];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) gp((float*)s.alt[P_OX + d])[dst] = gp((const float*)s.p[P_OX + d])[p];
-    } else {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) gp((double*)s.alt[P_X + d])[dst] = gp((const double*)s.p[P_X + d])[p];
+    dst[it] = -1;
+    if (key[it] >= 0) {
+      const int64_t slot = (int64_t)base + (__lane_id() - head);
+      if (spread) {
+        const int32_t b0 = offsets[key[it]], nb = offsets[key[it] + 1] - b0;
+        dst[it] = b0 + ((slot - b0) * mult[key[it]]) % nb - s.pbase;
+      } else {
+        dst[it] = slot - s.pbase;
+      }
     }
-#pragma unroll
-    for (int q = P_UX; q <= P_W; ++q) gp((R*)s.alt[q])[dst] = gp((const R*)s.p[q])[p];
   }
+  // move the particle arrays, one array at a time for all items (loads issued together)
+  if constexpr (sizeof(R) == 4) {
+    move_items(p, dst, (const int32_t*)s.p[P_CELL], (int32_t*)s.alt[P_CELL]);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) move_items(p, dst, (const float*)s.p[P_OX + d], (float*)s.alt[P_OX + d]);
+  } else {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) move_items(p, dst, (const double*)s.p[P_X + d], (double*)s.alt[P_X + d]);
+  }
+#pragma unroll
+  for (int q = P_UX; q <= P_W; ++q) move_items(p, dst, (const R*)s.p[q], (R*)s.alt[q]);
 }
 
 // After a sort inside a simulation, the device segment table points at the sorted buffers.
@@ -1015,10 +1050,12 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
 }
 
 void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* counts,
-                 int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, hipStream_t st) {
+                 int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
+                 hipStream_t st) {
   LPIC_PD(prec, dim, (k_sort_count<R, D><<<nblocks, 256, 0, st>>>(T, counts)));
-  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins);
-  LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult)));
+  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread);
+  LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult,
+                                                                     spread)));
 }
 
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {

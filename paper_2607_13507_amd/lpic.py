@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblpic.so")
 F32_CELLOFS = 0
 F64_ABS = 1
 YEE_ZERO_J = 1
+SORT_SPREAD = 1
 
 STAGES = ["START", "LOOP_START", "MAXWELL_1", "PUSH_POSITION_1", "INTERPOLATOR",
           "PUSH_MOMENTUM", "PUSH_POSITION_2", "CURRENT_DEPOSITION", "QED_CREATE",
@@ -49,7 +50,7 @@ class Species(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_int32), ("ty", ctypes.c_int32), ("tz", ctypes.c_int32),
-                ("halo", ctypes.c_int32), ("chunk", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("halo", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):

@@ -75,3 +75,7 @@ def test_error_path_without_gpu(lib):
     with pytest.raises(L.LpicError) as e:
         L.lpic_sort_tiles(g, s, s, t, 1, 1, 1 << 20, L.F32_CELLOFS, stream=0)
     assert "power" in str(e.value)
+    t = L.Tiling(16, 16, 1, 4, 256, 4)
+    with pytest.raises(L.LpicError) as e:
+        L.lpic_sort_tiles(g, s, s, t, 1, 1, 1 << 20, L.F32_CELLOFS, stream=0)
+    assert "flags" in str(e.value)

@@ -114,8 +114,9 @@ def _tile_of(grid, tiling, pos):
 
 @pytest.mark.parametrize("prec", PRECS, ids=PNAME.get)
 @pytest.mark.parametrize("ndim", [2, 3])
-def test_sort_is_an_exact_tile_grouping(prec, ndim):
-    banner(f"sort prec={PNAME[prec]} ndim={ndim}")
+@pytest.mark.parametrize("spread", [False, True], ids=["plain", "spread"])
+def test_sort_is_an_exact_tile_grouping(prec, ndim, spread):
+    banner(f"sort prec={PNAME[prec]} ndim={ndim} spread={spread}")
     wl = small_2d(2) if ndim == 2 else small_3d(2)
     n = wl.species[0].n
     wl.species[0].w = np.arange(1, n + 1, dtype=np.float64)   # unique tags (exact in FP32)
@@ -123,6 +124,7 @@ def test_sort_is_an_exact_tile_grouping(prec, ndim):
     dead = np.arange(0, n, 97)
     wl.species[0].x[dead] = -1.0
     tiling = _tiling(prec, ndim, chunk=64)
+    tiling.flags = L.SORT_SPREAD if spread else 0
     grid, F, d0, alt, offs, orc = _sorted_state(wl, prec, tiling)
     # after the call the struct's pointers were exchanged: `alt` tensors hold the sorted data
     cur, before = alt, d0
