@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 KERNEL_SOURCES = ("paper_2607_13507_amd/csrc/lpic_device.hpp",
-                  "paper_2607_13507_amd/csrc/lpic_kernels.hip")
+                  "paper_2607_13507_amd/csrc/lpic_fused.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_laser_slab_2048x1024_pmc.md")
 
 

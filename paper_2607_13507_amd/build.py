@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblpic.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lpic_kernels.hip", "lpic_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lpic_kernels.hip", "lpic_fused.hip", "lpic_api.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("lpic_device.hpp", "lpic_internal.hpp")] + \
           [os.path.join(ROOT, "include", "lpic.h")]
 

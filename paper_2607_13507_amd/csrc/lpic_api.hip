@@ -408,8 +408,13 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   Chunk* chunks = (Chunk*)((char*)ws + 256);
   esc.items = (unsigned long long*)((char*)chunks + align256((size_t)maxch * sizeof(Chunk)));
   esc.capacity = sp->n;
-  launch_zero_u32((uint32_t*)ws, 64, stream);          // chunk count, escape counters, total
+  unsigned long long* wmax = (unsigned long long*)((char*)ws + 192);
+  int32_t* jshift = (int32_t*)((char*)ws + 224);
+  launch_zero_u32((uint32_t*)ws, 64, stream);   // chunk count, escape counters, weight max
   CHK(last_launch("fused clear"));
+  launch_fixed_shift(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), 1, 1,
+                     wmax, jshift, stream);
+  CHK(last_launch("fixed-point shift"));
   launch_build_chunks(T, tile_offsets, r.ntiles + 1, t.chunk, chunks, nchunks, stream);
   CHK(last_launch("build chunks"));
   const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
@@ -417,7 +422,7 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   int bpc = 1;
   HIPCHK(prepare_fused(prec, grid->ndim, geo, smem, &bpc));
   launch_fused(T, prec, grid->ndim, geo, fused_grid(maxch, bpc), smem, chunks, nchunks, with_rho,
-               kinetic, 0, esc, stream);
+               kinetic, 0, esc, jshift, stream);
   return last_launch("fused");
 }
 
@@ -502,6 +507,8 @@ struct lpic_sim {
   unsigned long long* escapes = nullptr;     // cumulative escape count
   unsigned int* esc_count = nullptr;         // per-step escape counters
   unsigned long long* esc_items = nullptr;   // escape list (capacity: all particles)
+  unsigned long long* wmax = nullptr;        // per segment: max |w| (FP64 bits)
+  int32_t* jshift = nullptr;                 // per run: fixed-point shift of FP32 currents
   int64_t esc_capacity = 0;
   int blocks_per_cu = 1;
   void* old_state = nullptr;
@@ -538,6 +545,12 @@ void drop_graphs(lpic_sim* s) {
 bool intermediate_hooks(const lpic_sim* s) {
   for (int st = LPIC_STAGE_PUSH_POSITION_1; st <= LPIC_STAGE_PUSH_POSITION_2; ++st)
     if (!s->hooks[st].empty()) return true;
+  return false;
+}
+
+bool any_hooks(const lpic_sim* s) {
+  for (const auto& v : s->hooks)
+    if (!v.empty()) return true;
   return false;
 }
 
@@ -646,6 +659,10 @@ lpic_status configure(lpic_sim* s) {
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1);
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, &s->blocks_per_cu));
+  if (!s->wmax) {
+    ALLOC(s->wmax, sizeof(unsigned long long) * std::max(1, s->nsegs));
+    ALLOC(s->jshift, sizeof(int32_t) * std::max(1, s->nruns));
+  }
   if (!s->esc_items) {
     s->esc_capacity = std::max<int64_t>(pbase, 1);
     ALLOC(s->esc_items, sizeof(unsigned long long) * s->esc_capacity);
@@ -662,6 +679,18 @@ void swap_host_buffers(lpic_sim* s) {
     std::swap(s->sp[i], s->alt[i]);
     for (int q = 0; q < P_NUM; ++q) std::swap(s->segs_h[i].p[q], s->segs_h[i].alt[q]);
   }
+}
+
+// Fixed-point shift of the FP32 current accumulators from the present weights.  Weights
+// change only through the caller (between lpic_step calls or in hooks), so this runs at
+// the start of every lpic_step call and, when hooks are registered, in every step.
+lpic_status enqueue_fixed_shift(lpic_sim* s, hipStream_t st) {
+  if (s->nsegs == 0 || s->prec != LPIC_F32_CELLOFS) return LPIC_OK;
+  launch_zero_u32((uint32_t*)s->wmax, 2 * (int64_t)s->nsegs, st);
+  CHK(last_launch("weight max clear"));
+  launch_fixed_shift(sim_tables(s, s->seg_blk_sort_d), s->prec, s->ndim, s->nblk_sort, s->nruns,
+                     s->nsegs, s->wmax, s->jshift, st);
+  return last_launch("fixed-point shift");
 }
 
 // The device work of one step between the LOOP_START and LOOP_END hooks.  With hooks at the
@@ -695,6 +724,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     if (!capturing) swap_host_buffers(s);
   }
   // particle loop
+  if (any_hooks(s)) CHK(enqueue_fixed_shift(s, st));
   const bool fused = !intermediate_hooks(s);
   s->last_fused = fused;
   if (s->nsegs > 0) {
@@ -718,7 +748,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       esc.capacity = s->esc_capacity;
       launch_fused(Tc, s->prec, s->ndim, s->geo, fused_grid(s->max_chunks, s->blocks_per_cu),
                    diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
-                   diag ? 1 : 0, esc, st);
+                   diag ? 1 : 0, esc, s->jshift, st);
       CHK(last_launch("fused"));
       if (s->timing) {
         HIPCHK(hipEventRecord(e1, st));
@@ -857,6 +887,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
   free_dev(s->esc_items); free_dev(s->esc_count);
+  free_dev(s->wmax); free_dev(s->jshift);
   free_dev(s->old_state);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
@@ -886,6 +917,7 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
   const bool use_graph = s->opt.use_graph && !s->timing && !inner_hooks(s);
   s->last_graph = use_graph;
   CHK(run_hooks(s, LPIC_STAGE_START));
+  if (nsteps > 0) CHK(enqueue_fixed_shift(s, s->stream));
   for (int n = 0; n < nsteps; ++n) {
     CHK(run_hooks(s, LPIC_STAGE_LOOP_START));
     const bool do_sort = s->need_sort || (s->step % s->opt.sort_interval) == 0;

@@ -216,8 +216,9 @@ struct DynStrides {
 template <typename R, class S>
 struct LdsAcc {
   R* fbase;       // planes Ex Ey Ez Bx By Bz
-  double* jbase;  // planes Jx Jy Jz, then rho0 rho1
+  double* jbase;  // planes Jx Jy Jz, then rho0 rho1 (FP32 path: int64 fixed point)
   S st;
+  double jscale;  // FP32 path: 2^S, the fixed-point scale of the current accumulators
   __device__ __forceinline__ int xo(int x) const { return x; }
   __device__ __forceinline__ int yo(int y) const { return y * st.sy(); }
   __device__ __forceinline__ int zo(int z) const { return z * st.sz(); }
@@ -226,8 +227,23 @@ struct LdsAcc {
   }
   // Exact zeros are skipped: a particle that keeps its nearest node leaves a zero row and
   // column in its window, and a lane masked off costs the LDS nothing.
+  // FP32 path: the accumulators are signed 64-bit fixed point with 2^-S resolution
+  // (integer LDS atomics run about twice as fast as FP64 ones on gfx950, and integer sums
+  // do not depend on the order of the adds).  v 2^S is rounded to the nearest integer by
+  // adding 1.5 2^52 in FP64, whose low mantissa bits then hold it; |v| 2^S < 2^51 is
+  // guaranteed by the choice of S (fixed_shift).
   __device__ __forceinline__ void add(int comp, int off, R v) const {
-    if (v != R(0)) atomic_add_lds(jbase + (comp - F_JX) * st.plane() + off, (double)v);
+    if (v == R(0)) return;
+    double* p = jbase + (comp - F_JX) * st.plane() + off;
+    if constexpr (sizeof(R) == 4) {
+      const double y = __builtin_fma((double)v, jscale, 0x1.8p52);
+      const unsigned long long k =
+          (unsigned long long)__double_as_longlong(y) - 0x4338000000000000ull;
+      __hip_atomic_fetch_add((unsigned long long*)p, k, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      atomic_add_lds(p, (double)v);
+    }
   }
 };
 
@@ -695,6 +711,65 @@ __device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
   }
   vz1 = ps.u[2] * ig1;
   gamma1 = R(1) / ig1;
+}
+
+// Global-memory accumulator over a run's field arrays.
+template <typename R>
+__device__ __forceinline__ GlobalAcc<R> global_acc(const RunDesc& r) {
+  GlobalAcc<R> A;
+#pragma unroll
+  for (int c = 0; c < F_NUM; ++c) A.f[c] = gp((R*)r.f[c]);
+  A.nx = r.nx; A.ny = r.ny; A.nz = r.nz;
+  return A;
+}
+
+// =======================================================================================
+// Descriptor lookup and wave/block utilities shared by the kernels
+// =======================================================================================
+__device__ __forceinline__ const RunDesc& run_of(const Tables& T, int r) {
+  return T.runs ? T.runs[r] : T.run0;
+}
+__device__ __forceinline__ const SegDesc& seg_of(const Tables& T, int s) {
+  return T.segs ? T.segs[s] : T.seg0;
+}
+
+// Block -> (run, block within run) for kernels over grid cells.
+__device__ __forceinline__ int cell_block(const Tables& T, int& blk) {
+  blk = blockIdx.x;
+  if (!T.runs) return 0;
+  const int r = uniform(find_owner(T.run_blk, T.nruns, blk));
+  blk = uniform(blk - T.run_blk[r]);
+  return r;
+}
+// Block -> (segment, block within segment) for kernels over particles.
+__device__ __forceinline__ int part_block(const Tables& T, int& blk) {
+  blk = blockIdx.x;
+  if (!T.segs) return 0;
+  const int s = uniform(find_owner(T.seg_blk, T.nsegs, blk));
+  blk = uniform(blk - T.seg_blk[s]);
+  return s;
+}
+
+// Full periodic wrap (the staged region may be wider than a small box).
+__device__ __forceinline__ int wrapm(int i, int n) {
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
 }
 
 }  // namespace lpic

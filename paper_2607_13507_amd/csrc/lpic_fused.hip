@@ -1,0 +1,416 @@
+// The fused particle kernel of the PIC hot path (gfx950, wave64): gather + relativistic
+// Boris push + Esirkepov deposit in one pass over a tile-sorted particle stream, with the
+// field tile staged in LDS and the tile's current accumulated in LDS (FP64) before one
+// global atomic flush per non-zero entry; plus the kernel that handles, through global
+// memory, the particles that have left the on-chip margin of their tile.
+#include "lpic_internal.hpp"
+
+namespace lpic {
+
+// =======================================================================================
+// Fused gather + push + deposit (unified pusher).  One workgroup per chunk; the chunk's
+// field tile (tile + halo) is staged in LDS, the current accumulates in LDS and is flushed
+// once.  Workgroups are mapped to chunks so that each XCD (every 8th workgroup) walks a
+// contiguous range of chunks: neighbouring tiles share that XCD's L2.
+// =======================================================================================
+// Region geometries compiled with constant strides: (tile x, y, z, halo).  Geometry 0 is the
+// runtime-stride kernel used for every other tiling.
+struct GeoFix { int tx, ty, tz, halo; };
+__host__ __device__ constexpr GeoFix geo_table(int g) {
+  return g == 1 ? GeoFix{16, 16, 1, 5} : g == 2 ? GeoFix{8, 8, 1, 5} : g == 3 ? GeoFix{32, 32, 1, 5}
+       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 8, 8, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
+       : GeoFix{0, 0, 0, 0};
+}
+constexpr int NUM_GEO = 7;
+
+template <int DIM, int G>
+struct GeoStrides {
+  static constexpr GeoFix f = geo_table(G);
+  using type = FixStrides<f.tx + 2 * f.halo, f.ty + 2 * f.halo, DIM == 3 ? f.tz + 2 * f.halo : 1>;
+};
+template <int DIM>
+struct GeoStrides<DIM, 0> {
+  using type = DynStrides;
+};
+
+// One staged region: the home tile of a run plus `halo` cells, in LDS.
+struct Region {
+  int r0[3];     // global origin (may be negative: periodic)
+  int rw[3];     // extent
+};
+
+template <int DIM>
+__device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, int tile) {
+  Region g;
+  const int TXs[3] = {1 << s.lx, 1 << s.ly, DIM == 3 ? (1 << s.lz) : 1};
+  int tc[3];
+  tc[0] = tile % r.ntx; tile /= r.ntx;
+  tc[1] = tile % r.nty;
+  tc[2] = tile / r.nty;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) { g.r0[d] = tc[d] * TXs[d] - s.halo; g.rw[d] = TXs[d] + 2 * s.halo; }
+    else { g.r0[d] = 0; g.rw[d] = 1; }
+  }
+  return g;
+}
+
+__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, int e) {
+  const int lx = e % g.rw[0];
+  const int rest = e / g.rw[0];
+  const int ly = rest % g.rw[1];
+  const int lz = rest / g.rw[1];
+  return ((int64_t)wrapm(g.r0[2] + lz, r.nz) * r.ny + wrapm(g.r0[1] + ly, r.ny)) * r.nx +
+         wrapm(g.r0[0] + lx, r.nx);
+}
+
+// Stage E and B of the region, clear its current (and charge) planes.
+template <typename R>
+__device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, int plane,
+                                             int njplanes, R* sm, double* jm) {
+  gptr<R> F[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) F[c] = gp((R*)r.f[c]);
+  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+    const int64_t gi = region_global(r, g, e);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
+    for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
+  }
+}
+
+// Add the region's current (and charge) into the global arrays: one atomic per non-zero
+// entry, converted to the field precision (FP32 path: from fixed point, times 2^-S).
+template <typename R>
+__device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, int plane,
+                                             int njplanes, const double* jm, double unscale) {
+  gptr<R> F[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
+  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+    const int64_t gi = region_global(r, g, e);
+    for (int c = 0; c < njplanes; ++c) {
+      double v;
+      if constexpr (sizeof(R) == 4) v = (double)((const long long*)jm)[c * plane + e] * unscale;
+      else v = jm[c * plane + e];
+      if (v != 0.0) atomic_add_global(F[c] + gi, R(v));
+    }
+  }
+}
+
+__device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, int seg,
+                                              int32_t p) {
+  const uint64_t mask = __ballot(want);
+  if (!mask) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(esc.count, (unsigned int)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (want) {
+    const unsigned int k = base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
+    if ((int64_t)k < esc.capacity) esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
+  }
+}
+
+// The particles of one chunk against the staged region, in rounds: each thread first
+// issues the loads of BATCH particles (256 apart, so every load instruction reads 64
+// consecutive particles) and then pushes them one by one, so HBM latency is paid once per
+// round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
+constexpr int BATCH = 4;
+
+template <typename R, int DIM, int ORDER, class ST>
+__device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
+                                                const Chunk& ch, const Region& g,
+                                                const LdsAcc<R, ST>& L, int with_rho,
+                                                bool want_ke, const EscapeList& esc) {
+  const int n[3] = {r.nx, r.ny, r.nz};
+  const PushConst<R> k = push_const<R>(r, s);
+  const PartPtrs<R> q = part_ptrs<R>(s, r);
+  double ke = 0.0;
+  const int32_t span = (int32_t)blockDim.x * BATCH;
+  for (int32_t base = ch.beg; base < ch.end; base += span) {
+    PState<R> ps[BATCH];
+    int32_t pi[BATCH];
+    bool ok[BATCH];
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      pi[b] = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+      ok[b] = pi[b] < ch.end;
+      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      bool inside = ok[b] && ps[b].alive;
+      int a[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d < DIM) {
+          // local start cell; gather and deposit touch cells [a-3, a+4] per axis
+          int v = ps[b].c[d] - g.r0[d];
+          v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
+          a[d] = v;
+          inside = inside && v >= 3 && v <= g.rw[d] - 5;
+        } else {
+          a[d] = 0;
+        }
+      }
+      escape_append(esc, ok[b] && ps[b].alive && !inside, seg, pi[b]);
+      if (!inside) continue;
+      int pcell[3];
+      R po[3], pe[3], x1[3], vz1, g1;
+      push<DIM, ORDER>(L, a, ps[b], k, pcell, po, pe, x1, vz1, g1);
+      deposit<DIM, ORDER>(L, pcell, po, pe, ps[b].w, vz1, k, with_rho != 0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps[b].c[d], ps[b].o[d], x1[d], n[d]);
+      store_particle<R, DIM>(q, pi[b], ps[b]);
+      if (want_ke) {   // diagnostic steps only
+        const double u2 = (double)ps[b].u[0] * ps[b].u[0] + (double)ps[b].u[1] * ps[b].u[1] +
+                          (double)ps[b].u[2] * ps[b].u[2];
+        ke += (double)ps[b].w * u2 / (1.0 + (double)g1);
+      }
+    }
+  }
+  return ke * s.m;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T t = T(0);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+// Fused gather + push + deposit over the chunk table, persistent: the grid is a multiple of
+// 8 and XCD x (workgroups x, x+8, ...) owns the contiguous chunk range [x*per, (x+1)*per),
+// split into equal contiguous slices per workgroup.  Consecutive chunks of one tile (and of
+// the other species of the same box, which follow in the table) reuse the staged region;
+// the region is flushed when the tile changes.
+template <typename R, int DIM, int G>
+__global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
+                                               const int32_t* nchunks, int with_rho,
+                                               double* kinetic, int ke_to_diag,
+                                               EscapeList esc, const int32_t* jshift) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
+  R* sm = (R*)smem_raw;
+  const int nch = uniform(*nchunks);
+  const int nb8 = gridDim.x >> 3;
+  const int per = (nch + 7) >> 3;
+  const int q = (per + nb8 - 1) / nb8;
+  const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int lo = xcd * per + j * q;
+  const int hi = min(min(lo + q, (xcd + 1) * per), nch);
+  if (lo >= hi) return;
+
+  using ST = typename GeoStrides<DIM, G>::type;
+  const SegDesc& s0 = seg_of(T, uniform(chunks[lo].seg));
+  ST st;
+  if constexpr (G == 0) {
+    const int rw = (1 << s0.lx) + 2 * s0.halo, rh = (1 << s0.ly) + 2 * s0.halo;
+    const int rd = DIM == 3 ? (1 << s0.lz) + 2 * s0.halo : 1;
+    st.sy_ = rw;
+    st.sz_ = rw * rh;
+    st.plane_ = rw * rh * rd;
+  }
+  const int plane = st.plane();
+  const int njplanes = 3 + (with_rho ? 2 : 0);
+  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
+  LdsAcc<R, ST> L;
+  L.fbase = sm;
+  L.jbase = jm;
+  L.st = st;
+
+  int cur_run = -1, cur_tile = -1;
+  Region g;
+  double ke = 0.0;
+  double unscale = 1.0;
+  for (int c = lo; c < hi; ++c) {
+    Chunk ch = chunks[c];
+    ch.seg = uniform(ch.seg);
+    ch.tile = uniform(ch.tile);
+    ch.beg = uniform(ch.beg);
+    ch.end = uniform(ch.end);
+    const SegDesc s = seg_of(T, ch.seg);
+    if (s.run != cur_run || ch.tile != cur_tile) {
+      if (cur_run >= 0) {
+        const RunDesc& rp = run_of(T, cur_run);
+        __syncthreads();
+        flush_region<R>(rp, g, plane, njplanes, jm, unscale);
+        if (kinetic || ke_to_diag) {
+          const double t = block_sum(ke, red);
+          if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rp.diag + DIAG_UKIN : kinetic, t);
+          ke = 0.0;
+        }
+      }
+      if constexpr (sizeof(R) == 4) {
+        const int sh = uniform(jshift[s.run]);
+        L.jscale = ldexp(1.0, sh);
+        unscale = ldexp(1.0, -sh);
+      }
+      const RunDesc rn = run_of(T, s.run);
+      g = region_of<DIM>(rn, s, ch.tile);
+      __syncthreads();
+      stage_region<R>(rn, g, plane, njplanes, sm, jm);
+      __syncthreads();
+      cur_run = s.run;
+      cur_tile = ch.tile;
+    }
+    const RunDesc r = run_of(T, s.run);
+    const bool want_ke = kinetic || ke_to_diag;
+    ke += s.order == 1 ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc)
+                       : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc);
+  }
+  const RunDesc& rl = run_of(T, cur_run);
+  __syncthreads();
+  flush_region<R>(rl, g, plane, njplanes, jm, unscale);
+  if (kinetic || ke_to_diag) {
+    const double t = block_sum(ke, red);
+    if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rl.diag + DIAG_UKIN : kinetic, t);
+  }
+}
+
+// Escaped particles: the same push and deposit through global memory.  The last workgroup
+// to finish clears the list for the next step.
+template <typename R, int DIM, int ORDER>
+__device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s, int64_t p,
+                                             int with_rho) {
+  PState<R> ps;
+  load_particle<R, DIM>(s, r, p, ps);
+  if (!ps.alive) return 0.0;
+  const GlobalAcc<R> G = global_acc<R>(r);
+  const PushConst<R> k = push_const<R>(r, s);
+  int pcell[3];
+  R po[3], pe[3], x1[3], vz1, g1;
+  push<DIM, ORDER>(G, ps.c, ps, k, pcell, po, pe, x1, vz1, g1);
+  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+  const int n[3] = {r.nx, r.ny, r.nz};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
+  store_particle<R, DIM>(s, r, p, ps);
+  const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] + (double)ps.u[2] * ps.u[2];
+  return (double)ps.w * s.m * u2 / (1.0 + (double)g1);
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_escape(Tables T, int with_rho, double* kinetic,
+                                                int ke_to_diag, EscapeList esc) {
+  const unsigned int cnt = min((int64_t)esc.count[0], esc.capacity);
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += gridDim.x * blockDim.x) {
+    const unsigned long long v = esc.items[i];
+    const int seg = (int)(v >> 32);
+    const int64_t p = (int64_t)(v & 0xffffffffull);
+    const SegDesc& s = seg_of(T, seg);
+    const RunDesc& r = run_of(T, s.run);
+    const double ke = s.order == 1 ? escape_one<R, DIM, 1>(r, s, p, with_rho)
+                                   : escape_one<R, DIM, 2>(r, s, p, with_rho);
+    if (kinetic || ke_to_diag) atomic_add_global(ke_to_diag ? r.diag + DIAG_UKIN : kinetic, ke);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int done = atomicAdd(esc.count + 1, 1u);
+    if (done == gridDim.x - 1) {
+      atomicAdd(esc.total, (unsigned long long)esc.count[0]);
+      atomicExch(esc.count, 0u);
+      atomicExch(esc.count + 1, 0u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------------------
+int fused_geometry(int dim, int tx, int ty, int tz, int halo) {
+  for (int g = 1; g < NUM_GEO; ++g) {
+    const GeoFix f = geo_table(g);
+    if (dim == 2 && f.tz == 1 && f.tx == tx && f.ty == ty && f.halo == halo) return g;
+    if (dim == 3 && f.tz > 1 && f.tx == tx && f.ty == ty && f.tz == tz && f.halo == halo) return g;
+  }
+  return 0;
+}
+
+template <typename R, int D, int G>
+static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
+                           const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
+                           const EscapeList& esc, const int32_t* jshift, hipStream_t st) {
+  k_fused<R, D, G><<<nblocks, 256, smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
+                                               ke_to_diag, esc, jshift);
+}
+
+template <typename R, int D>
+static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
+                           const Chunk* chunks, const int32_t* nchunks, int with_rho,
+                           double* kinetic, int ke_to_diag, const EscapeList& esc,
+                           const int32_t* jshift, hipStream_t st) {
+#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, jshift, st)
+  if constexpr (D == 2) {
+    switch (geo) {
+      case 1: LPIC_GEO(1); return;
+      case 2: LPIC_GEO(2); return;
+      case 3: LPIC_GEO(3); return;
+      case 4: LPIC_GEO(4); return;
+      default: LPIC_GEO(0); return;
+    }
+  } else {
+    switch (geo) {
+      case 5: LPIC_GEO(5); return;
+      case 6: LPIC_GEO(6); return;
+      default: LPIC_GEO(0); return;
+    }
+  }
+#undef LPIC_GEO
+}
+
+void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
+                  const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
+                  int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
+                  hipStream_t st) {
+  LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, chunks, nchunks, with_rho,
+                                           kinetic, ke_to_diag, esc, jshift, st)));
+  LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(T, with_rho, kinetic,
+                                                                    ke_to_diag, esc)));
+}
+
+template <typename R, int D, int G>
+static hipError_t set_smem(size_t smem, int* blocks_per_cu) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_fused<R, D, G>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256, smem);
+}
+
+hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu) {
+  hipError_t e = hipSuccess;
+  int* b = blocks_per_cu;
+  if (dim == 2) {
+    switch (geo) {
+      case 1: e = prec == 0 ? set_smem<float, 2, 1>(smem, b) : set_smem<double, 2, 1>(smem, b); break;
+      case 2: e = prec == 0 ? set_smem<float, 2, 2>(smem, b) : set_smem<double, 2, 2>(smem, b); break;
+      case 3: e = prec == 0 ? set_smem<float, 2, 3>(smem, b) : set_smem<double, 2, 3>(smem, b); break;
+      case 4: e = prec == 0 ? set_smem<float, 2, 4>(smem, b) : set_smem<double, 2, 4>(smem, b); break;
+      default: e = prec == 0 ? set_smem<float, 2, 0>(smem, b) : set_smem<double, 2, 0>(smem, b); break;
+    }
+  } else {
+    switch (geo) {
+      case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, b) : set_smem<double, 3, 5>(smem, b); break;
+      case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, b) : set_smem<double, 3, 6>(smem, b); break;
+      default: e = prec == 0 ? set_smem<float, 3, 0>(smem, b) : set_smem<double, 3, 0>(smem, b); break;
+    }
+  }
+  return e;
+}
+
+size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
+  const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
+  // six field planes in the kernel precision (padded to 8 bytes), then FP64 current planes
+  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * (3 + (with_rho ? 2 : 0)) * 8;
+}
+
+}  // namespace lpic

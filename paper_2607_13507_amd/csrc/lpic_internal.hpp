@@ -1,9 +1,22 @@
-// Internal interface between the C ABI (lpic_api.hip) and the kernels (lpic_kernels.hip).
+// Internal interface between the C ABI (lpic_api.hip) and the kernels (lpic_kernels.hip,
+// lpic_fused.hip).
 #pragma once
 
 #include "lpic_device.hpp"
 
 namespace lpic {
+
+// Instantiate `call` with R (float / double) and D (2 / 3) from runtime values.
+#define LPIC_PD(prec, dim, call)                                  \
+  do {                                                            \
+    if (prec == 0) {                                              \
+      if (dim == 2) { using R = float; constexpr int D = 2; call; } \
+      else { using R = float; constexpr int D = 3; call; }        \
+    } else {                                                      \
+      if (dim == 2) { using R = double; constexpr int D = 2; call; } \
+      else { using R = double; constexpr int D = 3; call; }       \
+    }                                                             \
+  } while (0)
 
 constexpr int SORT_BLOCK = 2048;   // particles per workgroup of the sort kernels
 
@@ -35,9 +48,16 @@ constexpr int ESCAPE_BLOCKS = 512;
 int fused_geometry(int dim, int tx, int ty, int tz, int halo);
 // Launches the fused kernel (persistent grid of nblocks, a multiple of 8) and then the
 // escape kernel on the same stream.
+// jshift[run]: the fixed-point shift S of the FP32 current accumulators (launch_fixed_shift).
 void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
                   const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
-                  int ke_to_diag, const EscapeList& esc, hipStream_t st);
+                  int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
+                  hipStream_t st);
+// Per run, the shift S for the fixed-point current accumulators of the fused kernel, from
+// the largest |q w| of its species (wmax: one 8-byte slot per segment, zeroed by the
+// caller; nblocks workgroups of SORT_BLOCK particles as for the sort) and its particle count.
+void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
+                        unsigned long long* wmax, int32_t* jshift, hipStream_t st);
 // Sets the dynamic LDS limit and returns how many workgroups of the kernel fit on a CU.
 hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu);
 void launch_reduce_fields(const Tables& T, int prec, int dim, int nblocks, int with_rho,

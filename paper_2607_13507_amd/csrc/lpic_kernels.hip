@@ -6,55 +6,6 @@
 
 namespace lpic {
 
-// =======================================================================================
-// Small utilities
-// =======================================================================================
-__device__ __forceinline__ const RunDesc& run_of(const Tables& T, int r) {
-  return T.runs ? T.runs[r] : T.run0;
-}
-__device__ __forceinline__ const SegDesc& seg_of(const Tables& T, int s) {
-  return T.segs ? T.segs[s] : T.seg0;
-}
-
-// Block -> (run, block within run) for kernels over grid cells.
-__device__ __forceinline__ int cell_block(const Tables& T, int& blk) {
-  blk = blockIdx.x;
-  if (!T.runs) return 0;
-  const int r = uniform(find_owner(T.run_blk, T.nruns, blk));
-  blk = uniform(blk - T.run_blk[r]);
-  return r;
-}
-// Block -> (segment, block within segment) for kernels over particles.
-__device__ __forceinline__ int part_block(const Tables& T, int& blk) {
-  blk = blockIdx.x;
-  if (!T.segs) return 0;
-  const int s = uniform(find_owner(T.seg_blk, T.nsegs, blk));
-  blk = uniform(blk - T.seg_blk[s]);
-  return s;
-}
-
-// Full periodic wrap (the staged region may be wider than a small box).
-__device__ __forceinline__ int wrapm(int i, int n) {
-  const int r = i % n;
-  return r < 0 ? r + n : r;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T o = __shfl_xor(v, off, 64);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
 __global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -72,10 +23,18 @@ __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, C
   const int64_t ncell = plane * (dim == 3 ? r.nz : 1);
   const int64_t c = (int64_t)blk * 256 + threadIdx.x;
   if (c >= ncell) return false;
-  const int i = (int)(c % r.nx);
-  const int64_t rest = c / r.nx;
-  const int j = (int)(rest % r.ny);
-  const int k = (int)(rest / r.ny);
+  int i, j, k;
+  if (ncell <= 0x7fffffff) {   // 32-bit index arithmetic (no 64-bit division)
+    const uint32_t cc = (uint32_t)c, rest = cc / (uint32_t)r.nx;
+    i = (int)(cc - rest * (uint32_t)r.nx);
+    j = (int)(rest % (uint32_t)r.ny);
+    k = (int)(rest / (uint32_t)r.ny);
+  } else {
+    const int64_t rest = c / r.nx;
+    i = (int)(c - rest * r.nx);
+    j = (int)(rest % r.ny);
+    k = (int)(rest / r.ny);
+  }
   x.c = c;
   x.cim = c + (i == 0 ? r.nx - 1 : -1);
   x.cip = c + (i == r.nx - 1 ? 1 - r.nx : 1);
@@ -168,15 +127,6 @@ struct OldState {
     }
   }
 };
-
-template <typename R>
-__device__ __forceinline__ GlobalAcc<R> global_acc(const RunDesc& r) {
-  GlobalAcc<R> A;
-#pragma unroll
-  for (int c = 0; c < F_NUM; ++c) A.f[c] = gp((R*)r.f[c]);
-  A.nx = r.nx; A.ny = r.ny; A.nz = r.nz;
-  return A;
-}
 
 template <typename R, int DIM, int ORDER>
 __device__ __forceinline__ void gather_push_one(const SegDesc& s, const RunDesc& r, int64_t p,
@@ -477,6 +427,62 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
   for (int q = P_UX; q <= P_W; ++q) move_items(p, dst, (const R*)s.p[q], (R*)s.alt[q]);
 }
 
+// =======================================================================================
+// Fixed-point scale of the FP32 current accumulators.  A deposit contribution is bounded
+// by |q w| max(1, h/dt) (the Esirkepov running sums and shape products are at most 1 and
+// |v| < c), so with cmax = 2 max|q w| max(1, h/dt) and n particles in a run:
+//   |v| 2^S < 2^50 for every contribution (exact FP64 rounding to an integer), and
+//   |any accumulated sum| <= n cmax 2^S < 2^61 (no 64-bit overflow, whatever the order).
+// =======================================================================================
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_wmax(Tables T, unsigned long long* wmax) {
+  __shared__ double red[4];
+  int blk;
+  const int si = part_block(T, blk);
+  const SegDesc s = seg_of(T, si);
+  const int64_t beg = (int64_t)blk * 256 * SORT_ITEMS;
+  const gptr<const R> w = gp((const R*)s.p[P_W]);
+  double m = 0.0;
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const int64_t p = beg + it * 256 + threadIdx.x;
+    if (p < s.n) m = fmax(m, fabs((double)w[p]));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(&wmax[si], (unsigned long long)__double_as_longlong(m));   // m >= 0
+  }
+}
+
+__global__ void k_fixed_shift(Tables T, int nruns, int nsegs, const unsigned long long* wmax,
+                              int32_t* jshift) {
+  const int ri = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ri >= nruns) return;
+  const RunDesc r = run_of(T, ri);
+  double h = fmax(1.0, fmax(r.dx, r.dy) / r.dt);
+  if (r.ndim == 3) h = fmax(h, r.dz / r.dt);
+  double cmax = 0.0, n = 0.0;
+  for (int i = 0; i < nsegs; ++i) {
+    const SegDesc& s = seg_of(T, i);
+    if (s.run != ri) continue;
+    cmax = fmax(cmax, fabs(s.q) * __longlong_as_double((long long)wmax[i]));
+    n += (double)s.n;
+  }
+  cmax *= 2.0 * h;
+  int sh = 32;
+  if (cmax > 0.0 && n > 0.0) {
+    int e1, e2;
+    frexp(cmax, &e1);       // cmax < 2^e1
+    frexp(n * cmax, &e2);   // n cmax < 2^e2
+    sh = min(50 - e1, 61 - e2);
+    sh = max(-900, min(900, sh));
+  }
+  jshift[ri] = sh;
+}
+
 // After a sort inside a simulation, the device segment table points at the sorted buffers.
 __global__ void k_swap_segments(SegDesc* segs, int nsegs) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -554,333 +560,75 @@ __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* 
 }
 
 // =======================================================================================
-// Fused gather + push + deposit (unified pusher).  One workgroup per chunk; the chunk's
-// field tile (tile + halo) is staged in LDS, the current accumulates in LDS and is flushed
-// once.  Workgroups are mapped to chunks so that each XCD (every 8th workgroup) walks a
-// contiguous range of chunks: neighbouring tiles share that XCD's L2.
-// =======================================================================================
-// Region geometries compiled with constant strides: (tile x, y, z, halo).  Geometry 0 is the
-// runtime-stride kernel used for every other tiling.
-struct GeoFix { int tx, ty, tz, halo; };
-__host__ __device__ constexpr GeoFix geo_table(int g) {
-  return g == 1 ? GeoFix{16, 16, 1, 5} : g == 2 ? GeoFix{8, 8, 1, 5} : g == 3 ? GeoFix{32, 32, 1, 5}
-       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 8, 8, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
-       : GeoFix{0, 0, 0, 0};
-}
-constexpr int NUM_GEO = 7;
-
-template <int DIM, int G>
-struct GeoStrides {
-  static constexpr GeoFix f = geo_table(G);
-  using type = FixStrides<f.tx + 2 * f.halo, f.ty + 2 * f.halo, DIM == 3 ? f.tz + 2 * f.halo : 1>;
-};
-template <int DIM>
-struct GeoStrides<DIM, 0> {
-  using type = DynStrides;
-};
-
-// One staged region: the home tile of a run plus `halo` cells, in LDS.
-struct Region {
-  int r0[3];     // global origin (may be negative: periodic)
-  int rw[3];     // extent
-};
-
-template <int DIM>
-__device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, int tile) {
-  Region g;
-  const int TXs[3] = {1 << s.lx, 1 << s.ly, DIM == 3 ? (1 << s.lz) : 1};
-  int tc[3];
-  tc[0] = tile % r.ntx; tile /= r.ntx;
-  tc[1] = tile % r.nty;
-  tc[2] = tile / r.nty;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (d < DIM) { g.r0[d] = tc[d] * TXs[d] - s.halo; g.rw[d] = TXs[d] + 2 * s.halo; }
-    else { g.r0[d] = 0; g.rw[d] = 1; }
-  }
-  return g;
-}
-
-__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, int e) {
-  const int lx = e % g.rw[0];
-  const int rest = e / g.rw[0];
-  const int ly = rest % g.rw[1];
-  const int lz = rest / g.rw[1];
-  return ((int64_t)wrapm(g.r0[2] + lz, r.nz) * r.ny + wrapm(g.r0[1] + ly, r.ny)) * r.nx +
-         wrapm(g.r0[0] + lx, r.nx);
-}
-
-// Stage E and B of the region, clear its current (and charge) planes.
-template <typename R>
-__device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, int plane,
-                                             int njplanes, R* sm, double* jm) {
-  gptr<R> F[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) F[c] = gp((R*)r.f[c]);
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int64_t gi = region_global(r, g, e);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
-    for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
-  }
-}
-
-// Add the region's current (and charge) into the global arrays: one atomic per non-zero
-// entry, converted to the field precision.
-template <typename R>
-__device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, int plane,
-                                             int njplanes, const double* jm) {
-  gptr<R> F[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int64_t gi = region_global(r, g, e);
-    for (int c = 0; c < njplanes; ++c) {
-      const double v = jm[c * plane + e];
-      if (v != 0.0) atomic_add_global(F[c] + gi, R(v));
-    }
-  }
-}
-
-__device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, int seg,
-                                              int32_t p) {
-  const uint64_t mask = __ballot(want);
-  if (!mask) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  unsigned int base = 0;
-  if (lane == leader) base = atomicAdd(esc.count, (unsigned int)__popcll(mask));
-  base = __shfl(base, leader, 64);
-  if (want) {
-    const unsigned int k = base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
-    if ((int64_t)k < esc.capacity) esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
-  }
-}
-
-// The particles of one chunk against the staged region, in rounds: each thread first
-// issues the loads of BATCH particles (256 apart, so every load instruction reads 64
-// consecutive particles) and then pushes them one by one, so HBM latency is paid once per
-// round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
-constexpr int BATCH = 4;
-
-template <typename R, int DIM, int ORDER, class ST>
-__device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
-                                                const Chunk& ch, const Region& g,
-                                                const LdsAcc<R, ST>& L, int with_rho,
-                                                bool want_ke, const EscapeList& esc) {
-  const int n[3] = {r.nx, r.ny, r.nz};
-  const PushConst<R> k = push_const<R>(r, s);
-  const PartPtrs<R> q = part_ptrs<R>(s, r);
-  double ke = 0.0;
-  const int32_t span = (int32_t)blockDim.x * BATCH;
-  for (int32_t base = ch.beg; base < ch.end; base += span) {
-    PState<R> ps[BATCH];
-    int32_t pi[BATCH];
-    bool ok[BATCH];
-#pragma unroll
-    for (int b = 0; b < BATCH; ++b) {
-      pi[b] = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
-      ok[b] = pi[b] < ch.end;
-      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);
-    }
-#pragma unroll
-    for (int b = 0; b < BATCH; ++b) {
-      bool inside = ok[b] && ps[b].alive;
-      int a[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d < DIM) {
-          // local start cell; gather and deposit touch cells [a-3, a+4] per axis
-          int v = ps[b].c[d] - g.r0[d];
-          v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
-          a[d] = v;
-          inside = inside && v >= 3 && v <= g.rw[d] - 5;
-        } else {
-          a[d] = 0;
-        }
-      }
-      escape_append(esc, ok[b] && ps[b].alive && !inside, seg, pi[b]);
-      if (!inside) continue;
-      int pcell[3];
-      R po[3], pe[3], x1[3], vz1, g1;
-      push<DIM, ORDER>(L, a, ps[b], k, pcell, po, pe, x1, vz1, g1);
-      deposit<DIM, ORDER>(L, pcell, po, pe, ps[b].w, vz1, k, with_rho != 0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps[b].c[d], ps[b].o[d], x1[d], n[d]);
-      store_particle<R, DIM>(q, pi[b], ps[b]);
-      if (want_ke) {   // diagnostic steps only
-        const double u2 = (double)ps[b].u[0] * ps[b].u[0] + (double)ps[b].u[1] * ps[b].u[1] +
-                          (double)ps[b].u[2] * ps[b].u[2];
-        ke += (double)ps[b].w * u2 / (1.0 + (double)g1);
-      }
-    }
-  }
-  return ke * s.m;
-}
-
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  T t = T(0);
-  if (threadIdx.x == 0)
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-  return t;
-}
-
-// Fused gather + push + deposit over the chunk table, persistent: the grid is a multiple of
-// 8 and XCD x (workgroups x, x+8, ...) owns the contiguous chunk range [x*per, (x+1)*per),
-// split into equal contiguous slices per workgroup.  Consecutive chunks of one tile (and of
-// the other species of the same box, which follow in the table) reuse the staged region;
-// the region is flushed when the tile changes.
-template <typename R, int DIM, int G>
-__global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
-                                               const int32_t* nchunks, int with_rho,
-                                               double* kinetic, int ke_to_diag,
-                                               EscapeList esc) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[4];
-  R* sm = (R*)smem_raw;
-  const int nch = uniform(*nchunks);
-  const int nb8 = gridDim.x >> 3;
-  const int per = (nch + 7) >> 3;
-  const int q = (per + nb8 - 1) / nb8;
-  const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-  const int lo = xcd * per + j * q;
-  const int hi = min(min(lo + q, (xcd + 1) * per), nch);
-  if (lo >= hi) return;
-
-  using ST = typename GeoStrides<DIM, G>::type;
-  const SegDesc& s0 = seg_of(T, uniform(chunks[lo].seg));
-  ST st;
-  if constexpr (G == 0) {
-    const int rw = (1 << s0.lx) + 2 * s0.halo, rh = (1 << s0.ly) + 2 * s0.halo;
-    const int rd = DIM == 3 ? (1 << s0.lz) + 2 * s0.halo : 1;
-    st.sy_ = rw;
-    st.sz_ = rw * rh;
-    st.plane_ = rw * rh * rd;
-  }
-  const int plane = st.plane();
-  const int njplanes = 3 + (with_rho ? 2 : 0);
-  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
-  LdsAcc<R, ST> L;
-  L.fbase = sm;
-  L.jbase = jm;
-  L.st = st;
-
-  int cur_run = -1, cur_tile = -1;
-  Region g;
-  double ke = 0.0;
-  for (int c = lo; c < hi; ++c) {
-    Chunk ch = chunks[c];
-    ch.seg = uniform(ch.seg);
-    ch.tile = uniform(ch.tile);
-    ch.beg = uniform(ch.beg);
-    ch.end = uniform(ch.end);
-    const SegDesc s = seg_of(T, ch.seg);
-    if (s.run != cur_run || ch.tile != cur_tile) {
-      if (cur_run >= 0) {
-        const RunDesc& rp = run_of(T, cur_run);
-        __syncthreads();
-        flush_region<R>(rp, g, plane, njplanes, jm);
-        if (kinetic || ke_to_diag) {
-          const double t = block_sum(ke, red);
-          if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rp.diag + DIAG_UKIN : kinetic, t);
-          ke = 0.0;
-        }
-      }
-      const RunDesc rn = run_of(T, s.run);
-      g = region_of<DIM>(rn, s, ch.tile);
-      __syncthreads();
-      stage_region<R>(rn, g, plane, njplanes, sm, jm);
-      __syncthreads();
-      cur_run = s.run;
-      cur_tile = ch.tile;
-    }
-    const RunDesc r = run_of(T, s.run);
-    const bool want_ke = kinetic || ke_to_diag;
-    ke += s.order == 1 ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc)
-                       : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc);
-  }
-  const RunDesc& rl = run_of(T, cur_run);
-  __syncthreads();
-  flush_region<R>(rl, g, plane, njplanes, jm);
-  if (kinetic || ke_to_diag) {
-    const double t = block_sum(ke, red);
-    if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rl.diag + DIAG_UKIN : kinetic, t);
-  }
-}
-
-// Escaped particles: the same push and deposit through global memory.  The last workgroup
-// to finish clears the list for the next step.
-template <typename R, int DIM, int ORDER>
-__device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s, int64_t p,
-                                             int with_rho) {
-  PState<R> ps;
-  load_particle<R, DIM>(s, r, p, ps);
-  if (!ps.alive) return 0.0;
-  const GlobalAcc<R> G = global_acc<R>(r);
-  const PushConst<R> k = push_const<R>(r, s);
-  int pcell[3];
-  R po[3], pe[3], x1[3], vz1, g1;
-  push<DIM, ORDER>(G, ps.c, ps, k, pcell, po, pe, x1, vz1, g1);
-  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
-  const int n[3] = {r.nx, r.ny, r.nz};
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
-  store_particle<R, DIM>(s, r, p, ps);
-  const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] + (double)ps.u[2] * ps.u[2];
-  return (double)ps.w * s.m * u2 / (1.0 + (double)g1);
-}
-
-template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_escape(Tables T, int with_rho, double* kinetic,
-                                                int ke_to_diag, EscapeList esc) {
-  const unsigned int cnt = min((int64_t)esc.count[0], esc.capacity);
-  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += gridDim.x * blockDim.x) {
-    const unsigned long long v = esc.items[i];
-    const int seg = (int)(v >> 32);
-    const int64_t p = (int64_t)(v & 0xffffffffull);
-    const SegDesc& s = seg_of(T, seg);
-    const RunDesc& r = run_of(T, s.run);
-    const double ke = s.order == 1 ? escape_one<R, DIM, 1>(r, s, p, with_rho)
-                                   : escape_one<R, DIM, 2>(r, s, p, with_rho);
-    if (kinetic || ke_to_diag) atomic_add_global(ke_to_diag ? r.diag + DIAG_UKIN : kinetic, ke);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int done = atomicAdd(esc.count + 1, 1u);
-    if (done == gridDim.x - 1) {
-      atomicAdd(esc.total, (unsigned long long)esc.count[0]);
-      atomicExch(esc.count, 0u);
-      atomicExch(esc.count + 1, 0u);
-    }
-  }
-}
-
-// =======================================================================================
 // FP64 diagnostics: field energy, continuity and Gauss residuals (max over cells).
 // =======================================================================================
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
   atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
 }
 
+// Each workgroup walks REDUCE_SPAN consecutive 256-cell blocks of the cell-block space (all
+// runs end to end) and flushes its partial sums once per run it touched: one set of global
+// atomics per workgroup rather than per 256 cells.
+constexpr int REDUCE_SPAN = 16;
+
+template <int DIM>
+__device__ __forceinline__ void reduce_flush(const RunDesc& r, double* out, int with_rho,
+                                             double en, double res, double rm, double ga,
+                                             double (*red)[4]) {
+  en = wave_sum(en);
+  res = wave_max(res);
+  rm = wave_max(rm);
+  ga = wave_max(ga);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();   // red[] may still be read by the previous flush
+  if ((threadIdx.x & 63) == 0) { red[0][w] = en; red[1][w] = res; red[2][w] = rm; red[3][w] = ga; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0, c = 0, d = 0;
+    for (int i = 0; i < 4; ++i) {
+      a += red[0][i];
+      b = fmax(b, red[1][i]);
+      c = fmax(c, red[2][i]);
+      d = fmax(d, red[3][i]);
+    }
+    double* o = out ? out : r.diag;
+    const double dV = r.dx * r.dy * (DIM == 3 ? r.dz : 1.0);
+    atomic_add_global(o + (out ? 0 : DIAG_UFIELD), 0.5 * a * dV);
+    if (with_rho) {
+      atomic_max_nonneg(o + (out ? 1 : DIAG_RES), b);
+      atomic_max_nonneg(o + (out ? 2 : DIAG_RHOMAX), c);
+      atomic_max_nonneg(o + (out ? 3 : DIAG_GAUSS), d);
+    }
+  }
+}
+
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int with_rho, double* out) {
-  int blk;
-  const int ri = cell_block(T, blk);
-  const RunDesc& r = run_of(T, ri);
-  double* o = out ? out : r.diag;
-  CellIdx x;
+__global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int ncellblk, int with_rho,
+                                                       double* out) {
+  __shared__ double red[4][4];
   double en = 0.0, res = 0.0, rm = 0.0, ga = 0.0;
-  if (cell_index(r, blk, DIM, x)) {
+  int cur = -1;
+  RunDesc r;
+  for (int k = 0; k < REDUCE_SPAN; ++k) {
+    const int vb = blockIdx.x * REDUCE_SPAN + k;
+    if (vb >= ncellblk) break;
+    int blk = vb, ri = 0;
+    if (T.runs) {
+      ri = uniform(find_owner(T.run_blk, T.nruns, vb));
+      blk = uniform(vb - T.run_blk[ri]);
+    }
+    if (ri != cur) {
+      if (cur >= 0) reduce_flush<DIM>(r, out, with_rho, en, res, rm, ga, red);
+      en = res = rm = ga = 0.0;
+      cur = ri;
+      r = run_of(T, ri);
+    }
+    CellIdx x;
+    if (!cell_index(r, blk, DIM, x)) continue;
     gptr<R> f[F_NUM];
 #pragma unroll
     for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
       const double v = (double)f[c][x.c];
       en += v * v;
@@ -895,35 +643,12 @@ __global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int with_rho, d
         divj += ((double)f[F_JZ][x.c] - (double)f[F_JZ][x.ckm]) / r.dz;
         dive += ((double)f[F_EZ][x.c] - (double)f[F_EZ][x.ckm]) / r.dz;
       }
-      res = fabs(r1 - r0 + r.dt * divj);
-      rm = fabs(r1);
-      ga = fabs(dive - 0.5 * (r0 + r1) - r.rho_bg);
+      res = fmax(res, fabs(r1 - r0 + r.dt * divj));
+      rm = fmax(rm, fabs(r1));
+      ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
     }
   }
-  __shared__ double red[4][4];
-  en = wave_sum(en);
-  res = wave_max(res);
-  rm = wave_max(rm);
-  ga = wave_max(ga);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { red[0][w] = en; red[1][w] = res; red[2][w] = rm; red[3][w] = ga; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0, b = 0, c = 0, d = 0;
-    for (int i = 0; i < 4; ++i) {
-      a += red[0][i];
-      b = fmax(b, red[1][i]);
-      c = fmax(c, red[2][i]);
-      d = fmax(d, red[3][i]);
-    }
-    const double dV = r.dx * r.dy * (DIM == 3 ? r.dz : 1.0);
-    atomic_add_global(o + (out ? 0 : DIAG_UFIELD), 0.5 * a * dV);
-    if (with_rho) {
-      atomic_max_nonneg(o + (out ? 1 : DIAG_RES), b);
-      atomic_max_nonneg(o + (out ? 2 : DIAG_RHOMAX), c);
-      atomic_max_nonneg(o + (out ? 3 : DIAG_GAUSS), d);
-    }
-  }
+  if (cur >= 0) reduce_flush<DIM>(r, out, with_rho, en, res, rm, ga, red);
 }
 
 __global__ void k_zero_doubles(double* p, int n) {
@@ -1023,16 +748,6 @@ void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, doub
   }
 }
 
-#define LPIC_PD(prec, dim, call)                                  \
-  do {                                                            \
-    if (prec == 0) {                                              \
-      if (dim == 2) { using R = float; constexpr int D = 2; call; } \
-      else { using R = float; constexpr int D = 3; call; }        \
-    } else {                                                      \
-      if (dim == 2) { using R = double; constexpr int D = 2; call; } \
-      else { using R = double; constexpr int D = 3; call; }       \
-    }                                                             \
-  } while (0)
 
 void launch_gather_push(const Tables& T, int prec, int dim, int nblocks, void* old,
                         hipStream_t st) {
@@ -1058,6 +773,12 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
                                                                      spread)));
 }
 
+void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
+                        unsigned long long* wmax, int32_t* jshift, hipStream_t st) {
+  if (nblocks > 0) LPIC_PD(prec, dim, (k_wmax<R, D><<<nblocks, 256, 0, st>>>(T, wmax)));
+  k_fixed_shift<<<(nruns + 63) / 64, 64, 0, st>>>(T, nruns, nsegs, wmax, jshift);
+}
+
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
   k_swap_segments<<<(nsegs + 63) / 64, 64, 0, st>>>(segs, nsegs);
 }
@@ -1065,85 +786,6 @@ void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st) {
   k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nbins, chunk, out, nchunks);
-}
-
-int fused_geometry(int dim, int tx, int ty, int tz, int halo) {
-  for (int g = 1; g < NUM_GEO; ++g) {
-    const GeoFix f = geo_table(g);
-    if (dim == 2 && f.tz == 1 && f.tx == tx && f.ty == ty && f.halo == halo) return g;
-    if (dim == 3 && f.tz > 1 && f.tx == tx && f.ty == ty && f.tz == tz && f.halo == halo) return g;
-  }
-  return 0;
-}
-
-template <typename R, int D, int G>
-static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
-                           const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
-                           const EscapeList& esc, hipStream_t st) {
-  k_fused<R, D, G><<<nblocks, 256, smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
-                                               ke_to_diag, esc);
-}
-
-template <typename R, int D>
-static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
-                           const Chunk* chunks, const int32_t* nchunks, int with_rho,
-                           double* kinetic, int ke_to_diag, const EscapeList& esc,
-                           hipStream_t st) {
-#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, st)
-  if constexpr (D == 2) {
-    switch (geo) {
-      case 1: LPIC_GEO(1); return;
-      case 2: LPIC_GEO(2); return;
-      case 3: LPIC_GEO(3); return;
-      case 4: LPIC_GEO(4); return;
-      default: LPIC_GEO(0); return;
-    }
-  } else {
-    switch (geo) {
-      case 5: LPIC_GEO(5); return;
-      case 6: LPIC_GEO(6); return;
-      default: LPIC_GEO(0); return;
-    }
-  }
-#undef LPIC_GEO
-}
-
-void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
-                  const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
-                  int ke_to_diag, const EscapeList& esc, hipStream_t st) {
-  LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, chunks, nchunks, with_rho,
-                                           kinetic, ke_to_diag, esc, st)));
-  LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(T, with_rho, kinetic,
-                                                                    ke_to_diag, esc)));
-}
-
-template <typename R, int D, int G>
-static hipError_t set_smem(size_t smem, int* blocks_per_cu) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_fused<R, D, G>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256, smem);
-}
-
-hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu) {
-  hipError_t e = hipSuccess;
-  int* b = blocks_per_cu;
-  if (dim == 2) {
-    switch (geo) {
-      case 1: e = prec == 0 ? set_smem<float, 2, 1>(smem, b) : set_smem<double, 2, 1>(smem, b); break;
-      case 2: e = prec == 0 ? set_smem<float, 2, 2>(smem, b) : set_smem<double, 2, 2>(smem, b); break;
-      case 3: e = prec == 0 ? set_smem<float, 2, 3>(smem, b) : set_smem<double, 2, 3>(smem, b); break;
-      case 4: e = prec == 0 ? set_smem<float, 2, 4>(smem, b) : set_smem<double, 2, 4>(smem, b); break;
-      default: e = prec == 0 ? set_smem<float, 2, 0>(smem, b) : set_smem<double, 2, 0>(smem, b); break;
-    }
-  } else {
-    switch (geo) {
-      case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, b) : set_smem<double, 3, 5>(smem, b); break;
-      case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, b) : set_smem<double, 3, 6>(smem, b); break;
-      default: e = prec == 0 ? set_smem<float, 3, 0>(smem, b) : set_smem<double, 3, 0>(smem, b); break;
-    }
-  }
-  return e;
 }
 
 template <typename R, int DIM>
@@ -1179,7 +821,8 @@ void launch_kinetic(const Tables& T, int prec, int dim, int nblocks, double* out
 
 void launch_reduce_fields(const Tables& T, int prec, int dim, int nblocks, int with_rho,
                           double* out, hipStream_t st) {
-  LPIC_PD(prec, dim, (k_reduce_fields<R, D><<<nblocks, 256, 0, st>>>(T, with_rho, out)));
+  const int grid = (nblocks + REDUCE_SPAN - 1) / REDUCE_SPAN;
+  LPIC_PD(prec, dim, (k_reduce_fields<R, D><<<grid, 256, 0, st>>>(T, nblocks, with_rho, out)));
 }
 
 void launch_zero_doubles(double* p, int n, hipStream_t st) {
@@ -1200,10 +843,5 @@ void launch_store_positions(const Tables& T, int prec, int dim, int nblocks, dou
   LPIC_PD(prec, dim, (k_store_positions<R, D><<<nblocks, 256, 0, st>>>(T, x, y, z)));
 }
 
-size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
-  const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
-  // six field planes in the kernel precision (padded to 8 bytes), then FP64 current planes
-  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * (3 + (with_rho ? 2 : 0)) * 8;
-}
 
 }  // namespace lpic

@@ -126,22 +126,29 @@ def _fold(a, L):
 
 
 def gaussian_pulse_fields(nx, ny, dx, dy, a0, x_lo, x_hi, waist, y_centre):
-    """Linearly polarised (E along y) pulse moving in +x, laid out on the Yee stagger:
-    Ey(x,y) = a0 sin^2(pi (x - x_lo)/(x_hi - x_lo)) exp(-((y - yc)/waist)^2) sin(x), Bz = Ey
-    evaluated at Bz's own location; zero outside [x_lo, x_hi)."""
-    def profile(xs, ys):
+    """Linearly polarised (E mostly along y) pulse moving in +x, laid out on the Yee stagger
+    with a discretely divergence-free E.  With the profile
+        f(x, y) = a0 sin^2(pi (x - x_lo)/(x_hi - x_lo)) exp(-((y - yc)/waist)^2)
+    (zero outside [x_lo, x_hi)), a stream function psi = f cos(x) sits at the Bz points
+    (i+1/2, j+1/2); Ey = -d psi/dx and Ex = d psi/dy are its one-cell differences, so the
+    discrete div E vanishes at every node and Ey ~ f sin(x).  Bz = f sin(x) at its own
+    points (B has only a z component in this 2D layout, so div B = 0 as well)."""
+    def env(xs, ys):
         inside = (xs >= x_lo) & (xs < x_hi)
-        env = np.where(inside, np.sin(math.pi * (xs - x_lo) / (x_hi - x_lo)) ** 2, 0.0)
-        return a0 * env * np.exp(-((ys - y_centre) / waist) ** 2) * np.sin(xs)
+        e = np.where(inside, np.sin(math.pi * (xs - x_lo) / (x_hi - x_lo)) ** 2, 0.0)
+        return a0 * e * np.exp(-((ys - y_centre) / waist) ** 2)
 
     i = np.arange(nx)
     j = np.arange(ny)
-    # Ey at (i, j+1/2), Bz at (i+1/2, j+1/2)
-    Y, X = np.meshgrid((j + 0.5) * dy, i * dx, indexing="ij")
-    ey = profile(X, Y)
-    Y, X = np.meshgrid((j + 0.5) * dy, (i + 0.5) * dx, indexing="ij")
-    bz = profile(X, Y)
-    return {"ey": ey.reshape(-1), "bz": bz.reshape(-1)}
+    Y, X = np.meshgrid((j + 0.5) * dy, (i + 0.5) * dx, indexing="ij")   # Bz points [j, i]
+    f = env(X, Y)
+    psi = f * np.cos(X)
+    bz = f * np.sin(X)
+    # Ey at (i, j+1/2): -(psi[i+1/2] - psi[i-1/2]) / dx;  Ex at (i+1/2, j): (psi[j+1/2] -
+    # psi[j-1/2]) / dy, with periodic neighbours
+    ey = -(psi - np.roll(psi, 1, axis=1)) / dx
+    ex = (psi - np.roll(psi, 1, axis=0)) / dy
+    return {"ex": ex.reshape(-1), "ey": ey.reshape(-1), "bz": bz.reshape(-1)}
 
 
 # ----------------------------------------------------------------------------------------
@@ -166,16 +173,18 @@ def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), densit
                   pulse_cells=None, waist_lambda=6.25, name="laser_slab_2d") -> Workload:
     """2D3V hydrogen slab (electrons + protons, `ppc` each) of `density` n_c in cells
     [slab[0], slab[1]) over the whole y extent, with a Gaussian pulse of peak a0 in the
-    vacuum in front of it (x in [0, pulse_cells) cells, sin^2 envelope over that span)."""
+    vacuum in front of it (x in [0, pulse_cells) cells, sin^2 envelope over that span).
+    Electrons sit uniformly at random in their cells, each proton on an electron, so the
+    plasma starts neutral node by node; momenta are drawn independently per species."""
     rng = np.random.default_rng(seed)
     dx = LAMBDA / cells_per_lambda
     cx, cy = _cell_lists_2d(slab[0], slab[1], 0, ny)
     xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
     xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
     e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
-    xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
-    xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
-    p = _thermal_species(rng, "proton", +1.0, M_PROTON, order, xs, ys, None, T, density, ppc)
+    # each proton starts on an electron: zero net charge at every node at t = 0
+    p = _thermal_species(rng, "proton", +1.0, M_PROTON, order, xs.copy(), ys.copy(), None, T,
+                         density, ppc)
     if pulse_cells is None:
         pulse_cells = min(slab[0], nx)
     flds = {}
