@@ -181,6 +181,7 @@ __device__ __forceinline__ void weights_half(R o, int c, int& base, R w[ORDER + 
 // ---------------------------------------------------------------------------------------
 template <typename R>
 struct GlobalAcc {
+  static constexpr bool kPaired = false;
   gptr<R> f[F_NUM];
   int nx, ny, nz;
   __device__ __forceinline__ int xo(int x) const { return wrapi(x, nx); }
@@ -213,9 +214,13 @@ struct DynStrides {
 // charge) planes accumulated in FP64 whatever that precision: FP64 LDS atomic adds run at
 // full rate on gfx950, FP32 ones do not, and FP64 sums also keep the per-tile totals exact to
 // FP32 before the flush.
-template <typename R, class S>
+// LDS accessor of a staged region.  PAIR (2D): components that share a staggering are
+// interleaved so that one 8-byte (FP32) / 16-byte (FP64) read fetches both at a node:
+// planes [ (Ex,By) pairs | (Ey,Bx) pairs | Ez | Bz ]; otherwise planes Ex Ey Ez Bx By Bz.
+template <typename R, class S, bool PAIR = false>
 struct LdsAcc {
-  R* fbase;       // planes Ex Ey Ez Bx By Bz
+  static constexpr bool kPaired = PAIR;
+  R* fbase;       // the six field components, laid out as above
   double* jbase;  // planes Jx Jy Jz, then rho0 rho1 (FP32 path: int64 fixed point)
   S st;
   double jscale;  // FP32 path: 2^S, the fixed-point scale of the current accumulators
@@ -224,6 +229,14 @@ struct LdsAcc {
   __device__ __forceinline__ int zo(int z) const { return z * st.sz(); }
   __device__ __forceinline__ R get(int comp, int off) const {
     return fbase[comp * st.plane() + off];
+  }
+  // PAIR layout: pair 0 = (Ex, By), pair 1 = (Ey, Bx); single 4 = Ez, 5 = Bz.
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  __device__ __forceinline__ R2 get2(int pair, int off) const {
+    return *(const R2*)(fbase + 2 * (pair * st.plane() + off));
+  }
+  __device__ __forceinline__ R get1(int plane_idx, int off) const {
+    return fbase[plane_idx * st.plane() + off];
   }
   // Exact zeros are skipped: a particle that keeps its nearest node leaves a zero row and
   // column in its window, and a lane masked off costs the LDS nothing.
@@ -285,6 +298,40 @@ __device__ __forceinline__ R interp3(const Acc& A, int comp, const int* xo, cons
   return s;
 }
 
+// Two components with the same staggering from the paired layout: one read per node.
+template <int N, typename R, class Acc>
+__device__ __forceinline__ void interp2_pair(const Acc& A, int pair, const int* xo, const R* wx,
+                                             const int* yo, const R* wy, R& s0, R& s1) {
+  s0 = R(0);
+  s1 = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    R r0 = R(0), r1 = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const auto v = A.get2(pair, yo[b] + xo[a]);
+      r0 += wx[a] * v.x;
+      r1 += wx[a] * v.y;
+    }
+    s0 += wy[b] * r0;
+    s1 += wy[b] * r1;
+  }
+}
+
+template <int N, typename R, class Acc>
+__device__ __forceinline__ R interp2_single(const Acc& A, int plane_idx, const int* xo,
+                                            const R* wx, const int* yo, const R* wy) {
+  R s = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    R r = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) r += wx[a] * A.get1(plane_idx, yo[b] + xo[a]);
+    s += wy[b] * r;
+  }
+  return s;
+}
+
 template <int ORDER, typename R, class Acc>
 __device__ __forceinline__ void stencil_axis(const Acc& A, int axis, int c, R o, int* oi,
                                              R* wi, int* oh, R* wh) {
@@ -307,7 +354,12 @@ __device__ __forceinline__ void gather(const Acc& A, const int* c, const R* o, R
   R wxi[N], wxh[N], wyi[N], wyh[N];
   stencil_axis<ORDER>(A, 0, c[0], o[0], xi, wxi, xh, wxh);
   stencil_axis<ORDER>(A, 1, c[1], o[1], yi, wyi, yh, wyh);
-  if constexpr (DIM == 2) {
+  if constexpr (DIM == 2 && Acc::kPaired) {
+    interp2_pair<N>(A, 0, xh, wxh, yi, wyi, E[0], B[1]);   // (h,i): Ex, By
+    interp2_pair<N>(A, 1, xi, wxi, yh, wyh, E[1], B[0]);   // (i,h): Ey, Bx
+    E[2] = interp2_single<N>(A, 4, xi, wxi, yi, wyi);
+    B[2] = interp2_single<N>(A, 5, xh, wxh, yh, wyh);
+  } else if constexpr (DIM == 2) {
     E[0] = interp2<N>(A, F_EX, xh, wxh, yi, wyi);
     E[1] = interp2<N>(A, F_EY, xi, wxi, yh, wyh);
     E[2] = interp2<N>(A, F_EZ, xi, wxi, yi, wyi);

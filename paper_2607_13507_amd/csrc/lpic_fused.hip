@@ -67,14 +67,23 @@ __device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region&
 // Stage E and B of the region, clear its current (and charge) planes.
 template <typename R>
 __device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, int plane,
-                                             int njplanes, R* sm, double* jm) {
+                                             int njplanes, R* sm, double* jm, bool paired) {
   gptr<R> F[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = gp((R*)r.f[c]);
   for (int e = threadIdx.x; e < plane; e += blockDim.x) {
     const int64_t gi = region_global(r, g, e);
+    if (paired) {   // 2D: (Ex,By) pairs, (Ey,Bx) pairs, Ez, Bz
+      sm[2 * e] = F[F_EX][gi];
+      sm[2 * e + 1] = F[F_BY][gi];
+      sm[2 * (plane + e)] = F[F_EY][gi];
+      sm[2 * (plane + e) + 1] = F[F_BX][gi];
+      sm[4 * plane + e] = F[F_EZ][gi];
+      sm[5 * plane + e] = F[F_BZ][gi];
+    } else {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
+      for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
+    }
     for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
   }
 }
@@ -119,10 +128,10 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
 constexpr int BATCH = 4;
 
-template <typename R, int DIM, int ORDER, class ST>
+template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
                                                 const Chunk& ch, const Region& g,
-                                                const LdsAcc<R, ST>& L, int with_rho,
+                                                const LA& L, int with_rho,
                                                 bool want_ke, const EscapeList& esc) {
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
   const int plane = st.plane();
   const int njplanes = 3 + (with_rho ? 2 : 0);
   double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
-  LdsAcc<R, ST> L;
+  LdsAcc<R, ST, DIM == 2> L;
   L.fbase = sm;
   L.jbase = jm;
   L.st = st;
@@ -256,7 +265,7 @@ __global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
       const RunDesc rn = run_of(T, s.run);
       g = region_of<DIM>(rn, s, ch.tile);
       __syncthreads();
-      stage_region<R>(rn, g, plane, njplanes, sm, jm);
+      stage_region<R>(rn, g, plane, njplanes, sm, jm, DIM == 2);
       __syncthreads();
       cur_run = s.run;
       cur_tile = ch.tile;

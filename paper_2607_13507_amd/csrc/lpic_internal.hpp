@@ -42,7 +42,7 @@ struct EscapeList {
   unsigned long long* total;   // cumulative number of escapes
   int64_t capacity;
 };
-constexpr int ESCAPE_BLOCKS = 512;
+constexpr int ESCAPE_BLOCKS = 128;
 
 // geometry: 0 = runtime strides, else a compiled (tile, halo) shape (fused_geometry()).
 int fused_geometry(int dim, int tx, int ty, int tz, int halo);

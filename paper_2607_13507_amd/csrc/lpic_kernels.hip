@@ -289,19 +289,58 @@ __device__ __forceinline__ void block_keys(const SegDesc& s, const RunDesc& r, i
   }
 }
 
+// Per-workgroup key cache in LDS: the 2048 particles of a workgroup come from a handful of
+// tiles (their home tile and its neighbours), so the counts of a workgroup are summed in LDS
+// and reach the global bins with one atomic per distinct key.  A key whose cache slot is
+// taken by another key falls back to global atomics.
+constexpr int SORT_SLOTS = 256;
+
+struct SortCache {
+  int32_t tag[SORT_SLOTS];
+  int32_t cnt[SORT_SLOTS];
+  int32_t base[SORT_SLOTS];
+};
+
+__device__ __forceinline__ void sort_cache_clear(SortCache& C) {
+  for (int i = threadIdx.x; i < SORT_SLOTS; i += blockDim.x) {
+    C.tag[i] = -1;
+    C.cnt[i] = 0;
+  }
+}
+
+// Claims the cache slot of `key`; true if the slot holds this key.
+__device__ __forceinline__ bool sort_cache_claim(SortCache& C, int key) {
+  const int slot = key & (SORT_SLOTS - 1);
+  int t = C.tag[slot];
+  if (t == -1) {
+    t = atomicCAS(&C.tag[slot], -1, key);
+    if (t == -1) t = key;
+  }
+  return t == key;
+}
+
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_sort_count(Tables T, int32_t* counts) {
+  __shared__ SortCache C;
   int blk;
   const SegDesc s = seg_of(T, part_block(T, blk));
   const RunDesc r = run_of(T, s.run);
+  sort_cache_clear(C);
   int key[SORT_ITEMS];
   int64_t p[SORT_ITEMS];
   block_keys<R, DIM>(s, r, blk, key, p);
+  __syncthreads();
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     int len, head;
-    if (wave_runs(key[it], key[it] >= 0, len, head)) atomicAdd(&counts[key[it]], len);
+    if (wave_runs(key[it], key[it] >= 0, len, head)) {
+      if (sort_cache_claim(C, key[it])) atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len);
+      else atomicAdd(&counts[key[it]], len);
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SORT_SLOTS; i += blockDim.x)
+    if (C.tag[i] >= 0 && C.cnt[i] > 0) atomicAdd(&counts[C.tag[i]], C.cnt[i]);
 }
 
 // Spread placement inside a bin (on request): the particle of rank r (arrival order,
@@ -389,29 +428,48 @@ template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
                                                       const int32_t* offsets,
                                                       const int32_t* mult, int spread) {
+  __shared__ SortCache C;
   int blk;
   const SegDesc s = seg_of(T, part_block(T, blk));
   const RunDesc r = run_of(T, s.run);
+  sort_cache_clear(C);
   int key[SORT_ITEMS];
   int64_t p[SORT_ITEMS];
   block_keys<R, DIM>(s, r, blk, key, p);
-  // destinations: one cursor atomic per run of equal keys in a wave
-  int64_t dst[SORT_ITEMS];
+  __syncthreads();
+  // ranks: inside the workgroup for cached keys, straight from the bin cursor otherwise
+  int32_t rank[SORT_ITEMS];
+  bool cached[SORT_ITEMS];
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     int len, head;
-    int base = 0;
-    if (wave_runs(key[it], key[it] >= 0, len, head)) base = atomicAdd(&cursor[key[it]], len);
+    int base = 0, hit = 0;
+    if (wave_runs(key[it], key[it] >= 0, len, head)) {
+      hit = sort_cache_claim(C, key[it]);
+      base = hit ? atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len)
+                 : atomicAdd(&cursor[key[it]], len);
+    }
     base = __shfl(base, head, 64);
+    hit = __shfl(hit, head, 64);
+    rank[it] = base + (__lane_id() - head);
+    cached[it] = hit != 0;
+  }
+  __syncthreads();
+  // one cursor reservation per cached key
+  for (int i = threadIdx.x; i < SORT_SLOTS; i += blockDim.x)
+    if (C.tag[i] >= 0 && C.cnt[i] > 0) C.base[i] = atomicAdd(&cursor[C.tag[i]], C.cnt[i]);
+  __syncthreads();
+  int64_t dst[SORT_ITEMS];
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
     dst[it] = -1;
-    if (key[it] >= 0) {
-      const int64_t slot = (int64_t)base + (__lane_id() - head);
-      if (spread) {
-        const int32_t b0 = offsets[key[it]], nb = offsets[key[it] + 1] - b0;
-        dst[it] = b0 + ((slot - b0) * mult[key[it]]) % nb - s.pbase;
-      } else {
-        dst[it] = slot - s.pbase;
-      }
+    if (key[it] < 0) continue;
+    const int64_t slot = (cached[it] ? (int64_t)C.base[key[it] & (SORT_SLOTS - 1)] : 0) + rank[it];
+    if (spread) {
+      const int32_t b0 = offsets[key[it]], nb = offsets[key[it] + 1] - b0;
+      dst[it] = b0 + ((slot - b0) * mult[key[it]]) % nb - s.pbase;
+    } else {
+      dst[it] = slot - s.pbase;
     }
   }
   // move the particle arrays, one array at a time for all items (loads issued together)
@@ -434,26 +492,51 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
 //   |v| 2^S < 2^50 for every contribution (exact FP64 rounding to an integer), and
 //   |any accumulated sum| <= n cmax 2^S < 2^61 (no 64-bit overflow, whatever the order).
 // =======================================================================================
+constexpr int WMAX_SPAN = 16;   // sort-sized particle blocks per workgroup
+
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_wmax(Tables T, unsigned long long* wmax) {
+__global__ __launch_bounds__(256) void k_wmax(Tables T, int nvblk, unsigned long long* wmax) {
   __shared__ double red[4];
-  int blk;
-  const int si = part_block(T, blk);
-  const SegDesc s = seg_of(T, si);
-  const int64_t beg = (int64_t)blk * 256 * SORT_ITEMS;
-  const gptr<const R> w = gp((const R*)s.p[P_W]);
   double m = 0.0;
+  int cur = -1;
+  for (int k = 0; k < WMAX_SPAN; ++k) {
+    const int vb = blockIdx.x * WMAX_SPAN + k;
+    if (vb >= nvblk) break;
+    int blk = vb, si = 0;
+    if (T.segs) {
+      si = uniform(find_owner(T.seg_blk, T.nsegs, vb));
+      blk = uniform(vb - T.seg_blk[si]);
+    }
+    if (si != cur) {
+      if (cur >= 0) {
+        m = wave_max(m);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0)
+          atomicMax(&wmax[cur], (unsigned long long)__double_as_longlong(
+                                    fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+      }
+      m = 0.0;
+      cur = si;
+    }
+    const SegDesc& s = seg_of(T, si);
+    const gptr<const R> w = gp((const R*)s.p[P_W]);
+    const int64_t beg = (int64_t)blk * 256 * SORT_ITEMS;
 #pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
-    const int64_t p = beg + it * 256 + threadIdx.x;
-    if (p < s.n) m = fmax(m, fabs((double)w[p]));
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+      const int64_t p = beg + it * 256 + threadIdx.x;
+      if (p < s.n) m = fmax(m, fabs((double)w[p]));
+    }
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    atomicMax(&wmax[si], (unsigned long long)__double_as_longlong(m));   // m >= 0
+  if (cur >= 0) {
+    m = wave_max(m);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      atomicMax(&wmax[cur], (unsigned long long)__double_as_longlong(
+                                fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));   // >= 0
   }
 }
 
@@ -775,7 +858,10 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
 
 void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
                         unsigned long long* wmax, int32_t* jshift, hipStream_t st) {
-  if (nblocks > 0) LPIC_PD(prec, dim, (k_wmax<R, D><<<nblocks, 256, 0, st>>>(T, wmax)));
+  if (nblocks > 0) {
+    const int grid = (nblocks + WMAX_SPAN - 1) / WMAX_SPAN;
+    LPIC_PD(prec, dim, (k_wmax<R, D><<<grid, 256, 0, st>>>(T, nblocks, wmax)));
+  }
   k_fixed_shift<<<(nruns + 63) / 64, 64, 0, st>>>(T, nruns, nsegs, wmax, jshift);
 }
 
