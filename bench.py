@@ -145,6 +145,16 @@ def copy_calibration(mib):
                 launches=3)
 
 
+def host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(wl):
     """The FP64 oracle (single thread) on one full step of the same workload."""
     import oracle
@@ -154,7 +164,8 @@ def cpu_baseline(wl):
     dt = time.perf_counter() - t0
     return dict(value=wl.nparticles / dt, unit="particle-pushes/s", cores=1, kind="oracle",
                 sample=f"one full step (all {wl.nparticles} particles, {wl.nx}x{wl.ny} grid) "
-                       f"of the benchmark workload, FP64, single thread, {dt:.1f} s")
+                       f"of the benchmark workload, FP64, single thread on {host_cpu()} "
+                       f"({os.cpu_count()} logical CPUs visible), {dt:.1f} s")
 
 
 def main():

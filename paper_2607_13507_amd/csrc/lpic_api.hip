@@ -420,7 +420,7 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
   const int geo = fused_geometry(grid->ndim, t.tx, t.ty, t.tz, t.halo);
   int bpc = 1;
-  HIPCHK(prepare_fused(prec, grid->ndim, geo, smem, &bpc));
+  HIPCHK(prepare_fused(prec, grid->ndim, geo, smem, smem, &bpc));
   launch_fused(T, prec, grid->ndim, geo, fused_grid(maxch, bpc), smem, chunks, nchunks, with_rho,
                kinetic, 0, esc, jshift, stream);
   return last_launch("fused");
@@ -510,7 +510,8 @@ struct lpic_sim {
   unsigned long long* wmax = nullptr;        // per segment: max |w| (FP64 bits)
   int32_t* jshift = nullptr;                 // per run: fixed-point shift of FP32 currents
   int64_t esc_capacity = 0;
-  int blocks_per_cu = 1;
+  int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
+  int blocks_per_cu_rho = 1;
   void* old_state = nullptr;
   std::vector<size_t> old_off;
   std::vector<HookEntry> hooks[LPIC_NUM_STAGES];
@@ -658,7 +659,8 @@ lpic_status configure(lpic_sim* s) {
   s->smem = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 0);
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1);
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, &s->blocks_per_cu));
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem_rho, &s->blocks_per_cu_rho));
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem, &s->blocks_per_cu));
   if (!s->wmax) {
     ALLOC(s->wmax, sizeof(unsigned long long) * std::max(1, s->nsegs));
     ALLOC(s->jshift, sizeof(int32_t) * std::max(1, s->nruns));
@@ -746,7 +748,8 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       esc.count = s->esc_count;
       esc.total = s->escapes;
       esc.capacity = s->esc_capacity;
-      launch_fused(Tc, s->prec, s->ndim, s->geo, fused_grid(s->max_chunks, s->blocks_per_cu),
+      launch_fused(Tc, s->prec, s->ndim, s->geo,
+                   fused_grid(s->max_chunks, diag ? s->blocks_per_cu_rho : s->blocks_per_cu),
                    diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
                    diag ? 1 : 0, esc, s->jshift, st);
       CHK(last_launch("fused"));

@@ -127,6 +127,10 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // consecutive particles) and then pushes them one by one, so HBM latency is paid once per
 // round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
 constexpr int BATCH = 4;
+// Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (128 VGPRs,
+// a few spills, measured faster than 3 waves without); the others keep the compiler's choice.
+template <typename R, int DIM>
+constexpr int fused_waves() { return (sizeof(R) == 4 && DIM == 2) ? 4 : 1; }
 
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
@@ -201,7 +205,7 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 // the other species of the same box, which follow in the table) reuse the staged region;
 // the region is flushed when the tile changes.
 template <typename R, int DIM, int G>
-__global__ __launch_bounds__(256) void k_fused(Tables T, const Chunk* chunks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
                                                EscapeList esc, const int32_t* jshift) {
@@ -388,29 +392,31 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
 }
 
 template <typename R, int D, int G>
-static hipError_t set_smem(size_t smem, int* blocks_per_cu) {
+static hipError_t set_smem(size_t smem, size_t smem_occ, int* blocks_per_cu) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fused<R, D, G>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256, smem);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256,
+                                                      smem_occ);
 }
 
-hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu) {
+hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_occ,
+                         int* blocks_per_cu) {
   hipError_t e = hipSuccess;
   int* b = blocks_per_cu;
   if (dim == 2) {
     switch (geo) {
-      case 1: e = prec == 0 ? set_smem<float, 2, 1>(smem, b) : set_smem<double, 2, 1>(smem, b); break;
-      case 2: e = prec == 0 ? set_smem<float, 2, 2>(smem, b) : set_smem<double, 2, 2>(smem, b); break;
-      case 3: e = prec == 0 ? set_smem<float, 2, 3>(smem, b) : set_smem<double, 2, 3>(smem, b); break;
-      case 4: e = prec == 0 ? set_smem<float, 2, 4>(smem, b) : set_smem<double, 2, 4>(smem, b); break;
-      default: e = prec == 0 ? set_smem<float, 2, 0>(smem, b) : set_smem<double, 2, 0>(smem, b); break;
+      case 1: e = prec == 0 ? set_smem<float, 2, 1>(smem, smem_occ, b) : set_smem<double, 2, 1>(smem, smem_occ, b); break;
+      case 2: e = prec == 0 ? set_smem<float, 2, 2>(smem, smem_occ, b) : set_smem<double, 2, 2>(smem, smem_occ, b); break;
+      case 3: e = prec == 0 ? set_smem<float, 2, 3>(smem, smem_occ, b) : set_smem<double, 2, 3>(smem, smem_occ, b); break;
+      case 4: e = prec == 0 ? set_smem<float, 2, 4>(smem, smem_occ, b) : set_smem<double, 2, 4>(smem, smem_occ, b); break;
+      default: e = prec == 0 ? set_smem<float, 2, 0>(smem, smem_occ, b) : set_smem<double, 2, 0>(smem, smem_occ, b); break;
     }
   } else {
     switch (geo) {
-      case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, b) : set_smem<double, 3, 5>(smem, b); break;
-      case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, b) : set_smem<double, 3, 6>(smem, b); break;
-      default: e = prec == 0 ? set_smem<float, 3, 0>(smem, b) : set_smem<double, 3, 0>(smem, b); break;
+      case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, smem_occ, b) : set_smem<double, 3, 5>(smem, smem_occ, b); break;
+      case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, smem_occ, b) : set_smem<double, 3, 6>(smem, smem_occ, b); break;
+      default: e = prec == 0 ? set_smem<float, 3, 0>(smem, smem_occ, b) : set_smem<double, 3, 0>(smem, smem_occ, b); break;
     }
   }
   return e;

@@ -58,8 +58,10 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
 // caller; nblocks workgroups of SORT_BLOCK particles as for the sort) and its particle count.
 void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
                         unsigned long long* wmax, int32_t* jshift, hipStream_t st);
-// Sets the dynamic LDS limit and returns how many workgroups of the kernel fit on a CU.
-hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, int* blocks_per_cu);
+// Sets the dynamic LDS limit to smem and returns how many workgroups of the kernel fit on a
+// CU when each uses smem_occ bytes.
+hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_occ,
+                         int* blocks_per_cu);
 void launch_reduce_fields(const Tables& T, int prec, int dim, int nblocks, int with_rho,
                           double* out, hipStream_t st);
 void launch_kinetic(const Tables& T, int prec, int dim, int nblocks, double* out,

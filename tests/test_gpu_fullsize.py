@@ -1,0 +1,102 @@
+"""Parity at the benchmark's full size, in the benchmark's launch configuration.
+
+Workload: the 2D3V laser-slab box, 2048 x 1024 cells, dx = lambda/32, electrons + protons at
+32 ppc each in the slab (16,777,216 particles), quadratic shape, FP32 cell + offset path,
+tiles 16 x 16 with a 5-cell halo, chunks of 2048, graph replay -- what bench.py times.
+
+- One whole step (Algorithm 1: field halves, fused gather + Boris + Esirkepov over every
+  particle, field halves) against the FP64 oracle stepping the same state: every field
+  component and every particle, element by element.  The step compared is one without a
+  sort, so both sides hold the particles in the same order; the sort is checked on its own.
+- The tile sort at full size: an exact permutation of the particle records, grouped by tile
+  as tile_offsets says, dead particles last.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner, compare_fields, compare_particles
+from oracle import OracleSim
+from paper_2607_13507_amd import lpic as L
+from paper_2607_13507_amd import workloads as W
+from paper_2607_13507_amd.simulation import DeviceSpecies, Simulation, grid_struct
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_from_gpu(sim, wl):
+    orc = OracleSim.from_workload(wl, with_rho=True)
+    for k, v in sim.fields[0].numpy().items():
+        if k in orc.f:
+            orc.f[k][:] = v
+    for i, s in enumerate(orc.species):
+        pos = sim.positions(i)
+        s.x[:], s.y[:] = pos[0], pos[1]
+        cur = sim.current(i)
+        for k in ("ux", "uy", "uz", "w"):
+            getattr(s, k)[:] = cur.numpy(k)
+    return orc
+
+
+def test_laser_slab_full_size_step_matches_oracle():
+    banner("full-size laser slab: one FP32 step vs the oracle")
+    wl = W.laser_slab_2d()
+    assert wl.nparticles == 16_777_216
+    sim = Simulation(wl, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=5, chunk=2048,
+                     sort_interval=10, diag_interval=1, use_graph=True)
+    sim.step(1)                      # sort + first step
+    torch.cuda.synchronize()
+    orc = _oracle_from_gpu(sim, wl)  # the oracle starts from the GPU's state after step 1
+    banner("full-size laser slab: GPU step 2")
+    sim.step(1)                      # no sort (interval 10): same particle order as the oracle
+    torch.cuda.synchronize()
+    banner("full-size laser slab: oracle step 2")
+    orc.step(1)
+    d = sim.diagnostics(0)
+    assert d["continuity"] < 1e-5, d
+    compare_fields(sim.fields[0], orc, L.F32_CELLOFS, tol=2e-5, what="full-size step")
+    for i in range(len(wl.species)):
+        compare_particles(sim.grids[0], sim.current(i), orc.species[i], L.F32_CELLOFS,
+                          tol_pos=2e-5, tol_u=2e-5, what=f"species {i}")
+    assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-5)
+    assert d["kinetic_energy"] == pytest.approx(orc.kinetic_energy(), rel=1e-5)
+    sim.close()
+
+
+def test_laser_slab_full_size_sort_is_exact():
+    banner("full-size laser slab: tile sort")
+    wl = W.laser_slab_2d()
+    grid = grid_struct(wl)
+    tiling = L.Tiling(16, 16, 1, 5, 2048, 0)
+    nt = L.lpic_num_tiles(grid, tiling)
+    for s in wl.species:
+        d = DeviceSpecies.from_init(grid, s, L.F32_CELLOFS)
+        # kill every 1001st particle: dead particles must end up after every tile
+        d.a["cell"][::1001] = -1
+        before = {k: d.numpy(k) for k in d.a}
+        alt = d.like()
+        offs = torch.zeros(nt + 2, dtype=torch.int32, device="cuda")
+        wsb = L.lpic_sort_ws_bytes(grid, tiling, d.n)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        L.lpic_sort_tiles(grid, d.struct(), alt.struct(), tiling, offs.data_ptr(),
+                          ws.data_ptr(), wsb, L.F32_CELLOFS)
+        torch.cuda.synchronize()
+        after = {k: alt.numpy(k) for k in alt.a}   # the sorted data landed in `alt`
+        # exact permutation of the records (compared as raw 32-bit rows)
+        keys = ("cell", "ox", "oy", "ux", "uy", "uz", "w")
+        rb = np.stack([before[k].view(np.int32) for k in keys], axis=1)
+        ra = np.stack([after[k].view(np.int32) for k in keys], axis=1)
+        rb = rb[np.lexsort(rb.T[::-1])]
+        ra = ra[np.lexsort(ra.T[::-1])]
+        np.testing.assert_array_equal(ra, rb)
+        # grouping by tile
+        o = offs.cpu().numpy().astype(np.int64)
+        assert o[0] == 0 and o[-1] == d.n and np.all(np.diff(o) >= 0)
+        cell = after["cell"]
+        ndead = int((before["cell"] < 0).sum())
+        assert o[nt + 1] - o[nt] == ndead and np.all(cell[o[nt]:] < 0)
+        ix, iy = cell[: o[nt]] & 0xFFFF, cell[: o[nt]] >> 16
+        tiles = (iy // 16) * (wl.nx // 16) + ix // 16
+        np.testing.assert_array_equal(tiles, np.repeat(np.arange(nt), np.diff(o[: nt + 1])))
+        del d, alt, ws
+        torch.cuda.empty_cache()
