@@ -377,9 +377,10 @@ size_t lpic_fused_ws_bytes(const lpic_grid* grid, const lpic_tiling* tiling, int
   if (!tiling || tiling->chunk < 1) return 0;
   const int64_t nt = lpic_num_tiles(grid, tiling);
   if (nt < 0) return 0;
-  // chunk count, escape counters and total, chunk table, escape list
+  // chunk count, escape counters and total, fixed-point shift; chunk table; escape list;
+  // weight maxima
   return 256 + align256((size_t)max_chunks_of(nt, n, tiling->chunk) * sizeof(Chunk)) +
-         (size_t)std::max<int64_t>(n, 1) * 8;
+         align256((size_t)std::max<int64_t>(n, 1) * 8) + (size_t)fixed_shift_slots() * 8;
 }
 
 lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fields,
@@ -408,10 +409,12 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   Chunk* chunks = (Chunk*)((char*)ws + 256);
   esc.items = (unsigned long long*)((char*)chunks + align256((size_t)maxch * sizeof(Chunk)));
   esc.capacity = sp->n;
-  unsigned long long* wmax = (unsigned long long*)((char*)ws + 192);
-  int32_t* jshift = (int32_t*)((char*)ws + 224);
-  launch_zero_u32((uint32_t*)ws, 64, stream);   // chunk count, escape counters, weight max
+  int32_t* jshift = (int32_t*)((char*)ws + 192);
+  unsigned long long* wmax = (unsigned long long*)((char*)esc.items + align256((size_t)sp->n * 8));
+  launch_zero_u32((uint32_t*)ws, 64, stream);   // chunk count, escape counters
   CHK(last_launch("fused clear"));
+  launch_zero_u32((uint32_t*)wmax, 2 * (int64_t)fixed_shift_slots(), stream);
+  CHK(last_launch("weight max clear"));
   launch_fixed_shift(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), 1, 1,
                      wmax, jshift, stream);
   CHK(last_launch("fixed-point shift"));
@@ -662,7 +665,7 @@ lpic_status configure(lpic_sim* s) {
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem_rho, &s->blocks_per_cu_rho));
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem, &s->blocks_per_cu));
   if (!s->wmax) {
-    ALLOC(s->wmax, sizeof(unsigned long long) * std::max(1, s->nsegs));
+    ALLOC(s->wmax, sizeof(unsigned long long) * fixed_shift_slots() * std::max(1, s->nsegs));
     ALLOC(s->jshift, sizeof(int32_t) * std::max(1, s->nruns));
   }
   if (!s->esc_items) {
@@ -688,7 +691,7 @@ void swap_host_buffers(lpic_sim* s) {
 // the start of every lpic_step call and, when hooks are registered, in every step.
 lpic_status enqueue_fixed_shift(lpic_sim* s, hipStream_t st) {
   if (s->nsegs == 0 || s->prec != LPIC_F32_CELLOFS) return LPIC_OK;
-  launch_zero_u32((uint32_t*)s->wmax, 2 * (int64_t)s->nsegs, st);
+  launch_zero_u32((uint32_t*)s->wmax, 2 * (int64_t)fixed_shift_slots() * s->nsegs, st);
   CHK(last_launch("weight max clear"));
   launch_fixed_shift(sim_tables(s, s->seg_blk_sort_d), s->prec, s->ndim, s->nblk_sort, s->nruns,
                      s->nsegs, s->wmax, s->jshift, st);

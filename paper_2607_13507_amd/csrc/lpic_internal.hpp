@@ -54,8 +54,10 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
                   int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
                   hipStream_t st);
 // Per run, the shift S for the fixed-point current accumulators of the fused kernel, from
-// the largest |q w| of its species (wmax: one 8-byte slot per segment, zeroed by the
-// caller; nblocks workgroups of SORT_BLOCK particles as for the sort) and its particle count.
+// the largest |q w| of its species (wmax: fixed_shift_slots() 8-byte words per segment,
+// zeroed by the caller; nblocks workgroups of SORT_BLOCK particles as for the sort) and its
+// particle count.
+int fixed_shift_slots();
 void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
                         unsigned long long* wmax, int32_t* jshift, hipStream_t st);
 // Sets the dynamic LDS limit to smem and returns how many workgroups of the kernel fit on a

@@ -492,7 +492,10 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
 //   |v| 2^S < 2^50 for every contribution (exact FP64 rounding to an integer), and
 //   |any accumulated sum| <= n cmax 2^S < 2^61 (no 64-bit overflow, whatever the order).
 // =======================================================================================
-constexpr int WMAX_SPAN = 16;   // sort-sized particle blocks per workgroup
+constexpr int WMAX_SPAN = 4;    // sort-sized particle blocks per workgroup
+// Each segment's maximum is spread over WMAX_SLOTS words (workgroup b uses slot b mod
+// WMAX_SLOTS) so that the workgroups' atomics do not all queue on one address.
+constexpr int WMAX_SLOTS = 64;
 
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_wmax(Tables T, int nvblk, unsigned long long* wmax) {
@@ -514,8 +517,9 @@ __global__ __launch_bounds__(256) void k_wmax(Tables T, int nvblk, unsigned long
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
         __syncthreads();
         if (threadIdx.x == 0)
-          atomicMax(&wmax[cur], (unsigned long long)__double_as_longlong(
-                                    fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+          atomicMax(&wmax[cur * WMAX_SLOTS + (blockIdx.x & (WMAX_SLOTS - 1))],
+                    (unsigned long long)__double_as_longlong(
+                        fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
       }
       m = 0.0;
       cur = si;
@@ -535,8 +539,9 @@ __global__ __launch_bounds__(256) void k_wmax(Tables T, int nvblk, unsigned long
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0)
-      atomicMax(&wmax[cur], (unsigned long long)__double_as_longlong(
-                                fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));   // >= 0
+      atomicMax(&wmax[cur * WMAX_SLOTS + (blockIdx.x & (WMAX_SLOTS - 1))],
+                (unsigned long long)__double_as_longlong(
+                    fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));   // >= 0
   }
 }
 
@@ -551,7 +556,10 @@ __global__ void k_fixed_shift(Tables T, int nruns, int nsegs, const unsigned lon
   for (int i = 0; i < nsegs; ++i) {
     const SegDesc& s = seg_of(T, i);
     if (s.run != ri) continue;
-    cmax = fmax(cmax, fabs(s.q) * __longlong_as_double((long long)wmax[i]));
+    double wm = 0.0;
+    for (int k = 0; k < WMAX_SLOTS; ++k)
+      wm = fmax(wm, __longlong_as_double((long long)wmax[i * WMAX_SLOTS + k]));
+    cmax = fmax(cmax, fabs(s.q) * wm);
     n += (double)s.n;
   }
   cmax *= 2.0 * h;
@@ -855,6 +863,8 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
   LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult,
                                                                      spread)));
 }
+
+int fixed_shift_slots() { return WMAX_SLOTS; }
 
 void launch_fixed_shift(const Tables& T, int prec, int dim, int nblocks, int nruns, int nsegs,
                         unsigned long long* wmax, int32_t* jshift, hipStream_t st) {
