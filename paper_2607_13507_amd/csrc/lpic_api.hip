@@ -523,7 +523,9 @@ struct lpic_sim {
   bool need_sort = true;
   bool need_spread = true;   // the first sort after particles are loaded spreads tiles
   // graphs indexed by (sort, diag)
-  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  // captured steps keyed by (sort, diagnostics, full first E update, last E half deferred)
+  static constexpr int NGRAPHS = 16;
+  hipGraphExec_t gexec[NGRAPHS] = {};
   bool gparity[4] = {false, false, false, false};
   // timing
   bool timing = false;
@@ -540,7 +542,7 @@ void free_dev(void* p) {
 }
 
 void drop_graphs(lpic_sim* s) {
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < lpic_sim::NGRAPHS; ++i) {
     if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
     s->gexec[i] = nullptr;
   }
@@ -700,8 +702,11 @@ lpic_status enqueue_fixed_shift(lpic_sim* s, hipStream_t st) {
 
 // The device work of one step between the LOOP_START and LOOP_END hooks.  With hooks at the
 // inner stages the host runs them in between (eager mode only).
+// first_full: the previous step deferred its last E half (skip_last), so this step's first
+// E update covers both halves at once: between them B does not change and J is the same
+// array, so E + (dt/2)(curl B - J) twice is E + dt (curl B - J).
 lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread, bool diag,
-                         bool eager_hooks, bool capturing) {
+                         bool eager_hooks, bool capturing, bool first_full, bool skip_last) {
   const Tables Tc = sim_tables(s, nullptr);
   const Tables Ts = sim_tables(s, s->seg_blk_sort_d);
   if (diag) {
@@ -709,7 +714,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     CHK(last_launch("diag clear"));
   }
   // field half update t -> t + dt/2 (E first), clearing J for the deposit
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 1, st);
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, 1, st);
   CHK(last_launch("yee E"));
   launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
   CHK(last_launch("yee B"));
@@ -790,8 +795,10 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
   // field half update t + dt/2 -> t + dt (B first)
   launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
   CHK(last_launch("yee B"));
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, st);
-  CHK(last_launch("yee E"));
+  if (!skip_last) {
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, st);
+    CHK(last_launch("yee E"));
+  }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_2));
   if (diag) {
     launch_reduce_fields(Tc, s->prec, s->ndim, s->nblk_cells, 1, nullptr, st);
@@ -924,20 +931,28 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
   s->last_graph = use_graph;
   CHK(run_hooks(s, LPIC_STAGE_START));
   if (nsteps > 0) CHK(enqueue_fixed_shift(s, s->stream));
+  const bool hooks = any_hooks(s);
+  bool e_half_pending = false;
   for (int n = 0; n < nsteps; ++n) {
     CHK(run_hooks(s, LPIC_STAGE_LOOP_START));
     const bool do_sort = s->need_sort || (s->step % s->opt.sort_interval) == 0;
     const bool always_spread = (s->opt.tiling.flags & LPIC_SORT_SPREAD) != 0;
     const bool spread = do_sort && (s->need_spread || always_spread);
     const bool diag = s->opt.diag_interval > 0 && ((s->step + 1) % s->opt.diag_interval) == 0;
+    // inside one call, with no hooks that could look at the fields between steps, a step
+    // that ends without diagnostics leaves its last E half to the next step
+    const bool first_full = e_half_pending;
+    const bool skip_last = !hooks && !diag && n + 1 < nsteps;
+    e_half_pending = skip_last;
     // the one-off spreading sort runs eagerly; captured sort steps use the plain sort unless
     // every sort spreads
     if (use_graph && (!spread || always_spread)) {
-      const int gi = (do_sort ? 2 : 0) + (diag ? 1 : 0);
+      const int gi = (do_sort ? 8 : 0) + (diag ? 4 : 0) + (first_full ? 2 : 0) + (skip_last ? 1 : 0);
       if (!s->gexec[gi]) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-        lpic_status st = enqueue_step(s, s->cap_stream, do_sort, spread, diag, false, true);
+        lpic_status st = enqueue_step(s, s->cap_stream, do_sort, spread, diag, false, true,
+                                      first_full, skip_last);
         hipError_t ee = hipStreamEndCapture(s->cap_stream, &g);
         if (st != LPIC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
         if (ee != hipSuccess) return fail(LPIC_EHIP, "graph capture: %s", hipGetErrorString(ee));
@@ -948,7 +963,7 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
       HIPCHK(hipGraphLaunch(s->gexec[gi], s->stream));
       if (do_sort && s->nsegs > 0) swap_host_buffers(s);
     } else {
-      CHK(enqueue_step(s, s->stream, do_sort, spread, diag, true, false));
+      CHK(enqueue_step(s, s->stream, do_sort, spread, diag, true, false, first_full, skip_last));
     }
     if (do_sort && s->nsegs > 0) {
       ++s->sorts;
