@@ -36,7 +36,17 @@ def build(force: bool = True) -> str:
 class Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
-                ("dz", ctypes.c_double), ("dt", ctypes.c_double), ("rho_bg", ctypes.c_double)]
+                ("dz", ctypes.c_double), ("dt", ctypes.c_double), ("rho_bg", ctypes.c_double),
+                ("open_x", ctypes.c_int32)]
+
+
+class Laser(ctypes.Structure):
+    _fields_ = [("pol", ctypes.c_int32), ("ia", ctypes.c_int32), ("a0", ctypes.c_double),
+                ("omega", ctypes.c_double), ("waist", ctypes.c_double), ("yc", ctypes.c_double),
+                ("zc", ctypes.c_double), ("t0", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+OPEN_MARGIN = 3   # cells at each open x end where particles are removed (oracle.h)
 
 
 class Fields(ctypes.Structure):
@@ -76,7 +86,10 @@ def lib():
         L.orc_gather_push.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
                                       ctypes.POINTER(Species)]
         L.orc_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
-                               ctypes.POINTER(Species), ctypes.c_int32]
+                               ctypes.POINTER(Species), ctypes.c_int32, ctypes.POINTER(Laser),
+                               ctypes.c_double]
+        L.orc_laser_source.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
+                                       ctypes.POINTER(Laser), ctypes.c_double]
         L.orc_field_energy.restype = ctypes.c_double
         L.orc_field_energy.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fields)]
         L.orc_kinetic_energy.restype = ctypes.c_double
@@ -121,9 +134,10 @@ class OracleSim:
     """One periodic run: grid, FP64 fields (flat, x fastest) and species."""
 
     def __init__(self, ndim, nx, ny, nz, dx, dy, dz, dt, rho_bg=0.0, species=(), fields=None,
-                 with_rho=True):
+                 with_rho=True, open_x=False, laser=None):
         self.grid = Grid(ndim, nx, ny, nz if ndim == 3 else 1, dx, dy, dz if ndim == 3 else 1.0,
-                         dt, rho_bg)
+                         dt, rho_bg, int(bool(open_x)))
+        self.laser = None if laser is None else Laser(**laser)
         self.ncell = nx * ny * (nz if ndim == 3 else 1)
         self.f = {k: np.zeros(self.ncell) for k in FIELD_NAMES}
         if fields:
@@ -140,7 +154,7 @@ class OracleSim:
         sp = [OracleSpecies(s.q, s.m, s.order, s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w)
               for s in wl.species]
         return cls(wl.ndim, wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.rho_bg, sp,
-                   wl.fields, with_rho)
+                   wl.fields, with_rho, getattr(wl, "open_x", False), getattr(wl, "laser", None))
 
     def fields_struct(self):
         f = self.f
@@ -201,10 +215,17 @@ class OracleSim:
     def step(self, n=1):
         fs = self.fields_struct()
         arr = (Species * max(1, len(self.species)))(*[s.struct() for s in self.species])
+        las = ctypes.byref(self.laser) if self.laser is not None else None
         for _ in range(n):
-            lib().orc_step(ctypes.byref(self.grid), ctypes.byref(fs), arr, len(self.species))
+            lib().orc_step(ctypes.byref(self.grid), ctypes.byref(fs), arr, len(self.species),
+                           las, (self.nstep + 1) * self.grid.dt)
             self.t += self.grid.dt
             self.nstep += 1
+
+    def laser_source(self, t):
+        fs = self.fields_struct()
+        lib().orc_laser_source(ctypes.byref(self.grid), ctypes.byref(fs),
+                               ctypes.byref(self.laser), t)
 
     # --- diagnostics ---------------------------------------------------------------------
     def field_energy(self):

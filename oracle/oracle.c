@@ -8,6 +8,7 @@
  *
  * Each function names the passage of the paper it follows (section, equation, algorithm).
  */
+#define _DEFAULT_SOURCE
 #include "oracle.h"
 
 #include <math.h>
@@ -103,8 +104,49 @@ void orc_gather(const orc_grid *g, const orc_fields *f, int32_t order, const dou
   B[0] = out[3]; B[1] = out[4]; B[2] = out[5];
 }
 
-/* Sec. 3.2, Eq. 3 in normalised units: E += frac*dt*(curl B - J) on the Yee stagger. */
+/* First-order Mur outgoing-wave condition on one column of a field component: the edge
+ * column `e` takes u_old(inner) + k (u_new(inner) - u_old(edge)) (Sec. 3.2 absorbing
+ * boundary; see the header).  old_edge and old_inner hold the values before the update. */
+static void mur_column(const orc_grid *g, double *u, const double *old_edge,
+                       const double *old_inner, int64_t e, int64_t inner, double h) {
+  double k = (h - g->dx) / (h + g->dx);
+  int nz = (g->ndim == 3) ? g->nz : 1;
+  for (int64_t kk = 0; kk < nz; ++kk)
+    for (int64_t j = 0; j < g->ny; ++j) {
+      int64_t t = kk * g->ny + j;
+      u[nidx(g, e, j, kk)] = old_inner[t] + k * (u[nidx(g, inner, j, kk)] - old_edge[t]);
+    }
+}
+
+/* Copy of column i of u into out[ny*nz]. */
+static void save_column(const orc_grid *g, const double *u, int64_t i, double *out) {
+  int nz = (g->ndim == 3) ? g->nz : 1;
+  for (int64_t kk = 0; kk < nz; ++kk)
+    for (int64_t j = 0; j < g->ny; ++j) out[kk * g->ny + j] = u[nidx(g, i, j, kk)];
+}
+
+static void yee_e_all(const orc_grid *g, orc_fields *f, double frac);
+
+/* Sec. 3.2, Eq. 3 in normalised units: E += frac*dt*(curl B - J) on the Yee stagger; with
+ * open x ends the tangential E of column 0 then follows the Mur condition. */
 void orc_yee_e(const orc_grid *g, orc_fields *f, double frac) {
+  if (!g->open_x) {
+    yee_e_all(g, f, frac);
+    return;
+  }
+  int64_t m = (int64_t)g->ny * ((g->ndim == 3) ? g->nz : 1);
+  double *buf = (double *)malloc(sizeof(double) * 4 * m);
+  save_column(g, f->ey, 0, buf);
+  save_column(g, f->ey, 1, buf + m);
+  save_column(g, f->ez, 0, buf + 2 * m);
+  save_column(g, f->ez, 1, buf + 3 * m);
+  yee_e_all(g, f, frac);
+  mur_column(g, f->ey, buf, buf + m, 0, 1, frac * g->dt);
+  mur_column(g, f->ez, buf + 2 * m, buf + 3 * m, 0, 1, frac * g->dt);
+  free(buf);
+}
+
+static void yee_e_all(const orc_grid *g, orc_fields *f, double frac) {
   double h = frac * g->dt;
   int three = (g->ndim == 3);
   int nz = three ? g->nz : 1;
@@ -124,8 +166,29 @@ void orc_yee_e(const orc_grid *g, orc_fields *f, double frac) {
       }
 }
 
-/* Sec. 3.2, Eq. 4: B -= frac*dt*curl E on the Yee stagger. */
+static void yee_b_all(const orc_grid *g, orc_fields *f, double frac);
+
+/* Sec. 3.2, Eq. 4: B -= frac*dt*curl E on the Yee stagger; with open x ends the tangential
+ * B of the last column then follows the Mur condition. */
 void orc_yee_b(const orc_grid *g, orc_fields *f, double frac) {
+  if (!g->open_x) {
+    yee_b_all(g, f, frac);
+    return;
+  }
+  int64_t m = (int64_t)g->ny * ((g->ndim == 3) ? g->nz : 1);
+  int64_t e = g->nx - 1;
+  double *buf = (double *)malloc(sizeof(double) * 4 * m);
+  save_column(g, f->by, e, buf);
+  save_column(g, f->by, e - 1, buf + m);
+  save_column(g, f->bz, e, buf + 2 * m);
+  save_column(g, f->bz, e - 1, buf + 3 * m);
+  yee_b_all(g, f, frac);
+  mur_column(g, f->by, buf, buf + m, e, e - 1, frac * g->dt);
+  mur_column(g, f->bz, buf + 2 * m, buf + 3 * m, e, e - 1, frac * g->dt);
+  free(buf);
+}
+
+static void yee_b_all(const orc_grid *g, orc_fields *f, double frac) {
   double h = frac * g->dt;
   int three = (g->ndim == 3);
   int nz = three ? g->nz : 1;
@@ -303,6 +366,9 @@ static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, in
     s->ux[p] = u[0];
     s->uy[p] = u[1];
     s->uz[p] = u[2];
+    if (g->open_x && (p1[0] < ORC_OPEN_MARGIN * g->dx ||
+                      p1[0] >= (g->nx - ORC_OPEN_MARGIN) * g->dx))
+      s->x[p] = -1.0;   /* left through an open x end */
   }
 }
 
@@ -315,10 +381,31 @@ void orc_gather_push(const orc_grid *g, const orc_fields *f, orc_species *s) {
   advance_species(g, (orc_fields *)f, s, 0, NULL, NULL, NULL);
 }
 
+/* The antenna current of the header's definition, added into J at time t. */
+void orc_laser_source(const orc_grid *g, orc_fields *f, const orc_laser *laser, double t) {
+  double tau = t - laser->t0;
+  if (tau < 0.0 || tau > laser->tau) return;
+  double env = sin(M_PI * tau / laser->tau);
+  double amp = laser->a0 * laser->omega * env * env * sin(laser->omega * tau);
+  int three = (g->ndim == 3);
+  int nz = three ? g->nz : 1;
+  double *J = (laser->pol == 1) ? f->jy : f->jz;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < g->ny; ++j) {
+      /* position of the J component's node: J_y at (ia, j+1/2, k), J_z at (ia, j, k+1/2) */
+      double y = (j + (laser->pol == 1 ? 0.5 : 0.0)) * g->dy;
+      double z = three ? (k + (laser->pol == 2 ? 0.5 : 0.0)) * g->dz : laser->zc;
+      double r2 = (y - laser->yc) * (y - laser->yc) + (z - laser->zc) * (z - laser->zc);
+      double einc = amp * exp(-r2 / (laser->waist * laser->waist));
+      J[nidx(g, laser->ia, j, k)] += -2.0 * einc / g->dx;
+    }
+}
+
 /* Algorithm 1: one timestep.  The first E half uses the current still held in J (the one
  * deposited by the previous step, zero before the first step), so that together with the
  * second half of the previous step E advances by a whole dt with that J, as in Eq. 3. */
-void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies) {
+void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies,
+              const orc_laser *laser, double t_next) {
   int64_t n = ncell(g);
   orc_yee_e(g, f, 0.5);
   orc_yee_b(g, f, 0.5);
@@ -328,6 +415,7 @@ void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecie
   if (f->rho0) memset(f->rho0, 0, sizeof(double) * n);
   if (f->rho1) memset(f->rho1, 0, sizeof(double) * n);
   for (int s = 0; s < nspecies; ++s) advance_species(g, f, &sp[s], 1, NULL, NULL, NULL);
+  if (laser) orc_laser_source(g, f, laser, t_next);
   orc_yee_b(g, f, 0.5);
   orc_yee_e(g, f, 0.5);
 }

@@ -38,7 +38,32 @@ typedef struct {
   int32_t nx, ny, nz;    /* cells; nz = 1 when ndim == 2 */
   double dx, dy, dz, dt;
   double rho_bg;         /* fixed neutralising background charge density (added in Gauss) */
+  int32_t open_x;        /* 0: periodic in x; 1: open x ends (see below) */
 } orc_grid;
+
+/* Open x ends (the absorbing boundaries of Sec. 3.2 and the particle loss at boundaries of
+ * Sec. 2.1; the paper uses a CPML layer, this oracle the first-order Mur condition):
+ *   - fields: after each E update the tangential E at the first node column (i = 0) and
+ *     after each B update the tangential B at the last column (i = nx-1) follow the
+ *     outgoing-wave condition u_new(edge) = u_old(inner) + k (u_new(inner) - u_old(edge)),
+ *     k = (c h - dx) / (c h + dx), h the time step of that update;
+ *   - particles: alive only with x in [ORC_OPEN_MARGIN dx, (nx - ORC_OPEN_MARGIN) dx); a
+ *     particle whose new position leaves that range is removed (x = -1) after depositing
+ *     its current for the step, so no interpolation or deposit stencil ever wraps in x. */
+#define ORC_OPEN_MARGIN 3
+
+/* Laser antenna (the GaussianLaser callback of Sec. 2.2, injection from the left boundary
+ * as in Sec. 4.2): a current sheet on the node column i = ia, J_pol = -2 E_inc / dx, which
+ * radiates E_inc to +x (and the same to -x, absorbed by the open boundary), with
+ *   E_inc(t, y, z) = a0 omega sin^2(pi (t - t0) / tau) exp(-((y-yc)^2 + (z-zc)^2) / w^2)
+ *                    sin(omega (t - t0))   for 0 <= t - t0 <= tau, else 0
+ * (2D drops z).  pol = 1: E along y (J_y at (ia, j+1/2)); pol = 2: E along z (J_z at
+ * (ia, j) in 2D, (ia, j, k+1/2) in 3D).  The current of step n is taken at t = (n+1) dt,
+ * the time level at which the E updates around the step end use J (Algorithm 1). */
+typedef struct {
+  int32_t pol, ia;
+  double a0, omega, waist, yc, zc, t0, tau;
+} orc_laser;
 
 typedef struct {
   double *ex, *ey, *ez, *bx, *by, *bz, *jx, *jy, *jz;
@@ -89,8 +114,13 @@ void orc_push_deposit(const orc_grid *g, orc_fields *f, orc_species *s, int32_t 
 /* Gather + push only (no deposit); positions are wrapped. */
 void orc_gather_push(const orc_grid *g, const orc_fields *f, orc_species *s);
 
-/* One full timestep of Algorithm 1 over all species. */
-void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies);
+/* Adds the antenna current of `laser` at time t into J. */
+void orc_laser_source(const orc_grid *g, orc_fields *f, const orc_laser *laser, double t);
+
+/* One full timestep of Algorithm 1 over all species; with laser != NULL the antenna current
+ * at t_next = (n+1) dt is added after the particles' deposit. */
+void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies,
+              const orc_laser *laser, double t_next);
 
 /* Diagnostics (all FP64).  dV is the cell volume (dx*dy or dx*dy*dz). */
 double orc_field_energy(const orc_grid *g, const orc_fields *f);
