@@ -7,9 +7,10 @@ advanced through gather + push + deposit.
 
 Workload (default): 2D3V 2048x1024 Yee grid, dx = lambda/32, fully ionised hydrogen slab of
 20 n_c in cells x in [512, 768), electrons + protons at 32 ppc each (16,777,216 particles),
-T = 1 keV, quadratic shape, linearly polarised a0 = 10 Gaussian pulse initialised in the
-vacuum in front of the slab (periodic box), seeded synthetic data.  The FP32 cell+offset
-path is `value`; the plain FP64 path is reported beside it.
+T = 1 keV, quadratic shape, linearly polarised a0 = 10 Gaussian laser (waist 6.25 lambda,
+sin^2 envelope of 25 lambda / c) injected by an antenna 4 cells from the open left end, open
+(absorbing) x ends, periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
+the plain FP64 path is reported beside it.
 
 Output: one JSON line (rank 0).  With --gpus > 1 the script exits: this build measures one
 GPU.
@@ -235,8 +236,9 @@ def main():
         "config": {"workload": f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c "
                                f"cells x in [{args.nx // 4},{args.nx * 3 // 8}), e- + p+ "
                                f"{args.ppc} ppc each ({wl.nparticles} particles), T=1 keV, "
-                               "quadratic, a0=10 pulse in-box (periodic stand-in for the "
-                               "boundary-injected laser), FP32 cell+offset",
+                               "quadratic, a0=10 laser injected at the open left end "
+                               "(antenna, waist 6.25 lambda, 25 lambda sin^2), open x ends, "
+                               "FP32 cell+offset",
                    "particles": wl.nparticles, "grid": [args.nx, args.ny],
                    "shape_order": 2, "sort_interval": f32["options"]["sort_interval"],
                    "diag_interval": 10, "tiling": f32["options"]},

@@ -63,13 +63,44 @@ typedef enum {
 typedef enum { LPIC_F32_CELLOFS = 0, LPIC_F64_ABS = 1 } lpic_precision;
 
 /* One simulation box (Sec. 3.2).  dt must satisfy the CFL bound
- * dt <= 1 / sqrt(dx^-2 + dy^-2 [+ dz^-2]). */
+ * dt <= 1 / sqrt(dx^-2 + dy^-2 [+ dz^-2]).
+ * open_x = 1 makes both x ends open (the absorbing boundaries of Sec. 3.2, where the paper
+ * uses a CPML layer; here the first-order Mur outgoing-wave condition):
+ *   - after every E update the tangential E of the first node column (Ey, Ez at i = 0), and
+ *     after every B update the tangential B of the last column (By, Bz at i = nx-1), take
+ *     u_new(edge) = u_old(inner) + k (u_new(inner) - u_old(edge)), k = (h - dx)/(h + dx),
+ *     h the time step of that update (c = 1);
+ *   - particles live only with x in [LPIC_OPEN_MARGIN dx, (nx - LPIC_OPEN_MARGIN) dx): a
+ *     particle whose new position leaves that range is marked dead after depositing the
+ *     current of that step (particles lost at boundaries, Sec. 2.1), so no interpolation
+ *     or deposit stencil reaches across an open end.
+ * y and z stay periodic. */
+#define LPIC_OPEN_MARGIN 3
 typedef struct {
   int32_t ndim;              /* 2 or 3 */
   int32_t nx, ny, nz;        /* cells; nz = 1 for ndim == 2 */
   double dx, dy, dz, dt;     /* dz ignored in 2D */
   double rho_bg;             /* fixed uniform background charge density (Gauss diagnostic) */
+  int32_t open_x;            /* 0: periodic in x; 1: open x ends (above) */
+  int32_t reserved0;         /* 0 */
 } lpic_grid;
+
+/* Laser antenna: the GaussianLaser callback of Sec. 2.2, injecting from the left boundary
+ * as in the laser-plasma setup of Sec. 4.2.  A current sheet on node column ia,
+ * J_pol += -2 E_inc / dx, radiates E_inc towards +x (and the same towards -x, which an
+ * open left end absorbs), with
+ *   E_inc(t, y, z) = a0 omega sin^2(pi (t - t0)/tau) exp(-((y - yc)^2 + (z - zc)^2)/waist^2)
+ *                    sin(omega (t - t0))    for 0 <= t - t0 <= tau, else 0
+ * (2D drops z; a0 is the normalised vector potential, omega the laser frequency, tau the
+ * full duration of the sin^2 envelope).  pol = 1: E along y (J_y at (ia, j+1/2, k));
+ * pol = 2: E along z (J_z at (ia, j) in 2D, (ia, j, k+1/2) in 3D).  Within a step the
+ * antenna current is taken at t = (n+1) dt, the time level at which the E updates around
+ * the end of step n use J (Algorithm 1). */
+typedef struct {
+  int32_t pol;               /* 1 or 2 */
+  int32_t ia;                /* antenna node column, 0 <= ia < nx */
+  double a0, omega, waist, yc, zc, t0, tau;
+} lpic_laser;
 
 /* Field arrays of one box, each ncell elements of float (F32) or double (F64). */
 typedef struct {
@@ -201,6 +232,14 @@ lpic_status lpic_store_positions(const lpic_grid *grid, const lpic_species *sp, 
                                  hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Laser antenna (struct lpic_laser above): adds the antenna current at time t into the
+ * J component of `laser->pol` of `fields` (device arrays of the grid's size).
+ * ------------------------------------------------------------------------------------- */
+lpic_status lpic_laser_source(const lpic_grid *grid, const lpic_fields *fields,
+                              const lpic_laser *laser, double t, lpic_precision prec,
+                              hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
  * FP64 field diagnostics (energy of Sec. 4.1, continuity of Sec. 3.1).  Writes into
  * out (device, 4 doubles, overwritten):
  *   out[0] = sum (E^2 + B^2)/2 * dV                 field energy
@@ -284,7 +323,9 @@ lpic_status lpic_get_species(lpic_sim *sim, int32_t s, lpic_species *out);
 lpic_status lpic_get_stats(lpic_sim *sim, lpic_stats *out);
 /* Latest diagnostics of box r, synchronous: out[0] field energy, out[1] kinetic energy,
  * out[2] continuity residual / max|rho1|, out[3] Gauss residual max, out[4] the step they
- * were taken at.  LPIC_ENUMERIC if any is NaN or Inf. */
+ * were taken at.  LPIC_ENUMERIC if any is NaN or Inf.  With a laser antenna the two
+ * residuals leave out the antenna's node column: its current is prescribed, not carried by
+ * charges, and its transverse profile has a divergence. */
 lpic_status lpic_get_diagnostics(lpic_sim *sim, int32_t r, double out[5]);
 /* Per-kernel timing of the fused kernel with HIP events on the simulation's stream
  * (on = 1).  Timing forces eager launches (no graph). */
@@ -292,6 +333,10 @@ lpic_status lpic_set_timing(lpic_sim *sim, int32_t on);
 /* Replace the options (tiling, intervals, graph) of an existing simulation, e.g. from an
  * autotuner; the next step re-sorts. */
 lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
+/* Attach a laser antenna to run r (laser = NULL removes it).  Every step then adds the
+ * antenna current at t = (step + 1) dt after the particles' deposit (before the
+ * CURRENT_DEPOSITION hooks), where step counts the steps taken so far. */
+lpic_status lpic_set_laser(lpic_sim *sim, int32_t r, const lpic_laser *laser);
 /* Try the listed candidate options for `steps_each` steps each (the simulation really
  * advances), keep the fastest; writes the winner into *best when non-NULL. */
 lpic_status lpic_autotune(lpic_sim *sim, const lpic_options *candidates, int32_t ncand,

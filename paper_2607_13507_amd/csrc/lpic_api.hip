@@ -6,11 +6,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
 #include "lpic.h"
 #include "lpic_internal.hpp"
+
+static_assert(LPIC_OPEN_MARGIN == lpic::OPEN_MARGIN, "open-end margin differs");
 
 using namespace lpic;
 
@@ -77,6 +80,9 @@ lpic_status check_grid(const lpic_grid* g, int prec) {
       return fail(LPIC_EINVAL, "3D cell packing needs nx, ny <= 2048, nz <= 512");
   }
   if (ncells(g) >= (int64_t)1 << 31) return fail(LPIC_EINVAL, "grid has too many cells");
+  if (g->open_x != 0 && g->open_x != 1) return fail(LPIC_EINVAL, "open_x must be 0 or 1");
+  if (g->open_x && g->nx < 2 * LPIC_OPEN_MARGIN + 2)
+    return fail(LPIC_EINVAL, "open x ends need nx >= %d", 2 * LPIC_OPEN_MARGIN + 2);
   if (prec != LPIC_F32_CELLOFS && prec != LPIC_F64_ABS)
     return fail(LPIC_EINVAL, "unknown precision %d", prec);
   return LPIC_OK;
@@ -144,6 +150,8 @@ RunDesc make_run(const lpic_grid* g, const lpic_fields* f, const lpic_tiling* t)
   r.dz = g->ndim == 3 ? g->dz : 1.0;
   r.dt = g->dt;
   r.rho_bg = g->rho_bg;
+  r.open_x = g->open_x;
+  r.has_laser = 0;
   if (t) {
     tile_counts(g, t, r.ntx, r.nty, r.ntz);
     r.ntiles = r.ntx * r.nty * r.ntz;
@@ -277,8 +285,50 @@ lpic_status lpic_yee_update_EB(const lpic_grid* grid, const lpic_fields* fields,
   RunDesc r = make_run(grid, fields, nullptr);
   Tables T = single_tables(r, nullptr);
   const int64_t nb = (ncells(grid) + 255) / 256;
-  launch_yee(T, prec, grid->ndim, (int)nb, which, frac, (flags & LPIC_YEE_ZERO_J) ? 1 : 0, stream);
+  launch_yee(T, prec, grid->ndim, (int)nb, which, frac, (flags & LPIC_YEE_ZERO_J) ? 1 : 0, 1,
+             stream);
   return last_launch("yee");
+}
+
+lpic_status check_laser(const lpic_laser* l, const lpic_grid* g) {
+  if (!l) return fail(LPIC_EINVAL, "laser is NULL");
+  if (l->pol != 1 && l->pol != 2) return fail(LPIC_EINVAL, "laser pol must be 1 (y) or 2 (z)");
+  if (l->ia < 0 || l->ia >= g->nx) return fail(LPIC_EINVAL, "laser column %d outside the grid", l->ia);
+  if (!(l->tau > 0) || !(l->waist > 0) || !std::isfinite(l->a0) || !std::isfinite(l->omega))
+    return fail(LPIC_EINVAL, "laser needs tau > 0, waist > 0 and finite a0, omega");
+  return LPIC_OK;
+}
+
+LaserDesc make_laser(const lpic_laser* l) {
+  LaserDesc d;
+  d.pol = l->pol;
+  d.ia = l->ia;
+  d.e0 = l->a0 * l->omega;
+  d.omega = l->omega;
+  d.waist = l->waist;
+  d.yc = l->yc;
+  d.zc = l->zc;
+  d.t0 = l->t0;
+  d.tau = l->tau;
+  return d;
+}
+
+int columns_bpr(const lpic_grid* g) {
+  return (int)(((int64_t)g->ny * (g->ndim == 3 ? g->nz : 1) + 255) / 256);
+}
+
+lpic_status lpic_laser_source(const lpic_grid* grid, const lpic_fields* fields,
+                              const lpic_laser* laser, double t, lpic_precision prec,
+                              hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, false));
+  CHK(check_laser(laser, grid));
+  RunDesc r = make_run(grid, fields, nullptr);
+  r.has_laser = 1;
+  r.laser = make_laser(laser);
+  Tables T = single_tables(r, nullptr);
+  launch_laser(T, prec, grid->ndim, 1, columns_bpr(grid), t, nullptr, nullptr, stream);
+  return last_launch("laser");
 }
 
 size_t lpic_old_state_bytes(int32_t ndim, int64_t n, lpic_precision prec) {
@@ -511,6 +561,11 @@ struct lpic_sim {
   unsigned int* esc_count = nullptr;         // per-step escape counters
   unsigned long long* esc_items = nullptr;   // escape list (capacity: all particles)
   unsigned long long* wmax = nullptr;        // per segment: max |w| (FP64 bits)
+  std::vector<int> has_laser;                // per run
+  std::vector<LaserDesc> lasers;             // per run
+  int laser_bpr = 0;                         // antenna kernel blocks per run (0: no laser)
+  int64_t* step_dev = nullptr;               // steps taken, on the device (antenna time)
+  unsigned int* laser_done = nullptr;        // workgroup counter of the antenna kernel
   int32_t* jshift = nullptr;                 // per run: fixed-point shift of FP32 currents
   int64_t esc_capacity = 0;
   int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
@@ -601,9 +656,15 @@ lpic_status configure(lpic_sim* s) {
   // runs
   s->runs_h.clear();
   std::vector<int32_t> run_blk(1, 0);
+  s->has_laser.resize(s->nruns, 0);
+  s->lasers.resize(s->nruns);
+  s->laser_bpr = 0;
   for (int r = 0; r < s->nruns; ++r) {
     RunDesc d = make_run(&s->grids[r], &s->fields[r], &t);
     d.diag = s->diag + (size_t)r * DIAG_NUM;
+    d.has_laser = s->has_laser[r];
+    d.laser = s->lasers[r];
+    if (d.has_laser) s->laser_bpr = std::max(s->laser_bpr, columns_bpr(&s->grids[r]));
     s->runs_h.push_back(d);
     run_blk.push_back(run_blk.back() + (int32_t)((ncells(&s->grids[r]) + 255) / 256));
   }
@@ -666,6 +727,12 @@ lpic_status configure(lpic_sim* s) {
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem_rho, &s->blocks_per_cu_rho));
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem, &s->blocks_per_cu));
+  if (!s->step_dev) {
+    ALLOC(s->step_dev, 256);
+    s->laser_done = (unsigned int*)((char*)s->step_dev + 64);
+    HIPCHK(hipMemset(s->step_dev, 0, 256));
+  }
+  HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
   if (!s->wmax) {
     ALLOC(s->wmax, sizeof(unsigned long long) * fixed_shift_slots() * std::max(1, s->nsegs));
     ALLOC(s->jshift, sizeof(int32_t) * std::max(1, s->nruns));
@@ -714,9 +781,10 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     CHK(last_launch("diag clear"));
   }
   // field half update t -> t + dt/2 (E first), clearing J for the deposit
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, 1, st);
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, 1,
+             first_full ? 2 : 1, st);
   CHK(last_launch("yee E"));
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);
   CHK(last_launch("yee B"));
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_1));
   // sort particles (every sort_interval steps)
@@ -791,12 +859,17 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       }
     }
   }
+  if (s->laser_bpr > 0) {   // antenna current at t = (step + 1) dt
+    launch_laser(Tc, s->prec, s->ndim, s->nruns, s->laser_bpr, 0.0, s->step_dev, s->laser_done,
+                 st);
+    CHK(last_launch("laser"));
+  }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_CURRENT_DEPOSITION));
   // field half update t + dt/2 -> t + dt (B first)
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, st);
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);
   CHK(last_launch("yee B"));
   if (!skip_last) {
-    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, st);
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, 1, st);
     CHK(last_launch("yee E"));
   }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_2));
@@ -900,7 +973,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
   free_dev(s->esc_items); free_dev(s->esc_count);
-  free_dev(s->wmax); free_dev(s->jshift);
+  free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
   free_dev(s->old_state);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
@@ -1053,6 +1126,17 @@ lpic_status lpic_set_options(lpic_sim* s, const lpic_options* opt) {
     g_err = err;
   }
   return st;
+}
+
+lpic_status lpic_set_laser(lpic_sim* s, int32_t r, const lpic_laser* laser) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "run index %d out of range", r);
+  if (laser) {
+    CHK(check_laser(laser, &s->grids[r]));
+    s->lasers[r] = make_laser(laser);
+  }
+  s->has_laser[r] = laser ? 1 : 0;
+  return configure(s);   // rebuilds the device tables and the step counter, drops graphs
 }
 
 lpic_status lpic_autotune(lpic_sim* s, const lpic_options* cand, int32_t ncand,

@@ -25,14 +25,30 @@ enum PartSlot { P_CELL = 0, P_X = 0, P_OX = 1, P_Y = 1, P_OY = 2, P_Z = 2, P_OZ 
 enum { DIAG_UFIELD = 0, DIAG_UKIN = 1, DIAG_RES = 2, DIAG_RHOMAX = 3, DIAG_GAUSS = 4,
        DIAG_NUM = 8 };
 
+// Laser antenna of a box: E_inc amplitude e0 = a0 omega (see lpic_laser).
+struct LaserDesc {
+  int32_t pol, ia;
+  double e0, omega, waist, yc, zc, t0, tau;
+};
+
+// Cells at each open x end in which particles do not live.
+constexpr int OPEN_MARGIN = 3;
+
 // One simulation box.
 struct RunDesc {
   int32_t ndim, nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;   // tiles per axis of the current tiling
+  int32_t open_x, has_laser;       // open x ends; laser antenna present
   double dx, dy, dz, dt, rho_bg;
   void* f[F_NUM];
   double* diag;                    // DIAG_NUM device accumulators
+  LaserDesc laser;
 };
+
+// A particle whose cell column is inside the margin of an open x end leaves the box.
+__device__ __forceinline__ bool leaves_box(const RunDesc& r, int cx) {
+  return r.open_x && (cx < OPEN_MARGIN || cx >= r.nx - OPEN_MARGIN);
+}
 
 // One species of one box (a "segment" of the global particle key space).
 struct SegDesc {
@@ -702,7 +718,10 @@ __device__ __forceinline__ void advance_cell(int& c, R& o, R x1, int n) {
 template <typename R, int DIM>
 __device__ __forceinline__ void store_particle(const PartPtrs<R>& q, int32_t p,
                                                const PState<R>& ps) {
-  if constexpr (sizeof(R) == 4) {
+  if (!ps.alive) {   // removed during this step: the dead marker instead of the position
+    if constexpr (sizeof(R) == 4) q.cell[p] = -1;
+    else q.pos[0][p] = -1.0;
+  } else if constexpr (sizeof(R) == 4) {
     q.cell[p] = pack_cell(ps.c, DIM);
     q.pos[0][p] = ps.o[0];
     q.pos[1][p] = ps.o[1];

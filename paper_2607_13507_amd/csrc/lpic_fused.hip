@@ -176,8 +176,9 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
       deposit<DIM, ORDER>(L, pcell, po, pe, ps[b].w, vz1, k, with_rho != 0);
 #pragma unroll
       for (int d = 0; d < DIM; ++d) advance_cell<R>(ps[b].c[d], ps[b].o[d], x1[d], n[d]);
+      if (leaves_box(r, ps[b].c[0])) ps[b].alive = false;
       store_particle<R, DIM>(q, pi[b], ps[b]);
-      if (want_ke) {   // diagnostic steps only
+      if (want_ke && ps[b].alive) {   // diagnostic steps only
         const double u2 = (double)ps[b].u[0] * ps[b].u[0] + (double)ps[b].u[1] * ps[b].u[1] +
                           (double)ps[b].u[2] * ps[b].u[2];
         ke += (double)ps[b].w * u2 / (1.0 + (double)g1);
@@ -305,7 +306,9 @@ __device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s,
   const int n[3] = {r.nx, r.ny, r.nz};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
+  if (leaves_box(r, ps.c[0])) ps.alive = false;
   store_particle<R, DIM>(s, r, p, ps);
+  if (!ps.alive) return 0.0;
   const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] + (double)ps.u[2] * ps.u[2];
   return (double)ps.w * s.m * u2 / (1.0 + (double)g1);
 }

@@ -20,8 +20,14 @@ namespace lpic {
 
 constexpr int SORT_BLOCK = 2048;   // particles per workgroup of the sort kernels
 
+// which = 0: E update (zero_j also clears J and rho), 1: B update.  halves = 2: the E
+// update stands for two equal half updates (open x ends apply their condition twice).
 void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, double frac,
-                int zero_j, hipStream_t st);
+                int zero_j, int halves, hipStream_t st);
+// Laser antennas of the runs that have one (bpr workgroups of 256 (j, k) cells per run).
+// step != NULL: t = (*step + 1) dt, and the launch advances *step (done: a zeroed counter).
+void launch_laser(const Tables& T, int prec, int dim, int nruns, int bpr, double t,
+                  int64_t* step, unsigned int* done, hipStream_t st);
 void launch_gather_push(const Tables& T, int prec, int dim, int nblocks, void* old,
                         hipStream_t st);
 void launch_deposit(const Tables& T, int prec, int dim, int nblocks, const void* old,

@@ -16,6 +16,7 @@ __global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
 // =======================================================================================
 struct CellIdx {
   int64_t c, cim, cip, cjm, cjp, ckm, ckp;
+  int i;   // x index
 };
 
 __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, CellIdx& x) {
@@ -35,6 +36,7 @@ __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, C
     j = (int)(rest % r.ny);
     k = (int)(rest / r.ny);
   }
+  x.i = i;
   x.c = c;
   x.cim = c + (i == 0 ? r.nx - 1 : -1);
   x.cip = c + (i == r.nx - 1 ? 1 - r.nx : 1);
@@ -49,8 +51,56 @@ __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, C
   return true;
 }
 
+// E += h (curl B - J) at one cell: the increments (shared by the edge kernel).
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j) {
+__device__ __forceinline__ void yee_e_delta(const gptr<R>* f, const CellIdx& x, R hx, R hy,
+                                            R hz, R hh, R& dex, R& dey, R& dez) {
+  const R bx = f[F_BX][x.c], by = f[F_BY][x.c], bz = f[F_BZ][x.c];
+  const R jx = f[F_JX][x.c], jy = f[F_JY][x.c], jz = f[F_JZ][x.c];
+  dex = hy * (bz - f[F_BZ][x.cjm]) - hh * jx;
+  dey = -hx * (bz - f[F_BZ][x.cim]) - hh * jy;
+  dez = hx * (by - f[F_BY][x.cim]) - hy * (bx - f[F_BX][x.cjm]) - hh * jz;
+  if (DIM == 3) {
+    dex -= hz * (by - f[F_BY][x.ckm]);
+    dey += hz * (bx - f[F_BX][x.ckm]);
+  }
+}
+
+// B -= h curl E at one cell: the increments.
+template <typename R, int DIM>
+__device__ __forceinline__ void yee_b_delta(const gptr<R>* f, const CellIdx& x, R hx, R hy,
+                                            R hz, R& dbx, R& dby, R& dbz) {
+  const R ex = f[F_EX][x.c], ey = f[F_EY][x.c], ez = f[F_EZ][x.c];
+  dbx = -hy * (f[F_EZ][x.cjp] - ez);
+  dby = hx * (f[F_EZ][x.cip] - ez);
+  dbz = -hx * (f[F_EY][x.cip] - ey) + hy * (f[F_EX][x.cjp] - ex);
+  if (DIM == 3) {
+    dbx += hz * (f[F_EY][x.ckp] - ey);
+    dby -= hz * (f[F_EX][x.ckp] - ex);
+  }
+}
+
+// Open x ends, first-order Mur condition on a tangential component u of the edge column:
+// u_new(edge) = u_old(inner) + k (u_new(inner) - u_old(edge)), k = (h - dx)/(h + dx).  The
+// thread of the inner column applies it (it knows u_old and u_new there, and the edge
+// column's own thread leaves u alone), so no thread reads a value another one writes.
+// halves = 2: the update is two equal half updates of step h/2 merged into one (the inner
+// increment is d = 2 d_half), and the condition is applied twice.
+template <typename R>
+__device__ __forceinline__ R mur_edge(R u_edge_old, R u_in_old, R d, double h, double dx,
+                                      int halves) {
+  if (halves == 2) {
+    const R k = R((0.5 * h - dx) / (0.5 * h + dx));
+    const R u_in_mid = u_in_old + R(0.5) * d;
+    const R u_edge_mid = u_in_old + k * (u_in_mid - u_edge_old);
+    return u_in_mid + k * ((u_in_old + d) - u_edge_mid);
+  }
+  const R k = R((h - dx) / (h + dx));
+  return u_in_old + k * ((u_in_old + d) - u_edge_old);
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j, int halves) {
   int blk;
   const RunDesc& r = run_of(T, cell_block(T, blk));
   CellIdx x;
@@ -60,18 +110,18 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
   const double h = frac * r.dt;
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0), hh = R(h);
-  const R bx = f[F_BX][x.c], by = f[F_BY][x.c], bz = f[F_BZ][x.c];
-  const R jx = f[F_JX][x.c], jy = f[F_JY][x.c], jz = f[F_JZ][x.c];
-  R dex = hy * (bz - f[F_BZ][x.cjm]) - hh * jx;
-  R dey = -hx * (bz - f[F_BZ][x.cim]) - hh * jy;
-  R dez = hx * (by - f[F_BY][x.cim]) - hy * (bx - f[F_BX][x.cjm]) - hh * jz;
-  if (DIM == 3) {
-    dex -= hz * (by - f[F_BY][x.ckm]);
-    dey += hz * (bx - f[F_BX][x.ckm]);
-  }
+  R dex, dey, dez;
+  yee_e_delta<R, DIM>(f, x, hx, hy, hz, hh, dex, dey, dez);
   f[F_EX][x.c] += dex;
-  f[F_EY][x.c] += dey;
-  f[F_EZ][x.c] += dez;
+  if (r.open_x && x.i == 1) {   // Mur for column 0 (same j, k)
+    const R ey1 = f[F_EY][x.c], ez1 = f[F_EZ][x.c];
+    f[F_EY][x.cim] = mur_edge<R>(f[F_EY][x.cim], ey1, dey, h, r.dx, halves);
+    f[F_EZ][x.cim] = mur_edge<R>(f[F_EZ][x.cim], ez1, dez, h, r.dx, halves);
+  }
+  if (!(r.open_x && x.i == 0)) {   // column 0 of an open end: set by the thread of column 1
+    f[F_EY][x.c] += dey;
+    f[F_EZ][x.c] += dez;
+  }
   if (zero_j) {
     f[F_JX][x.c] = R(0);
     f[F_JY][x.c] = R(0);
@@ -92,17 +142,59 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac) {
   for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
   const double h = frac * r.dt;
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0);
-  const R ex = f[F_EX][x.c], ey = f[F_EY][x.c], ez = f[F_EZ][x.c];
-  R dbx = -hy * (f[F_EZ][x.cjp] - ez);
-  R dby = hx * (f[F_EZ][x.cip] - ez);
-  R dbz = -hx * (f[F_EY][x.cip] - ey) + hy * (f[F_EX][x.cjp] - ex);
-  if (DIM == 3) {
-    dbx += hz * (f[F_EY][x.ckp] - ey);
-    dby -= hz * (f[F_EX][x.ckp] - ex);
-  }
+  R dbx, dby, dbz;
+  yee_b_delta<R, DIM>(f, x, hx, hy, hz, dbx, dby, dbz);
   f[F_BX][x.c] += dbx;
-  f[F_BY][x.c] += dby;
-  f[F_BZ][x.c] += dbz;
+  if (r.open_x && x.i == r.nx - 2) {   // Mur for column nx-1 (same j, k)
+    const R by1 = f[F_BY][x.c], bz1 = f[F_BZ][x.c];
+    f[F_BY][x.cip] = mur_edge<R>(f[F_BY][x.cip], by1, dby, h, r.dx, 1);
+    f[F_BZ][x.cip] = mur_edge<R>(f[F_BZ][x.cip], bz1, dbz, h, r.dx, 1);
+  }
+  if (!(r.open_x && x.i == r.nx - 1)) {   // last column of an open end: set by column nx-2
+    f[F_BY][x.c] += dby;
+    f[F_BZ][x.c] += dbz;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Laser antenna: J_pol += -2 E_inc(t) / dx on node column ia (see lpic_laser).  With a
+// device step counter, t = (step + 1) dt and the last workgroup advances the counter (one
+// launch per step); otherwise t is the argument.
+// ---------------------------------------------------------------------------------------
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_laser(Tables T, int nruns, int bpr, double t_arg,
+                                               int64_t* step, unsigned int* done) {
+  const int ri = blockIdx.x / bpr;
+  if (ri < nruns) {
+    const RunDesc& r = run_of(T, ri);
+    const int64_t m = (int64_t)r.ny * (DIM == 3 ? r.nz : 1);
+    const int64_t tcell = (int64_t)(blockIdx.x % bpr) * 256 + threadIdx.x;
+    if (r.has_laser && tcell < m) {
+      const LaserDesc& L = r.laser;
+      const double t = (step ? (double)(*step + 1) * r.dt : t_arg) - L.t0;
+      if (t >= 0.0 && t <= L.tau) {
+        const int j = (int)(tcell % r.ny), k = (int)(tcell / r.ny);
+        const double y = (j + (L.pol == 1 ? 0.5 : 0.0)) * r.dy;
+        const double z = DIM == 3 ? (k + (L.pol == 2 ? 0.5 : 0.0)) * r.dz : L.zc;
+        const double env = sin(M_PI * t / L.tau);
+        const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
+        const double einc = L.e0 * env * env * sin(L.omega * t) * exp(-r2 / (L.waist * L.waist));
+        const int64_t c = ((int64_t)k * r.ny + j) * r.nx + L.ia;
+        gptr<R> J = gp((R*)r.f[L.pol == 1 ? F_JY : F_JZ]);
+        J[c] += R(-2.0 * einc / r.dx);
+      }
+    }
+  }
+  if (step) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(done, 1u) == gridDim.x - 1) {
+        *step += 1;
+        *done = 0u;
+      }
+    }
+  }
 }
 
 // =======================================================================================
@@ -215,6 +307,10 @@ __device__ __forceinline__ void deposit_one(const SegDesc& s, const RunDesc& r, 
   for (int d = 0; d < 3; ++d) pe[d] = d < DIM ? o0[d] + R(2) * (hd[d] * now.u[d] * ig1) : R(0);
   const GlobalAcc<R> A = global_acc<R>(r);
   deposit<DIM, ORDER>(A, c0, o0, pe, now.w, now.u[2] * ig1, k, with_rho);
+  if (leaves_box(r, now.c[0])) {   // its new position is in an open end's margin
+    now.alive = false;
+    store_particle<R, DIM>(s, r, (int32_t)p, now);
+  }
 }
 
 template <typename R, int DIM>
@@ -734,9 +830,13 @@ __global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int ncellblk, i
         divj += ((double)f[F_JZ][x.c] - (double)f[F_JZ][x.ckm]) / r.dz;
         dive += ((double)f[F_EZ][x.c] - (double)f[F_EZ][x.ckm]) / r.dz;
       }
-      res = fmax(res, fabs(r1 - r0 + r.dt * divj));
       rm = fmax(rm, fabs(r1));
-      ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
+      // a laser antenna's current is prescribed, not carried by charges (its transverse
+      // profile has a divergence): its node column is left out of both residuals
+      if (!(r.has_laser && x.i == r.laser.ia)) {
+        res = fmax(res, fabs(r1 - r0 + r.dt * divj));
+        ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
+      }
     }
   }
   if (cur >= 0) reduce_flush<DIM>(r, out, with_rho, en, res, rm, ga, red);
@@ -823,20 +923,25 @@ __global__ __launch_bounds__(256) void k_store_positions(Tables T, double* x, do
 // =======================================================================================
 template <typename R, int DIM>
 static void launch_yee_t(const Tables& T, int nblocks, int which, double frac, int zero_j,
-                         hipStream_t st) {
-  if (which == 0) k_yee_e<R, DIM><<<nblocks, 256, 0, st>>>(T, frac, zero_j);
+                         int halves, hipStream_t st) {
+  if (which == 0) k_yee_e<R, DIM><<<nblocks, 256, 0, st>>>(T, frac, zero_j, halves);
   else k_yee_b<R, DIM><<<nblocks, 256, 0, st>>>(T, frac);
 }
 
 void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, double frac,
-                int zero_j, hipStream_t st) {
+                int zero_j, int halves, hipStream_t st) {
   if (prec == 0) {
-    if (dim == 2) launch_yee_t<float, 2>(T, nblocks, which, frac, zero_j, st);
-    else launch_yee_t<float, 3>(T, nblocks, which, frac, zero_j, st);
+    if (dim == 2) launch_yee_t<float, 2>(T, nblocks, which, frac, zero_j, halves, st);
+    else launch_yee_t<float, 3>(T, nblocks, which, frac, zero_j, halves, st);
   } else {
-    if (dim == 2) launch_yee_t<double, 2>(T, nblocks, which, frac, zero_j, st);
-    else launch_yee_t<double, 3>(T, nblocks, which, frac, zero_j, st);
+    if (dim == 2) launch_yee_t<double, 2>(T, nblocks, which, frac, zero_j, halves, st);
+    else launch_yee_t<double, 3>(T, nblocks, which, frac, zero_j, halves, st);
   }
+}
+
+void launch_laser(const Tables& T, int prec, int dim, int nruns, int bpr, double t,
+                  int64_t* step, unsigned int* done, hipStream_t st) {
+  LPIC_PD(prec, dim, (k_laser<R, D><<<nruns * bpr, 256, 0, st>>>(T, nruns, bpr, t, step, done)));
 }
 
 

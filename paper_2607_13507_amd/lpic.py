@@ -29,10 +29,20 @@ STATUS = {0: "LPIC_OK", -1: "LPIC_EINVAL", -2: "LPIC_EHIP", -3: "LPIC_ENOMEM",
 _vp = ctypes.c_void_p
 
 
+OPEN_MARGIN = 3   # LPIC_OPEN_MARGIN
+
+
 class Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
-                ("dz", ctypes.c_double), ("dt", ctypes.c_double), ("rho_bg", ctypes.c_double)]
+                ("dz", ctypes.c_double), ("dt", ctypes.c_double), ("rho_bg", ctypes.c_double),
+                ("open_x", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+class Laser(ctypes.Structure):
+    _fields_ = [("pol", ctypes.c_int32), ("ia", ctypes.c_int32), ("a0", ctypes.c_double),
+                ("omega", ctypes.c_double), ("waist", ctypes.c_double), ("yc", ctypes.c_double),
+                ("zc", ctypes.c_double), ("t0", ctypes.c_double), ("tau", ctypes.c_double)]
 
 
 class Fields(ctypes.Structure):
@@ -106,6 +116,10 @@ EXPORTS = {
                                             _vp, _vp, ctypes.c_int, _vp]),
     "lpic_reduce_fields": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
                                           ctypes.c_int32, _vp, ctypes.c_int, _vp]),
+    "lpic_laser_source": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
+                                         ctypes.POINTER(Laser), ctypes.c_double, ctypes.c_int,
+                                         _vp]),
+    "lpic_set_laser": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Laser)]),
     "lpic_sim_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(Grid),
                                        ctypes.POINTER(Fields), ctypes.c_int32,
                                        ctypes.POINTER(Species), ctypes.POINTER(ctypes.c_int32),
@@ -237,6 +251,17 @@ def lpic_store_positions(grid, species, x, y, z, prec, stream=None):
 def lpic_reduce_fields(grid, fields, with_rho, out, prec, stream=None):
     _check("lpic_reduce_fields", lib().lpic_reduce_fields(ctypes.byref(grid), ctypes.byref(fields),
                                                           with_rho, out, prec, _stream(stream)))
+
+
+def lpic_laser_source(grid, fields, laser, t, prec, stream=None):
+    _check("lpic_laser_source", lib().lpic_laser_source(ctypes.byref(grid), ctypes.byref(fields),
+                                                        ctypes.byref(laser), float(t), prec,
+                                                        _stream(stream)))
+
+
+def lpic_set_laser(h, r, laser):
+    """laser: a Laser struct, or None to remove the run's antenna."""
+    _check("lpic_set_laser", lib().lpic_set_laser(h, r, ctypes.byref(laser) if laser else None))
 
 
 def lpic_sim_create(grids, fields, species, species_run, species_alt, prec, options, stream=None):

@@ -26,7 +26,8 @@ def torch_dtype(prec):
 
 def grid_struct(wl: Workload) -> L.Grid:
     return L.Grid(wl.ndim, wl.nx, wl.ny, wl.nz if wl.ndim == 3 else 1, wl.dx, wl.dy,
-                  wl.dz if wl.ndim == 3 else 1.0, wl.dt, wl.rho_bg)
+                  wl.dz if wl.ndim == 3 else 1.0, wl.dt, wl.rho_bg,
+                  int(bool(getattr(wl, "open_x", False))), 0)
 
 
 class DeviceFields:
@@ -199,6 +200,14 @@ class Simulation:
         self._callbacks: List[Callback] = []
         self.nstep = 0
         self.dt = wls[0].dt
+        for r, w in enumerate(wls):   # laser antennas (GaussianLaser, Sec. 2.2)
+            if getattr(w, "laser", None):
+                self.set_laser(r, w.laser)
+
+    def set_laser(self, r, laser):
+        """Attach the antenna `laser` (dict with the fields of lpic_laser) to run r, or
+        remove it with None."""
+        L.lpic_set_laser(self.h, r, L.Laser(**laser) if laser else None)
 
     # -- state ------------------------------------------------------------------------------
     @property

@@ -68,6 +68,8 @@ class Workload:
     fields: Dict[str, np.ndarray] = field(default_factory=dict)   # initial E, B (flat, x fastest)
     steps: int = 1
     meta: dict = field(default_factory=dict)
+    open_x: bool = False                  # open (absorbing) x ends instead of periodic
+    laser: Optional[dict] = None          # antenna: pol, ia, a0, omega, waist, yc, zc, t0, tau
 
     @property
     def ncell(self) -> int:
@@ -170,10 +172,15 @@ def thermal_2d(nx=64, ny=64, dx=0.05, ppc=16, T=0.01, density=1.0, order=1, seed
 
 def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), density=20.0,
                   ppc=32, T=T_1KEV, a0=10.0, order=2, seed=2, eta=0.95, steps=2000,
-                  pulse_cells=None, waist_lambda=6.25, name="laser_slab_2d") -> Workload:
+                  pulse_cells=None, waist_lambda=6.25, inject=True, duration_lambda=25.0,
+                  name="laser_slab_2d") -> Workload:
     """2D3V hydrogen slab (electrons + protons, `ppc` each) of `density` n_c in cells
-    [slab[0], slab[1]) over the whole y extent, with a Gaussian pulse of peak a0 in the
-    vacuum in front of it (x in [0, pulse_cells) cells, sin^2 envelope over that span).
+    [slab[0], slab[1]) over the whole y extent, and a linearly polarised (E along y)
+    Gaussian laser of peak a0, waist `waist_lambda` wavelengths.
+    inject=True: open x ends and a laser antenna 4 cells from the left end, sin^2 envelope
+    of full duration `duration_lambda` wavelengths (the setup of Sec. 4.2); y periodic.
+    inject=False: periodic box with the pulse placed in the vacuum in front of the slab
+    (x in [0, pulse_cells) cells, sin^2 envelope over that span).
     Electrons sit uniformly at random in their cells, each proton on an electron, so the
     plasma starts neutral node by node; momenta are drawn independently per species."""
     rng = np.random.default_rng(seed)
@@ -185,16 +192,22 @@ def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), densit
     # each proton starts on an electron: zero net charge at every node at t = 0
     p = _thermal_species(rng, "proton", +1.0, M_PROTON, order, xs.copy(), ys.copy(), None, T,
                          density, ppc)
+    dt = cfl_dt(eta, dx, dx)
+    if inject:
+        laser = dict(pol=1, ia=4, a0=a0, omega=1.0, waist=waist_lambda * LAMBDA,
+                     yc=0.5 * ny * dx, zc=0.0, t0=0.0, tau=duration_lambda * LAMBDA)
+        return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [e, p], {}, steps,
+                        dict(ppc=ppc, T=T, density=density, order=order, seed=seed, a0=a0,
+                             slab=slab, inject=True), open_x=True, laser=laser)
     if pulse_cells is None:
         pulse_cells = min(slab[0], nx)
     flds = {}
     if a0 > 0 and pulse_cells > 0:
         flds = gaussian_pulse_fields(nx, ny, dx, dx, a0, 0.0, pulse_cells * dx,
                                      waist_lambda * LAMBDA, 0.5 * ny * dx)
-    dt = cfl_dt(eta, dx, dx)
     return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [e, p], flds, steps,
                     dict(ppc=ppc, T=T, density=density, order=order, seed=seed, a0=a0,
-                         slab=slab, pulse_cells=pulse_cells))
+                         slab=slab, pulse_cells=pulse_cells, inject=False))
 
 
 def thermal_3d(n=256, dx=0.1, ppc=8, T=0.05, density=1.0, order=2, seed=3, eta=0.95,
@@ -217,8 +230,9 @@ def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
                 sizes_y=(128, 256, 512), cells_per_lambda=32, eta=0.95, steps=20):
     """Independent 2D3V laser-slab runs drawn from one seed: nx >= ny from the listed sizes,
     ppc per species from {4, 8, 16, 32}, slab density log-uniform in [0.1, 10] n_c filling
-    the right half, a0 log-uniform in [0.5, 20], CIC or quadratic with probability 1/2.
-    All members share dx = lambda/32 and hence dt."""
+    the right half (up to 8 cells from the open right end), a0 log-uniform in [0.5, 20]
+    injected from the left, CIC or quadratic with probability 1/2.  All members share
+    dx = lambda/32 and hence dt."""
     rng = np.random.default_rng(seed)
     runs = []
     for r in range(members):
@@ -235,7 +249,7 @@ def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
         order = int(rng.choice([1, 2]))
         sub = int(rng.integers(0, 2 ** 31 - 1))
         wl = laser_slab_2d(nx=nx, ny=ny, cells_per_lambda=cells_per_lambda,
-                           slab=(nx // 2, nx), density=dens, ppc=ppc, a0=a0, order=order,
+                           slab=(nx // 2, nx - 8), density=dens, ppc=ppc, a0=a0, order=order,
                            seed=sub, eta=eta, steps=steps, pulse_cells=nx // 2,
                            waist_lambda=min(6.25, 0.2 * ny / cells_per_lambda),
                            name=f"ensemble_member_{r}")

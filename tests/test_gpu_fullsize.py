@@ -2,7 +2,8 @@
 
 Workload: the 2D3V laser-slab box, 2048 x 1024 cells, dx = lambda/32, electrons + protons at
 32 ppc each in the slab (16,777,216 particles), quadratic shape, FP32 cell + offset path,
-tiles 16 x 16 with a 5-cell halo, chunks of 2048, graph replay -- what bench.py times.
+laser injected by an antenna near the open left end, open x ends, tiles 16 x 16 with a
+5-cell halo, chunks of 2048, graph replay -- what bench.py times.
 
 - One whole step (Algorithm 1: field halves, fused gather + Boris + Esirkepov over every
   particle, field halves) against the FP64 oracle stepping the same state: every field
@@ -47,6 +48,7 @@ def test_laser_slab_full_size_step_matches_oracle():
     sim.step(1)                      # sort + first step
     torch.cuda.synchronize()
     orc = _oracle_from_gpu(sim, wl)  # the oracle starts from the GPU's state after step 1
+    orc.nstep = 1                    # (the antenna's clock)
     banner("full-size laser slab: GPU step 2")
     sim.step(1)                      # no sort (interval 10): same particle order as the oracle
     torch.cuda.synchronize()
