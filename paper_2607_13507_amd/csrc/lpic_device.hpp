@@ -496,6 +496,11 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   int bx, by;
   esk_axis<ORDER>(x0[0], x1[0], bx, S0x, S1x);
   esk_axis<ORDER>(x0[1], x1[1], by, S0y, S1y);
+  // The last node of an axis' window carries weight only for a path that changes its
+  // nearest node along that axis.  When no lane of the wave has such a path, every entry
+  // on that node is an exact zero and the wave skips it (a uniform branch).
+  const bool lx = __ballot(S0x[W - 1] != R(0) || S1x[W - 1] != R(0)) != 0;
+  const bool ly = __ballot(S0y[W - 1] != R(0) || S1y[W - 1] != R(0)) != 0;
   int xo[W], yo[W];
 #pragma unroll
   for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
@@ -504,6 +509,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     const R cz = k.q * w * vz_bar * R(1.0 / 6.0);
 #pragma unroll
     for (int b = 0; b < W; ++b) {
+      if (b == W - 1 && !ly) continue;
       const R hy = cx * R(0.5) * (S0y[b] + S1y[b]);
       R acc = R(0);
 #pragma unroll
@@ -514,6 +520,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     }
 #pragma unroll
     for (int a = 0; a < W; ++a) {
+      if (a == W - 1 && !lx) continue;
       const R hx = cy * R(0.5) * (S0x[a] + S1x[a]);
       R acc = R(0);
 #pragma unroll
@@ -524,9 +531,13 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
+      if (b == W - 1 && !ly) continue;
       const R ay = R(2) * S0y[b] + S1y[b], by2 = S0y[b] + R(2) * S1y[b];
 #pragma unroll
-      for (int a = 0; a < W; ++a) A.add(F_JZ, yo[b] + xo[a], cz * (S0x[a] * ay + S1x[a] * by2));
+      for (int a = 0; a < W; ++a) {
+        if (a == W - 1 && !lx) continue;
+        A.add(F_JZ, yo[b] + xo[a], cz * (S0x[a] * ay + S1x[a] * by2));
+      }
     }
     if (with_rho) {
       const R qw = k.q * w;
@@ -534,6 +545,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
       for (int b = 0; b < W; ++b)
 #pragma unroll
         for (int a = 0; a < W; ++a) {
+          if ((a == W - 1 && !lx) || (b == W - 1 && !ly)) continue;
           A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
           A.add(F_R1, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
         }
@@ -542,6 +554,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     R S0z[W], S1z[W];
     int bz;
     esk_axis<ORDER>(x0[2], x1[2], bz, S0z, S1z);
+    const bool lz = __ballot(S0z[W - 1] != R(0) || S1z[W - 1] != R(0)) != 0;
     int zo[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) zo[a] = A.zo(c[2] + bz + a);
@@ -552,6 +565,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     for (int cc = 0; cc < W; ++cc)
 #pragma unroll
       for (int b = 0; b < W; ++b) {
+        if ((b == W - 1 && !ly) || (cc == W - 1 && !lz)) continue;
         const R ryz = cx * sixth * (S0y[b] * (R(2) * S0z[cc] + S1z[cc]) +
                                     S1y[b] * (S0z[cc] + R(2) * S1z[cc]));
         R acc = R(0);
@@ -565,6 +579,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     for (int cc = 0; cc < W; ++cc)
 #pragma unroll
       for (int a = 0; a < W; ++a) {
+        if ((a == W - 1 && !lx) || (cc == W - 1 && !lz)) continue;
         const R rxz = cy * sixth * (S0x[a] * (R(2) * S0z[cc] + S1z[cc]) +
                                     S1x[a] * (S0z[cc] + R(2) * S1z[cc]));
         R acc = R(0);
@@ -578,6 +593,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     for (int b = 0; b < W; ++b)
 #pragma unroll
       for (int a = 0; a < W; ++a) {
+        if ((a == W - 1 && !lx) || (b == W - 1 && !ly)) continue;
         const R rxy = cz * sixth * (S0x[a] * (R(2) * S0y[b] + S1y[b]) +
                                     S1x[a] * (S0y[b] + R(2) * S1y[b]));
         R acc = R(0);
@@ -595,6 +611,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         for (int b = 0; b < W; ++b)
 #pragma unroll
           for (int a = 0; a < W; ++a) {
+            if ((a == W - 1 && !lx) || (b == W - 1 && !ly) || (cc == W - 1 && !lz)) continue;
             const int off = zo[cc] + yo[b] + xo[a];
             A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
             A.add(F_R1, off, qw * S1x[a] * S1y[b] * S1z[cc]);
