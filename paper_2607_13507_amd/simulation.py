@@ -204,6 +204,10 @@ class Simulation:
             if getattr(w, "laser", None):
                 self.set_laser(r, w.laser)
 
+    def species_of_run(self, r) -> List[int]:
+        """Global indices of run r's species, in the order its workload lists them."""
+        return [i for i, rr in enumerate(self.species_run) if rr == r]
+
     def set_laser(self, r, laser):
         """Attach the antenna `laser` (dict with the fields of lpic_laser) to run r, or
         remove it with None."""

@@ -94,14 +94,16 @@ def cfl_dt(eta: float, *h: float) -> float:
 def _random_in_cells(rng, cells_x, cells_y, cells_z, ppc, dx, dy, dz):
     """ppc particles uniformly at random inside each listed cell (C-order cell lists)."""
     nc = cells_x.shape[0]
-    ix = np.repeat(cells_x, ppc)
-    iy = np.repeat(cells_y, ppc)
-    x = (ix + rng.random(nc * ppc)) * dx
-    y = (iy + rng.random(nc * ppc)) * dy
-    z = None
-    if cells_z is not None:
-        iz = np.repeat(cells_z, ppc)
-        z = (iz + rng.random(nc * ppc)) * dz
+
+    def axis(cells, h):
+        v = rng.random(nc * ppc)
+        v.reshape(nc, ppc)[...] += cells.astype(np.float64)[:, None]
+        v *= h
+        return v
+
+    x = axis(cells_x, dx)
+    y = axis(cells_y, dy)
+    z = axis(cells_z, dz) if cells_z is not None else None
     # a draw of exactly 1.0 cannot happen (rng.random is in [0, 1)), but rounding of
     # (i + r) * dx at the top cell can reach the box edge: fold it back
     return x, y, z
@@ -234,7 +236,7 @@ def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
     injected from the left, CIC or quadratic with probability 1/2.  All members share
     dx = lambda/32 and hence dt."""
     rng = np.random.default_rng(seed)
-    runs = []
+    params = []
     for r in range(members):
         while True:
             nx = int(rng.choice(sizes_x))
@@ -248,13 +250,12 @@ def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
         a0 = float(10 ** rng.uniform(math.log10(0.5), math.log10(20)))
         order = int(rng.choice([1, 2]))
         sub = int(rng.integers(0, 2 ** 31 - 1))
-        wl = laser_slab_2d(nx=nx, ny=ny, cells_per_lambda=cells_per_lambda,
+        params.append(dict(nx=nx, ny=ny, cells_per_lambda=cells_per_lambda,
                            slab=(nx // 2, nx - 8), density=dens, ppc=ppc, a0=a0, order=order,
                            seed=sub, eta=eta, steps=steps, pulse_cells=nx // 2,
                            waist_lambda=min(6.25, 0.2 * ny / cells_per_lambda),
-                           name=f"ensemble_member_{r}")
-        runs.append(wl)
-    return runs
+                           name=f"ensemble_member_{r}"))
+    return [laser_slab_2d(**kw) for kw in params]
 
 
 def wakefield_2d(nx=8192, ny=512, cells_per_lambda=40, density=0.01, ppc=4, a0=2.0,

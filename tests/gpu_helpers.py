@@ -66,13 +66,16 @@ def compare_particles(grid, dspec, ospec, prec, tol_pos=None, tol_u=None, what="
         assert err <= tol_u, f"{what} {k}: {err}"
 
 
-def compare_fields(F, orc, prec, keys=FIELDS, tol=None, what=""):
+def compare_fields(F, orc, prec, keys=FIELDS, tol=None, what="", floor=None):
+    """Max error of each component relative to its largest magnitude (or to floor[k] when
+    that is larger: a component that is nearly zero everywhere is compared against the
+    scale it would have in a non-trivial state)."""
     tol = tol if tol is not None else TOL[prec]
     g = F.numpy()
     worst = {}
     for k in keys:
         o = orc.f[k] if k in orc.f else getattr(orc, k)
-        scale = max(1e-300, np.abs(o).max(initial=0))
+        scale = max(1e-300, np.abs(o).max(initial=0), (floor or {}).get(k, 0.0))
         err = np.abs(g[k] - o).max(initial=0) / scale
         worst[k] = err
         assert err <= tol, f"{what} {k}: rel err {err} (scale {scale})"
