@@ -73,9 +73,35 @@ def read_traffic(launch_bytes_key="per_launch_bytes"):
 
 
 def build_workload(args):
+    """(list of runs, description, ndim, particles per occupied cell of each run)."""
     from paper_2607_13507_amd import workloads as W
-    return W.laser_slab_2d(nx=args.nx, ny=args.ny, slab=(args.nx // 4, args.nx * 3 // 8),
-                           ppc=args.ppc, steps=args.steps)
+    if args.workload == "laser_slab":
+        wl = W.laser_slab_2d(nx=args.nx, ny=args.ny, slab=(args.nx // 4, args.nx * 3 // 8),
+                             ppc=args.ppc, steps=args.steps)
+        desc = (f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c cells x in "
+                f"[{args.nx // 4},{args.nx * 3 // 8}), e- + p+ {args.ppc} ppc each "
+                f"({wl.nparticles} particles), T=1 keV, quadratic, a0=10 laser injected at the "
+                "open left end (antenna, waist 6.25 lambda, 25 lambda sin^2), open x ends, "
+                "FP32 cell+offset")
+        return [wl], desc, 2, [2 * args.ppc]
+    if args.workload == "thermal_3d":
+        wl = W.thermal_3d()
+        desc = (f"thermal_3d 256^3 dx=0.1 c/omega_p, electrons 8 ppc ({wl.nparticles} "
+                "particles) on a fixed ion background, T=0.05, quadratic, periodic, "
+                "FP32 cell+offset")
+        return [wl], desc, 3, [8]
+    if args.workload == "wakefield":
+        wl = W.wakefield_2d()
+        desc = (f"wakefield_2d 8192x512 dx=lambda/40, electrons 0.01 n_c 4 ppc "
+                f"({wl.nparticles} particles) on fixed ions, a0=2 pulse in a static window, "
+                "quadratic, periodic, FP32 cell+offset")
+        return [wl], desc, 2, [4]
+    members = W.ensemble_2d(seed=4, members=64)
+    n = sum(m.nparticles for m in members)
+    desc = (f"ensemble_2d 64 independent laser-slab runs from seed 4 ({n} particles), grids "
+            "128^2..1024x512, ppc 4-32, CIC/quadratic, lasers from the left, one step of all "
+            "of them per launch, FP32 cell+offset")
+    return members, desc, 2, [2 * m.meta["ppc"] for m in members]
 
 
 def run_gpu(wl, prec, args, steps, warmup, tune):
@@ -83,7 +109,12 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     from paper_2607_13507_amd import lpic as L
     from paper_2607_13507_amd.simulation import Simulation
 
-    sim = Simulation(wl, prec=prec, tiling=(args.tile, args.tile, 1), halo=args.halo,
+    ty, halo = args.tile, args.halo
+    if wl[0].ndim == 3:   # a 3D region with its charge planes must fit one CU's LDS
+        ty = max(1, args.tile // 2)
+        if prec == L.F64_ABS:
+            halo = max(3, halo - 1)
+    sim = Simulation(wl, prec=prec, tiling=(args.tile, ty, args.tile_z), halo=halo,
                      chunk=args.chunk, sort_interval=args.sort_interval, diag_interval=10,
                      use_graph=not args.no_graph)
     tuned = None
@@ -91,7 +122,7 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
         cands = []
         for t in (16, 32):
             for ch in (1024, 2048, 4096, 8192):
-                cands.append(dict(tiling=(t, t, 1), halo=args.halo, chunk=ch,
+                cands.append(dict(tiling=(t, t, args.tile_z), halo=args.halo, chunk=ch,
                                   sort_interval=args.sort_interval, use_graph=True))
         tuned = sim.autotune(cands, steps_each=2)
     sim.step(warmup)
@@ -114,7 +145,7 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     g1 = time.perf_counter()
     diag = sim.diagnostics(0)
     stg = sim.stats()
-    n = wl.nparticles
+    n = sum(w.nparticles for w in wl)
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps,
                pushes_per_s=n * steps / (t1 - t0),
                ms_per_step_graph=None if args.no_graph else 1e3 * (g1 - g0) / steps,
@@ -177,10 +208,15 @@ def main():
     ap.add_argument("--nx", type=int, default=2048)
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--ppc", type=int, default=32)
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--halo", type=int, default=5)
+    ap.add_argument("--workload", default="laser_slab",
+                    choices=("laser_slab", "thermal_3d", "wakefield", "ensemble"),
+                    help="laser_slab (default, the headline configuration); the others are "
+                         "extra measurements")
+    ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--tile-z", type=int, default=None)
+    ap.add_argument("--halo", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=2048)
-    ap.add_argument("--sort-interval", type=int, default=10)
+    ap.add_argument("--sort-interval", type=int, default=None)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -200,26 +236,38 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    wl = build_workload(args)
-    ppc_tot = 2 * args.ppc
+    wl, desc, ndim, ppc_tot = build_workload(args)
+    if args.tile is None:
+        args.tile = 16 if ndim == 2 else 8
+    if args.tile_z is None:
+        args.tile_z = 1 if ndim == 2 else 4
+    if args.halo is None:
+        args.halo = 5 if ndim == 2 else 4
+    if args.sort_interval is None:
+        args.sort_interval = 10 if ndim == 2 else 5
+    nparticles = sum(w.nparticles for w in wl)
     f32 = run_gpu(wl, L.F32_CELLOFS, args, args.steps, args.warmup, args.autotune)
     f64 = None
     if not args.no_fp64:
         s64 = max(5, args.steps // 5)
         f64 = run_gpu(wl, L.F64_ABS, args, s64, max(2, args.warmup // 5), False)
 
-    bpp = algorithmic_bytes_per_push(2, True, ppc_tot)
-    launch_bytes = bpp * wl.nparticles
+    def launch_bytes_of(f32_path):
+        # particle state in and out once per particle; E, B in and J out once per occupied cell
+        return sum(algorithmic_bytes_per_push(ndim, f32_path, p) * w.nparticles
+                   for w, p in zip(wl, ppc_tot))
+    launch_bytes = launch_bytes_of(True)
+    bpp = launch_bytes / nparticles
     achieved = launch_bytes / (f32["fused_ms"] * 1e-3) / 1e9
-    traffic = read_traffic()
+    traffic = read_traffic() if args.workload == "laser_slab" else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="lpic::k_fused<float,2>", bytes_per_push=round(bpp, 3),
+                kernel=f"lpic::k_fused<float,{ndim}>", bytes_per_push=round(bpp, 3),
                 bytes_per_launch=int(launch_bytes), avg_launch_ms=round(f32["fused_ms"], 4),
                 launches=f32["fused_launches"], kernel_source_sha256=kernel_source_hash())
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl)
+    if not args.no_cpu_baseline and args.workload == "laser_slab":
+        cpu = cpu_baseline(wl[0])
     out = {
         "metric": "particle-pushes/sec (gather+push+deposit) FP32 vs FP64, % HBM roofline",
         "value": round(f32["pushes_per_s"], 1),
@@ -233,18 +281,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c "
-                               f"cells x in [{args.nx // 4},{args.nx * 3 // 8}), e- + p+ "
-                               f"{args.ppc} ppc each ({wl.nparticles} particles), T=1 keV, "
-                               "quadratic, a0=10 laser injected at the open left end "
-                               "(antenna, waist 6.25 lambda, 25 lambda sin^2), open x ends, "
-                               "FP32 cell+offset",
-                   "particles": wl.nparticles, "grid": [args.nx, args.ny],
-                   "shape_order": 2, "sort_interval": f32["options"]["sort_interval"],
+        "config": {"workload": desc,
+                   "particles": nparticles, "runs": len(wl),
+                   "grid": [wl[0].nx, wl[0].ny] + ([wl[0].nz] if ndim == 3 else []),
+                   "sort_interval": f32["options"]["sort_interval"],
                    "diag_interval": 10, "tiling": f32["options"]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "fused_pushes_per_s": round(wl.nparticles / (f32["fused_ms"] * 1e-3), 1),
+        "fused_pushes_per_s": round(nparticles / (f32["fused_ms"] * 1e-3), 1),
         "graph_mode": None if args.no_graph else {
             "ms_per_step": round(f32["ms_per_step_graph"], 4),
             "pushes_per_s": round(f32["pushes_per_s_graph"], 1)},
@@ -255,8 +299,8 @@ def main():
         out["fp64"] = {"pushes_per_s": round(f64["pushes_per_s"], 1),
                        "ms_per_step": round(f64["ms_per_step"], 4),
                        "fused_avg_ms": round(f64["fused_ms"], 4),
-                       "fused_hbm_gbs": round(algorithmic_bytes_per_push(2, False, ppc_tot) *
-                                              wl.nparticles / (f64["fused_ms"] * 1e-3) / 1e9, 1),
+                       "fused_hbm_gbs": round(launch_bytes_of(False) /
+                                              (f64["fused_ms"] * 1e-3) / 1e9, 1),
                        "graph_pushes_per_s": None if args.no_graph else
                        round(f64["pushes_per_s_graph"], 1),
                        "fp32_over_fp64": round(f32["pushes_per_s"] / f64["pushes_per_s"], 3),

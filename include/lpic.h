@@ -125,8 +125,8 @@ typedef struct {
 /* Tiling used by the sort and the fused particle kernel.  Tile edges are powers of two;
  * the field tile staged in on-chip memory is the tile plus `halo` cells on each side, and
  * a tile's particles are processed in chunks of at most `chunk` particles per workgroup.
- * A particle's gather and deposit touch cells up to 3 below and 4 above its cell, so with
- * halo h a particle may drift h - 3 cells below and h - 4 cells above its tile since the
+ * A particle's gather and deposit touch cells up to 2 below and 3 above its cell, so with
+ * halo h a particle may drift h - 2 cells below and h - 3 cells above its tile since the
  * last sort and stay on chip; particles beyond that are still handled exactly, through
  * global memory (counted in lpic_stats.halo_escapes).  halo must be >= 3.
  * flags: LPIC_SORT_SPREAD makes every sort spread each tile's particles over the tile's

@@ -620,6 +620,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   }
 }
 
+
 // ---------------------------------------------------------------------------------------
 // Particle state in (cell, offset) form.
 // ---------------------------------------------------------------------------------------

@@ -18,7 +18,7 @@ namespace lpic {
 struct GeoFix { int tx, ty, tz, halo; };
 __host__ __device__ constexpr GeoFix geo_table(int g) {
   return g == 1 ? GeoFix{16, 16, 1, 5} : g == 2 ? GeoFix{8, 8, 1, 5} : g == 3 ? GeoFix{32, 32, 1, 5}
-       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 8, 8, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
+       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
        : GeoFix{0, 0, 0, 0};
 }
 constexpr int NUM_GEO = 7;
@@ -123,7 +123,7 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 }
 
 // The particles of one chunk against the staged region, in rounds: each thread first
-// issues the loads of BATCH particles (256 apart, so every load instruction reads 64
+// issues the loads of BATCH particles (a workgroup apart, so every load instruction reads 64
 // consecutive particles) and then pushes them one by one, so HBM latency is paid once per
 // round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
 constexpr int BATCH = 4;
@@ -131,6 +131,11 @@ constexpr int BATCH = 4;
 // a few spills, measured faster than 3 waves without); the others keep the compiler's choice.
 template <typename R, int DIM>
 constexpr int fused_waves() { return (sizeof(R) == 4 && DIM == 2) ? 4 : 1; }
+
+// Threads per workgroup: a 3D region (tile + halo on three axes) fills most of a CU's LDS,
+// so one workgroup per CU must bring enough waves by itself.
+template <int DIM>
+constexpr int fused_block() { return DIM == 2 ? 256 : 512; }
 
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
@@ -159,11 +164,14 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         if (d < DIM) {
-          // local start cell; gather and deposit touch cells [a-3, a+4] per axis
+          // local start cell a; gather and deposit touch cells [a-2, a+3] per axis: with
+          // dt at most the CFL step the half push moves < 0.36 cells and the deposit path
+          // < 0.71 cells, which bounds both the half-step cell (a-1..a+1) and, jointly with
+          // it, the 4-node Esirkepov window
           int v = ps[b].c[d] - g.r0[d];
           v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
           a[d] = v;
-          inside = inside && v >= 3 && v <= g.rw[d] - 5;
+          inside = inside && v >= 2 && v <= g.rw[d] - 4;
         } else {
           a[d] = 0;
         }
@@ -206,12 +214,12 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 // the other species of the same box, which follow in the table) reuse the staged region;
 // the region is flushed when the tile changes.
 template <typename R, int DIM, int G>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
+__global__ __launch_bounds__(fused_block<DIM>()) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
                                                EscapeList esc, const int32_t* jshift) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[4];
+  __shared__ double red[fused_block<DIM>() / 64];
   R* sm = (R*)smem_raw;
   const int nch = uniform(*nchunks);
   const int nb8 = gridDim.x >> 3;
@@ -356,7 +364,7 @@ template <typename R, int D, int G>
 static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
                            const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
                            const EscapeList& esc, const int32_t* jshift, hipStream_t st) {
-  k_fused<R, D, G><<<nblocks, 256, smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
+  k_fused<R, D, G><<<nblocks, fused_block<D>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
                                                ke_to_diag, esc, jshift);
 }
 
@@ -399,7 +407,8 @@ static hipError_t set_smem(size_t smem, size_t smem_occ, int* blocks_per_cu) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fused<R, D, G>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>, 256,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>,
+                                                      fused_block<D>(),
                                                       smem_occ);
 }
 
@@ -427,8 +436,10 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
 
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
   const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
-  // six field planes in the kernel precision (padded to 8 bytes), then FP64 current planes
-  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * (3 + (with_rho ? 2 : 0)) * 8;
+  // six field planes in the kernel precision (padded to 8 bytes), then 8-byte current
+  // planes (and, on diagnostic steps, two charge planes)
+  const int jplanes = 3 + (with_rho ? 2 : 0);
+  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * jplanes * 8;
 }
 
 }  // namespace lpic

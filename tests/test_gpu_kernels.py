@@ -328,3 +328,54 @@ def test_fused_covers_every_chunk(prec, n):
     orc.push_deposit(o)
     compare_particles(grid, cur, o, prec, what="fused push")
     compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"), what="fused deposit")
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PNAME.get)
+@pytest.mark.parametrize("ndim,order", [(2, 1), (2, 2), (3, 2)])
+@pytest.mark.parametrize("halo", [3, 4])
+def test_fused_window_edges(prec, ndim, order, halo):
+    """Particles moved after the sort to the farthest cells that still count as on chip
+    (h - 2 below their tile, h - 3 above it), moving outwards at 0.99 c along every axis at
+    once: their gather and deposit windows reach the edges of the staged region, and the
+    results must equal the oracle's."""
+    banner(f"fused window edges prec={PNAME[prec]} ndim={ndim} order={order} halo={halo}")
+    if prec == L.F64_ABS and ndim == 3 and halo == 4:
+        pytest.skip("FP64 3D region with halo 4 does not fit the LDS at this tile")
+    wl = small_2d(order) if ndim == 2 else small_3d(order)
+    T = (16, 8, 1) if ndim == 2 else (8, 4, 4)
+    tiling = L.Tiling(*T, halo, 61, 0)
+    grid, F, d0, cur, offs, orc = _sorted_state(wl, prec, tiling)
+    o = orc.species[0]
+    pos = cur.positions(grid)
+    h = (grid.dx, grid.dy, grid.dz)
+    n = (grid.nx, grid.ny, grid.nz)
+    rng = np.random.default_rng(7)
+    side = rng.integers(0, 2, (ndim, cur.n))            # 0: low edge, 1: high edge, per axis
+    new, u = [], []
+    for a in range(ndim):
+        cell = np.floor(pos[a] / h[a]).astype(np.int64)
+        t0 = (cell // T[a]) * T[a]                        # the home tile's first cell
+        lo = t0 - (halo - 2)
+        hi = t0 + T[a] - 1 + (halo - 3)
+        c = np.where(side[a] == 0, lo, hi)
+        frac = np.where(side[a] == 0, 0.01, 0.99)
+        new.append(np.mod((c + frac) * h[a], n[a] * h[a]))
+        u.append(np.where(side[a] == 0, -7.0, 7.0))
+    cur.load_positions(grid, *new, *([None] * (3 - ndim)))
+    for a, k in enumerate(("ux", "uy", "uz")[:ndim]):
+        cur.a[k].copy_(torch.from_numpy(u[a]).to(cur.a[k].dtype))
+    pos = cur.positions(grid)
+    o.x[:], o.y[:] = pos[0], pos[1]
+    if ndim == 3:
+        o.z[:] = pos[2]
+    for k in ("ux", "uy", "uz", "w"):
+        getattr(o, k)[:] = cur.numpy(k)
+    wsb = L.lpic_fused_ws_bytes(grid, tiling, cur.n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    L.lpic_push_deposit_fused(grid, F.struct(), cur.struct(), tiling, offs.data_ptr(),
+                              ws.data_ptr(), wsb, 1, None, prec)
+    torch.cuda.synchronize()
+    orc.zero_currents()
+    orc.push_deposit(o)
+    compare_particles(grid, cur, o, prec, what="edge push")
+    compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"), what="edge deposit")
