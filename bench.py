@@ -244,7 +244,7 @@ def main():
     if args.halo is None:
         args.halo = 5 if ndim == 2 else 4
     if args.sort_interval is None:
-        args.sort_interval = 10 if ndim == 2 else 5
+        args.sort_interval = 20   # the sort interval the 3D thermal configuration fixes
     nparticles = sum(w.nparticles for w in wl)
     f32 = run_gpu(wl, L.F32_CELLOFS, args, args.steps, args.warmup, args.autotune)
     f64 = None
