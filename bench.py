@@ -136,7 +136,10 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     t1 = time.perf_counter()
     st = sim.stats()
     sim.set_timing(False)
-    # the same number of steps again as captured graphs (no per-kernel events)
+    # the same number of steps again as captured graphs (no per-kernel events), after one
+    # untimed sort period in graph mode so that every step variant is already captured
+    if not args.no_graph:
+        sim.step(max(args.sort_interval, 10) + 2)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     if not args.no_graph:
