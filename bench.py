@@ -12,8 +12,8 @@ sin^2 envelope of 25 lambda / c) injected by an antenna 4 cells from the open le
 (absorbing) x ends, periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
 the plain FP64 path is reported beside it.
 
-Output: one JSON line (rank 0).  With --gpus > 1 the script exits: this build measures one
-GPU.
+Output: one JSON line.  The benchmark runs on one GPU; with --gpus > 1 it exits (the
+multi-GPU decomposition is a design, not implemented).
 """
 from __future__ import annotations
 
@@ -231,7 +231,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is a design, not implemented", file=sys.stderr)
         sys.exit(2)
 
     from paper_2607_13507_amd import lpic as L
