@@ -208,7 +208,7 @@ lpic_status lpic_sort_tiles(const lpic_grid *grid, lpic_species *sp, lpic_specie
  * since left their tile are still handled exactly.  with_rho as in the deposit.
  * FP32: a tile's current is summed on chip in signed 64-bit fixed point, 2^-S per unit,
  * with S chosen per call from the particle count and the largest |q w| so that no sum can
- * overflow (S = 38 for 16.8M particles of |q w| ~ 0.6 and dx/dt ~ 1.5); the flush rounds
+ * overflow (S = 36 for 16.8M particles of |q w| ~ 0.6 and dx/dt ~ 1.5); the flush rounds
  * to FP32 once.  Such sums do not depend on the order of the adds.
  * kinetic (device double, may be NULL): adds sum w m u^2/(1+gamma) over the pushed
  * particles (new momenta, not multiplied by the cell volume).
@@ -302,7 +302,9 @@ typedef struct {
 
 /* Create a simulation over nruns independent boxes.  species[s] belongs to box
  * species_run[s]; species_alt[s] holds same-sized arrays used as the sort's second buffer.
- * fields[r].rho0/rho1 must be non-NULL when diagnostics are on.  All arrays stay owned by
+ * fields[r].rho0/rho1 must be non-NULL when diagnostics are on; they hold the charge of the
+ * latest diagnostic step (steps without diagnostics neither write nor clear them).  All
+ * arrays stay owned by
  * the caller and must outlive the simulation; the library allocates only its own scratch
  * (sort workspace, tile and chunk tables, diagnostics) and frees it in lpic_sim_destroy. */
 lpic_status lpic_sim_create(lpic_sim **out, int32_t nruns, const lpic_grid *grids,

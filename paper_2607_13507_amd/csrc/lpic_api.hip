@@ -781,7 +781,8 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     CHK(last_launch("diag clear"));
   }
   // field half update t -> t + dt/2 (E first), clearing J for the deposit
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, 1,
+  // (the charge arrays are only written, and so only cleared, on diagnostic steps)
+  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, diag ? 1 : 2,
              first_full ? 2 : 1, st);
   CHK(last_launch("yee E"));
   launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);

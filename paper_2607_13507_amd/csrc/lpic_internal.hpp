@@ -20,7 +20,7 @@ namespace lpic {
 
 constexpr int SORT_BLOCK = 2048;   // particles per workgroup of the sort kernels
 
-// which = 0: E update (zero_j also clears J and rho), 1: B update.  halves = 2: the E
+// which = 0: E update (zero_j = 1 also clears J and rho, 2 J only), 1: B update.  halves = 2: the E
 // update stands for two equal half updates (open x ends apply their condition twice).
 void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, double frac,
                 int zero_j, int halves, hipStream_t st);

@@ -122,12 +122,12 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
     f[F_EY][x.c] += dey;
     f[F_EZ][x.c] += dez;
   }
-  if (zero_j) {
+  if (zero_j) {   // 1: clear J (and the charge arrays when given); 2: J only
     f[F_JX][x.c] = R(0);
     f[F_JY][x.c] = R(0);
     f[F_JZ][x.c] = R(0);
-    if (f[F_R0]) f[F_R0][x.c] = R(0);
-    if (f[F_R1]) f[F_R1][x.c] = R(0);
+    if (zero_j == 1 && f[F_R0]) f[F_R0][x.c] = R(0);
+    if (zero_j == 1 && f[F_R1]) f[F_R1][x.c] = R(0);
   }
 }
 
