@@ -171,3 +171,26 @@ def test_antenna_pulse_leaves_through_the_open_end():
     final = sim.diagnostics(0)["field_energy"]
     assert peak > 1.0 and final < 2e-3 * peak, (peak, final)
     sim.close()
+
+
+def test_laser_attached_after_some_steps_keeps_the_clock():
+    """An antenna attached after steps without one starts from the simulation's clock
+    (t = (step + 1) dt), eager and graph replay alike."""
+    banner("laser attached late")
+    for graph in (False, True):
+        wl = _open_laser_box(2, 2, seed=23)
+        las = wl.laser
+        wl.laser = None
+        sim = Simulation(wl, prec=L.F64_ABS, tiling=(8, 8, 1), halo=4, chunk=128,
+                         sort_interval=4, diag_interval=0, use_graph=graph)
+        orc = _oracle_like(sim, wl)
+        sim.step(5)
+        orc.step(5)
+        sim.set_laser(0, dict(las, t0=0.2))
+        orc.laser = Laser(**dict(las, t0=0.2))
+        sim.step(7)
+        orc.step(7)
+        torch.cuda.synchronize()
+        compare_fields(sim.fields[0], orc, L.F64_ABS, tol=1e-10, what=f"graph={graph}")
+        assert orc.field_energy() > 0.01
+        sim.close()
