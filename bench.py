@@ -263,11 +263,19 @@ def main():
     bpp = launch_bytes / nparticles
     achieved = launch_bytes / (f32["fused_ms"] * 1e-3) / 1e9
     traffic = read_traffic() if args.workload == "laser_slab" else None
+    valu = read_traffic("valu_insts_per_launch") if args.workload == "laser_slab" else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=f"lpic::k_fused<float,{ndim}>", bytes_per_push=round(bpp, 3),
                 bytes_per_launch=int(launch_bytes), avg_launch_ms=round(f32["fused_ms"], 4),
                 launches=f32["fused_launches"], kernel_source_sha256=kernel_source_hash())
+    if valu:
+        # the unit that binds this kernel: VALU issue.  A wave64 VALU instruction occupies a
+        # SIMD for 4 cycles; 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions/s
+        rate = valu / (f32["fused_ms"] * 1e-3)
+        roof["valu_issue"] = dict(insts_per_launch=int(valu), achieved=round(rate / 1e9, 1),
+                                  peak=614.4, unit="G wave-instructions/s",
+                                  frac=round(rate / 614.4e9, 4))
     cpu = None
     if not args.no_cpu_baseline and args.workload == "laser_slab":
         cpu = cpu_baseline(wl[0])

@@ -131,13 +131,18 @@ typedef struct {
  * global memory (counted in lpic_stats.halo_escapes).  halo must be >= 3.
  * flags: LPIC_SORT_SPREAD makes every sort spread each tile's particles over the tile's
  * range (see lpic_sort_tiles); without it only a simulation's first sort after particles
- * are loaded does. */
+ * are loaded does.  LPIC_FIELD_SEPARATE (lpic_step in 2D): run the three field updates
+ * between two particle pushes of consecutive steps (B by dt/2, E by dt, B by dt/2; Sec. 3.3,
+ * Algorithm 1) as three grid-wide kernels; without it they run as one kernel over field
+ * tiles of up to 64 x 16 cells whenever every box's nx and ny are multiples of a tile edge
+ * (>= 8 and >= 4), which computes the same values with one pass over the arrays. */
 #define LPIC_SORT_SPREAD 1
+#define LPIC_FIELD_SEPARATE 2
 typedef struct {
   int32_t tx, ty, tz;        /* tz ignored in 2D */
   int32_t halo;
   int32_t chunk;
-  int32_t flags;             /* 0 or LPIC_SORT_SPREAD; other bits must be 0 */
+  int32_t flags;             /* LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE; other bits must be 0 */
 } lpic_tiling;
 
 /* ---------------------------------------------------------------------------------------
@@ -298,6 +303,9 @@ typedef struct {
   int64_t fused_launches;    /* launches covered by fused_ms */
   int64_t halo_escapes;      /* particle pushes that left their tile's on-chip halo and went
                                 through global memory (cumulative) */
+  int32_t field_tile[2];     /* tile (x, y) of the fused field update between steps; 0 0 when
+                                those updates run as separate kernels (3D, LPIC_FIELD_SEPARATE,
+                                or no tile edge divides every box) */
 } lpic_stats;
 
 /* Create a simulation over nruns independent boxes.  species[s] belongs to box
@@ -337,7 +345,9 @@ lpic_status lpic_set_timing(lpic_sim *sim, int32_t on);
 lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
 /* Attach a laser antenna to run r (laser = NULL removes it).  Every step then adds the
  * antenna current at t = (step + 1) dt after the particles' deposit (before the
- * CURRENT_DEPOSITION hooks), where step counts the steps taken so far. */
+ * CURRENT_DEPOSITION hooks), where step counts the steps taken so far.  (A step whose
+ * field updates are fused with the next step's -- see LPIC_FIELD_SEPARATE -- adds it inside
+ * the E update instead of to the J array; J is cleared before anything else reads it.) */
 lpic_status lpic_set_laser(lpic_sim *sim, int32_t r, const lpic_laser *laser);
 /* Try the listed candidate options for `steps_each` steps each (the simulation really
  * advances), keep the fastest; writes the winner into *best when non-NULL. */

@@ -125,7 +125,8 @@ lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec,
   if (t->halo > g->nx || t->halo > g->ny || (nd == 3 && t->halo > g->nz))
     return fail(LPIC_EINVAL, "halo larger than the grid");
   if (t->chunk < 1) return fail(LPIC_EINVAL, "chunk must be >= 1");
-  if (t->flags & ~LPIC_SORT_SPREAD) return fail(LPIC_EINVAL, "unknown tiling flags 0x%x", t->flags);
+  if (t->flags & ~(LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE))
+    return fail(LPIC_EINVAL, "unknown tiling flags 0x%x", t->flags);
   const size_t smem = fused_smem_bytes(prec, nd, t->tx, t->ty, nd == 3 ? t->tz : 1, t->halo, 1);
   if (need_lds && smem > 160 * 1024)
     return fail(LPIC_EINVAL, "tile + halo needs %zu bytes of LDS (limit 163840)", smem);
@@ -570,6 +571,11 @@ struct lpic_sim {
   int64_t esc_capacity = 0;
   int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
   int blocks_per_cu_rho = 1;
+  // fused 2D field update between steps (launch_yee_mid); mid_tx == 0: not in use
+  int mid_tx = 0, mid_ty = 0, mid_ntiles = 0;
+  int32_t* mid_pfx_d = nullptr;              // nruns + 1 prefix of field tiles
+  void* bands = nullptr;                     // two edge snapshots
+  int64_t band_half = 0;                     // values per snapshot
   void* old_state = nullptr;
   std::vector<size_t> old_off;
   std::vector<HookEntry> hooks[LPIC_NUM_STAGES];
@@ -577,11 +583,10 @@ struct lpic_sim {
   int64_t step = 0, sorts = 0, diag_step = -1;
   bool need_sort = true;
   bool need_spread = true;   // the first sort after particles are loaded spreads tiles
-  // graphs indexed by (sort, diag)
-  // captured steps keyed by (sort, diagnostics, full first E update, last E half deferred)
+  // captured steps keyed by (sort, diagnostics, first field updates already done by the
+  // previous step, last field updates merged into the next step's)
   static constexpr int NGRAPHS = 16;
   hipGraphExec_t gexec[NGRAPHS] = {};
-  bool gparity[4] = {false, false, false, false};
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
@@ -733,6 +738,33 @@ lpic_status configure(lpic_sim* s) {
     HIPCHK(hipMemset(s->step_dev, 0, 256));
   }
   HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
+  // fused 2D field update between steps: the largest field tile dividing every box
+  free_dev(s->mid_pfx_d);
+  free_dev(s->bands);
+  s->mid_pfx_d = nullptr;
+  s->bands = nullptr;
+  s->mid_tx = s->mid_ty = s->mid_ntiles = 0;
+  s->band_half = 0;
+  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE)) {
+    int tx = MID_MAX_TX, ty = MID_MAX_TY;
+    for (int r = 0; r < s->nruns; ++r) {
+      while (tx >= 8 && s->grids[r].nx % tx) tx >>= 1;
+      while (ty >= 4 && s->grids[r].ny % ty) ty >>= 1;
+    }
+    if (tx >= 8 && ty >= 4) {
+      std::vector<int32_t> pfx(1, 0);
+      for (int r = 0; r < s->nruns; ++r)
+        pfx.push_back(pfx.back() + (s->grids[r].nx / tx) * (s->grids[r].ny / ty));
+      s->band_half = (int64_t)pfx.back() * band_values_per_tile(tx, ty);
+      ALLOC(s->mid_pfx_d, sizeof(int32_t) * pfx.size());
+      ALLOC(s->bands, 2 * (size_t)s->band_half * (s->prec == LPIC_F32_CELLOFS ? 4 : 8));
+      HIPCHK(hipMemcpy(s->mid_pfx_d, pfx.data(), sizeof(int32_t) * pfx.size(),
+                       hipMemcpyHostToDevice));
+      s->mid_tx = tx;
+      s->mid_ty = ty;
+      s->mid_ntiles = pfx.back();
+    }
+  }
   if (!s->wmax) {
     ALLOC(s->wmax, sizeof(unsigned long long) * fixed_shift_slots() * std::max(1, s->nsegs));
     ALLOC(s->jshift, sizeof(int32_t) * std::max(1, s->nruns));
@@ -767,26 +799,61 @@ lpic_status enqueue_fixed_shift(lpic_sim* s, hipStream_t st) {
   return last_launch("fixed-point shift");
 }
 
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// The edge snapshots of the fused 2D field update; the parity word sits in the device step
+// block.
+FieldBands sim_bands(const lpic_sim* s) {
+  FieldBands b;
+  memset(&b, 0, sizeof(b));
+  b.base = s->bands;
+  b.half = s->band_half;
+  b.tile_pfx = s->mid_pfx_d;
+  b.parity = (int32_t*)((char*)s->step_dev + 128);
+  b.step = s->laser_bpr > 0 ? s->step_dev : nullptr;
+  b.tx = s->mid_tx;
+  b.ty = s->mid_ty;
+  b.lx = log2i(s->mid_tx);
+  b.ly = log2i(s->mid_ty);
+  return b;
+}
+
 // The device work of one step between the LOOP_START and LOOP_END hooks.  With hooks at the
 // inner stages the host runs them in between (eager mode only).
 // first_full: the previous step deferred its last E half (skip_last), so this step's first
 // E update covers both halves at once: between them B does not change and J is the same
-// array, so E + (dt/2)(curl B - J) twice is E + dt (curl B - J).
+// array, so E + (dt/2)(curl B - J) twice is E + dt (curl B - J).  With the fused 2D field
+// update the previous step already did all of it (its B half, this full E update and this
+// step's first B half), and this step only clears the sources.
 lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread, bool diag,
                          bool eager_hooks, bool capturing, bool first_full, bool skip_last) {
   const Tables Tc = sim_tables(s, nullptr);
   const Tables Ts = sim_tables(s, s->seg_blk_sort_d);
+  const bool mid = s->mid_tx > 0;
+  const FieldBands bands = mid ? sim_bands(s) : FieldBands{};
   if (diag) {
     launch_diag_clear(Tc, s->nruns, st);
     CHK(last_launch("diag clear"));
   }
-  // field half update t -> t + dt/2 (E first), clearing J for the deposit
   // (the charge arrays are only written, and so only cleared, on diagnostic steps)
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, diag ? 1 : 2,
-             first_full ? 2 : 1, st);
-  CHK(last_launch("yee E"));
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);
-  CHK(last_launch("yee B"));
+  if (first_full && mid) {
+    launch_clear_sources(Tc, s->prec, s->ndim, s->nblk_cells, diag ? 1 : 0, bands.parity,
+                         s->laser_bpr > 0 ? s->step_dev : nullptr, st);
+    CHK(last_launch("clear sources"));
+  } else {
+    // field half update t -> t + dt/2 (E first), clearing J for the deposit
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, diag ? 1 : 2,
+               first_full ? 2 : 1, st);
+    CHK(last_launch("yee E"));
+    // a step whose last field updates go to the fused update publishes the tile edges
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st,
+               (mid && skip_last) ? &bands : nullptr);
+    CHK(last_launch("yee B"));
+  }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_1));
   // sort particles (every sort_interval steps)
   if (do_sort && s->nsegs > 0) {
@@ -860,18 +927,27 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       }
     }
   }
-  if (s->laser_bpr > 0) {   // antenna current at t = (step + 1) dt
+  if (s->laser_bpr > 0 && !(skip_last && mid)) {   // antenna current at t = (step + 1) dt
+    // (a fused field update adds it itself)
     launch_laser(Tc, s->prec, s->ndim, s->nruns, s->laser_bpr, 0.0, s->step_dev, s->laser_done,
                  st);
     CHK(last_launch("laser"));
   }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_CURRENT_DEPOSITION));
-  // field half update t + dt/2 -> t + dt (B first)
-  launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);
-  CHK(last_launch("yee B"));
-  if (!skip_last) {
-    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, 1, st);
-    CHK(last_launch("yee E"));
+  if (skip_last && mid) {
+    // this step's last field halves and the next step's first ones, fused
+    Tables Tm = Tc;
+    Tm.run_blk = s->mid_pfx_d;
+    launch_yee_mid(Tm, s->prec, s->mid_ntiles, bands, st);
+    CHK(last_launch("yee fused"));
+  } else {
+    // field half update t + dt/2 -> t + dt (B first)
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 1, 0.5, 0, 1, st);
+    CHK(last_launch("yee B"));
+    if (!skip_last) {
+      launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, 0.5, 0, 1, st);
+      CHK(last_launch("yee E"));
+    }
   }
   if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_MAXWELL_2));
   if (diag) {
@@ -975,6 +1051,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
   free_dev(s->esc_items); free_dev(s->esc_count);
   free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
+  free_dev(s->mid_pfx_d); free_dev(s->bands);
   free_dev(s->old_state);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
@@ -1080,6 +1157,8 @@ lpic_status lpic_get_stats(lpic_sim* s, lpic_stats* out) {
   HIPCHK(hipStreamSynchronize(s->stream));
   HIPCHK(hipMemcpy(&esc, s->escapes, sizeof(esc), hipMemcpyDeviceToHost));
   out->halo_escapes = (int64_t)esc;
+  out->field_tile[0] = s->mid_tx;
+  out->field_tile[1] = s->mid_ty;
   return LPIC_OK;
 }
 

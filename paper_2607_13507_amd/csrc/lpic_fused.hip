@@ -336,9 +336,10 @@ __global__ __launch_bounds__(256) void k_escape(Tables T, int with_rho, double* 
                                    : escape_one<R, DIM, 2>(r, s, p, with_rho);
     if (kinetic || ke_to_diag) atomic_add_global(ke_to_diag ? r.diag + DIAG_UKIN : kinetic, ke);
   }
+  // the last workgroup to finish clears the list (every workgroup has read the count by
+  // then; no fence: nothing this launch wrote is read before the launch ends)
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned int done = atomicAdd(esc.count + 1, 1u);
     if (done == gridDim.x - 1) {
       atomicAdd(esc.total, (unsigned long long)esc.count[0]);

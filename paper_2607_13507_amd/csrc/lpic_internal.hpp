@@ -20,10 +20,45 @@ namespace lpic {
 
 constexpr int SORT_BLOCK = 2048;   // particles per workgroup of the sort kernels
 
+// Snapshot of the tile edges for the fused 2D field update (launch_yee_mid): the domain is
+// cut into field tiles of tx x ty cells, and every tile publishes, per field component
+// (Ex Ey Ez Bx By Bz), the values of its first two and its last column (3 ty values) and
+// of its first two and its last row (3 tx values).  Two buffers of `half` values: the
+// word *parity names the one holding the present fields.
+struct FieldBands {
+  void* base;
+  int64_t half;
+  const int32_t* tile_pfx;     // nruns + 1 prefix of field tiles (one workgroup per tile)
+  int32_t* parity;
+  const int64_t* step;         // antenna clock (steps taken); NULL: no run has an antenna
+  int32_t tx, ty;              // powers of two, tx <= MID_MAX_TX, ty <= MID_MAX_TY
+  int32_t lx, ly;              // their log2
+};
+constexpr int MID_MAX_TX = 64, MID_MAX_TY = 16;
+inline int64_t band_values_per_tile(int tx, int ty) { return 6 * 3 * (int64_t)(tx + ty); }
+
 // which = 0: E update (zero_j = 1 also clears J and rho, 2 J only), 1: B update.  halves = 2: the E
 // update stands for two equal half updates (open x ends apply their condition twice).
+// bands (B update in 2D only, may be NULL): also publish E and the new B of the tile edges
+// into the snapshot buffer named by *parity, for a fused update that follows.
 void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, double frac,
-                int zero_j, int halves, hipStream_t st);
+                int zero_j, int halves, hipStream_t st, const FieldBands* bands = nullptr);
+// The three field updates between two particle pushes of 2D steps, fused: B by dt/2, E by
+// dt (two merged halves, with the J in place), B by dt/2 -- the last half update of one
+// step and the first two of the next.  T.run_blk must be the tile prefix (one workgroup
+// per field tile).  Reads the snapshot named by *parity and writes the other one; J is
+// only read.  Runs with an antenna get its current of this step (t = (*step + 1) dt) added
+// in the E update instead of through the array, so the antenna kernel is not launched for
+// the step.  The next launch on the stream must be launch_clear_sources with
+// flip = bands.parity and clock = bands.step: it clears J for the next deposit, names the
+// new snapshot and advances the antenna clock.
+void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands,
+                    hipStream_t st);
+// J := 0 (and the charge arrays when with_rho) over every cell of every run (nblocks: the
+// 256-cell blocks of T.run_blk).  flip != NULL: also *flip ^= 1 and, clock != NULL,
+// *clock += 1 (one thread).
+void launch_clear_sources(const Tables& T, int prec, int dim, int nblocks, int with_rho,
+                          int32_t* flip, int64_t* clock, hipStream_t st);
 // Laser antennas of the runs that have one (bpr workgroups of 256 (j, k) cells per run).
 // step != NULL: t = (*step + 1) dt, and the launch advances *step (done: a zeroed counter).
 void launch_laser(const Tables& T, int prec, int dim, int nruns, int bpr, double t,

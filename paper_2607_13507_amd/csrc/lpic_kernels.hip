@@ -2,6 +2,8 @@
 // dense contraction.  The particle stream is structure-of-arrays and read/written once per
 // step with unit stride; field tiles are staged in LDS for the gather and the current of a
 // tile is accumulated in LDS, then flushed with one global atomic per non-zero cell.
+#include <cstring>
+
 #include "lpic_internal.hpp"
 
 namespace lpic {
@@ -131,10 +133,58 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   }
 }
 
+// Antenna current on node (j, k) of column ia at time t (the current component is Jy for
+// pol 1, Jz for pol 2); false outside the pulse envelope.
+template <int DIM>
+__device__ __forceinline__ bool antenna_current(const RunDesc& r, double t_abs, int j, int k,
+                                                double& jant) {
+  const LaserDesc& L = r.laser;
+  const double t = t_abs - L.t0;
+  if (!(t >= 0.0 && t <= L.tau)) return false;
+  const double y = (j + (L.pol == 1 ? 0.5 : 0.0)) * r.dy;
+  const double z = DIM == 3 ? (k + (L.pol == 2 ? 0.5 : 0.0)) * r.dz : L.zc;
+  const double env = sin(M_PI * t / L.tau);
+  const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
+  const double einc = L.e0 * env * env * sin(L.omega * t) * exp(-r2 / (L.waist * L.waist));
+  jant = -2.0 * einc / r.dx;
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile-edge snapshot of the fused 2D field update (FieldBands).  Cell (i, j) of a run lies
+// in field tile (i >> lx, j >> ly) at (li, lj); the tile's slice of component k starts at
+// ((tile0 + tile) * 6 + k) * 3 (tx + ty) and holds columns li = 0, 1, tx-1 (ty values
+// each), then rows lj = 0, 1, ty-1 (tx values each).  A corner cell is in both.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int band_col(int li, int tx) { return li <= 1 ? li : (li == tx - 1 ? 2 : -1); }
+
+// Snapshot index of cell (i, j), component k; the cell must lie on an edge band.
+__device__ __forceinline__ int64_t band_at(const FieldBands& Bd, int ntx, int64_t tile0, int i,
+                                          int j, int k) {
+  const int ti = i >> Bd.lx, tj = j >> Bd.ly;
+  const int li = i - (ti << Bd.lx), lj = j - (tj << Bd.ly);
+  const int64_t base = ((tile0 + (int64_t)tj * ntx + ti) * 6 + k) * (3 * (Bd.tx + Bd.ty));
+  const int cb = band_col(li, Bd.tx);
+  if (cb >= 0) return base + cb * Bd.ty + lj;
+  return base + 3 * Bd.ty + band_col(lj, Bd.ty) * Bd.tx + li;
+}
+
+// Publishes value v of a cell at (li, lj) of a tile whose slice of component 0 starts at
+// `base` (stride 3 (tx + ty) per component).
+template <typename R>
+__device__ __forceinline__ void band_put(R* out, const FieldBands& Bd, int64_t base, int li,
+                                         int lj, int k, R v) {
+  const int64_t b = base + (int64_t)k * (3 * (Bd.tx + Bd.ty));
+  const int cb = band_col(li, Bd.tx), rb = band_col(lj, Bd.ty);
+  if (cb >= 0) out[b + cb * Bd.ty + lj] = v;
+  if (rb >= 0) out[b + 3 * Bd.ty + rb * Bd.tx + li] = v;
+}
+
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac) {
+__global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac, FieldBands Bd) {
   int blk;
-  const RunDesc& r = run_of(T, cell_block(T, blk));
+  const int ri = cell_block(T, blk);
+  const RunDesc& r = run_of(T, ri);
   CellIdx x;
   if (!cell_index(r, blk, DIM, x)) return;
   gptr<R> f[F_NUM];
@@ -144,16 +194,350 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac) {
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0);
   R dbx, dby, dbz;
   yee_b_delta<R, DIM>(f, x, hx, hy, hz, dbx, dby, dbz);
-  f[F_BX][x.c] += dbx;
-  if (r.open_x && x.i == r.nx - 2) {   // Mur for column nx-1 (same j, k)
+  const R bx = f[F_BX][x.c] + dbx;
+  f[F_BX][x.c] = bx;
+  const bool edge_in = r.open_x && x.i == r.nx - 2;
+  const bool edge = r.open_x && x.i == r.nx - 1;
+  R by_e = R(0), bz_e = R(0);
+  if (edge_in) {   // Mur for column nx-1 (same j, k)
     const R by1 = f[F_BY][x.c], bz1 = f[F_BZ][x.c];
-    f[F_BY][x.cip] = mur_edge<R>(f[F_BY][x.cip], by1, dby, h, r.dx, 1);
-    f[F_BZ][x.cip] = mur_edge<R>(f[F_BZ][x.cip], bz1, dbz, h, r.dx, 1);
+    by_e = mur_edge<R>(f[F_BY][x.cip], by1, dby, h, r.dx, 1);
+    bz_e = mur_edge<R>(f[F_BZ][x.cip], bz1, dbz, h, r.dx, 1);
+    f[F_BY][x.cip] = by_e;
+    f[F_BZ][x.cip] = bz_e;
   }
-  if (!(r.open_x && x.i == r.nx - 1)) {   // last column of an open end: set by column nx-2
-    f[F_BY][x.c] += dby;
-    f[F_BZ][x.c] += dbz;
+  R by = R(0), bz = R(0);
+  if (!edge) {   // last column of an open end: set by column nx-2
+    by = f[F_BY][x.c] + dby;
+    bz = f[F_BZ][x.c] + dbz;
+    f[F_BY][x.c] = by;
+    f[F_BZ][x.c] = bz;
   }
+  if (DIM == 2 && Bd.base) {
+    const int j = (int)(x.c / r.nx);
+    const int ti = x.i >> Bd.lx, tj = j >> Bd.ly;
+    const int li = x.i - (ti << Bd.lx), lj = j - (tj << Bd.ly);
+    const int ntx = r.nx >> Bd.lx;
+    R* out = (R*)Bd.base + (int64_t)(*Bd.parity & 1) * Bd.half;
+    const int64_t base = (Bd.tile_pfx[ri] + (int64_t)tj * ntx + ti) * 6 * (3 * (Bd.tx + Bd.ty));
+    if (band_col(li, Bd.tx) >= 0 || band_col(lj, Bd.ty) >= 0) {
+      band_put(out, Bd, base, li, lj, 0, (R)f[F_EX][x.c]);
+      band_put(out, Bd, base, li, lj, 1, (R)f[F_EY][x.c]);
+      band_put(out, Bd, base, li, lj, 2, (R)f[F_EZ][x.c]);
+      band_put(out, Bd, base, li, lj, 3, bx);
+      if (!edge) {
+        band_put(out, Bd, base, li, lj, 4, by);
+        band_put(out, Bd, base, li, lj, 5, bz);
+      }
+    }
+    if (edge_in) {   // column nx-1: the last column of this thread's tile (tx divides nx)
+      band_put(out, Bd, base, li + 1, lj, 4, by_e);
+      band_put(out, Bd, base, li + 1, lj, 5, bz_e);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// The field updates between the particle pushes of two 2D steps in one pass per tile:
+// B += (dt/2) (-curl E), E += dt (curl B - J), B += (dt/2) (-curl E) -- the same arithmetic,
+// cell by cell, as k_yee_b, k_yee_e (two merged halves) and k_yee_b in sequence.  The output
+// tile [a, a+tx) x [c, c+ty) needs E on [a-1, a+tx+2) x [c-1, c+ty+2) and B on
+// [a-1, a+tx+1) x [c-1, c+ty+1); its own cells come from the field arrays, the others from
+// the neighbours' edge snapshot (never from the arrays, which the neighbours overwrite during
+// this launch).  Cells outside the output tile are recomputed redundantly.  With open x
+// ends, values computed for a wrapped image of column 0 or nx-1 only feed components that
+// the open-end condition replaces, so they are left as computed.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_once(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+// Cell h of the halo ring of a region (TX + 1 + HI) x (TY + 1 + HI) whose interior TX x TY
+// starts at (1, 1): first the 1 + HI full rows (v = 0, TY + 1, ..), then the 1 + HI columns
+// (u = 0, TX + 1, ..) of the interior rows.
+template <int TX, int TY, int HI>
+__device__ __forceinline__ void ring_cell(int h, int& u, int& v) {
+  constexpr int W = TX + 1 + HI;
+  if (h < (1 + HI) * W) {
+    const int r = h / W;
+    u = h - r * W;
+    v = r == 0 ? 0 : TY + r;
+  } else {
+    h -= (1 + HI) * W;
+    const int r = h / TY;
+    v = 1 + h - r * TY;
+    u = r == 0 ? 0 : TX + r;
+  }
+}
+
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
+  constexpr int EW = TX + 3, EH = TY + 3, BW = TX + 2, BH = TY + 2, NC = TX * TY;
+  constexpr int LX = Log2<TX>::v;
+  constexpr int PER = (NC + 255) / 256;                    // interior cells per thread
+  constexpr int ER = EW * EH - NC, BR = BW * BH - NC;      // halo rings of E and B
+  constexpr int JR = TX + TY + 1;                          // J outside the tile that E needs
+  constexpr int NER = (ER + 255) / 256, NBR = (BR + 255) / 256, NJR = (JR + 255) / 256;
+  static_assert(TX <= MID_MAX_TX && TY <= MID_MAX_TY, "field tile too large");
+  __shared__ R sE[3][EW * EH];
+  __shared__ R sB[3][BW * BH];
+  int blk;
+  const int ri = cell_block(T, blk);   // blk: tile of the run (T.run_blk is the tile prefix)
+  const RunDesc& r = run_of(T, ri);
+  const int nx = r.nx, ny = r.ny;
+  const int ntx = nx / TX;
+  const int tj = blk / ntx, ti = blk - tj * ntx;
+  const int a = ti * TX, c = tj * TY;
+  const int64_t tile0 = Bd.tile_pfx[ri];
+  const int cur = *Bd.parity & 1;
+  const R* bin = (const R*)Bd.base + (int64_t)cur * Bd.half;
+  R* bout = (R*)Bd.base + (int64_t)(cur ^ 1) * Bd.half;
+  gptr<R> f[F_NUM];
+#pragma unroll
+  for (int k = 0; k < F_NUM; ++k) f[k] = gp((R*)r.f[k]);
+  const int tid = threadIdx.x;
+  // the antenna current of this step where a run has one, added to J in the E update
+  // exactly as the antenna kernel would have added it to the array (that kernel does not
+  // run before a fused update; the clock advances in the launch that follows).  Column ia
+  // is local column u_ant of the E-update range [a, a + TX] (maybe as the wrapped image of
+  // column 0); it is computed first, per row, while nothing else is live.
+  __shared__ R sAnt[MID_MAX_TY + 2];
+  int u_ant = -1;
+  if (r.has_laser && Bd.step) {
+    const int ia = r.laser.ia;
+    const int ua = ia >= a && ia <= a + TX ? ia - a + 1 : (ia == 0 && a + TX == nx ? TX + 1 : -1);
+    double jant;
+    const double t_ant = (double)(*Bd.step + 1) * r.dt;
+    if (ua > 0 && antenna_current<2>(r, t_ant, 0, 0, jant)) {   // inside the envelope
+      u_ant = ua;
+      if (tid < TY + 1) {
+        antenna_current<2>(r, t_ant, wrap_once(c + tid, ny), 0, jant);
+        sAnt[1 + tid] = R(jant);
+      }
+    }
+  }
+  // every load of the workgroup is issued before the first is used: the tile's own E, B
+  // and J, the halo rings from the snapshot, and the J of the column and row past the tile
+  R e[PER][3], b[PER][3], jv[PER][3], er[NER][3], br[NBR][3], je[NJR][3];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC) {
+      const int64_t g = (int64_t)(c + (q >> LX)) * nx + a + (q & (TX - 1));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        e[p][k] = f[F_EX + k][g];
+        b[p][k] = f[F_BX + k][g];
+        jv[p][k] = f[F_JX + k][g];
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NER; ++p) {
+    const int h = tid + p * 256;
+    if (h < ER) {
+      int u, v;
+      ring_cell<TX, TY, 2>(h, u, v);
+      const int i = wrap_once(a - 1 + u, nx), j = wrap_once(c - 1 + v, ny);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) er[p][k] = bin[band_at(Bd, ntx, tile0, i, j, k)];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NBR; ++p) {
+    const int h = tid + p * 256;
+    if (h < BR) {
+      int u, v;
+      ring_cell<TX, TY, 1>(h, u, v);
+      const int i = wrap_once(a - 1 + u, nx), j = wrap_once(c - 1 + v, ny);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) br[p][k] = bin[band_at(Bd, ntx, tile0, i, j, 3 + k)];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NJR; ++p) {
+    const int h = tid + p * 256;
+    if (h < JR) {   // column u = TX + 1 (v = 1 .. TY + 1), then row v = TY + 1 (u = 1 .. TX)
+      const int u = h <= TY ? TX + 1 : h - TY, v = h <= TY ? 1 + h : TY + 1;
+      const int64_t g = (int64_t)wrap_once(c - 1 + v, ny) * nx + wrap_once(a - 1 + u, nx);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) je[p][k] = f[F_JX + k][g];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC) {
+      const int v = (q >> LX) + 1, u = (q & (TX - 1)) + 1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sE[k][v * EW + u] = e[p][k];
+        sB[k][v * BW + u] = b[p][k];
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NER; ++p) {
+    const int h = tid + p * 256;
+    if (h < ER) {
+      int u, v;
+      ring_cell<TX, TY, 2>(h, u, v);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sE[k][v * EW + u] = er[p][k];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NBR; ++p) {
+    const int h = tid + p * 256;
+    if (h < BR) {
+      int u, v;
+      ring_cell<TX, TY, 1>(h, u, v);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sB[k][v * BW + u] = br[p][k];
+    }
+  }
+  __syncthreads();
+  const double h1 = 0.5 * r.dt, h2 = r.dt;
+  const R hx1 = R(h1 / r.dx), hy1 = R(h1 / r.dy);
+  const R hx2 = R(h2 / r.dx), hy2 = R(h2 / r.dy), hh2 = R(h2);
+  const bool open = r.open_x != 0;
+  // 1. B half update on the whole B region (reads E only)
+  for (int q = tid; q < BW * BH; q += 256) {
+    const int v = q / BW, u = q - v * BW;
+    const int ie = v * EW + u, gu = a - 1 + u;
+    const R ex = sE[0][ie], ey = sE[1][ie], ez = sE[2][ie];
+    const R dbx = -hy1 * (sE[2][ie + EW] - ez);
+    const R dby = hx1 * (sE[2][ie + 1] - ez);
+    const R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+    sB[0][q] += dbx;
+    if (open && gu == nx - 2 && u + 1 < BW) {   // Mur for column nx-1
+      sB[1][q + 1] = mur_edge<R>(sB[1][q + 1], sB[1][q], dby, h1, r.dx, 1);
+      sB[2][q + 1] = mur_edge<R>(sB[2][q + 1], sB[2][q], dbz, h1, r.dx, 1);
+    }
+    if (!(open && gu == nx - 1 && u >= 1)) {
+      sB[1][q] += dby;
+      sB[2][q] += dbz;
+    }
+  }
+  __syncthreads();
+  // 2. E full update on [a, a+TX+1) x [c, c+TY+1) (reads B): the tile's cells with the J
+  // held by their threads, then the column and row past the tile
+  auto e_update = [&](int u, int v, R jx, R jy, R jz) {
+    const int ib = v * BW + u, ie = v * EW + u, gu = a - 1 + u;
+    if (u == u_ant) {
+      if (r.laser.pol == 1) jy += sAnt[v];
+      else jz += sAnt[v];
+    }
+    const R bx = sB[0][ib], by = sB[1][ib], bz = sB[2][ib];
+    const R dex = hy2 * (bz - sB[2][ib - BW]) - hh2 * jx;
+    const R dey = -hx2 * (bz - sB[2][ib - 1]) - hh2 * jy;
+    const R dez = hx2 * (by - sB[1][ib - 1]) - hy2 * (bx - sB[0][ib - BW]) - hh2 * jz;
+    sE[0][ie] += dex;
+    if (open && gu == 1 && u >= 2) {   // Mur for column 0
+      sE[1][ie - 1] = mur_edge<R>(sE[1][ie - 1], sE[1][ie], dey, h2, r.dx, 2);
+      sE[2][ie - 1] = mur_edge<R>(sE[2][ie - 1], sE[2][ie], dez, h2, r.dx, 2);
+    }
+    if (!(open && gu == 0)) {
+      sE[1][ie] += dey;
+      sE[2][ie] += dez;
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC)
+      e_update((q & (TX - 1)) + 1, (q >> LX) + 1, jv[p][0], jv[p][1], jv[p][2]);
+  }
+#pragma unroll
+  for (int p = 0; p < NJR; ++p) {
+    const int h = tid + p * 256;
+    if (h < JR) e_update(h <= TY ? TX + 1 : h - TY, h <= TY ? 1 + h : TY + 1, je[p][0], je[p][1], je[p][2]);
+  }
+  __syncthreads();
+  // 3. B half update on the output tile (reads E only)
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC) {
+      const int v = (q >> LX) + 1, u = (q & (TX - 1)) + 1;
+      const int ie = v * EW + u, ib = v * BW + u, gu = a - 1 + u;
+      const R ex = sE[0][ie], ey = sE[1][ie], ez = sE[2][ie];
+      const R dbx = -hy1 * (sE[2][ie + EW] - ez);
+      const R dby = hx1 * (sE[2][ie + 1] - ez);
+      const R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+      sB[0][ib] += dbx;
+      if (open && gu == nx - 2 && u + 1 <= TX) {   // Mur for column nx-1
+        sB[1][ib + 1] = mur_edge<R>(sB[1][ib + 1], sB[1][ib], dby, h1, r.dx, 1);
+        sB[2][ib + 1] = mur_edge<R>(sB[2][ib + 1], sB[2][ib], dbz, h1, r.dx, 1);
+      }
+      if (!(open && gu == nx - 1 && u >= 2)) {
+        sB[1][ib] += dby;
+        sB[2][ib] += dbz;
+      }
+    }
+  }
+  __syncthreads();
+  // 4. the tile's E and B to the arrays, its edges to the other snapshot
+  const int64_t bbase = (tile0 + blk) * 6 * (3 * (TX + TY));
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC) {
+      const int lj = q >> LX, li = q & (TX - 1);
+      const int ie = (lj + 1) * EW + li + 1, ib = (lj + 1) * BW + li + 1;
+      const int64_t g = (int64_t)(c + lj) * nx + a + li;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        f[F_EX + k][g] = sE[k][ie];
+        f[F_BX + k][g] = sB[k][ib];
+      }
+      if (band_col(li, TX) >= 0 || band_col(lj, TY) >= 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          band_put(bout, Bd, bbase, li, lj, k, sE[k][ie]);
+          band_put(bout, Bd, bbase, li, lj, 3 + k, sB[k][ib]);
+        }
+      }
+    }
+  }
+}
+
+// J := 0 (and the charge arrays when asked and present), four cells per thread, 256 cells
+// per workgroup of 64.  flip != NULL: the launch follows a fused field update; its first
+// thread makes the snapshot that update wrote the present one and, with clock != NULL,
+// advances the antenna clock as the antenna kernel would have.
+template <typename R>
+__device__ __forceinline__ void zero4(R* p, int64_t c, int64_t n) {
+  if (c + 3 < n && ((uintptr_t)p & 15) == 0) {
+    if constexpr (sizeof(R) == 4) {
+      *(float4*)(p + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      *(double2*)(p + c) = make_double2(0.0, 0.0);
+      *(double2*)(p + c + 2) = make_double2(0.0, 0.0);
+    }
+  } else {
+    for (int64_t i = c; i < n && i < c + 4; ++i) p[i] = R(0);
+  }
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(64) void k_clear_sources(Tables T, int with_rho, int32_t* flip,
+                                                      int64_t* clock) {
+  if (flip && blockIdx.x == 0 && threadIdx.x == 0) {
+    *flip ^= 1;
+    if (clock) *clock += 1;
+  }
+  int blk;
+  const RunDesc& r = run_of(T, cell_block(T, blk));
+  const int64_t n = (int64_t)r.nx * r.ny * (DIM == 3 ? r.nz : 1);
+  const int64_t c = (int64_t)blk * 256 + 4 * threadIdx.x;
+  if (c >= n) return;
+  zero4((R*)r.f[F_JX], c, n);
+  zero4((R*)r.f[F_JY], c, n);
+  zero4((R*)r.f[F_JZ], c, n);
+  if (with_rho && r.f[F_R0]) zero4((R*)r.f[F_R0], c, n);
+  if (with_rho && r.f[F_R1]) zero4((R*)r.f[F_R1], c, n);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -170,25 +554,18 @@ __global__ __launch_bounds__(256) void k_laser(Tables T, int nruns, int bpr, dou
     const int64_t m = (int64_t)r.ny * (DIM == 3 ? r.nz : 1);
     const int64_t tcell = (int64_t)(blockIdx.x % bpr) * 256 + threadIdx.x;
     if (r.has_laser && tcell < m) {
-      const LaserDesc& L = r.laser;
-      const double t = (step ? (double)(*step + 1) * r.dt : t_arg) - L.t0;
-      if (t >= 0.0 && t <= L.tau) {
-        const int j = (int)(tcell % r.ny), k = (int)(tcell / r.ny);
-        const double y = (j + (L.pol == 1 ? 0.5 : 0.0)) * r.dy;
-        const double z = DIM == 3 ? (k + (L.pol == 2 ? 0.5 : 0.0)) * r.dz : L.zc;
-        const double env = sin(M_PI * t / L.tau);
-        const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
-        const double einc = L.e0 * env * env * sin(L.omega * t) * exp(-r2 / (L.waist * L.waist));
-        const int64_t c = ((int64_t)k * r.ny + j) * r.nx + L.ia;
-        gptr<R> J = gp((R*)r.f[L.pol == 1 ? F_JY : F_JZ]);
-        J[c] += R(-2.0 * einc / r.dx);
+      const int j = (int)(tcell % r.ny), k = (int)(tcell / r.ny);
+      double jant;
+      if (antenna_current<DIM>(r, step ? (double)(*step + 1) * r.dt : t_arg, j, k, jant)) {
+        const int64_t c = ((int64_t)k * r.ny + j) * r.nx + r.laser.ia;
+        gptr<R> J = gp((R*)r.f[r.laser.pol == 1 ? F_JY : F_JZ]);
+        J[c] += R(jant);
       }
     }
   }
-  if (step) {
+  if (step) {   // the last workgroup advances the clock (all have read it by then)
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();
       if (atomicAdd(done, 1u) == gridDim.x - 1) {
         *step += 1;
         *done = 0u;
@@ -359,18 +736,19 @@ __device__ __forceinline__ int particle_bin(const SegDesc& s, const RunDesc& r, 
   return s.bin_base + t;
 }
 
-// Run-length grouping of equal keys inside a wave.  Returns true for the first lane of each
-// run, with `len` the run length; `head` is the first lane of this lane's run.
-__device__ __forceinline__ bool wave_runs(int key, bool valid, int& len, int& head) {
-  const int lane = __lane_id();
-  const int prev = __shfl_up(key, 1, 64);
-  const bool is_head = valid && (lane == 0 || prev != key);
-  const uint64_t heads = __ballot(is_head) | ~__ballot(valid);
-  const uint64_t above = heads & ~((2ull << lane) - 1ull);
-  len = (above ? __ffsll((unsigned long long)above) - 1 : 64) - lane;
-  const uint64_t upto = heads & ((2ull << lane) - 1ull);
-  head = 63 - __clzll((unsigned long long)upto);
-  return is_head;
+// Groups the lanes of a wave by key: the mask of the lanes holding this lane's key (0 for an
+// invalid lane).  One pass per distinct key in the wave, so a wave whose particles sit in a
+// few tiles, in any lane order, costs a few passes.
+__device__ __forceinline__ uint64_t wave_match(int key, bool valid) {
+  uint64_t todo = __ballot(valid);
+  uint64_t mine = 0;
+  while (todo) {
+    const int k = __shfl(key, __ffsll((unsigned long long)todo) - 1, 64);
+    const uint64_t m = __ballot(valid && key == k);
+    if (valid && key == k) mine = m;
+    todo &= ~m;
+  }
+  return mine;
 }
 
 // Keys of the SORT_ITEMS particles a thread handles (loads issued together); -1 past the end.
@@ -428,8 +806,9 @@ __global__ __launch_bounds__(256) void k_sort_count(Tables T, int32_t* counts) {
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    int len, head;
-    if (wave_runs(key[it], key[it] >= 0, len, head)) {
+    const uint64_t m = wave_match(key[it], key[it] >= 0);
+    if (m && __lane_id() == __ffsll((unsigned long long)m) - 1) {   // first lane of its key
+      const int len = __popcll(m);
       if (sort_cache_claim(C, key[it])) atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len);
       else atomicAdd(&counts[key[it]], len);
     }
@@ -538,16 +917,20 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
   bool cached[SORT_ITEMS];
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    int len, head;
+    // lanes of one key take consecutive ranks in lane order after the first lane's reservation
+    const uint64_t m = wave_match(key[it], key[it] >= 0);
+    const int lane = __lane_id();
+    const int head = m ? __ffsll((unsigned long long)m) - 1 : lane;
     int base = 0, hit = 0;
-    if (wave_runs(key[it], key[it] >= 0, len, head)) {
+    if (m && lane == head) {
+      const int len = __popcll(m);
       hit = sort_cache_claim(C, key[it]);
       base = hit ? atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len)
                  : atomicAdd(&cursor[key[it]], len);
     }
     base = __shfl(base, head, 64);
     hit = __shfl(hit, head, 64);
-    rank[it] = base + (__lane_id() - head);
+    rank[it] = base + __popcll(m & ((1ull << lane) - 1ull));
     cached[it] = hit != 0;
   }
   __syncthreads();
@@ -923,20 +1306,50 @@ __global__ __launch_bounds__(256) void k_store_positions(Tables T, double* x, do
 // =======================================================================================
 template <typename R, int DIM>
 static void launch_yee_t(const Tables& T, int nblocks, int which, double frac, int zero_j,
-                         int halves, hipStream_t st) {
+                         int halves, hipStream_t st, const FieldBands& bands) {
   if (which == 0) k_yee_e<R, DIM><<<nblocks, 256, 0, st>>>(T, frac, zero_j, halves);
-  else k_yee_b<R, DIM><<<nblocks, 256, 0, st>>>(T, frac);
+  else k_yee_b<R, DIM><<<nblocks, 256, 0, st>>>(T, frac, bands);
 }
 
 void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, double frac,
-                int zero_j, int halves, hipStream_t st) {
+                int zero_j, int halves, hipStream_t st, const FieldBands* bands) {
+  FieldBands nb;
+  memset(&nb, 0, sizeof(nb));
+  const FieldBands& b = (bands && dim == 2) ? *bands : nb;
   if (prec == 0) {
-    if (dim == 2) launch_yee_t<float, 2>(T, nblocks, which, frac, zero_j, halves, st);
-    else launch_yee_t<float, 3>(T, nblocks, which, frac, zero_j, halves, st);
+    if (dim == 2) launch_yee_t<float, 2>(T, nblocks, which, frac, zero_j, halves, st, b);
+    else launch_yee_t<float, 3>(T, nblocks, which, frac, zero_j, halves, st, b);
   } else {
-    if (dim == 2) launch_yee_t<double, 2>(T, nblocks, which, frac, zero_j, halves, st);
-    else launch_yee_t<double, 3>(T, nblocks, which, frac, zero_j, halves, st);
+    if (dim == 2) launch_yee_t<double, 2>(T, nblocks, which, frac, zero_j, halves, st, b);
+    else launch_yee_t<double, 3>(T, nblocks, which, frac, zero_j, halves, st, b);
   }
+}
+
+template <typename R, int TX>
+static void launch_yee_mid_t(const Tables& T, int ntiles, const FieldBands& b, hipStream_t st) {
+  if (b.ty == 16) k_yee_mid<R, TX, 16><<<ntiles, 256, 0, st>>>(T, b);
+  else if (b.ty == 8) k_yee_mid<R, TX, 8><<<ntiles, 256, 0, st>>>(T, b);
+  else k_yee_mid<R, TX, 4><<<ntiles, 256, 0, st>>>(T, b);
+}
+
+template <typename R>
+static void launch_yee_mid_r(const Tables& T, int ntiles, const FieldBands& b, hipStream_t st) {
+  if (b.tx == 64) launch_yee_mid_t<R, 64>(T, ntiles, b, st);
+  else if (b.tx == 32) launch_yee_mid_t<R, 32>(T, ntiles, b, st);
+  else if (b.tx == 16) launch_yee_mid_t<R, 16>(T, ntiles, b, st);
+  else launch_yee_mid_t<R, 8>(T, ntiles, b, st);
+}
+
+void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands,
+                    hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (prec == 0) launch_yee_mid_r<float>(T, ntiles, bands, st);
+  else launch_yee_mid_r<double>(T, ntiles, bands, st);
+}
+
+void launch_clear_sources(const Tables& T, int prec, int dim, int nblocks, int with_rho,
+                          int32_t* flip, int64_t* clock, hipStream_t st) {
+  LPIC_PD(prec, dim, (k_clear_sources<R, D><<<nblocks, 64, 0, st>>>(T, with_rho, flip, clock)));
 }
 
 void launch_laser(const Tables& T, int prec, int dim, int nruns, int bpr, double t,

@@ -17,6 +17,7 @@ F32_CELLOFS = 0
 F64_ABS = 1
 YEE_ZERO_J = 1
 SORT_SPREAD = 1
+FIELD_SEPARATE = 2
 
 STAGES = ["START", "LOOP_START", "MAXWELL_1", "PUSH_POSITION_1", "INTERPOLATOR",
           "PUSH_MOMENTUM", "PUSH_POSITION_2", "CURRENT_DEPOSITION", "QED_CREATE",
@@ -72,7 +73,8 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("sorts", ctypes.c_int64), ("fused", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("fused_ms", ctypes.c_double),
-                ("fused_launches", ctypes.c_int64), ("halo_escapes", ctypes.c_int64)]
+                ("fused_launches", ctypes.c_int64), ("halo_escapes", ctypes.c_int64),
+                ("field_tile", ctypes.c_int32 * 2)]
 
 
 HOOK_FN = ctypes.CFUNCTYPE(ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int64, _vp)

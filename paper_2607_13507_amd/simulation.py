@@ -173,7 +173,7 @@ class Simulation:
 
     def __init__(self, workloads: Union[Workload, Sequence[Workload]], prec=L.F32_CELLOFS,
                  tiling=(16, 16, 8), halo=5, chunk=2048, sort_interval=10, diag_interval=0,
-                 use_graph=True, device="cuda", with_rho=True, stream=None):
+                 use_graph=True, device="cuda", with_rho=True, stream=None, flags=0):
         wls = [workloads] if isinstance(workloads, Workload) else list(workloads)
         self.workloads = wls
         self.prec = prec
@@ -191,7 +191,7 @@ class Simulation:
                 self.alt.append(d.like())
                 self.species_run.append(r)
         self.options = L.Options(L.Tiling(tiling[0], tiling[1], tiling[2] if self.ndim == 3 else 1,
-                                          halo, chunk, 0),
+                                          halo, chunk, flags),
                                  sort_interval, diag_interval, int(use_graph), 0)
         self.h = L.lpic_sim_create(self.grids, [f.struct() for f in self.fields],
                                    [s.struct() for s in self.species], self.species_run,
@@ -247,7 +247,8 @@ class Simulation:
         s = L.lpic_get_stats(self.h)
         return dict(steps=s.steps, sorts=s.sorts, fused=bool(s.fused), graph=bool(s.graph),
                     fused_ms=s.fused_ms, fused_launches=s.fused_launches,
-                    halo_escapes=s.halo_escapes)
+                    halo_escapes=s.halo_escapes,
+                    field_tile=(s.field_tile[0], s.field_tile[1]))
 
     def set_timing(self, on):
         L.lpic_set_timing(self.h, on)
@@ -257,7 +258,8 @@ class Simulation:
         t = o.tiling
         tiling = kw.get("tiling", (t.tx, t.ty, t.tz))
         self.options = L.Options(L.Tiling(tiling[0], tiling[1], tiling[2] if self.ndim == 3 else 1,
-                                          kw.get("halo", t.halo), kw.get("chunk", t.chunk), 0),
+                                          kw.get("halo", t.halo), kw.get("chunk", t.chunk),
+                                          kw.get("flags", t.flags)),
                                  kw.get("sort_interval", o.sort_interval),
                                  kw.get("diag_interval", o.diag_interval),
                                  int(kw.get("use_graph", o.use_graph)), 0)

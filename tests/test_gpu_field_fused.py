@@ -1,0 +1,135 @@
+"""The fused 2D field update between two steps (one workgroup per field tile: B by dt/2, E by
+dt, B by dt/2, the tile's neighbours read from the edge snapshot of the previous update)
+against the same steps with the three updates as separate grid-wide kernels
+(LPIC_FIELD_SEPARATE), and against the FP64 oracle.
+
+Cases: periodic, open x ends with a laser antenna, a box that is a single field tile in both
+directions (its halo wraps onto its own edges), and an ensemble of boxes of different sizes
+(a tile prefix over runs).  Steps include sorts and diagnostic steps (which end with the
+unfused updates), so the edge snapshot is rebuilt after each of them.  The arithmetic per
+cell is the same in both paths, so FP64 agrees to rounding (1e-12 relative to each
+component's largest value) and FP32 to a few ulps amplified over the steps (1e-5)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner, compare_fields
+from oracle import OracleSim
+from paper_2607_13507_amd import lpic as L
+from paper_2607_13507_amd import workloads as W
+from paper_2607_13507_amd.simulation import Simulation
+
+pytestmark = pytest.mark.gpu
+
+PNAME = {L.F64_ABS: "f64", L.F32_CELLOFS: "f32"}
+FIELDS = ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz")
+LASER = dict(pol=1, ia=3, a0=2.0, omega=4.0, waist=1.2, yc=2.0, zc=0.0, t0=0.0, tau=3.0)
+
+
+def _box(case, seed=41):
+    if case == "one_tile":
+        wl = W.thermal_2d(nx=32, ny=4, dx=0.1, ppc=4, T=0.2, order=2, seed=seed)
+    elif case == "wide":
+        wl = W.thermal_2d(nx=128, ny=32, dx=0.1, ppc=2, T=0.2, order=1, seed=seed)
+    else:
+        wl = W.thermal_2d(nx=48, ny=40, dx=0.1, ppc=4, T=0.2, order=2, seed=seed)
+    wl.fields = W.random_fields(wl.ncell, seed + 1, 0.5)
+    if case == "open_laser":
+        wl.open_x = True
+        wl.laser = dict(LASER)
+    for s in wl.species:   # unique weights: particles are followed through the sorts
+        s.w = s.w * (1.0 + 1e-3 * np.arange(s.n) / s.n)
+    return wl
+
+
+def _run(wls, prec, graph, flags, nsteps):
+    sim = Simulation(wls, prec=prec, tiling=(8, 8, 1), halo=4, chunk=128, sort_interval=4,
+                     diag_interval=5, use_graph=graph, flags=flags)
+    sim.step(nsteps)
+    torch.cuda.synchronize()
+    return sim
+
+
+def _rel(a, b):
+    scale = max(1e-300, np.abs(b).max(initial=0))
+    return np.abs(a.astype(np.float64) - b.astype(np.float64)).max(initial=0) / scale
+
+
+def _compare(fused, sep, prec, what):
+    tol = 1e-12 if prec == L.F64_ABS else 1e-5
+    for r in range(len(fused.fields)):
+        fa, fb = fused.fields[r].numpy(), sep.fields[r].numpy()
+        for k in FIELDS:
+            err = _rel(fa[k], fb[k])
+            assert err <= tol, f"{what} run {r} {k}: {err}"
+        da, db = fused.diagnostics(r), sep.diagnostics(r)
+        for k in ("field_energy", "kinetic_energy"):
+            assert da[k] == pytest.approx(db[k], rel=tol, abs=1e-300), (what, r, k)
+    for i in range(len(fused.species)):
+        ta, tb = fused.current(i).numpy("w"), sep.current(i).numpy("w")
+        ia, ib = np.argsort(ta), np.argsort(tb)
+        np.testing.assert_array_equal(ta[ia], tb[ib])
+        pa, pb = fused.positions(i), sep.positions(i)
+        for d in range(2):
+            assert np.abs(pa[d][ia] - pb[d][ib]).max(initial=0) <= 10 * tol, (what, i, d)
+        for k in ("ux", "uy", "uz"):
+            assert _rel(fused.current(i).numpy(k)[ia], sep.current(i).numpy(k)[ib]) <= 10 * tol
+
+
+@pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=PNAME.get)
+@pytest.mark.parametrize("case,tile", [("periodic", (16, 8)), ("open_laser", (16, 8)),
+                                       ("one_tile", (32, 4)), ("wide", (64, 16))])
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_fused_field_update_matches_separate_kernels(prec, case, tile, graph):
+    banner(f"fused field update {case} prec={PNAME[prec]} graph={graph}")
+    wl = _box(case)
+    fused = _run(wl, prec, graph, 0, 13)
+    sep = _run(wl, prec, graph, L.FIELD_SEPARATE, 13)
+    assert fused.stats()["field_tile"] == tile
+    assert sep.stats()["field_tile"] == (0, 0)
+    _compare(fused, sep, prec, case)
+    if case == "open_laser":
+        assert fused.diagnostics(0)["field_energy"] > 0.0
+    fused.close()
+    sep.close()
+
+
+@pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=PNAME.get)
+def test_fused_field_update_over_an_ensemble(prec):
+    banner(f"fused field update ensemble prec={PNAME[prec]}")
+    wls = [W.thermal_2d(nx=64, ny=32, dx=0.1, ppc=2, T=0.2, order=2, seed=51),
+           W.thermal_2d(nx=32, ny=16, dx=0.1, ppc=4, T=0.2, order=1, seed=52),
+           W.thermal_2d(nx=96, ny=24, dx=0.1, ppc=1, T=0.2, order=2, seed=53)]
+    for i, wl in enumerate(wls):
+        wl.fields = W.random_fields(wl.ncell, 60 + i, 0.5)
+        for s in wl.species:
+            s.w = s.w * (1.0 + 1e-3 * np.arange(s.n) / s.n)
+    fused = _run(wls, prec, True, 0, 11)
+    sep = _run(wls, prec, True, L.FIELD_SEPARATE, 11)
+    assert fused.stats()["field_tile"] == (32, 8)
+    _compare(fused, sep, prec, "ensemble")
+    fused.close()
+    sep.close()
+
+
+def test_fused_field_update_matches_oracle_over_many_steps():
+    """FP64, open ends and an antenna, 40 steps in one call (39 fused updates), against the
+    oracle stepping the same state."""
+    banner("fused field update vs oracle, 40 steps")
+    wl = _box("open_laser", seed=43)
+    sim = Simulation(wl, prec=L.F64_ABS, tiling=(8, 8, 1), halo=4, chunk=128, sort_interval=8,
+                     diag_interval=0, use_graph=True)
+    orc = OracleSim.from_workload(wl)
+    for k, v in sim.fields[0].numpy().items():
+        if k in orc.f:
+            orc.f[k][:] = v
+    s, pos, cur = orc.species[0], sim.positions(0), sim.current(0)
+    s.x[:], s.y[:] = pos[0], pos[1]
+    for k in ("ux", "uy", "uz", "w"):
+        getattr(s, k)[:] = cur.numpy(k)
+    sim.step(40)
+    orc.step(40)
+    torch.cuda.synchronize()
+    assert sim.stats()["field_tile"] == (16, 8)
+    compare_fields(sim.fields[0], orc, L.F64_ABS, tol=1e-10, what="40 fused steps")
+    sim.close()
