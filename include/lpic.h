@@ -349,8 +349,12 @@ lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
  * field updates are fused with the next step's -- see LPIC_FIELD_SEPARATE -- adds it inside
  * the E update instead of to the J array; J is cleared before anything else reads it.) */
 lpic_status lpic_set_laser(lpic_sim *sim, int32_t r, const lpic_laser *laser);
-/* Try the listed candidate options for `steps_each` steps each (the simulation really
- * advances), keep the fastest; writes the winner into *best when non-NULL. */
+/* Try the listed candidate options and keep the fastest (the simulation really advances);
+ * writes the winner into *best when non-NULL.  Each candidate runs n steps untimed (its
+ * sort, graph captures) and then n steps timed, where n is steps_each rounded up to a
+ * multiple of its sort interval and of its diagnostics interval, so that every candidate
+ * pays its own sorts and diagnostics in proportion; candidates compare by time per step.
+ * Infeasible candidates (e.g. an LDS demand above the limit) are skipped. */
 lpic_status lpic_autotune(lpic_sim *sim, const lpic_options *candidates, int32_t ncand,
                           int32_t steps_each, lpic_options *best);
 

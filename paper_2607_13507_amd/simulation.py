@@ -270,7 +270,8 @@ class Simulation:
         for c in candidates:
             t = c.get("tiling", (16, 16, 8))
             opts.append(L.Options(L.Tiling(t[0], t[1], t[2] if self.ndim == 3 else 1,
-                                           c.get("halo", 5), c.get("chunk", 2048), 0),
+                                           c.get("halo", 5), c.get("chunk", 2048),
+                                           c.get("flags", self.options.tiling.flags)),
                                   c.get("sort_interval", self.options.sort_interval),
                                   c.get("diag_interval", self.options.diag_interval),
                                   int(c.get("use_graph", self.options.use_graph)), 0))
