@@ -120,13 +120,17 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
         # the autotuner (lpic_autotune) times each candidate over whole sort and diagnostics
         # periods and keeps the fastest per step; it advances the simulation it tunes, so it
         # runs on a copy and the measured run starts from the workload's initial state
-        cands = [dict(tiling=(16, 16, 1), halo=5, chunk=ch, sort_interval=k, use_graph=True)
-                 for k in (20, 40) for ch in (1024, 2048)]
-        cands += [dict(tiling=(16, 16, 1), halo=6, chunk=1024, sort_interval=k, use_graph=True)
-                  for k in (40, 60)]
+        if wl[0].ndim == 2:
+            cands = [dict(tiling=(16, 16, 1), halo=5, chunk=ch, sort_interval=k, use_graph=True)
+                     for k in (20, 40) for ch in (1024, 2048)]
+            cands.append(dict(tiling=(16, 16, 1), halo=6, chunk=1024, sort_interval=40,
+                              use_graph=True))
+        else:   # a 3D tile region with its charge planes fills most of one CU's LDS
+            cands = [dict(tiling=(8, 4, 4), halo=halo, chunk=2048, sort_interval=k,
+                          use_graph=True) for k in (5, 10, 20)]
         tsim = Simulation(wl, prec=prec, tiling=tiling, halo=halo, chunk=chunk,
                           sort_interval=sort_interval, diag_interval=10, use_graph=True)
-        tuned = tsim.autotune(cands, steps_each=20)
+        tuned = tsim.autotune(cands, steps_each=40 if wl[0].ndim == 2 else 10)
         tsim.close()
         del tsim
         torch.cuda.empty_cache()
@@ -235,8 +239,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=2048)
     ap.add_argument("--sort-interval", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true",
-                    help="2D: use the fixed tile / halo / chunk / sort interval instead of the "
-                         "autotuner's pick (3D always uses them)")
+                    help="use the fixed tile / halo / chunk / sort interval instead of the "
+                         "autotuner's pick")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
@@ -265,7 +269,7 @@ def main():
     if args.sort_interval is None:
         args.sort_interval = 20   # the sort interval the 3D thermal configuration fixes
     nparticles = sum(w.nparticles for w in wl)
-    tune = ndim == 2 and not args.no_autotune
+    tune = not args.no_autotune
     f32 = run_gpu(wl, L.F32_CELLOFS, args, args.steps, args.warmup, tune)
     f64 = None
     if not args.no_fp64:

@@ -843,48 +843,72 @@ __device__ __forceinline__ int32_t spread_multiplier(int32_t n) {
   return (int32_t)t0;
 }
 
+// Exclusive scan over the 1024 threads of a workgroup (wsum: 17 shared words); *total gets
+// the sum.  Contains barriers: every thread must call it.
+__device__ __forceinline__ int32_t block_exscan1024(int32_t local, int32_t* wsum,
+                                                    int32_t* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int32_t incl = local;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  __syncthreads();   // wsum may still be read from a previous call
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  if (tid < 64) {
+    const int32_t v = tid < 16 ? wsum[tid] : 0;
+    int32_t vi = v;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int32_t o = __shfl_up(vi, off, 64);
+      if (lane >= off) vi += o;
+    }
+    if (tid < 16) wsum[tid] = vi - v;
+    if (tid == 15) wsum[16] = vi;
+  }
+  __syncthreads();
+  *total = wsum[16];
+  return wsum[wid] + incl - local;
+}
+
+// Bins per thread and pass of the one-workgroup kernels over all bins: a thread loads its
+// run of bins at once (one memory latency per pass rather than one per bin).
+constexpr int SCAN_PER = 16;
+
 // Exclusive scan of the bin counts by one workgroup; clears the counts for the next sort
 // and records each bin's placement multiplier.
 __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* offsets,
                                                     int32_t* cursor, int32_t* mult, int nbins,
                                                     int spread) {
-  __shared__ int32_t wsum[16];
-  const int tid = threadIdx.x;
-  const int per = (nbins + 1023) / 1024;
-  const int b0 = tid * per, b1 = min(nbins, b0 + per);
-  int32_t local = 0;
-  for (int b = b0; b < b1; ++b) local += counts[b];
-  // block exclusive scan of `local`
-  const int lane = tid & 63, wid = tid >> 6;
-  int32_t incl = local;
+  __shared__ int32_t wsum[17];
+  int32_t base = 0;
+  for (int pass = 0; pass < nbins; pass += 1024 * SCAN_PER) {
+    const int b0 = pass + threadIdx.x * SCAN_PER;
+    int32_t v[SCAN_PER];
+    int32_t local = 0;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int32_t o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  if (lane == 63) wsum[wid] = incl;
-  __syncthreads();
-  if (tid < 64) {
-    int32_t v = tid < 16 ? wsum[tid] : 0;
-    int32_t vi = v;
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      int32_t o = __shfl_up(vi, off, 64);
-      if (lane >= off) vi += o;
+    for (int k = 0; k < SCAN_PER; ++k) {
+      v[k] = b0 + k < nbins ? counts[b0 + k] : 0;
+      local += v[k];
     }
-    if (tid < 16) wsum[tid] = vi - v;
+    int32_t total;
+    int32_t run = base + block_exscan1024(local, wsum, &total);
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+      const int b = b0 + k;
+      if (b < nbins) {
+        offsets[b] = run;
+        cursor[b] = run;
+        mult[b] = spread ? spread_multiplier(v[k]) : 1;
+        counts[b] = 0;
+      }
+      run += v[k];
+    }
+    base += total;
   }
-  __syncthreads();
-  int32_t run = wsum[wid] + incl - local;
-  for (int b = b0; b < b1; ++b) {
-    const int32_t c = counts[b];
-    offsets[b] = run;
-    cursor[b] = run;
-    mult[b] = spread ? spread_multiplier(c) : 1;
-    counts[b] = 0;
-    run += c;
-  }
-  if (tid == 1023) offsets[nbins] = run;
+  if (threadIdx.x == 0) offsets[nbins] = base;
 }
 
 template <class V>
@@ -1075,58 +1099,63 @@ __device__ __forceinline__ int seg_of_bin(const Tables& T, int bin) {
   return lo;
 }
 
+// Segment owning bin b and what the chunks need of it.
+struct BinSeg {
+  int si, base, end, ntiles;   // bins [base, end) belong to segment si
+  int64_t pbase;
+};
+__device__ __forceinline__ BinSeg bin_seg(const Tables& T, int b) {
+  BinSeg q;
+  q.si = seg_of_bin(T, b);
+  const SegDesc& s = seg_of(T, q.si);
+  q.base = s.bin_base;
+  q.pbase = s.pbase;
+  q.ntiles = run_of(T, s.run).ntiles;
+  q.end = q.base + q.ntiles + 1;
+  return q;
+}
+
 __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* offsets,
                                                        int nbins, int chunk, Chunk* out,
                                                        int32_t* nchunks) {
-  __shared__ int32_t wsum[16];
-  const int tid = threadIdx.x;
-  const int per = (nbins + 1023) / 1024;
-  const int b0 = tid * per, b1 = min(nbins, b0 + per);
-  int32_t local = 0;
-  for (int b = b0; b < b1; ++b) {
-    const SegDesc& s = seg_of(T, seg_of_bin(T, b));
-    const int tile = b - s.bin_base;
-    if (tile >= run_of(T, s.run).ntiles) continue;   // dead bin
-    const int32_t cnt = offsets[b + 1] - offsets[b];
-    local += (cnt + chunk - 1) / chunk;
-  }
-  const int lane = tid & 63, wid = tid >> 6;
-  int32_t incl = local;
+  __shared__ int32_t wsum[17];
+  int32_t cbase = 0;
+  for (int pass = 0; pass < nbins; pass += 1024 * SCAN_PER) {
+    const int b0 = pass + threadIdx.x * SCAN_PER;
+    int32_t o[SCAN_PER + 1];
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int32_t o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  if (lane == 63) wsum[wid] = incl;
-  __syncthreads();
-  if (tid < 64) {
-    int32_t v = tid < 16 ? wsum[tid] : 0;
-    int32_t vi = v;
+    for (int k = 0; k <= SCAN_PER; ++k) o[k] = b0 + k <= nbins ? offsets[b0 + k] : 0;
+    BinSeg q = bin_seg(T, min(b0, nbins - 1));
+    int32_t local = 0;
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      int32_t o = __shfl_up(vi, off, 64);
-      if (lane >= off) vi += o;
+    for (int k = 0; k < SCAN_PER; ++k) {
+      const int b = b0 + k;
+      if (b >= nbins) break;
+      if (b >= q.end) q = bin_seg(T, b);
+      if (b - q.base < q.ntiles) local += (o[k + 1] - o[k] + chunk - 1) / chunk;   // not dead
     }
-    if (tid < 16) wsum[tid] = vi - v;
-  }
-  __syncthreads();
-  int32_t pos = wsum[wid] + incl - local;
-  for (int b = b0; b < b1; ++b) {
-    const int si = seg_of_bin(T, b);
-    const SegDesc& s = seg_of(T, si);
-    const int tile = b - s.bin_base;
-    if (tile >= run_of(T, s.run).ntiles) continue;
-    const int32_t o0 = offsets[b] - (int32_t)s.pbase, o1 = offsets[b + 1] - (int32_t)s.pbase;
-    for (int32_t a = o0; a < o1; a += chunk) {
-      Chunk c;
-      c.seg = si;
-      c.tile = tile;
-      c.beg = a;
-      c.end = min(o1, a + chunk);
-      out[pos++] = c;
+    int32_t total;
+    int32_t pos = cbase + block_exscan1024(local, wsum, &total);
+    q = bin_seg(T, min(b0, nbins - 1));
+    for (int k = 0; k < SCAN_PER; ++k) {
+      const int b = b0 + k;
+      if (b >= nbins) break;
+      if (b >= q.end) q = bin_seg(T, b);
+      const int tile = b - q.base;
+      if (tile >= q.ntiles) continue;   // dead bin
+      const int32_t o0 = o[k] - (int32_t)q.pbase, o1 = o[k + 1] - (int32_t)q.pbase;
+      for (int32_t a = o0; a < o1; a += chunk) {
+        Chunk c;
+        c.seg = q.si;
+        c.tile = tile;
+        c.beg = a;
+        c.end = min(o1, a + chunk);
+        out[pos++] = c;
+      }
     }
+    cbase += total;
   }
-  if (tid == 1023) *nchunks = pos;
+  if (threadIdx.x == 0) *nchunks = cbase;
 }
 
 // =======================================================================================
@@ -1172,15 +1201,69 @@ __device__ __forceinline__ void reduce_flush(const RunDesc& r, double* out, int 
   }
 }
 
+// One cell's terms: field energy density (sum of squares), and with the charge arrays the
+// continuity residual, max |rho1| and the Gauss residual.
+template <typename R, int DIM>
+__device__ __forceinline__ void reduce_cell(const RunDesc& r, const CellIdx& x, int with_rho,
+                                            double& en, double& res, double& rm, double& ga) {
+  gptr<R> f[F_NUM];
+#pragma unroll
+  for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double v = (double)f[c][x.c];
+    en += v * v;
+  }
+  if (with_rho) {
+    const double r0 = (double)f[F_R0][x.c], r1 = (double)f[F_R1][x.c];
+    double divj = ((double)f[F_JX][x.c] - (double)f[F_JX][x.cim]) / r.dx +
+                  ((double)f[F_JY][x.c] - (double)f[F_JY][x.cjm]) / r.dy;
+    double dive = ((double)f[F_EX][x.c] - (double)f[F_EX][x.cim]) / r.dx +
+                  ((double)f[F_EY][x.c] - (double)f[F_EY][x.cjm]) / r.dy;
+    if (DIM == 3) {
+      divj += ((double)f[F_JZ][x.c] - (double)f[F_JZ][x.ckm]) / r.dz;
+      dive += ((double)f[F_EZ][x.c] - (double)f[F_EZ][x.ckm]) / r.dz;
+    }
+    rm = fmax(rm, fabs(r1));
+    // a laser antenna's current is prescribed, not carried by charges (its transverse
+    // profile has a divergence): its node column is left out of both residuals
+    if (!(r.has_laser && x.i == r.laser.ia)) {
+      res = fmax(res, fabs(r1 - r0 + r.dt * divj));
+      ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
+    }
+  }
+}
+
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int ncellblk, int with_rho,
                                                        double* out) {
   __shared__ double red[4][4];
   double en = 0.0, res = 0.0, rm = 0.0, ga = 0.0;
+  const int vb0 = blockIdx.x * REDUCE_SPAN;
+  const int vb1 = min(vb0 + REDUCE_SPAN, ncellblk) - 1;
+  int r0 = 0, r1 = 0;
+  if (T.runs) {
+    r0 = uniform(find_owner(T.run_blk, T.nruns, vb0));
+    r1 = uniform(find_owner(T.run_blk, T.nruns, vb1));
+  }
+  if (r0 == r1) {
+    // all blocks in one run: no flush inside the loop, so the loads of several blocks can
+    // be in flight together
+    const RunDesc r = run_of(T, r0);
+    const int blk0 = vb0 - (T.runs ? T.run_blk[r0] : 0);
+#pragma unroll 4
+    for (int k = 0; k < REDUCE_SPAN; ++k) {
+      CellIdx x;
+      if (vb0 + k <= vb1 && cell_index(r, blk0 + k, DIM, x))
+        reduce_cell<R, DIM>(r, x, with_rho, en, res, rm, ga);
+    }
+    reduce_flush<DIM>(r, out, with_rho, en, res, rm, ga, red);
+    return;
+  }
   int cur = -1;
   RunDesc r;
   for (int k = 0; k < REDUCE_SPAN; ++k) {
-    const int vb = blockIdx.x * REDUCE_SPAN + k;
+    const int vb = vb0 + k;
     if (vb >= ncellblk) break;
     int blk = vb, ri = 0;
     if (T.runs) {
@@ -1195,32 +1278,7 @@ __global__ __launch_bounds__(256) void k_reduce_fields(Tables T, int ncellblk, i
     }
     CellIdx x;
     if (!cell_index(r, blk, DIM, x)) continue;
-    gptr<R> f[F_NUM];
-#pragma unroll
-    for (int c = 0; c < F_NUM; ++c) f[c] = gp((R*)r.f[c]);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double v = (double)f[c][x.c];
-      en += v * v;
-    }
-    if (with_rho) {
-      const double r0 = (double)f[F_R0][x.c], r1 = (double)f[F_R1][x.c];
-      double divj = ((double)f[F_JX][x.c] - (double)f[F_JX][x.cim]) / r.dx +
-                    ((double)f[F_JY][x.c] - (double)f[F_JY][x.cjm]) / r.dy;
-      double dive = ((double)f[F_EX][x.c] - (double)f[F_EX][x.cim]) / r.dx +
-                    ((double)f[F_EY][x.c] - (double)f[F_EY][x.cjm]) / r.dy;
-      if (DIM == 3) {
-        divj += ((double)f[F_JZ][x.c] - (double)f[F_JZ][x.ckm]) / r.dz;
-        dive += ((double)f[F_EZ][x.c] - (double)f[F_EZ][x.ckm]) / r.dz;
-      }
-      rm = fmax(rm, fabs(r1));
-      // a laser antenna's current is prescribed, not carried by charges (its transverse
-      // profile has a divergence): its node column is left out of both residuals
-      if (!(r.has_laser && x.i == r.laser.ia)) {
-        res = fmax(res, fabs(r1 - r0 + r.dt * divj));
-        ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
-      }
-    }
+    reduce_cell<R, DIM>(r, x, with_rho, en, res, rm, ga);
   }
   if (cur >= 0) reduce_flush<DIM>(r, out, with_rho, en, res, rm, ga, red);
 }
