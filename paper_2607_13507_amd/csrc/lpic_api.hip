@@ -154,6 +154,9 @@ RunDesc make_run(const lpic_grid* g, const lpic_fields* f, const lpic_tiling* t)
   r.rho_bg = g->rho_bg;
   r.open_x = g->open_x;
   r.has_laser = 0;
+  r.seg_first = 0;
+  r.nseg = 1;
+  r.vbase = 0;
   if (t) {
     tile_counts(g, t, r.ntx, r.nty, r.ntz);
     r.ntiles = r.ntx * r.nty * r.ntz;
@@ -470,7 +473,7 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
   launch_fixed_shift(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), 1, 1,
                      wmax, jshift, stream);
   CHK(last_launch("fixed-point shift"));
-  launch_build_chunks(T, tile_offsets, r.ntiles + 1, t.chunk, chunks, nchunks, stream);
+  launch_build_chunks(T, tile_offsets, r.ntiles, t.chunk, chunks, nchunks, stream);
   CHK(last_launch("build chunks"));
   const size_t smem = fused_smem_bytes(prec, grid->ndim, t.tx, t.ty, t.tz, t.halo, with_rho);
   const int geo = fused_geometry(grid->ndim, t.tx, t.ty, t.tz, t.halo);
@@ -553,6 +556,7 @@ struct lpic_sim {
   int nblk_cells = 0, nblk_p256 = 0, nblk_sort = 0;
   int32_t *counts = nullptr, *offsets = nullptr, *cursor = nullptr, *mult = nullptr;
   int nbins = 0;
+  int nvirt = 0;                             // (tile, species) slots of the chunk order
   Chunk* chunks = nullptr;
   int32_t* nchunks = nullptr;
   int64_t max_chunks = 0;
@@ -690,6 +694,21 @@ lpic_status configure(lpic_sim* s) {
     blks.push_back(blks.back() + (int32_t)((s->sp[i].n + SORT_BLOCK - 1) / SORT_BLOCK));
   }
   if (pbase >= ((int64_t)1 << 31) - 1) return fail(LPIC_EINVAL, "too many particles in total");
+  // chunk order: run by run, tile by tile, the run's species one after the other, so that
+  // the chunks of all species of one tile are consecutive (one staging of the tile)
+  s->nvirt = 0;
+  for (int r = 0; r < s->nruns; ++r) {
+    RunDesc& d = s->runs_h[r];
+    d.seg_first = 0;
+    d.nseg = 0;
+    for (int i = 0; i < s->nsegs; ++i)
+      if (s->species_run[i] == r) {
+        if (d.nseg == 0) d.seg_first = i;
+        ++d.nseg;
+      }
+    d.vbase = s->nvirt;
+    s->nvirt += d.ntiles * d.nseg;
+  }
   s->nblk_cells = run_blk.back();
   s->nblk_p256 = blk256.back();
   s->nblk_sort = blks.back();
@@ -863,7 +882,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     CHK(last_launch("sort"));
     launch_swap_segments(s->segs_d, s->nsegs, st);
     CHK(last_launch("swap"));
-    launch_build_chunks(Tc, s->offsets, s->nbins, s->opt.tiling.chunk, s->chunks, s->nchunks, st);
+    launch_build_chunks(Tc, s->offsets, s->nvirt, s->opt.tiling.chunk, s->chunks, s->nchunks, st);
     CHK(last_launch("chunks"));
     // the host mirror follows the device table at once, so that launches later in this
     // step that take descriptors by value see the sorted buffers (not while capturing: a

@@ -39,6 +39,8 @@ struct RunDesc {
   int32_t ndim, nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;   // tiles per axis of the current tiling
   int32_t open_x, has_laser;       // open x ends; laser antenna present
+  int32_t seg_first, nseg;         // the run's species: segments [seg_first, seg_first + nseg)
+  int32_t vbase, pad0;             // first (tile, species) slot of the run in the chunk order
   double dx, dy, dz, dt, rho_bg;
   void* f[F_NUM];
   double* diag;                    // DIAG_NUM device accumulators

@@ -72,7 +72,10 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
                  int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
                  hipStream_t st);
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st);
-void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int chunk,
+// Work list of the fused kernel: every (tile, species) particle range cut into chunks, run
+// by run, tile by tile, the run's species consecutive (nvirt = sum over runs of tiles x
+// species; RunDesc seg_first / nseg / vbase describe the order).
+void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st);
 // Particles outside the on-chip margin of their home tile: the fused kernel records them
 // here and a second kernel pushes them through global memory; that kernel's last workgroup

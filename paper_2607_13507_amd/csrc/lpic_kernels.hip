@@ -1099,57 +1099,69 @@ __device__ __forceinline__ int seg_of_bin(const Tables& T, int bin) {
   return lo;
 }
 
-// Segment owning bin b and what the chunks need of it.
-struct BinSeg {
-  int si, base, end, ntiles;   // bins [base, end) belong to segment si
-  int64_t pbase;
+// Slot v of the chunk order (run by run, tile by tile, species by species): its segment,
+// tile and bin.
+struct VSlot {
+  int run, vbase, vend, nseg, seg_first;
 };
-__device__ __forceinline__ BinSeg bin_seg(const Tables& T, int b) {
-  BinSeg q;
-  q.si = seg_of_bin(T, b);
-  const SegDesc& s = seg_of(T, q.si);
-  q.base = s.bin_base;
-  q.pbase = s.pbase;
-  q.ntiles = run_of(T, s.run).ntiles;
-  q.end = q.base + q.ntiles + 1;
+__device__ __forceinline__ VSlot vslot_run(const Tables& T, int v) {
+  int lo = 0, hi = T.runs ? T.nruns - 1 : 0;   // last run with vbase <= v
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (T.runs[mid].vbase <= v) lo = mid; else hi = mid - 1;
+  }
+  const RunDesc& r = run_of(T, lo);
+  VSlot q;
+  q.run = lo;
+  q.vbase = r.vbase;
+  q.nseg = r.nseg;
+  q.seg_first = r.seg_first;
+  q.vend = r.vbase + r.ntiles * r.nseg;
   return q;
 }
 
 __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* offsets,
-                                                       int nbins, int chunk, Chunk* out,
+                                                       int nvirt, int chunk, Chunk* out,
                                                        int32_t* nchunks) {
   __shared__ int32_t wsum[17];
   int32_t cbase = 0;
-  for (int pass = 0; pass < nbins; pass += 1024 * SCAN_PER) {
-    const int b0 = pass + threadIdx.x * SCAN_PER;
-    int32_t o[SCAN_PER + 1];
+  for (int pass = 0; pass < nvirt; pass += 1024 * SCAN_PER) {
+    const int v0 = pass + threadIdx.x * SCAN_PER;
+    // each slot's segment, tile and particle range (loads issued together)
+    int sg[SCAN_PER], tl[SCAN_PER];
+    int32_t o0[SCAN_PER], o1[SCAN_PER];
+    VSlot q = vslot_run(T, min(v0, nvirt - 1));
 #pragma unroll
-    for (int k = 0; k <= SCAN_PER; ++k) o[k] = b0 + k <= nbins ? offsets[b0 + k] : 0;
-    BinSeg q = bin_seg(T, min(b0, nbins - 1));
+    for (int k = 0; k < SCAN_PER; ++k) {
+      const int v = v0 + k;
+      sg[k] = -1;
+      tl[k] = 0;
+      o0[k] = o1[k] = 0;
+      if (v < nvirt) {
+        while (v >= q.vend) q = vslot_run(T, v);   // runs without species span no slots
+        const int w = v - q.vbase;
+        tl[k] = w / q.nseg;
+        sg[k] = q.seg_first + (w - tl[k] * q.nseg);
+        const SegDesc& s = seg_of(T, sg[k]);
+        const int b = s.bin_base + tl[k];
+        o0[k] = offsets[b] - (int32_t)s.pbase;
+        o1[k] = offsets[b + 1] - (int32_t)s.pbase;
+      }
+    }
     int32_t local = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_PER; ++k) {
-      const int b = b0 + k;
-      if (b >= nbins) break;
-      if (b >= q.end) q = bin_seg(T, b);
-      if (b - q.base < q.ntiles) local += (o[k + 1] - o[k] + chunk - 1) / chunk;   // not dead
-    }
+    for (int k = 0; k < SCAN_PER; ++k)
+      if (sg[k] >= 0) local += (o1[k] - o0[k] + chunk - 1) / chunk;
     int32_t total;
     int32_t pos = cbase + block_exscan1024(local, wsum, &total);
-    q = bin_seg(T, min(b0, nbins - 1));
     for (int k = 0; k < SCAN_PER; ++k) {
-      const int b = b0 + k;
-      if (b >= nbins) break;
-      if (b >= q.end) q = bin_seg(T, b);
-      const int tile = b - q.base;
-      if (tile >= q.ntiles) continue;   // dead bin
-      const int32_t o0 = o[k] - (int32_t)q.pbase, o1 = o[k + 1] - (int32_t)q.pbase;
-      for (int32_t a = o0; a < o1; a += chunk) {
+      if (sg[k] < 0) continue;
+      for (int32_t a = o0[k]; a < o1[k]; a += chunk) {
         Chunk c;
-        c.seg = q.si;
-        c.tile = tile;
+        c.seg = sg[k];
+        c.tile = tl[k];
         c.beg = a;
-        c.end = min(o1, a + chunk);
+        c.end = min(o1[k], a + chunk);
         out[pos++] = c;
       }
     }
@@ -1455,9 +1467,9 @@ void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
   k_swap_segments<<<(nsegs + 63) / 64, 64, 0, st>>>(segs, nsegs);
 }
 
-void launch_build_chunks(const Tables& T, const int32_t* offsets, int nbins, int chunk,
+void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st) {
-  k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nbins, chunk, out, nchunks);
+  k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, nchunks);
 }
 
 template <typename R, int DIM>
