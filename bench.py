@@ -198,6 +198,26 @@ def copy_calibration(mib):
                 launches=3)
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """GB/s of a plain device-to-device copy of mib MiB (bytes read + bytes written per
+    second), timed with events: the practical HBM rate beside the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def host_cpu():
     try:
         for line in open("/proc/cpuinfo"):
@@ -290,6 +310,7 @@ def main():
                 kernel=f"lpic::k_fused<float,{ndim}>", bytes_per_push=round(bpp, 3),
                 bytes_per_launch=int(launch_bytes), avg_launch_ms=round(f32["fused_ms"], 4),
                 launches=f32["fused_launches"], kernel_source_sha256=kernel_source_hash())
+    roof["copy_gbs"] = copy_bandwidth()   # measured, for context (not the peak)
     if valu:
         # the unit that binds this kernel: VALU issue.  A wave64 VALU instruction occupies a
         # SIMD for 4 cycles; 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions/s
