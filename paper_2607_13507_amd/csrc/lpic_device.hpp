@@ -503,6 +503,11 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   // on that node is an exact zero and the wave skips it (a uniform branch).
   const bool lx = __ballot(S0x[W - 1] != R(0) || S1x[W - 1] != R(0)) != 0;
   const bool ly = __ballot(S0y[W - 1] != R(0) || S1y[W - 1] != R(0)) != 0;
+  // A lane whose path keeps its nearest node along an axis has both shapes on the first W-1
+  // nodes; each shape sums to 1 there, so the running sum of the current along that axis is
+  // exactly zero at node W-2: the lane adds nothing there rather than the rounding residue.
+  const bool xs = S0x[W - 1] == R(0) && S1x[W - 1] == R(0);
+  const bool ys = S0y[W - 1] == R(0) && S1y[W - 1] == R(0);
   int xo[W], yo[W];
 #pragma unroll
   for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
@@ -517,7 +522,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
       for (int a = 0; a < W - 1; ++a) {
         acc += (S1x[a] - S0x[a]) * hy;
-        A.add(F_JX, yo[b] + xo[a], acc);
+        A.add(F_JX, yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
       }
     }
 #pragma unroll
@@ -528,7 +533,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
       for (int b = 0; b < W - 1; ++b) {
         acc += (S1y[b] - S0y[b]) * hx;
-        A.add(F_JY, yo[b] + xo[a], acc);
+        A.add(F_JY, yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
       }
     }
 #pragma unroll
@@ -557,6 +562,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     int bz;
     esk_axis<ORDER>(x0[2], x1[2], bz, S0z, S1z);
     const bool lz = __ballot(S0z[W - 1] != R(0) || S1z[W - 1] != R(0)) != 0;
+    const bool zs = S0z[W - 1] == R(0) && S1z[W - 1] == R(0);
     int zo[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) zo[a] = A.zo(c[2] + bz + a);
@@ -574,7 +580,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
         for (int a = 0; a < W - 1; ++a) {
           acc += (S1x[a] - S0x[a]) * ryz;
-          A.add(F_JX, zo[cc] + yo[b] + xo[a], acc);
+          A.add(F_JX, zo[cc] + yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
         }
       }
 #pragma unroll
@@ -588,7 +594,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
         for (int b = 0; b < W - 1; ++b) {
           acc += (S1y[b] - S0y[b]) * rxz;
-          A.add(F_JY, zo[cc] + yo[b] + xo[a], acc);
+          A.add(F_JY, zo[cc] + yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
         }
       }
 #pragma unroll
@@ -602,7 +608,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
         for (int cc = 0; cc < W - 1; ++cc) {
           acc += (S1z[cc] - S0z[cc]) * rxy;
-          A.add(F_JZ, zo[cc] + yo[b] + xo[a], acc);
+          A.add(F_JZ, zo[cc] + yo[b] + xo[a], cc == W - 2 && zs ? R(0) : acc);
         }
       }
     if (with_rho) {
