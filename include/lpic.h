@@ -349,6 +349,33 @@ lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
  * field updates are fused with the next step's -- see LPIC_FIELD_SEPARATE -- adds it inside
  * the E update instead of to the J array; J is cleared before anything else reads it.) */
 lpic_status lpic_set_laser(lpic_sim *sim, int32_t r, const lpic_laser *laser);
+/* Fresh plasma for a moving window: ppc_x x ppc_y macro-particles per cell of species
+ * `species` (a global species index of the run) on a regular lattice (offsets
+ * (l + 1/2)/ppc per axis), weight density / (ppc_x ppc_y), momentum (ux, uy, uz). */
+typedef struct {
+  int32_t species;
+  int32_t ppc_x, ppc_y;
+  int32_t reserved0;
+  double density;
+  double ux, uy, uz;
+} lpic_plasma;
+
+/* Moving window (open x ends, 2D): between two steps, move box r by m cells in +x (a window
+ * that follows a laser pulse; the paper's lazy deletion of Sec. 2.1 recycles the slots).
+ * Field arrays are circular in x with a moving origin, so nothing is copied: the m columns
+ * that were the box's first become its last, with their fields set to zero and their
+ * particles removed (marked dead); with plasma != NULL, the m columns just inside the
+ * right-hand margin (box columns nx-3-m .. nx-4) receive fresh particles, written into the
+ * species' dead slots that follow its alive particles as of the last sort (slots beyond the
+ * arrays are dropped and counted).  The next step re-sorts.  Field arrays and particle
+ * arrays are then in the array frame: box column c is array column (c + x0) mod nx with
+ * x0 = (total shift) mod nx (lpic_window_info), so lpic_store_positions returns array-frame
+ * x, and box x = array x - x0 dx (mod nx dx).  A simulation that has moved a window runs the
+ * field updates between steps as separate kernels.  1 <= m <= nx - 2*3 - 1; at least one
+ * step must have been taken (the alive/dead split of the last sort is used). */
+lpic_status lpic_window_shift(lpic_sim *sim, int32_t r, int32_t m, const lpic_plasma *plasma);
+/* Total cells box r has moved, and fresh particles that found no free slot. */
+lpic_status lpic_window_info(lpic_sim *sim, int32_t r, int64_t *shifted, int64_t *dropped);
 /* Try the listed candidate options and keep the fastest (the simulation really advances);
  * writes the winner into *best when non-NULL.  Each candidate runs n steps untimed (its
  * sort, graph captures) and then n steps timed, where n is steps_each rounded up to a

@@ -222,6 +222,51 @@ class OracleSim:
             self.t += self.grid.dt
             self.nstep += 1
 
+    # --- moving window (open x ends, 2D) -------------------------------------------------
+    def window_shift(self, m, plasma=None):
+        """Move the box m cells in +x between two steps: every field array moves m columns
+        to the left and the m columns entering at the right start at zero; particles keep
+        their place in the lab, so their box coordinate drops by m dx, and those that fall
+        behind the box's left end are removed (x = -1); with `plasma` (dict: species index,
+        ppc_x, ppc_y, density, ux, uy, uz), the m columns just inside the right-hand margin
+        (box columns nx - 3 - m .. nx - 4) get ppc_x x ppc_y macro-particles per cell at the
+        lattice points ((l + 1/2)/ppc) of each cell, weight density / (ppc_x ppc_y), in the
+        order column, row, lattice point (x fastest)."""
+        g = self.grid
+        assert g.ndim == 2 and g.open_x, "a moving window needs a 2D box with open x ends"
+        nx, ny = g.nx, g.ny
+        arrays = [self.f[k] for k in FIELD_NAMES] + [a for a in (self.rho0, self.rho1)
+                                                     if a is not None]
+        for a in arrays:
+            v = a.reshape(ny, nx)
+            v[:, :nx - m] = v[:, m:].copy()
+            v[:, nx - m:] = 0.0
+        for s in self.species:
+            alive = s.x >= 0.0
+            s.x[alive] -= m * g.dx
+            gone = alive & (s.x < 0.0)
+            s.x[gone] = -1.0
+            s.y[gone] = -1.0
+        self.shifted = getattr(self, "shifted", 0) + m
+        if plasma:
+            s = self.species[plasma["species"]]
+            px, py = int(plasma["ppc_x"]), int(plasma["ppc_y"])
+            xs, ys = [], []
+            for col in range(m):
+                c = nx - OPEN_MARGIN - m + col
+                for j in range(ny):
+                    for l in range(px * py):
+                        lx, ly = l % px, l // px
+                        xs.append((c + (2 * lx + 1) / (2 * px)) * g.dx)
+                        ys.append((j + (2 * ly + 1) / (2 * py)) * g.dy)
+            k = len(xs)
+            s.x = np.concatenate([s.x, np.array(xs)])
+            s.y = np.concatenate([s.y, np.array(ys)])
+            s.ux = np.concatenate([s.ux, np.full(k, float(plasma.get("ux", 0.0)))])
+            s.uy = np.concatenate([s.uy, np.full(k, float(plasma.get("uy", 0.0)))])
+            s.uz = np.concatenate([s.uz, np.full(k, float(plasma.get("uz", 0.0)))])
+            s.w = np.concatenate([s.w, np.full(k, plasma["density"] / (px * py))])
+
     def laser_source(self, t):
         fs = self.fields_struct()
         lib().orc_laser_source(ctypes.byref(self.grid), ctypes.byref(fs),

@@ -569,6 +569,13 @@ struct lpic_sim {
   unsigned long long* wmax = nullptr;        // per segment: max |w| (FP64 bits)
   std::vector<int> has_laser;                // per run
   std::vector<LaserDesc> lasers;             // per run
+  // moving windows: per run the origin column and the total shift; per segment the fresh
+  // particles written since the last sort; `windows` once any window has moved
+  std::vector<int32_t> x0;
+  std::vector<int64_t> shifted;
+  std::vector<int64_t> inject_used;
+  bool windows = false;
+  bool offsets_valid = false;                // bin offsets of the current particle layout
   int laser_bpr = 0;                         // antenna kernel blocks per run (0: no laser)
   int64_t* step_dev = nullptr;               // steps taken, on the device (antenna time)
   unsigned int* laser_done = nullptr;        // workgroup counter of the antenna kernel
@@ -668,12 +675,16 @@ lpic_status configure(lpic_sim* s) {
   std::vector<int32_t> run_blk(1, 0);
   s->has_laser.resize(s->nruns, 0);
   s->lasers.resize(s->nruns);
+  s->x0.resize(s->nruns, 0);
+  s->shifted.resize(s->nruns, 0);
+  s->inject_used.resize(std::max(1, s->nsegs), 0);
   s->laser_bpr = 0;
   for (int r = 0; r < s->nruns; ++r) {
     RunDesc d = make_run(&s->grids[r], &s->fields[r], &t);
     d.diag = s->diag + (size_t)r * DIAG_NUM;
     d.has_laser = s->has_laser[r];
     d.laser = s->lasers[r];
+    d.x0 = s->x0[r];
     if (d.has_laser) s->laser_bpr = std::max(s->laser_bpr, columns_bpr(&s->grids[r]));
     s->runs_h.push_back(d);
     run_blk.push_back(run_blk.back() + (int32_t)((ncells(&s->grids[r]) + 255) / 256));
@@ -765,7 +776,7 @@ lpic_status configure(lpic_sim* s) {
   s->bands = nullptr;
   s->mid_tx = s->mid_ty = s->mid_ntiles = 0;
   s->band_half = 0;
-  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE)) {
+  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE) && !s->windows) {
     int tx = MID_MAX_TX, ty = MID_MAX_TY;
     for (int r = 0; r < s->nruns; ++r) {
       while (tx >= 8 && s->grids[r].nx % tx) tx >>= 1;
@@ -796,6 +807,7 @@ lpic_status configure(lpic_sim* s) {
     HIPCHK(hipMemset(s->esc_count, 0, 256));
   }
   s->need_sort = true;
+  s->offsets_valid = false;
   return LPIC_OK;
 #undef ALLOC
 }
@@ -1140,6 +1152,8 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
       ++s->sorts;
       s->need_sort = false;
       s->need_spread = false;
+      std::fill(s->inject_used.begin(), s->inject_used.end(), 0);
+      s->offsets_valid = true;
     }
     if (diag) s->diag_step = s->step + 1;
     ++s->step;
@@ -1237,6 +1251,63 @@ lpic_status lpic_set_laser(lpic_sim* s, int32_t r, const lpic_laser* laser) {
   }
   s->has_laser[r] = laser ? 1 : 0;
   return configure(s);   // rebuilds the device tables and the step counter, drops graphs
+}
+
+lpic_status lpic_window_shift(lpic_sim* s, int32_t r, int32_t m, const lpic_plasma* plasma) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "run index %d out of range", r);
+  const lpic_grid& g = s->grids[r];
+  if (!g.open_x) return fail(LPIC_EINVAL, "a moving window needs open x ends");
+  if (s->ndim != 2) return fail(LPIC_EUNSUPPORTED, "moving windows are 2D only");
+  if (m < 1 || m > g.nx - 2 * LPIC_OPEN_MARGIN - 1)
+    return fail(LPIC_EINVAL, "shift %d outside [1, nx - 7]", m);
+  if (!s->offsets_valid) return fail(LPIC_EINVAL, "take a step before moving the window");
+  int seg = -1;
+  if (plasma) {
+    seg = plasma->species;
+    if (seg < 0 || seg >= s->nsegs || s->species_run[seg] != r)
+      return fail(LPIC_EINVAL, "species %d is not a species of box %d", seg, r);
+    if (plasma->ppc_x < 1 || plasma->ppc_y < 1 || plasma->ppc_x * plasma->ppc_y > 4096)
+      return fail(LPIC_EINVAL, "plasma lattice %d x %d", plasma->ppc_x, plasma->ppc_y);
+    if (!(plasma->density >= 0.0) || !std::isfinite(plasma->ux) || !std::isfinite(plasma->uy) ||
+        !std::isfinite(plasma->uz))
+      return fail(LPIC_EINVAL, "bad plasma density or momentum");
+  }
+  if (!s->windows) {   // the fused field update assumes the origin at column 0
+    s->windows = true;
+    s->mid_tx = s->mid_ty = s->mid_ntiles = 0;
+    drop_graphs(s);
+  }
+  Tables T = sim_tables(s, s->seg_blk256_d);
+  launch_window_shift(T, s->prec, s->ndim, r, m, (int64_t)g.ny, s->nblk_p256, s->stream);
+  CHK(last_launch("window shift"));
+  s->x0[r] = (s->x0[r] + m) % g.nx;
+  s->runs_h[r].x0 = s->x0[r];
+  s->shifted[r] += m;
+  if (plasma) {
+    const int64_t count = (int64_t)m * g.ny * plasma->ppc_x * plasma->ppc_y;
+    const double w = plasma->density / (plasma->ppc_x * plasma->ppc_y);
+    launch_window_inject(T, s->prec, s->ndim, seg, m, count, plasma->ppc_x, plasma->ppc_y, w,
+                         plasma->ux, plasma->uy, plasma->uz, s->offsets, s->inject_used[seg],
+                         (unsigned long long*)((char*)s->step_dev + 192), s->stream);
+    CHK(last_launch("window inject"));
+    s->inject_used[seg] += count;
+  }
+  s->need_sort = true;
+  return LPIC_OK;
+}
+
+lpic_status lpic_window_info(lpic_sim* s, int32_t r, int64_t* shifted, int64_t* dropped) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "run index %d out of range", r);
+  if (shifted) *shifted = s->shifted[r];
+  if (dropped) {
+    unsigned long long v = 0;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpy(&v, (char*)s->step_dev + 192, sizeof(v), hipMemcpyDeviceToHost));
+    *dropped = (int64_t)v;
+  }
+  return LPIC_OK;
 }
 
 lpic_status lpic_autotune(lpic_sim* s, const lpic_options* cand, int32_t ncand,

@@ -40,16 +40,29 @@ struct RunDesc {
   int32_t ntx, nty, ntz, ntiles;   // tiles per axis of the current tiling
   int32_t open_x, has_laser;       // open x ends; laser antenna present
   int32_t seg_first, nseg;         // the run's species: segments [seg_first, seg_first + nseg)
-  int32_t vbase, pad0;             // first (tile, species) slot of the run in the chunk order
+  int32_t vbase;                   // first (tile, species) slot of the run in the chunk order
+  int32_t x0;                      // array column of the box's column 0 (a moving window's
+                                   // origin; 0 otherwise): x is circular in the arrays
   double dx, dy, dz, dt, rho_bg;
   void* f[F_NUM];
   double* diag;                    // DIAG_NUM device accumulators
   LaserDesc laser;
 };
 
+// Box column of array column i, and back (x0: the moving window's origin).
+__device__ __forceinline__ int box_x(const RunDesc& r, int i) {
+  const int p = i - r.x0;
+  return p < 0 ? p + r.nx : p;
+}
+__device__ __forceinline__ int array_x(const RunDesc& r, int p) {
+  const int i = p + r.x0;
+  return i >= r.nx ? i - r.nx : i;
+}
+
 // A particle whose cell column is inside the margin of an open x end leaves the box.
 __device__ __forceinline__ bool leaves_box(const RunDesc& r, int cx) {
-  return r.open_x && (cx < OPEN_MARGIN || cx >= r.nx - OPEN_MARGIN);
+  const int p = box_x(r, cx);
+  return r.open_x && (p < OPEN_MARGIN || p >= r.nx - OPEN_MARGIN);
 }
 
 // One species of one box (a "segment" of the global particle key space).

@@ -114,6 +114,18 @@ void launch_kinetic(const Tables& T, int prec, int dim, int nblocks, double* out
                     hipStream_t st);
 void launch_zero_doubles(double* p, int n, hipStream_t st);
 void launch_diag_clear(const Tables& T, int nruns, hipStream_t st);
+// Moving window of run `run` (open x ends): clear the fields of its first m box columns,
+// remove the particles there (nblk_part: 256-particle blocks of all segments, T.seg_blk the
+// matching prefix), then advance the run's origin x0 by m on the device.
+void launch_window_shift(const Tables& T, int prec, int dim, int run, int m, int64_t rows,
+                         int nblk_part, hipStream_t st);
+// Fresh plasma for the m box columns inside the right-hand margin of segment seg's run (after
+// launch_window_shift): count = m * ny * px * py particles on a px x py lattice per cell,
+// written after the segment's alive particles of the last sort (offsets) plus `used`.
+void launch_window_inject(const Tables& T, int prec, int dim, int seg, int m, int64_t count,
+                          int px, int py, double w, double ux, double uy, double uz,
+                          const int32_t* offsets, int64_t used, unsigned long long* dropped,
+                          hipStream_t st);
 void launch_load_positions(const Tables& T, int prec, int dim, int nblocks, const double* x,
                            const double* y, const double* z, hipStream_t st);
 void launch_store_positions(const Tables& T, int prec, int dim, int nblocks, double* x,

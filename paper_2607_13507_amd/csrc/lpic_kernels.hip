@@ -115,12 +115,13 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   R dex, dey, dez;
   yee_e_delta<R, DIM>(f, x, hx, hy, hz, hh, dex, dey, dez);
   f[F_EX][x.c] += dex;
-  if (r.open_x && x.i == 1) {   // Mur for column 0 (same j, k)
+  const int bxi = box_x(r, x.i);   // box column (a moving window shifts the arrays' origin)
+  if (r.open_x && bxi == 1) {   // Mur for column 0 (same j, k)
     const R ey1 = f[F_EY][x.c], ez1 = f[F_EZ][x.c];
     f[F_EY][x.cim] = mur_edge<R>(f[F_EY][x.cim], ey1, dey, h, r.dx, halves);
     f[F_EZ][x.cim] = mur_edge<R>(f[F_EZ][x.cim], ez1, dez, h, r.dx, halves);
   }
-  if (!(r.open_x && x.i == 0)) {   // column 0 of an open end: set by the thread of column 1
+  if (!(r.open_x && bxi == 0)) {   // column 0 of an open end: set by the thread of column 1
     f[F_EY][x.c] += dey;
     f[F_EZ][x.c] += dez;
   }
@@ -196,8 +197,9 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac, FieldBands
   yee_b_delta<R, DIM>(f, x, hx, hy, hz, dbx, dby, dbz);
   const R bx = f[F_BX][x.c] + dbx;
   f[F_BX][x.c] = bx;
-  const bool edge_in = r.open_x && x.i == r.nx - 2;
-  const bool edge = r.open_x && x.i == r.nx - 1;
+  const int bxi = box_x(r, x.i);   // box column (a moving window shifts the arrays' origin)
+  const bool edge_in = r.open_x && bxi == r.nx - 2;
+  const bool edge = r.open_x && bxi == r.nx - 1;
   R by_e = R(0), bz_e = R(0);
   if (edge_in) {   // Mur for column nx-1 (same j, k)
     const R by1 = f[F_BY][x.c], bz1 = f[F_BZ][x.c];
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   __shared__ R sAnt[MID_MAX_TY + 2];
   int u_ant = -1;
   if (r.has_laser && Bd.step) {
-    const int ia = r.laser.ia;
+    const int ia = array_x(r, r.laser.ia);
     const int ua = ia >= a && ia <= a + TX ? ia - a + 1 : (ia == 0 && a + TX == nx ? TX + 1 : -1);
     double jant;
     const double t_ant = (double)(*Bd.step + 1) * r.dt;
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(256) void k_laser(Tables T, int nruns, int bpr, dou
       const int j = (int)(tcell % r.ny), k = (int)(tcell / r.ny);
       double jant;
       if (antenna_current<DIM>(r, step ? (double)(*step + 1) * r.dt : t_arg, j, k, jant)) {
-        const int64_t c = ((int64_t)k * r.ny + j) * r.nx + r.laser.ia;
+        const int64_t c = ((int64_t)k * r.ny + j) * r.nx + array_x(r, r.laser.ia);
         gptr<R> J = gp((R*)r.f[r.laser.pol == 1 ? F_JY : F_JZ]);
         J[c] += R(jant);
       }
@@ -1239,7 +1241,7 @@ __device__ __forceinline__ void reduce_cell(const RunDesc& r, const CellIdx& x, 
     rm = fmax(rm, fabs(r1));
     // a laser antenna's current is prescribed, not carried by charges (its transverse
     // profile has a divergence): its node column is left out of both residuals
-    if (!(r.has_laser && x.i == r.laser.ia)) {
+    if (!(r.has_laser && box_x(r, x.i) == r.laser.ia)) {
       res = fmax(res, fabs(r1 - r0 + r.dt * divj));
       ga = fmax(ga, fabs(dive - 0.5 * (r0 + r1) - r.rho_bg));
     }
@@ -1307,6 +1309,101 @@ __global__ void k_diag_clear(Tables T) {
 }
 
 // =======================================================================================
+// Moving window (open x ends): the box moves m cells in +x between two steps.  x is circular
+// in the arrays, so only the box's origin column x0 moves: the m array columns that held the
+// box's first columns become its last ones, so their fields are cleared and their particles
+// removed, and fresh plasma fills the m columns just inside the right-hand margin.
+// =======================================================================================
+template <typename R>
+__global__ __launch_bounds__(256) void k_window_clear(Tables T, int run, int m) {
+  const RunDesc& r = run_of(T, run);
+  const int64_t rows = (int64_t)r.ny * (r.ndim == 3 ? r.nz : 1);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * m) return;
+  const int col = (int)(e / rows);
+  const int64_t c = (e - col * rows) * r.nx + array_x(r, col);   // box column col < m
+#pragma unroll
+  for (int k = 0; k < F_NUM; ++k)
+    if (r.f[k]) gp((R*)r.f[k])[c] = R(0);
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_window_kill(Tables T, int run, int m) {
+  int blk;
+  const SegDesc& s = seg_of(T, part_block(T, blk));
+  if (s.run != run) return;
+  const RunDesc& r = run_of(T, s.run);
+  const int64_t p = (int64_t)blk * 256 + threadIdx.x;
+  if (p >= s.n) return;
+  if constexpr (sizeof(R) == 4) {
+    gptr<int32_t> cell = gp((int32_t*)s.p[P_CELL]);
+    const int32_t cv = cell[p];
+    if (cv < 0) return;
+    int c[3];
+    unpack_cell(cv, DIM, c);
+    if (box_x(r, c[0]) < m) cell[p] = -1;
+  } else {
+    gptr<double> x = gp((double*)s.p[P_X]);
+    const double X = x[p] / r.dx;
+    if (!(X >= 0.0 && X <= (double)r.nx)) return;   // dead already
+    int ci = (int)floor(X);
+    ci = ci >= r.nx ? ci - r.nx : ci;
+    if (box_x(r, ci) < m) x[p] = -1.0;
+  }
+}
+
+__global__ void k_window_advance(Tables T, int run, int m) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    RunDesc* r = const_cast<RunDesc*>(&T.runs[run]);
+    const int x0 = r->x0 + m;
+    r->x0 = x0 >= r->nx ? x0 - r->nx : x0;
+  }
+}
+
+// Fresh plasma: particle k of the m * ny * px * py new ones sits in box column
+// nx - OPEN_MARGIN - m + k / (ny px py), row (k / (px py)) mod ny, at lattice point
+// ((l mod px) + 1/2) / px, ((l / px) + 1/2) / py of its cell (l = k mod px py).  It takes slot
+// n_alive + used + k of the segment, n_alive being the start of the dead particles after the
+// last sort; slots past the segment's end are not written and are counted in *dropped.
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_window_inject(Tables T, int seg, int m, int px,
+                                                       int py, double w, double ux, double uy,
+                                                       double uz, const int32_t* offsets,
+                                                       int64_t used,
+                                                       unsigned long long* dropped) {
+  const SegDesc& s = seg_of(T, seg);
+  const RunDesc& r = run_of(T, s.run);
+  const int ppc = px * py;
+  const int64_t per_col = (int64_t)r.ny * ppc;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= per_col * m) return;
+  const int col = (int)(k / per_col);
+  const int64_t rem = k - col * per_col;
+  const int j = (int)(rem / ppc), l = (int)(rem - (int64_t)j * ppc);
+  const int lx = l % px, ly = l / px;
+  const int i = array_x(r, r.nx - OPEN_MARGIN - m + col);
+  const double ox = (2.0 * lx + 1.0) / (2.0 * px), oy = (2.0 * ly + 1.0) / (2.0 * py);
+  const int64_t slot = (int64_t)offsets[s.bin_base + r.ntiles] - s.pbase + used + k;
+  if (slot < 0 || slot >= s.n) {
+    atomicAdd(dropped, 1ull);
+    return;
+  }
+  if constexpr (sizeof(R) == 4) {
+    const int c[3] = {i, j, 0};
+    gp((int32_t*)s.p[P_CELL])[slot] = pack_cell(c, DIM);
+    gp((float*)s.p[P_OX])[slot] = (float)ox;
+    gp((float*)s.p[P_OY])[slot] = (float)oy;
+  } else {
+    gp((double*)s.p[P_X])[slot] = (i + ox) * r.dx;
+    gp((double*)s.p[P_Y])[slot] = (j + oy) * r.dy;
+  }
+  gp((R*)s.p[P_UX])[slot] = R(ux);
+  gp((R*)s.p[P_UY])[slot] = R(uy);
+  gp((R*)s.p[P_UZ])[slot] = R(uz);
+  gp((R*)s.p[P_W])[slot] = R(w);
+}
+
+// =======================================================================================
 // Position representation <-> absolute FP64 coordinates.
 // =======================================================================================
 template <typename R, int DIM>
@@ -1337,12 +1434,17 @@ __global__ __launch_bounds__(256) void k_load_positions(Tables T, const double* 
       float o = (float)(X - f);
       if (o >= 1.0f) { o = 0.0f; ci += 1; }
       ci = ci >= n[d] ? ci - n[d] : ci;
-      c[d] = ci;
+      c[d] = d == 0 ? array_x(r, ci) : ci;
       ((float*)s.p[P_OX + d])[p] = o;
     }
     ((int32_t*)s.p[P_CELL])[p] = pack_cell(c, DIM);
   } else {
     for (int d = 0; d < DIM; ++d) ((double*)s.p[P_X + d])[p] = src[d][p];
+    if (r.x0 != 0 && src[0][p] >= 0.0) {   // array frame of a moved window
+      const double L = r.nx * r.dx;
+      double xa = src[0][p] + r.x0 * r.dx;
+      ((double*)s.p[P_X])[p] = xa >= L ? xa - L : xa;
+    }
   }
 }
 
@@ -1363,11 +1465,16 @@ __global__ __launch_bounds__(256) void k_store_positions(Tables T, double* x, do
     }
     int c[3];
     unpack_cell(cell, DIM, c);
+    c[0] = box_x(r, c[0]);
     const double h[3] = {r.dx, r.dy, r.dz};
     for (int d = 0; d < DIM; ++d)
       dst[d][p] = ((double)c[d] + (double)((const float*)s.p[P_OX + d])[p]) * h[d];
   } else {
     for (int d = 0; d < DIM; ++d) dst[d][p] = ((const double*)s.p[P_X + d])[p];
+    if (r.x0 != 0 && dst[0][p] >= 0.0) {   // box frame of a moved window
+      const double xb = dst[0][p] - r.x0 * r.dx;
+      dst[0][p] = xb < 0.0 ? xb + r.nx * r.dx : xb;
+    }
   }
 }
 
@@ -1515,6 +1622,26 @@ void launch_zero_doubles(double* p, int n, hipStream_t st) {
 
 void launch_diag_clear(const Tables& T, int nruns, hipStream_t st) {
   k_diag_clear<<<nruns, 64, 0, st>>>(T);
+}
+
+void launch_window_shift(const Tables& T, int prec, int dim, int run, int m, int64_t rows,
+                         int nblk_part, hipStream_t st) {
+  const unsigned nb = (unsigned)((rows * m + 255) / 256);
+  if (prec == 0) k_window_clear<float><<<nb, 256, 0, st>>>(T, run, m);
+  else k_window_clear<double><<<nb, 256, 0, st>>>(T, run, m);
+  if (nblk_part > 0)
+    LPIC_PD(prec, dim, (k_window_kill<R, D><<<nblk_part, 256, 0, st>>>(T, run, m)));
+  k_window_advance<<<1, 64, 0, st>>>(T, run, m);
+}
+
+void launch_window_inject(const Tables& T, int prec, int dim, int seg, int m, int64_t count,
+                          int px, int py, double w, double ux, double uy, double uz,
+                          const int32_t* offsets, int64_t used, unsigned long long* dropped,
+                          hipStream_t st) {
+  const unsigned nb = (unsigned)((count + 255) / 256);
+  if (nb == 0) return;
+  LPIC_PD(prec, dim, (k_window_inject<R, D><<<nb, 256, 0, st>>>(T, seg, m, px, py, w, ux, uy,
+                                                                 uz, offsets, used, dropped)));
 }
 
 void launch_load_positions(const Tables& T, int prec, int dim, int nblocks, const double* x,

@@ -46,6 +46,12 @@ class Laser(ctypes.Structure):
                 ("zc", ctypes.c_double), ("t0", ctypes.c_double), ("tau", ctypes.c_double)]
 
 
+class Plasma(ctypes.Structure):
+    _fields_ = [("species", ctypes.c_int32), ("ppc_x", ctypes.c_int32), ("ppc_y", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("density", ctypes.c_double),
+                ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("uz", ctypes.c_double)]
+
+
 class Fields(ctypes.Structure):
     _fields_ = [(n, _vp) for n in ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz",
                                    "rho0", "rho1")]
@@ -122,6 +128,10 @@ EXPORTS = {
                                          ctypes.POINTER(Laser), ctypes.c_double, ctypes.c_int,
                                          _vp]),
     "lpic_set_laser": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Laser)]),
+    "lpic_window_shift": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(Plasma)]),
+    "lpic_window_info": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "lpic_sim_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(Grid),
                                        ctypes.POINTER(Fields), ctypes.c_int32,
                                        ctypes.POINTER(Species), ctypes.POINTER(ctypes.c_int32),
@@ -264,6 +274,20 @@ def lpic_laser_source(grid, fields, laser, t, prec, stream=None):
 def lpic_set_laser(h, r, laser):
     """laser: a Laser struct, or None to remove the run's antenna."""
     _check("lpic_set_laser", lib().lpic_set_laser(h, r, ctypes.byref(laser) if laser else None))
+
+
+def lpic_window_shift(h, r, m, plasma=None):
+    """Move box r's window by m cells (plasma: a Plasma struct for the fresh columns, or
+    None)."""
+    _check("lpic_window_shift",
+           lib().lpic_window_shift(h, r, m, ctypes.byref(plasma) if plasma else None))
+
+
+def lpic_window_info(h, r):
+    """(cells moved so far, fresh particles dropped for lack of slots)"""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check("lpic_window_info", lib().lpic_window_info(h, r, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def lpic_sim_create(grids, fields, species, species_run, species_alt, prec, options, stream=None):

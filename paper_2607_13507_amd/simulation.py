@@ -213,6 +213,30 @@ class Simulation:
         remove it with None."""
         L.lpic_set_laser(self.h, r, L.Laser(**laser) if laser else None)
 
+    def window_shift(self, r, m, plasma=None):
+        """Move box r's window by m cells in +x (open x ends).  plasma: dict(species=global
+        species index, ppc_x, ppc_y, density, ux=0, uy=0, uz=0) for the fresh columns."""
+        pl = None
+        if plasma:
+            pl = L.Plasma(plasma["species"], plasma["ppc_x"], plasma["ppc_y"], 0,
+                          plasma["density"], plasma.get("ux", 0.0), plasma.get("uy", 0.0),
+                          plasma.get("uz", 0.0))
+        L.lpic_window_shift(self.h, r, m, pl)
+
+    def window_info(self, r=0):
+        """(cells box r has moved, fresh particles dropped for lack of slots)"""
+        return L.lpic_window_info(self.h, r)
+
+    def box_fields(self, r=0):
+        """Field arrays of box r in the box frame (column 0 = the window's left end), as
+        float64 numpy arrays shaped (nz,) ny, nx."""
+        import numpy as np
+        shift = self.window_info(r)[0] % self.grids[r].nx
+        g = self.grids[r]
+        shape = (g.nz, g.ny, g.nx) if self.ndim == 3 else (g.ny, g.nx)
+        return {k: np.roll(v.reshape(shape).astype(np.float64), -shift, axis=-1)
+                for k, v in self.fields[r].numpy().items()}
+
     # -- state ------------------------------------------------------------------------------
     @property
     def time(self):
@@ -230,8 +254,17 @@ class Simulation:
         return b
 
     def positions(self, i):
+        """Absolute FP64 positions of species i in its box's frame (dead particles: -1)."""
         r = self.species_run[i]
-        return self.current(i).positions(self.grids[r], self.stream)
+        pos = self.current(i).positions(self.grids[r], self.stream)
+        shift = self.window_info(r)[0] % self.grids[r].nx if self.ndim == 2 else 0
+        if shift:   # the arrays' frame of a moved window: box x = array x - x0 dx (mod L)
+            g = self.grids[r]
+            x = pos[0]
+            alive = x >= 0.0
+            xb = x[alive] - shift * g.dx
+            x[alive] = np.where(xb < 0.0, xb + g.nx * g.dx, xb)
+        return pos
 
     def step(self, n=1):
         start = self.nstep
