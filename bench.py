@@ -91,10 +91,12 @@ def build_workload(args):
                 "FP32 cell+offset")
         return [wl], desc, 3, [8]
     if args.workload == "wakefield":
-        wl = W.wakefield_2d()
-        desc = (f"wakefield_2d 8192x512 dx=lambda/40, electrons 0.01 n_c 4 ppc "
-                f"({wl.nparticles} particles) on fixed ions, a0=2 pulse in a static window, "
-                "quadratic, periodic, FP32 cell+offset")
+        wl = W.wakefield_2d(moving=True)
+        alive0 = int((wl.species[0].x >= 0).sum())
+        desc = (f"wakefield_2d 8192x512 dx=lambda/40, electrons 0.01 n_c 4 ppc on a 2x2 "
+                f"lattice ({alive0} at start) on fixed ions, a0=2 waist 8 lambda pulse, "
+                "window moving with light (open x ends; fresh plasma injected at the leading "
+                "edge at every sort), quadratic, FP32 cell+offset")
         return [wl], desc, 2, [4]
     members = W.ensemble_2d(seed=4, members=64)
     n = sum(m.nparticles for m in members)
@@ -102,6 +104,35 @@ def build_workload(args):
             "128^2..1024x512, ppc 4-32, CIC/quadratic, lasers from the left, one step of all "
             "of them per launch, FP32 cell+offset")
     return members, desc, 2, [2 * m.meta["ppc"] for m in members]
+
+
+def alive(sim):
+    """Alive macro-particles of all species (dead slots excluded)."""
+    from paper_2607_13507_amd import lpic as L
+    n = 0
+    for i in range(len(sim.species)):
+        cur = sim.current(i)
+        key = "cell" if sim.prec == L.F32_CELLOFS else "x"
+        n += int((cur.a[key] >= 0).sum().item())
+    return n
+
+
+def advance(sim, wl, n):
+    """n steps; a box with a moving window moves with light at every sort boundary (its
+    fresh plasma then meets the regular sort), by the whole cells light has gained."""
+    win = wl[0].meta.get("window") if len(wl) == 1 else None
+    if not win:
+        sim.step(n)
+        return
+    k = sim.options.sort_interval
+    while n > 0:
+        take = min(n, k - sim.nstep % k)
+        sim.step(take)
+        n -= take
+        if sim.nstep % k == 0:
+            m = int(sim.nstep * win["cells_per_step"]) - sim.window_info(0)[0]
+            if m >= 1:
+                sim.window_shift(0, m, win["plasma"])
 
 
 def run_gpu(wl, prec, args, steps, warmup, tune):
@@ -138,42 +169,48 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
                                               tuned["sort_interval"])
     sim = Simulation(wl, prec=prec, tiling=tiling, halo=halo, chunk=chunk,
                      sort_interval=sort_interval, diag_interval=10, use_graph=not args.no_graph)
-    sim.step(warmup)
+    advance(sim, wl, warmup)
     # the timed steps start where a sort and a diagnostics step fall together, so that the
     # window holds at least its proportional share of both (whole periods: exactly)
     k = sim.options.sort_interval
     period = k // math.gcd(k, 10) * 10
-    sim.step((-sim.nstep) % period)
+    advance(sim, wl, (-sim.nstep) % period)
     torch.cuda.synchronize()
     # timed region: eager launches with HIP events around every fused launch
     sim.set_timing(True)
+    n0 = alive(sim)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps)
+    advance(sim, wl, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = sim.stats()
     sim.set_timing(False)
+    n = 0.5 * (n0 + alive(sim))   # pushes per step (a moving window adds particles)
     # the same number of steps again as captured graphs (no per-kernel events), after one
     # untimed sort period in graph mode so that every step variant is already captured
     if not args.no_graph:
-        sim.step(period + (-(sim.nstep + period)) % period)
+        advance(sim, wl, period + (-(sim.nstep + period)) % period)
+    torch.cuda.synchronize()
+    ng0 = alive(sim)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     if not args.no_graph:
-        sim.step(steps)
+        advance(sim, wl, steps)
     torch.cuda.synchronize()
     g1 = time.perf_counter()
+    ng = 0.5 * (ng0 + alive(sim))
     diag = sim.diagnostics(0)
     stg = sim.stats()
-    n = sum(w.nparticles for w in wl)
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps,
                pushes_per_s=n * steps / (t1 - t0),
+               alive=int(n),
                ms_per_step_graph=None if args.no_graph else 1e3 * (g1 - g0) / steps,
-               pushes_per_s_graph=None if args.no_graph else n * steps / (g1 - g0),
+               pushes_per_s_graph=None if args.no_graph else ng * steps / (g1 - g0),
                fused_ms=st["fused_ms"] / max(1, st["fused_launches"]),
                fused_launches=st["fused_launches"],
                halo_escapes_per_push=stg["halo_escapes"] / max(1, n * stg["steps"]),
+               window_cells=sim.window_info(0)[0] if wl[0].ndim == 2 else 0,
                graph=stg["graph"], diagnostics=diag, tuned=tuned,
                options=dict(tile=sim.options.tiling.tx, halo=sim.options.tiling.halo,
                             chunk=sim.options.tiling.chunk,
@@ -296,10 +333,13 @@ def main():
         s64 = max(5, args.steps // 5)
         f64 = run_gpu(wl, L.F64_ABS, args, s64, max(2, args.warmup // 5), tune)
 
+    slots = nparticles
+    nparticles = f32["alive"]   # alive macro-particles per timed step (dead slots excluded)
+
     def launch_bytes_of(f32_path):
         # particle state in and out once per particle; E, B in and J out once per occupied cell
         return sum(algorithmic_bytes_per_push(ndim, f32_path, p) * w.nparticles
-                   for w, p in zip(wl, ppc_tot))
+                   for w, p in zip(wl, ppc_tot)) * nparticles / slots
     launch_bytes = launch_bytes_of(True)
     bpp = launch_bytes / nparticles
     achieved = launch_bytes / (f32["fused_ms"] * 1e-3) / 1e9
@@ -360,6 +400,8 @@ def main():
                        "diagnostics": f64["diagnostics"]}
     if f32["tuned"]:
         out["autotuned"] = f32["tuned"]
+    if f32.get("window_cells"):
+        out["config"]["window_cells_moved"] = f32["window_cells"]
     if args.copy_calibration > 0:
         out["copy_calibration"] = copy_calibration(args.copy_calibration)
     print(json.dumps(out), flush=True)

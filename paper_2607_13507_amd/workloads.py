@@ -260,21 +260,45 @@ def ensemble_2d(seed=4, members=64, max_scale=1, sizes_x=(128, 256, 512, 1024),
 
 def wakefield_2d(nx=8192, ny=512, cells_per_lambda=40, density=0.01, ppc=4, a0=2.0,
                  waist_lambda=8.0, order=2, seed=5, eta=0.95, steps=20000, T=0.0,
-                 pulse_cells=None, name="wakefield_2d") -> Workload:
-    """Underdense electrons (fixed ions) filling the box behind an in-box Gaussian pulse."""
+                 pulse_cells=None, moving=False, spare=1 << 20,
+                 name="wakefield_2d") -> Workload:
+    """Underdense electrons (fixed ions) filling the box ahead of an in-box Gaussian pulse.
+
+    moving=False: a static periodic box, electrons random in their cells.
+    moving=True: the box has open x ends and is meant to move with the pulse at c
+    (meta["window"]: cells per step and the plasma to inject at the leading edge); the
+    electrons sit on a sqrt(ppc) x sqrt(ppc) lattice in every cell, as the injected plasma
+    will, and `spare` dead slots follow them for the injected particles."""
     rng = np.random.default_rng(seed)
     dx = LAMBDA / cells_per_lambda
     if pulse_cells is None:
         pulse_cells = min(nx // 4, 20 * cells_per_lambda)
-    cx, cy = _cell_lists_2d(pulse_cells, nx, 0, ny)
-    xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
-    xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
-    e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
+    dt = cfl_dt(eta, dx, dx)
+    meta = dict(ppc=ppc, density=density, order=order, seed=seed, a0=a0)
+    if moving:
+        side = int(round(math.sqrt(ppc)))
+        assert side * side == ppc, "a moving window injects a square lattice"
+        lo, hi = max(pulse_cells, 3), nx - 3          # between the open ends' margins
+        cx, cy = _cell_lists_2d(lo, hi, 0, ny)
+        sub = (np.arange(side) + 0.5) / side
+        oy, ox = np.meshgrid(sub, sub, indexing="ij")
+        xs = ((cx[:, None] + ox.reshape(1, -1)) * dx).reshape(-1)
+        ys = ((cy[:, None] + oy.reshape(1, -1)) * dx).reshape(-1)
+        dead = np.full(spare, -1.0)
+        xs, ys = np.concatenate([xs, dead]), np.concatenate([ys, dead])
+        e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
+        e.w[-spare:] = 0.0
+        meta["window"] = dict(cells_per_step=dt / dx,
+                              plasma=dict(species=0, ppc_x=side, ppc_y=side, density=density))
+    else:
+        cx, cy = _cell_lists_2d(pulse_cells, nx, 0, ny)
+        xs, ys, _ = _random_in_cells(rng, cx, cy, None, ppc, dx, dx, None)
+        xs, ys = _fold(xs, nx * dx), _fold(ys, ny * dx)
+        e = _thermal_species(rng, "electron", -1.0, 1.0, order, xs, ys, None, T, density, ppc)
     flds = gaussian_pulse_fields(nx, ny, dx, dx, a0, 0.0, pulse_cells * dx,
                                  waist_lambda * LAMBDA, 0.5 * ny * dx)
-    dt = cfl_dt(eta, dx, dx)
-    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, +density, [e], flds, steps,
-                    dict(ppc=ppc, density=density, order=order, seed=seed, a0=a0))
+    return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, +density, [e], flds, steps, meta,
+                    open_x=moving)
 
 
 def cold_langmuir(nx=64, ny=64, dx=0.05, lattice=4, amp=1e-3, order=1, eta=0.95, steps=1000,
