@@ -33,11 +33,29 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+class Pml(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("a_order", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("sigma_max", ctypes.c_double), ("kappa_max", ctypes.c_double),
+                ("a_max", ctypes.c_double), ("psi", _dp)]
+
+
 class Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("dz", ctypes.c_double), ("dt", ctypes.c_double), ("rho_bg", ctypes.c_double),
-                ("open_x", ctypes.c_int32)]
+                ("open_x", ctypes.c_int32), ("pml", ctypes.POINTER(Pml))]
+
+
+def pml_defaults(pml, dx):
+    """The layer parameters with their defaults filled in: order 3, a_order 1, sigma_max =
+    0.8 (m + 1) / dx (the usual choice for a graded layer, normalised impedance 1),
+    kappa_max 1, a_max 0."""
+    m = int(pml.get("order", 3))
+    sigma = pml.get("sigma_max")
+    return dict(cells=int(pml["cells"]), order=m, a_order=int(pml.get("a_order", 1)),
+                sigma_max=float(0.8 * (m + 1) / dx if sigma is None or sigma < 0 else sigma),
+                kappa_max=float(pml.get("kappa_max", 1.0)), a_max=float(pml.get("a_max", 0.0)))
 
 
 class Laser(ctypes.Structure):
@@ -134,9 +152,18 @@ class OracleSim:
     """One periodic run: grid, FP64 fields (flat, x fastest) and species."""
 
     def __init__(self, ndim, nx, ny, nz, dx, dy, dz, dt, rho_bg=0.0, species=(), fields=None,
-                 with_rho=True, open_x=False, laser=None):
+                 with_rho=True, open_x=False, laser=None, pml=None):
         self.grid = Grid(ndim, nx, ny, nz if ndim == 3 else 1, dx, dy, dz if ndim == 3 else 1.0,
-                         dt, rho_bg, int(bool(open_x)))
+                         dt, rho_bg, int(bool(open_x)), None)
+        self.pml = None
+        if pml:
+            assert open_x, "a PML needs open x ends"
+            p = pml_defaults(pml, dx)
+            assert p["cells"] >= 1 and 2 * p["cells"] < nx
+            self.psi = np.zeros(4 * 2 * p["cells"] * ny * (nz if ndim == 3 else 1))
+            self.pml = Pml(p["cells"], p["order"], p["a_order"], 0, p["sigma_max"],
+                           p["kappa_max"], p["a_max"], _ptr(self.psi))
+            self.grid.pml = ctypes.pointer(self.pml)
         self.laser = None if laser is None else Laser(**laser)
         self.ncell = nx * ny * (nz if ndim == 3 else 1)
         self.f = {k: np.zeros(self.ncell) for k in FIELD_NAMES}
@@ -154,7 +181,8 @@ class OracleSim:
         sp = [OracleSpecies(s.q, s.m, s.order, s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w)
               for s in wl.species]
         return cls(wl.ndim, wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.rho_bg, sp,
-                   wl.fields, with_rho, getattr(wl, "open_x", False), getattr(wl, "laser", None))
+                   wl.fields, with_rho, getattr(wl, "open_x", False), getattr(wl, "laser", None),
+                   getattr(wl, "pml", None))
 
     def fields_struct(self):
         f = self.f
@@ -234,6 +262,7 @@ class OracleSim:
         order column, row, lattice point (x fastest)."""
         g = self.grid
         assert g.ndim == 2 and g.open_x, "a moving window needs a 2D box with open x ends"
+        assert self.pml is None, "a moving window keeps the Mur condition"
         nx, ny = g.nx, g.ny
         arrays = [self.f[k] for k in FIELD_NAMES] + [a for a in (self.rho0, self.rho1)
                                                      if a is not None]

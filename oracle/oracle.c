@@ -125,12 +125,59 @@ static void save_column(const orc_grid *g, const double *u, int64_t i, double *o
     for (int64_t j = 0; j < g->ny; ++j) out[kk * g->ny + j] = u[nidx(g, i, j, kk)];
 }
 
+/* The convolutional PML of the header: is node column i in a layer, and which slot. */
+static int pml_slot(const orc_grid *g, int64_t i) {
+  if (!g->open_x || !g->pml) return -1;
+  int64_t L = g->pml->cells;
+  if (i < L) return (int)i;
+  if (i >= g->nx - L) return (int)(i - g->nx + 2 * L);
+  return -1;
+}
+
+/* Depth (cells) of slot l from its layer's inner face, for a location on a whole column
+ * (E side, half = 0) or half a column further in +x (B side, half = 1). */
+static double pml_depth(const orc_grid *g, int l, int half) {
+  double L = g->pml->cells;
+  double x = (l < g->pml->cells) ? (double)l : (double)(l - g->pml->cells) + (g->nx - L);
+  if (half) x += 0.5;
+  return (l < g->pml->cells) ? L - x : x - (g->nx - L);
+}
+
+/* The profiles at `depth` and the recursion coefficients for an update of step tau. */
+static void pml_coef(const orc_pml *p, double depth, double tau, double *b, double *c,
+                     double *kappa) {
+  double s = depth / p->cells;
+  double sm = 1.0;
+  for (int q = 0; q < p->order; ++q) sm *= s;
+  double sigma = p->sigma_max * sm;
+  *kappa = 1.0 + (p->kappa_max - 1.0) * sm;
+  double sa = 1.0;
+  for (int q = 0; q < p->a_order; ++q) sa *= 1.0 - s;
+  double a = p->a_max * sa;
+  *b = exp(-(sigma / *kappa + a) * tau);
+  *c = (sigma == 0.0) ? 0.0 : sigma * (*b - 1.0) / (*kappa * (sigma + *kappa * a));
+}
+
+/* Replaces the x derivative D of component comp at (slot, j, k) by D/kappa + psi after the
+ * recursion step of psi (header). */
+static double pml_apply(const orc_grid *g, int comp, int l, int64_t j, int64_t k,
+                        double depth, double tau, double D) {
+  const orc_pml *p = g->pml;
+  int64_t nz = (g->ndim == 3) ? g->nz : 1;
+  double *psi = p->psi + ((comp * 2 * (int64_t)p->cells + l) * nz + k) * g->ny + j;
+  double b, c, kappa;
+  pml_coef(p, depth, tau, &b, &c, &kappa);
+  *psi = b * *psi + c * D;
+  return D / kappa + *psi;
+}
+
 static void yee_e_all(const orc_grid *g, orc_fields *f, double frac);
 
 /* Sec. 3.2, Eq. 3 in normalised units: E += frac*dt*(curl B - J) on the Yee stagger; with
- * open x ends the tangential E of column 0 then follows the Mur condition. */
+ * open x ends the tangential E of column 0 then follows the Mur condition, or the x
+ * derivatives inside the PML layers take their convolutional form (header). */
 void orc_yee_e(const orc_grid *g, orc_fields *f, double frac) {
-  if (!g->open_x) {
+  if (!g->open_x || g->pml) {
     yee_e_all(g, f, frac);
     return;
   }
@@ -160,6 +207,12 @@ static void yee_e_all(const orc_grid *g, orc_fields *f, double frac) {
         double dBx_dy = (f->bx[c] - f->bx[nidx(g, i, j - 1, k)]) / g->dy;
         double dBy_dz = three ? (f->by[c] - f->by[nidx(g, i, j, k - 1)]) / g->dz : 0.0;
         double dBx_dz = three ? (f->bx[c] - f->bx[nidx(g, i, j, k - 1)]) / g->dz : 0.0;
+        int l = pml_slot(g, i);
+        if (l >= 0) {
+          double depth = pml_depth(g, l, 0);
+          dBz_dx = pml_apply(g, 0, l, j, k, depth, h, dBz_dx);
+          dBy_dx = pml_apply(g, 1, l, j, k, depth, h, dBy_dx);
+        }
         f->ex[c] += h * ((dBz_dy - dBy_dz) - f->jx[c]);
         f->ey[c] += h * ((dBx_dz - dBz_dx) - f->jy[c]);
         f->ez[c] += h * ((dBy_dx - dBx_dy) - f->jz[c]);
@@ -169,9 +222,10 @@ static void yee_e_all(const orc_grid *g, orc_fields *f, double frac) {
 static void yee_b_all(const orc_grid *g, orc_fields *f, double frac);
 
 /* Sec. 3.2, Eq. 4: B -= frac*dt*curl E on the Yee stagger; with open x ends the tangential
- * B of the last column then follows the Mur condition. */
+ * B of the last column then follows the Mur condition, or the x derivatives inside the
+ * PML layers take their convolutional form (header). */
 void orc_yee_b(const orc_grid *g, orc_fields *f, double frac) {
-  if (!g->open_x) {
+  if (!g->open_x || g->pml) {
     yee_b_all(g, f, frac);
     return;
   }
@@ -202,6 +256,12 @@ static void yee_b_all(const orc_grid *g, orc_fields *f, double frac) {
         double dEx_dy = (f->ex[nidx(g, i, j + 1, k)] - f->ex[c]) / g->dy;
         double dEy_dz = three ? (f->ey[nidx(g, i, j, k + 1)] - f->ey[c]) / g->dz : 0.0;
         double dEx_dz = three ? (f->ex[nidx(g, i, j, k + 1)] - f->ex[c]) / g->dz : 0.0;
+        int l = pml_slot(g, i);
+        if (l >= 0) {
+          double depth = pml_depth(g, l, 1);
+          dEz_dx = pml_apply(g, 2, l, j, k, depth, h, dEz_dx);
+          dEy_dx = pml_apply(g, 3, l, j, k, depth, h, dEy_dx);
+        }
         f->bx[c] -= h * (dEz_dy - dEy_dz);
         f->by[c] -= h * (dEx_dz - dEz_dx);
         f->bz[c] -= h * (dEy_dx - dEx_dy);

@@ -33,16 +33,44 @@
 extern "C" {
 #endif
 
+/* Convolutional PML at the open x ends (the absorbing layer that Sec. 3.2 attaches to the
+ * boundaries of the box, after Berenger; here in the recursive-convolution form of Roden
+ * and Gedney, Microw. Opt. Technol. Lett. 27, 334 (2000), with the complex frequency
+ * shift a).  The first and the last `cells` (L) node columns of x form the two layers; x
+ * stays circular, so the layers meet back to back across the wrap, and the Mur condition
+ * below is not applied.  Inside a layer every x derivative of the curls (dBz/dx in the Ey
+ * update, dBy/dx in Ez, dEz/dx in By, dEy/dx in Bz) is replaced by D/kappa + psi, where
+ * psi, one value per component and location, first takes
+ *     psi <- b psi + c D,   b = exp(-(sigma/kappa + a) tau),
+ *                           c = sigma (b - 1) / (kappa (sigma + kappa a)),
+ * tau the time step of that update (eps0 = mu0 = c = 1, so the magnetic profile equals the
+ * electric one).  Profiles, with s = depth / L and depth the distance in cells of the
+ * component's location from the layer's inner face (node column L on the left, nx - L on
+ * the right; E-side locations are whole columns, B-side ones half columns):
+ *     sigma = sigma_max s^m,  kappa = 1 + (kappa_max - 1) s^m,  a = a_max (1 - s)^ma
+ * (x^0 = 1: orders 0 make a uniform layer). */
+typedef struct {
+  int32_t cells;         /* L >= 1, 2 L < nx */
+  int32_t order;         /* grading exponent m >= 0 of sigma and kappa */
+  int32_t a_order;       /* grading exponent ma >= 0 of a */
+  int32_t reserved0;
+  double sigma_max, kappa_max, a_max;
+  double *psi;           /* 4 x (2L) x nz x ny auxiliary values, zero at the start; index
+                            ((comp * 2L + slot) * nz + k) * ny + j, comp 0..3 = Ey, Ez, By,
+                            Bz, slot = column i (left layer) or i - nx + 2L (right layer) */
+} orc_pml;
+
 typedef struct {
   int32_t ndim;          /* 2 or 3 */
   int32_t nx, ny, nz;    /* cells; nz = 1 when ndim == 2 */
   double dx, dy, dz, dt;
   double rho_bg;         /* fixed neutralising background charge density (added in Gauss) */
   int32_t open_x;        /* 0: periodic in x; 1: open x ends (see below) */
+  const orc_pml *pml;    /* NULL, or (with open_x) the layers above instead of Mur */
 } orc_grid;
 
 /* Open x ends (the absorbing boundaries of Sec. 3.2 and the particle loss at boundaries of
- * Sec. 2.1; the paper uses a CPML layer, this oracle the first-order Mur condition):
+ * Sec. 2.1), without a PML (pml == NULL) the first-order Mur condition:
  *   - fields: after each E update the tangential E at the first node column (i = 0) and
  *     after each B update the tangential B at the last column (i = nx-1) follow the
  *     outgoing-wave condition u_new(edge) = u_old(inner) + k (u_new(inner) - u_old(edge)),

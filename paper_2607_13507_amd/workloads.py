@@ -70,6 +70,8 @@ class Workload:
     meta: dict = field(default_factory=dict)
     open_x: bool = False                  # open (absorbing) x ends instead of periodic
     laser: Optional[dict] = None          # antenna: pol, ia, a0, omega, waist, yc, zc, t0, tau
+    pml: Optional[dict] = None            # open x ends: CPML layers (cells, order, sigma_max,
+                                          # kappa_max, a_max) instead of the Mur condition
 
     @property
     def ncell(self) -> int:
