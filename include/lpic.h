@@ -349,6 +349,38 @@ lpic_status lpic_set_options(lpic_sim *sim, const lpic_options *opt);
  * field updates are fused with the next step's -- see LPIC_FIELD_SEPARATE -- adds it inside
  * the E update instead of to the J array; J is cleared before anything else reads it.) */
 lpic_status lpic_set_laser(lpic_sim *sim, int32_t r, const lpic_laser *laser);
+
+/* Convolutional PML at the open x ends of run r (the absorbing layers Sec. 3.2 attaches to
+ * the boundaries of the box; recursive-convolution form of Roden and Gedney, 2000, with the
+ * complex frequency shift a), replacing the Mur condition of lpic_grid.open_x for that run.
+ * The first and the last `cells` (L) node columns of x are the two layers (x stays
+ * circular, so they meet back to back across the wrap).  Inside a layer each x derivative
+ * D of the curls (dBz/dx in the Ey update, dBy/dx in Ez, dEz/dx in By, dEy/dx in Bz)
+ * becomes D/kappa + psi, where psi (one value per component and location, held by the
+ * library) first takes psi <- b psi + c D over an update of step tau:
+ *   b = exp(-(sigma/kappa + a) tau),  c = sigma (b - 1) / (kappa (sigma + kappa a)),
+ *   sigma = sigma_max s^order, kappa = 1 + (kappa_max - 1) s^order, a = a_max (1-s)^a_order,
+ * s = depth / L, depth the distance in cells of the component's location from the layer's
+ * inner face (node column L on the left, nx - L on the right; E-side locations on whole
+ * columns, B-side ones half a column further in +x); x^0 = 1, so orders 0 give a uniform
+ * layer.  sigma_max < 0 selects 0.8 (order + 1) / dx.  An E update of a whole dt made of two
+ * merged halves applies the recursion twice.  Particles keep the open-end rule of
+ * lpic_grid; a laser antenna belongs outside the layers (inside one its field is damped).
+ * Requirements: run r has open_x; 1 <= cells, 2 cells <= nx - 8; order, a_order in [0, 8];
+ * kappa_max >= 1, a_max >= 0, all finite.  pml = NULL removes the layers (Mur again).  Every
+ * call sets psi to zero, rebuilds the device tables and drops captured graphs.  A run with
+ * layers cannot move a window (LPIC_EUNSUPPORTED). */
+typedef struct {
+  int32_t cells;             /* L: layer thickness in cells at each open x end */
+  int32_t order;             /* grading exponent of sigma and kappa (3 is usual) */
+  int32_t a_order;           /* grading exponent of a (1 is usual) */
+  int32_t reserved0;         /* 0 */
+  double sigma_max;          /* < 0: 0.8 (order + 1) / dx */
+  double kappa_max;          /* >= 1 */
+  double a_max;              /* >= 0, in units of the inverse time unit */
+} lpic_pml;
+lpic_status lpic_set_pml(lpic_sim *sim, int32_t r, const lpic_pml *pml);
+
 /* Fresh plasma for a moving window: ppc_x x ppc_y macro-particles per cell of species
  * `species` (a global species index of the run) on a regular lattice (offsets
  * (l + 1/2)/ppc per axis), weight density / (ppc_x ppc_y), momentum (ux, uy, uz). */

@@ -569,6 +569,9 @@ struct lpic_sim {
   unsigned long long* wmax = nullptr;        // per segment: max |w| (FP64 bits)
   std::vector<int> has_laser;                // per run
   std::vector<LaserDesc> lasers;             // per run
+  // convolutional PML per run (cells = 0: none) and its auxiliary values (2 halves)
+  std::vector<lpic_pml> pmls;
+  std::vector<void*> psi;
   // moving windows: per run the origin column and the total shift; per segment the fresh
   // particles written since the last sort; `windows` once any window has moved
   std::vector<int32_t> x0;
@@ -675,6 +678,15 @@ lpic_status configure(lpic_sim* s) {
   std::vector<int32_t> run_blk(1, 0);
   s->has_laser.resize(s->nruns, 0);
   s->lasers.resize(s->nruns);
+  s->pmls.resize(s->nruns, lpic_pml{});
+  s->psi.resize(s->nruns, nullptr);
+  if (!s->step_dev) {
+    if (hipMalloc((void**)&s->step_dev, 256) != hipSuccess)
+      return fail(LPIC_ENOMEM, "device allocation of 256 bytes failed");
+    s->laser_done = (unsigned int*)((char*)s->step_dev + 64);
+    HIPCHK(hipMemset(s->step_dev, 0, 256));
+  }
+  bool any_pml = false;
   s->x0.resize(s->nruns, 0);
   s->shifted.resize(s->nruns, 0);
   s->inject_used.resize(std::max(1, s->nsegs), 0);
@@ -685,6 +697,18 @@ lpic_status configure(lpic_sim* s) {
     d.has_laser = s->has_laser[r];
     d.laser = s->lasers[r];
     d.x0 = s->x0[r];
+    const lpic_pml& pm = s->pmls[r];
+    if (pm.cells > 0) {
+      any_pml = true;
+      d.pml_cells = pm.cells;
+      d.pml_order = pm.order;
+      d.pml_a_order = pm.a_order;
+      d.pml_sigma = pm.sigma_max;
+      d.pml_kappa = pm.kappa_max;
+      d.pml_a = pm.a_max;
+      d.psi = s->psi[r];
+      d.psi_parity = (const int32_t*)((char*)s->step_dev + 128);
+    }
     if (d.has_laser) s->laser_bpr = std::max(s->laser_bpr, columns_bpr(&s->grids[r]));
     s->runs_h.push_back(d);
     run_blk.push_back(run_blk.back() + (int32_t)((ncells(&s->grids[r]) + 255) / 256));
@@ -763,11 +787,6 @@ lpic_status configure(lpic_sim* s) {
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem_rho, &s->blocks_per_cu_rho));
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem, &s->blocks_per_cu));
-  if (!s->step_dev) {
-    ALLOC(s->step_dev, 256);
-    s->laser_done = (unsigned int*)((char*)s->step_dev + 64);
-    HIPCHK(hipMemset(s->step_dev, 0, 256));
-  }
   HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
   // fused 2D field update between steps: the largest field tile dividing every box
   free_dev(s->mid_pfx_d);
@@ -776,7 +795,7 @@ lpic_status configure(lpic_sim* s) {
   s->bands = nullptr;
   s->mid_tx = s->mid_ty = s->mid_ntiles = 0;
   s->band_half = 0;
-  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE) && !s->windows) {
+  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE) && !s->windows && !any_pml) {
     int tx = MID_MAX_TX, ty = MID_MAX_TY;
     for (int r = 0; r < s->nruns; ++r) {
       while (tx >= 8 && s->grids[r].nx % tx) tx >>= 1;
@@ -1085,6 +1104,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
   free_dev(s->mid_pfx_d); free_dev(s->bands);
   free_dev(s->old_state);
+  for (void* p : s->psi) free_dev(p);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
@@ -1253,11 +1273,49 @@ lpic_status lpic_set_laser(lpic_sim* s, int32_t r, const lpic_laser* laser) {
   return configure(s);   // rebuilds the device tables and the step counter, drops graphs
 }
 
+lpic_status lpic_set_pml(lpic_sim* s, int32_t r, const lpic_pml* pml) {
+  if (!s) return fail(LPIC_EINVAL, "sim is NULL");
+  if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "run index %d out of range", r);
+  const lpic_grid& g = s->grids[r];
+  s->pmls.resize(s->nruns, lpic_pml{});
+  s->psi.resize(s->nruns, nullptr);
+  if (pml) {
+    if (!g.open_x) return fail(LPIC_EINVAL, "a PML needs open x ends (grid.open_x)");
+    if (s->x0.size() > (size_t)r && s->shifted[r] != 0)
+      return fail(LPIC_EUNSUPPORTED, "box %d has moved its window", r);
+    if (pml->cells < 1 || 2 * pml->cells > g.nx - 8)
+      return fail(LPIC_EINVAL, "PML of %d cells in a box of %d", pml->cells, g.nx);
+    if (pml->order < 0 || pml->order > 8 || pml->a_order < 0 || pml->a_order > 8)
+      return fail(LPIC_EINVAL, "PML grading orders %d, %d outside [0, 8]", pml->order,
+                  pml->a_order);
+    if (!std::isfinite(pml->sigma_max) || !std::isfinite(pml->kappa_max) ||
+        !std::isfinite(pml->a_max) || !(pml->kappa_max >= 1.0) || !(pml->a_max >= 0.0))
+      return fail(LPIC_EINVAL, "PML needs finite sigma_max, kappa_max >= 1 and a_max >= 0");
+    if (pml->reserved0 != 0) return fail(LPIC_EINVAL, "lpic_pml.reserved0 must be 0");
+  }
+  free_dev(s->psi[r]);
+  s->psi[r] = nullptr;
+  s->pmls[r] = lpic_pml{};
+  if (pml) {
+    lpic_pml p = *pml;
+    if (p.sigma_max < 0.0) p.sigma_max = 0.8 * (p.order + 1) / g.dx;
+    const size_t bytes = (size_t)2 * 4 * g.ny * (s->ndim == 3 ? g.nz : 1) * 2 * p.cells *
+                         (s->prec == LPIC_F32_CELLOFS ? 4 : 8);
+    if (hipMalloc(&s->psi[r], bytes) != hipSuccess)
+      return fail(LPIC_ENOMEM, "PML allocation of %zu bytes failed", bytes);
+    HIPCHK(hipMemset(s->psi[r], 0, bytes));
+    s->pmls[r] = p;
+  }
+  return configure(s);   // device tables (and the field update path), drops graphs
+}
+
 lpic_status lpic_window_shift(lpic_sim* s, int32_t r, int32_t m, const lpic_plasma* plasma) {
   if (!s) return fail(LPIC_EINVAL, "sim is NULL");
   if (r < 0 || r >= s->nruns) return fail(LPIC_EINVAL, "run index %d out of range", r);
   const lpic_grid& g = s->grids[r];
   if (!g.open_x) return fail(LPIC_EINVAL, "a moving window needs open x ends");
+  if (s->pmls.size() > (size_t)r && s->pmls[r].cells > 0)
+    return fail(LPIC_EUNSUPPORTED, "box %d has PML layers (moving windows use Mur ends)", r);
   if (s->ndim != 2) return fail(LPIC_EUNSUPPORTED, "moving windows are 2D only");
   if (m < 1 || m > g.nx - 2 * LPIC_OPEN_MARGIN - 1)
     return fail(LPIC_EINVAL, "shift %d outside [1, nx - 7]", m);

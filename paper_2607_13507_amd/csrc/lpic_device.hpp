@@ -47,6 +47,11 @@ struct RunDesc {
   void* f[F_NUM];
   double* diag;                    // DIAG_NUM device accumulators
   LaserDesc laser;
+  // convolutional PML at the open x ends (pml_cells = 0: Mur condition instead)
+  int32_t pml_cells, pml_order, pml_a_order, pad1;
+  double pml_sigma, pml_kappa, pml_a;
+  void* psi;                       // 2 halves x 4 components x rows x 2 pml_cells values
+  const int32_t* psi_parity;       // which half is current (the fused field update's parity)
 };
 
 // Box column of array column i, and back (x0: the moving window's origin).

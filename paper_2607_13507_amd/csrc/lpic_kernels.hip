@@ -18,7 +18,8 @@ __global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
 // =======================================================================================
 struct CellIdx {
   int64_t c, cim, cip, cjm, cjp, ckm, ckp;
-  int i;   // x index
+  int64_t row;   // k ny + j
+  int i;         // x index
 };
 
 __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, CellIdx& x) {
@@ -40,6 +41,7 @@ __device__ __forceinline__ bool cell_index(const RunDesc& r, int blk, int dim, C
   }
   x.i = i;
   x.c = c;
+  x.row = (int64_t)k * r.ny + j;
   x.cim = c + (i == 0 ? r.nx - 1 : -1);
   x.cip = c + (i == r.nx - 1 ? 1 - r.nx : 1);
   x.cjm = c + (j == 0 ? (int64_t)(r.ny - 1) * r.nx : -(int64_t)r.nx);
@@ -101,6 +103,54 @@ __device__ __forceinline__ R mur_edge(R u_edge_old, R u_in_old, R d, double h, d
   return u_in_old + k * ((u_in_old + d) - u_edge_old);
 }
 
+// ---------------------------------------------------------------------------------------
+// Convolutional PML at the open x ends (lpic_set_pml).  The auxiliary values psi are held
+// in units of a difference (psi * dx), so that a stretched difference is D/kappa + psi with
+// D the plain difference of two neighbouring values.
+// ---------------------------------------------------------------------------------------
+// Slot of array column i in the auxiliary arrays: 0 .. L-1 the left layer, L .. 2L-1 the
+// right one, -1 outside both.
+__device__ __forceinline__ int pml_slot(const RunDesc& r, int i) {
+  const int L = r.pml_cells;
+  if (L == 0) return -1;
+  const int p = box_x(r, i);
+  return p < L ? p : (p >= r.nx - L ? p - r.nx + 2 * L : -1);
+}
+
+// One stretched x difference at slot `slot` of row `row` for component comp (0 Ey, 1 Ez:
+// E side, locations on whole columns; 2 By, 3 Bz: B side, half a column further in +x):
+// advances psi over `steps` updates of step tau with the same difference D (an E update of
+// a whole dt made of two merged halves takes steps = 2 and returns the mean of the two
+// stretched differences), stores psi and returns the stretched difference.
+template <typename R>
+__device__ __forceinline__ R pml_stretch(const RunDesc& r, int comp, int64_t row, int slot,
+                                         double tau, int steps, R D) {
+  const int L = r.pml_cells;
+  const double half = comp >= 2 ? 0.5 : 0.0;
+  const double depth = slot < L ? (L - slot) - half : (slot - L) + half;
+  const double s = depth / L;
+  double sm = 1.0, sa = 1.0;
+  for (int q = 0; q < r.pml_order; ++q) sm *= s;
+  for (int q = 0; q < r.pml_a_order; ++q) sa *= 1.0 - s;
+  const double sigma = r.pml_sigma * sm, kappa = 1.0 + (r.pml_kappa - 1.0) * sm;
+  const double a = r.pml_a * sa;
+  const double bd = exp(-(sigma / kappa + a) * tau);
+  const R b = R(bd);
+  const R c = R(sigma > 0.0 ? sigma * (bd - 1.0) / (kappa * (sigma + kappa * a)) : 0.0);
+  const R ik = R(1.0 / kappa);
+  const int64_t rows = (int64_t)r.ny * r.nz;
+  const int par = r.psi_parity ? (*r.psi_parity & 1) : 0;
+  R* psi = (R*)r.psi + ((int64_t)(par * 4 + comp) * rows + row) * (2 * L) + slot;
+  const R p1 = b * *psi + c * D;
+  if (steps == 1) {
+    *psi = p1;
+    return D * ik + p1;
+  }
+  const R p2 = b * p1 + c * D;
+  *psi = p2;
+  return D * ik + R(0.5) * (p1 + p2);
+}
+
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j, int halves) {
   int blk;
@@ -114,14 +164,23 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0), hh = R(h);
   R dex, dey, dez;
   yee_e_delta<R, DIM>(f, x, hx, hy, hz, hh, dex, dey, dez);
+  const int ps = pml_slot(r, x.i);
+  if (ps >= 0) {   // in a PML layer: the x differences of Bz and By are stretched
+    const R dbz = f[F_BZ][x.c] - f[F_BZ][x.cim], dby = f[F_BY][x.c] - f[F_BY][x.cim];
+    const int64_t row = x.row;
+    const double tau = halves == 2 ? 0.5 * h : h;
+    dey += hx * (dbz - pml_stretch<R>(r, 0, row, ps, tau, halves, dbz));
+    dez -= hx * (dby - pml_stretch<R>(r, 1, row, ps, tau, halves, dby));
+  }
   f[F_EX][x.c] += dex;
   const int bxi = box_x(r, x.i);   // box column (a moving window shifts the arrays' origin)
-  if (r.open_x && bxi == 1) {   // Mur for column 0 (same j, k)
+  const bool mur = r.open_x && r.pml_cells == 0;
+  if (mur && bxi == 1) {   // Mur for column 0 (same j, k)
     const R ey1 = f[F_EY][x.c], ez1 = f[F_EZ][x.c];
     f[F_EY][x.cim] = mur_edge<R>(f[F_EY][x.cim], ey1, dey, h, r.dx, halves);
     f[F_EZ][x.cim] = mur_edge<R>(f[F_EZ][x.cim], ez1, dez, h, r.dx, halves);
   }
-  if (!(r.open_x && bxi == 0)) {   // column 0 of an open end: set by the thread of column 1
+  if (!(mur && bxi == 0)) {   // column 0 of an open end: set by the thread of column 1
     f[F_EY][x.c] += dey;
     f[F_EZ][x.c] += dez;
   }
@@ -195,11 +254,19 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac, FieldBands
   const R hx = R(h / r.dx), hy = R(h / r.dy), hz = R(DIM == 3 ? h / r.dz : 0.0);
   R dbx, dby, dbz;
   yee_b_delta<R, DIM>(f, x, hx, hy, hz, dbx, dby, dbz);
+  const int ps = pml_slot(r, x.i);
+  if (ps >= 0) {   // in a PML layer: the x differences of Ez and Ey are stretched
+    const R dez = f[F_EZ][x.cip] - f[F_EZ][x.c], dey = f[F_EY][x.cip] - f[F_EY][x.c];
+    const int64_t row = x.row;
+    dby -= hx * (dez - pml_stretch<R>(r, 2, row, ps, h, 1, dez));
+    dbz += hx * (dey - pml_stretch<R>(r, 3, row, ps, h, 1, dey));
+  }
   const R bx = f[F_BX][x.c] + dbx;
   f[F_BX][x.c] = bx;
   const int bxi = box_x(r, x.i);   // box column (a moving window shifts the arrays' origin)
-  const bool edge_in = r.open_x && bxi == r.nx - 2;
-  const bool edge = r.open_x && bxi == r.nx - 1;
+  const bool mur = r.open_x && r.pml_cells == 0;
+  const bool edge_in = mur && bxi == r.nx - 2;
+  const bool edge = mur && bxi == r.nx - 1;
   R by_e = R(0), bz_e = R(0);
   if (edge_in) {   // Mur for column nx-1 (same j, k)
     const R by1 = f[F_BY][x.c], bz1 = f[F_BZ][x.c];

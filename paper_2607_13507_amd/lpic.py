@@ -52,6 +52,13 @@ class Plasma(ctypes.Structure):
                 ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("uz", ctypes.c_double)]
 
 
+class Pml(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("a_order", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("sigma_max", ctypes.c_double), ("kappa_max", ctypes.c_double),
+                ("a_max", ctypes.c_double)]
+
+
 class Fields(ctypes.Structure):
     _fields_ = [(n, _vp) for n in ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz",
                                    "rho0", "rho1")]
@@ -128,6 +135,7 @@ EXPORTS = {
                                          ctypes.POINTER(Laser), ctypes.c_double, ctypes.c_int,
                                          _vp]),
     "lpic_set_laser": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Laser)]),
+    "lpic_set_pml": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Pml)]),
     "lpic_window_shift": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(Plasma)]),
     "lpic_window_info": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -274,6 +282,11 @@ def lpic_laser_source(grid, fields, laser, t, prec, stream=None):
 def lpic_set_laser(h, r, laser):
     """laser: a Laser struct, or None to remove the run's antenna."""
     _check("lpic_set_laser", lib().lpic_set_laser(h, r, ctypes.byref(laser) if laser else None))
+
+
+def lpic_set_pml(h, r, pml):
+    """pml: a Pml struct for run r's open x ends, or None for the Mur condition."""
+    _check("lpic_set_pml", lib().lpic_set_pml(h, r, ctypes.byref(pml) if pml else None))
 
 
 def lpic_window_shift(h, r, m, plasma=None):

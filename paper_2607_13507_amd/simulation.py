@@ -203,6 +203,8 @@ class Simulation:
         for r, w in enumerate(wls):   # laser antennas (GaussianLaser, Sec. 2.2)
             if getattr(w, "laser", None):
                 self.set_laser(r, w.laser)
+            if getattr(w, "pml", None):
+                self.set_pml(r, w.pml)
 
     def species_of_run(self, r) -> List[int]:
         """Global indices of run r's species, in the order its workload lists them."""
@@ -212,6 +214,17 @@ class Simulation:
         """Attach the antenna `laser` (dict with the fields of lpic_laser) to run r, or
         remove it with None."""
         L.lpic_set_laser(self.h, r, L.Laser(**laser) if laser else None)
+
+    def set_pml(self, r, pml):
+        """Convolutional PML layers at run r's open x ends (dict: cells, order=3, a_order=1,
+        sigma_max=-1 for 0.8 (order + 1) / dx, kappa_max=1, a_max=0), or None for Mur."""
+        p = None
+        if pml:
+            p = L.Pml(int(pml["cells"]), int(pml.get("order", 3)), int(pml.get("a_order", 1)),
+                      0, float(pml.get("sigma_max", -1.0) if pml.get("sigma_max") is not None
+                               else -1.0),
+                      float(pml.get("kappa_max", 1.0)), float(pml.get("a_max", 0.0)))
+        L.lpic_set_pml(self.h, r, p)
 
     def window_shift(self, r, m, plasma=None):
         """Move box r's window by m cells in +x (open x ends).  plasma: dict(species=global

@@ -1,0 +1,182 @@
+"""Convolutional PML at the open x ends (lpic_set_pml) on the GPU against the FP64 oracle's
+layer, through the C ABI: whole steps with particles crossing the layers, a laser antenna
+outside them, sorts and diagnostic steps (FP64: rounding order only, 1e-10 of each
+component's largest value; FP32: tracking, 1e-4), a 45-degree packet leaving through the
+layer over many FP32 steps (reflection measured against the oracle's unbounded reference),
+and the entry point's argument checks."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner, compare_fields, compare_particles
+from oracle import OracleSim
+from paper_2607_13507_amd import lpic as L
+from paper_2607_13507_amd import workloads as W
+from paper_2607_13507_amd.simulation import Simulation
+
+pytestmark = pytest.mark.gpu
+
+PML = dict(cells=8, order=3, a_order=1, kappa_max=3.0, a_max=0.5)   # every term in play
+KEYS = ("ex", "ey", "ez", "bx", "by", "bz")
+
+
+def _pml_box(ndim, seed=81):
+    if ndim == 2:
+        wl = W.thermal_2d(nx=48, ny=40, dx=0.1, ppc=4, T=0.2, order=2, seed=seed)
+        las = dict(pol=1, ia=10, a0=2.0, omega=4.0, waist=1.2, yc=2.0, zc=0.0, t0=0.0, tau=3.0)
+    else:
+        wl = W.thermal_3d(n=32, dx=0.1, ppc=1, T=0.2, order=2, seed=seed)
+        las = dict(pol=2, ia=10, a0=2.0, omega=4.0, waist=0.6, yc=1.6, zc=1.6, t0=0.0, tau=3.0)
+    wl.open_x = True
+    wl.laser = las
+    wl.pml = dict(PML)
+    wl.fields = W.random_fields(wl.ncell, seed + 1, 0.3)
+    for s in wl.species:   # unique weights: particles are followed through the sorts
+        s.w = s.w * (1.0 + 1e-3 * np.arange(s.n) / s.n)
+    return wl
+
+
+def _oracle_like(sim, wl):
+    orc = OracleSim.from_workload(wl)
+    for k, v in sim.fields[0].numpy().items():
+        if k in orc.f:
+            orc.f[k][:] = v
+    for i, s in enumerate(orc.species):
+        pos = sim.positions(i)
+        s.x[:], s.y[:] = pos[0], pos[1]
+        if wl.ndim == 3:
+            s.z[:] = pos[2]
+        cur = sim.current(i)
+        for k in ("ux", "uy", "uz", "w"):
+            getattr(s, k)[:] = cur.numpy(k)
+    return orc
+
+
+def _follow_gpu_order(orc_s, sim, i):
+    tags = sim.current(i).numpy("w").astype(np.float64)
+    idx = np.argsort(orc_s.w)
+    perm = idx[np.searchsorted(orc_s.w[idx], tags)]
+    for k in ("x", "y", "z", "ux", "uy", "uz", "w"):
+        a = getattr(orc_s, k)
+        if a is not None:
+            a[:] = a[perm]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_pml_steps_match_oracle(ndim, graph):
+    banner(f"pml f64 steps ndim={ndim} graph={graph}")
+    wl = _pml_box(ndim)
+    tiling, halo = ((8, 8, 1), 4) if ndim == 2 else ((8, 4, 4), 3)
+    sim = Simulation(wl, prec=L.F64_ABS, tiling=tiling, halo=halo, chunk=128, sort_interval=3,
+                     diag_interval=4, use_graph=graph)
+    assert sim.stats()["field_tile"] == (0, 0)   # separate field kernels with layers
+    orc = _oracle_like(sim, wl)
+    assert orc.pml is not None
+    sim.step(7)        # one call: the E updates between its steps are two merged halves
+    orc.step(7)
+    sim.step(9)
+    orc.step(9)
+    torch.cuda.synchronize()
+    compare_fields(sim.fields[0], orc, L.F64_ABS, tol=1e-10, what="fields")
+    _follow_gpu_order(orc.species[0], sim, 0)
+    np.testing.assert_array_equal(sim.positions(0)[0] < 0, orc.species[0].x < 0)
+    compare_particles(sim.grids[0], sim.current(0), orc.species[0], L.F64_ABS, tol_pos=1e-10,
+                      tol_u=1e-10)
+    d = sim.diagnostics(0)
+    assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-10)
+    assert d["continuity"] < 1e-12
+    assert np.abs(orc.psi).max() > 1e-3   # the layers did work
+    sim.close()
+
+
+def test_pml_fp32_tracks_oracle_and_conserves_charge():
+    banner("pml f32 steps")
+    wl = _pml_box(2, seed=83)
+    sim = Simulation(wl, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=4, chunk=256,
+                     sort_interval=4, diag_interval=1, use_graph=True)
+    orc = _oracle_like(sim, wl)
+    for n in range(1, 9):
+        sim.step(1)
+        orc.step(1)
+        d = sim.diagnostics(0)
+        assert d["continuity"] < 1e-5, (n, d)
+        if n <= 4:
+            compare_fields(sim.fields[0], orc, L.F32_CELLOFS, tol=1e-4, what=f"step {n}")
+            assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-4)
+    sim.close()
+
+
+def _packet_45(nx, ny, x_lo, x_hi, dx):
+    """Plane-wave packet, E along z, |k| = 1 at about 45 degrees (ky = 2 pi / (ny dy)), sin^2
+    envelope along x; B the discrete curl of A_z."""
+    ky = 2 * math.pi / (ny * dx)
+    kx = math.sqrt(1.0 - ky * ky)
+    i = np.arange(nx)[None, :] * dx
+    j = np.arange(ny)[:, None] * dx
+    s = np.clip((i - x_lo) / (x_hi - x_lo), 0.0, 1.0)
+    env = np.sin(math.pi * s) ** 2
+    ph = kx * (i - x_lo) + ky * j
+    az = -env * np.cos(ph)
+    return {"ez": (env * np.sin(ph)).ravel(),
+            "bx": ((np.roll(az, -1, axis=0) - az) / dx).ravel(),
+            "by": (-(np.roll(az, -1, axis=1) - az) / dx).ravel()}, kx
+
+
+def test_oblique_packet_leaves_through_the_layer_fp32():
+    """FP32, graph replay, ~840 steps: a 45-degree packet crosses a 400 x 45 box and leaves
+    through a 12-cell graded layer; the field left in the interior differs from the same
+    packet in an unbounded (oracle, periodic, wide) box by less than 1e-6 of its energy (the
+    first-order Mur condition leaves ~3.5e-2 there)."""
+    banner("pml oblique packet f32")
+    nx, ny, pad, Lc = 400, 45, 300, 12
+    dx = 2 * math.pi / 32
+    dt = W.cfl_dt(0.95, dx, dx)
+    c0 = 0.5 * nx * dx
+    f, kx = _packet_45(nx, ny, c0 - 64 * dx, c0 + 64 * dx, dx)
+    wl = W.Workload("pml_packet", 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [], f, 1, {},
+                    open_x=True, pml=dict(cells=Lc))
+    sim = Simulation(wl, prec=L.F32_CELLOFS, diag_interval=0, use_graph=True)
+    fr, _ = _packet_45(nx + 2 * pad, ny, c0 + (pad - 64) * dx, c0 + (pad + 64) * dx, dx)
+    ref = OracleSim(2, nx + 2 * pad, ny, 1, dx, dx, 1.0, dt, 0.0, [], fr)
+    e0 = ref.field_energy()
+    steps = int(nx * dx / (kx * dt))
+    sim.step(steps)
+    ref.step(steps)
+    torch.cuda.synchronize()
+    g = sim.fields[0].numpy()
+    d = sum(((g[k].reshape(ny, nx)[:, Lc:nx - Lc].astype(np.float64)
+              - ref.f[k].reshape(ny, nx + 2 * pad)[:, pad + Lc:pad + nx - Lc]) ** 2).sum()
+            for k in KEYS)
+    refl = 0.5 * d * dx * dx / e0
+    assert refl < 1e-6, refl
+    sim.close()
+
+
+def test_pml_arguments_and_removal():
+    banner("pml arguments")
+    wl = W.thermal_2d(nx=64, ny=32, dx=0.1, ppc=1, T=0.1, order=1, seed=85)
+    wl.open_x = True
+    sim = Simulation(wl, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=4, use_graph=False)
+    assert sim.stats()["field_tile"] != (0, 0)      # Mur ends: fused field update
+    for bad in (dict(cells=0), dict(cells=29), dict(cells=8, order=9),
+                dict(cells=8, kappa_max=0.5), dict(cells=8, a_max=-1.0)):
+        with pytest.raises(RuntimeError):
+            sim.set_pml(0, bad)
+    sim.set_pml(0, dict(cells=8))
+    assert sim.stats()["field_tile"] == (0, 0)
+    sim.step(3)
+    with pytest.raises(RuntimeError, match="PML"):
+        sim.window_shift(0, 2)
+    sim.set_pml(0, None)                             # Mur again
+    assert sim.stats()["field_tile"] != (0, 0)
+    sim.step(2)
+    torch.cuda.synchronize()
+    sim.close()
+    per = W.thermal_2d(nx=64, ny=32, dx=0.1, ppc=1, T=0.1, order=1, seed=86)
+    sim = Simulation(per, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=4, use_graph=False)
+    with pytest.raises(RuntimeError, match="open x"):
+        sim.set_pml(0, dict(cells=8))
+    sim.close()
