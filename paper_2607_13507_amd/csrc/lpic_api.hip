@@ -686,7 +686,6 @@ lpic_status configure(lpic_sim* s) {
     s->laser_done = (unsigned int*)((char*)s->step_dev + 64);
     HIPCHK(hipMemset(s->step_dev, 0, 256));
   }
-  bool any_pml = false;
   s->x0.resize(s->nruns, 0);
   s->shifted.resize(s->nruns, 0);
   s->inject_used.resize(std::max(1, s->nsegs), 0);
@@ -699,7 +698,6 @@ lpic_status configure(lpic_sim* s) {
     d.x0 = s->x0[r];
     const lpic_pml& pm = s->pmls[r];
     if (pm.cells > 0) {
-      any_pml = true;
       d.pml_cells = pm.cells;
       d.pml_order = pm.order;
       d.pml_a_order = pm.a_order;
@@ -795,7 +793,7 @@ lpic_status configure(lpic_sim* s) {
   s->bands = nullptr;
   s->mid_tx = s->mid_ty = s->mid_ntiles = 0;
   s->band_half = 0;
-  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE) && !s->windows && !any_pml) {
+  if (s->ndim == 2 && !(t.flags & LPIC_FIELD_SEPARATE) && !s->windows) {
     int tx = MID_MAX_TX, ty = MID_MAX_TY;
     for (int r = 0; r < s->nruns; ++r) {
       while (tx >= 8 && s->grids[r].nx % tx) tx >>= 1;
@@ -989,7 +987,9 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     // this step's last field halves and the next step's first ones, fused
     Tables Tm = Tc;
     Tm.run_blk = s->mid_pfx_d;
-    launch_yee_mid(Tm, s->prec, s->mid_ntiles, bands, st);
+    bool pml = false;
+    for (const lpic_pml& p : s->pmls) pml = pml || p.cells > 0;
+    launch_yee_mid(Tm, s->prec, s->mid_ntiles, bands, pml, st);
     CHK(last_launch("yee fused"));
   } else {
     // field half update t + dt/2 -> t + dt (B first)

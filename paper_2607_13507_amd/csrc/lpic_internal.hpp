@@ -51,8 +51,10 @@ void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, doub
 // in the E update instead of through the array, so the antenna kernel is not launched for
 // the step.  The next launch on the stream must be launch_clear_sources with
 // flip = bands.parity and clock = bands.step: it clears J for the next deposit, names the
-// new snapshot and advances the antenna clock.
-void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands,
+// new snapshot and advances the antenna clock.  pml: some run has PML layers (their psi
+// follow the same two-half scheme, with the same parity word); false selects kernels
+// without that code.
+void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands, bool pml,
                     hipStream_t st);
 // J := 0 (and the charge arrays when with_rho) over every cell of every run (nblocks: the
 // 256-cell blocks of T.run_blk).  flip != NULL: also *flip ^= 1 and, clock != NULL,

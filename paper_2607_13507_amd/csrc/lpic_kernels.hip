@@ -117,16 +117,13 @@ __device__ __forceinline__ int pml_slot(const RunDesc& r, int i) {
   return p < L ? p : (p >= r.nx - L ? p - r.nx + 2 * L : -1);
 }
 
-// One stretched x difference at slot `slot` of row `row` for component comp (0 Ey, 1 Ez:
-// E side, locations on whole columns; 2 By, 3 Bz: B side, half a column further in +x):
-// advances psi over `steps` updates of step tau with the same difference D (an E update of
-// a whole dt made of two merged halves takes steps = 2 and returns the mean of the two
-// stretched differences), stores psi and returns the stretched difference.
+// Recursion coefficients b, c and 1/kappa at slot `slot` for an update of step tau; B-side
+// locations (bside) lie half a column further in +x than the E-side ones.
 template <typename R>
-__device__ __forceinline__ R pml_stretch(const RunDesc& r, int comp, int64_t row, int slot,
-                                         double tau, int steps, R D) {
+__device__ __forceinline__ void pml_coef(const RunDesc& r, bool bside, int slot, double tau,
+                                         R& b, R& c, R& ik) {
   const int L = r.pml_cells;
-  const double half = comp >= 2 ? 0.5 : 0.0;
+  const double half = bside ? 0.5 : 0.0;
   const double depth = slot < L ? (L - slot) - half : (slot - L) + half;
   const double s = depth / L;
   double sm = 1.0, sa = 1.0;
@@ -135,12 +132,32 @@ __device__ __forceinline__ R pml_stretch(const RunDesc& r, int comp, int64_t row
   const double sigma = r.pml_sigma * sm, kappa = 1.0 + (r.pml_kappa - 1.0) * sm;
   const double a = r.pml_a * sa;
   const double bd = exp(-(sigma / kappa + a) * tau);
-  const R b = R(bd);
-  const R c = R(sigma > 0.0 ? sigma * (bd - 1.0) / (kappa * (sigma + kappa * a)) : 0.0);
-  const R ik = R(1.0 / kappa);
+  b = R(bd);
+  c = R(sigma > 0.0 ? sigma * (bd - 1.0) / (kappa * (sigma + kappa * a)) : 0.0);
+  ik = R(1.0 / kappa);
+}
+
+// Index of psi for component comp (0 Ey, 1 Ez, 2 By, 3 Bz) at (row, slot) in half `half`.
+__device__ __forceinline__ int64_t pml_index(const RunDesc& r, int half, int comp, int64_t row,
+                                             int slot) {
   const int64_t rows = (int64_t)r.ny * r.nz;
-  const int par = r.psi_parity ? (*r.psi_parity & 1) : 0;
-  R* psi = (R*)r.psi + ((int64_t)(par * 4 + comp) * rows + row) * (2 * L) + slot;
+  return ((int64_t)(half * 4 + comp) * rows + row) * (2 * r.pml_cells) + slot;
+}
+
+__device__ __forceinline__ int pml_half(const RunDesc& r) {
+  return r.psi_parity ? (*r.psi_parity & 1) : 0;
+}
+
+// One stretched x difference of component comp at (row, slot), in place in the current
+// half: advances psi over `steps` updates of step tau with the same plain difference D (an
+// E update of a whole dt made of two merged halves takes steps = 2 and returns the mean of
+// the two stretched differences) and returns the stretched difference.
+template <typename R>
+__device__ __forceinline__ R pml_stretch(const RunDesc& r, int comp, int64_t row, int slot,
+                                         double tau, int steps, R D) {
+  R b, c, ik;
+  pml_coef<R>(r, comp >= 2, slot, tau, b, c, ik);
+  R* psi = (R*)r.psi + pml_index(r, pml_half(r), comp, row, slot);
   const R p1 = b * *psi + c * D;
   if (steps == 1) {
     *psi = p1;
@@ -340,7 +357,7 @@ __device__ __forceinline__ void ring_cell(int h, int& u, int& v) {
   }
 }
 
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, bool PML>
 __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   constexpr int EW = TX + 3, EH = TY + 3, BW = TX + 2, BH = TY + 2, NC = TX * TY;
   constexpr int LX = Log2<TX>::v;
@@ -470,29 +487,68 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   const double h1 = 0.5 * r.dt, h2 = r.dt;
   const R hx1 = R(h1 / r.dx), hy1 = R(h1 / r.dy);
   const R hx2 = R(h2 / r.dx), hy2 = R(h2 / r.dy), hh2 = R(h2);
-  const bool open = r.open_x != 0;
-  // 1. B half update on the whole B region (reads E only)
-  for (int q = tid; q < BW * BH; q += 256) {
-    const int v = q / BW, u = q - v * BW;
-    const int ie = v * EW + u, gu = a - 1 + u;
+  const bool mur = r.open_x != 0 && r.pml_cells == 0;
+  // PML layers (lpic_set_pml) in reach of this tile: psi is read from the current half
+  // and, for the tile's own cells, written to the other half (the neighbours recompute
+  // this tile's edge values from the current half during this launch)
+  const int PL = r.pml_cells;
+  const bool pml_tile = PML && PL > 0 && (a - 1 < PL || a + TX + 1 > nx - PL);
+  const int hcur = pml_tile ? pml_half(r) : 0;
+  R* psi = (R*)r.psi;
+  // 1. B half update on the whole B region (reads E only): the tile's cells (their psi
+  // kept for the second B half), then the ring around it
+  auto b_first = [&](int u, int v, R* keep) {
+    const int ie = v * EW + u, q = v * BW + u, gu = a - 1 + u;
     const R ex = sE[0][ie], ey = sE[1][ie], ez = sE[2][ie];
     const R dbx = -hy1 * (sE[2][ie + EW] - ez);
-    const R dby = hx1 * (sE[2][ie + 1] - ez);
-    const R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+    R dby = hx1 * (sE[2][ie + 1] - ez);
+    R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+    if (pml_tile) {
+      const int sl = pml_slot(r, wrap_once(gu, nx));
+      if (sl >= 0) {
+        const int64_t row = wrap_once(c - 1 + v, ny);
+        R pb, pc, ik;
+        pml_coef<R>(r, true, sl, h1, pb, pc, ik);
+        const R Dz = sE[2][ie + 1] - ez, Dy = sE[1][ie + 1] - ey;
+        const R p2 = pb * psi[pml_index(r, hcur, 2, row, sl)] + pc * Dz;
+        const R p3 = pb * psi[pml_index(r, hcur, 3, row, sl)] + pc * Dy;
+        dby = hx1 * (Dz * ik + p2);
+        dbz = -hx1 * (Dy * ik + p3) + hy1 * (sE[0][ie + EW] - ex);
+        if (keep) {
+          keep[0] = p2;
+          keep[1] = p3;
+        }
+      }
+    }
     sB[0][q] += dbx;
-    if (open && gu == nx - 2 && u + 1 < BW) {   // Mur for column nx-1
+    if (mur && gu == nx - 2 && u + 1 < BW) {   // Mur for column nx-1
       sB[1][q + 1] = mur_edge<R>(sB[1][q + 1], sB[1][q], dby, h1, r.dx, 1);
       sB[2][q + 1] = mur_edge<R>(sB[2][q + 1], sB[2][q], dbz, h1, r.dx, 1);
     }
-    if (!(open && gu == nx - 1 && u >= 1)) {
+    if (!(mur && gu == nx - 1 && u >= 1)) {
       sB[1][q] += dby;
       sB[2][q] += dbz;
+    }
+  };
+  R keep[PER][2];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = tid + p * 256;
+    if (NC % 256 == 0 || q < NC) b_first((q & (TX - 1)) + 1, (q >> LX) + 1, keep[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < NBR; ++p) {
+    const int h = tid + p * 256;
+    if (h < BR) {
+      int u, v;
+      ring_cell<TX, TY, 1>(h, u, v);
+      b_first(u, v, nullptr);
     }
   }
   __syncthreads();
   // 2. E full update on [a, a+TX+1) x [c, c+TY+1) (reads B): the tile's cells with the J
   // held by their threads, then the column and row past the tile
-  auto e_update = [&](int u, int v, R jx, R jy, R jz) {
+  auto e_update = [&](int u, int v, R jx, R jy, R jz, bool own) {
     const int ib = v * BW + u, ie = v * EW + u, gu = a - 1 + u;
     if (u == u_ant) {
       if (r.laser.pol == 1) jy += sAnt[v];
@@ -500,14 +556,31 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
     }
     const R bx = sB[0][ib], by = sB[1][ib], bz = sB[2][ib];
     const R dex = hy2 * (bz - sB[2][ib - BW]) - hh2 * jx;
-    const R dey = -hx2 * (bz - sB[2][ib - 1]) - hh2 * jy;
-    const R dez = hx2 * (by - sB[1][ib - 1]) - hy2 * (bx - sB[0][ib - BW]) - hh2 * jz;
+    R dey = -hx2 * (bz - sB[2][ib - 1]) - hh2 * jy;
+    R dez = hx2 * (by - sB[1][ib - 1]) - hy2 * (bx - sB[0][ib - BW]) - hh2 * jz;
+    if (pml_tile) {   // two merged halves of dt/2: the recursion runs twice
+      const int sl = pml_slot(r, wrap_once(gu, nx));
+      if (sl >= 0) {
+        const int64_t row = wrap_once(c - 1 + v, ny);
+        R pb, pc, ik;
+        pml_coef<R>(r, false, sl, h1, pb, pc, ik);
+        const R Dz = bz - sB[2][ib - 1], Dy = by - sB[1][ib - 1];
+        const R q0 = pb * psi[pml_index(r, hcur, 0, row, sl)] + pc * Dz, q0b = pb * q0 + pc * Dz;
+        const R q1 = pb * psi[pml_index(r, hcur, 1, row, sl)] + pc * Dy, q1b = pb * q1 + pc * Dy;
+        dey = -hx2 * (Dz * ik + R(0.5) * (q0 + q0b)) - hh2 * jy;
+        dez = hx2 * (Dy * ik + R(0.5) * (q1 + q1b)) - hy2 * (bx - sB[0][ib - BW]) - hh2 * jz;
+        if (own) {
+          psi[pml_index(r, hcur ^ 1, 0, row, sl)] = q0b;
+          psi[pml_index(r, hcur ^ 1, 1, row, sl)] = q1b;
+        }
+      }
+    }
     sE[0][ie] += dex;
-    if (open && gu == 1 && u >= 2) {   // Mur for column 0
+    if (mur && gu == 1 && u >= 2) {   // Mur for column 0
       sE[1][ie - 1] = mur_edge<R>(sE[1][ie - 1], sE[1][ie], dey, h2, r.dx, 2);
       sE[2][ie - 1] = mur_edge<R>(sE[2][ie - 1], sE[2][ie], dez, h2, r.dx, 2);
     }
-    if (!(open && gu == 0)) {
+    if (!(mur && gu == 0)) {
       sE[1][ie] += dey;
       sE[2][ie] += dez;
     }
@@ -516,12 +589,14 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   for (int p = 0; p < PER; ++p) {
     const int q = tid + p * 256;
     if (NC % 256 == 0 || q < NC)
-      e_update((q & (TX - 1)) + 1, (q >> LX) + 1, jv[p][0], jv[p][1], jv[p][2]);
+      e_update((q & (TX - 1)) + 1, (q >> LX) + 1, jv[p][0], jv[p][1], jv[p][2], true);
   }
 #pragma unroll
   for (int p = 0; p < NJR; ++p) {
     const int h = tid + p * 256;
-    if (h < JR) e_update(h <= TY ? TX + 1 : h - TY, h <= TY ? 1 + h : TY + 1, je[p][0], je[p][1], je[p][2]);
+    if (h < JR)
+      e_update(h <= TY ? TX + 1 : h - TY, h <= TY ? 1 + h : TY + 1, je[p][0], je[p][1],
+               je[p][2], false);
   }
   __syncthreads();
   // 3. B half update on the output tile (reads E only)
@@ -533,14 +608,28 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
       const int ie = v * EW + u, ib = v * BW + u, gu = a - 1 + u;
       const R ex = sE[0][ie], ey = sE[1][ie], ez = sE[2][ie];
       const R dbx = -hy1 * (sE[2][ie + EW] - ez);
-      const R dby = hx1 * (sE[2][ie + 1] - ez);
-      const R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+      R dby = hx1 * (sE[2][ie + 1] - ez);
+      R dbz = -hx1 * (sE[1][ie + 1] - ey) + hy1 * (sE[0][ie + EW] - ex);
+      if (pml_tile) {
+        const int sl = pml_slot(r, wrap_once(gu, nx));
+        if (sl >= 0) {
+          const int64_t row = c - 1 + v;
+          R pb, pc, ik;
+          pml_coef<R>(r, true, sl, h1, pb, pc, ik);
+          const R Dz = sE[2][ie + 1] - ez, Dy = sE[1][ie + 1] - ey;
+          const R p2 = pb * keep[p][0] + pc * Dz, p3 = pb * keep[p][1] + pc * Dy;
+          dby = hx1 * (Dz * ik + p2);
+          dbz = -hx1 * (Dy * ik + p3) + hy1 * (sE[0][ie + EW] - ex);
+          psi[pml_index(r, hcur ^ 1, 2, row, sl)] = p2;
+          psi[pml_index(r, hcur ^ 1, 3, row, sl)] = p3;
+        }
+      }
       sB[0][ib] += dbx;
-      if (open && gu == nx - 2 && u + 1 <= TX) {   // Mur for column nx-1
+      if (mur && gu == nx - 2 && u + 1 <= TX) {   // Mur for column nx-1
         sB[1][ib + 1] = mur_edge<R>(sB[1][ib + 1], sB[1][ib], dby, h1, r.dx, 1);
         sB[2][ib + 1] = mur_edge<R>(sB[2][ib + 1], sB[2][ib], dbz, h1, r.dx, 1);
       }
-      if (!(open && gu == nx - 1 && u >= 2)) {
+      if (!(mur && gu == nx - 1 && u >= 2)) {
         sB[1][ib] += dby;
         sB[2][ib] += dbz;
       }
@@ -1569,26 +1658,31 @@ void launch_yee(const Tables& T, int prec, int dim, int nblocks, int which, doub
   }
 }
 
-template <typename R, int TX>
+template <typename R, int TX, bool PML>
 static void launch_yee_mid_t(const Tables& T, int ntiles, const FieldBands& b, hipStream_t st) {
-  if (b.ty == 16) k_yee_mid<R, TX, 16><<<ntiles, 256, 0, st>>>(T, b);
-  else if (b.ty == 8) k_yee_mid<R, TX, 8><<<ntiles, 256, 0, st>>>(T, b);
-  else k_yee_mid<R, TX, 4><<<ntiles, 256, 0, st>>>(T, b);
+  if (b.ty == 16) k_yee_mid<R, TX, 16, PML><<<ntiles, 256, 0, st>>>(T, b);
+  else if (b.ty == 8) k_yee_mid<R, TX, 8, PML><<<ntiles, 256, 0, st>>>(T, b);
+  else k_yee_mid<R, TX, 4, PML><<<ntiles, 256, 0, st>>>(T, b);
 }
 
-template <typename R>
+template <typename R, bool PML>
 static void launch_yee_mid_r(const Tables& T, int ntiles, const FieldBands& b, hipStream_t st) {
-  if (b.tx == 64) launch_yee_mid_t<R, 64>(T, ntiles, b, st);
-  else if (b.tx == 32) launch_yee_mid_t<R, 32>(T, ntiles, b, st);
-  else if (b.tx == 16) launch_yee_mid_t<R, 16>(T, ntiles, b, st);
-  else launch_yee_mid_t<R, 8>(T, ntiles, b, st);
+  if (b.tx == 64) launch_yee_mid_t<R, 64, PML>(T, ntiles, b, st);
+  else if (b.tx == 32) launch_yee_mid_t<R, 32, PML>(T, ntiles, b, st);
+  else if (b.tx == 16) launch_yee_mid_t<R, 16, PML>(T, ntiles, b, st);
+  else launch_yee_mid_t<R, 8, PML>(T, ntiles, b, st);
 }
 
-void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands,
+void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& bands, bool pml,
                     hipStream_t st) {
   if (ntiles <= 0) return;
-  if (prec == 0) launch_yee_mid_r<float>(T, ntiles, bands, st);
-  else launch_yee_mid_r<double>(T, ntiles, bands, st);
+  if (prec == 0) {
+    if (pml) launch_yee_mid_r<float, true>(T, ntiles, bands, st);
+    else launch_yee_mid_r<float, false>(T, ntiles, bands, st);
+  } else {
+    if (pml) launch_yee_mid_r<double, true>(T, ntiles, bands, st);
+    else launch_yee_mid_r<double, false>(T, ntiles, bands, st);
+  }
 }
 
 void launch_clear_sources(const Tables& T, int prec, int dim, int nblocks, int with_rho,

@@ -3,9 +3,10 @@ dt, B by dt/2, the tile's neighbours read from the edge snapshot of the previous
 against the same steps with the three updates as separate grid-wide kernels
 (LPIC_FIELD_SEPARATE), and against the FP64 oracle.
 
-Cases: periodic, open x ends with a laser antenna, a box that is a single field tile in both
-directions (its halo wraps onto its own edges), and an ensemble of boxes of different sizes
-(a tile prefix over runs).  Steps include sorts and diagnostic steps (which end with the
+Cases: periodic, open x ends with a laser antenna (Mur ends, or PML layers whose auxiliary
+values follow the same two-half scheme as the edge snapshot), a box that is a single field
+tile in both directions (its halo wraps onto its own edges; also with both PML layers in
+it), and an ensemble of boxes of different sizes (a tile prefix over runs).  Steps include sorts and diagnostic steps (which end with the
 unfused updates), so the edge snapshot is rebuilt after each of them.  The arithmetic per
 cell is the same in both paths, so FP64 agrees to rounding (1e-12 relative to each
 component's largest value) and FP32 to a few ulps amplified over the steps (1e-5)."""
@@ -27,16 +28,22 @@ LASER = dict(pol=1, ia=3, a0=2.0, omega=4.0, waist=1.2, yc=2.0, zc=0.0, t0=0.0, 
 
 
 def _box(case, seed=41):
-    if case == "one_tile":
+    if case in ("one_tile", "one_tile_pml"):
         wl = W.thermal_2d(nx=32, ny=4, dx=0.1, ppc=4, T=0.2, order=2, seed=seed)
     elif case == "wide":
         wl = W.thermal_2d(nx=128, ny=32, dx=0.1, ppc=2, T=0.2, order=1, seed=seed)
     else:
         wl = W.thermal_2d(nx=48, ny=40, dx=0.1, ppc=4, T=0.2, order=2, seed=seed)
     wl.fields = W.random_fields(wl.ncell, seed + 1, 0.5)
-    if case == "open_laser":
+    if case in ("open_laser", "open_pml", "one_tile_pml"):
         wl.open_x = True
+    if case == "open_laser":
         wl.laser = dict(LASER)
+    if case == "open_pml":   # layers of 8 cells, every term of the stretch in play
+        wl.laser = dict(LASER, ia=10)
+        wl.pml = dict(cells=8, order=3, a_order=1, kappa_max=3.0, a_max=0.5)
+    if case == "one_tile_pml":   # one tile holds both layers and wraps onto itself
+        wl.pml = dict(cells=6, order=2, a_order=1, kappa_max=2.0, a_max=0.3)
     for s in wl.species:   # unique weights: particles are followed through the sorts
         s.w = s.w * (1.0 + 1e-3 * np.arange(s.n) / s.n)
     return wl
@@ -78,7 +85,8 @@ def _compare(fused, sep, prec, what):
 
 @pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=PNAME.get)
 @pytest.mark.parametrize("case,tile", [("periodic", (16, 8)), ("open_laser", (16, 8)),
-                                       ("one_tile", (32, 4)), ("wide", (64, 16))])
+                                       ("open_pml", (16, 8)), ("one_tile", (32, 4)),
+                                       ("one_tile_pml", (32, 4)), ("wide", (64, 16))])
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
 def test_fused_field_update_matches_separate_kernels(prec, case, tile, graph):
     banner(f"fused field update {case} prec={PNAME[prec]} graph={graph}")
