@@ -8,8 +8,9 @@ advanced through gather + push + deposit.
 Workload (default): 2D3V 2048x1024 Yee grid, dx = lambda/32, fully ionised hydrogen slab of
 20 n_c in cells x in [512, 768), electrons + protons at 32 ppc each (16,777,216 particles),
 T = 1 keV, quadratic shape, linearly polarised a0 = 10 Gaussian laser (waist 6.25 lambda,
-sin^2 envelope of 25 lambda / c) injected by an antenna 4 cells from the open left end, open
-(absorbing) x ends, periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
+sin^2 envelope of 25 lambda / c) injected by an antenna 4 cells inside the left absorbing
+layer, open x ends with 16-cell graded convolutional PML layers (the absorbing boundaries
+of Sec. 3.2; --pml 0: first-order Mur ends), periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
 the plain FP64 path is reported beside it.
 
 Output: one JSON line.  The benchmark runs on one GPU; with --gpus > 1 it exits (the
@@ -77,11 +78,13 @@ def build_workload(args):
     from paper_2607_13507_amd import workloads as W
     if args.workload == "laser_slab":
         wl = W.laser_slab_2d(nx=args.nx, ny=args.ny, slab=(args.nx // 4, args.nx * 3 // 8),
-                             ppc=args.ppc, steps=args.steps)
+                             ppc=args.ppc, steps=args.steps, pml_cells=args.pml)
+        ends = (f"open x ends with {args.pml}-cell graded PML layers" if args.pml else
+                "open x ends (first-order Mur)")
         desc = (f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c cells x in "
                 f"[{args.nx // 4},{args.nx * 3 // 8}), e- + p+ {args.ppc} ppc each "
                 f"({wl.nparticles} particles), T=1 keV, quadratic, a0=10 laser injected at the "
-                "open left end (antenna, waist 6.25 lambda, 25 lambda sin^2), open x ends, "
+                f"open left end (antenna, waist 6.25 lambda, 25 lambda sin^2), {ends}, "
                 "FP32 cell+offset")
         return [wl], desc, 2, [2 * args.ppc]
     if args.workload == "thermal_3d":
@@ -290,6 +293,10 @@ def main():
                     choices=("laser_slab", "thermal_3d", "wakefield", "ensemble"),
                     help="laser_slab (default, the headline configuration); the others are "
                          "extra measurements")
+    ap.add_argument("--pml", type=int, default=16, metavar="CELLS",
+                    help="laser_slab: graded PML layers of CELLS cells at the open x ends, "
+                         "the antenna 4 cells inside the left one (0: first-order Mur ends, "
+                         "the antenna 4 cells from the left end)")
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--tile-z", type=int, default=None)
     ap.add_argument("--halo", type=int, default=None)

@@ -663,6 +663,12 @@ lpic_status run_hooks(lpic_sim* s, int stage) {
 }
 
 // (Re)build everything that depends on the options: tiling, bins, chunk tables.
+// Bytes of the two halves of a run's PML auxiliary values (the coefficient table follows).
+size_t pml_psi_bytes(const lpic_grid* g, int cells, int prec) {
+  return (size_t)2 * 4 * g->ny * (g->ndim == 3 ? g->nz : 1) * 2 * cells *
+         (prec == LPIC_F32_CELLOFS ? 4 : 8);
+}
+
 lpic_status configure(lpic_sim* s) {
   drop_graphs(s);
   lpic_tiling t = s->opt.tiling;
@@ -699,12 +705,8 @@ lpic_status configure(lpic_sim* s) {
     const lpic_pml& pm = s->pmls[r];
     if (pm.cells > 0) {
       d.pml_cells = pm.cells;
-      d.pml_order = pm.order;
-      d.pml_a_order = pm.a_order;
-      d.pml_sigma = pm.sigma_max;
-      d.pml_kappa = pm.kappa_max;
-      d.pml_a = pm.a_max;
       d.psi = s->psi[r];
+      d.pml_tab = (const char*)s->psi[r] + pml_psi_bytes(&s->grids[r], pm.cells, s->prec);
       d.psi_parity = (const int32_t*)((char*)s->step_dev + 128);
     }
     if (d.has_laser) s->laser_bpr = std::max(s->laser_bpr, columns_bpr(&s->grids[r]));
@@ -1299,11 +1301,35 @@ lpic_status lpic_set_pml(lpic_sim* s, int32_t r, const lpic_pml* pml) {
   if (pml) {
     lpic_pml p = *pml;
     if (p.sigma_max < 0.0) p.sigma_max = 0.8 * (p.order + 1) / g.dx;
-    const size_t bytes = (size_t)2 * 4 * g.ny * (s->ndim == 3 ? g.nz : 1) * 2 * p.cells *
-                         (s->prec == LPIC_F32_CELLOFS ? 4 : 8);
-    if (hipMalloc(&s->psi[r], bytes) != hipSuccess)
-      return fail(LPIC_ENOMEM, "PML allocation of %zu bytes failed", bytes);
-    HIPCHK(hipMemset(s->psi[r], 0, bytes));
+    // recursion coefficients per slot for a half step dt/2 (every field update of a
+    // simulation is made of such halves): E side, then B side, each {b, c, 1/kappa}
+    const int L = p.cells;
+    std::vector<double> tab;
+    for (int side = 0; side < 2; ++side)
+      for (int slot = 0; slot < 2 * L; ++slot) {
+        const double half = side ? 0.5 : 0.0;
+        const double depth = slot < L ? (L - slot) - half : (slot - L) + half;
+        const double sd = depth / L;
+        double sm = 1.0, sa = 1.0;
+        for (int q = 0; q < p.order; ++q) sm *= sd;
+        for (int q = 0; q < p.a_order; ++q) sa *= 1.0 - sd;
+        const double sigma = p.sigma_max * sm, kappa = 1.0 + (p.kappa_max - 1.0) * sm;
+        const double a = p.a_max * sa;
+        const double b = std::exp(-(sigma / kappa + a) * 0.5 * g.dt);
+        tab.push_back(b);
+        tab.push_back(sigma > 0.0 ? sigma * (b - 1.0) / (kappa * (sigma + kappa * a)) : 0.0);
+        tab.push_back(1.0 / kappa);
+      }
+    const size_t psi_bytes = pml_psi_bytes(&g, L, s->prec);
+    const bool f32 = s->prec == LPIC_F32_CELLOFS;
+    std::vector<float> tabf(tab.begin(), tab.end());
+    const size_t tab_bytes = tab.size() * (f32 ? 4 : 8);
+    if (hipMalloc(&s->psi[r], psi_bytes + tab_bytes) != hipSuccess)
+      return fail(LPIC_ENOMEM, "PML allocation of %zu bytes failed", psi_bytes + tab_bytes);
+    HIPCHK(hipMemset(s->psi[r], 0, psi_bytes));
+    HIPCHK(hipMemcpy((char*)s->psi[r] + psi_bytes, f32 ? (const void*)tabf.data()
+                                                      : (const void*)tab.data(),
+                     tab_bytes, hipMemcpyHostToDevice));
     s->pmls[r] = p;
   }
   return configure(s);   // device tables (and the field update path), drops graphs

@@ -48,9 +48,10 @@ struct RunDesc {
   double* diag;                    // DIAG_NUM device accumulators
   LaserDesc laser;
   // convolutional PML at the open x ends (pml_cells = 0: Mur condition instead)
-  int32_t pml_cells, pml_order, pml_a_order, pad1;
-  double pml_sigma, pml_kappa, pml_a;
+  int32_t pml_cells, pad1;
   void* psi;                       // 2 halves x 4 components x rows x 2 pml_cells values
+  const void* pml_tab;             // b, c, 1/kappa per slot for a half step dt/2: E side
+                                   // (2 pml_cells slots), then B side
   const int32_t* psi_parity;       // which half is current (the fused field update's parity)
 };
 

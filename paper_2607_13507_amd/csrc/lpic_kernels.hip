@@ -106,7 +106,9 @@ __device__ __forceinline__ R mur_edge(R u_edge_old, R u_in_old, R d, double h, d
 // ---------------------------------------------------------------------------------------
 // Convolutional PML at the open x ends (lpic_set_pml).  The auxiliary values psi are held
 // in units of a difference (psi * dx), so that a stretched difference is D/kappa + psi with
-// D the plain difference of two neighbouring values.
+// D the plain difference of two neighbouring values.  Every field update of a simulation
+// is made of half steps dt/2 (an E update of a whole dt between two steps is two merged
+// halves), so the recursion coefficients are a per-slot table for that step.
 // ---------------------------------------------------------------------------------------
 // Slot of array column i in the auxiliary arrays: 0 .. L-1 the left layer, L .. 2L-1 the
 // right one, -1 outside both.
@@ -117,24 +119,15 @@ __device__ __forceinline__ int pml_slot(const RunDesc& r, int i) {
   return p < L ? p : (p >= r.nx - L ? p - r.nx + 2 * L : -1);
 }
 
-// Recursion coefficients b, c and 1/kappa at slot `slot` for an update of step tau; B-side
-// locations (bside) lie half a column further in +x than the E-side ones.
+// Recursion coefficients b, c and 1/kappa at slot `slot` (B-side locations lie half a
+// column further in +x than the E-side ones).
 template <typename R>
-__device__ __forceinline__ void pml_coef(const RunDesc& r, bool bside, int slot, double tau,
-                                         R& b, R& c, R& ik) {
-  const int L = r.pml_cells;
-  const double half = bside ? 0.5 : 0.0;
-  const double depth = slot < L ? (L - slot) - half : (slot - L) + half;
-  const double s = depth / L;
-  double sm = 1.0, sa = 1.0;
-  for (int q = 0; q < r.pml_order; ++q) sm *= s;
-  for (int q = 0; q < r.pml_a_order; ++q) sa *= 1.0 - s;
-  const double sigma = r.pml_sigma * sm, kappa = 1.0 + (r.pml_kappa - 1.0) * sm;
-  const double a = r.pml_a * sa;
-  const double bd = exp(-(sigma / kappa + a) * tau);
-  b = R(bd);
-  c = R(sigma > 0.0 ? sigma * (bd - 1.0) / (kappa * (sigma + kappa * a)) : 0.0);
-  ik = R(1.0 / kappa);
+__device__ __forceinline__ void pml_coef(const RunDesc& r, bool bside, int slot, R& b, R& c,
+                                         R& ik) {
+  const R* t = (const R*)r.pml_tab + ((bside ? 2 * r.pml_cells : 0) + slot) * 3;
+  b = t[0];
+  c = t[1];
+  ik = t[2];
 }
 
 // Index of psi for component comp (0 Ey, 1 Ez, 2 By, 3 Bz) at (row, slot) in half `half`.
@@ -149,14 +142,14 @@ __device__ __forceinline__ int pml_half(const RunDesc& r) {
 }
 
 // One stretched x difference of component comp at (row, slot), in place in the current
-// half: advances psi over `steps` updates of step tau with the same plain difference D (an
-// E update of a whole dt made of two merged halves takes steps = 2 and returns the mean of
+// half: advances psi over `steps` half-step updates with the same plain difference D (an E
+// update of a whole dt made of two merged halves takes steps = 2 and returns the mean of
 // the two stretched differences) and returns the stretched difference.
 template <typename R>
 __device__ __forceinline__ R pml_stretch(const RunDesc& r, int comp, int64_t row, int slot,
-                                         double tau, int steps, R D) {
+                                         int steps, R D) {
   R b, c, ik;
-  pml_coef<R>(r, comp >= 2, slot, tau, b, c, ik);
+  pml_coef<R>(r, comp >= 2, slot, b, c, ik);
   R* psi = (R*)r.psi + pml_index(r, pml_half(r), comp, row, slot);
   const R p1 = b * *psi + c * D;
   if (steps == 1) {
@@ -185,9 +178,8 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
   if (ps >= 0) {   // in a PML layer: the x differences of Bz and By are stretched
     const R dbz = f[F_BZ][x.c] - f[F_BZ][x.cim], dby = f[F_BY][x.c] - f[F_BY][x.cim];
     const int64_t row = x.row;
-    const double tau = halves == 2 ? 0.5 * h : h;
-    dey += hx * (dbz - pml_stretch<R>(r, 0, row, ps, tau, halves, dbz));
-    dez -= hx * (dby - pml_stretch<R>(r, 1, row, ps, tau, halves, dby));
+    dey += hx * (dbz - pml_stretch<R>(r, 0, row, ps, halves, dbz));
+    dez -= hx * (dby - pml_stretch<R>(r, 1, row, ps, halves, dby));
   }
   f[F_EX][x.c] += dex;
   const int bxi = box_x(r, x.i);   // box column (a moving window shifts the arrays' origin)
@@ -275,8 +267,8 @@ __global__ __launch_bounds__(256) void k_yee_b(Tables T, double frac, FieldBands
   if (ps >= 0) {   // in a PML layer: the x differences of Ez and Ey are stretched
     const R dez = f[F_EZ][x.cip] - f[F_EZ][x.c], dey = f[F_EY][x.cip] - f[F_EY][x.c];
     const int64_t row = x.row;
-    dby -= hx * (dez - pml_stretch<R>(r, 2, row, ps, h, 1, dez));
-    dbz += hx * (dey - pml_stretch<R>(r, 3, row, ps, h, 1, dey));
+    dby -= hx * (dez - pml_stretch<R>(r, 2, row, ps, 1, dez));
+    dbz += hx * (dey - pml_stretch<R>(r, 3, row, ps, 1, dey));
   }
   const R bx = f[F_BX][x.c] + dbx;
   f[F_BX][x.c] = bx;
@@ -373,7 +365,24 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   const RunDesc& r = run_of(T, ri);
   const int nx = r.nx, ny = r.ny;
   const int ntx = nx / TX;
-  const int tj = blk / ntx, ti = blk - tj * ntx;
+  int tj = blk / ntx, ti = blk - tj * ntx;
+  if (PML && r.pml_cells > 0) {
+    // the tile columns that reach into a layer (ke at each end) come first, so that their
+    // longer work overlaps the interior tiles instead of trailing them
+    const int ke = (r.pml_cells + TX) / TX, nty = ny / TY;
+    if (2 * ke < ntx) {
+      if (blk < 2 * ke * nty) {
+        const int col = blk / nty;
+        tj = blk - col * nty;
+        ti = col < ke ? col : ntx - 2 * ke + col;
+      } else {
+        const int rest = blk - 2 * ke * nty, ncol = ntx - 2 * ke;
+        tj = rest / ncol;
+        ti = ke + rest - tj * ncol;
+      }
+    }
+  }
+  const int tile = tj * ntx + ti;
   const int a = ti * TX, c = tj * TY;
   const int64_t tile0 = Bd.tile_pfx[ri];
   const int cur = *Bd.parity & 1;
@@ -496,8 +505,9 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   const int hcur = pml_tile ? pml_half(r) : 0;
   R* psi = (R*)r.psi;
   // 1. B half update on the whole B region (reads E only): the tile's cells (their psi
-  // kept for the second B half), then the ring around it
-  auto b_first = [&](int u, int v, R* keep) {
+  // parked in the other half, where the same thread picks it up for the second B half),
+  // then the ring around it
+  auto b_first = [&](int u, int v, bool own) {
     const int ie = v * EW + u, q = v * BW + u, gu = a - 1 + u;
     const R ex = sE[0][ie], ey = sE[1][ie], ez = sE[2][ie];
     const R dbx = -hy1 * (sE[2][ie + EW] - ez);
@@ -508,15 +518,15 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
       if (sl >= 0) {
         const int64_t row = wrap_once(c - 1 + v, ny);
         R pb, pc, ik;
-        pml_coef<R>(r, true, sl, h1, pb, pc, ik);
+        pml_coef<R>(r, true, sl, pb, pc, ik);
         const R Dz = sE[2][ie + 1] - ez, Dy = sE[1][ie + 1] - ey;
         const R p2 = pb * psi[pml_index(r, hcur, 2, row, sl)] + pc * Dz;
         const R p3 = pb * psi[pml_index(r, hcur, 3, row, sl)] + pc * Dy;
         dby = hx1 * (Dz * ik + p2);
         dbz = -hx1 * (Dy * ik + p3) + hy1 * (sE[0][ie + EW] - ex);
-        if (keep) {
-          keep[0] = p2;
-          keep[1] = p3;
+        if (own) {
+          psi[pml_index(r, hcur ^ 1, 2, row, sl)] = p2;
+          psi[pml_index(r, hcur ^ 1, 3, row, sl)] = p3;
         }
       }
     }
@@ -530,11 +540,10 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
       sB[2][q] += dbz;
     }
   };
-  R keep[PER][2];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int q = tid + p * 256;
-    if (NC % 256 == 0 || q < NC) b_first((q & (TX - 1)) + 1, (q >> LX) + 1, keep[p]);
+    if (NC % 256 == 0 || q < NC) b_first((q & (TX - 1)) + 1, (q >> LX) + 1, true);
   }
 #pragma unroll
   for (int p = 0; p < NBR; ++p) {
@@ -542,7 +551,7 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
     if (h < BR) {
       int u, v;
       ring_cell<TX, TY, 1>(h, u, v);
-      b_first(u, v, nullptr);
+      b_first(u, v, false);
     }
   }
   __syncthreads();
@@ -563,7 +572,7 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
       if (sl >= 0) {
         const int64_t row = wrap_once(c - 1 + v, ny);
         R pb, pc, ik;
-        pml_coef<R>(r, false, sl, h1, pb, pc, ik);
+        pml_coef<R>(r, false, sl, pb, pc, ik);
         const R Dz = bz - sB[2][ib - 1], Dy = by - sB[1][ib - 1];
         const R q0 = pb * psi[pml_index(r, hcur, 0, row, sl)] + pc * Dz, q0b = pb * q0 + pc * Dz;
         const R q1 = pb * psi[pml_index(r, hcur, 1, row, sl)] + pc * Dy, q1b = pb * q1 + pc * Dy;
@@ -615,13 +624,15 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
         if (sl >= 0) {
           const int64_t row = c - 1 + v;
           R pb, pc, ik;
-          pml_coef<R>(r, true, sl, h1, pb, pc, ik);
+          pml_coef<R>(r, true, sl, pb, pc, ik);
           const R Dz = sE[2][ie + 1] - ez, Dy = sE[1][ie + 1] - ey;
-          const R p2 = pb * keep[p][0] + pc * Dz, p3 = pb * keep[p][1] + pc * Dy;
+          R* q2 = psi + pml_index(r, hcur ^ 1, 2, row, sl);
+          R* q3 = psi + pml_index(r, hcur ^ 1, 3, row, sl);
+          const R p2 = pb * *q2 + pc * Dz, p3 = pb * *q3 + pc * Dy;
           dby = hx1 * (Dz * ik + p2);
           dbz = -hx1 * (Dy * ik + p3) + hy1 * (sE[0][ie + EW] - ex);
-          psi[pml_index(r, hcur ^ 1, 2, row, sl)] = p2;
-          psi[pml_index(r, hcur ^ 1, 3, row, sl)] = p3;
+          *q2 = p2;
+          *q3 = p3;
         }
       }
       sB[0][ib] += dbx;
@@ -637,7 +648,7 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
   }
   __syncthreads();
   // 4. the tile's E and B to the arrays, its edges to the other snapshot
-  const int64_t bbase = (tile0 + blk) * 6 * (3 * (TX + TY));
+  const int64_t bbase = (tile0 + tile) * 6 * (3 * (TX + TY));
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int q = tid + p * 256;

@@ -177,12 +177,14 @@ def thermal_2d(nx=64, ny=64, dx=0.05, ppc=16, T=0.01, density=1.0, order=1, seed
 def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), density=20.0,
                   ppc=32, T=T_1KEV, a0=10.0, order=2, seed=2, eta=0.95, steps=2000,
                   pulse_cells=None, waist_lambda=6.25, inject=True, duration_lambda=25.0,
-                  name="laser_slab_2d") -> Workload:
+                  pml_cells=0, name="laser_slab_2d") -> Workload:
     """2D3V hydrogen slab (electrons + protons, `ppc` each) of `density` n_c in cells
     [slab[0], slab[1]) over the whole y extent, and a linearly polarised (E along y)
     Gaussian laser of peak a0, waist `waist_lambda` wavelengths.
     inject=True: open x ends and a laser antenna 4 cells from the left end, sin^2 envelope
     of full duration `duration_lambda` wavelengths (the setup of Sec. 4.2); y periodic.
+    pml_cells > 0 (with inject): graded PML layers of that many cells at both x ends
+    instead of the Mur condition, the antenna 4 cells inside the left layer's inner face.
     inject=False: periodic box with the pulse placed in the vacuum in front of the slab
     (x in [0, pulse_cells) cells, sin^2 envelope over that span).
     Electrons sit uniformly at random in their cells, each proton on an electron, so the
@@ -198,11 +200,12 @@ def laser_slab_2d(nx=2048, ny=1024, cells_per_lambda=32, slab=(512, 768), densit
                          density, ppc)
     dt = cfl_dt(eta, dx, dx)
     if inject:
-        laser = dict(pol=1, ia=4, a0=a0, omega=1.0, waist=waist_lambda * LAMBDA,
+        laser = dict(pol=1, ia=pml_cells + 4, a0=a0, omega=1.0, waist=waist_lambda * LAMBDA,
                      yc=0.5 * ny * dx, zc=0.0, t0=0.0, tau=duration_lambda * LAMBDA)
         return Workload(name, 2, nx, ny, 1, dx, dx, 1.0, dt, 0.0, [e, p], {}, steps,
                         dict(ppc=ppc, T=T, density=density, order=order, seed=seed, a0=a0,
-                             slab=slab, inject=True), open_x=True, laser=laser)
+                             slab=slab, inject=True, pml_cells=pml_cells), open_x=True,
+                        laser=laser, pml=dict(cells=pml_cells) if pml_cells else None)
     if pulse_cells is None:
         pulse_cells = min(slab[0], nx)
     flds = {}
