@@ -180,3 +180,50 @@ def test_pml_arguments_and_removal():
     with pytest.raises(RuntimeError, match="open x"):
         sim.set_pml(0, dict(cells=8))
     sim.close()
+
+
+def test_mixed_ensemble_matches_oracle_per_member():
+    """One simulation advancing a periodic box, a box with Mur ends and an antenna, and a
+    box with PML layers and an antenna (FP64, graph replay, fused field update over all
+    three): every member equals its own oracle run."""
+    banner("pml in a mixed ensemble")
+    per = W.thermal_2d(nx=64, ny=32, dx=0.1, ppc=2, T=0.2, order=2, seed=91)
+    mur = W.thermal_2d(nx=32, ny=16, dx=0.1, ppc=4, T=0.2, order=1, seed=92)
+    mur.open_x = True
+    mur.laser = dict(pol=2, ia=3, a0=1.0, omega=4.0, waist=0.5, yc=0.8, zc=0.0, t0=0.0, tau=2.0)
+    pml = W.thermal_2d(nx=96, ny=24, dx=0.1, ppc=2, T=0.2, order=2, seed=93)
+    pml.open_x = True
+    pml.laser = dict(pol=1, ia=10, a0=2.0, omega=4.0, waist=0.8, yc=1.2, zc=0.0, t0=0.0, tau=3.0)
+    pml.pml = dict(PML)
+    members = [per, mur, pml]
+    for i, m in enumerate(members):
+        m.fields = W.random_fields(m.ncell, 95 + i, 0.3)
+    sim = Simulation(members, prec=L.F64_ABS, tiling=(8, 8, 1), halo=4, chunk=128,
+                     sort_interval=3, diag_interval=5, use_graph=True)
+    assert sim.stats()["field_tile"] == (32, 8)
+    orcs = [_oracle_like_run(sim, m, r) for r, m in enumerate(members)]
+    sim.step(10)
+    for o in orcs:
+        o.step(10)
+    torch.cuda.synchronize()
+    for r, o in enumerate(orcs):
+        compare_fields(sim.fields[r], o, L.F64_ABS, tol=1e-10, what=f"member {r}")
+        d = sim.diagnostics(r)
+        assert d["field_energy"] == pytest.approx(o.field_energy(), rel=1e-10), r
+        assert d["continuity"] < 1e-12
+    assert np.abs(orcs[2].psi).max() > 1e-3
+    sim.close()
+
+
+def _oracle_like_run(sim, wl, r):
+    orc = OracleSim.from_workload(wl)
+    for k, v in sim.fields[r].numpy().items():
+        if k in orc.f:
+            orc.f[k][:] = v
+    for s, i in zip(orc.species, sim.species_of_run(r)):
+        pos = sim.positions(i)
+        s.x[:], s.y[:] = pos[0], pos[1]
+        cur = sim.current(i)
+        for k in ("ux", "uy", "uz", "w"):
+            getattr(s, k)[:] = cur.numpy(k)
+    return orc
