@@ -13,6 +13,12 @@ layer, open x ends with 16-cell graded convolutional PML layers (the absorbing b
 of Sec. 3.2; --pml 0: first-order Mur ends), periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
 the plain FP64 path is reported beside it.
 
+Timing: after the warmup steps (and alignment to a sort period), K steps run eagerly with HIP
+events around every fused launch (the kernel's average launch time for the roofline), then,
+after one untimed period that captures every step variant, the same K steps replay from the
+captured graphs, the library's default mode: that pass is `value` and `ms_per_step`
+(`eager_mode` reports the first one; --no-graph makes it `value`).
+
 Output: one JSON line.  The benchmark runs on one GPU; with --gpus > 1 it exits (the
 multi-GPU decomposition is a design, not implemented).
 """
@@ -368,14 +374,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and args.workload == "laser_slab":
         cpu = cpu_baseline(wl[0])
+    # `value` is the simulation as it runs by default: K steps replayed from captured graphs
+    # (the eager pass before them records HIP events around every fused launch for the
+    # roofline, which costs launch time of its own); --no-graph reports the eager pass
+    graph = not args.no_graph
+    key = "_graph" if graph else ""
     out = {
         "metric": "particle-pushes/sec (gather+push+deposit) FP32 vs FP64, % HBM roofline",
-        "value": round(f32["pushes_per_s"], 1),
+        "value": round(f32["pushes_per_s" + key], 1),
         "unit": "particle-pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(f32["ms_per_step"], 4),
+        "ms_per_step": round(f32["ms_per_step" + key], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -389,21 +400,23 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fused_pushes_per_s": round(nparticles / (f32["fused_ms"] * 1e-3), 1),
-        "graph_mode": None if args.no_graph else {
-            "ms_per_step": round(f32["ms_per_step_graph"], 4),
-            "pushes_per_s": round(f32["pushes_per_s_graph"], 1)},
+        "timed_mode": "graph replay" if graph else "eager",
+        "eager_mode": {"ms_per_step": round(f32["ms_per_step"], 4),
+                       "pushes_per_s": round(f32["pushes_per_s"], 1),
+                       "note": "the same K steps launched one by one, with HIP events around "
+                               "every fused launch (the source of avg_launch_ms)"},
         "halo_escapes_per_push": f32["halo_escapes_per_push"],
         "diagnostics_fp32": f32["diagnostics"],
     }
     if f64:
-        out["fp64"] = {"pushes_per_s": round(f64["pushes_per_s"], 1),
-                       "ms_per_step": round(f64["ms_per_step"], 4),
+        out["fp64"] = {"pushes_per_s": round(f64["pushes_per_s" + key], 1),
+                       "ms_per_step": round(f64["ms_per_step" + key], 4),
                        "fused_avg_ms": round(f64["fused_ms"], 4),
                        "fused_hbm_gbs": round(launch_bytes_of(False) /
                                               (f64["fused_ms"] * 1e-3) / 1e9, 1),
-                       "graph_pushes_per_s": None if args.no_graph else
-                       round(f64["pushes_per_s_graph"], 1),
-                       "fp32_over_fp64": round(f32["pushes_per_s"] / f64["pushes_per_s"], 3),
+                       "eager_pushes_per_s": round(f64["pushes_per_s"], 1),
+                       "fp32_over_fp64": round(f32["pushes_per_s" + key] /
+                                               f64["pushes_per_s" + key], 3),
                        "diagnostics": f64["diagnostics"]}
     if f32["tuned"]:
         out["autotuned"] = f32["tuned"]
