@@ -220,9 +220,9 @@ class Simulation:
         sigma_max=-1 for 0.8 (order + 1) / dx, kappa_max=1, a_max=0), or None for Mur."""
         p = None
         if pml:
+            sigma = pml.get("sigma_max")
             p = L.Pml(int(pml["cells"]), int(pml.get("order", 3)), int(pml.get("a_order", 1)),
-                      0, float(pml.get("sigma_max", -1.0) if pml.get("sigma_max") is not None
-                               else -1.0),
+                      0, -1.0 if sigma is None else float(sigma),
                       float(pml.get("kappa_max", 1.0)), float(pml.get("a_max", 0.0)))
         L.lpic_set_pml(self.h, r, p)
 
