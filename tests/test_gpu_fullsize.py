@@ -2,8 +2,9 @@
 
 Workload: the 2D3V laser-slab box, 2048 x 1024 cells, dx = lambda/32, electrons + protons at
 32 ppc each in the slab (16,777,216 particles), quadratic shape, FP32 cell + offset path,
-laser injected by an antenna near the open left end, open x ends, tiles 16 x 16 with a
-5-cell halo, chunks of 2048, graph replay -- what bench.py times.
+laser injected by an antenna inside the left one of two 16-cell PML layers at the open x
+ends, tiles 16 x 16 with a 5-cell halo, chunks of 1024, graph replay -- what bench.py times.
+Also the 64-run ensemble of the benchmark (179.6M particles), sampled.
 
 - One whole step (Algorithm 1: field halves, fused gather + Boris + Esirkepov over every
   particle, field halves) against the FP64 oracle stepping the same state: every field
@@ -41,9 +42,9 @@ def _oracle_from_gpu(sim, wl):
 
 def test_laser_slab_full_size_step_matches_oracle():
     banner("full-size laser slab: one FP32 step vs the oracle")
-    wl = W.laser_slab_2d()
+    wl = W.laser_slab_2d(pml_cells=16)
     assert wl.nparticles == 16_777_216
-    sim = Simulation(wl, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=5, chunk=2048,
+    sim = Simulation(wl, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=5, chunk=1024,
                      sort_interval=10, diag_interval=1, use_graph=True)
     sim.step(1)                      # sort + first step
     torch.cuda.synchronize()
@@ -192,7 +193,7 @@ def test_laser_slab_fp32_tracks_fp64_over_1000_steps():
     The FP64 path stands in for the oracle here (it matches the oracle to 1e-10 per step in
     the tests above; the oracle needs ~10 s per step of this box)."""
     banner("full-size laser slab: FP32 vs FP64, 1000 steps")
-    wl = W.laser_slab_2d()
+    wl = W.laser_slab_2d(pml_cells=16)
     hist = {}
     for prec in (L.F64_ABS, L.F32_CELLOFS):
         sim = Simulation(wl, prec=prec, tiling=(16, 16, 1), halo=5, chunk=1024,
@@ -208,3 +209,48 @@ def test_laser_slab_fp32_tracks_fp64_over_1000_steps():
         assert d32["field_energy"] == pytest.approx(d64["field_energy"], rel=1e-4), d32["step"]
         assert d32["kinetic_energy"] == pytest.approx(d64["kinetic_energy"], rel=1e-3), d32["step"]
         assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (d32, d64)
+
+
+def test_ensemble_full_size_sampled_members_match_oracle():
+    """The benchmark's ensemble (64 laser-slab runs of mixed sizes, 179.6M particles, one
+    launch per kernel for all runs), one FP32 step after the first in the benchmark's launch
+    configuration: the three members with the fewest particles against the oracle stepping
+    the same state (every field component and particle), and every member's charge
+    continuity below 1e-5 of its max |rho|."""
+    banner("full-size ensemble: build")
+    members = W.ensemble_2d(seed=4, members=64)
+    assert sum(m.nparticles for m in members) > 170_000_000
+    sim = Simulation(members, prec=L.F32_CELLOFS, tiling=(16, 16, 1), halo=5, chunk=1024,
+                     sort_interval=20, diag_interval=1, use_graph=True)
+    sim.step(1)                      # sort + first step
+    torch.cuda.synchronize()
+    picks = sorted(range(len(members)), key=lambda r: members[r].nparticles)[:3]
+    orcs = {}
+    for r in picks:
+        orc = OracleSim.from_workload(members[r], with_rho=True)
+        for k, v in sim.fields[r].numpy().items():
+            if k in orc.f:
+                orc.f[k][:] = v
+        for s, i in zip(orc.species, sim.species_of_run(r)):
+            pos = sim.positions(i)
+            s.x[:], s.y[:] = pos[0], pos[1]
+            cur = sim.current(i)
+            for k in ("ux", "uy", "uz", "w"):
+                getattr(s, k)[:] = cur.numpy(k)
+        orc.nstep = 1                # the antenna's clock
+        orcs[r] = orc
+    banner("full-size ensemble: GPU step 2")
+    sim.step(1)                      # no sort: the same particle order as the oracle
+    torch.cuda.synchronize()
+    for r in range(len(members)):
+        assert sim.diagnostics(r)["continuity"] < 1e-5, r
+    for r, orc in orcs.items():
+        banner(f"full-size ensemble: oracle step 2 of member {r}")
+        orc.step(1)
+        compare_fields(sim.fields[r], orc, L.F32_CELLOFS, tol=2e-5, what=f"member {r}")
+        for s, i in zip(orc.species, sim.species_of_run(r)):
+            compare_particles(sim.grids[r], sim.current(i), s, L.F32_CELLOFS, tol_pos=2e-5,
+                              tol_u=2e-5, what=f"member {r} species {i}")
+        d = sim.diagnostics(r)
+        assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-5), r
+    sim.close()
