@@ -208,6 +208,23 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return t;
 }
 
+// A descriptor copied into wavefront-uniform registers word by word.  Every lane holds the
+// same descriptor, but loaded through a generic reference (the device table, or the copy in
+// the kernel arguments) its words land in vector registers; with the particle loop's
+// registers at the limit of four waves per SIMD they were spilled to scratch memory around
+// every chunk, which raised the kernel's memory traffic about 40% above the bytes its
+// particles and fields need.
+template <typename D>
+__device__ __forceinline__ D uniform_copy(const D& src) {
+  static_assert(sizeof(D) % 4 == 0, "descriptor of whole words");
+  D out;
+  const uint32_t* w = (const uint32_t*)&src;
+  uint32_t* o = (uint32_t*)&out;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(D) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  return out;
+}
+
 // Fused gather + push + deposit over the chunk table, persistent: the grid is a multiple of
 // 8 and XCD x (workgroups x, x+8, ...) owns the contiguous chunk range [x*per, (x+1)*per),
 // split into equal contiguous slices per workgroup.  Consecutive chunks of one tile (and of
@@ -258,7 +275,7 @@ __global__ __launch_bounds__(fused_block<DIM>()) __attribute__((amdgpu_waves_per
     ch.tile = uniform(ch.tile);
     ch.beg = uniform(ch.beg);
     ch.end = uniform(ch.end);
-    const SegDesc s = seg_of(T, ch.seg);
+    const SegDesc s = uniform_copy(seg_of(T, ch.seg));
     if (s.run != cur_run || ch.tile != cur_tile) {
       if (cur_run >= 0) {
         const RunDesc& rp = run_of(T, cur_run);
