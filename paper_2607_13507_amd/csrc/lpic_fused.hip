@@ -127,15 +127,16 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // consecutive particles) and then pushes them one by one, so HBM latency is paid once per
 // round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
 constexpr int BATCH = 4;
-// Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (128 VGPRs,
-// a few spills, measured faster than 3 waves without); the others keep the compiler's choice.
+// Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (at most 128
+// VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM>
 constexpr int fused_waves() { return (sizeof(R) == 4 && DIM == 2) ? 4 : 1; }
 
 // Threads per workgroup: a 3D region (tile + halo on three axes) fills most of a CU's LDS,
-// so one workgroup per CU must bring enough waves by itself.
-template <int DIM>
-constexpr int fused_block() { return DIM == 2 ? 256 : 512; }
+// so one workgroup per CU must bring enough waves by itself: 16 (four per SIMD) in FP32, whose
+// quadratic particle loop fits 128 VGPRs; 8 in FP64, which needs more registers per lane.
+template <typename R, int DIM>
+constexpr int fused_block() { return DIM == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 512); }
 
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
@@ -231,12 +232,12 @@ __device__ __forceinline__ D uniform_copy(const D& src) {
 // the other species of the same box, which follow in the table) reuse the staged region;
 // the region is flushed when the tile changes.
 template <typename R, int DIM, int G>
-__global__ __launch_bounds__(fused_block<DIM>()) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
+__global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
                                                EscapeList esc, const int32_t* jshift) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[fused_block<DIM>() / 64];
+  __shared__ double red[fused_block<R, DIM>() / 64];
   R* sm = (R*)smem_raw;
   const int nch = uniform(*nchunks);
   const int nb8 = gridDim.x >> 3;
@@ -382,7 +383,7 @@ template <typename R, int D, int G>
 static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
                            const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
                            const EscapeList& esc, const int32_t* jshift, hipStream_t st) {
-  k_fused<R, D, G><<<nblocks, fused_block<D>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
+  k_fused<R, D, G><<<nblocks, fused_block<R, D>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
                                                ke_to_diag, esc, jshift);
 }
 
@@ -426,7 +427,7 @@ static hipError_t set_smem(size_t smem, size_t smem_occ, int* blocks_per_cu) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>,
-                                                      fused_block<D>(),
+                                                      fused_block<R, D>(),
                                                       smem_occ);
 }
 
