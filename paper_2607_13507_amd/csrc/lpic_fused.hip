@@ -126,7 +126,11 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // issues the loads of BATCH particles (a workgroup apart, so every load instruction reads 64
 // consecutive particles) and then pushes them one by one, so HBM latency is paid once per
 // round rather than once per particle.  Returns the summed w m u^2/(1+gamma).
-constexpr int BATCH = 4;
+// In 3D one particle per thread per round: the unrolled body of four 3D particles is too
+// large for the compiler to keep their states in registers (it put them in scratch memory,
+// read and written for every particle), and a 3D workgroup brings 16 waves per CU anyway.
+template <int DIM>
+constexpr int batch_of() { return DIM == 3 ? 1 : 4; }
 // Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (at most 128
 // VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM>
@@ -147,6 +151,7 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
   const PushConst<R> k = push_const<R>(r, s);
   const PartPtrs<R> q = part_ptrs<R>(s, r);
   double ke = 0.0;
+  constexpr int BATCH = batch_of<DIM>();
   const int32_t span = (int32_t)blockDim.x * BATCH;
   for (int32_t base = ch.beg; base < ch.end; base += span) {
     PState<R> ps[BATCH];
