@@ -254,3 +254,34 @@ def test_ensemble_full_size_sampled_members_match_oracle():
         d = sim.diagnostics(r)
         assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-5), r
     sim.close()
+
+
+def test_wakefield_moving_window_fp32_tracks_fp64_over_1000_steps():
+    """The full wakefield box (8192 x 512, 15.2M electrons) with its window moving with light
+    (fresh plasma injected at the leading edge at every sort, as the benchmark runs it) for
+    1000 steps on the FP32 and the FP64 path: field energy within 1e-4 of the FP64 run's at
+    every 100th step, FP32 charge continuity below 1e-5, both windows at the same place, and
+    the alive particle counts within 1e-5 of each other (a particle at the removal margin
+    may fall either side of it in the two precisions)."""
+    import bench
+    banner("full-size wakefield, moving window: FP32 vs FP64, 1000 steps")
+    wl = W.wakefield_2d(moving=True)
+    hist = {}
+    for prec in (L.F64_ABS, L.F32_CELLOFS):
+        sim = Simulation(wl, prec=prec, tiling=(16, 16, 1), halo=5, chunk=1024,
+                         sort_interval=20, diag_interval=100, use_graph=True)
+        hist[prec] = []
+        for _ in range(10):
+            bench.advance(sim, [wl], 100)
+            d = sim.diagnostics(0)
+            d["shifted"] = sim.window_info(0)[0]
+            d["alive"] = bench.alive(sim)
+            hist[prec].append(d)
+        sim.close()
+        torch.cuda.empty_cache()
+    for d32, d64 in zip(hist[L.F32_CELLOFS], hist[L.F64_ABS]):
+        assert d32["step"] == d64["step"] and d32["shifted"] == d64["shifted"] > 0
+        # a particle at a removal boundary may go either way in the two precisions
+        assert abs(d32["alive"] - d64["alive"]) <= 1e-5 * d64["alive"], d32["step"]
+        assert d32["field_energy"] == pytest.approx(d64["field_energy"], rel=1e-4), d32["step"]
+        assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (d32, d64)
