@@ -285,3 +285,35 @@ def test_wakefield_moving_window_fp32_tracks_fp64_over_1000_steps():
         assert abs(d32["alive"] - d64["alive"]) <= 1e-5 * d64["alive"], d32["step"]
         assert d32["field_energy"] == pytest.approx(d64["field_energy"], rel=1e-4), d32["step"]
         assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (d32, d64)
+
+
+def test_thermal_3d_fp32_tracks_fp64_over_200_steps():
+    """The full 3D box (256^3, 134M electrons, quadratic, the configuration's 200 steps) on
+    the FP32 and the FP64 path with the benchmark's options: field energy and total energy
+    (field + kinetic) within 1e-4 of the FP64 run's at every 20th step, FP32 charge
+    continuity below 1e-5 (measured: 2.1e-7, 3.4e-9 and 3.4e-7)."""
+    banner("full-size 3D thermal: FP32 vs FP64, 200 steps")
+    wl = W.thermal_3d()
+    hist = {}
+    for prec in (L.F64_ABS, L.F32_CELLOFS):
+        sim = Simulation(wl, prec=prec, tiling=(8, 4, 4), halo=4 if prec == L.F32_CELLOFS else 3,
+                         chunk=2048, sort_interval=5, diag_interval=20, use_graph=True)
+        hist[prec] = []
+        for _ in range(10):
+            sim.step(20)
+            hist[prec].append(sim.diagnostics(0))
+        sim.close()
+        torch.cuda.empty_cache()
+    rel = lambda a, b: abs(a - b) / abs(b)
+    banner("max rel. differences: field %.2e, total %.2e, FP32 continuity %.2e" % (
+        max(rel(a["field_energy"], b["field_energy"]) for a, b in zip(hist[L.F32_CELLOFS], hist[L.F64_ABS])),
+        max(rel(a["field_energy"] + a["kinetic_energy"], b["field_energy"] + b["kinetic_energy"])
+            for a, b in zip(hist[L.F32_CELLOFS], hist[L.F64_ABS])),
+        max(a["continuity"] for a in hist[L.F32_CELLOFS])))
+    for d32, d64 in zip(hist[L.F32_CELLOFS], hist[L.F64_ABS]):
+        assert d32["step"] == d64["step"]
+        e32 = d32["field_energy"] + d32["kinetic_energy"]
+        e64 = d64["field_energy"] + d64["kinetic_energy"]
+        assert e32 == pytest.approx(e64, rel=1e-4), d32["step"]
+        assert d32["field_energy"] == pytest.approx(d64["field_energy"], rel=1e-4), d32["step"]
+        assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (d32, d64)
