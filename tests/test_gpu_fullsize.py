@@ -317,3 +317,29 @@ def test_thermal_3d_fp32_tracks_fp64_over_200_steps():
         assert e32 == pytest.approx(e64, rel=1e-4), d32["step"]
         assert d32["field_energy"] == pytest.approx(d64["field_energy"], rel=1e-4), d32["step"]
         assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (d32, d64)
+
+
+def test_ensemble_fp32_tracks_fp64_over_200_steps():
+    """The benchmark's 64-run ensemble (179.6M particles) for 200 steps on the FP32 and the
+    FP64 path: every member's field energy within 1e-4 of its FP64 run at steps 100 and 200,
+    and its FP32 charge continuity below 1e-5."""
+    banner("full-size ensemble: FP32 vs FP64, 200 steps")
+    members = W.ensemble_2d(seed=4, members=64)
+    hist = {}
+    for prec in (L.F64_ABS, L.F32_CELLOFS):
+        sim = Simulation(members, prec=prec, tiling=(16, 16, 1), halo=5, chunk=1024,
+                         sort_interval=20, diag_interval=100, use_graph=True)
+        hist[prec] = []
+        for _ in range(2):
+            sim.step(100)
+            hist[prec].append([sim.diagnostics(r) for r in range(len(members))])
+        sim.close()
+        torch.cuda.empty_cache()
+    worst = 0.0
+    for h32, h64 in zip(hist[L.F32_CELLOFS], hist[L.F64_ABS]):
+        for r, (d32, d64) in enumerate(zip(h32, h64)):
+            assert d32["step"] == d64["step"]
+            worst = max(worst, abs(d32["field_energy"] - d64["field_energy"]) / d64["field_energy"])
+            assert d32["continuity"] < 1e-5 and d64["continuity"] < 1e-12, (r, d32, d64)
+    banner(f"worst member field-energy difference {worst:.2e}")
+    assert worst < 1e-4
