@@ -269,3 +269,30 @@ def test_autotune_picks_a_candidate_and_keeps_physics():
     orc.step(1)
     assert sim.diagnostics(0)["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-10)
     sim.close()
+
+
+@pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=["f64", "f32"])
+def test_small_thermal_configuration_100_steps_vs_oracle(prec):
+    """The small thermal configuration as stated (64 x 64, dx = 0.05, 16 ppc, T = 0.01, CIC,
+    100 steps, 65,536 electrons on a fixed ion background), all 100 steps in one call with
+    graphs, against the oracle's 100 steps from the same state: fields element by element,
+    field and kinetic energy, continuity (FP64: 1e-8 after 100 steps of round-off growth;
+    FP32: 1e-4 tracking)."""
+    banner(f"thermal 64x64 100 steps prec={'f64' if prec == L.F64_ABS else 'f32'}")
+    wl = W.thermal_2d()
+    assert wl.nparticles == 65_536 and wl.steps == 100
+    sim = Simulation(wl, prec=prec, tiling=(16, 16, 1), halo=4, chunk=512, sort_interval=10,
+                     diag_interval=100, use_graph=True)
+    orc = _oracle_like_gpu(sim, wl)
+    sim.step(100)
+    orc.step(100)
+    torch.cuda.synchronize()
+    f64 = prec == L.F64_ABS
+    tol = 1e-8 if f64 else 1e-4
+    compare_fields(sim.fields[0], orc, prec, tol=tol, what="fields after 100 steps")
+    d = sim.diagnostics(0)
+    assert d["step"] == 100
+    assert d["field_energy"] == pytest.approx(orc.field_energy(), rel=tol)
+    assert d["kinetic_energy"] == pytest.approx(orc.kinetic_energy(), rel=tol)
+    assert d["continuity"] < (1e-12 if f64 else 1e-5)
+    sim.close()
