@@ -1080,18 +1080,6 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
   if (threadIdx.x == 0) offsets[nbins] = base;
 }
 
-template <class V>
-__device__ __forceinline__ void move_items(const int64_t p[SORT_ITEMS],
-                                           const int64_t dst[SORT_ITEMS], const V* from, V* to) {
-  V v[SORT_ITEMS];
-#pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it)
-    if (dst[it] >= 0) v[it] = gp(from)[p[it]];
-#pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it)
-    if (dst[it] >= 0) gp(to)[dst[it]] = v[it];
-}
-
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
                                                       const int32_t* offsets,
@@ -1144,17 +1132,40 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
       dst[it] = slot - s.pbase;
     }
   }
-  // move the particle arrays, one array at a time for all items (loads issued together)
-  if constexpr (sizeof(R) == 4) {
-    move_items(p, dst, (const int32_t*)s.p[P_CELL], (int32_t*)s.alt[P_CELL]);
+  // move the particle arrays: every item's words of every array are loaded before the first
+  // store, so the workgroup waits for memory once rather than once per array
+  constexpr int NA = (sizeof(R) == 4 ? 1 + DIM : DIM) + 4;   // arrays per particle
+  constexpr int WPA = sizeof(R) / 4;                          // 32-bit words per entry
+  int map[NA];
+  {
+    int k = 0;
+    if constexpr (sizeof(R) == 4) {
+      map[k++] = P_CELL;
+      for (int d = 0; d < DIM; ++d) map[k++] = P_OX + d;
+    } else {
+      for (int d = 0; d < DIM; ++d) map[k++] = P_X + d;
+    }
+    for (int q = P_UX; q <= P_W; ++q) map[k++] = q;
+  }
+  uint32_t v[NA][SORT_ITEMS][WPA];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) move_items(p, dst, (const float*)s.p[P_OX + d], (float*)s.alt[P_OX + d]);
-  } else {
+  for (int a = 0; a < NA; ++a) {
+    const uint32_t* from = (const uint32_t*)s.p[map[a]];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) move_items(p, dst, (const double*)s.p[P_X + d], (double*)s.alt[P_X + d]);
+    for (int it = 0; it < SORT_ITEMS; ++it)
+      if (dst[it] >= 0)
+#pragma unroll
+        for (int w = 0; w < WPA; ++w) v[a][it][w] = gp(from)[p[it] * WPA + w];
   }
 #pragma unroll
-  for (int q = P_UX; q <= P_W; ++q) move_items(p, dst, (const R*)s.p[q], (R*)s.alt[q]);
+  for (int a = 0; a < NA; ++a) {
+    uint32_t* to = (uint32_t*)s.alt[map[a]];
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it)
+      if (dst[it] >= 0)
+#pragma unroll
+        for (int w = 0; w < WPA; ++w) gp(to)[dst[it] * WPA + w] = v[a][it][w];
+  }
 }
 
 // =======================================================================================
