@@ -673,7 +673,7 @@ __global__ __launch_bounds__(256) void k_yee_mid(Tables T, FieldBands Bd) {
 }
 
 // J := 0 (and the charge arrays when asked and present), four cells per thread, 256 cells
-// per workgroup of 64.  flip != NULL: the launch follows a fused field update; its first
+// per wave, four waves per workgroup.  flip != NULL: the launch follows a fused field update; its first
 // thread makes the snapshot that update wrote the present one and, with clock != NULL,
 // advances the antenna clock as the antenna kernel would have.
 template <typename R>
@@ -691,16 +691,23 @@ __device__ __forceinline__ void zero4(R* p, int64_t c, int64_t n) {
 }
 
 template <typename R, int DIM>
-__global__ __launch_bounds__(64) void k_clear_sources(Tables T, int with_rho, int32_t* flip,
-                                                      int64_t* clock) {
+__global__ __launch_bounds__(256) void k_clear_sources(Tables T, int nblk, int with_rho,
+                                                       int32_t* flip, int64_t* clock) {
   if (flip && blockIdx.x == 0 && threadIdx.x == 0) {
     *flip ^= 1;
     if (clock) *clock += 1;
   }
-  int blk;
-  const RunDesc& r = run_of(T, cell_block(T, blk));
+  // each wave clears one 256-cell block of the cell-block prefix (four per workgroup)
+  const int vb = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (vb >= nblk) return;
+  int blk = vb, ri = 0;
+  if (T.runs) {
+    ri = uniform(find_owner(T.run_blk, T.nruns, vb));
+    blk = uniform(vb - T.run_blk[ri]);
+  }
+  const RunDesc& r = run_of(T, ri);
   const int64_t n = (int64_t)r.nx * r.ny * (DIM == 3 ? r.nz : 1);
-  const int64_t c = (int64_t)blk * 256 + 4 * threadIdx.x;
+  const int64_t c = (int64_t)blk * 256 + 4 * (threadIdx.x & 63);
   if (c >= n) return;
   zero4((R*)r.f[F_JX], c, n);
   zero4((R*)r.f[F_JY], c, n);
@@ -1709,7 +1716,8 @@ void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& ban
 
 void launch_clear_sources(const Tables& T, int prec, int dim, int nblocks, int with_rho,
                           int32_t* flip, int64_t* clock, hipStream_t st) {
-  LPIC_PD(prec, dim, (k_clear_sources<R, D><<<nblocks, 64, 0, st>>>(T, with_rho, flip, clock)));
+  LPIC_PD(prec, dim, (k_clear_sources<R, D><<<(nblocks + 3) / 4, 256, 0, st>>>(T, nblocks, with_rho,
+                                                                              flip, clock)));
 }
 
 void launch_laser(const Tables& T, int prec, int dim, int nruns, int bpr, double t,
