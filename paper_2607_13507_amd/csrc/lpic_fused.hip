@@ -129,8 +129,9 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // In 3D one particle per thread per round: the unrolled body of four 3D particles is too
 // large for the compiler to keep their states in registers (it put them in scratch memory,
 // read and written for every particle), and a 3D workgroup brings 16 waves per CU anyway.
-template <int DIM>
-constexpr int batch_of() { return DIM == 3 ? 1 : 4; }
+// In 2D FP64 two: four FP64 states take the registers of a third wave per SIMD.
+template <typename R, int DIM>
+constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 2); }
 // Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (at most 128
 // VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM>
@@ -151,7 +152,7 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
   const PushConst<R> k = push_const<R>(r, s);
   const PartPtrs<R> q = part_ptrs<R>(s, r);
   double ke = 0.0;
-  constexpr int BATCH = batch_of<DIM>();
+  constexpr int BATCH = batch_of<R, DIM>();
   const int32_t span = (int32_t)blockDim.x * BATCH;
   for (int32_t base = ch.beg; base < ch.end; base += span) {
     PState<R> ps[BATCH];
