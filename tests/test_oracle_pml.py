@@ -172,3 +172,37 @@ def test_graded_layer_reflects_far_less_than_mur(n_y, ny):
         theory = ((1 - kx) / (1 + kx)) ** 2
         assert r_mur == pytest.approx(theory, rel=0.25)
     assert r_mur > 1e3 * r_pml
+
+
+def _einc(las, t):
+    """The antenna's incident field on its axis (the definition in the oracle's header)."""
+    t = np.asarray(t, dtype=np.float64) - las["t0"]
+    env = np.where((t >= 0) & (t <= las["tau"]), np.sin(np.pi * t / las["tau"]) ** 2, 0.0)
+    return las["a0"] * las["omega"] * env * np.sin(las["omega"] * t)
+
+
+@pytest.mark.parametrize("pol", [1, 2])
+def test_antenna_between_layers_in_3d(pol):
+    """3D, plane antenna (huge waist) between two graded layers: right of it the field is the
+    retarded incident field, left of it the left-going half, and once the pulse has left
+    through both layers (nothing comes back from them) the box is empty."""
+    nx, ny, nz, ia, Lc = 400, 2, 2, 40, 12
+    las = dict(pol=pol, ia=ia, a0=1.0, omega=1.0, waist=1e9, yc=0.0, zc=0.0, t0=0.0, tau=40.0)
+    dt = W.cfl_dt(0.95, DX, DX, DX)
+    o = OracleSim(3, nx, ny, nz, DX, DX, DX, dt, 0.0, [], None, open_x=True, laser=las,
+                  pml=dict(cells=Lc))
+    n = int(60.0 / dt)
+    o.step(n)
+    t = n * dt
+    x = np.arange(nx) * DX
+    comp = "ey" if pol == 1 else "ez"
+    e = o.f[comp].reshape(nz, ny, nx)[0, 0]
+    near = (x > (ia + 2) * DX) & (x < (ia + 60) * DX)
+    np.testing.assert_allclose(e[near], _einc(las, t - (x[near] - ia * DX)), atol=0.02)
+    left = (x >= Lc * DX) & (x < (ia - 2) * DX)
+    np.testing.assert_allclose(e[left], _einc(las, t - (ia * DX - x[left])), atol=0.02)
+    # both halves leave: the pulse is 40/dx ~ 200 cells long, the box 400; after it has
+    # crossed the right layer nothing of it is left
+    peak = o.field_energy()
+    o.step(int(70.0 / dt))
+    assert o.field_energy() < 1e-6 * peak
