@@ -227,3 +227,28 @@ def _oracle_like_run(sim, wl, r):
         for k in ("ux", "uy", "uz", "w"):
             getattr(s, k)[:] = cur.numpy(k)
     return orc
+
+
+@pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=["f64", "f32"])
+def test_pml_with_hooks_equals_the_fused_path(prec):
+    """A hook at an intermediate particle stage runs the split kernels and the unmerged field
+    halves; with PML layers and an antenna the result equals the fused path's (FP64 1e-12,
+    FP32 1e-5 of each component's largest value)."""
+    banner(f"pml split path prec={'f64' if prec == L.F64_ABS else 'f32'}")
+    wl = _pml_box(2, seed=89)
+    kw = dict(prec=prec, tiling=(8, 8, 1), halo=4, chunk=128, sort_interval=3, diag_interval=4,
+              use_graph=True)
+    a = Simulation(wl, **kw)
+    b = Simulation(wl, **kw)
+    b.register_hook("PUSH_MOMENTUM", lambda sim, stage, step: None)
+    a.step(8)
+    b.step(8)
+    torch.cuda.synchronize()
+    assert a.stats()["fused"] and not b.stats()["fused"]
+    fa, fb = a.fields[0].numpy(), b.fields[0].numpy()
+    tol = 1e-12 if prec == L.F64_ABS else 1e-5
+    for k in KEYS:
+        scale = max(1e-300, np.abs(fa[k]).max())
+        assert np.abs(fa[k].astype(np.float64) - fb[k]).max() / scale < tol, k
+    a.close()
+    b.close()
