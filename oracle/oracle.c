@@ -4,7 +4,8 @@
  * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the benchmark's
  * CPU-baseline leg, never by the product path.  Deliberately simple: every loop visits a
  * generous window of nodes and evaluates the shape function from its piecewise definition,
- * so that each formula can be checked against the paper by eye.  Single threaded.
+ * so that each formula can be checked against the paper by eye.  Single threaded; only
+ * orc_step_threads, a timing driver, runs the same particle loop on several threads.
  *
  * Each function names the passage of the paper it follows (section, equation, algorithm).
  */
@@ -14,6 +15,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static int64_t wrap(int64_t i, int64_t n) {
   int64_t r = i % n;
@@ -390,12 +394,13 @@ static double wrap_pos(double p, double L) {
  * x^{n+1/2} to x^{n+1/2} + dt v^{n+1}, which gives J at the whole time level n+1 that
  * Eq. 3 pairs with E^{n+1/2} -> E^{n+3/2}.  The stored position x^{n+1} is the midpoint of
  * that path. */
-static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
-                            double *xso, double *yso, double *zso) {
+static void advance_range(const orc_grid *g, orc_fields *f, orc_species *s, int64_t p_begin,
+                          int64_t p_end, int32_t deposit, double *xso, double *yso,
+                          double *zso) {
   int nd = g->ndim;
   double dt = g->dt;
   double L[3] = {g->nx * g->dx, g->ny * g->dy, g->nz * g->dz};
-  for (int64_t p = 0; p < s->n; ++p) {
+  for (int64_t p = p_begin; p < p_end; ++p) {
     if (s->x[p] < 0.0) continue; /* dead particle */
     double p0[3] = {s->x[p], s->y[p], (nd == 3) ? s->z[p] : 0.0};
     double u[3] = {s->ux[p], s->uy[p], s->uz[p]};
@@ -430,6 +435,11 @@ static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, in
                       p1[0] >= (g->nx - ORC_OPEN_MARGIN) * g->dx))
       s->x[p] = -1.0;   /* left through an open x end */
   }
+}
+
+static void advance_species(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
+                            double *xso, double *yso, double *zso) {
+  advance_range(g, f, s, 0, s->n, deposit, xso, yso, zso);
 }
 
 void orc_push_deposit(const orc_grid *g, orc_fields *f, orc_species *s, int32_t deposit,
@@ -478,6 +488,61 @@ void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecie
   if (laser) orc_laser_source(g, f, laser, t_next);
   orc_yee_b(g, f, 0.5);
   orc_yee_e(g, f, 0.5);
+}
+
+/* The same timestep with the particle loop spread over nthreads threads, for timing the
+ * oracle on all host cores.  Every particle takes exactly the arithmetic of orc_step; each
+ * thread deposits into private zeroed current (and charge) arrays, which are added into the
+ * shared ones afterwards in thread order, so the result differs from orc_step only in the
+ * order of the current sums.  Field updates and the antenna stay single threaded.  Returns
+ * the number of threads that ran the particle loop. */
+int32_t orc_step_threads(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies,
+                         const orc_laser *laser, double t_next, int32_t nthreads) {
+  int64_t n = ncell(g);
+  int nt = nthreads > 0 ? nthreads : 1;
+  const int nprivate = 5;
+  double *priv = (double *)calloc((size_t)nt * nprivate * n, sizeof(double));
+  if (!priv) return -1;
+  int ran = 1;
+  orc_yee_e(g, f, 0.5);
+  orc_yee_b(g, f, 0.5);
+#pragma omp parallel num_threads(nt)
+  {
+    int t = 0, tn = 1;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+    tn = omp_get_num_threads();
+#pragma omp single
+    ran = tn;
+#endif
+    double *base = priv + (size_t)t * nprivate * n;
+    orc_fields mine = *f;
+    mine.jx = base;
+    mine.jy = base + n;
+    mine.jz = base + 2 * n;
+    mine.rho0 = f->rho0 ? base + 3 * n : NULL;
+    mine.rho1 = f->rho1 ? base + 4 * n : NULL;
+    for (int s = 0; s < nspecies; ++s) {
+      int64_t per = (sp[s].n + tn - 1) / tn;
+      int64_t lo = (int64_t)t * per, hi = lo + per < sp[s].n ? lo + per : sp[s].n;
+      if (lo < hi) advance_range(g, &mine, &sp[s], lo, hi, 1, NULL, NULL, NULL);
+    }
+#pragma omp barrier
+    double *dst[5] = {f->jx, f->jy, f->jz, f->rho0, f->rho1};
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < nprivate; ++c) {
+        if (!dst[c]) continue;
+        double acc = 0.0;
+        for (int k = 0; k < tn; ++k) acc += priv[((size_t)k * nprivate + c) * n + i];
+        dst[c][i] = acc;
+      }
+  }
+  free(priv);
+  if (laser) orc_laser_source(g, f, laser, t_next);
+  orc_yee_b(g, f, 0.5);
+  orc_yee_e(g, f, 0.5);
+  return ran;
 }
 
 static double cell_volume(const orc_grid *g) {

@@ -150,6 +150,12 @@ void orc_laser_source(const orc_grid *g, orc_fields *f, const orc_laser *laser, 
 void orc_step(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies,
               const orc_laser *laser, double t_next);
 
+/* orc_step with the particle loop on nthreads threads (private current arrays added in
+ * thread order afterwards; timing only).  Returns the threads used, or -1 if the private
+ * arrays cannot be allocated.  The current and charge arrays are overwritten. */
+int32_t orc_step_threads(const orc_grid *g, orc_fields *f, orc_species *sp, int32_t nspecies,
+                         const orc_laser *laser, double t_next, int32_t nthreads);
+
 /* Diagnostics (all FP64).  dV is the cell volume (dx*dy or dx*dy*dz). */
 double orc_field_energy(const orc_grid *g, const orc_fields *f);
 double orc_kinetic_energy(const orc_grid *g, const orc_species *s);
