@@ -355,3 +355,27 @@ def random_fields(ncell, seed, scale=1.0, names=("ex", "ey", "ez", "bx", "by", "
     """Uniform random field values in [-scale, scale) for unit-level kernel checks."""
     rng = np.random.default_rng(seed)
     return {k: scale * (2 * rng.random(ncell) - 1) for k in names}
+
+
+def deterministic_ensemble(steps=1000):
+    """Independent 2D boxes of mixed sizes whose evolution is deterministic (no thermal
+    noise): vacuum standing modes, a vacuum Gaussian pulse, and cold electron lattices
+    (CIC and quadratic) on fixed ions with a velocity perturbation along x or y."""
+    members = [
+        vacuum_mode(nx=64, ny=64, dx=0.05, mx=2, my=1, steps=steps, name="ens_vacuum_64x64"),
+        vacuum_mode(nx=48, ny=32, dx=0.05, mx=1, my=2, amp=0.5, steps=steps,
+                    name="ens_vacuum_48x32"),
+        gaussian_pulse_vacuum(nx=256, ny=64, cells_per_lambda=32, a0=2.0, steps=steps,
+                              name="ens_pulse_256x64"),
+        cold_langmuir(nx=64, ny=16, dx=0.05, lattice=4, amp=1e-2, order=1, steps=steps,
+                      name="ens_cold_cic_64x16"),
+        cold_langmuir(nx=32, ny=32, dx=0.05, lattice=2, amp=2e-2, order=2, steps=steps,
+                      name="ens_cold_quad_32x32"),
+        cold_langmuir(nx=128, ny=16, dx=0.05, lattice=2, amp=5e-3, order=2, steps=steps,
+                      name="ens_cold_quad_128x16"),
+    ]
+    # the last lattice oscillates along y instead of x: same plasma, axes exchanged in u
+    s = members[-1].species[0]
+    s.ux, s.uy = np.zeros_like(s.ux), 5e-3 * np.sin(2 * math.pi * s.y / (16 * 0.05))
+    members[-1].meta["perturbed_axis"] = "y"
+    return members
