@@ -5,19 +5,26 @@ tile sort (every K steps), fused gather + Boris push + Esirkepov deposit over al
 field half updates, FP64 diagnostics every 10 steps.  A push is one alive macro-particle
 advanced through gather + push + deposit.
 
-Workload (default): 2D3V 2048x1024 Yee grid, dx = lambda/32, fully ionised hydrogen slab of
-20 n_c in cells x in [512, 768), electrons + protons at 32 ppc each (16,777,216 particles),
-T = 1 keV, quadratic shape, linearly polarised a0 = 10 Gaussian laser (waist 6.25 lambda,
-sin^2 envelope of 25 lambda / c) injected by an antenna 4 cells inside the left absorbing
-layer, open x ends with 16-cell graded convolutional PML layers (the absorbing boundaries
-of Sec. 3.2; --pml 0: first-order Mur ends), periodic y, seeded synthetic data.  The FP32 cell+offset path is `value`;
-the plain FP64 path is reported beside it.
+Headline workload (default): the batched ensemble of 64 independent 2D3V laser-slab runs
+drawn from seed 4 (grids 128x128 .. 1024x512, ppc 4-32 per species, slab density 0.1-10
+n_c, a0 0.5-20 injected from the left, CIC or quadratic, 179,609,600 particles), all of them
+advanced by one launch per kernel and one captured graph per step, options chosen by the
+library's autotuner.  It is the largest configuration of the metric that fits one GPU.
 
-Timing: after the warmup steps (and alignment to a sort period), K steps run eagerly with HIP
-events around every fused launch (the kernel's average launch time for the roofline), then,
-after one untimed period that captures every step variant, the same K steps replay from the
-captured graphs, the library's default mode: that pass is `value` and `ms_per_step`
-(`eager_mode` reports the first one; --no-graph makes it `value`).
+Also measured, each with its own roofline and CPU baseline (keys of "extra"):
+  laser_slab              2D3V 2048x1024, H slab 20 n_c, e- + p+ 32 ppc (16,777,216), quadratic,
+                          a0 = 10 antenna inside a 16-cell PML layer: the first steps;
+  laser_slab_interaction  the same box timed from step 1200, when the pulse is inside the
+                          slab (relativistic hot electrons, particles leaving their tiles);
+  thermal_3d              3D3V periodic 256^3, 8 ppc (134,217,728), T = 0.05, quadratic, sort
+                          every 20 steps as the configuration states;
+  wakefield               2D3V 8192x512, 0.01 n_c at 4 ppc, a0 = 2, window moving with light.
+
+Every configuration runs the FP32 cell+offset path (`value`) and the plain FP64 path beside
+it.  Timing: after the warmup steps (and alignment to a sort period), K steps run eagerly
+with HIP events around every fused launch (the kernel's average launch time for the
+roofline), then, after one untimed period that captures every step variant, the same K
+steps replay from the captured graphs, the library's default mode: that pass is the rate.
 
 Output: one JSON line.  The benchmark runs on one GPU; with --gpus > 1 it exits (the
 multi-GPU decomposition is a design, not implemented).
@@ -36,9 +43,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_PEAK = 614.4e9            # wave64 VALU instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz / 4
 KERNEL_SOURCES = ("paper_2607_13507_amd/csrc/lpic_device.hpp",
                   "paper_2607_13507_amd/csrc/lpic_fused.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_laser_slab_2048x1024_pmc.md")
+METRIC = "particle-pushes/sec (gather+push+deposit) FP32 vs FP64, % HBM roofline"
+WORKLOADS = ("ensemble", "laser_slab", "thermal_3d", "wakefield")
+INTERACTION_STEP = 1200        # the laser slab's pulse is inside the slab by then
 
 
 def kernel_source_hash():
@@ -61,45 +71,45 @@ def algorithmic_bytes_per_push(ndim, prec_f32, ppc_tot):
     return part + grid / ppc_tot
 
 
-def read_traffic(launch_bytes_key="per_launch_bytes"):
-    """HBM bytes per fused launch from the committed PMC summary, if it was taken on the
-    current kernel source (else None)."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def read_summary(name, key):
+    """A value from a committed PMC summary (profiles/fused_<name>_pmc.md), if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"fused_{name}_pmc.md")
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_SUMMARY):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(vals[launch_bytes_key])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
 
-def build_workload(args):
+# ------------------------------------------------------------------------------------------
+# workloads
+# ------------------------------------------------------------------------------------------
+def build_workload(name):
     """(list of runs, description, ndim, particles per occupied cell of each run)."""
     from paper_2607_13507_amd import workloads as W
-    if args.workload == "laser_slab":
-        wl = W.laser_slab_2d(nx=args.nx, ny=args.ny, slab=(args.nx // 4, args.nx * 3 // 8),
-                             ppc=args.ppc, steps=args.steps, pml_cells=args.pml)
-        ends = (f"open x ends with {args.pml}-cell graded PML layers" if args.pml else
-                "open x ends (first-order Mur)")
-        desc = (f"laser_slab_2d {args.nx}x{args.ny} dx=lambda/32, H slab 20 n_c cells x in "
-                f"[{args.nx // 4},{args.nx * 3 // 8}), e- + p+ {args.ppc} ppc each "
-                f"({wl.nparticles} particles), T=1 keV, quadratic, a0=10 laser injected at the "
-                f"open left end (antenna, waist 6.25 lambda, 25 lambda sin^2), {ends}, "
-                "FP32 cell+offset")
-        return [wl], desc, 2, [2 * args.ppc]
-    if args.workload == "thermal_3d":
+    if name == "laser_slab":
+        wl = W.laser_slab_2d(pml_cells=16)
+        desc = ("laser_slab_2d 2048x1024 dx=lambda/32, H slab 20 n_c cells x in [512,768), "
+                f"e- + p+ 32 ppc each ({wl.nparticles} particles), T=1 keV, quadratic, a0=10 "
+                "laser injected at the open left end (antenna, waist 6.25 lambda, 25 lambda "
+                "sin^2), open x ends with 16-cell graded PML layers, FP32 cell+offset")
+        return [wl], desc, 2, [64]
+    if name == "thermal_3d":
         wl = W.thermal_3d()
         desc = (f"thermal_3d 256^3 dx=0.1 c/omega_p, electrons 8 ppc ({wl.nparticles} "
-                "particles) on a fixed ion background, T=0.05, quadratic, periodic, "
-                "FP32 cell+offset")
+                "particles) on a fixed ion background, T=0.05, quadratic, periodic, sort every "
+                "20 steps, FP32 cell+offset")
         return [wl], desc, 3, [8]
-    if args.workload == "wakefield":
+    if name == "wakefield":
         wl = W.wakefield_2d(moving=True)
         alive0 = int((wl.species[0].x >= 0).sum())
         desc = (f"wakefield_2d 8192x512 dx=lambda/40, electrons 0.01 n_c 4 ppc on a 2x2 "
@@ -110,9 +120,24 @@ def build_workload(args):
     members = W.ensemble_2d(seed=4, members=64)
     n = sum(m.nparticles for m in members)
     desc = (f"ensemble_2d 64 independent laser-slab runs from seed 4 ({n} particles), grids "
-            "128^2..1024x512, ppc 4-32, CIC/quadratic, lasers from the left, one step of all "
-            "of them per launch, FP32 cell+offset")
+            "128^2..1024x512, ppc 4-32 per species, density 0.1-10 n_c, a0 0.5-20 injected "
+            "from the left, CIC/quadratic, one launch per kernel for all runs, FP32 cell+offset")
     return members, desc, 2, [2 * m.meta["ppc"] for m in members]
+
+
+def tune_space(name, ndim, f32):
+    """Search space of the autotuner (lpic_autotune_search) per workload."""
+    if ndim == 3:   # sort every 20 steps, as the 3D configuration states
+        return dict(tile=((4, 4, 4), (8, 8, 8)), halo=(3, 5 if f32 else 4), chunk=(1024, 4096),
+                    sort_interval=(20, 20), steps_each=20, max_trials=10)
+    return dict(tile=((8, 8, 1), (32, 32, 1)), halo=(3, 7), chunk=(512, 4096),
+                sort_interval=(10, 80), steps_each=40, max_trials=24 if f32 else 12)
+
+
+def start_options(ndim, f32):
+    if ndim == 3:
+        return dict(tiling=(8, 4, 4), halo=4 if f32 else 3, chunk=2048, sort_interval=20)
+    return dict(tiling=(16, 16, 1), halo=5, chunk=1024, sort_interval=20)
 
 
 def alive(sim):
@@ -144,50 +169,18 @@ def advance(sim, wl, n):
                 sim.window_shift(0, m, win["plasma"])
 
 
-def run_gpu(wl, prec, args, steps, warmup, tune):
+# ------------------------------------------------------------------------------------------
+# GPU measurement
+# ------------------------------------------------------------------------------------------
+def timed_window(sim, wl, steps, graph):
+    """K steps eagerly with HIP events around every fused launch, then (graph) one untimed
+    period in graph mode and the same K steps replayed from the captured graphs."""
     import torch
-    from paper_2607_13507_amd import lpic as L
-    from paper_2607_13507_amd.simulation import Simulation
-
-    ty, halo = args.tile, args.halo
-    if wl[0].ndim == 3:   # a 3D region with its charge planes must fit one CU's LDS
-        ty = max(1, args.tile // 2)
-        if prec == L.F64_ABS:
-            halo = max(3, halo - 1)
-    tiling, chunk, sort_interval = (args.tile, ty, args.tile_z), args.chunk, args.sort_interval
-    tuned = None
-    if tune:
-        # the autotuner (lpic_autotune) times each candidate over whole sort and diagnostics
-        # periods and keeps the fastest per step; it advances the simulation it tunes, so it
-        # runs on a copy and the measured run starts from the workload's initial state
-        if wl[0].ndim == 2:
-            cands = [dict(tiling=(16, 16, 1), halo=5, chunk=ch, sort_interval=k, use_graph=True)
-                     for k in (20, 40) for ch in (1024, 2048)]
-            cands.append(dict(tiling=(16, 16, 1), halo=6, chunk=1024, sort_interval=40,
-                              use_graph=True))
-        else:   # a 3D tile region with its charge planes fills most of one CU's LDS
-            cands = [dict(tiling=(8, 4, 4), halo=halo, chunk=2048, sort_interval=k,
-                          use_graph=True) for k in (5, 10, 20)]
-        tsim = Simulation(wl, prec=prec, tiling=tiling, halo=halo, chunk=chunk,
-                          sort_interval=sort_interval, diag_interval=10, use_graph=True)
-        tuned = tsim.autotune(cands, steps_each=40 if wl[0].ndim == 2 else 10)
-        tsim.close()
-        del tsim
-        torch.cuda.empty_cache()
-        tiling, halo, chunk, sort_interval = (tuned["tiling"], tuned["halo"], tuned["chunk"],
-                                              tuned["sort_interval"])
-    sim = Simulation(wl, prec=prec, tiling=tiling, halo=halo, chunk=chunk,
-                     sort_interval=sort_interval, diag_interval=10, use_graph=not args.no_graph)
-    advance(sim, wl, warmup)
-    # the timed steps start where a sort and a diagnostics step fall together, so that the
-    # window holds at least its proportional share of both (whole periods: exactly)
     k = sim.options.sort_interval
     period = k // math.gcd(k, 10) * 10
-    advance(sim, wl, (-sim.nstep) % period)
-    torch.cuda.synchronize()
-    # timed region: eager launches with HIP events around every fused launch
     sim.set_timing(True)
     n0 = alive(sim)
+    e0 = sim.stats()["halo_escapes"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     advance(sim, wl, steps)
@@ -196,38 +189,76 @@ def run_gpu(wl, prec, args, steps, warmup, tune):
     st = sim.stats()
     sim.set_timing(False)
     n = 0.5 * (n0 + alive(sim))   # pushes per step (a moving window adds particles)
-    # the same number of steps again as captured graphs (no per-kernel events), after one
-    # untimed sort period in graph mode so that every step variant is already captured
-    if not args.no_graph:
-        advance(sim, wl, period + (-(sim.nstep + period)) % period)
-    torch.cuda.synchronize()
-    ng0 = alive(sim)
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    if not args.no_graph:
-        advance(sim, wl, steps)
-    torch.cuda.synchronize()
-    g1 = time.perf_counter()
-    ng = 0.5 * (ng0 + alive(sim))
-    diag = sim.diagnostics(0)
-    stg = sim.stats()
-    res = dict(ms_per_step=1e3 * (t1 - t0) / steps,
-               pushes_per_s=n * steps / (t1 - t0),
-               alive=int(n),
-               ms_per_step_graph=None if args.no_graph else 1e3 * (g1 - g0) / steps,
-               pushes_per_s_graph=None if args.no_graph else ng * steps / (g1 - g0),
-               fused_ms=st["fused_ms"] / max(1, st["fused_launches"]),
+    res = dict(eager_ms_per_step=1e3 * (t1 - t0) / steps, eager_pushes_per_s=n * steps / (t1 - t0),
+               alive=int(n), fused_ms=st["fused_ms"] / max(1, st["fused_launches"]),
                fused_launches=st["fused_launches"],
-               halo_escapes_per_push=stg["halo_escapes"] / max(1, n * stg["steps"]),
-               window_cells=sim.window_info(0)[0] if wl[0].ndim == 2 else 0,
-               graph=stg["graph"], diagnostics=diag, tuned=tuned,
-               options=dict(tile=sim.options.tiling.tx, halo=sim.options.tiling.halo,
-                            chunk=sim.options.tiling.chunk,
-                            sort_interval=sim.options.sort_interval))
+               halo_escapes_per_push=(st["halo_escapes"] - e0) / max(1.0, n * steps))
+    res["ms_per_step"], res["pushes_per_s"] = res["eager_ms_per_step"], res["eager_pushes_per_s"]
+    if graph:
+        advance(sim, wl, period + (-(sim.nstep + period)) % period)
+        torch.cuda.synchronize()
+        ng0 = alive(sim)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        advance(sim, wl, steps)
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        ng = 0.5 * (ng0 + alive(sim))
+        res["ms_per_step"] = 1e3 * (g1 - g0) / steps
+        res["pushes_per_s"] = ng * steps / (g1 - g0)
+    res["step_at_end"] = sim.nstep
+    res["diagnostics"] = sim.diagnostics(0)
+    return res
+
+
+def run_gpu(name, wl, ndim, prec, args, steps, warmup, tune, interaction=False):
+    import torch
+    from paper_2607_13507_amd import lpic as L
+    from paper_2607_13507_amd.simulation import Simulation
+
+    f32 = prec == L.F32_CELLOFS
+    opt = start_options(ndim, f32)
+    if args.tile:
+        opt["tiling"] = tuple(args.tile)
+    for key in ("halo", "chunk", "sort_interval"):
+        if getattr(args, key) is not None:
+            opt[key] = getattr(args, key)
+    tuned, trials = None, []
+    if tune:
+        # lpic_autotune_search advances the simulation it tunes, so it runs on a copy and
+        # the measured run starts from the workload's initial state
+        tsim = Simulation(wl, prec=prec, tiling=opt["tiling"], halo=opt["halo"],
+                          chunk=opt["chunk"], sort_interval=opt["sort_interval"],
+                          diag_interval=10, use_graph=True)
+        tuned, trials = tsim.autotune_search(**tune_space(name, ndim, f32))
+        tsim.close()
+        del tsim
+        torch.cuda.empty_cache()
+        opt = dict(tiling=tuned["tiling"], halo=tuned["halo"], chunk=tuned["chunk"],
+                   sort_interval=tuned["sort_interval"])
+    sim = Simulation(wl, prec=prec, tiling=opt["tiling"], halo=opt["halo"], chunk=opt["chunk"],
+                     sort_interval=opt["sort_interval"], diag_interval=10,
+                     use_graph=not args.no_graph)
+    advance(sim, wl, warmup)
+    # the timed steps start where a sort and a diagnostics step fall together, so that the
+    # window holds at least its proportional share of both (whole periods: exactly)
+    k = sim.options.sort_interval
+    period = k // math.gcd(k, 10) * 10
+    advance(sim, wl, (-sim.nstep) % period)
+    out = dict(start=timed_window(sim, wl, steps, not args.no_graph))
+    if interaction:
+        advance(sim, wl, max(0, INTERACTION_STEP - sim.nstep))
+        advance(sim, wl, (-sim.nstep) % period)
+        out["interaction"] = timed_window(sim, wl, steps, not args.no_graph)
+    t = sim.options.tiling
+    out["options"] = dict(tiling=[t.tx, t.ty, t.tz], halo=t.halo, chunk=t.chunk,
+                          sort_interval=sim.options.sort_interval)
+    out["tuned"] = tuned
+    out["tune_trials"] = trials
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return res
+    return out
 
 
 def copy_calibration(mib):
@@ -264,6 +295,9 @@ def copy_bandwidth(mib=1024, reps=5):
     return round(gbs, 1)
 
 
+# ------------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host
+# ------------------------------------------------------------------------------------------
 def host_cpu():
     try:
         for line in open("/proc/cpuinfo"):
@@ -274,17 +308,148 @@ def host_cpu():
     return "unknown CPU"
 
 
-def cpu_baseline(wl):
-    """The FP64 oracle (single thread) on one full step of the same workload."""
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_sample(wls, target):
+    """Oracle simulations holding about `target` particles of the workload: whole boxes in
+    order, the last one (or a single box) cut to its first particles of every species (the
+    generators lay particles out cell by cell, so a cut keeps whole cells)."""
+    import numpy as np
     import oracle
-    orc = oracle.OracleSim.from_workload(wl)
+    sims, taken = [], 0
+    for wl in wls:
+        if taken >= target:
+            break
+        orc = oracle.OracleSim.from_workload(wl, with_rho=False)
+        if taken + wl.nparticles > target:
+            frac = (target - taken) / wl.nparticles
+            for s in orc.species:
+                m = max(1, int(s.n * frac))
+                for k in ("x", "y", "z", "ux", "uy", "uz", "w"):
+                    a = getattr(s, k)
+                    if a is not None:
+                        setattr(s, k, np.ascontiguousarray(a[:m]))
+        alive_n = sum(int((s.x >= 0).sum()) for s in orc.species)
+        sims.append(orc)
+        taken += alive_n
+    return sims, taken
+
+
+def cpu_baseline(name, wls):
+    """The FP64 oracle as it is, one step of a bounded sample of the workload: once on one
+    thread (the parity mode) and once with its particle loop on every host thread
+    (orc_step_threads: private current arrays per thread, added afterwards)."""
+    nthreads = host_threads()
+    single_target = 3_000_000 if name == "thermal_3d" else 12_000_000
+    multi_target = min(sum(w.nparticles for w in wls),
+                       (4_000_000 if name == "thermal_3d" else 16_000_000) * max(1, nthreads // 2))
+    sims, n1 = _oracle_sample(wls, single_target)
     t0 = time.perf_counter()
-    orc.step(1)
-    dt = time.perf_counter() - t0
-    return dict(value=wl.nparticles / dt, unit="particle-pushes/s", cores=1, kind="oracle",
-                sample=f"one full step (all {wl.nparticles} particles, {wl.nx}x{wl.ny} grid) "
-                       f"of the benchmark workload, FP64, single thread on {host_cpu()} "
-                       f"({os.cpu_count()} logical CPUs visible), {dt:.1f} s")
+    for s in sims:
+        s.step(1)
+    t1 = time.perf_counter() - t0
+    del sims
+    sims, nm = _oracle_sample(wls, multi_target)
+    used = 1
+    t0 = time.perf_counter()
+    for s in sims:
+        used = s.step_threads(1, nthreads)
+    tm = time.perf_counter() - t0
+    del sims
+    what = "boxes" if len(wls) > 1 else "particles"
+    return dict(value=round(nm / tm, 1), unit="particle-pushes/s", cores=used, kind="oracle",
+                sample=f"one step of {nm} {name} particles ({what} taken in order up to that "
+                       f"count, full grids), FP64, particle loop on {used} threads of "
+                       f"{host_cpu()} ({nthreads} usable), {tm:.1f} s",
+                single_thread=dict(value=round(n1 / t1, 1), cores=1,
+                                   sample=f"one step of {n1} particles, one thread, {t1:.1f} s"))
+
+
+# ------------------------------------------------------------------------------------------
+def roofline_of(name, ndim, wls, ppc_tot, res, launch_key="start"):
+    """HBM roofline of the dominant kernel (k_fused, FP32) for one configuration."""
+    w = res[launch_key]
+    slots = sum(x.nparticles for x in wls)
+    nparticles = w["alive"]
+    launch_bytes = sum(algorithmic_bytes_per_push(ndim, True, p) * x.nparticles
+                       for x, p in zip(wls, ppc_tot)) * nparticles / slots
+    achieved = launch_bytes / (w["fused_ms"] * 1e-3) / 1e9
+    key = name if launch_key == "start" else f"{name}_{launch_key}"
+    traffic = read_summary(key, "per_launch_bytes")
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=f"lpic::k_fused<float,{ndim}>",
+                bytes_per_push=round(launch_bytes / nparticles, 3),
+                bytes_per_launch=int(launch_bytes), avg_launch_ms=round(w["fused_ms"], 4),
+                launches=w["fused_launches"], kernel_source_sha256=kernel_source_hash())
+    valu = read_summary(key, "valu_insts_per_launch")
+    if valu:
+        rate = valu / (w["fused_ms"] * 1e-3)
+        roof["valu_issue"] = dict(insts_per_launch=int(valu), achieved=round(rate / 1e9, 1),
+                                  peak=VALU_PEAK / 1e9, unit="G wave-instructions/s",
+                                  frac=round(rate / VALU_PEAK, 4))
+    return roof
+
+
+def fp64_entry(ndim, wls, ppc_tot, r64, key="start"):
+    w = r64[key]
+    slots = sum(x.nparticles for x in wls)
+    launch_bytes = sum(algorithmic_bytes_per_push(ndim, False, p) * x.nparticles
+                       for x, p in zip(wls, ppc_tot)) * w["alive"] / slots
+    gbs = launch_bytes / (w["fused_ms"] * 1e-3) / 1e9
+    return dict(pushes_per_s=round(w["pushes_per_s"], 1), ms_per_step=round(w["ms_per_step"], 4),
+                fused_avg_ms=round(w["fused_ms"], 4), kernel=f"lpic::k_fused<double,{ndim}>",
+                bytes_per_push=round(launch_bytes / w["alive"], 3),
+                fused_hbm_gbs=round(gbs, 1), fused_frac=round(gbs / HBM_PEAK_GBS, 4),
+                halo_escapes_per_push=w["halo_escapes_per_push"], diagnostics=w["diagnostics"])
+
+
+def measure(name, args, want_cpu):
+    """Every number of one configuration: FP32 and FP64 paths, roofline, CPU baseline."""
+    import gc
+    from paper_2607_13507_amd import lpic as L
+    wls, desc, ndim, ppc_tot = build_workload(name)
+    tune = not args.no_autotune
+    inter = name == "laser_slab" and not args.no_interaction
+    print(f"[bench] {name}: FP32", file=sys.stderr, flush=True)
+    r32 = run_gpu(name, wls, ndim, L.F32_CELLOFS, args, args.steps, args.warmup, tune, inter)
+    r64 = None
+    if not args.no_fp64:
+        print(f"[bench] {name}: FP64", file=sys.stderr, flush=True)
+        s64 = max(5, args.steps // 5)
+        r64 = run_gpu(name, wls, ndim, L.F64_ABS, args, s64, max(2, args.warmup // 5), tune,
+                      inter)
+    windows = ["start"] + (["interaction"] if inter else [])
+    entries = {}
+    for key in windows:
+        w = r32[key]
+        e = dict(workload=desc + (f"; timed from step {INTERACTION_STEP}, the pulse inside the "
+                                  "slab" if key == "interaction" else ""),
+                 value=round(w["pushes_per_s"], 1), unit="particle-pushes/s",
+                 ms_per_step=round(w["ms_per_step"], 4), particles=w["alive"], runs=len(wls),
+                 last_timed_step=w["step_at_end"] - 1,
+                 roofline=roofline_of(name, ndim, wls, ppc_tot, r32, key),
+                 fused_pushes_per_s=round(w["alive"] / (w["fused_ms"] * 1e-3), 1),
+                 eager_mode=dict(ms_per_step=round(w["eager_ms_per_step"], 4),
+                                 pushes_per_s=round(w["eager_pushes_per_s"], 1)),
+                 halo_escapes_per_push=w["halo_escapes_per_push"],
+                 options=r32["options"], diagnostics_fp32=w["diagnostics"])
+        if r64:
+            e["fp64"] = fp64_entry(ndim, wls, ppc_tot, r64, key)
+            e["fp32_over_fp64"] = round(w["pushes_per_s"] / r64[key]["pushes_per_s"], 3)
+        entries[key] = e
+    head = entries["start"]
+    if r32["tuned"]:
+        head["autotuned"] = dict(r32["tuned"], trials=len(r32["tune_trials"]))
+    if r64 and r64["tuned"]:
+        head["autotuned_fp64"] = dict(r64["tuned"], trials=len(r64["tune_trials"]))
+    gc.collect()
+    return wls, entries, want_cpu
 
 
 def main():
@@ -292,27 +457,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--nx", type=int, default=2048)
-    ap.add_argument("--ny", type=int, default=1024)
-    ap.add_argument("--ppc", type=int, default=32)
-    ap.add_argument("--workload", default="laser_slab",
-                    choices=("laser_slab", "thermal_3d", "wakefield", "ensemble"),
-                    help="laser_slab (default, the headline configuration); the others are "
-                         "extra measurements")
-    ap.add_argument("--pml", type=int, default=16, metavar="CELLS",
-                    help="laser_slab: graded PML layers of CELLS cells at the open x ends, "
-                         "the antenna 4 cells inside the left one (0: first-order Mur ends, "
-                         "the antenna 4 cells from the left end)")
-    ap.add_argument("--tile", type=int, default=None)
-    ap.add_argument("--tile-z", type=int, default=None)
+    ap.add_argument("--workload", default=None, choices=WORKLOADS,
+                    help="measure one configuration only (it becomes the headline); default: "
+                         "the ensemble as headline and the others as extra keys")
+    ap.add_argument("--extra", default="laser_slab,thermal_3d,wakefield",
+                    help="comma-separated configurations measured beside the headline")
+    ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="T",
+                    help="start (or, with --no-autotune, fixed) tile edges x y [z]")
     ap.add_argument("--halo", type=int, default=None)
-    ap.add_argument("--chunk", type=int, default=2048)
+    ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--sort-interval", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true",
-                    help="use the fixed tile / halo / chunk / sort interval instead of the "
-                         "autotuner's pick")
+                    help="use the start / given options instead of the autotuner's pick")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-interaction", action="store_true",
+                    help="laser_slab: skip the window timed from step 1200")
     ap.add_argument("--no-graph", action="store_true",
                     help="eager launches only (profiler passes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -329,99 +489,56 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    wl, desc, ndim, ppc_tot = build_workload(args)
-    if args.tile is None:
-        args.tile = 16 if ndim == 2 else 8
-    if args.tile_z is None:
-        args.tile_z = 1 if ndim == 2 else 4
-    if args.halo is None:
-        args.halo = 5 if ndim == 2 else 4
-    if args.sort_interval is None:
-        args.sort_interval = 20   # the sort interval the 3D thermal configuration fixes
-    nparticles = sum(w.nparticles for w in wl)
-    tune = not args.no_autotune
-    f32 = run_gpu(wl, L.F32_CELLOFS, args, args.steps, args.warmup, tune)
-    f64 = None
-    if not args.no_fp64:
-        s64 = max(5, args.steps // 5)
-        f64 = run_gpu(wl, L.F64_ABS, args, s64, max(2, args.warmup // 5), tune)
+    head_name = args.workload or "ensemble"
+    extras = [] if args.workload else [e for e in args.extra.split(",") if e]
+    copy_gbs = copy_bandwidth()
+    results, pending_cpu = {}, []
+    for name in [head_name] + extras:
+        wls, entries, _ = measure(name, args, not args.no_cpu_baseline)
+        results[name] = entries
+        if not args.no_cpu_baseline:
+            pending_cpu.append((name, wls))   # oracle timings after all GPU work
+        else:
+            del wls
+    for name, wls in pending_cpu:
+        print(f"[bench] {name}: CPU baseline (oracle)", file=sys.stderr, flush=True)
+        results[name]["start"]["cpu_baseline"] = cpu_baseline(name, wls)
+    pending_cpu.clear()
 
-    slots = nparticles
-    nparticles = f32["alive"]   # alive macro-particles per timed step (dead slots excluded)
-
-    def launch_bytes_of(f32_path):
-        # particle state in and out once per particle; E, B in and J out once per occupied cell
-        return sum(algorithmic_bytes_per_push(ndim, f32_path, p) * w.nparticles
-                   for w, p in zip(wl, ppc_tot)) * nparticles / slots
-    launch_bytes = launch_bytes_of(True)
-    bpp = launch_bytes / nparticles
-    achieved = launch_bytes / (f32["fused_ms"] * 1e-3) / 1e9
-    traffic = read_traffic() if args.workload == "laser_slab" else None
-    valu = read_traffic("valu_insts_per_launch") if args.workload == "laser_slab" else None
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=f"lpic::k_fused<float,{ndim}>", bytes_per_push=round(bpp, 3),
-                bytes_per_launch=int(launch_bytes), avg_launch_ms=round(f32["fused_ms"], 4),
-                launches=f32["fused_launches"], kernel_source_sha256=kernel_source_hash())
-    roof["copy_gbs"] = copy_bandwidth()   # measured, for context (not the peak)
-    if valu:
-        # the unit that binds this kernel: VALU issue.  A wave64 VALU instruction occupies a
-        # SIMD for 4 cycles; 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions/s
-        rate = valu / (f32["fused_ms"] * 1e-3)
-        roof["valu_issue"] = dict(insts_per_launch=int(valu), achieved=round(rate / 1e9, 1),
-                                  peak=614.4, unit="G wave-instructions/s",
-                                  frac=round(rate / 614.4e9, 4))
-    cpu = None
-    if not args.no_cpu_baseline and args.workload == "laser_slab":
-        cpu = cpu_baseline(wl[0])
-    # `value` is the simulation as it runs by default: K steps replayed from captured graphs
-    # (the eager pass before them records HIP events around every fused launch for the
-    # roofline, which costs launch time of its own); --no-graph reports the eager pass
-    graph = not args.no_graph
-    key = "_graph" if graph else ""
+    head = results[head_name]["start"]
+    head["roofline"]["copy_gbs"] = copy_gbs
     out = {
-        "metric": "particle-pushes/sec (gather+push+deposit) FP32 vs FP64, % HBM roofline",
-        "value": round(f32["pushes_per_s" + key], 1),
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "particle-pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(f32["ms_per_step" + key], 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc,
-                   "particles": nparticles, "runs": len(wl),
-                   "grid": [wl[0].nx, wl[0].ny] + ([wl[0].nz] if ndim == 3 else []),
-                   "sort_interval": f32["options"]["sort_interval"],
-                   "diag_interval": 10, "tiling": f32["options"]},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "fused_pushes_per_s": round(nparticles / (f32["fused_ms"] * 1e-3), 1),
-        "timed_mode": "graph replay" if graph else "eager",
-        "eager_mode": {"ms_per_step": round(f32["ms_per_step"], 4),
-                       "pushes_per_s": round(f32["pushes_per_s"], 1),
-                       "note": "the same K steps launched one by one, with HIP events around "
-                               "every fused launch (the source of avg_launch_ms)"},
-        "halo_escapes_per_push": f32["halo_escapes_per_push"],
-        "diagnostics_fp32": f32["diagnostics"],
+        "config": {"workload": head["workload"], "particles": head["particles"],
+                   "runs": head["runs"], "diag_interval": 10, "options": head["options"]},
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "timed_mode": "eager" if args.no_graph else "graph replay",
     }
-    if f64:
-        out["fp64"] = {"pushes_per_s": round(f64["pushes_per_s" + key], 1),
-                       "ms_per_step": round(f64["ms_per_step" + key], 4),
-                       "fused_avg_ms": round(f64["fused_ms"], 4),
-                       "fused_hbm_gbs": round(launch_bytes_of(False) /
-                                              (f64["fused_ms"] * 1e-3) / 1e9, 1),
-                       "eager_pushes_per_s": round(f64["pushes_per_s"], 1),
-                       "fp32_over_fp64": round(f32["pushes_per_s" + key] /
-                                               f64["pushes_per_s" + key], 3),
-                       "diagnostics": f64["diagnostics"]}
-    if f32["tuned"]:
-        out["autotuned"] = f32["tuned"]
-    if f32.get("window_cells"):
-        out["config"]["window_cells_moved"] = f32["window_cells"]
+    for k in ("fp64", "fp32_over_fp64", "fused_pushes_per_s", "eager_mode",
+              "halo_escapes_per_push", "diagnostics_fp32", "autotuned", "autotuned_fp64"):
+        if k in head:
+            out[k] = head[k]
+    extra = {}
+    for key, e in results[head_name].items():
+        if key != "start":
+            extra[f"{head_name}_{key}"] = e
+    for name in extras:
+        for key, e in results[name].items():
+            extra[name if key == "start" else f"{name}_{key}"] = e
+    if extra:
+        out["extra"] = extra
     if args.copy_calibration > 0:
         out["copy_calibration"] = copy_calibration(args.copy_calibration)
     print(json.dumps(out), flush=True)

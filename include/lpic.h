@@ -417,6 +417,41 @@ lpic_status lpic_window_info(lpic_sim *sim, int32_t r, int64_t *shifted, int64_t
 lpic_status lpic_autotune(lpic_sim *sim, const lpic_options *candidates, int32_t ncand,
                           int32_t steps_each, lpic_options *best);
 
+/* Search space of lpic_autotune_search.  Each pair of bounds is inclusive and equal bounds
+ * fix the parameter.  Tile edges and chunk sizes are powers of two (bounds are rounded to
+ * them); tile_*[2] is ignored in 2D. */
+#define LPIC_TUNE_MAX_TRIALS 64
+typedef struct {
+  int32_t tile_min[3], tile_max[3];
+  int32_t halo_min, halo_max;
+  int32_t chunk_min, chunk_max;
+  int32_t sort_min, sort_max;  /* sort interval in steps */
+  int32_t steps_each;          /* timed steps per trial, rounded up to whole periods */
+  int32_t max_trials;          /* at most this many timed trials (<= LPIC_TUNE_MAX_TRIALS;
+                                  0 = LPIC_TUNE_MAX_TRIALS) */
+} lpic_tune_space;
+
+/* What the search tried: options and time per step of every trial in order (infeasible
+ * ones, e.g. an LDS demand above the limit, have ms_per_step < 0), and the winner. */
+typedef struct {
+  int32_t ntrials;
+  int32_t best;                /* index of the winning trial */
+  lpic_options trial[LPIC_TUNE_MAX_TRIALS];
+  double ms_per_step[LPIC_TUNE_MAX_TRIALS];
+} lpic_tune_report;
+
+/* Autotuner (the options of the fused kernel and the sort): a coordinate search over the
+ * space, from the simulation's present options clamped into it.  For one parameter at a
+ * time (tile edge x, y, z, halo, chunk, sort interval) it times the neighbouring values
+ * (twice / half the size, or one more / one less halo cell) and keeps walking in a
+ * direction while the time per step falls; it passes over the parameters again until no
+ * move helps or the trial budget is spent.  Every trial runs as lpic_autotune's candidates
+ * do (untimed warm-up period, then the timed steps; the simulation really advances), and
+ * no option set is timed twice.  Leaves the simulation on the winner, written into *best
+ * when non-NULL; *report (optional) receives every trial. */
+lpic_status lpic_autotune_search(lpic_sim *sim, const lpic_tune_space *space,
+                                 lpic_options *best, lpic_tune_report *report);
+
 const char *lpic_last_error(void);
 const char *lpic_version(void);
 

@@ -1394,34 +1394,185 @@ lpic_status lpic_window_info(lpic_sim* s, int32_t r, int64_t* shifted, int64_t* 
   return LPIC_OK;
 }
 
-lpic_status lpic_autotune(lpic_sim* s, const lpic_options* cand, int32_t ncand,
-                          int32_t steps_each, lpic_options* best) {
-  if (!s || !cand || ncand < 1 || steps_each < 1) return fail(LPIC_EINVAL, "bad autotune arguments");
+}  // extern "C"
+
+namespace {
+
+// One autotuner trial: the options set (false: infeasible), an untimed warm-up of whole
+// periods of its sort and diagnostics intervals (sorts, graph captures), then as many steps
+// timed with events on the simulation's stream.
+lpic_status time_trial(lpic_sim* s, const lpic_options& o, int32_t steps_each, bool* feasible,
+                       double* ms_per_step) {
+  *feasible = false;
+  if (lpic_set_options(s, &o) != LPIC_OK) return LPIC_OK;
+  *feasible = true;
+  const int k = std::max(1, o.sort_interval), d = std::max(1, o.diag_interval);
+  const int period = k / std::gcd(k, d) * d;
+  const int n = (std::max(1, steps_each) + period - 1) / period * period;
   hipEvent_t a, b;
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
+  lpic_status st = lpic_step(s, n);
+  if (st == LPIC_OK && hipEventRecord(a, s->stream) != hipSuccess) st = fail(LPIC_EHIP, "event");
+  if (st == LPIC_OK) st = lpic_step(s, n);
+  if (st == LPIC_OK && (hipEventRecord(b, s->stream) != hipSuccess ||
+                        hipEventSynchronize(b) != hipSuccess))
+    st = fail(LPIC_EHIP, "event");
+  float ms = 0.f;
+  if (st == LPIC_OK && hipEventElapsedTime(&ms, a, b) != hipSuccess) st = fail(LPIC_EHIP, "event");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms_per_step = (double)ms / n;
+  return st;
+}
+
+int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p *= 2;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpic_status lpic_autotune(lpic_sim* s, const lpic_options* cand, int32_t ncand,
+                          int32_t steps_each, lpic_options* best) {
+  if (!s || !cand || ncand < 1 || steps_each < 1) return fail(LPIC_EINVAL, "bad autotune arguments");
   double best_ms = 1e300;
   int best_i = -1;
   for (int i = 0; i < ncand; ++i) {
-    if (lpic_set_options(s, &cand[i]) != LPIC_OK) continue;   // skip infeasible candidates
-    // whole periods of the candidate's sort and diagnostics
-    const int k = std::max(1, cand[i].sort_interval), d = std::max(1, cand[i].diag_interval);
-    const int period = k / std::gcd(k, d) * d;
-    const int n = (steps_each + period - 1) / period * period;
-    CHK(lpic_step(s, n));   // warm-up: sorts, graph captures
-    HIPCHK(hipEventRecord(a, s->stream));
-    CHK(lpic_step(s, n));
-    HIPCHK(hipEventRecord(b, s->stream));
-    HIPCHK(hipEventSynchronize(b));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, a, b));
-    if (ms / n < best_ms) { best_ms = ms / n; best_i = i; }
+    bool ok = false;
+    double ms = 0.0;
+    CHK(time_trial(s, cand[i], steps_each, &ok, &ms));
+    if (ok && ms < best_ms) { best_ms = ms; best_i = i; }
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   if (best_i < 0) return fail(LPIC_EINVAL, "no feasible candidate");
   CHK(lpic_set_options(s, &cand[best_i]));
   if (best) *best = cand[best_i];
+  return LPIC_OK;
+}
+
+lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_options* best,
+                                 lpic_tune_report* report) {
+  if (!s || !sp) return fail(LPIC_EINVAL, "sim or search space is NULL");
+  if (sp->steps_each < 1) return fail(LPIC_EINVAL, "steps_each must be >= 1");
+  const int nd = s->ndim;
+  // parameter p: 0..2 tile edges, 3 halo, 4 chunk, 5 sort interval; lo/hi per parameter
+  int lo[6], hi[6];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = pow2_ceil(std::max(1, sp->tile_min[d]));
+    hi[d] = pow2_floor(std::max(1, sp->tile_max[d]));
+  }
+  if (nd != 3) lo[2] = hi[2] = 1;
+  lo[3] = std::max(3, sp->halo_min);
+  hi[3] = sp->halo_max;
+  lo[4] = pow2_ceil(std::max(1, sp->chunk_min));
+  hi[4] = pow2_floor(std::max(1, sp->chunk_max));
+  lo[5] = std::max(1, sp->sort_min);
+  hi[5] = sp->sort_max;
+  for (int p = 0; p < 6; ++p)
+    if (lo[p] > hi[p]) return fail(LPIC_EINVAL, "empty search range for parameter %d", p);
+  const int budget = std::min(LPIC_TUNE_MAX_TRIALS,
+                              sp->max_trials > 0 ? sp->max_trials : LPIC_TUNE_MAX_TRIALS);
+  const lpic_options base = s->opt;
+  auto get = [&](const lpic_options& o, int p) {
+    switch (p) {
+      case 0: return o.tiling.tx;
+      case 1: return o.tiling.ty;
+      case 2: return o.tiling.tz;
+      case 3: return o.tiling.halo;
+      case 4: return o.tiling.chunk;
+      default: return o.sort_interval;
+    }
+  };
+  auto put = [&](lpic_options& o, int p, int v) {
+    switch (p) {
+      case 0: o.tiling.tx = v; break;
+      case 1: o.tiling.ty = v; break;
+      case 2: o.tiling.tz = v; break;
+      case 3: o.tiling.halo = v; break;
+      case 4: o.tiling.chunk = v; break;
+      default: o.sort_interval = v; break;
+    }
+  };
+  // the starting point: the present options clamped into the space
+  lpic_options cur = base;
+  if (nd != 3) cur.tiling.tz = 1;
+  for (int p = 0; p < 6; ++p) {
+    int v = get(cur, p);
+    if (p <= 2 || p == 4) v = pow2_floor(std::max(1, v));
+    put(cur, p, std::min(hi[p], std::max(lo[p], v)));
+  }
+  std::vector<lpic_options> tried;
+  std::vector<double> times;
+  auto same = [](const lpic_options& a, const lpic_options& b) {
+    return a.tiling.tx == b.tiling.tx && a.tiling.ty == b.tiling.ty &&
+           a.tiling.tz == b.tiling.tz && a.tiling.halo == b.tiling.halo &&
+           a.tiling.chunk == b.tiling.chunk && a.sort_interval == b.sort_interval;
+  };
+  // time of an option set (cached); < 0 infeasible; budget exhausted: +inf, not recorded
+  auto trial = [&](const lpic_options& o, double* ms) -> lpic_status {
+    for (size_t i = 0; i < tried.size(); ++i)
+      if (same(tried[i], o)) { *ms = times[i]; return LPIC_OK; }
+    if ((int)tried.size() >= budget) { *ms = 1e300; return LPIC_OK; }
+    bool ok = false;
+    double t = 0.0;
+    CHK(time_trial(s, o, sp->steps_each, &ok, &t));
+    tried.push_back(o);
+    times.push_back(ok ? t : -1.0);
+    *ms = ok ? t : -1.0;
+    return LPIC_OK;
+  };
+  auto better = [](double a, double b) { return a >= 0.0 && (b < 0.0 || a < b); };
+  double cur_ms = 0.0;
+  CHK(trial(cur, &cur_ms));
+  bool moved = true;
+  while (moved && (int)tried.size() < budget) {
+    moved = false;
+    for (int p = 0; p < 6; ++p) {
+      if (lo[p] == hi[p]) continue;
+      for (int dir = +1; dir >= -1; dir -= 2) {
+        for (;;) {
+          const int v = get(cur, p);
+          // halo: one cell more or less; sizes and the sort interval: twice or half
+          const int nv = p == 3 ? v + dir : (dir > 0 ? v * 2 : v / 2);
+          if (nv < lo[p] || nv > hi[p] || nv == v) break;
+          lpic_options o = cur;
+          put(o, p, nv);
+          double ms = 0.0;
+          CHK(trial(o, &ms));
+          if (!better(ms, cur_ms) || ms >= 1e299) break;
+          cur = o;
+          cur_ms = ms;
+          moved = true;
+        }
+      }
+    }
+  }
+  int bi = -1;
+  for (size_t i = 0; i < tried.size(); ++i)
+    if (times[i] >= 0.0 && (bi < 0 || times[i] < times[bi])) bi = (int)i;
+  if (bi < 0) {
+    (void)lpic_set_options(s, &base);
+    return fail(LPIC_EINVAL, "no feasible option set in the search space");
+  }
+  CHK(lpic_set_options(s, &tried[bi]));
+  if (best) *best = tried[bi];
+  if (report) {
+    memset(report, 0, sizeof(*report));
+    report->ntrials = (int32_t)tried.size();
+    report->best = bi;
+    for (size_t i = 0; i < tried.size(); ++i) {
+      report->trial[i] = tried[i];
+      report->ms_per_step[i] = times[i];
+    }
+  }
   return LPIC_OK;
 }
 

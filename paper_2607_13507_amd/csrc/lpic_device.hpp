@@ -225,9 +225,12 @@ struct GlobalAcc {
   __device__ __forceinline__ int yo(int y) const { return wrapi(y, ny) * nx; }
   __device__ __forceinline__ int zo(int z) const { return wrapi(z, nz) * nx * ny; }
   __device__ __forceinline__ R get(int comp, int off) const { return f[comp][off]; }
+  // current values arrive unscaled; exact zeros are skipped (a global atomic each)
+  __device__ __forceinline__ R fold() const { return R(1); }
   __device__ __forceinline__ void add(int comp, int off, R v) const {
     if (v != R(0)) atomic_add_global(f[comp] + off, v);
   }
+  __device__ __forceinline__ void add_core(int comp, int off, R v) const { add(comp, off, v); }
 };
 
 // Strides of the staged region (tile + halo).  Fixed strides are compile-time constants, so
@@ -247,11 +250,9 @@ struct DynStrides {
   __device__ __forceinline__ int plane() const { return plane_; }
 };
 
-// On-chip tile: the six field planes in the kernel's precision, and the current (and
-// charge) planes accumulated in FP64 whatever that precision: FP64 LDS atomic adds run at
-// full rate on gfx950, FP32 ones do not, and FP64 sums also keep the per-tile totals exact to
-// FP32 before the flush.
-// LDS accessor of a staged region.  PAIR (2D): components that share a staggering are
+// LDS accessor of a staged region: the six field planes in the kernel's precision, and the
+// current (and charge) planes: signed 64-bit fixed point on the FP32 path (see add()), FP64
+// on the FP64 path.  PAIR (2D): components that share a staggering are
 // interleaved so that one 8-byte (FP32) / 16-byte (FP64) read fetches both at a node:
 // planes [ (Ex,By) pairs | (Ey,Bx) pairs | Ez | Bz ]; otherwise planes Ex Ey Ez Bx By Bz.
 template <typename R, class S, bool PAIR = false>
@@ -260,7 +261,7 @@ struct LdsAcc {
   R* fbase;       // the six field components, laid out as above
   double* jbase;  // planes Jx Jy Jz, then rho0 rho1 (FP32 path: int64 fixed point)
   S st;
-  double jscale;  // FP32 path: 2^S, the fixed-point scale of the current accumulators
+  float jfold;    // FP32 path: 2^S, the fixed-point scale of the current accumulators
   __device__ __forceinline__ int xo(int x) const { return x; }
   __device__ __forceinline__ int yo(int y) const { return y * st.sy(); }
   __device__ __forceinline__ int zo(int z) const { return z * st.sz(); }
@@ -275,25 +276,40 @@ struct LdsAcc {
   __device__ __forceinline__ R get1(int plane_idx, int off) const {
     return fbase[plane_idx * st.plane() + off];
   }
-  // Exact zeros are skipped: a particle that keeps its nearest node leaves a zero row and
-  // column in its window, and a lane masked off costs the LDS nothing.
-  // FP32 path: the accumulators are signed 64-bit fixed point with 2^-S resolution
-  // (integer LDS atomics run about twice as fast as FP64 ones on gfx950, and integer sums
-  // do not depend on the order of the adds).  v 2^S is rounded to the nearest integer by
-  // adding 1.5 2^52 in FP64, whose low mantissa bits then hold it; |v| 2^S < 2^51 is
-  // guaranteed by the choice of S (fixed_shift).
-  __device__ __forceinline__ void add(int comp, int off, R v) const {
-    if (v == R(0)) return;
+  __device__ __forceinline__ const R2* pair_ptr(int pair, int off) const {
+    return (const R2*)(fbase + 2 * (pair * st.plane() + off));
+  }
+  __device__ __forceinline__ const R* plane_ptr(int plane_idx, int off) const {
+    return fbase + plane_idx * st.plane() + off;
+  }
+  // The factor the deposit folds into its per-particle current constants, so that every
+  // value reaching add() is already in accumulator units.  FP32 path: the accumulators are
+  // signed 64-bit fixed point with 2^-S resolution (integer LDS atomics run about twice as
+  // fast as FP64 ones on gfx950 and their sums do not depend on the order of the adds; FP32
+  // LDS atomics take a slow path there), and the scale 2^S is chosen per run (fixed_shift)
+  // so that every single contribution stays below 2^29 in these units: it rounds to a
+  // 32-bit integer (half-up) that is sign-extended into the 64-bit add, and no sum of a
+  // run's contributions can overflow.
+  __device__ __forceinline__ R fold() const {
+    if constexpr (sizeof(R) == 4) return jfold;
+    else return R(1);
+  }
+  __device__ __forceinline__ void add_core(int comp, int off, R v) const {
     double* p = jbase + (comp - F_JX) * st.plane() + off;
     if constexpr (sizeof(R) == 4) {
-      const double y = __builtin_fma((double)v, jscale, 0x1.8p52);
-      const unsigned long long k =
-          (unsigned long long)__double_as_longlong(y) - 0x4338000000000000ull;
-      __hip_atomic_fetch_add((unsigned long long*)p, k, __ATOMIC_RELAXED,
+      int k;
+      asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(k) : "v"(v));
+      __hip_atomic_fetch_add((long long*)p, (long long)k, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
       atomic_add_lds(p, (double)v);
     }
+  }
+  // Entries that are exactly zero for most particles (the window's last node, which only a
+  // path that changes its nearest node reaches) skip the add: a lane masked off costs the
+  // LDS nothing.  The other entries (add_core) are added unconditionally.
+  __device__ __forceinline__ void add(int comp, int off, R v) const {
+    if (v != R(0)) add_core(comp, off, v);
   }
 };
 
@@ -384,18 +400,63 @@ __device__ __forceinline__ void stencil_axis(const Acc& A, int axis, int c, R o,
   }
 }
 
+// 2D gather from the paired LDS layout: one base address per staggering, every node of
+// the (ORDER+1)^2 stencil a compile-time offset from it (an immediate of the LDS read when
+// the region's strides are fixed).
+template <int ORDER, typename R, class Acc>
+__device__ __forceinline__ void gather2_paired(const Acc& A, const int* c, const R* o, R E[3],
+                                               R B[3]) {
+  constexpr int N = ORDER + 1;
+  int bix, bhx, biy, bhy;
+  R wxi[N], wxh[N], wyi[N], wyh[N];
+  weights_int<ORDER>(o[0], c[0], bix, wxi);
+  weights_half<ORDER>(o[0], c[0], bhx, wxh);
+  weights_int<ORDER>(o[1], c[1], biy, wyi);
+  weights_half<ORDER>(o[1], c[1], bhy, wyh);
+  const int sy = A.st.sy();
+  const auto* p0 = A.pair_ptr(0, biy * sy + bhx);   // (h,i): Ex, By
+  const auto* p1 = A.pair_ptr(1, bhy * sy + bix);   // (i,h): Ey, Bx
+  const R* pz = A.plane_ptr(4, biy * sy + bix);     // (i,i): Ez
+  const R* pb = A.plane_ptr(5, bhy * sy + bhx);     // (h,h): Bz
+  R ex = R(0), by = R(0), ey = R(0), bx = R(0), ez = R(0), bz = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    R r0 = R(0), r1 = R(0), r2 = R(0), r3 = R(0), r4 = R(0), r5 = R(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const int off = b * sy + a;
+      const auto v0 = p0[off];
+      const auto v1 = p1[off];
+      r0 += wxh[a] * v0.x;
+      r1 += wxh[a] * v0.y;
+      r2 += wxi[a] * v1.x;
+      r3 += wxi[a] * v1.y;
+      r4 += wxi[a] * pz[off];
+      r5 += wxh[a] * pb[off];
+    }
+    ex += wyi[b] * r0;
+    by += wyi[b] * r1;
+    ey += wyh[b] * r2;
+    bx += wyh[b] * r3;
+    ez += wyi[b] * r4;
+    bz += wyh[b] * r5;
+  }
+  E[0] = ex; E[1] = ey; E[2] = ez;
+  B[0] = bx; B[1] = by; B[2] = bz;
+}
+
 template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void gather(const Acc& A, const int* c, const R* o, R E[3], R B[3]) {
+  if constexpr (DIM == 2 && Acc::kPaired) {
+    gather2_paired<ORDER>(A, c, o, E, B);
+    return;
+  }
   constexpr int N = ORDER + 1;
   int xi[N], xh[N], yi[N], yh[N];
   R wxi[N], wxh[N], wyi[N], wyh[N];
   stencil_axis<ORDER>(A, 0, c[0], o[0], xi, wxi, xh, wxh);
   stencil_axis<ORDER>(A, 1, c[1], o[1], yi, wyi, yh, wyh);
   if constexpr (DIM == 2 && Acc::kPaired) {
-    interp2_pair<N>(A, 0, xh, wxh, yi, wyi, E[0], B[1]);   // (h,i): Ex, By
-    interp2_pair<N>(A, 1, xi, wxi, yh, wyh, E[1], B[0]);   // (i,h): Ey, Bx
-    E[2] = interp2_single<N>(A, 4, xi, wxi, yi, wyi);
-    B[2] = interp2_single<N>(A, 5, xh, wxh, yh, wyh);
   } else if constexpr (DIM == 2) {
     E[0] = interp2<N>(A, F_EX, xh, wxh, yi, wyi);
     E[1] = interp2<N>(A, F_EY, xi, wxi, yh, wyh);
@@ -509,6 +570,10 @@ __device__ __forceinline__ PushConst<R> push_const(const RunDesc& r, const SegDe
 //   2D: Wx = dSx (S0y + S1y)/2 summed along x, Wy likewise, and
 //       Wz = (S0x (2 S0y + S1y) + S1x (S0y + 2 S1y)) / 6   (= S0 S0 + dS S0/2 + S0 dS/2 + dS dS/3)
 //   3D: Wx = dSx (S0y (2 S0z + S1z) + S1y (S0z + 2 S1z)) / 6 summed along x, cyclic.
+// The accessor's scale (A.fold()) is folded into the per-particle factors.  Entries on the
+// first W-1 nodes of every axis (and, along a running sum, before its last node) are the
+// ones a path that keeps its nearest node fills: they go through add_core; the others are
+// exactly zero for such a path and go through add, which skips zeros.
 template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0, const R* x1,
                                         R w, R vz_bar, const PushConst<R>& k, bool with_rho) {
@@ -530,9 +595,13 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   int xo[W], yo[W];
 #pragma unroll
   for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
-  const R cx = k.jx * w, cy = k.jy * w;
+  const R fw = A.fold() * w;
+  const R cx = k.jx * fw, cy = k.jy * fw;
+  R dSx[W], dSy[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) { dSx[a] = S1x[a] - S0x[a]; dSy[a] = S1y[a] - S0y[a]; }
   if constexpr (DIM == 2) {
-    const R cz = k.q * w * vz_bar * R(1.0 / 6.0);
+    const R cz = k.q * fw * vz_bar * R(1.0 / 6.0);
 #pragma unroll
     for (int b = 0; b < W; ++b) {
       if (b == W - 1 && !ly) continue;
@@ -540,8 +609,9 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
       R acc = R(0);
 #pragma unroll
       for (int a = 0; a < W - 1; ++a) {
-        acc += (S1x[a] - S0x[a]) * hy;
-        A.add(F_JX, yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
+        acc += dSx[a] * hy;
+        if (b < W - 1 && a < W - 2) A.add_core(F_JX, yo[b] + xo[a], acc);
+        else A.add(F_JX, yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
       }
     }
 #pragma unroll
@@ -551,10 +621,14 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
       R acc = R(0);
 #pragma unroll
       for (int b = 0; b < W - 1; ++b) {
-        acc += (S1y[b] - S0y[b]) * hx;
-        A.add(F_JY, yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
+        acc += dSy[b] * hx;
+        if (a < W - 1 && b < W - 2) A.add_core(F_JY, yo[b] + xo[a], acc);
+        else A.add(F_JY, yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
       }
     }
+    R p0[W], p1[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) { p0[a] = cz * S0x[a]; p1[a] = cz * S1x[a]; }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
       if (b == W - 1 && !ly) continue;
@@ -562,11 +636,13 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
       for (int a = 0; a < W; ++a) {
         if (a == W - 1 && !lx) continue;
-        A.add(F_JZ, yo[b] + xo[a], cz * (S0x[a] * ay + S1x[a] * by2));
+        const R v = p0[a] * ay + p1[a] * by2;
+        if (a < W - 1 && b < W - 1) A.add_core(F_JZ, yo[b] + xo[a], v);
+        else A.add(F_JZ, yo[b] + xo[a], v);
       }
     }
     if (with_rho) {
-      const R qw = k.q * w;
+      const R qw = k.q * fw;
 #pragma unroll
       for (int b = 0; b < W; ++b)
 #pragma unroll
@@ -583,9 +659,10 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     const bool lz = __ballot(S0z[W - 1] != R(0) || S1z[W - 1] != R(0)) != 0;
     const bool zs = S0z[W - 1] == R(0) && S1z[W - 1] == R(0);
     int zo[W];
+    R dSz[W];
 #pragma unroll
-    for (int a = 0; a < W; ++a) zo[a] = A.zo(c[2] + bz + a);
-    const R cz = k.jz * w;
+    for (int a = 0; a < W; ++a) { zo[a] = A.zo(c[2] + bz + a); dSz[a] = S1z[a] - S0z[a]; }
+    const R cz = k.jz * fw;
     const R sixth = R(1.0 / 6.0);
     // Jx: running sum along x of dSx * Ryz
 #pragma unroll
@@ -598,8 +675,9 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         R acc = R(0);
 #pragma unroll
         for (int a = 0; a < W - 1; ++a) {
-          acc += (S1x[a] - S0x[a]) * ryz;
-          A.add(F_JX, zo[cc] + yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
+          acc += dSx[a] * ryz;
+          if (b < W - 1 && cc < W - 1 && a < W - 2) A.add_core(F_JX, zo[cc] + yo[b] + xo[a], acc);
+          else A.add(F_JX, zo[cc] + yo[b] + xo[a], a == W - 2 && xs ? R(0) : acc);
         }
       }
 #pragma unroll
@@ -612,8 +690,9 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         R acc = R(0);
 #pragma unroll
         for (int b = 0; b < W - 1; ++b) {
-          acc += (S1y[b] - S0y[b]) * rxz;
-          A.add(F_JY, zo[cc] + yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
+          acc += dSy[b] * rxz;
+          if (a < W - 1 && cc < W - 1 && b < W - 2) A.add_core(F_JY, zo[cc] + yo[b] + xo[a], acc);
+          else A.add(F_JY, zo[cc] + yo[b] + xo[a], b == W - 2 && ys ? R(0) : acc);
         }
       }
 #pragma unroll
@@ -626,12 +705,13 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         R acc = R(0);
 #pragma unroll
         for (int cc = 0; cc < W - 1; ++cc) {
-          acc += (S1z[cc] - S0z[cc]) * rxy;
-          A.add(F_JZ, zo[cc] + yo[b] + xo[a], cc == W - 2 && zs ? R(0) : acc);
+          acc += dSz[cc] * rxy;
+          if (a < W - 1 && b < W - 1 && cc < W - 2) A.add_core(F_JZ, zo[cc] + yo[b] + xo[a], acc);
+          else A.add(F_JZ, zo[cc] + yo[b] + xo[a], cc == W - 2 && zs ? R(0) : acc);
         }
       }
     if (with_rho) {
-      const R qw = k.q * w;
+      const R qw = k.q * fw;
 #pragma unroll
       for (int cc = 0; cc < W; ++cc)
 #pragma unroll

@@ -266,11 +266,14 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
   }
   const int plane = st.plane();
   const int njplanes = 3 + (with_rho ? 2 : 0);
-  double* jm = (double*)(sm + 6 * plane + (plane & 1));   // 8-byte aligned after the fields
+  // the current planes follow the six field planes; 6 plane values of 4 or 8 bytes end on an
+  // 8-byte boundary, as the 64-bit LDS atomics need
+  double* jm = (double*)(sm + 6 * plane);
   LdsAcc<R, ST, DIM == 2> L;
   L.fbase = sm;
   L.jbase = jm;
   L.st = st;
+  L.jfold = 1.0f;
 
   int cur_run = -1, cur_tile = -1;
   Region g;
@@ -296,7 +299,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
       }
       if constexpr (sizeof(R) == 4) {
         const int sh = uniform(jshift[s.run]);
-        L.jscale = ldexp(1.0, sh);
+        L.jfold = ldexpf(1.0f, sh);
         unscale = ldexp(1.0, -sh);
       }
       const RunDesc rn = run_of(T, s.run);
@@ -461,10 +464,12 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
 
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
   const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
-  // six field planes in the kernel precision (padded to 8 bytes), then 8-byte current
-  // planes (and, on diagnostic steps, two charge planes)
+  // six field planes in the kernel precision (24 or 48 bytes per cell: the current planes
+  // after them start 8-byte aligned), then 8-byte current planes (and, on diagnostic steps,
+  // two charge planes)
   const int jplanes = 3 + (with_rho ? 2 : 0);
-  return (plane * 6 + (plane & 1)) * (prec == 0 ? 4 : 8) + plane * jplanes * 8;
+  static_assert((6 * sizeof(float)) % 8 == 0, "current planes must start 8-byte aligned");
+  return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8;
 }
 
 }  // namespace lpic

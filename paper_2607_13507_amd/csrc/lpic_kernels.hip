@@ -1179,8 +1179,10 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
 // Fixed-point scale of the FP32 current accumulators.  A deposit contribution is bounded
 // by |q w| max(1, h/dt) (the Esirkepov running sums and shape products are at most 1 and
 // |v| < c), so with cmax = 2 max|q w| max(1, h/dt) and n particles in a run:
-//   |v| 2^S < 2^50 for every contribution (exact FP64 rounding to an integer), and
+//   |v| 2^S < 2^29 for every contribution (it rounds to a 32-bit integer, sign-extended
+//   into the 64-bit accumulator), and
 //   |any accumulated sum| <= n cmax 2^S < 2^61 (no 64-bit overflow, whatever the order).
+// S stays within [-120, 120] so that 2^S is a normal FP32 number.
 // =======================================================================================
 constexpr int WMAX_SPAN = 4;    // sort-sized particle blocks per workgroup
 // Each segment's maximum is spread over WMAX_SLOTS words (workgroup b uses slot b mod
@@ -1258,8 +1260,8 @@ __global__ void k_fixed_shift(Tables T, int nruns, int nsegs, const unsigned lon
     int e1, e2;
     frexp(cmax, &e1);       // cmax < 2^e1
     frexp(n * cmax, &e2);   // n cmax < 2^e2
-    sh = min(50 - e1, 61 - e2);
-    sh = max(-900, min(900, sh));
+    sh = min(30 - e1, 61 - e2);
+    sh = max(-120, min(120, sh));
   }
   jshift[ri] = sh;
 }

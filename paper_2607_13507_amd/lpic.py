@@ -90,6 +90,23 @@ class Stats(ctypes.Structure):
                 ("field_tile", ctypes.c_int32 * 2)]
 
 
+TUNE_MAX_TRIALS = 64
+
+
+class TuneSpace(ctypes.Structure):
+    _fields_ = [("tile_min", ctypes.c_int32 * 3), ("tile_max", ctypes.c_int32 * 3),
+                ("halo_min", ctypes.c_int32), ("halo_max", ctypes.c_int32),
+                ("chunk_min", ctypes.c_int32), ("chunk_max", ctypes.c_int32),
+                ("sort_min", ctypes.c_int32), ("sort_max", ctypes.c_int32),
+                ("steps_each", ctypes.c_int32), ("max_trials", ctypes.c_int32)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("ntrials", ctypes.c_int32), ("best", ctypes.c_int32),
+                ("trial", Options * TUNE_MAX_TRIALS),
+                ("ms_per_step", ctypes.c_double * TUNE_MAX_TRIALS)]
+
+
 HOOK_FN = ctypes.CFUNCTYPE(ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int64, _vp)
 
 
@@ -156,6 +173,8 @@ EXPORTS = {
     "lpic_set_options": (ctypes.c_int, [_vp, ctypes.POINTER(Options)]),
     "lpic_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(Options)]),
+    "lpic_autotune_search": (ctypes.c_int, [_vp, ctypes.POINTER(TuneSpace),
+                                            ctypes.POINTER(Options), ctypes.POINTER(TuneReport)]),
 }
 
 _lib = None
@@ -364,3 +383,12 @@ def lpic_autotune(h, candidates, steps_each):
     _check("lpic_autotune", lib().lpic_autotune(h, arr, len(candidates), steps_each,
                                                 ctypes.byref(best)))
     return best
+
+
+def lpic_autotune_search(h, space):
+    best = Options()
+    rep = TuneReport()
+    _check("lpic_autotune_search", lib().lpic_autotune_search(h, ctypes.byref(space),
+                                                              ctypes.byref(best),
+                                                              ctypes.byref(rep)))
+    return best, rep

@@ -14,7 +14,8 @@ from paper_2607_13507_amd import lpic as L
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PAIRS = [("lpic_grid", L.Grid), ("lpic_laser", L.Laser), ("lpic_fields", L.Fields),
          ("lpic_species", L.Species), ("lpic_tiling", L.Tiling), ("lpic_options", L.Options),
-         ("lpic_stats", L.Stats), ("lpic_pml", L.Pml), ("lpic_plasma", L.Plasma)]
+         ("lpic_stats", L.Stats), ("lpic_pml", L.Pml), ("lpic_plasma", L.Plasma),
+         ("lpic_tune_space", L.TuneSpace), ("lpic_tune_report", L.TuneReport)]
 
 
 def _layout(tmp_path, header, pairs, include_dirs):

@@ -271,6 +271,35 @@ def test_autotune_picks_a_candidate_and_keeps_physics():
     sim.close()
 
 
+def test_autotune_search_stays_in_its_space_and_keeps_physics():
+    """lpic_autotune_search walks tile, halo, chunk and sort interval inside the given
+    bounds, times no option set twice, keeps the fastest, and the simulation it tuned goes
+    on taking exactly the oracle's steps."""
+    banner("autotune search")
+    wl = _wl(2)
+    sim = Simulation(wl, prec=L.F64_ABS, tiling=(16, 16, 1), halo=4, chunk=256,
+                     sort_interval=4, use_graph=True, diag_interval=2)
+    best, trials = sim.autotune_search(tile=((8, 8, 1), (16, 16, 1)), halo=(3, 5),
+                                       chunk=(64, 512), sort_interval=(2, 8), steps_each=4,
+                                       max_trials=12)
+    assert 2 <= len(trials) <= 12
+    keys = [(t["tiling"], t["halo"], t["chunk"], t["sort_interval"]) for t in trials]
+    assert len(set(keys)) == len(keys)
+    for t in trials:
+        assert t["tiling"][0] in (8, 16) and t["tiling"][1] in (8, 16)
+        assert 3 <= t["halo"] <= 5 and 64 <= t["chunk"] <= 512 and 2 <= t["sort_interval"] <= 8
+    fastest = min((t for t in trials if t["ms_per_step"] >= 0), key=lambda t: t["ms_per_step"])
+    assert (best["tiling"], best["halo"], best["chunk"], best["sort_interval"]) == (
+        fastest["tiling"], fastest["halo"], fastest["chunk"], fastest["sort_interval"])
+    n_done = sim.nstep
+    orc = OracleSim.from_workload(wl)
+    orc.step(n_done)
+    sim.step(2)
+    orc.step(2)
+    assert sim.diagnostics(0)["field_energy"] == pytest.approx(orc.field_energy(), rel=1e-10)
+    sim.close()
+
+
 @pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=["f64", "f32"])
 def test_small_thermal_configuration_100_steps_vs_oracle(prec):
     """The small thermal configuration as stated (64 x 64, dx = 0.05, 16 ppc, T = 0.01, CIC,
