@@ -205,6 +205,23 @@ lpic_status lpic_sort_tiles(const lpic_grid *grid, lpic_species *sp, lpic_specie
                             size_t ws_bytes, lpic_precision prec, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------
+ * lpic_sort_tiles for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same sort, argument
+ * for argument, except that the bin counts, cursors and placement multipliers live in a
+ * device array inside the library (3 x (LPIC_SORT_STATIC_MAX_TILES + 64) 32-bit words, about
+ * 3 MiB, held on every device the library runs on until the process ends) instead of a
+ * caller workspace.  It allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and enqueues only kernels.  At most LPIC_SORT_STATIC_MAX_TILES tiles: a larger
+ * tiling returns LPIC_EINVAL.  Every call on one device shares that array, so calls that
+ * overlap on one device (different streams, or host threads) race and must be serialised
+ * by the caller; consecutive calls on one stream are fine (each clears the counts first).
+ * ------------------------------------------------------------------------------------- */
+#define LPIC_SORT_STATIC_MAX_TILES 262144
+lpic_status lpic_sort_tiles_static(const lpic_grid *grid, lpic_species *sp, lpic_species *alt,
+                                   const lpic_tiling *tiling, int32_t *tile_offsets,
+                                   lpic_precision prec, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
  * Fused gather + push + deposit -- the unified pusher of Sec. 2.3 / Sec. 3.3: one pass
  * over the particles of a species that does everything lpic_gather_push and
  * lpic_deposit_esirkepov do, with the field tile staged on chip and the current of a tile

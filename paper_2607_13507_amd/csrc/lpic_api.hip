@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <cmath>
 #include <string>
@@ -418,6 +419,88 @@ lpic_status lpic_sort_tiles(const lpic_grid* grid, lpic_species* sp, lpic_specie
   } else {
     launch_zero_u32((uint32_t*)tile_offsets, nbins + 1, stream);
     return last_launch("sort clear");
+  }
+  void* a[P_NUM];
+  void* b[P_NUM];
+  species_ptrs(sp, prec, a);
+  species_ptrs(alt, prec, b);
+  set_species_ptrs(sp, prec, b);
+  set_species_ptrs(alt, prec, a);
+  return LPIC_OK;
+}
+
+}  // extern "C"
+
+// =======================================================================================
+// Tile sort without allocation: the bin counts, cursors and placement multipliers live in a
+// file-scope device array instead of a caller workspace.
+// =======================================================================================
+namespace {
+
+constexpr size_t STATIC_SORT_ARRAY = (size_t)LPIC_SORT_STATIC_MAX_TILES + 64;   // words
+__device__ __align__(256) int32_t scratch[3 * STATIC_SORT_ARRAY];
+
+// Device address of `scratch` on each device, looked up once per device with that device
+// current (in host code the symbol's name is only a stand-in for it).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[MAX_DEVICES] = {};
+
+lpic_status static_scratch(int32_t** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES)
+    return fail(LPIC_EUNSUPPORTED, "device %d beyond the %d the library tracks", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LPIC_EHIP, "no device address for the sort scratch array");
+    g_scratch_ptr[dev] = (int32_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpic_status lpic_sort_tiles_static(const lpic_grid* grid, lpic_species* sp, lpic_species* alt,
+                                   const lpic_tiling* tiling, int32_t* tile_offsets,
+                                   lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_species(sp, grid->ndim, prec));
+  CHK(check_species(alt, grid->ndim, prec));
+  CHK(check_tiling(tiling, grid, prec, false));
+  if (alt->n != sp->n) return fail(LPIC_EINVAL, "alt must have as many slots as sp");
+  if (!tile_offsets) return fail(LPIC_EINVAL, "tile_offsets is NULL");
+  const int64_t nt = lpic_num_tiles(grid, tiling);
+  if (nt < 1 || nt > LPIC_SORT_STATIC_MAX_TILES)
+    return fail(LPIC_EINVAL, "%lld tiles: lpic_sort_tiles_static handles at most %d",
+                (long long)nt, LPIC_SORT_STATIC_MAX_TILES);
+  int32_t* base = nullptr;
+  CHK(static_scratch(&base));
+  lpic_tiling t = *tiling;
+  if (grid->ndim != 3) t.tz = 1;
+  RunDesc r = make_run(grid, nullptr, &t);
+  const int nbins = r.ntiles + 1;
+  int32_t* counts = base;
+  int32_t* cursor = base + STATIC_SORT_ARRAY;
+  int32_t* mult = base + 2 * STATIC_SORT_ARRAY;
+  if (sp->n > 0) {
+    SegDesc s = make_seg(sp, alt, 0, &t, 0, 0, prec);
+    Tables T = single_tables(r, &s);
+    // the array keeps whatever the last call left: the counts start from zero (a fill
+    // kernel, no memset node)
+    launch_zero_u32((uint32_t*)counts, nbins, stream);
+    CHK(last_launch("static sort clear"));
+    launch_sort(T, prec, grid->ndim, (int)((sp->n + SORT_BLOCK - 1) / SORT_BLOCK), counts,
+                tile_offsets, cursor, mult, nbins, (t.flags & LPIC_SORT_SPREAD) ? 1 : 0, stream);
+    CHK(last_launch("static sort"));
+  } else {
+    launch_zero_u32((uint32_t*)tile_offsets, nbins + 1, stream);
+    return last_launch("static sort clear");
   }
   void* a[P_NUM];
   void* b[P_NUM];

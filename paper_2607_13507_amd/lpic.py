@@ -136,6 +136,9 @@ EXPORTS = {
     "lpic_sort_tiles": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Species),
                                        ctypes.POINTER(Species), ctypes.POINTER(Tiling), _vp,
                                        _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "lpic_sort_tiles_static": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Species),
+                                              ctypes.POINTER(Species), ctypes.POINTER(Tiling),
+                                              _vp, ctypes.c_int, _vp]),
     "lpic_fused_ws_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.POINTER(Tiling),
                                               ctypes.c_int64]),
     "lpic_push_deposit_fused": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
@@ -260,6 +263,17 @@ def lpic_sort_tiles(grid, species, alt, tiling, tile_offsets, ws, ws_bytes, prec
                                                     ctypes.byref(alt), ctypes.byref(tiling),
                                                     tile_offsets, ws, ws_bytes, prec,
                                                     _stream(stream)))
+
+
+SORT_STATIC_MAX_TILES = 262144   # LPIC_SORT_STATIC_MAX_TILES
+
+
+def lpic_sort_tiles_static(grid, species, alt, tiling, tile_offsets, prec, stream=None):
+    """lpic_sort_tiles with the library's own static scratch (allocates nothing)."""
+    _check("lpic_sort_tiles_static",
+           lib().lpic_sort_tiles_static(ctypes.byref(grid), ctypes.byref(species),
+                                        ctypes.byref(alt), ctypes.byref(tiling), tile_offsets,
+                                        prec, _stream(stream)))
 
 
 def lpic_fused_ws_bytes(grid, tiling, n):
