@@ -126,18 +126,22 @@ def build_workload(name):
 
 
 def tune_space(name, ndim, f32):
-    """Search space of the autotuner (lpic_autotune_search) per workload."""
+    """Search space of the autotuner (lpic_autotune_search) per workload: tile edges, halo,
+    chunk, sort interval and the re-binned escape path (tried on and off)."""
     if ndim == 3:   # sort every 20 steps, as the 3D configuration states
         return dict(tile=((4, 4, 4), (8, 8, 8)), halo=(3, 5 if f32 else 4), chunk=(1024, 4096),
-                    sort_interval=(20, 20), steps_each=20, max_trials=10)
+                    sort_interval=(20, 20), rebin=2, steps_each=20, max_trials=10)
     return dict(tile=((8, 8, 1), (32, 32, 1)), halo=(3, 7), chunk=(512, 4096),
-                sort_interval=(10, 80), steps_each=40, max_trials=24 if f32 else 12)
+                sort_interval=(10, 80), rebin=2, steps_each=40, max_trials=24 if f32 else 12)
 
 
 def start_options(ndim, f32):
-    if ndim == 3:
-        return dict(tiling=(8, 4, 4), halo=4 if f32 else 3, chunk=2048, sort_interval=20)
-    return dict(tiling=(16, 16, 1), halo=5, chunk=1024, sort_interval=20)
+    """The autotuner's starting point (and the options of --no-autotune)."""
+    from paper_2607_13507_amd import lpic as L
+    if ndim == 3:   # at 20 steps per sort most 3D particles leave their tile's margin
+        return dict(tiling=(8, 4, 4), halo=4 if f32 else 3, chunk=2048, sort_interval=20,
+                    flags=L.ESCAPE_REBIN)
+    return dict(tiling=(16, 16, 1), halo=5, chunk=1024, sort_interval=20, flags=0)
 
 
 def alive(sim):
@@ -223,22 +227,24 @@ def run_gpu(name, wl, ndim, prec, args, steps, warmup, tune, interaction=False):
     for key in ("halo", "chunk", "sort_interval"):
         if getattr(args, key) is not None:
             opt[key] = getattr(args, key)
+    if args.rebin is not None:
+        opt["flags"] = L.ESCAPE_REBIN if args.rebin else 0
     tuned, trials = None, []
     if tune:
         # lpic_autotune_search advances the simulation it tunes, so it runs on a copy and
         # the measured run starts from the workload's initial state
         tsim = Simulation(wl, prec=prec, tiling=opt["tiling"], halo=opt["halo"],
                           chunk=opt["chunk"], sort_interval=opt["sort_interval"],
-                          diag_interval=10, use_graph=True)
+                          diag_interval=10, use_graph=True, flags=opt["flags"])
         tuned, trials = tsim.autotune_search(**tune_space(name, ndim, f32))
         tsim.close()
         del tsim
         torch.cuda.empty_cache()
         opt = dict(tiling=tuned["tiling"], halo=tuned["halo"], chunk=tuned["chunk"],
-                   sort_interval=tuned["sort_interval"])
+                   sort_interval=tuned["sort_interval"], flags=tuned["flags"])
     sim = Simulation(wl, prec=prec, tiling=opt["tiling"], halo=opt["halo"], chunk=opt["chunk"],
                      sort_interval=opt["sort_interval"], diag_interval=10,
-                     use_graph=not args.no_graph)
+                     use_graph=not args.no_graph, flags=opt["flags"])
     advance(sim, wl, warmup)
     # the timed steps start where a sort and a diagnostics step fall together, so that the
     # window holds at least its proportional share of both (whole periods: exactly)
@@ -252,7 +258,8 @@ def run_gpu(name, wl, ndim, prec, args, steps, warmup, tune, interaction=False):
         out["interaction"] = timed_window(sim, wl, steps, not args.no_graph)
     t = sim.options.tiling
     out["options"] = dict(tiling=[t.tx, t.ty, t.tz], halo=t.halo, chunk=t.chunk,
-                          sort_interval=sim.options.sort_interval)
+                          sort_interval=sim.options.sort_interval,
+                          escape_rebin=bool(t.flags & L.ESCAPE_REBIN))
     out["tuned"] = tuned
     out["tune_trials"] = trials
     sim.close()
@@ -467,6 +474,8 @@ def main():
     ap.add_argument("--halo", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--sort-interval", type=int, default=None)
+    ap.add_argument("--rebin", type=int, default=None, choices=(0, 1),
+                    help="start (or fixed) setting of the re-binned escape path")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the start / given options instead of the autotuner's pick")
     ap.add_argument("--no-cpu-baseline", action="store_true")

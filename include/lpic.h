@@ -112,7 +112,7 @@ typedef struct {
 
 /* Particle arrays of one species (Sec. 2.1, structure of arrays), n slots each. */
 typedef struct {
-  int64_t n;                 /* number of slots (alive + dead) */
+  int64_t n;                 /* number of slots (alive + dead), at most 2^29 */
   double q, m;               /* charge [e] and mass [m_e] */
   int32_t shape_order;       /* 1 = CIC (linear), 2 = quadratic spline */
   int32_t reserved0;
@@ -135,14 +135,21 @@ typedef struct {
  * between two particle pushes of consecutive steps (B by dt/2, E by dt, B by dt/2; Sec. 3.3,
  * Algorithm 1) as three grid-wide kernels; without it they run as one kernel over field
  * tiles of up to 64 x 16 cells whenever every box's nx and ny are multiples of a tile edge
- * (>= 8 and >= 4), which computes the same values with one pass over the arrays. */
+ * (>= 8 and >= 4), which computes the same values with one pass over the arrays.
+ * LPIC_ESCAPE_REBIN (lpic_step): when a step finds many particles (at least 4096) outside
+ * the on-chip margin of the tile they were sorted into, group them by the tile they are in
+ * now (a count, a scan and a scatter of their indices) and push them in a second pass of
+ * the fused kernel against the staged regions of those tiles, instead of through global
+ * memory; the sort itself still runs every sort_interval steps. */
 #define LPIC_SORT_SPREAD 1
 #define LPIC_FIELD_SEPARATE 2
+#define LPIC_ESCAPE_REBIN 4
 typedef struct {
   int32_t tx, ty, tz;        /* tz ignored in 2D */
   int32_t halo;
   int32_t chunk;
-  int32_t flags;             /* LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE; other bits must be 0 */
+  int32_t flags;             /* LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE | LPIC_ESCAPE_REBIN;
+                                other bits must be 0 */
 } lpic_tiling;
 
 /* ---------------------------------------------------------------------------------------
@@ -443,6 +450,7 @@ typedef struct {
   int32_t halo_min, halo_max;
   int32_t chunk_min, chunk_max;
   int32_t sort_min, sort_max;  /* sort interval in steps */
+  int32_t rebin;               /* LPIC_ESCAPE_REBIN: 0 off, 1 on, 2 both tried */
   int32_t steps_each;          /* timed steps per trial, rounded up to whole periods */
   int32_t max_trials;          /* at most this many timed trials (<= LPIC_TUNE_MAX_TRIALS;
                                   0 = LPIC_TUNE_MAX_TRIALS) */
@@ -459,8 +467,9 @@ typedef struct {
 
 /* Autotuner (the options of the fused kernel and the sort): a coordinate search over the
  * space, from the simulation's present options clamped into it.  For one parameter at a
- * time (tile edge x, y, z, halo, chunk, sort interval) it times the neighbouring values
- * (twice / half the size, or one more / one less halo cell) and keeps walking in a
+ * time (tile edge x, y, z, halo, chunk, sort interval, re-binned escape path) it times the
+ * neighbouring values (twice / half the size, one more / one less halo cell, the path on /
+ * off) and keeps walking in a
  * direction while the time per step falls; it passes over the parameters again until no
  * move helps or the trial budget is spent.  Every trial runs as lpic_autotune's candidates
  * do (untimed warm-up period, then the timed steps; the simulation really advances), and

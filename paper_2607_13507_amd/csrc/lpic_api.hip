@@ -102,7 +102,8 @@ lpic_status check_fields(const lpic_fields* f, bool need_rho) {
 lpic_status check_species(const lpic_species* s, int ndim, int prec) {
   if (!s) return fail(LPIC_EINVAL, "species is NULL");
   if (s->n < 0) return fail(LPIC_EINVAL, "negative particle count");
-  if (s->n >= ((int64_t)1 << 31) - 1) return fail(LPIC_EINVAL, "too many particles");
+  // (kernels address a particle array with a 32-bit byte offset: slot * 8 < 2^32)
+  if (s->n > ((int64_t)1 << 29)) return fail(LPIC_EINVAL, "a species holds at most 2^29 slots");
   if (s->shape_order != 1 && s->shape_order != 2)
     return fail(LPIC_EINVAL, "shape_order must be 1 or 2 (got %d)", s->shape_order);
   if (!(s->m > 0)) return fail(LPIC_EINVAL, "mass must be positive");
@@ -127,7 +128,7 @@ lpic_status check_tiling(const lpic_tiling* t, const lpic_grid* g, int prec,
   if (t->halo > g->nx || t->halo > g->ny || (nd == 3 && t->halo > g->nz))
     return fail(LPIC_EINVAL, "halo larger than the grid");
   if (t->chunk < 1) return fail(LPIC_EINVAL, "chunk must be >= 1");
-  if (t->flags & ~(LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE))
+  if (t->flags & ~(LPIC_SORT_SPREAD | LPIC_FIELD_SEPARATE | LPIC_ESCAPE_REBIN))
     return fail(LPIC_EINVAL, "unknown tiling flags 0x%x", t->flags);
   const size_t smem = fused_smem_bytes(prec, nd, t->tx, t->ty, nd == 3 ? t->tz : 1, t->halo, 1);
   if (need_lds && smem > 160 * 1024)
@@ -253,6 +254,11 @@ int64_t max_chunks_of(int64_t ntiles, int64_t n, int chunk) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Escapes per step from which a simulation with LPIC_ESCAPE_REBIN groups them by present
+// tile for a second fused pass (below it, k_escape's global atomics cost less than the
+// grouping's scans).
+constexpr int REBIN_THRESHOLD = 4096;
 
 // The fused kernel is persistent: XCD x (workgroups x, x+8, x+16, ...) owns the contiguous
 // chunk range [x*per, (x+1)*per), per = ceil(nchunks/8), split into equal slices.  The grid
@@ -667,6 +673,12 @@ struct lpic_sim {
   unsigned int* laser_done = nullptr;        // workgroup counter of the antenna kernel
   int32_t* jshift = nullptr;                 // per run: fixed-point shift of FP32 currents
   int64_t esc_capacity = 0;
+  // re-binned escape path (LPIC_ESCAPE_REBIN)
+  Rebin rb{};
+  bool rebin = false;
+  unsigned long long* rb_items = nullptr;     // grouped escape list
+  unsigned long long* esc2_items = nullptr;   // the second pass's own escape list
+  unsigned int* esc2_count = nullptr;         // its counters (and a total)
   int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
   int blocks_per_cu_rho = 1;
   // fused 2D field update between steps (launch_yee_mid); mid_tx == 0: not in use
@@ -837,6 +849,10 @@ lpic_status configure(lpic_sim* s) {
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks);
+  free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
+  free_dev(s->rb.chunks); free_dev(s->rb.nchunks);
+  s->rb = Rebin{};
+  s->rebin = false;
   s->mult = nullptr;
   s->runs_d = nullptr; s->segs_d = nullptr; s->run_blk_d = nullptr;
   s->seg_blk256_d = s->seg_blk_sort_d = nullptr;
@@ -907,6 +923,33 @@ lpic_status configure(lpic_sim* s) {
     ALLOC(s->esc_items, sizeof(unsigned long long) * s->esc_capacity);
     ALLOC(s->esc_count, 256);
     HIPCHK(hipMemset(s->esc_count, 0, 256));
+  }
+  if (t.flags & LPIC_ESCAPE_REBIN) {
+    if (!s->rb_items) {
+      ALLOC(s->rb_items, sizeof(unsigned long long) * s->esc_capacity);
+      ALLOC(s->esc2_items, sizeof(unsigned long long) * s->esc_capacity);
+      ALLOC(s->esc2_count, 256);
+      HIPCHK(hipMemset(s->esc2_count, 0, 256));
+    }
+    Rebin& rb = s->rb;
+    ALLOC(rb.counts, sizeof(int32_t) * (s->nbins + 1));
+    ALLOC(rb.offsets, sizeof(int32_t) * (s->nbins + 1));
+    ALLOC(rb.cursor, sizeof(int32_t) * (s->nbins + 1));
+    ALLOC(rb.chunks, sizeof(Chunk) * std::max<int64_t>(1, maxch));
+    ALLOC(rb.nchunks, 256);
+    HIPCHK(hipMemset(rb.counts, 0, sizeof(int32_t) * (s->nbins + 1)));
+    HIPCHK(hipMemset(rb.nchunks, 0, 256));
+    rb.threshold = REBIN_THRESHOLD;
+    rb.nbins = s->nbins;
+    rb.nvirt = s->nvirt;
+    rb.chunk = t.chunk;
+    rb.count_blocks = (int)std::min<int64_t>(2048, (s->esc_capacity + 2047) / 2048);
+    rb.items = s->rb_items;
+    rb.esc2.items = s->esc2_items;
+    rb.esc2.count = s->esc2_count;
+    rb.esc2.total = (unsigned long long*)((char*)s->esc2_count + 64);
+    rb.esc2.capacity = s->esc_capacity;
+    s->rebin = true;
   }
   s->need_sort = true;
   s->offsets_valid = false;
@@ -1029,7 +1072,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       launch_fused(Tc, s->prec, s->ndim, s->geo,
                    fused_grid(s->max_chunks, diag ? s->blocks_per_cu_rho : s->blocks_per_cu),
                    diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
-                   diag ? 1 : 0, esc, s->jshift, st);
+                   diag ? 1 : 0, esc, s->jshift, st, s->rebin ? &s->rb : nullptr);
       CHK(last_launch("fused"));
       if (s->timing) {
         HIPCHK(hipEventRecord(e1, st));
@@ -1186,6 +1229,9 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
   free_dev(s->esc_items); free_dev(s->esc_count);
+  free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
+  free_dev(s->rb.chunks); free_dev(s->rb.nchunks);
+  free_dev(s->rb_items); free_dev(s->esc2_items); free_dev(s->esc2_count);
   free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
   free_dev(s->mid_pfx_d); free_dev(s->bands);
   free_dev(s->old_state);
@@ -1546,8 +1592,10 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
   if (!s || !sp) return fail(LPIC_EINVAL, "sim or search space is NULL");
   if (sp->steps_each < 1) return fail(LPIC_EINVAL, "steps_each must be >= 1");
   const int nd = s->ndim;
-  // parameter p: 0..2 tile edges, 3 halo, 4 chunk, 5 sort interval; lo/hi per parameter
-  int lo[6], hi[6];
+  // parameter p: 0..2 tile edges, 3 halo, 4 chunk, 5 sort interval, 6 the re-binned
+  // escape path (0 / 1); lo/hi per parameter
+  constexpr int NP = 7;
+  int lo[NP], hi[NP];
   for (int d = 0; d < 3; ++d) {
     lo[d] = pow2_ceil(std::max(1, sp->tile_min[d]));
     hi[d] = pow2_floor(std::max(1, sp->tile_max[d]));
@@ -1559,7 +1607,9 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
   hi[4] = pow2_floor(std::max(1, sp->chunk_max));
   lo[5] = std::max(1, sp->sort_min);
   hi[5] = sp->sort_max;
-  for (int p = 0; p < 6; ++p)
+  lo[6] = sp->rebin == 1 ? 1 : 0;
+  hi[6] = sp->rebin == 0 ? 0 : 1;
+  for (int p = 0; p < NP; ++p)
     if (lo[p] > hi[p]) return fail(LPIC_EINVAL, "empty search range for parameter %d", p);
   const int budget = std::min(LPIC_TUNE_MAX_TRIALS,
                               sp->max_trials > 0 ? sp->max_trials : LPIC_TUNE_MAX_TRIALS);
@@ -1571,7 +1621,8 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
       case 2: return o.tiling.tz;
       case 3: return o.tiling.halo;
       case 4: return o.tiling.chunk;
-      default: return o.sort_interval;
+      case 5: return o.sort_interval;
+      default: return (o.tiling.flags & LPIC_ESCAPE_REBIN) ? 1 : 0;
     }
   };
   auto put = [&](lpic_options& o, int p, int v) {
@@ -1581,13 +1632,16 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
       case 2: o.tiling.tz = v; break;
       case 3: o.tiling.halo = v; break;
       case 4: o.tiling.chunk = v; break;
-      default: o.sort_interval = v; break;
+      case 5: o.sort_interval = v; break;
+      default:
+        o.tiling.flags = v ? (o.tiling.flags | LPIC_ESCAPE_REBIN) : (o.tiling.flags & ~LPIC_ESCAPE_REBIN);
+        break;
     }
   };
   // the starting point: the present options clamped into the space
   lpic_options cur = base;
   if (nd != 3) cur.tiling.tz = 1;
-  for (int p = 0; p < 6; ++p) {
+  for (int p = 0; p < NP; ++p) {
     int v = get(cur, p);
     if (p <= 2 || p == 4) v = pow2_floor(std::max(1, v));
     put(cur, p, std::min(hi[p], std::max(lo[p], v)));
@@ -1597,7 +1651,8 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
   auto same = [](const lpic_options& a, const lpic_options& b) {
     return a.tiling.tx == b.tiling.tx && a.tiling.ty == b.tiling.ty &&
            a.tiling.tz == b.tiling.tz && a.tiling.halo == b.tiling.halo &&
-           a.tiling.chunk == b.tiling.chunk && a.sort_interval == b.sort_interval;
+           a.tiling.chunk == b.tiling.chunk && a.sort_interval == b.sort_interval &&
+           a.tiling.flags == b.tiling.flags;
   };
   // time of an option set (cached); < 0 infeasible; budget exhausted: +inf, not recorded
   auto trial = [&](const lpic_options& o, double* ms) -> lpic_status {
@@ -1618,13 +1673,14 @@ lpic_status lpic_autotune_search(lpic_sim* s, const lpic_tune_space* sp, lpic_op
   bool moved = true;
   while (moved && (int)tried.size() < budget) {
     moved = false;
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < NP; ++p) {
       if (lo[p] == hi[p]) continue;
       for (int dir = +1; dir >= -1; dir -= 2) {
         for (;;) {
           const int v = get(cur, p);
-          // halo: one cell more or less; sizes and the sort interval: twice or half
-          const int nv = p == 3 ? v + dir : (dir > 0 ? v * 2 : v / 2);
+          // halo: one cell more or less; sizes and the sort interval: twice or half; the
+          // re-binned path: on or off
+          const int nv = (p == 3 || p == 6) ? v + dir : (dir > 0 ? v * 2 : v / 2);
           if (nv < lo[p] || nv > hi[p] || nv == v) break;
           lpic_options o = cur;
           put(o, p, nv);

@@ -219,6 +219,7 @@ __device__ __forceinline__ void weights_half(R o, int c, int& base, R w[ORDER + 
 template <typename R>
 struct GlobalAcc {
   static constexpr bool kPaired = false;
+  static constexpr bool kLinear = false;   // offsets wrap: one per node
   gptr<R> f[F_NUM];
   int nx, ny, nz;
   __device__ __forceinline__ int xo(int x) const { return wrapi(x, nx); }
@@ -258,6 +259,9 @@ struct DynStrides {
 template <typename R, class S, bool PAIR = false>
 struct LdsAcc {
   static constexpr bool kPaired = PAIR;
+  // offsets are linear in the node index: one base per window, the nodes at compile-time
+  // offsets from it (immediates of the LDS instructions when the strides are fixed)
+  static constexpr bool kLinear = true;
   R* fbase;       // the six field components, laid out as above
   double* jbase;  // planes Jx Jy Jz, then rho0 rho1 (FP32 path: int64 fixed point)
   S st;
@@ -445,10 +449,57 @@ __device__ __forceinline__ void gather2_paired(const Acc& A, const int* c, const
   B[0] = bx; B[1] = by; B[2] = bz;
 }
 
+// One 3D component from a linear LDS layout: p at the stencil's first node.
+template <int N, typename R, class Acc>
+__device__ __forceinline__ R interp3_lin(const Acc& A, const R* p, const R* wx, const R* wy,
+                                         const R* wz) {
+  const int sy = A.st.sy(), sz = A.st.sz();
+  R s = R(0);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    R t = R(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      R r = R(0);
+#pragma unroll
+      for (int a = 0; a < N; ++a) r += wx[a] * p[c * sz + b * sy + a];
+      t += wy[b] * r;
+    }
+    s += wz[c] * t;
+  }
+  return s;
+}
+
+// 3D gather from the LDS planes Ex Ey Ez Bx By Bz: one base address per component (its
+// staggering), every node a compile-time offset from it when the strides are fixed.
+template <int ORDER, typename R, class Acc>
+__device__ __forceinline__ void gather3_linear(const Acc& A, const int* c, const R* o, R E[3],
+                                               R B[3]) {
+  constexpr int N = ORDER + 1;
+  int ix, hx, iy, hy, iz, hz;
+  R wxi[N], wxh[N], wyi[N], wyh[N], wzi[N], wzh[N];
+  weights_int<ORDER>(o[0], c[0], ix, wxi);
+  weights_half<ORDER>(o[0], c[0], hx, wxh);
+  weights_int<ORDER>(o[1], c[1], iy, wyi);
+  weights_half<ORDER>(o[1], c[1], hy, wyh);
+  weights_int<ORDER>(o[2], c[2], iz, wzi);
+  weights_half<ORDER>(o[2], c[2], hz, wzh);
+  const int sy = A.st.sy(), sz = A.st.sz();
+  E[0] = interp3_lin<N>(A, A.plane_ptr(F_EX, iz * sz + iy * sy + hx), wxh, wyi, wzi);
+  E[1] = interp3_lin<N>(A, A.plane_ptr(F_EY, iz * sz + hy * sy + ix), wxi, wyh, wzi);
+  E[2] = interp3_lin<N>(A, A.plane_ptr(F_EZ, hz * sz + iy * sy + ix), wxi, wyi, wzh);
+  B[0] = interp3_lin<N>(A, A.plane_ptr(F_BX, hz * sz + hy * sy + ix), wxi, wyh, wzh);
+  B[1] = interp3_lin<N>(A, A.plane_ptr(F_BY, hz * sz + iy * sy + hx), wxh, wyi, wzh);
+  B[2] = interp3_lin<N>(A, A.plane_ptr(F_BZ, iz * sz + hy * sy + hx), wxh, wyh, wzi);
+}
+
 template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void gather(const Acc& A, const int* c, const R* o, R E[3], R B[3]) {
   if constexpr (DIM == 2 && Acc::kPaired) {
     gather2_paired<ORDER>(A, c, o, E, B);
+    return;
+  } else if constexpr (DIM == 3 && Acc::kLinear) {
+    gather3_linear<ORDER>(A, c, o, E, B);
     return;
   }
   constexpr int N = ORDER + 1;
@@ -593,8 +644,14 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   const bool xs = S0x[W - 1] == R(0) && S1x[W - 1] == R(0);
   const bool ys = S0y[W - 1] == R(0) && S1y[W - 1] == R(0);
   int xo[W], yo[W];
+  if constexpr (Acc::kLinear) {
+    const int wb = A.yo(c[1] + by) + A.xo(c[0] + bx);
 #pragma unroll
-  for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
+    for (int a = 0; a < W; ++a) { xo[a] = wb + a; yo[a] = A.yo(a); }
+  } else {
+#pragma unroll
+    for (int a = 0; a < W; ++a) { xo[a] = A.xo(c[0] + bx + a); yo[a] = A.yo(c[1] + by + a); }
+  }
   const R fw = A.fold() * w;
   const R cx = k.jx * fw, cy = k.jy * fw;
   R dSx[W], dSy[W];
@@ -661,7 +718,10 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     int zo[W];
     R dSz[W];
 #pragma unroll
-    for (int a = 0; a < W; ++a) { zo[a] = A.zo(c[2] + bz + a); dSz[a] = S1z[a] - S0z[a]; }
+    for (int a = 0; a < W; ++a) {
+      zo[a] = Acc::kLinear ? A.zo(a) + A.zo(c[2] + bz) : A.zo(c[2] + bz + a);
+      dSz[a] = S1z[a] - S0z[a];
+    }
     const R cz = k.jz * fw;
     const R sixth = R(1.0 / 6.0);
     // Jx: running sum along x of dSx * Ryz
@@ -784,16 +844,26 @@ __device__ __forceinline__ PartPtrs<R> part_ptrs(const SegDesc& s, const RunDesc
   return q;
 }
 
+// Element p of a particle array through a 32-bit byte offset from the array's (uniform)
+// base: the load or store can then take the base from scalar registers and one 32-bit
+// offset per lane, shared by every array of the same element size, instead of a 64-bit
+// address per array.  Slots are below 2^29 (check_species), so p * 8 fits.
+template <typename T>
+__device__ __forceinline__ gptr<T> at_byte(gptr<T> base, uint32_t off) {
+  return (gptr<T>)((__attribute__((address_space(1))) char*)base + off);
+}
+
 template <typename R, int DIM>
 __device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, PState<R>& ps) {
+  const uint32_t o4 = (uint32_t)p * 4u, oR = (uint32_t)p * (uint32_t)sizeof(R);
   if constexpr (sizeof(R) == 4) {
-    const int32_t cell = q.cell[p];
+    const int32_t cell = *at_byte(q.cell, o4);
     unpack_cell(cell < 0 ? 0 : cell, DIM, ps.c);
     // a cell outside the box cannot come from the library; treat it like a dead slot
     ps.alive = cell >= 0 && ps.c[0] < q.nx && ps.c[1] < q.ny && (DIM == 2 || ps.c[2] < q.nz);
-    ps.o[0] = q.pos[0][p];
-    ps.o[1] = q.pos[1][p];
-    ps.o[2] = DIM == 3 ? q.pos[2][p] : 0.f;
+    ps.o[0] = *at_byte(q.pos[0], oR);
+    ps.o[1] = *at_byte(q.pos[1], oR);
+    ps.o[2] = DIM == 3 ? *at_byte(q.pos[2], oR) : 0.f;
   } else {
     const double h[3] = {q.dx, q.dy, q.dz};
     const int n[3] = {q.nx, q.ny, q.nz};
@@ -801,7 +871,7 @@ __device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, P
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d < DIM) {
-        const double X = q.pos[d][p] / h[d];
+        const double X = *at_byte(q.pos[d], oR) / h[d];
         // positions outside [0, L] (or NaN) cannot come from the library: dead slot
         if (!(X >= 0.0 && X <= (double)n[d])) ps.alive = false;
         const double f = floor_clamped<double>(X, 0.0, (double)n[d]);
@@ -815,10 +885,11 @@ __device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, P
       }
     }
   }
-  ps.u[0] = q.u[0][p];
-  ps.u[1] = q.u[1][p];
-  ps.u[2] = q.u[2][p];
-  ps.w = q.w[p];
+  ps.u[0] = *at_byte(q.u[0], oR);
+  ps.u[1] = *at_byte(q.u[1], oR);
+  ps.u[2] = *at_byte(q.u[2], oR);
+  ps.w = *at_byte(q.w, oR);
+  (void)o4;
 }
 
 template <typename R, int DIM>
@@ -843,22 +914,25 @@ __device__ __forceinline__ void advance_cell(int& c, R& o, R x1, int n) {
 template <typename R, int DIM>
 __device__ __forceinline__ void store_particle(const PartPtrs<R>& q, int32_t p,
                                                const PState<R>& ps) {
-  if (!ps.alive) {   // removed during this step: the dead marker instead of the position
-    if constexpr (sizeof(R) == 4) q.cell[p] = -1;
-    else q.pos[0][p] = -1.0;
-  } else if constexpr (sizeof(R) == 4) {
-    q.cell[p] = pack_cell(ps.c, DIM);
-    q.pos[0][p] = ps.o[0];
-    q.pos[1][p] = ps.o[1];
-    if (DIM == 3) q.pos[2][p] = ps.o[2];
+  const uint32_t o4 = (uint32_t)p * 4u, oR = (uint32_t)p * (uint32_t)sizeof(R);
+  // a particle removed during this step gets the dead marker (cell -1 / x = -1) in place of
+  // its position; the other words are written either way (no branch around the stores)
+  if constexpr (sizeof(R) == 4) {
+    *at_byte(q.cell, o4) = ps.alive ? pack_cell(ps.c, DIM) : -1;
+    *at_byte(q.pos[0], oR) = ps.o[0];
+    *at_byte(q.pos[1], oR) = ps.o[1];
+    if (DIM == 3) *at_byte(q.pos[2], oR) = ps.o[2];
   } else {
     const double h[3] = {q.dx, q.dy, q.dz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) q.pos[d][p] = ((double)ps.c[d] + ps.o[d]) * h[d];
+    for (int d = 0; d < DIM; ++d) {
+      const double x = ((double)ps.c[d] + ps.o[d]) * h[d];
+      *at_byte(q.pos[d], oR) = (d == 0 && !ps.alive) ? -1.0 : x;
+    }
   }
-  q.u[0][p] = ps.u[0];
-  q.u[1][p] = ps.u[1];
-  q.u[2][p] = ps.u[2];
+  *at_byte(q.u[0], oR) = ps.u[0];
+  *at_byte(q.u[1], oR) = ps.u[1];
+  *at_byte(q.u[2], oR) = ps.u[2];
 }
 
 template <typename R, int DIM>

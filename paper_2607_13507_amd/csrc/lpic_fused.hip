@@ -143,11 +143,14 @@ constexpr int fused_waves() { return (sizeof(R) == 4 && DIM == 2) ? 4 : 1; }
 template <typename R, int DIM>
 constexpr int fused_block() { return DIM == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 512); }
 
+// list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
+// `list`, whose entries name the particles (segment << 32 | slot).
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
                                                 const Chunk& ch, const Region& g,
                                                 const LA& L, int with_rho,
-                                                bool want_ke, const EscapeList& esc) {
+                                                bool want_ke, const EscapeList& esc,
+                                                const unsigned long long* list) {
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
   const PartPtrs<R> q = part_ptrs<R>(s, r);
@@ -162,6 +165,7 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
     for (int b = 0; b < BATCH; ++b) {
       pi[b] = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
       ok[b] = pi[b] < ch.end;
+      if (list && ok[b]) pi[b] = (int32_t)(gp(list)[pi[b]] & 0xffffffffull);
       if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);
     }
 #pragma unroll
@@ -241,7 +245,8 @@ template <typename R, int DIM, int G>
 __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
-                                               EscapeList esc, const int32_t* jshift) {
+                                               EscapeList esc, const int32_t* jshift,
+                                               const unsigned long long* list) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[fused_block<R, DIM>() / 64];
   R* sm = (R*)smem_raw;
@@ -312,8 +317,9 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
     }
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
-    ke += s.order == 1 ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc)
-                       : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc);
+    ke += s.order == 1
+              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list)
+              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
@@ -348,10 +354,13 @@ __device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s,
   return (double)ps.w * s.m * u2 / (1.0 + (double)g1);
 }
 
+// skip_at: a list of at least this many entries was taken by the re-binned path; only the
+// clearing is left to do.
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_escape(Tables T, int with_rho, double* kinetic,
-                                                int ke_to_diag, EscapeList esc) {
-  const unsigned int cnt = min((int64_t)esc.count[0], esc.capacity);
+                                                int ke_to_diag, EscapeList esc, int skip_at) {
+  unsigned int cnt = min((int64_t)esc.count[0], esc.capacity);
+  if ((int)min(esc.count[0], 0x7fffffffu) >= skip_at) cnt = 0;
   for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += gridDim.x * blockDim.x) {
     const unsigned long long v = esc.items[i];
@@ -391,17 +400,19 @@ int fused_geometry(int dim, int tx, int ty, int tz, int halo) {
 template <typename R, int D, int G>
 static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
                            const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
-                           const EscapeList& esc, const int32_t* jshift, hipStream_t st) {
+                           const EscapeList& esc, const int32_t* jshift,
+                           const unsigned long long* list, hipStream_t st) {
   k_fused<R, D, G><<<nblocks, fused_block<R, D>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
-                                               ke_to_diag, esc, jshift);
+                                               ke_to_diag, esc, jshift, list);
 }
 
 template <typename R, int D>
 static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
                            const Chunk* chunks, const int32_t* nchunks, int with_rho,
                            double* kinetic, int ke_to_diag, const EscapeList& esc,
-                           const int32_t* jshift, hipStream_t st) {
-#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, jshift, st)
+                           const int32_t* jshift, const unsigned long long* list,
+                           hipStream_t st) {
+#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, jshift, list, st)
   if constexpr (D == 2) {
     switch (geo) {
       case 1: LPIC_GEO(1); return;
@@ -423,11 +434,24 @@ static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
 void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
                   const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
                   int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
-                  hipStream_t st) {
+                  hipStream_t st, const Rebin* rb) {
   LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, chunks, nchunks, with_rho,
-                                           kinetic, ke_to_diag, esc, jshift, st)));
-  LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(T, with_rho, kinetic,
-                                                                    ke_to_diag, esc)));
+                                           kinetic, ke_to_diag, esc, jshift, nullptr, st)));
+  if (rb) {
+    // escapees by present tile, a second pass over them, then whatever that pass could not
+    // place (normally nothing) through global memory
+    launch_rebin(T, prec, dim, esc, *rb, st);
+    LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, rb->chunks, rb->nchunks,
+                                             with_rho, kinetic, ke_to_diag, rb->esc2, jshift,
+                                             rb->items, st)));
+    LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
+                           T, with_rho, kinetic, ke_to_diag, esc, rb->threshold)));
+    LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
+                           T, with_rho, kinetic, ke_to_diag, rb->esc2, 0x7fffffff)));
+  } else {
+    LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
+                           T, with_rho, kinetic, ke_to_diag, esc, 0x7fffffff)));
+  }
 }
 
 template <typename R, int D, int G>

@@ -90,14 +90,36 @@ struct EscapeList {
 };
 constexpr int ESCAPE_BLOCKS = 128;
 
+// The re-binned escape path (tiling flag LPIC_ESCAPE_REBIN): when a step's escape list
+// holds at least `threshold` particles, they are grouped by the tile they are in now (bins
+// in the sort's layout: segment s owns [bin_base, bin_base + ntiles]) and pushed by a
+// second fused pass against the staged regions of those tiles; below the threshold
+// k_escape pushes them through global memory as without the flag.
+struct Rebin {
+  int threshold;
+  int nbins;                   // bins of all segments
+  int nvirt, chunk;            // the chunk order of the fused kernel (launch_build_chunks)
+  int count_blocks;            // workgroups of the count and scatter kernels
+  int32_t *counts, *offsets, *cursor;   // nbins + 1 each; counts zero between steps
+  unsigned long long* items;   // the escape list grouped by bin (capacity of the list)
+  Chunk* chunks;
+  int32_t* nchunks;
+  EscapeList esc2;             // particles the second pass finds outside its regions
+};
+
 // geometry: 0 = runtime strides, else a compiled (tile, halo) shape (fused_geometry()).
 int fused_geometry(int dim, int tx, int ty, int tz, int halo);
 // Launches the fused kernel (persistent grid of nblocks, a multiple of 8) and then the
 // escape kernel on the same stream.
 // jshift[run]: the fixed-point shift S of the FP32 current accumulators (launch_fixed_shift).
+// rebin != NULL: the re-binned escape path follows the first pass (see Rebin).
 void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size_t smem,
                   const Chunk* chunks, const int32_t* nchunks, int with_rho, double* kinetic,
                   int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
+                  hipStream_t st, const Rebin* rebin = nullptr);
+// Escape-list entries to (segment, present tile) bins and their grouped list (the first
+// three kernels of the re-binned path), then the chunk list over those bins.
+void launch_rebin(const Tables& T, int prec, int dim, const EscapeList& esc, const Rebin& rb,
                   hipStream_t st);
 // Per run, the shift S for the fixed-point current accumulators of the fused kernel, from
 // the largest |q w| of its species (wmax: fixed_shift_slots() 8-byte words per segment,

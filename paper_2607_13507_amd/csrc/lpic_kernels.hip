@@ -1055,9 +1055,12 @@ constexpr int SCAN_PER = 16;
 
 // Exclusive scan of the bin counts by one workgroup; clears the counts for the next sort
 // and records each bin's placement multiplier.
+// gate != NULL: only when *gate >= threshold (the re-binned escape path); mult may be NULL.
 __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* offsets,
                                                     int32_t* cursor, int32_t* mult, int nbins,
-                                                    int spread) {
+                                                    int spread, const unsigned int* gate,
+                                                    int threshold) {
+  if (gate && (int)min(gate[0], 0x7fffffffu) < threshold) return;
   __shared__ int32_t wsum[17];
   int32_t base = 0;
   for (int pass = 0; pass < nbins; pass += 1024 * SCAN_PER) {
@@ -1077,7 +1080,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
       if (b < nbins) {
         offsets[b] = run;
         cursor[b] = run;
-        mult[b] = spread ? spread_multiplier(v[k]) : 1;
+        if (mult) mult[b] = spread ? spread_multiplier(v[k]) : 1;
         counts[b] = 0;
       }
       run += v[k];
@@ -1309,9 +1312,18 @@ __device__ __forceinline__ VSlot vslot_run(const Tables& T, int v) {
   return q;
 }
 
+// absolute: chunk ranges are positions in the list the offsets describe (the re-binned
+// escape list) instead of slots relative to the segment.  gate != NULL: only when
+// *gate >= threshold; otherwise the chunk count is set to zero.
 __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* offsets,
                                                        int nvirt, int chunk, Chunk* out,
-                                                       int32_t* nchunks) {
+                                                       int32_t* nchunks, int absolute,
+                                                       const unsigned int* gate,
+                                                       int threshold) {
+  if (gate && (int)min(gate[0], 0x7fffffffu) < threshold) {
+    if (threadIdx.x == 0) *nchunks = 0;
+    return;
+  }
   __shared__ int32_t wsum[17];
   int32_t cbase = 0;
   for (int pass = 0; pass < nvirt; pass += 1024 * SCAN_PER) {
@@ -1333,8 +1345,9 @@ __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* 
         sg[k] = q.seg_first + (w - tl[k] * q.nseg);
         const SegDesc& s = seg_of(T, sg[k]);
         const int b = s.bin_base + tl[k];
-        o0[k] = offsets[b] - (int32_t)s.pbase;
-        o1[k] = offsets[b + 1] - (int32_t)s.pbase;
+        const int32_t rel = absolute ? 0 : (int32_t)s.pbase;
+        o0[k] = offsets[b] - rel;
+        o1[k] = offsets[b + 1] - rel;
       }
     }
     int32_t local = 0;
@@ -1357,6 +1370,115 @@ __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* 
     cbase += total;
   }
   if (threadIdx.x == 0) *nchunks = cbase;
+}
+
+// =======================================================================================
+// Re-binned escapes.  Particles that have left the on-chip margin of their home tile since
+// the last sort (the fused kernel's escape list) are grouped by the tile they are in now:
+// count per (segment, tile) bin, scan, scatter of the list entries, a chunk list over those
+// bins; a second fused pass then pushes them against the staged regions of their present
+// tiles, where they are always inside.  Every kernel of the path first reads the escape
+// count and does nothing below `threshold` (the step then leaves the escapees to k_escape),
+// so the path can sit in a captured graph.
+// =======================================================================================
+__device__ __forceinline__ bool rebin_on(const unsigned int* esc_count, int threshold) {
+  return (int)min(esc_count[0], 0x7fffffffu) >= threshold;
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ int escapee_bin(const Tables& T, unsigned long long item) {
+  const int seg = (int)(item >> 32);
+  const int64_t p = (int64_t)(item & 0xffffffffull);
+  const SegDesc& s = seg_of(T, seg);
+  return particle_bin<R, DIM>(s, run_of(T, s.run), p);
+}
+
+// ESC_ITEMS escape-list entries per thread: 2048 per workgroup of 256, as for the sort.
+constexpr int ESC_ITEMS = SORT_ITEMS;
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_rebin_count(Tables T, EscapeList esc, int threshold,
+                                                     int32_t* counts) {
+  if (!rebin_on(esc.count, threshold)) return;
+  const int64_t n = min((int64_t)esc.count[0], esc.capacity);
+  __shared__ SortCache C;
+  sort_cache_clear(C);
+  __syncthreads();
+  for (int64_t beg = (int64_t)blockIdx.x * 256 * ESC_ITEMS; beg < n;
+       beg += (int64_t)gridDim.x * 256 * ESC_ITEMS) {
+    int key[ESC_ITEMS];
+#pragma unroll
+    for (int it = 0; it < ESC_ITEMS; ++it) {
+      const int64_t i = beg + it * 256 + threadIdx.x;
+      key[it] = i < n ? escapee_bin<R, DIM>(T, esc.items[i]) : -1;
+    }
+#pragma unroll
+    for (int it = 0; it < ESC_ITEMS; ++it) {
+      const uint64_t m = wave_match(key[it], key[it] >= 0);
+      if (m && __lane_id() == __ffsll((unsigned long long)m) - 1) {
+        const int len = __popcll(m);
+        if (sort_cache_claim(C, key[it])) atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len);
+        else atomicAdd(&counts[key[it]], len);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SORT_SLOTS; i += blockDim.x)
+    if (C.tag[i] >= 0 && C.cnt[i] > 0) atomicAdd(&counts[C.tag[i]], C.cnt[i]);
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc, int threshold,
+                                                       int32_t* cursor,
+                                                       unsigned long long* out) {
+  if (!rebin_on(esc.count, threshold)) return;
+  const int64_t n = min((int64_t)esc.count[0], esc.capacity);
+  __shared__ SortCache C;
+  for (int64_t beg = (int64_t)blockIdx.x * 256 * ESC_ITEMS; beg < n;
+       beg += (int64_t)gridDim.x * 256 * ESC_ITEMS) {
+    sort_cache_clear(C);
+    __syncthreads();
+    int key[ESC_ITEMS];
+    unsigned long long item[ESC_ITEMS];
+#pragma unroll
+    for (int it = 0; it < ESC_ITEMS; ++it) {
+      const int64_t i = beg + it * 256 + threadIdx.x;
+      item[it] = i < n ? esc.items[i] : 0ull;
+      key[it] = i < n ? escapee_bin<R, DIM>(T, item[it]) : -1;
+    }
+    // ranks inside the workgroup for cached keys, straight from the bin cursor otherwise
+    int32_t rank[ESC_ITEMS];
+    bool cached[ESC_ITEMS];
+#pragma unroll
+    for (int it = 0; it < ESC_ITEMS; ++it) {
+      const uint64_t m = wave_match(key[it], key[it] >= 0);
+      const int lane = __lane_id();
+      const int head = m ? __ffsll((unsigned long long)m) - 1 : lane;
+      int base = 0, hit = 0;
+      if (m && lane == head) {
+        const int len = __popcll(m);
+        hit = sort_cache_claim(C, key[it]);
+        base = hit ? atomicAdd(&C.cnt[key[it] & (SORT_SLOTS - 1)], len)
+                   : atomicAdd(&cursor[key[it]], len);
+      }
+      base = __shfl(base, head, 64);
+      hit = __shfl(hit, head, 64);
+      rank[it] = base + __popcll(m & ((1ull << lane) - 1ull));
+      cached[it] = hit != 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < SORT_SLOTS; i += blockDim.x)
+      if (C.tag[i] >= 0 && C.cnt[i] > 0) C.base[i] = atomicAdd(&cursor[C.tag[i]], C.cnt[i]);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ESC_ITEMS; ++it) {
+      if (key[it] < 0) continue;
+      const int64_t slot =
+          (cached[it] ? (int64_t)C.base[key[it] & (SORT_SLOTS - 1)] : 0) + rank[it];
+      out[slot] = item[it];
+    }
+    __syncthreads();   // the cache is cleared for the next batch
+  }
 }
 
 // =======================================================================================
@@ -1747,7 +1869,7 @@ void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* count
                  int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
                  hipStream_t st) {
   LPIC_PD(prec, dim, (k_sort_count<R, D><<<nblocks, 256, 0, st>>>(T, counts)));
-  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread);
+  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread, nullptr, 0);
   LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult,
                                                                      spread)));
 }
@@ -1769,7 +1891,19 @@ void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
 
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st) {
-  k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, nchunks);
+  k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, nchunks, 0, nullptr, 0);
+}
+
+void launch_rebin(const Tables& T, int prec, int dim, const EscapeList& esc, const Rebin& rb,
+                  hipStream_t st) {
+  LPIC_PD(prec, dim, (k_rebin_count<R, D><<<rb.count_blocks, 256, 0, st>>>(T, esc, rb.threshold,
+                                                                          rb.counts)));
+  k_scan_bins<<<1, 1024, 0, st>>>(rb.counts, rb.offsets, rb.cursor, nullptr, rb.nbins, 0,
+                                  esc.count, rb.threshold);
+  LPIC_PD(prec, dim, (k_rebin_scatter<R, D><<<rb.count_blocks, 256, 0, st>>>(
+                         T, esc, rb.threshold, rb.cursor, rb.items)));
+  k_build_chunks<<<1, 1024, 0, st>>>(T, rb.offsets, rb.nvirt, rb.chunk, rb.chunks, rb.nchunks,
+                                     1, esc.count, rb.threshold);
 }
 
 template <typename R, int DIM>

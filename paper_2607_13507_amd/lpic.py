@@ -18,6 +18,7 @@ F64_ABS = 1
 YEE_ZERO_J = 1
 SORT_SPREAD = 1
 FIELD_SEPARATE = 2
+ESCAPE_REBIN = 4
 
 STAGES = ["START", "LOOP_START", "MAXWELL_1", "PUSH_POSITION_1", "INTERPOLATOR",
           "PUSH_MOMENTUM", "PUSH_POSITION_2", "CURRENT_DEPOSITION", "QED_CREATE",
@@ -98,7 +99,8 @@ class TuneSpace(ctypes.Structure):
                 ("halo_min", ctypes.c_int32), ("halo_max", ctypes.c_int32),
                 ("chunk_min", ctypes.c_int32), ("chunk_max", ctypes.c_int32),
                 ("sort_min", ctypes.c_int32), ("sort_max", ctypes.c_int32),
-                ("steps_each", ctypes.c_int32), ("max_trials", ctypes.c_int32)]
+                ("rebin", ctypes.c_int32), ("steps_each", ctypes.c_int32),
+                ("max_trials", ctypes.c_int32)]
 
 
 class TuneReport(ctypes.Structure):

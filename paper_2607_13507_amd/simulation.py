@@ -330,12 +330,13 @@ class Simulation:
                     sort_interval=best.sort_interval, use_graph=bool(best.use_graph))
 
     def autotune_search(self, tile=((8, 8, 1), (32, 32, 1)), halo=(3, 7), chunk=(512, 4096),
-                        sort_interval=(10, 80), steps_each=40, max_trials=24):
-        """lpic_autotune_search over the given (min, max) ranges; the simulation advances
-        while it tunes.  Returns the chosen options and every trial (options, ms per step)."""
+                        sort_interval=(10, 80), rebin=2, steps_each=40, max_trials=24):
+        """lpic_autotune_search over the given (min, max) ranges (rebin: the re-binned
+        escape path off 0, on 1, both tried 2); the simulation advances while it tunes.
+        Returns the chosen options and every trial (options, ms per step)."""
         sp = L.TuneSpace((ctypes.c_int32 * 3)(*tile[0]), (ctypes.c_int32 * 3)(*tile[1]),
                          halo[0], halo[1], chunk[0], chunk[1], sort_interval[0],
-                         sort_interval[1], steps_each, max_trials)
+                         sort_interval[1], rebin, steps_each, max_trials)
         before = L.lpic_get_stats(self.h).steps
         best, rep = L.lpic_autotune_search(self.h, sp)
         self.nstep += L.lpic_get_stats(self.h).steps - before
@@ -344,7 +345,8 @@ class Simulation:
         def od(o):
             t = o.tiling
             return dict(tiling=(t.tx, t.ty, t.tz), halo=t.halo, chunk=t.chunk,
-                        sort_interval=o.sort_interval)
+                        sort_interval=o.sort_interval, flags=t.flags,
+                        rebin=bool(t.flags & L.ESCAPE_REBIN))
         trials = [dict(od(rep.trial[i]), ms_per_step=round(rep.ms_per_step[i], 4))
                   for i in range(rep.ntrials)]
         return dict(od(best), use_graph=bool(best.use_graph)), trials

@@ -75,12 +75,12 @@ def test_error_path_without_gpu(lib):
     with pytest.raises(L.LpicError) as e:
         L.lpic_sort_tiles(g, s, s, t, 1, 1, 1 << 20, L.F32_CELLOFS, stream=0)
     assert "power" in str(e.value)
-    t = L.Tiling(16, 16, 1, 4, 256, 4)
+    t = L.Tiling(16, 16, 1, 4, 256, 8)   # no such flag
     with pytest.raises(L.LpicError) as e:
         L.lpic_sort_tiles(g, s, s, t, 1, 1, 1 << 20, L.F32_CELLOFS, stream=0)
     assert "flags" in str(e.value)
-    # the two defined flags pass the tiling check (the call then stops at the workspace size)
-    t = L.Tiling(16, 16, 1, 4, 256, L.SORT_SPREAD | L.FIELD_SEPARATE)
+    # the defined flags pass the tiling check (the call then stops at the workspace size)
+    t = L.Tiling(16, 16, 1, 4, 256, L.SORT_SPREAD | L.FIELD_SEPARATE | L.ESCAPE_REBIN)
     with pytest.raises(L.LpicError) as e:
         L.lpic_sort_tiles(g, s, s, t, 1, 1, 0, L.F32_CELLOFS, stream=0)
     assert "workspace" in str(e.value)

@@ -272,8 +272,8 @@ def test_autotune_picks_a_candidate_and_keeps_physics():
 
 
 def test_autotune_search_stays_in_its_space_and_keeps_physics():
-    """lpic_autotune_search walks tile, halo, chunk and sort interval inside the given
-    bounds, times no option set twice, keeps the fastest, and the simulation it tuned goes
+    """lpic_autotune_search walks tile, halo, chunk, sort interval and the re-binned escape
+    path inside the given bounds, times no option set twice, keeps the fastest, and the simulation it tuned goes
     on taking exactly the oracle's steps."""
     banner("autotune search")
     wl = _wl(2)
@@ -283,7 +283,7 @@ def test_autotune_search_stays_in_its_space_and_keeps_physics():
                                        chunk=(64, 512), sort_interval=(2, 8), steps_each=4,
                                        max_trials=12)
     assert 2 <= len(trials) <= 12
-    keys = [(t["tiling"], t["halo"], t["chunk"], t["sort_interval"]) for t in trials]
+    keys = [(t["tiling"], t["halo"], t["chunk"], t["sort_interval"], t["rebin"]) for t in trials]
     assert len(set(keys)) == len(keys)
     for t in trials:
         assert t["tiling"][0] in (8, 16) and t["tiling"][1] in (8, 16)
