@@ -629,10 +629,11 @@ template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0, const R* x1,
                                         R w, R vz_bar, const PushConst<R>& k, bool with_rho) {
   constexpr int W = ORDER + 2;
-  R S0x[W], S1x[W], S0y[W], S1y[W];
-  int bx, by;
+  R S0x[W], S1x[W], S0y[W], S1y[W], S0z[W], S1z[W];
+  int bx, by, bz = 0;
   esk_axis<ORDER>(x0[0], x1[0], bx, S0x, S1x);
   esk_axis<ORDER>(x0[1], x1[1], by, S0y, S1y);
+  if constexpr (DIM == 3) esk_axis<ORDER>(x0[2], x1[2], bz, S0z, S1z);
   // The last node of an axis' window carries weight only for a path that changes its
   // nearest node along that axis.  When no lane of the wave has such a path, every entry
   // on that node is an exact zero and the wave skips it (a uniform branch).
@@ -645,7 +646,9 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
   const bool ys = S0y[W - 1] == R(0) && S1y[W - 1] == R(0);
   int xo[W], yo[W];
   if constexpr (Acc::kLinear) {
-    const int wb = A.yo(c[1] + by) + A.xo(c[0] + bx);
+    // one base per particle (the window's first node, z included in 3D); every entry is a
+    // compile-time offset from it
+    const int wb = (DIM == 3 ? A.zo(c[2] + bz) : 0) + A.yo(c[1] + by) + A.xo(c[0] + bx);
 #pragma unroll
     for (int a = 0; a < W; ++a) { xo[a] = wb + a; yo[a] = A.yo(a); }
   } else {
@@ -710,16 +713,13 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         }
     }
   } else {
-    R S0z[W], S1z[W];
-    int bz;
-    esk_axis<ORDER>(x0[2], x1[2], bz, S0z, S1z);
     const bool lz = __ballot(S0z[W - 1] != R(0) || S1z[W - 1] != R(0)) != 0;
     const bool zs = S0z[W - 1] == R(0) && S1z[W - 1] == R(0);
     int zo[W];
     R dSz[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) {
-      zo[a] = Acc::kLinear ? A.zo(a) + A.zo(c[2] + bz) : A.zo(c[2] + bz + a);
+      zo[a] = Acc::kLinear ? A.zo(a) : A.zo(c[2] + bz + a);   // (linear: base in xo)
       dSz[a] = S1z[a] - S0z[a];
     }
     const R cz = k.jz * fw;
@@ -851,6 +851,33 @@ __device__ __forceinline__ PartPtrs<R> part_ptrs(const SegDesc& s, const RunDesc
 template <typename T>
 __device__ __forceinline__ gptr<T> at_byte(gptr<T> base, uint32_t off) {
   return (gptr<T>)((__attribute__((address_space(1))) char*)base + off);
+}
+
+// The cell of particle p only (FP32: the packed cell; FP64: from the absolute position);
+// false for a dead or invalid slot (as load_particle's alive).
+template <typename R, int DIM>
+__device__ __forceinline__ bool load_cell(const PartPtrs<R>& q, int32_t p, int c[3]) {
+  if constexpr (sizeof(R) == 4) {
+    const int32_t cell = *at_byte(q.cell, (uint32_t)p * 4u);
+    unpack_cell(cell < 0 ? 0 : cell, DIM, c);
+    return cell >= 0 && c[0] < q.nx && c[1] < q.ny && (DIM == 2 || c[2] < q.nz);
+  } else {
+    const double h[3] = {q.dx, q.dy, q.dz};
+    const int n[3] = {q.nx, q.ny, q.nz};
+    bool alive = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d < DIM) {
+        const double X = *at_byte(q.pos[d], (uint32_t)p * 8u) / h[d];
+        if (!(X >= 0.0 && X <= (double)n[d])) alive = false;
+        int ci = (int)floor_clamped<double>(X, 0.0, (double)n[d]);
+        c[d] = ci >= n[d] ? ci - n[d] : ci;
+      } else {
+        c[d] = 0;
+      }
+    }
+    return alive;
+  }
 }
 
 template <typename R, int DIM>

@@ -145,12 +145,125 @@ constexpr int fused_block() { return DIM == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 5
 
 // list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
 // `list`, whose entries name the particles (segment << 32 | slot).
+// Local start cell of a particle in the staged region and whether it is on chip: gather and
+// deposit touch cells [a-2, a+3] per axis (with dt at most the CFL step the half push moves
+// < 0.36 cells and the deposit path < 0.71 cells, which bounds both the half-step cell
+// a-1..a+1 and, jointly with it, the 4-node Esirkepov window).
+template <int DIM>
+__device__ __forceinline__ bool on_chip(const int c[3], const Region& g, const int n[3],
+                                        int a[3]) {
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) {
+      int v = c[d] - g.r0[d];
+      v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
+      a[d] = v;
+      inside = inside && v >= 2 && v <= g.rw[d] - 4;
+    } else {
+      a[d] = 0;
+    }
+  }
+  return inside;
+}
+
+// 3D rounds with compaction (one particle per thread per round): each thread first reads
+// only its particle's cell and classifies it (on chip / escaped / none); the on-chip
+// particles of the workgroup are then packed into the first threads (their slots pass
+// through LDS) and pushed there, so no wave carries idle lanes for escaped particles; the
+// escaped ones are appended to the escape list with one global reservation per round.
+// cbuf: 2 blockDim + 64 words of LDS.
+template <typename R, int DIM, int ORDER, class LA>
+__device__ __forceinline__ double process_chunk_compact(
+    const RunDesc& r, const SegDesc& s, int seg, const Chunk& ch, const Region& g, const LA& L,
+    int with_rho, bool want_ke, const EscapeList& esc, const unsigned long long* list,
+    int32_t* cbuf) {
+  const int n[3] = {r.nx, r.ny, r.nz};
+  const PushConst<R> k = push_const<R>(r, s);
+  const PartPtrs<R> q = part_ptrs<R>(s, r);
+  const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
+  const int lane = __lane_id(), wv = tid >> 6, nw = bd >> 6;
+  int32_t* cin = cbuf;                 // slots of the on-chip particles, packed
+  int32_t* cesc = cbuf + bd;           // slots of the escaped ones, packed
+  int32_t* wsum = cbuf + 2 * bd;       // per wave: on-chip and escaped counts -> bases;
+                                       // [2 nw], [2 nw + 1]: totals; [2 nw + 2]: list base
+  double ke = 0.0;
+  for (int32_t base = ch.beg; base < ch.end; base += bd) {
+    const int32_t lp = base + tid;
+    const bool ok = lp < ch.end;
+    int32_t slot = lp;
+    if (list && ok) slot = (int32_t)(gp(list)[lp] & 0xffffffffull);
+    bool alive = false;
+    int c[3] = {0, 0, 0};
+    if (ok) alive = load_cell<R, DIM>(q, slot, c);
+    int a[3];
+    const bool inside = alive && on_chip<DIM>(c, g, n, a);
+    const bool gone = alive && !inside;
+    const uint64_t mi = __ballot(inside), me = __ballot(gone);
+    const uint64_t below = (1ull << lane) - 1ull;
+    __syncthreads();                   // the previous round has read cin / cesc / wsum
+    if (lane == 0) {
+      wsum[wv] = __popcll(mi);
+      wsum[nw + wv] = __popcll(me);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int ti = 0, te = 0;
+      for (int w = 0; w < nw; ++w) {
+        const int vi = wsum[w], ve = wsum[nw + w];
+        wsum[w] = ti;
+        wsum[nw + w] = te;
+        ti += vi;
+        te += ve;
+      }
+      wsum[2 * nw] = ti;
+      wsum[2 * nw + 1] = te;
+      wsum[2 * nw + 2] = te ? (int32_t)atomicAdd(esc.count, (unsigned int)te) : 0;
+    }
+    __syncthreads();
+    if (inside) cin[wsum[wv] + __popcll(mi & below)] = slot;
+    if (gone) cesc[wsum[nw + wv] + __popcll(me & below)] = slot;
+    __syncthreads();
+    const int n_in = wsum[2 * nw], n_esc = wsum[2 * nw + 1];
+    const int64_t ebase = (int64_t)(uint32_t)wsum[2 * nw + 2];
+    for (int e = tid; e < n_esc; e += bd)
+      if (ebase + e < esc.capacity)
+        esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)cesc[e];
+    if (tid < n_in) {
+      const int32_t p = cin[tid];
+      PState<R> ps;
+      load_particle<R, DIM>(q, p, ps);
+      int b[3];
+      (void)on_chip<DIM>(ps.c, g, n, b);
+      int pcell[3];
+      R po[3], pe[3], x1[3], vz1, g1;
+      push<DIM, ORDER>(L, b, ps, k, pcell, po, pe, x1, vz1, g1);
+      deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
+      if (leaves_box(r, ps.c[0])) ps.alive = false;
+      store_particle<R, DIM>(q, p, ps);
+      if (want_ke && ps.alive) {   // diagnostic steps only
+        const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] +
+                          (double)ps.u[2] * ps.u[2];
+        ke += (double)ps.w * u2 / (1.0 + (double)g1);
+      }
+    }
+  }
+  return ke * s.m;
+}
+
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
                                                 const Chunk& ch, const Region& g,
                                                 const LA& L, int with_rho,
                                                 bool want_ke, const EscapeList& esc,
-                                                const unsigned long long* list) {
+                                                const unsigned long long* list,
+                                                int32_t* cbuf) {
+  if constexpr (DIM == 3)
+    return process_chunk_compact<R, DIM, ORDER>(r, s, seg, ch, g, L, with_rho, want_ke, esc,
+                                                list, cbuf);
+  (void)cbuf;
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
   const PartPtrs<R> q = part_ptrs<R>(s, r);
@@ -170,23 +283,8 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
     }
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
-      bool inside = ok[b] && ps[b].alive;
       int a[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d < DIM) {
-          // local start cell a; gather and deposit touch cells [a-2, a+3] per axis: with
-          // dt at most the CFL step the half push moves < 0.36 cells and the deposit path
-          // < 0.71 cells, which bounds both the half-step cell (a-1..a+1) and, jointly with
-          // it, the 4-node Esirkepov window
-          int v = ps[b].c[d] - g.r0[d];
-          v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
-          a[d] = v;
-          inside = inside && v >= 2 && v <= g.rw[d] - 4;
-        } else {
-          a[d] = 0;
-        }
-      }
+      const bool inside = ok[b] && ps[b].alive && on_chip<DIM>(ps[b].c, g, n, a);
       escape_append(esc, ok[b] && ps[b].alive && !inside, seg, pi[b]);
       if (!inside) continue;
       int pcell[3];
@@ -274,6 +372,8 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
   // the current planes follow the six field planes; 6 plane values of 4 or 8 bytes end on an
   // 8-byte boundary, as the 64-bit LDS atomics need
   double* jm = (double*)(sm + 6 * plane);
+  // 3D: the round compaction's slot lists after the current (and charge) planes
+  int32_t* cbuf = (int32_t*)(jm + (size_t)(3 + (with_rho ? 2 : 0)) * plane);
   LdsAcc<R, ST, DIM == 2> L;
   L.fbase = sm;
   L.jbase = jm;
@@ -318,8 +418,8 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
     ke += s.order == 1
-              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list)
-              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list);
+              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list, cbuf)
+              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list, cbuf);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
@@ -493,7 +593,11 @@ size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int
   // two charge planes)
   const int jplanes = 3 + (with_rho ? 2 : 0);
   static_assert((6 * sizeof(float)) % 8 == 0, "current planes must start 8-byte aligned");
-  return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8;
+  // 3D: the round compaction's two slot lists and wave sums (process_chunk_compact)
+  const size_t compact = dim == 3 ? (2 * (size_t)(prec == 0 ? fused_block<float, 3>()
+                                                             : fused_block<double, 3>()) + 64) * 4
+                                  : 0;
+  return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8 + compact;
 }
 
 }  // namespace lpic
