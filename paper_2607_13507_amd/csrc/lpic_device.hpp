@@ -236,10 +236,13 @@ struct GlobalAcc {
 
 // Strides of the staged region (tile + halo).  Fixed strides are compile-time constants, so
 // every stencil offset folds into the immediate offset of the LDS instruction; dynamic
-// strides serve any other tiling.
-template <int RW, int RH, int RD>
+// strides serve any other tiling.  PZ pads each z layer: with RW * RH a multiple of the LDS
+// bank count, every z layer of a 3D region maps onto the same banks, and the 64 lanes of a
+// wave (particles spread over one tile) fall on a fraction of them; a pad of a few entries
+// spreads the layers over the banks.
+template <int RW, int RH, int RD, int PZ = 0>
 struct FixStrides {
-  static constexpr int kSy = RW, kSz = RW * RH, kPlane = RW * RH * RD;
+  static constexpr int kSy = RW, kSz = RW * RH + PZ, kPlane = (RW * RH + PZ) * RD;
   __device__ __forceinline__ constexpr int sy() const { return kSy; }
   __device__ __forceinline__ constexpr int sz() const { return kSz; }
   __device__ __forceinline__ constexpr int plane() const { return kPlane; }
@@ -977,13 +980,14 @@ __device__ __forceinline__ void store_particle(const SegDesc& s, const RunDesc& 
 //   x1      the new position x^{n+1} (the path midpoint), relative to the start cell.
 // The deposited path is the trajectory over one dt centred on the end of the step
 // (Sec. 3.1 with the time levels of Eq. 3), so vz1 = v_z^{n+1} is the 2D Jz velocity.
-template <int DIM, int ORDER, typename R, class Acc>
-__device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
-                                     const PushConst<R>& k, int pc[3], R po[3], R pe[3],
-                                     R x1[3], R& vz1, R& gamma1) {
+// The first half push: xh = x^{n+1/2} relative to the start cell, and the same point as
+// (cell pc in the frame whose start cell is a[], offset po in [0,1)).
+template <int DIM, typename R>
+__device__ __forceinline__ void half_push(const int* a, const PState<R>& ps,
+                                          const PushConst<R>& k, int pc[3], R po[3],
+                                          R xh[3]) {
   const R ig0 = rsq<R>(R(1) + ps.u[0] * ps.u[0] + ps.u[1] * ps.u[1] + ps.u[2] * ps.u[2]);
   const R hd[3] = {k.hdx, k.hdy, k.hdz};
-  R xh[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < DIM) {
@@ -995,6 +999,59 @@ __device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
       xh[d] = R(0); pc[d] = 0; po[d] = R(0);
     }
   }
+}
+
+// Whether every node the gather at (pc, po) reads lies in [0, lim] on every axis.  Per axis
+// the integer-lattice weights sit on [pc + up - 1, pc + up + 1] (quadratic) or [pc, pc + 1]
+// (CIC), the half-lattice ones on [pc - 1, pc + 1] or [pc - 1 + up, pc + up], up = (po >=
+// 1/2); the union is [pc - 1, pc + 1 + up] or [pc - 1 + up, pc + 1].
+template <int DIM, int ORDER, typename R>
+__device__ __forceinline__ bool gather_fits(const int* pc, const R* po, const int* lim) {
+  bool fit = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int up = po[d] >= R(0.5);
+    const int lo = ORDER == 2 ? pc[d] - 1 : pc[d] - 1 + up;
+    const int hi = ORDER == 2 ? pc[d] + 1 + up : pc[d] + 1;
+    fit = fit && lo >= 0 && hi <= lim[d];
+  }
+  return fit;
+}
+
+// Whether every node the deposit of the path po -> pe (offsets relative to cell pc) touches
+// lies in [0, lim] on every axis.  The window of esk_axis starts at pc + base; its last node
+// (W - 1) carries weight only for a path that changes its nearest node, and deposit() adds
+// nothing there otherwise (exact zeros are skipped), so the nodes touched are
+// [pc + base, pc + base + W - 2 + cross].
+template <int DIM, int ORDER, typename R>
+__device__ __forceinline__ bool deposit_fits(const int* pc, const R* po, const R* pe,
+                                             const int* lim) {
+  bool fit = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    int base, cross;
+    if constexpr (ORDER == 1) {
+      const int c1 = (int)floor_clamped<R>(pe[d], R(-1), R(1));
+      base = c1 < 0 ? c1 : 0;
+      cross = c1 != 0;
+    } else {
+      const int c0 = po[d] >= R(0.5);
+      const int c1 = (int)floor_clamped<R>(pe[d] + R(0.5), R(-1), R(2));
+      base = (c0 < c1 ? c0 : c1) - 1;
+      cross = c0 != c1;
+    }
+    const int lo = pc[d] + base, hi = pc[d] + base + ORDER + cross;   // W - 2 = ORDER
+    fit = fit && lo >= 0 && hi <= lim[d];
+  }
+  return fit;
+}
+
+// The rest of the particle push after half_push: gather at (pc, po), Boris, second half.
+template <int DIM, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void push_rest(const Acc& A, const int* pc, const R* po,
+                                          const R* xh, PState<R>& ps, const PushConst<R>& k,
+                                          R pe[3], R x1[3], R& vz1, R& gamma1) {
+  const R hd[3] = {k.hdx, k.hdy, k.hdz};
   R E[3], B[3];
   gather<DIM, ORDER>(A, pc, po, E, B);
   boris<R>(ps.u, E, B, k.qdt2m);
@@ -1008,6 +1065,15 @@ __device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
   }
   vz1 = ps.u[2] * ig1;
   gamma1 = R(1) / ig1;
+}
+
+template <int DIM, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void push(const Acc& A, const int* a, PState<R>& ps,
+                                     const PushConst<R>& k, int pc[3], R po[3], R pe[3],
+                                     R x1[3], R& vz1, R& gamma1) {
+  R xh[3];
+  half_push<DIM>(a, ps, k, pc, po, xh);
+  push_rest<DIM, ORDER>(A, pc, po, xh, ps, k, pe, x1, vz1, gamma1);
 }
 
 // Global-memory accumulator over a run's field arrays.

@@ -13,20 +13,25 @@ namespace lpic {
 // once.  Workgroups are mapped to chunks so that each XCD (every 8th workgroup) walks a
 // contiguous range of chunks: neighbouring tiles share that XCD's L2.
 // =======================================================================================
-// Region geometries compiled with constant strides: (tile x, y, z, halo).  Geometry 0 is the
-// runtime-stride kernel used for every other tiling.
-struct GeoFix { int tx, ty, tz, halo; };
+// Region geometries compiled with constant strides: (tile x, y, z, halo, z-layer pad).
+// Geometry 0 is the runtime-stride kernel used for every other tiling.  The 3D pads put
+// consecutive z layers 4 (8 x 4 x 4 tiles: a 16 x 12 layer is 192 entries, 3 x 64) or 8
+// (8 x 8 x 4 tiles: 256 entries) banks apart; the 8 x 4 x 4 pad is also the largest whose
+// region, charge planes included, still fits the LDS.
+struct GeoFix { int tx, ty, tz, halo, pz; };
 __host__ __device__ constexpr GeoFix geo_table(int g) {
-  return g == 1 ? GeoFix{16, 16, 1, 5} : g == 2 ? GeoFix{8, 8, 1, 5} : g == 3 ? GeoFix{32, 32, 1, 5}
-       : g == 4 ? GeoFix{16, 16, 1, 4} : g == 5 ? GeoFix{8, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4}
-       : GeoFix{0, 0, 0, 0};
+  return g == 1 ? GeoFix{16, 16, 1, 5, 0} : g == 2 ? GeoFix{8, 8, 1, 5, 0}
+       : g == 3 ? GeoFix{32, 32, 1, 5, 0} : g == 4 ? GeoFix{16, 16, 1, 4, 0}
+       : g == 5 ? GeoFix{8, 4, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4, 8}
+       : GeoFix{0, 0, 0, 0, 0};
 }
 constexpr int NUM_GEO = 7;
 
 template <int DIM, int G>
 struct GeoStrides {
   static constexpr GeoFix f = geo_table(G);
-  using type = FixStrides<f.tx + 2 * f.halo, f.ty + 2 * f.halo, DIM == 3 ? f.tz + 2 * f.halo : 1>;
+  using type = FixStrides<f.tx + 2 * f.halo, f.ty + 2 * f.halo, DIM == 3 ? f.tz + 2 * f.halo : 1,
+                          DIM == 3 ? f.pz : 0>;
 };
 template <int DIM>
 struct GeoStrides<DIM, 0> {
@@ -55,49 +60,81 @@ __device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, 
   return g;
 }
 
-__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, int e) {
+// Region cell e (x fastest over rw[0] x rw[1] x rw[2]): its global index, and its LDS entry
+// li under the strides S (which may pad the z layers).
+template <class S>
+__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, const S& st,
+                                                 int e, int& li) {
   const int lx = e % g.rw[0];
   const int rest = e / g.rw[0];
   const int ly = rest % g.rw[1];
   const int lz = rest / g.rw[1];
+  li = lx + ly * st.sy() + lz * st.sz();
   return ((int64_t)wrapm(g.r0[2] + lz, r.nz) * r.ny + wrapm(g.r0[1] + ly, r.ny)) * r.nx +
          wrapm(g.r0[0] + lx, r.nx);
 }
 
-// Stage E and B of the region, clear its current (and charge) planes.
-template <typename R>
-__device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, int plane,
+// Stage E and B of the region, clear its current (and charge) planes.  Each thread takes
+// up to STAGE_BATCH region cells per pass and issues all their loads before the first LDS
+// write, so a tile change costs about one memory latency rather than one per cell (a 3D
+// region of 2304 cells is 2.25 cells per thread of a 1024-thread workgroup).
+constexpr int STAGE_BATCH = 4;
+
+template <typename R, class S>
+__device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, const S& st,
                                              int njplanes, R* sm, double* jm, bool paired) {
   gptr<R> F[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = gp((R*)r.f[c]);
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int64_t gi = region_global(r, g, e);
-    if (paired) {   // 2D: (Ex,By) pairs, (Ey,Bx) pairs, Ez, Bz
-      sm[2 * e] = F[F_EX][gi];
-      sm[2 * e + 1] = F[F_BY][gi];
-      sm[2 * (plane + e)] = F[F_EY][gi];
-      sm[2 * (plane + e) + 1] = F[F_BX][gi];
-      sm[4 * plane + e] = F[F_EZ][gi];
-      sm[5 * plane + e] = F[F_BZ][gi];
-    } else {
+  const int bd = (int)blockDim.x;
+  const int plane = st.plane();
+  const int ncell = g.rw[0] * g.rw[1] * g.rw[2];
+  for (int e0 = threadIdx.x; e0 < ncell; e0 += STAGE_BATCH * bd) {
+    R v[STAGE_BATCH][6];
+    int li[STAGE_BATCH];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sm[c * plane + e] = F[c][gi];
+    for (int k = 0; k < STAGE_BATCH; ++k) {
+      const int e = e0 + k * bd;
+      if (e < ncell) {
+        const int64_t gi = region_global(r, g, st, e, li[k]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[k][c] = F[c][gi];
+      }
     }
-    for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
+#pragma unroll
+    for (int k = 0; k < STAGE_BATCH; ++k) {
+      if (e0 + k * bd < ncell) {
+        const int e = li[k];
+        if (paired) {   // 2D: (Ex,By) pairs, (Ey,Bx) pairs, Ez, Bz
+          sm[2 * e] = v[k][F_EX];
+          sm[2 * e + 1] = v[k][F_BY];
+          sm[2 * (plane + e)] = v[k][F_EY];
+          sm[2 * (plane + e) + 1] = v[k][F_BX];
+          sm[4 * plane + e] = v[k][F_EZ];
+          sm[5 * plane + e] = v[k][F_BZ];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sm[c * plane + e] = v[k][c];
+        }
+        for (int c = 0; c < njplanes; ++c) jm[c * plane + e] = 0.0;
+      }
+    }
   }
 }
 
 // Add the region's current (and charge) into the global arrays: one atomic per non-zero
 // entry, converted to the field precision (FP32 path: from fixed point, times 2^-S).
-template <typename R>
-__device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, int plane,
+template <typename R, class S>
+__device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, const S& st,
                                              int njplanes, const double* jm, double unscale) {
   gptr<R> F[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int64_t gi = region_global(r, g, e);
+  const int plane = st.plane();
+  const int ncell = g.rw[0] * g.rw[1] * g.rw[2];
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    int e;
+    const int64_t gi = region_global(r, g, st, i, e);
     for (int c = 0; c < njplanes; ++c) {
       double v;
       if constexpr (sizeof(R) == 4) v = (double)((const long long*)jm)[c * plane + e] * unscale;
@@ -145,10 +182,11 @@ constexpr int fused_block() { return DIM == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 5
 
 // list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
 // `list`, whose entries name the particles (segment << 32 | slot).
-// Local start cell of a particle in the staged region and whether it is on chip: gather and
-// deposit touch cells [a-2, a+3] per axis (with dt at most the CFL step the half push moves
-// < 0.36 cells and the deposit path < 0.71 cells, which bounds both the half-step cell
-// a-1..a+1 and, jointly with it, the 4-node Esirkepov window).
+// Local start cell a of a particle in the staged region, and whether it can be on chip: a
+// particle that stays in its cell for the half push and keeps its nearest node reads and
+// adds cells [a-1, a+2] per axis, so a must lie in [1, rw-3].  The exact test follows once
+// the particle's own half-step position and path are known (gather_fits, deposit_fits): a
+// fast particle near the edge of the region may still need the cells beyond.
 template <int DIM>
 __device__ __forceinline__ bool on_chip(const int c[3], const Region& g, const int n[3],
                                         int a[3]) {
@@ -159,12 +197,60 @@ __device__ __forceinline__ bool on_chip(const int c[3], const Region& g, const i
       int v = c[d] - g.r0[d];
       v = v < 0 ? v + n[d] : (v >= n[d] ? v - n[d] : v);
       a[d] = v;
-      inside = inside && v >= 2 && v <= g.rw[d] - 4;
+      inside = inside && v >= 1 && v <= g.rw[d] - 3;
     } else {
       a[d] = 0;
     }
   }
   return inside;
+}
+
+// Whether start cell a lies at least two cells inside the staged region on every axis:
+// then, whatever the particle's momentum, its gather stencil and deposit window fit (with
+// dt below the CFL step a particle moves less than half a cell per axis in a half push, so
+// the stencil lies in [a-2, a+2] and the window in [a-2, a+3]), and the exact tests can be
+// skipped for a wave whose particles all start there.
+template <int DIM>
+__device__ __forceinline__ bool deep_inside(const int a[3], const Region& g) {
+  bool deep = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) deep = deep && a[d] >= 2 && a[d] <= g.rw[d] - 4;
+  return deep;
+}
+
+// Push and deposit one particle against the staged region if its gather stencil and its
+// deposit window both lie inside it (the particle is stored); false otherwise (nothing is
+// written and the particle's stored state is unchanged: it escapes to a later pass).
+// check: false when every particle of the wave starts deep inside the region (a uniform
+// value, so the tests are branched over rather than evaluated).
+template <typename R, int DIM, int ORDER, class LA>
+__device__ __forceinline__ bool push_on_chip(const RunDesc& r, const Region& g, const LA& L,
+                                             const int n[3], const int a[3], PState<R>& ps,
+                                             const PushConst<R>& k, const PartPtrs<R>& q,
+                                             int32_t slot, int with_rho, bool want_ke,
+                                             double& ke, bool check) {
+  const int lim[3] = {g.rw[0] - 1, g.rw[1] - 1, g.rw[2] - 1};
+  int pcell[3];
+  R po[3], xh[3];
+  half_push<DIM>(a, ps, k, pcell, po, xh);
+  bool fit = true;
+  if (check) fit = gather_fits<DIM, ORDER>(pcell, po, lim);
+  if (!fit) return false;
+  R pe[3], x1[3], vz1, g1;
+  push_rest<DIM, ORDER>(L, pcell, po, xh, ps, k, pe, x1, vz1, g1);
+  if (check) fit = deposit_fits<DIM, ORDER>(pcell, po, pe, lim);
+  if (!fit) return false;
+  deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
+  if (leaves_box(r, ps.c[0])) ps.alive = false;
+  store_particle<R, DIM>(q, slot, ps);
+  if (want_ke && ps.alive) {   // diagnostic steps only
+    const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] +
+                      (double)ps.u[2] * ps.u[2];
+    ke += (double)ps.w * u2 / (1.0 + (double)g1);
+  }
+  return true;
 }
 
 // 3D rounds with compaction (one particle per thread per round): each thread first reads
@@ -229,26 +315,19 @@ __device__ __forceinline__ double process_chunk_compact(
     for (int e = tid; e < n_esc; e += bd)
       if (ebase + e < esc.capacity)
         esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)cesc[e];
+    bool late = false;                 // on chip by its cell, not by its own path
+    int32_t p = 0;
     if (tid < n_in) {
-      const int32_t p = cin[tid];
+      p = cin[tid];
       PState<R> ps;
       load_particle<R, DIM>(q, p, ps);
       int b[3];
       (void)on_chip<DIM>(ps.c, g, n, b);
-      int pcell[3];
-      R po[3], pe[3], x1[3], vz1, g1;
-      push<DIM, ORDER>(L, b, ps, k, pcell, po, pe, x1, vz1, g1);
-      deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
-      if (leaves_box(r, ps.c[0])) ps.alive = false;
-      store_particle<R, DIM>(q, p, ps);
-      if (want_ke && ps.alive) {   // diagnostic steps only
-        const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] +
-                          (double)ps.u[2] * ps.u[2];
-        ke += (double)ps.w * u2 / (1.0 + (double)g1);
-      }
+      // always tested: skipping the tests for deep waves costs the 3D body a spilled register
+      late = !push_on_chip<R, DIM, ORDER>(r, g, L, n, b, ps, k, q, p, with_rho, want_ke, ke,
+                                          true);
     }
+    escape_append(esc, late, seg, p);
   }
   return ke * s.m;
 }
@@ -284,22 +363,14 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
       int a[3];
-      const bool inside = ok[b] && ps[b].alive && on_chip<DIM>(ps[b].c, g, n, a);
-      escape_append(esc, ok[b] && ps[b].alive && !inside, seg, pi[b]);
-      if (!inside) continue;
-      int pcell[3];
-      R po[3], pe[3], x1[3], vz1, g1;
-      push<DIM, ORDER>(L, a, ps[b], k, pcell, po, pe, x1, vz1, g1);
-      deposit<DIM, ORDER>(L, pcell, po, pe, ps[b].w, vz1, k, with_rho != 0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) advance_cell<R>(ps[b].c[d], ps[b].o[d], x1[d], n[d]);
-      if (leaves_box(r, ps[b].c[0])) ps[b].alive = false;
-      store_particle<R, DIM>(q, pi[b], ps[b]);
-      if (want_ke && ps[b].alive) {   // diagnostic steps only
-        const double u2 = (double)ps[b].u[0] * ps[b].u[0] + (double)ps[b].u[1] * ps[b].u[1] +
-                          (double)ps[b].u[2] * ps[b].u[2];
-        ke += (double)ps[b].w * u2 / (1.0 + (double)g1);
-      }
+      const bool live = ok[b] && ps[b].alive;
+      const bool in = live && on_chip<DIM>(ps[b].c, g, n, a);
+      const bool check = __ballot(in && !deep_inside<DIM>(a, g)) != 0;
+      bool done = false;
+      if (in)
+        done = push_on_chip<R, DIM, ORDER>(r, g, L, n, a, ps[b], k, q, pi[b], with_rho,
+                                           want_ke, ke, check);
+      escape_append(esc, live && !done, seg, pi[b]);
     }
   }
   return ke * s.m;
@@ -395,7 +466,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
       if (cur_run >= 0) {
         const RunDesc& rp = run_of(T, cur_run);
         __syncthreads();
-        flush_region<R>(rp, g, plane, njplanes, jm, unscale);
+        flush_region<R>(rp, g, st, njplanes, jm, unscale);
         if (kinetic || ke_to_diag) {
           const double t = block_sum(ke, red);
           if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rp.diag + DIAG_UKIN : kinetic, t);
@@ -410,7 +481,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
       const RunDesc rn = run_of(T, s.run);
       g = region_of<DIM>(rn, s, ch.tile);
       __syncthreads();
-      stage_region<R>(rn, g, plane, njplanes, sm, jm, DIM == 2);
+      stage_region<R>(rn, g, st, njplanes, sm, jm, DIM == 2);
       __syncthreads();
       cur_run = s.run;
       cur_tile = ch.tile;
@@ -423,7 +494,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
-  flush_region<R>(rl, g, plane, njplanes, jm, unscale);
+  flush_region<R>(rl, g, st, njplanes, jm, unscale);
   if (kinetic || ke_to_diag) {
     const double t = block_sum(ke, red);
     if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rl.diag + DIAG_UKIN : kinetic, t);
@@ -587,7 +658,10 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
 }
 
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
-  const size_t plane = (size_t)(tx + 2 * halo) * (ty + 2 * halo) * (dim == 3 ? (tz + 2 * halo) : 1);
+  // the z layers of a fixed 3D geometry are padded (GeoFix::pz)
+  const int pz = dim == 3 ? geo_table(fused_geometry(dim, tx, ty, tz, halo)).pz : 0;
+  const size_t plane = ((size_t)(tx + 2 * halo) * (ty + 2 * halo) + pz) *
+                       (dim == 3 ? (tz + 2 * halo) : 1);
   // six field planes in the kernel precision (24 or 48 bytes per cell: the current planes
   // after them start 8-byte aligned), then 8-byte current planes (and, on diagnostic steps,
   // two charge planes)

@@ -379,3 +379,56 @@ def test_fused_window_edges(prec, ndim, order, halo):
     orc.push_deposit(o)
     compare_particles(grid, cur, o, prec, what="edge push")
     compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"), what="edge deposit")
+
+
+@pytest.mark.parametrize("halo", [3, 4])
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("prec", [L.F64_ABS, L.F32_CELLOFS], ids=["f64", "f32"])
+def test_fused_exact_fit_edges(prec, ndim, order, halo):
+    """Particles placed after the sort on the first and last cells a particle can start from
+    and still be on chip (h - 1 below its tile, h - 2 above it: region cells 1 and rw - 3),
+    at random offsets, with momenta from slow (|u| ~ 0.01) to ultra-relativistic (|u| ~ 20)
+    along every axis: the slow ones stay on chip, the fast ones' gather stencil or deposit
+    window leaves the staged region and they escape to the global-memory path; either way
+    the results must equal the oracle's (and nothing outside the region is touched)."""
+    banner(f"fused exact fit edges prec={PNAME[prec]} ndim={ndim} order={order} halo={halo}")
+    if prec == L.F64_ABS and ndim == 3 and halo == 4:
+        pytest.skip("FP64 3D region with halo 4 does not fit the LDS at this tile")
+    wl = small_2d(order) if ndim == 2 else small_3d(order)
+    T = (16, 8, 1) if ndim == 2 else (8, 4, 4)
+    tiling = L.Tiling(*T, halo, 61, 0)
+    grid, F, d0, cur, offs, orc = _sorted_state(wl, prec, tiling)
+    o = orc.species[0]
+    pos = cur.positions(grid)
+    h = (grid.dx, grid.dy, grid.dz)
+    n = (grid.nx, grid.ny, grid.nz)
+    rng = np.random.default_rng(11 + halo + 3 * order + 7 * ndim)
+    side = rng.integers(0, 2, (ndim, cur.n))
+    speed = 10.0 ** rng.uniform(-2, 1.3, cur.n)        # |u| from 0.01 to 20
+    new, u = [], []
+    for a in range(ndim):
+        cell = np.floor(pos[a] / h[a]).astype(np.int64)
+        t0 = (cell // T[a]) * T[a]
+        c = np.where(side[a] == 0, t0 - (halo - 1), t0 + T[a] - 1 + (halo - 2))
+        new.append(np.mod((c + rng.random(cur.n)) * h[a], n[a] * h[a]))
+        u.append(speed * rng.uniform(-1, 1, cur.n))
+    cur.load_positions(grid, *new, *([None] * (3 - ndim)))
+    for a, k in enumerate(("ux", "uy", "uz")[:ndim]):
+        cur.a[k].copy_(torch.from_numpy(u[a]).to(cur.a[k].dtype))
+    pos = cur.positions(grid)
+    o.x[:], o.y[:] = pos[0], pos[1]
+    if ndim == 3:
+        o.z[:] = pos[2]
+    for k in ("ux", "uy", "uz", "w"):
+        getattr(o, k)[:] = cur.numpy(k)
+    wsb = L.lpic_fused_ws_bytes(grid, tiling, cur.n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    L.lpic_push_deposit_fused(grid, F.struct(), cur.struct(), tiling, offs.data_ptr(),
+                              ws.data_ptr(), wsb, 1, None, prec)
+    torch.cuda.synchronize()
+    orc.zero_currents()
+    orc.push_deposit(o)
+    compare_particles(grid, cur, o, prec, what="exact-fit edge push")
+    compare_fields(F, orc, prec, keys=("jx", "jy", "jz", "rho0", "rho1"),
+                   what="exact-fit edge deposit")

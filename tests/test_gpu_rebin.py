@@ -41,10 +41,10 @@ def test_rebin_2d_matches_oracle(prec, graph):
     wl = W.thermal_2d(nx=64, ny=64, ppc=16, T=0.1, order=2, seed=41)
     sim = Simulation(wl, prec=prec, tiling=(8, 8, 1), halo=3, chunk=256, sort_interval=40,
                      diag_interval=1, use_graph=graph, flags=L.ESCAPE_REBIN)
-    sim.step(5)                  # the first step sorts; then particles drift off their tiles
+    sim.step(10)                 # the first step sorts; then particles drift off their tiles
     torch.cuda.synchronize()
     orc = _oracle_like(sim, wl)
-    orc.nstep = 5
+    orc.nstep = 10
     e0 = sim.stats()["halo_escapes"]
     nsteps = 12 if prec == L.F64_ABS else 4
     for _ in range(nsteps):
