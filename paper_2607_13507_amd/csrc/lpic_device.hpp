@@ -246,12 +246,17 @@ struct FixStrides {
   __device__ __forceinline__ constexpr int sy() const { return kSy; }
   __device__ __forceinline__ constexpr int sz() const { return kSz; }
   __device__ __forceinline__ constexpr int plane() const { return kPlane; }
+  // region extents along x and y (cells)
+  __device__ __forceinline__ constexpr int ex() const { return RW; }
+  __device__ __forceinline__ constexpr int ey() const { return RH; }
 };
 struct DynStrides {
-  int sy_, sz_, plane_;
+  int sy_, sz_, plane_, ey_;
   __device__ __forceinline__ int sy() const { return sy_; }
   __device__ __forceinline__ int sz() const { return sz_; }
   __device__ __forceinline__ int plane() const { return plane_; }
+  __device__ __forceinline__ int ex() const { return sy_; }
+  __device__ __forceinline__ int ey() const { return ey_; }
 };
 
 // LDS accessor of a staged region: the six field planes in the kernel's precision, and the

@@ -60,18 +60,46 @@ __device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, 
   return g;
 }
 
-// Region cell e (x fastest over rw[0] x rw[1] x rw[2]): its global index, and its LDS entry
-// li under the strides S (which may pad the z layers).
+// The periodic wrap of a staged region (uniform per tile): the wrapped origin per axis,
+// and whether some extent exceeds its box's (then a full modulo per cell, else one
+// conditional subtraction).
+struct RegionWrap {
+  int o[3], n[3];
+  bool wide;
+};
+
+__device__ __forceinline__ RegionWrap region_wrap(const RunDesc& r, const Region& g) {
+  RegionWrap w;
+  w.n[0] = r.nx; w.n[1] = r.ny; w.n[2] = r.nz;
+  w.wide = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    w.o[d] = wrapm(g.r0[d], w.n[d]);
+    w.wide = w.wide || g.rw[d] > w.n[d];
+  }
+  return w;
+}
+
+// Region cell e (x fastest over the region's extents): its global index, and its LDS entry
+// li under the strides S (which may pad the z layers).  With the extents of a fixed
+// geometry the decomposition divides by constants.
 template <class S>
-__device__ __forceinline__ int64_t region_global(const RunDesc& r, const Region& g, const S& st,
-                                                 int e, int& li) {
-  const int lx = e % g.rw[0];
-  const int rest = e / g.rw[0];
-  const int ly = rest % g.rw[1];
-  const int lz = rest / g.rw[1];
+__device__ __forceinline__ int64_t region_cell(const RegionWrap& w, const S& st, int e,
+                                               int& li) {
+  const int lx = e % st.ex();
+  const int rest = e / st.ex();
+  const int ly = rest % st.ey();
+  const int lz = rest / st.ey();
   li = lx + ly * st.sy() + lz * st.sz();
-  return ((int64_t)wrapm(g.r0[2] + lz, r.nz) * r.ny + wrapm(g.r0[1] + ly, r.ny)) * r.nx +
-         wrapm(g.r0[0] + lx, r.nx);
+  int gx = w.o[0] + lx, gy = w.o[1] + ly, gz = w.o[2] + lz;
+  if (w.wide) {
+    gx %= w.n[0]; gy %= w.n[1]; gz %= w.n[2];
+  } else {
+    gx -= gx >= w.n[0] ? w.n[0] : 0;
+    gy -= gy >= w.n[1] ? w.n[1] : 0;
+    gz -= gz >= w.n[2] ? w.n[2] : 0;
+  }
+  return ((int64_t)gz * w.n[1] + gy) * w.n[0] + gx;
 }
 
 // Stage E and B of the region, clear its current (and charge) planes.  Each thread takes
@@ -89,6 +117,7 @@ __device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, 
   const int bd = (int)blockDim.x;
   const int plane = st.plane();
   const int ncell = g.rw[0] * g.rw[1] * g.rw[2];
+  const RegionWrap w = region_wrap(r, g);
   for (int e0 = threadIdx.x; e0 < ncell; e0 += STAGE_BATCH * bd) {
     R v[STAGE_BATCH][6];
     int li[STAGE_BATCH];
@@ -96,7 +125,7 @@ __device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, 
     for (int k = 0; k < STAGE_BATCH; ++k) {
       const int e = e0 + k * bd;
       if (e < ncell) {
-        const int64_t gi = region_global(r, g, st, e, li[k]);
+        const int64_t gi = region_cell(w, st, e, li[k]);
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[k][c] = F[c][gi];
       }
@@ -132,9 +161,10 @@ __device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, 
   for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
   const int plane = st.plane();
   const int ncell = g.rw[0] * g.rw[1] * g.rw[2];
+  const RegionWrap w = region_wrap(r, g);
   for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
     int e;
-    const int64_t gi = region_global(r, g, st, i, e);
+    const int64_t gi = region_cell(w, st, i, e);
     for (int c = 0; c < njplanes; ++c) {
       double v;
       if constexpr (sizeof(R) == 4) v = (double)((const long long*)jm)[c * plane + e] * unscale;
@@ -437,6 +467,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
     st.sy_ = rw;
     st.sz_ = rw * rh;
     st.plane_ = rw * rh * rd;
+    st.ey_ = rh;
   }
   const int plane = st.plane();
   const int njplanes = 3 + (with_rho ? 2 : 0);
