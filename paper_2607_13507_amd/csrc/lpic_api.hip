@@ -949,6 +949,17 @@ lpic_status configure(lpic_sim* s) {
     rb.esc2.count = s->esc2_count;
     rb.esc2.total = (unsigned long long*)((char*)s->esc2_count + 64);
     rb.esc2.capacity = s->esc_capacity;
+    // second pass: the re-binned particles lie inside their present tile, so a 3D FP32
+    // 8 x 4 x 4 tiling with halo 4 runs it on the halo-3 geometry, two workgroups per CU
+    const bool small = s->prec == LPIC_F32_CELLOFS && s->ndim == 3 && s->geo == 5;
+    rb.geo = small ? fused_geometry(3, 8, 4, 4, 3) : s->geo;
+    rb.smem[0] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 0) : s->smem;
+    rb.smem[1] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 1) : s->smem_rho;
+    int bpc[2] = {1, 1};
+    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo, rb.smem[1], rb.smem[1], &bpc[1]));
+    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo, rb.smem[1], rb.smem[0], &bpc[0]));
+    rb.grid[0] = fused_grid(maxch, bpc[0]);
+    rb.grid[1] = fused_grid(maxch, bpc[1]);
     s->rebin = true;
   }
   s->need_sort = true;

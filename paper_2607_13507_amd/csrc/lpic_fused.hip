@@ -17,15 +17,18 @@ namespace lpic {
 // Geometry 0 is the runtime-stride kernel used for every other tiling.  The 3D pads put
 // consecutive z layers 4 (8 x 4 x 4 tiles: a 16 x 12 layer is 192 entries, 3 x 64) or 8
 // (8 x 8 x 4 tiles: 256 entries) banks apart; the 8 x 4 x 4 pad is also the largest whose
-// region, charge planes included, still fits the LDS.
+// region, charge planes included, still fits the LDS.  Geometry 7 (8 x 4 x 4 tiles, halo 3)
+// runs 512-thread workgroups, two per CU: it is also the second pass of the re-binned
+// escape path for 8 x 4 x 4 tilings with halo 4 (its particles lie inside their present
+// tile, so a halo of 3 always holds their stencils).
 struct GeoFix { int tx, ty, tz, halo, pz; };
 __host__ __device__ constexpr GeoFix geo_table(int g) {
   return g == 1 ? GeoFix{16, 16, 1, 5, 0} : g == 2 ? GeoFix{8, 8, 1, 5, 0}
        : g == 3 ? GeoFix{32, 32, 1, 5, 0} : g == 4 ? GeoFix{16, 16, 1, 4, 0}
        : g == 5 ? GeoFix{8, 4, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4, 8}
-       : GeoFix{0, 0, 0, 0, 0};
+       : g == 7 ? GeoFix{8, 4, 4, 3, 8} : GeoFix{0, 0, 0, 0, 0};
 }
-constexpr int NUM_GEO = 7;
+constexpr int NUM_GEO = 8;
 
 template <int DIM, int G>
 struct GeoStrides {
@@ -45,7 +48,8 @@ struct Region {
 };
 
 template <int DIM>
-__device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, int tile) {
+__device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, int tile,
+                                            int halo) {
   Region g;
   const int TXs[3] = {1 << s.lx, 1 << s.ly, DIM == 3 ? (1 << s.lz) : 1};
   int tc[3];
@@ -54,7 +58,7 @@ __device__ __forceinline__ Region region_of(const RunDesc& r, const SegDesc& s, 
   tc[2] = tile / r.nty;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (d < DIM) { g.r0[d] = tc[d] * TXs[d] - s.halo; g.rw[d] = TXs[d] + 2 * s.halo; }
+    if (d < DIM) { g.r0[d] = tc[d] * TXs[d] - halo; g.rw[d] = TXs[d] + 2 * halo; }
     else { g.r0[d] = 0; g.rw[d] = 1; }
   }
   return g;
@@ -199,16 +203,19 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // In 2D FP64 two: four FP64 states take the registers of a third wave per SIMD.
 template <typename R, int DIM>
 constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 2); }
-// Waves per SIMD the fused kernel's register budget is set for: 2D FP32 fits 4 (at most 128
-// VGPRs), the others keep the compiler's choice.
-template <typename R, int DIM>
-constexpr int fused_waves() { return (sizeof(R) == 4 && DIM == 2) ? 4 : 1; }
+// Waves per SIMD the fused kernel's register budget is set for: 2D FP32 and the two-per-CU
+// 3D FP32 geometry fit 4 (at most 128 VGPRs), the others keep the compiler's choice.
+template <typename R, int DIM, int G>
+constexpr int fused_waves() { return (sizeof(R) == 4 && (DIM == 2 || G == 7)) ? 4 : 1; }
 
 // Threads per workgroup: a 3D region (tile + halo on three axes) fills most of a CU's LDS,
 // so one workgroup per CU must bring enough waves by itself: 16 (four per SIMD) in FP32, whose
 // quadratic particle loop fits 128 VGPRs; 8 in FP64, which needs more registers per lane.
-template <typename R, int DIM>
-constexpr int fused_block() { return DIM == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 512); }
+// Geometry 7's smaller region lets two 512-thread workgroups share a CU.
+template <typename R, int DIM, int G>
+constexpr int fused_block() {
+  return DIM == 2 ? 256 : (G == 7 || sizeof(R) == 8 ? 512 : 1024);
+}
 
 // list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
 // `list`, whose entries name the particles (segment << 32 | slot).
@@ -441,13 +448,13 @@ __device__ __forceinline__ D uniform_copy(const D& src) {
 // the other species of the same box, which follow in the table) reuse the staged region;
 // the region is flushed when the tile changes.
 template <typename R, int DIM, int G>
-__global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM>()))) void k_fused(Tables T, const Chunk* chunks,
+__global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_waves_per_eu(fused_waves<R, DIM, G>()))) void k_fused(Tables T, const Chunk* chunks,
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
                                                EscapeList esc, const int32_t* jshift,
                                                const unsigned long long* list) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[fused_block<R, DIM>() / 64];
+  __shared__ double red[fused_block<R, DIM, G>() / 64];
   R* sm = (R*)smem_raw;
   const int nch = uniform(*nchunks);
   const int nb8 = gridDim.x >> 3;
@@ -510,7 +517,7 @@ __global__ __launch_bounds__((fused_block<R, DIM>())) __attribute__((amdgpu_wave
         unscale = ldexp(1.0, -sh);
       }
       const RunDesc rn = run_of(T, s.run);
-      g = region_of<DIM>(rn, s, ch.tile);
+      g = region_of<DIM>(rn, s, ch.tile, G ? geo_table(G).halo : s.halo);
       __syncthreads();
       stage_region<R>(rn, g, st, njplanes, sm, jm, DIM == 2);
       __syncthreads();
@@ -604,7 +611,7 @@ static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chun
                            const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
                            const EscapeList& esc, const int32_t* jshift,
                            const unsigned long long* list, hipStream_t st) {
-  k_fused<R, D, G><<<nblocks, fused_block<R, D>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
+  k_fused<R, D, G><<<nblocks, fused_block<R, D, G>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
                                                ke_to_diag, esc, jshift, list);
 }
 
@@ -627,6 +634,7 @@ static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
     switch (geo) {
       case 5: LPIC_GEO(5); return;
       case 6: LPIC_GEO(6); return;
+      case 7: LPIC_GEO(7); return;
       default: LPIC_GEO(0); return;
     }
   }
@@ -643,9 +651,10 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
     // escapees by present tile, a second pass over them, then whatever that pass could not
     // place (normally nothing) through global memory
     launch_rebin(T, prec, dim, esc, *rb, st);
-    LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, rb->chunks, rb->nchunks,
-                                             with_rho, kinetic, ke_to_diag, rb->esc2, jshift,
-                                             rb->items, st)));
+    const int k = with_rho ? 1 : 0;
+    LPIC_PD(prec, dim, (launch_fused_d<R, D>(rb->geo, T, rb->grid[k], rb->smem[k], rb->chunks,
+                                             rb->nchunks, with_rho, kinetic, ke_to_diag,
+                                             rb->esc2, jshift, rb->items, st)));
     LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
                            T, with_rho, kinetic, ke_to_diag, esc, rb->threshold)));
     LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
@@ -662,7 +671,7 @@ static hipError_t set_smem(size_t smem, size_t smem_occ, int* blocks_per_cu) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused<R, D, G>,
-                                                      fused_block<R, D>(),
+                                                      fused_block<R, D, G>(),
                                                       smem_occ);
 }
 
@@ -682,6 +691,7 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
     switch (geo) {
       case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, smem_occ, b) : set_smem<double, 3, 5>(smem, smem_occ, b); break;
       case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, smem_occ, b) : set_smem<double, 3, 6>(smem, smem_occ, b); break;
+      case 7: e = prec == 0 ? set_smem<float, 3, 7>(smem, smem_occ, b) : set_smem<double, 3, 7>(smem, smem_occ, b); break;
       default: e = prec == 0 ? set_smem<float, 3, 0>(smem, smem_occ, b) : set_smem<double, 3, 0>(smem, smem_occ, b); break;
     }
   }
@@ -690,7 +700,8 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
 
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
   // the z layers of a fixed 3D geometry are padded (GeoFix::pz)
-  const int pz = dim == 3 ? geo_table(fused_geometry(dim, tx, ty, tz, halo)).pz : 0;
+  const int geo = fused_geometry(dim, tx, ty, tz, halo);
+  const int pz = dim == 3 ? geo_table(geo).pz : 0;
   const size_t plane = ((size_t)(tx + 2 * halo) * (ty + 2 * halo) + pz) *
                        (dim == 3 ? (tz + 2 * halo) : 1);
   // six field planes in the kernel precision (24 or 48 bytes per cell: the current planes
@@ -699,9 +710,9 @@ size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int
   const int jplanes = 3 + (with_rho ? 2 : 0);
   static_assert((6 * sizeof(float)) % 8 == 0, "current planes must start 8-byte aligned");
   // 3D: the round compaction's two slot lists and wave sums (process_chunk_compact)
-  const size_t compact = dim == 3 ? (2 * (size_t)(prec == 0 ? fused_block<float, 3>()
-                                                             : fused_block<double, 3>()) + 64) * 4
-                                  : 0;
+  const int block = geo == 7 ? fused_block<float, 3, 7>()
+                  : prec == 0 ? fused_block<float, 3, 0>() : fused_block<double, 3, 0>();
+  const size_t compact = dim == 3 ? (2 * (size_t)block + 64) * 4 : 0;
   return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8 + compact;
 }
 

@@ -105,6 +105,9 @@ struct Rebin {
   Chunk* chunks;
   int32_t* nchunks;
   EscapeList esc2;             // particles the second pass finds outside its regions
+  int geo;                     // the second pass's geometry (fused_geometry()), its grid and
+  int grid[2];                 // dynamic LDS without / with the charge planes
+  size_t smem[2];
 };
 
 // geometry: 0 = runtime strides, else a compiled (tile, halo) shape (fused_geometry()).
