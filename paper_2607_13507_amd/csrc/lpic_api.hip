@@ -678,6 +678,8 @@ struct lpic_sim {
   bool rebin = false;
   unsigned long long* rb_items = nullptr;     // grouped escape list
   unsigned long long* esc2_items = nullptr;   // the second pass's own escape list
+  void* esc_rec = nullptr;                    // escape records of the list, and grouped
+  void* rb_rec = nullptr;
   unsigned int* esc2_count = nullptr;         // its counters (and a total)
   int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
   int blocks_per_cu_rho = 1;
@@ -928,6 +930,12 @@ lpic_status configure(lpic_sim* s) {
     if (!s->rb_items) {
       ALLOC(s->rb_items, sizeof(unsigned long long) * s->esc_capacity);
       ALLOC(s->esc2_items, sizeof(unsigned long long) * s->esc_capacity);
+      // escape records (3D): 8 values of the kernel precision per entry
+      if (s->ndim == 3) {
+        const size_t rec = 8 * (s->prec == LPIC_F32_CELLOFS ? 4 : 8);
+        ALLOC(s->esc_rec, rec * s->esc_capacity);
+        ALLOC(s->rb_rec, rec * s->esc_capacity);
+      }
       ALLOC(s->esc2_count, 256);
       HIPCHK(hipMemset(s->esc2_count, 0, 256));
     }
@@ -945,6 +953,7 @@ lpic_status configure(lpic_sim* s) {
     rb.chunk = t.chunk;
     rb.count_blocks = (int)std::min<int64_t>(2048, (s->esc_capacity + 2047) / 2048);
     rb.items = s->rb_items;
+    rb.rec = s->rb_rec;
     rb.esc2.items = s->esc2_items;
     rb.esc2.count = s->esc2_count;
     rb.esc2.total = (unsigned long long*)((char*)s->esc2_count + 64);
@@ -1077,6 +1086,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       }
       EscapeList esc;
       esc.items = s->esc_items;
+      esc.rec = s->rebin && s->ndim == 3 ? s->esc_rec : nullptr;   // records: 3D only
       esc.count = s->esc_count;
       esc.total = s->escapes;
       esc.capacity = s->esc_capacity;
@@ -1243,6 +1253,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
   free_dev(s->rb.chunks); free_dev(s->rb.nchunks);
   free_dev(s->rb_items); free_dev(s->esc2_items); free_dev(s->esc2_count);
+  free_dev(s->esc_rec); free_dev(s->rb_rec);
   free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
   free_dev(s->mid_pfx_d); free_dev(s->bands);
   free_dev(s->old_state);

@@ -861,22 +861,35 @@ __device__ __forceinline__ gptr<T> at_byte(gptr<T> base, uint32_t off) {
   return (gptr<T>)((__attribute__((address_space(1))) char*)base + off);
 }
 
-// The cell of particle p only (FP32: the packed cell; FP64: from the absolute position);
-// false for a dead or invalid slot (as load_particle's alive).
+// A particle's array words as stored: FP32 the packed cell and the offsets, FP64 the
+// absolute positions (cell unused); then the momenta and the weight.  Every load of a
+// particle, from its slot or from an escape record, decodes these words the same way.
+template <typename R>
+struct PWords {
+  int32_t cell;
+  R pos[3];
+  R u[3];
+  R w;
+};
+
+// The cell of a particle from its words (FP32: the packed cell; FP64: from the absolute
+// position); false for a dead or invalid slot (as decode_particle's alive).
 template <typename R, int DIM>
-__device__ __forceinline__ bool load_cell(const PartPtrs<R>& q, int32_t p, int c[3]) {
+__device__ __forceinline__ bool decode_cell(const PartPtrs<R>& q, int32_t cell, const R* pos,
+                                            int c[3]) {
   if constexpr (sizeof(R) == 4) {
-    const int32_t cell = *at_byte(q.cell, (uint32_t)p * 4u);
+    (void)pos;
     unpack_cell(cell < 0 ? 0 : cell, DIM, c);
     return cell >= 0 && c[0] < q.nx && c[1] < q.ny && (DIM == 2 || c[2] < q.nz);
   } else {
+    (void)cell;
     const double h[3] = {q.dx, q.dy, q.dz};
     const int n[3] = {q.nx, q.ny, q.nz};
     bool alive = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d < DIM) {
-        const double X = *at_byte(q.pos[d], (uint32_t)p * 8u) / h[d];
+        const double X = pos[d] / h[d];
         if (!(X >= 0.0 && X <= (double)n[d])) alive = false;
         int ci = (int)floor_clamped<double>(X, 0.0, (double)n[d]);
         c[d] = ci >= n[d] ? ci - n[d] : ci;
@@ -889,16 +902,15 @@ __device__ __forceinline__ bool load_cell(const PartPtrs<R>& q, int32_t p, int c
 }
 
 template <typename R, int DIM>
-__device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, PState<R>& ps) {
-  const uint32_t o4 = (uint32_t)p * 4u, oR = (uint32_t)p * (uint32_t)sizeof(R);
+__device__ __forceinline__ void decode_particle(const PartPtrs<R>& q, const PWords<R>& x,
+                                                PState<R>& ps) {
   if constexpr (sizeof(R) == 4) {
-    const int32_t cell = *at_byte(q.cell, o4);
-    unpack_cell(cell < 0 ? 0 : cell, DIM, ps.c);
+    unpack_cell(x.cell < 0 ? 0 : x.cell, DIM, ps.c);
     // a cell outside the box cannot come from the library; treat it like a dead slot
-    ps.alive = cell >= 0 && ps.c[0] < q.nx && ps.c[1] < q.ny && (DIM == 2 || ps.c[2] < q.nz);
-    ps.o[0] = *at_byte(q.pos[0], oR);
-    ps.o[1] = *at_byte(q.pos[1], oR);
-    ps.o[2] = DIM == 3 ? *at_byte(q.pos[2], oR) : 0.f;
+    ps.alive = x.cell >= 0 && ps.c[0] < q.nx && ps.c[1] < q.ny && (DIM == 2 || ps.c[2] < q.nz);
+    ps.o[0] = x.pos[0];
+    ps.o[1] = x.pos[1];
+    ps.o[2] = DIM == 3 ? x.pos[2] : 0.f;
   } else {
     const double h[3] = {q.dx, q.dy, q.dz};
     const int n[3] = {q.nx, q.ny, q.nz};
@@ -906,7 +918,7 @@ __device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, P
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d < DIM) {
-        const double X = *at_byte(q.pos[d], oR) / h[d];
+        const double X = x.pos[d] / h[d];
         // positions outside [0, L] (or NaN) cannot come from the library: dead slot
         if (!(X >= 0.0 && X <= (double)n[d])) ps.alive = false;
         const double f = floor_clamped<double>(X, 0.0, (double)n[d]);
@@ -920,11 +932,127 @@ __device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, P
       }
     }
   }
-  ps.u[0] = *at_byte(q.u[0], oR);
-  ps.u[1] = *at_byte(q.u[1], oR);
-  ps.u[2] = *at_byte(q.u[2], oR);
-  ps.w = *at_byte(q.w, oR);
-  (void)o4;
+  ps.u[0] = x.u[0];
+  ps.u[1] = x.u[1];
+  ps.u[2] = x.u[2];
+  ps.w = x.w;
+}
+
+// The words of slot p from the species' arrays.
+template <typename R, int DIM>
+__device__ __forceinline__ PWords<R> load_words(const PartPtrs<R>& q, int32_t p) {
+  const uint32_t o4 = (uint32_t)p * 4u, oR = (uint32_t)p * (uint32_t)sizeof(R);
+  PWords<R> x;
+  x.cell = sizeof(R) == 4 ? *at_byte(q.cell, o4) : 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x.pos[d] = d < DIM ? *at_byte(q.pos[d], oR) : R(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x.u[d] = *at_byte(q.u[d], oR);
+  x.w = *at_byte(q.w, oR);
+  return x;
+}
+
+// The cell of particle p only; false for a dead or invalid slot.
+template <typename R, int DIM>
+__device__ __forceinline__ bool load_cell(const PartPtrs<R>& q, int32_t p, int c[3]) {
+  R pos[3] = {R(0), R(0), R(0)};
+  int32_t cell = 0;
+  if constexpr (sizeof(R) == 4) {
+    cell = *at_byte(q.cell, (uint32_t)p * 4u);
+  } else {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pos[d] = *at_byte(q.pos[d], (uint32_t)p * 8u);
+  }
+  return decode_cell<R, DIM>(q, cell, pos, c);
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void load_particle(const PartPtrs<R>& q, int32_t p, PState<R>& ps) {
+  decode_particle<R, DIM>(q, load_words<R, DIM>(q, p), ps);
+}
+
+// Escape records: the words of an escaped particle in eight consecutive slots of the kernel's
+// precision (FP32: the packed cell's bits, three offsets, three momenta, the weight; FP64:
+// three positions, three momenta, the weight, one unused slot), so that the re-binned pass
+// reads each particle as one contiguous 32- or 64-byte record instead of eight scattered
+// words.  Unused position slots (2D) hold zero.
+template <typename R>
+struct alignas(8 * sizeof(R)) EscRec {
+  R v[8];
+};
+
+template <typename R>
+__device__ __forceinline__ EscRec<R> rec_of(const PWords<R>& x) {
+  EscRec<R> e;
+  if constexpr (sizeof(R) == 4) {
+    e.v[0] = __int_as_float(x.cell);
+    e.v[1] = x.pos[0]; e.v[2] = x.pos[1]; e.v[3] = x.pos[2];
+  } else {
+    e.v[0] = x.pos[0]; e.v[1] = x.pos[1]; e.v[2] = x.pos[2]; e.v[3] = R(0);
+  }
+  e.v[4] = x.u[0]; e.v[5] = x.u[1]; e.v[6] = x.u[2]; e.v[7] = x.w;
+  return e;
+}
+
+template <typename R>
+__device__ __forceinline__ PWords<R> words_of(const EscRec<R>& e) {
+  PWords<R> x;
+  if constexpr (sizeof(R) == 4) {
+    x.cell = __float_as_int(e.v[0]);
+    x.pos[0] = e.v[1]; x.pos[1] = e.v[2]; x.pos[2] = e.v[3];
+  } else {
+    x.cell = 0;
+    x.pos[0] = e.v[0]; x.pos[1] = e.v[1]; x.pos[2] = e.v[2];
+  }
+  x.u[0] = e.v[4]; x.u[1] = e.v[5]; x.u[2] = e.v[6]; x.w = e.v[7];
+  return x;
+}
+
+// Records move as 16-byte vectors (two per FP32 record, four per FP64 record).
+template <typename R>
+using Rec16 = R __attribute__((ext_vector_type(16 / sizeof(R))));
+
+template <typename R>
+__device__ __forceinline__ void store_rec(void* base, int64_t k, const EscRec<R>& e) {
+  constexpr int NV = (int)(sizeof(EscRec<R>) / 16), L = (int)(16 / sizeof(R));
+  gptr<Rec16<R>> b = gp((Rec16<R>*)base) + k * NV;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    Rec16<R> v;
+#pragma unroll
+    for (int j = 0; j < L; ++j) v[j] = e.v[i * L + j];
+    b[i] = v;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ EscRec<R> load_rec(const void* base, int64_t k) {
+  constexpr int NV = (int)(sizeof(EscRec<R>) / 16), L = (int)(16 / sizeof(R));
+  gptr<const Rec16<R>> b = gp((const Rec16<R>*)base) + k * NV;
+  EscRec<R> e;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const Rec16<R> v = b[i];
+#pragma unroll
+    for (int j = 0; j < L; ++j) e.v[i * L + j] = v[j];
+  }
+  return e;
+}
+
+// The cell from a record only (the first slot in FP32; the positions in FP64).
+template <typename R, int DIM>
+__device__ __forceinline__ bool rec_cell(const PartPtrs<R>& q, const void* base, int64_t k,
+                                         int c[3]) {
+  const R* e = ((const EscRec<R>*)base)[k].v;
+  if constexpr (sizeof(R) == 4) {
+    const R pos[3] = {0.f, 0.f, 0.f};
+    return decode_cell<R, DIM>(q, __float_as_int(*gp(e)), pos, c);
+  } else {
+    R pos[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pos[d] = gp(e)[d];
+    return decode_cell<R, DIM>(q, 0, pos, c);
+  }
 }
 
 template <typename R, int DIM>

@@ -178,8 +178,20 @@ __device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, 
   }
 }
 
+// The second pass of the re-binned escape path: its chunk ranges index `list` (entries
+// segment << 32 | slot) and, when set, `rec` (the same particles' escape records in the same
+// order, read contiguously instead of the particles' scattered slots).
+struct PassList {
+  const unsigned long long* list;
+  const void* rec;
+};
+
+// Append the lanes that want it to the escape list (one reservation per wave), with their
+// escape records when the list keeps them (3D only: the 2D body has no registers to spare
+// for the record's words, and 2D particles rarely leave their regions).
+template <typename R, int DIM>
 __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, int seg,
-                                              int32_t p) {
+                                              int32_t p, const PartPtrs<R>& q) {
   const uint64_t mask = __ballot(want);
   if (!mask) return;
   const int lane = __lane_id();
@@ -189,7 +201,11 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
   base = __shfl(base, leader, 64);
   if (want) {
     const unsigned int k = base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
-    if ((int64_t)k < esc.capacity) esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
+    if ((int64_t)k < esc.capacity) {
+      esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
+      if constexpr (DIM == 3)
+        if (esc.rec) store_rec<R>(esc.rec, k, rec_of(load_words<R, DIM>(q, p)));
+    }
   }
 }
 
@@ -217,8 +233,8 @@ constexpr int fused_block() {
   return DIM == 2 ? 256 : (G == 7 || sizeof(R) == 8 ? 512 : 1024);
 }
 
-// list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
-// `list`, whose entries name the particles (segment << 32 | slot).
+// pl.list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
+// pl.list, whose entries name the particles (segment << 32 | slot), and pl.rec when set.
 // Local start cell a of a particle in the staged region, and whether it can be on chip: a
 // particle that stays in its cell for the half push and keeps its nearest node reads and
 // adds cells [a-1, a+2] per axis, so a must lie in [1, rw-3].  The exact test follows once
@@ -299,14 +315,14 @@ __device__ __forceinline__ bool push_on_chip(const RunDesc& r, const Region& g, 
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk_compact(
     const RunDesc& r, const SegDesc& s, int seg, const Chunk& ch, const Region& g, const LA& L,
-    int with_rho, bool want_ke, const EscapeList& esc, const unsigned long long* list,
-    int32_t* cbuf) {
+    int with_rho, bool want_ke, const EscapeList& esc, const PassList& pl, int32_t* cbuf) {
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
   const PartPtrs<R> q = part_ptrs<R>(s, r);
   const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
   const int lane = __lane_id(), wv = tid >> 6, nw = bd >> 6;
-  int32_t* cin = cbuf;                 // slots of the on-chip particles, packed
+  int32_t* cin = cbuf;                 // the on-chip particles (slots; list indexes when
+                                       // their records are read), packed
   int32_t* cesc = cbuf + bd;           // slots of the escaped ones, packed
   int32_t* wsum = cbuf + 2 * bd;       // per wave: on-chip and escaped counts -> bases;
                                        // [2 nw], [2 nw + 1]: totals; [2 nw + 2]: list base
@@ -315,10 +331,10 @@ __device__ __forceinline__ double process_chunk_compact(
     const int32_t lp = base + tid;
     const bool ok = lp < ch.end;
     int32_t slot = lp;
-    if (list && ok) slot = (int32_t)(gp(list)[lp] & 0xffffffffull);
+    if (pl.list && ok) slot = (int32_t)(gp(pl.list)[lp] & 0xffffffffull);
     bool alive = false;
     int c[3] = {0, 0, 0};
-    if (ok) alive = load_cell<R, DIM>(q, slot, c);
+    if (ok) alive = pl.rec ? rec_cell<R, DIM>(q, pl.rec, lp, c) : load_cell<R, DIM>(q, slot, c);
     int a[3];
     const bool inside = alive && on_chip<DIM>(c, g, n, a);
     const bool gone = alive && !inside;
@@ -344,27 +360,35 @@ __device__ __forceinline__ double process_chunk_compact(
       wsum[2 * nw + 2] = te ? (int32_t)atomicAdd(esc.count, (unsigned int)te) : 0;
     }
     __syncthreads();
-    if (inside) cin[wsum[wv] + __popcll(mi & below)] = slot;
+    if (inside) cin[wsum[wv] + __popcll(mi & below)] = pl.rec ? lp : slot;
     if (gone) cesc[wsum[nw + wv] + __popcll(me & below)] = slot;
     __syncthreads();
     const int n_in = wsum[2 * nw], n_esc = wsum[2 * nw + 1];
     const int64_t ebase = (int64_t)(uint32_t)wsum[2 * nw + 2];
     for (int e = tid; e < n_esc; e += bd)
-      if (ebase + e < esc.capacity)
+      if (ebase + e < esc.capacity) {
         esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)cesc[e];
+        if (esc.rec) store_rec<R>(esc.rec, ebase + e, rec_of(load_words<R, DIM>(q, cesc[e])));
+      }
     bool late = false;                 // on chip by its cell, not by its own path
     int32_t p = 0;
     if (tid < n_in) {
-      p = cin[tid];
+      const int32_t src = cin[tid];
       PState<R> ps;
-      load_particle<R, DIM>(q, p, ps);
+      if (pl.rec) {
+        p = (int32_t)(gp(pl.list)[src] & 0xffffffffull);
+        decode_particle<R, DIM>(q, words_of(load_rec<R>(pl.rec, src)), ps);
+      } else {
+        p = src;
+        load_particle<R, DIM>(q, p, ps);
+      }
       int b[3];
       (void)on_chip<DIM>(ps.c, g, n, b);
       // always tested: skipping the tests for deep waves costs the 3D body a spilled register
       late = !push_on_chip<R, DIM, ORDER>(r, g, L, n, b, ps, k, q, p, with_rho, want_ke, ke,
                                           true);
     }
-    escape_append(esc, late, seg, p);
+    escape_append<R, DIM>(esc, late, seg, p, q);
   }
   return ke * s.m;
 }
@@ -374,11 +398,10 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
                                                 const Chunk& ch, const Region& g,
                                                 const LA& L, int with_rho,
                                                 bool want_ke, const EscapeList& esc,
-                                                const unsigned long long* list,
-                                                int32_t* cbuf) {
+                                                const PassList& pl, int32_t* cbuf) {
   if constexpr (DIM == 3)
     return process_chunk_compact<R, DIM, ORDER>(r, s, seg, ch, g, L, with_rho, want_ke, esc,
-                                                list, cbuf);
+                                                pl, cbuf);
   (void)cbuf;
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
@@ -392,10 +415,11 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
     bool ok[BATCH];
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
-      pi[b] = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
-      ok[b] = pi[b] < ch.end;
-      if (list && ok[b]) pi[b] = (int32_t)(gp(list)[pi[b]] & 0xffffffffull);
-      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);
+      const int32_t lp = base + b * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+      ok[b] = lp < ch.end;
+      pi[b] = lp;
+      if (pl.list && ok[b]) pi[b] = (int32_t)(gp(pl.list)[lp] & 0xffffffffull);
+      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);   // 2D lists carry no records
     }
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
@@ -407,7 +431,7 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
       if (in)
         done = push_on_chip<R, DIM, ORDER>(r, g, L, n, a, ps[b], k, q, pi[b], with_rho,
                                            want_ke, ke, check);
-      escape_append(esc, live && !done, seg, pi[b]);
+      escape_append<R, DIM>(esc, live && !done, seg, pi[b], q);
     }
   }
   return ke * s.m;
@@ -452,7 +476,7 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
                                                const int32_t* nchunks, int with_rho,
                                                double* kinetic, int ke_to_diag,
                                                EscapeList esc, const int32_t* jshift,
-                                               const unsigned long long* list) {
+                                               PassList pl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[fused_block<R, DIM, G>() / 64];
   R* sm = (R*)smem_raw;
@@ -527,8 +551,8 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
     ke += s.order == 1
-              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list, cbuf)
-              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, list, cbuf);
+              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
+              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
@@ -609,19 +633,18 @@ int fused_geometry(int dim, int tx, int ty, int tz, int halo) {
 template <typename R, int D, int G>
 static void launch_fused_g(const Tables& T, int nblocks, size_t smem, const Chunk* chunks,
                            const int32_t* nchunks, int with_rho, double* kinetic, int ke_to_diag,
-                           const EscapeList& esc, const int32_t* jshift,
-                           const unsigned long long* list, hipStream_t st) {
+                           const EscapeList& esc, const int32_t* jshift, PassList pl,
+                           hipStream_t st) {
   k_fused<R, D, G><<<nblocks, fused_block<R, D, G>(), smem, st>>>(T, chunks, nchunks, with_rho, kinetic,
-                                               ke_to_diag, esc, jshift, list);
+                                               ke_to_diag, esc, jshift, pl);
 }
 
 template <typename R, int D>
 static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
                            const Chunk* chunks, const int32_t* nchunks, int with_rho,
                            double* kinetic, int ke_to_diag, const EscapeList& esc,
-                           const int32_t* jshift, const unsigned long long* list,
-                           hipStream_t st) {
-#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, jshift, list, st)
+                           const int32_t* jshift, PassList pl, hipStream_t st) {
+#define LPIC_GEO(g) launch_fused_g<R, D, g>(T, nblocks, smem, chunks, nchunks, with_rho, kinetic, ke_to_diag, esc, jshift, pl, st)
   if constexpr (D == 2) {
     switch (geo) {
       case 1: LPIC_GEO(1); return;
@@ -646,7 +669,8 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
                   int ke_to_diag, const EscapeList& esc, const int32_t* jshift,
                   hipStream_t st, const Rebin* rb) {
   LPIC_PD(prec, dim, (launch_fused_d<R, D>(geo, T, nblocks, smem, chunks, nchunks, with_rho,
-                                           kinetic, ke_to_diag, esc, jshift, nullptr, st)));
+                                           kinetic, ke_to_diag, esc, jshift,
+                                           PassList{nullptr, nullptr}, st)));
   if (rb) {
     // escapees by present tile, a second pass over them, then whatever that pass could not
     // place (normally nothing) through global memory
@@ -654,7 +678,9 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
     const int k = with_rho ? 1 : 0;
     LPIC_PD(prec, dim, (launch_fused_d<R, D>(rb->geo, T, rb->grid[k], rb->smem[k], rb->chunks,
                                              rb->nchunks, with_rho, kinetic, ke_to_diag,
-                                             rb->esc2, jshift, rb->items, st)));
+                                             rb->esc2, jshift,
+                                             PassList{rb->items, esc.rec ? rb->rec : nullptr},
+                                             st)));
     LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(
                            T, with_rho, kinetic, ke_to_diag, esc, rb->threshold)));
     LPIC_PD(prec, dim, (k_escape<R, D><<<ESCAPE_BLOCKS, 256, 0, st>>>(

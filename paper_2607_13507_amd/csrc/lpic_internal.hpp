@@ -87,6 +87,8 @@ struct EscapeList {
   unsigned int* count;         // two counters, zero between steps
   unsigned long long* total;   // cumulative number of escapes
   int64_t capacity;
+  void* rec = nullptr;         // with the re-binned path: entry k's particle words as an
+                               // escape record (EscRec, 8 values of the kernel precision)
 };
 constexpr int ESCAPE_BLOCKS = 128;
 
@@ -102,6 +104,7 @@ struct Rebin {
   int count_blocks;            // workgroups of the count and scatter kernels
   int32_t *counts, *offsets, *cursor;   // nbins + 1 each; counts zero between steps
   unsigned long long* items;   // the escape list grouped by bin (capacity of the list)
+  void* rec;                   // their escape records in the same order
   Chunk* chunks;
   int32_t* nchunks;
   EscapeList esc2;             // particles the second pass finds outside its regions

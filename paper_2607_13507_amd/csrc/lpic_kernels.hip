@@ -1385,12 +1385,19 @@ __device__ __forceinline__ bool rebin_on(const unsigned int* esc_count, int thre
   return (int)min(esc_count[0], 0x7fffffffu) >= threshold;
 }
 
+// The bin of escape-list entry i: from its escape record when the list carries them (one
+// contiguous read), else from the particle's slot.
 template <typename R, int DIM>
-__device__ __forceinline__ int escapee_bin(const Tables& T, unsigned long long item) {
+__device__ __forceinline__ int escapee_bin(const Tables& T, const EscapeList& esc, int64_t i,
+                                           unsigned long long item) {
   const int seg = (int)(item >> 32);
   const int64_t p = (int64_t)(item & 0xffffffffull);
   const SegDesc& s = seg_of(T, seg);
-  return particle_bin<R, DIM>(s, run_of(T, s.run), p);
+  const RunDesc& r = run_of(T, s.run);
+  if (!esc.rec) return particle_bin<R, DIM>(s, r, p);
+  int c[3];
+  if (!rec_cell<R, DIM>(part_ptrs<R>(s, r), esc.rec, i, c)) return s.bin_base + r.ntiles;
+  return s.bin_base + (((c[2] >> s.lz) * r.nty) + (c[1] >> s.ly)) * r.ntx + (c[0] >> s.lx);
 }
 
 // ESC_ITEMS escape-list entries per thread: 2048 per workgroup of 256, as for the sort.
@@ -1410,7 +1417,7 @@ __global__ __launch_bounds__(256) void k_rebin_count(Tables T, EscapeList esc, i
 #pragma unroll
     for (int it = 0; it < ESC_ITEMS; ++it) {
       const int64_t i = beg + it * 256 + threadIdx.x;
-      key[it] = i < n ? escapee_bin<R, DIM>(T, esc.items[i]) : -1;
+      key[it] = i < n ? escapee_bin<R, DIM>(T, esc, i, esc.items[i]) : -1;
     }
 #pragma unroll
     for (int it = 0; it < ESC_ITEMS; ++it) {
@@ -1430,7 +1437,7 @@ __global__ __launch_bounds__(256) void k_rebin_count(Tables T, EscapeList esc, i
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc, int threshold,
                                                        int32_t* cursor,
-                                                       unsigned long long* out) {
+                                                       unsigned long long* out, void* out_rec) {
   if (!rebin_on(esc.count, threshold)) return;
   const int64_t n = min((int64_t)esc.count[0], esc.capacity);
   __shared__ SortCache C;
@@ -1444,7 +1451,7 @@ __global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc,
     for (int it = 0; it < ESC_ITEMS; ++it) {
       const int64_t i = beg + it * 256 + threadIdx.x;
       item[it] = i < n ? esc.items[i] : 0ull;
-      key[it] = i < n ? escapee_bin<R, DIM>(T, item[it]) : -1;
+      key[it] = i < n ? escapee_bin<R, DIM>(T, esc, i, item[it]) : -1;
     }
     // ranks inside the workgroup for cached keys, straight from the bin cursor otherwise
     int32_t rank[ESC_ITEMS];
@@ -1476,6 +1483,8 @@ __global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc,
       const int64_t slot =
           (cached[it] ? (int64_t)C.base[key[it] & (SORT_SLOTS - 1)] : 0) + rank[it];
       out[slot] = item[it];
+      if (esc.rec)
+        store_rec<R>(out_rec, slot, load_rec<R>(esc.rec, beg + it * 256 + threadIdx.x));
     }
     __syncthreads();   // the cache is cleared for the next batch
   }
@@ -1901,7 +1910,7 @@ void launch_rebin(const Tables& T, int prec, int dim, const EscapeList& esc, con
   k_scan_bins<<<1, 1024, 0, st>>>(rb.counts, rb.offsets, rb.cursor, nullptr, rb.nbins, 0,
                                   esc.count, rb.threshold);
   LPIC_PD(prec, dim, (k_rebin_scatter<R, D><<<rb.count_blocks, 256, 0, st>>>(
-                         T, esc, rb.threshold, rb.cursor, rb.items)));
+                         T, esc, rb.threshold, rb.cursor, rb.items, rb.rec)));
   k_build_chunks<<<1, 1024, 0, st>>>(T, rb.offsets, rb.nvirt, rb.chunk, rb.chunks, rb.nchunks,
                                      1, esc.count, rb.threshold);
 }
