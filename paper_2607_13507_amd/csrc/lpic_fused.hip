@@ -393,15 +393,19 @@ __device__ __forceinline__ double process_chunk_compact(
   return ke * s.m;
 }
 
-template <typename R, int DIM, int ORDER, class LA>
+template <typename R, int DIM, int ORDER, bool DIRECT, class LA>
 __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc& s, int seg,
                                                 const Chunk& ch, const Region& g,
                                                 const LA& L, int with_rho,
                                                 bool want_ke, const EscapeList& esc,
                                                 const PassList& pl, int32_t* cbuf) {
+  // 3D: compacted rounds, except for the second pass of the re-binned path on the two-per-CU
+  // geometry (DIRECT), whose particles lie inside their present tile (nearly all on chip):
+  // there the records are loaded directly, one memory latency and no barriers per round
   if constexpr (DIM == 3)
-    return process_chunk_compact<R, DIM, ORDER>(r, s, seg, ch, g, L, with_rho, want_ke, esc,
-                                                pl, cbuf);
+    if (!(DIRECT && pl.rec))
+      return process_chunk_compact<R, DIM, ORDER>(r, s, seg, ch, g, L, with_rho, want_ke, esc,
+                                                  pl, cbuf);
   (void)cbuf;
   const int n[3] = {r.nx, r.ny, r.nz};
   const PushConst<R> k = push_const<R>(r, s);
@@ -419,7 +423,14 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
       ok[b] = lp < ch.end;
       pi[b] = lp;
       if (pl.list && ok[b]) pi[b] = (int32_t)(gp(pl.list)[lp] & 0xffffffffull);
-      if (ok[b]) load_particle<R, DIM>(q, pi[b], ps[b]);   // 2D lists carry no records
+      if (ok[b]) {
+        if constexpr (DIM == 3) {
+          if (pl.rec) decode_particle<R, DIM>(q, words_of(load_rec<R>(pl.rec, lp)), ps[b]);
+          else load_particle<R, DIM>(q, pi[b], ps[b]);
+        } else {
+          load_particle<R, DIM>(q, pi[b], ps[b]);   // 2D lists carry no records
+        }
+      }
     }
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
@@ -551,8 +562,8 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
     ke += s.order == 1
-              ? process_chunk<R, DIM, 1>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
-              : process_chunk<R, DIM, 2>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
+              ? process_chunk<R, DIM, 1, G == 7>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
+              : process_chunk<R, DIM, 2, G == 7>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
