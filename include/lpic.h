@@ -136,11 +136,15 @@ typedef struct {
  * Algorithm 1) as three grid-wide kernels; without it they run as one kernel over field
  * tiles of up to 64 x 16 cells whenever every box's nx and ny are multiples of a tile edge
  * (>= 8 and >= 4), which computes the same values with one pass over the arrays.
- * LPIC_ESCAPE_REBIN (lpic_step): when a step finds many particles (at least 4096) outside
- * the on-chip margin of the tile they were sorted into, group them by the tile they are in
- * now (a count, a scan and a scatter of their indices) and push them in a second pass of
- * the fused kernel against the staged regions of those tiles, instead of through global
- * memory; the sort itself still runs every sort_interval steps. */
+ * LPIC_ESCAPE_REBIN (lpic_step): when a step finds many particles (at least 4096) whose
+ * gather stencil or deposit window leaves the staged region of the tile they were sorted
+ * into, group them by the tile they are in now (a count, a scan and a scatter of their
+ * indices; in 3D with each particle's words copied into a contiguous escape record) and push
+ * them in a second pass of the fused kernel against the staged regions of those tiles,
+ * instead of through global memory; the sort itself still runs every sort_interval steps.
+ * Device memory, allocated when the flag is first set: two 8-byte entries per particle slot
+ * beyond the escape list's own, and in 3D two escape records of 32 (FP32) or 64 (FP64)
+ * bytes per slot. */
 #define LPIC_SORT_SPREAD 1
 #define LPIC_FIELD_SEPARATE 2
 #define LPIC_ESCAPE_REBIN 4
