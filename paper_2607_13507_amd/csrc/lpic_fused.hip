@@ -1,17 +1,19 @@
 // The fused particle kernel of the PIC hot path (gfx950, wave64): gather + relativistic
 // Boris push + Esirkepov deposit in one pass over a tile-sorted particle stream, with the
-// field tile staged in LDS and the tile's current accumulated in LDS (FP64) before one
-// global atomic flush per non-zero entry; plus the kernel that handles, through global
-// memory, the particles that have left the on-chip margin of their tile.
+// field tile staged in LDS and the tile's current accumulated in LDS (64-bit fixed point on
+// the FP32 path, FP64 on the FP64 path) before one global atomic flush per non-zero entry;
+// plus the kernel that handles, through global memory, the particles whose stencils have
+// left the staged region of their tile.
 #include "lpic_internal.hpp"
 
 namespace lpic {
 
 // =======================================================================================
-// Fused gather + push + deposit (unified pusher).  One workgroup per chunk; the chunk's
-// field tile (tile + halo) is staged in LDS, the current accumulates in LDS and is flushed
-// once.  Workgroups are mapped to chunks so that each XCD (every 8th workgroup) walks a
-// contiguous range of chunks: neighbouring tiles share that XCD's L2.
+// Fused gather + push + deposit (unified pusher).  Persistent workgroups walk the chunk
+// table; for each tile the field region (tile + halo) is staged in LDS once, the current
+// accumulates in LDS and is flushed when the tile changes.  Workgroups are mapped to chunks
+// so that each XCD (every 8th workgroup) walks a contiguous range of chunks: neighbouring
+// tiles share that XCD's L2.
 // =======================================================================================
 // Region geometries compiled with constant strides: (tile x, y, z, halo, z-layer pad).
 // Geometry 0 is the runtime-stride kernel used for every other tiling.  The 3D pads put
@@ -216,9 +218,10 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
 // In 3D one particle per thread per round: the unrolled body of four 3D particles is too
 // large for the compiler to keep their states in registers (it put them in scratch memory,
 // read and written for every particle), and a 3D workgroup brings 16 waves per CU anyway.
-// In 2D FP64 two: four FP64 states take the registers of a third wave per SIMD.
+// In 2D FP64 one as well: a second FP64 state takes the registers of a third wave per SIMD
+// (169 VGPRs with two, two waves; 154 with one, three waves and a 10% faster launch).
 template <typename R, int DIM>
-constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 2); }
+constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 1); }
 // Waves per SIMD the fused kernel's register budget is set for: 2D FP32 and the two-per-CU
 // 3D FP32 geometry fit 4 (at most 128 VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM, int G>

@@ -79,8 +79,9 @@ void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st);
 // species; RunDesc seg_first / nseg / vbase describe the order).
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
                          Chunk* out, int32_t* nchunks, hipStream_t st);
-// Particles outside the on-chip margin of their home tile: the fused kernel records them
-// here and a second kernel pushes them through global memory; that kernel's last workgroup
+// Particles whose stencils leave the staged region of their home tile: the fused kernel
+// records them here and a second kernel pushes them through global memory (or, re-binned, a
+// second fused pass); the escape kernel's last workgroup
 // clears the list (count[0] entries, count[1] workgroups done) for the next step.
 struct EscapeList {
   unsigned long long* items;   // (segment << 32) | particle

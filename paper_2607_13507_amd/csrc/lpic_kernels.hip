@@ -1373,8 +1373,9 @@ __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* 
 }
 
 // =======================================================================================
-// Re-binned escapes.  Particles that have left the on-chip margin of their home tile since
-// the last sort (the fused kernel's escape list) are grouped by the tile they are in now:
+// Re-binned escapes.  Particles whose stencils have left the staged region of their home
+// tile since the last sort (the fused kernel's escape list) are grouped by the tile they
+// are in now:
 // count per (segment, tile) bin, scan, scatter of the list entries, a chunk list over those
 // bins; a second fused pass then pushes them against the staged regions of their present
 // tiles, where they are always inside.  Every kernel of the path first reads the escape
