@@ -16,6 +16,8 @@ Also measured, each with its own roofline and CPU baseline (keys of "extra"):
                           a0 = 10 antenna inside a 16-cell PML layer: the first steps;
   laser_slab_interaction  the same box timed from step 1200, when the pulse is inside the
                           slab (relativistic hot electrons, particles leaving their tiles);
+                          the escape path is chosen again for this phase (the re-binned
+                          path on and off, tried on a copy advanced to the same step);
   thermal_3d              3D3V periodic 256^3, 8 ppc (134,217,728), T = 0.05, quadratic, sort
                           every 20 steps as the configuration states;
   wakefield               2D3V 8192x512, 0.01 n_c at 4 ppc, a0 = 2, window moving with light.
@@ -252,15 +254,39 @@ def run_gpu(name, wl, ndim, prec, args, steps, warmup, tune, interaction=False):
     k = sim.options.sort_interval
     period = k // math.gcd(k, 10) * 10
     advance(sim, wl, (-sim.nstep) % period)
+    def opts_now():
+        t = sim.options.tiling
+        return dict(tiling=[t.tx, t.ty, t.tz], halo=t.halo, chunk=t.chunk,
+                    sort_interval=sim.options.sort_interval,
+                    escape_rebin=bool(t.flags & L.ESCAPE_REBIN))
+
     out = dict(start=timed_window(sim, wl, steps, not args.no_graph))
+    out["start"]["options"] = opts_now()
     if interaction:
         advance(sim, wl, max(0, INTERACTION_STEP - sim.nstep))
         advance(sim, wl, (-sim.nstep) % period)
+        if tune:
+            # the escape path is chosen again for this phase (particles now leave their
+            # tiles): a copy advanced to the same step tries it on and off, and the measured
+            # run takes the faster setting
+            t = sim.options.tiling
+            tsim = Simulation(wl, prec=prec, tiling=(t.tx, t.ty, t.tz), halo=t.halo,
+                              chunk=t.chunk, sort_interval=k, diag_interval=10,
+                              use_graph=True, flags=t.flags)
+            advance(tsim, wl, sim.nstep)
+            tuned_i, trials_i = tsim.autotune_search(
+                tile=((t.tx, t.ty, t.tz), (t.tx, t.ty, t.tz)), halo=(t.halo, t.halo),
+                chunk=(t.chunk, t.chunk), sort_interval=(k, k), rebin=2, steps_each=k,
+                max_trials=2)
+            tsim.close()
+            del tsim
+            torch.cuda.empty_cache()
+            out["interaction_tuned"] = dict(tuned_i, trials=trials_i)
+            if tuned_i["flags"] != t.flags:
+                sim.set_options(flags=tuned_i["flags"])
+                advance(sim, wl, period)      # settle: the new options sort first
         out["interaction"] = timed_window(sim, wl, steps, not args.no_graph)
-    t = sim.options.tiling
-    out["options"] = dict(tiling=[t.tx, t.ty, t.tz], halo=t.halo, chunk=t.chunk,
-                          sort_interval=sim.options.sort_interval,
-                          escape_rebin=bool(t.flags & L.ESCAPE_REBIN))
+        out["interaction"]["options"] = opts_now()
     out["tuned"] = tuned
     out["tune_trials"] = trials
     sim.close()
@@ -446,7 +472,7 @@ def measure(name, args, want_cpu):
                  eager_mode=dict(ms_per_step=round(w["eager_ms_per_step"], 4),
                                  pushes_per_s=round(w["eager_pushes_per_s"], 1)),
                  halo_escapes_per_push=w["halo_escapes_per_push"],
-                 options=r32["options"], diagnostics_fp32=w["diagnostics"])
+                 options=w["options"], diagnostics_fp32=w["diagnostics"])
         if r64:
             e["fp64"] = fp64_entry(ndim, wls, ppc_tot, r64, key)
             e["fp32_over_fp64"] = round(w["pushes_per_s"] / r64[key]["pushes_per_s"], 3)
@@ -456,6 +482,14 @@ def measure(name, args, want_cpu):
         head["autotuned"] = dict(r32["tuned"], trials=len(r32["tune_trials"]))
     if r64 and r64["tuned"]:
         head["autotuned_fp64"] = dict(r64["tuned"], trials=len(r64["tune_trials"]))
+    if "interaction" in entries:
+        for r, k in ((r32, "autotuned"), (r64, "autotuned_fp64")):
+            if r and r.get("interaction_tuned"):
+                it = r["interaction_tuned"]
+                entries["interaction"][k] = dict(
+                    {x: v for x, v in it.items() if x != "trials"},
+                    trials=[dict(rebin=t["rebin"], ms_per_step=t["ms_per_step"])
+                            for t in it["trials"]])
     gc.collect()
     return wls, entries, want_cpu
 
