@@ -651,6 +651,7 @@ struct lpic_sim {
   int64_t max_chunks = 0;
   size_t smem = 0, smem_rho = 0;
   int geo = 0;
+  int geo_rho = 0;                  // the geometry of diagnostic steps (charge planes)
   double* diag = nullptr;
   unsigned long long* escapes = nullptr;     // cumulative escape count
   unsigned int* esc_count = nullptr;         // per-step escape counters
@@ -884,10 +885,15 @@ lpic_status configure(lpic_sim* s) {
   HIPCHK(hipMemset(s->counts, 0, sizeof(int32_t) * (s->nbins + 1)));
   HIPCHK(hipMemset(s->nchunks, 0, sizeof(int32_t)));
   s->smem = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 0);
-  s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1);
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem_rho, &s->blocks_per_cu_rho));
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, s->smem_rho, s->smem, &s->blocks_per_cu));
+  // FP32 8 x 4 x 4 tiles with halo 3: the charge planes of diagnostic steps leave one
+  // workgroup per CU, which then runs 1024 threads (geometry 8) instead of 512
+  s->geo_rho = (s->prec == LPIC_F32_CELLOFS && s->geo == 7) ? 8 : s->geo;
+  s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1, s->geo_rho);
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_rho, s->smem_rho, s->smem_rho,
+                       &s->blocks_per_cu_rho));
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, std::max(s->smem, s->geo == s->geo_rho ? s->smem_rho : 0),
+                       s->smem, &s->blocks_per_cu));
   HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
   // fused 2D field update between steps: the largest field tile dividing every box
   free_dev(s->mid_pfx_d);
@@ -961,12 +967,15 @@ lpic_status configure(lpic_sim* s) {
     // second pass: the re-binned particles lie inside their present tile, so a 3D FP32
     // 8 x 4 x 4 tiling with halo 4 runs it on the halo-3 geometry, two workgroups per CU
     const bool small = s->prec == LPIC_F32_CELLOFS && s->ndim == 3 && s->geo == 5;
-    rb.geo = small ? fused_geometry(3, 8, 4, 4, 3) : s->geo;
+    rb.geo[0] = small ? fused_geometry(3, 8, 4, 4, 3) : s->geo;
+    rb.geo[1] = small ? 8 : s->geo_rho;
     rb.smem[0] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 0) : s->smem;
-    rb.smem[1] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 1) : s->smem_rho;
+    rb.smem[1] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 1, 8) : s->smem_rho;
     int bpc[2] = {1, 1};
-    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo, rb.smem[1], rb.smem[1], &bpc[1]));
-    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo, rb.smem[1], rb.smem[0], &bpc[0]));
+    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[1], rb.smem[1], rb.smem[1], &bpc[1]));
+    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[0],
+                         std::max(rb.smem[0], rb.geo[0] == rb.geo[1] ? rb.smem[1] : 0),
+                         rb.smem[0], &bpc[0]));
     rb.grid[0] = fused_grid(maxch, bpc[0]);
     rb.grid[1] = fused_grid(maxch, bpc[1]);
     s->rebin = true;
@@ -1090,7 +1099,7 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       esc.count = s->esc_count;
       esc.total = s->escapes;
       esc.capacity = s->esc_capacity;
-      launch_fused(Tc, s->prec, s->ndim, s->geo,
+      launch_fused(Tc, s->prec, s->ndim, diag ? s->geo_rho : s->geo,
                    fused_grid(s->max_chunks, diag ? s->blocks_per_cu_rho : s->blocks_per_cu),
                    diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
                    diag ? 1 : 0, esc, s->jshift, st, s->rebin ? &s->rb : nullptr);

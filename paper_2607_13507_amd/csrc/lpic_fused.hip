@@ -22,15 +22,18 @@ namespace lpic {
 // region, charge planes included, still fits the LDS.  Geometry 7 (8 x 4 x 4 tiles, halo 3)
 // runs 512-thread workgroups, two per CU: it is also the second pass of the re-binned
 // escape path for 8 x 4 x 4 tilings with halo 4 (its particles lie inside their present
-// tile, so a halo of 3 always holds their stencils).
+// tile, so a halo of 3 always holds their stencils).  Geometry 8 is the same region with
+// 1024-thread workgroups, for FP32 diagnostic steps: their charge planes leave room for one
+// workgroup per CU, which then brings all sixteen waves by itself.
 struct GeoFix { int tx, ty, tz, halo, pz; };
 __host__ __device__ constexpr GeoFix geo_table(int g) {
   return g == 1 ? GeoFix{16, 16, 1, 5, 0} : g == 2 ? GeoFix{8, 8, 1, 5, 0}
        : g == 3 ? GeoFix{32, 32, 1, 5, 0} : g == 4 ? GeoFix{16, 16, 1, 4, 0}
        : g == 5 ? GeoFix{8, 4, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4, 8}
-       : g == 7 ? GeoFix{8, 4, 4, 3, 8} : GeoFix{0, 0, 0, 0, 0};
+       : g == 7 ? GeoFix{8, 4, 4, 3, 8} : g == 8 ? GeoFix{8, 4, 4, 3, 8}
+       : GeoFix{0, 0, 0, 0, 0};
 }
-constexpr int NUM_GEO = 8;
+constexpr int NUM_GEO = 9;   // fused_geometry() returns the first match: 7, never 8
 
 template <int DIM, int G>
 struct GeoStrides {
@@ -225,7 +228,9 @@ constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 1); }
 // Waves per SIMD the fused kernel's register budget is set for: 2D FP32 and the two-per-CU
 // 3D FP32 geometry fit 4 (at most 128 VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM, int G>
-constexpr int fused_waves() { return (sizeof(R) == 4 && (DIM == 2 || G == 7)) ? 4 : 1; }
+constexpr int fused_waves() {
+  return (sizeof(R) == 4 && (DIM == 2 || G == 7 || G == 8)) ? 4 : 1;
+}
 
 // Threads per workgroup: a 3D region (tile + halo on three axes) fills most of a CU's LDS,
 // so one workgroup per CU must bring enough waves by itself: 16 (four per SIMD) in FP32, whose
@@ -233,7 +238,7 @@ constexpr int fused_waves() { return (sizeof(R) == 4 && (DIM == 2 || G == 7)) ? 
 // Geometry 7's smaller region lets two 512-thread workgroups share a CU.
 template <typename R, int DIM, int G>
 constexpr int fused_block() {
-  return DIM == 2 ? 256 : (G == 7 || sizeof(R) == 8 ? 512 : 1024);
+  return DIM == 2 ? 256 : (sizeof(R) == 8 || G == 7 ? 512 : 1024);
 }
 
 // pl.list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
@@ -565,8 +570,8 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
     ke += s.order == 1
-              ? process_chunk<R, DIM, 1, G == 7>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
-              : process_chunk<R, DIM, 2, G == 7>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
+              ? process_chunk<R, DIM, 1, G == 7 || G == 8>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
+              : process_chunk<R, DIM, 2, G == 7 || G == 8>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
@@ -672,6 +677,7 @@ static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
       case 5: LPIC_GEO(5); return;
       case 6: LPIC_GEO(6); return;
       case 7: LPIC_GEO(7); return;
+      case 8: LPIC_GEO(8); return;
       default: LPIC_GEO(0); return;
     }
   }
@@ -690,7 +696,7 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
     // place (normally nothing) through global memory
     launch_rebin(T, prec, dim, esc, *rb, st);
     const int k = with_rho ? 1 : 0;
-    LPIC_PD(prec, dim, (launch_fused_d<R, D>(rb->geo, T, rb->grid[k], rb->smem[k], rb->chunks,
+    LPIC_PD(prec, dim, (launch_fused_d<R, D>(rb->geo[k], T, rb->grid[k], rb->smem[k], rb->chunks,
                                              rb->nchunks, with_rho, kinetic, ke_to_diag,
                                              rb->esc2, jshift,
                                              PassList{rb->items, esc.rec ? rb->rec : nullptr},
@@ -732,15 +738,17 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
       case 5: e = prec == 0 ? set_smem<float, 3, 5>(smem, smem_occ, b) : set_smem<double, 3, 5>(smem, smem_occ, b); break;
       case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, smem_occ, b) : set_smem<double, 3, 6>(smem, smem_occ, b); break;
       case 7: e = prec == 0 ? set_smem<float, 3, 7>(smem, smem_occ, b) : set_smem<double, 3, 7>(smem, smem_occ, b); break;
+      case 8: e = prec == 0 ? set_smem<float, 3, 8>(smem, smem_occ, b) : set_smem<double, 3, 8>(smem, smem_occ, b); break;
       default: e = prec == 0 ? set_smem<float, 3, 0>(smem, smem_occ, b) : set_smem<double, 3, 0>(smem, smem_occ, b); break;
     }
   }
   return e;
 }
 
-size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho) {
+size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho,
+                        int geo) {
   // the z layers of a fixed 3D geometry are padded (GeoFix::pz)
-  const int geo = fused_geometry(dim, tx, ty, tz, halo);
+  if (geo < 0) geo = fused_geometry(dim, tx, ty, tz, halo);
   const int pz = dim == 3 ? geo_table(geo).pz : 0;
   const size_t plane = ((size_t)(tx + 2 * halo) * (ty + 2 * halo) + pz) *
                        (dim == 3 ? (tz + 2 * halo) : 1);
@@ -752,6 +760,7 @@ size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int
   // 3D: the round compaction's two slot lists and wave sums (process_chunk_compact)
   const int block = geo == 7 ? fused_block<float, 3, 7>()
                   : prec == 0 ? fused_block<float, 3, 0>() : fused_block<double, 3, 0>();
+  // (geometry 8 has the default 3D blocks: 1024 threads FP32, 512 FP64)
   const size_t compact = dim == 3 ? (2 * (size_t)block + 64) * 4 : 0;
   return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8 + compact;
 }

@@ -109,7 +109,7 @@ struct Rebin {
   Chunk* chunks;
   int32_t* nchunks;
   EscapeList esc2;             // particles the second pass finds outside its regions
-  int geo;                     // the second pass's geometry (fused_geometry()), its grid and
+  int geo[2];                  // the second pass's geometry (fused_geometry()), grid and
   int grid[2];                 // dynamic LDS without / with the charge planes
   size_t smem[2];
 };
@@ -161,6 +161,8 @@ void launch_load_positions(const Tables& T, int prec, int dim, int nblocks, cons
                            const double* y, const double* z, hipStream_t st);
 void launch_store_positions(const Tables& T, int prec, int dim, int nblocks, double* x,
                             double* y, double* z, hipStream_t st);
-size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho);
+// geo >= 0: the LDS of that geometry's launch (its workgroup size), else the tiling's own
+size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho,
+                        int geo = -1);
 
 }  // namespace lpic
