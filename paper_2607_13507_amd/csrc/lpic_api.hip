@@ -648,6 +648,7 @@ struct lpic_sim {
   int nvirt = 0;                             // (tile, species) slots of the chunk order
   Chunk* chunks = nullptr;
   int32_t* nchunks = nullptr;
+  int32_t* scan_part = nullptr;     // scratch of the many-workgroup scans
   int64_t max_chunks = 0;
   size_t smem = 0, smem_rho = 0;
   int geo = 0;
@@ -851,7 +852,7 @@ lpic_status configure(lpic_sim* s) {
   free_dev(s->runs_d); free_dev(s->segs_d); free_dev(s->run_blk_d);
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
-  free_dev(s->chunks);
+  free_dev(s->chunks); free_dev(s->scan_part);
   free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
   free_dev(s->rb.chunks); free_dev(s->rb.nchunks);
   s->rb = Rebin{};
@@ -876,6 +877,7 @@ lpic_status configure(lpic_sim* s) {
   ALLOC(s->cursor, sizeof(int32_t) * (s->nbins + 1));
   ALLOC(s->mult, sizeof(int32_t) * (s->nbins + 1));
   ALLOC(s->chunks, sizeof(Chunk) * std::max<int64_t>(1, maxch));
+  ALLOC(s->scan_part, sizeof(int32_t) * part_words(std::max(s->nbins, s->nvirt)));
   HIPCHK(hipMemcpy(s->runs_d, s->runs_h.data(), sizeof(RunDesc) * s->nruns, hipMemcpyHostToDevice));
   if (s->nsegs)
     HIPCHK(hipMemcpy(s->segs_d, s->segs_h.data(), sizeof(SegDesc) * s->nsegs, hipMemcpyHostToDevice));
@@ -956,6 +958,7 @@ lpic_status configure(lpic_sim* s) {
     rb.threshold = REBIN_THRESHOLD;
     rb.nbins = s->nbins;
     rb.nvirt = s->nvirt;
+    rb.part = s->scan_part;
     rb.chunk = t.chunk;
     rb.count_blocks = (int)std::min<int64_t>(2048, (s->esc_capacity + 2047) / 2048);
     rb.items = s->rb_items;
@@ -1064,11 +1067,12 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
   // sort particles (every sort_interval steps)
   if (do_sort && s->nsegs > 0) {
     launch_sort(Ts, s->prec, s->ndim, s->nblk_sort, s->counts, s->offsets, s->cursor, s->mult,
-                s->nbins, spread ? 1 : 0, st);
+                s->nbins, spread ? 1 : 0, st, s->scan_part);
     CHK(last_launch("sort"));
     launch_swap_segments(s->segs_d, s->nsegs, st);
     CHK(last_launch("swap"));
-    launch_build_chunks(Tc, s->offsets, s->nvirt, s->opt.tiling.chunk, s->chunks, s->nchunks, st);
+    launch_build_chunks(Tc, s->offsets, s->nvirt, s->opt.tiling.chunk, s->chunks, s->nchunks, st,
+                        s->scan_part);
     CHK(last_launch("chunks"));
     // the host mirror follows the device table at once, so that launches later in this
     // step that take descriptors by value see the sorted buffers (not while capturing: a
@@ -1258,6 +1262,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->seg_blk256_d); free_dev(s->seg_blk_sort_d);
   free_dev(s->counts); free_dev(s->offsets); free_dev(s->cursor); free_dev(s->mult);
   free_dev(s->chunks); free_dev(s->nchunks); free_dev(s->diag); free_dev(s->escapes);
+  free_dev(s->scan_part);
   free_dev(s->esc_items); free_dev(s->esc_count);
   free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
   free_dev(s->rb.chunks); free_dev(s->rb.nchunks);

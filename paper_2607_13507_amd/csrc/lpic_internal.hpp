@@ -70,15 +70,20 @@ void launch_gather_push(const Tables& T, int prec, int dim, int nblocks, void* o
 void launch_deposit(const Tables& T, int prec, int dim, int nblocks, const void* old,
                     int with_rho, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
+// part: scan scratch of part_words(nbins) words (NULL: the one-workgroup scan).
 void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* counts,
                  int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
-                 hipStream_t st);
+                 hipStream_t st, int32_t* part = nullptr);
+// Words of scan scratch for n bins or chunk-order slots.
+int part_words(int n);
 void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st);
 // Work list of the fused kernel: every (tile, species) particle range cut into chunks, run
 // by run, tile by tile, the run's species consecutive (nvirt = sum over runs of tiles x
 // species; RunDesc seg_first / nseg / vbase describe the order).
+// part (NULL: one workgroup): scratch of part_words(nvirt) words for the many-workgroup
+// version.
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
-                         Chunk* out, int32_t* nchunks, hipStream_t st);
+                         Chunk* out, int32_t* nchunks, hipStream_t st, int32_t* part = nullptr);
 // Particles whose stencils leave the staged region of their home tile: the fused kernel
 // records them here and a second kernel pushes them through global memory (or, re-binned, a
 // second fused pass); the escape kernel's last workgroup
@@ -102,6 +107,7 @@ struct Rebin {
   int threshold;
   int nbins;                   // bins of all segments
   int nvirt, chunk;            // the chunk order of the fused kernel (launch_build_chunks)
+  int32_t* part;               // scan scratch (part_words(max(nbins, nvirt)) words)
   int count_blocks;            // workgroups of the count and scatter kernels
   int32_t *counts, *offsets, *cursor;   // nbins + 1 each; counts zero between steps
   unsigned long long* items;   // the escape list grouped by bin (capacity of the list)

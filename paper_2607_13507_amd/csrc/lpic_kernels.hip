@@ -1090,6 +1090,98 @@ __global__ __launch_bounds__(1024) void k_scan_bins(int32_t* counts, int32_t* of
   if (threadIdx.x == 0) offsets[nbins] = base;
 }
 
+// The same scan over many workgroups (a sum per workgroup of SCAN_TILE bins, a scan of those
+// sums, then each workgroup's bins from its base): one memory latency per phase instead of
+// one per SCAN_TILE bins, for the many-bin scans of every step (3D re-binned escapes).
+constexpr int SCAN_TILE = 1024 * SCAN_PER;
+
+__device__ __forceinline__ bool gate_closed(const unsigned int* gate, int threshold) {
+  return gate && (int)min(gate[0], 0x7fffffffu) < threshold;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(const int32_t* counts, int nbins,
+                                                    int32_t* part, const unsigned int* gate,
+                                                    int threshold) {
+  if (gate_closed(gate, threshold)) return;
+  __shared__ int32_t wsum[17];
+  const int b0 = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER;
+  int32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) local += b0 + k < nbins ? counts[b0 + k] : 0;
+  int32_t total;
+  (void)block_exscan1024(local, wsum, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Exclusive scan of the nparts workgroup sums in place (one workgroup); the grand total to
+// *total_out.
+__global__ __launch_bounds__(1024) void k_scan_parts(int32_t* part, int nparts,
+                                                     int32_t* total_out,
+                                                     const unsigned int* gate, int threshold,
+                                                     int zero_if_closed) {
+  if (gate_closed(gate, threshold)) {
+    if (zero_if_closed && threadIdx.x == 0) *total_out = 0;
+    return;
+  }
+  __shared__ int32_t wsum[17];
+  int32_t base = 0;
+  for (int pass = 0; pass < nparts; pass += 1024) {
+    const int i = pass + threadIdx.x;
+    const int32_t v = i < nparts ? part[i] : 0;
+    int32_t total;
+    const int32_t ex = block_exscan1024(v, wsum, &total);
+    if (i < nparts) part[i] = base + ex;
+    base += total;
+  }
+  if (threadIdx.x == 0) *total_out = base;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(int32_t* counts, int32_t* offsets,
+                                                     int32_t* cursor, int32_t* mult, int nbins,
+                                                     int spread, const int32_t* part,
+                                                     const unsigned int* gate, int threshold) {
+  if (gate_closed(gate, threshold)) return;
+  __shared__ int32_t wsum[17];
+  const int b0 = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER;
+  int32_t v[SCAN_PER];
+  int32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    v[k] = b0 + k < nbins ? counts[b0 + k] : 0;
+    local += v[k];
+  }
+  int32_t total;
+  int32_t run = part[blockIdx.x] + block_exscan1024(local, wsum, &total);
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    const int b = b0 + k;
+    if (b < nbins) {
+      offsets[b] = run;
+      cursor[b] = run;
+      if (mult) mult[b] = spread ? spread_multiplier(v[k]) : 1;
+      counts[b] = 0;
+    }
+    run += v[k];
+  }
+}
+
+int part_words(int n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void launch_scan(int32_t* counts, int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins,
+                 int spread, const unsigned int* gate, int threshold, int32_t* part,
+                 hipStream_t st) {
+  const int nparts = (nbins + SCAN_TILE - 1) / SCAN_TILE;
+  if (!part || nparts <= 1) {
+    k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread, gate,
+                                    threshold);
+    return;
+  }
+  k_scan_sums<<<nparts, 1024, 0, st>>>(counts, nbins, part, gate, threshold);
+  k_scan_parts<<<1, 1024, 0, st>>>(part, nparts, offsets + nbins, gate, threshold, 0);
+  k_scan_apply<<<nparts, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread, part,
+                                        gate, threshold);
+}
+
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_sort_scatter(Tables T, int32_t* cursor,
                                                       const int32_t* offsets,
@@ -1315,61 +1407,131 @@ __device__ __forceinline__ VSlot vslot_run(const Tables& T, int v) {
 // absolute: chunk ranges are positions in the list the offsets describe (the re-binned
 // escape list) instead of slots relative to the segment.  gate != NULL: only when
 // *gate >= threshold; otherwise the chunk count is set to zero.
+// The particle ranges of SCAN_PER consecutive slots from v0: segment (-1: none), tile and
+// range (relative to the segment, or absolute).
+__device__ __forceinline__ void slot_ranges(const Tables& T, const int32_t* offsets, int nvirt,
+                                            int v0, int absolute, int sg[SCAN_PER],
+                                            int tl[SCAN_PER], int32_t o0[SCAN_PER],
+                                            int32_t o1[SCAN_PER]) {
+  VSlot q = vslot_run(T, min(v0, nvirt - 1));
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    const int v = v0 + k;
+    sg[k] = -1;
+    tl[k] = 0;
+    o0[k] = o1[k] = 0;
+    if (v < nvirt) {
+      while (v >= q.vend) q = vslot_run(T, v);   // runs without species span no slots
+      const int w = v - q.vbase;
+      tl[k] = w / q.nseg;
+      sg[k] = q.seg_first + (w - tl[k] * q.nseg);
+      const SegDesc& s = seg_of(T, sg[k]);
+      const int b = s.bin_base + tl[k];
+      const int32_t rel = absolute ? 0 : (int32_t)s.pbase;
+      o0[k] = offsets[b] - rel;
+      o1[k] = offsets[b + 1] - rel;
+    }
+  }
+}
+
+__device__ __forceinline__ void write_chunks(Chunk* out, int32_t pos, int chunk,
+                                             const int sg[SCAN_PER], const int tl[SCAN_PER],
+                                             const int32_t o0[SCAN_PER],
+                                             const int32_t o1[SCAN_PER]) {
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (sg[k] < 0) continue;
+    for (int32_t a = o0[k]; a < o1[k]; a += chunk) {
+      Chunk c;
+      c.seg = sg[k];
+      c.tile = tl[k];
+      c.beg = a;
+      c.end = min(o1[k], a + chunk);
+      out[pos++] = c;
+    }
+  }
+}
+
+__device__ __forceinline__ int32_t chunk_count(int chunk, const int sg[SCAN_PER],
+                                               const int32_t o0[SCAN_PER],
+                                               const int32_t o1[SCAN_PER]) {
+  int32_t n = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k)
+    if (sg[k] >= 0) n += (o1[k] - o0[k] + chunk - 1) / chunk;
+  return n;
+}
+
 __global__ __launch_bounds__(1024) void k_build_chunks(Tables T, const int32_t* offsets,
                                                        int nvirt, int chunk, Chunk* out,
                                                        int32_t* nchunks, int absolute,
                                                        const unsigned int* gate,
                                                        int threshold) {
-  if (gate && (int)min(gate[0], 0x7fffffffu) < threshold) {
+  if (gate_closed(gate, threshold)) {
     if (threadIdx.x == 0) *nchunks = 0;
     return;
   }
   __shared__ int32_t wsum[17];
   int32_t cbase = 0;
   for (int pass = 0; pass < nvirt; pass += 1024 * SCAN_PER) {
-    const int v0 = pass + threadIdx.x * SCAN_PER;
-    // each slot's segment, tile and particle range (loads issued together)
     int sg[SCAN_PER], tl[SCAN_PER];
     int32_t o0[SCAN_PER], o1[SCAN_PER];
-    VSlot q = vslot_run(T, min(v0, nvirt - 1));
-#pragma unroll
-    for (int k = 0; k < SCAN_PER; ++k) {
-      const int v = v0 + k;
-      sg[k] = -1;
-      tl[k] = 0;
-      o0[k] = o1[k] = 0;
-      if (v < nvirt) {
-        while (v >= q.vend) q = vslot_run(T, v);   // runs without species span no slots
-        const int w = v - q.vbase;
-        tl[k] = w / q.nseg;
-        sg[k] = q.seg_first + (w - tl[k] * q.nseg);
-        const SegDesc& s = seg_of(T, sg[k]);
-        const int b = s.bin_base + tl[k];
-        const int32_t rel = absolute ? 0 : (int32_t)s.pbase;
-        o0[k] = offsets[b] - rel;
-        o1[k] = offsets[b + 1] - rel;
-      }
-    }
-    int32_t local = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_PER; ++k)
-      if (sg[k] >= 0) local += (o1[k] - o0[k] + chunk - 1) / chunk;
+    slot_ranges(T, offsets, nvirt, pass + threadIdx.x * SCAN_PER, absolute, sg, tl, o0, o1);
     int32_t total;
-    int32_t pos = cbase + block_exscan1024(local, wsum, &total);
-    for (int k = 0; k < SCAN_PER; ++k) {
-      if (sg[k] < 0) continue;
-      for (int32_t a = o0[k]; a < o1[k]; a += chunk) {
-        Chunk c;
-        c.seg = sg[k];
-        c.tile = tl[k];
-        c.beg = a;
-        c.end = min(o1[k], a + chunk);
-        out[pos++] = c;
-      }
-    }
+    const int32_t pos = cbase + block_exscan1024(chunk_count(chunk, sg, o0, o1), wsum, &total);
+    write_chunks(out, pos, chunk, sg, tl, o0, o1);
     cbase += total;
   }
   if (threadIdx.x == 0) *nchunks = cbase;
+}
+
+// The chunk list over many workgroups (counts per workgroup of SCAN_TILE slots, their scan,
+// then each workgroup's chunks from its base), as the bin scan above.
+__global__ __launch_bounds__(1024) void k_chunk_sums(Tables T, const int32_t* offsets,
+                                                     int nvirt, int chunk, int32_t* part,
+                                                     int absolute, const unsigned int* gate,
+                                                     int threshold) {
+  if (gate_closed(gate, threshold)) return;
+  __shared__ int32_t wsum[17];
+  int sg[SCAN_PER], tl[SCAN_PER];
+  int32_t o0[SCAN_PER], o1[SCAN_PER];
+  slot_ranges(T, offsets, nvirt, blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER, absolute,
+              sg, tl, o0, o1);
+  int32_t total;
+  (void)block_exscan1024(chunk_count(chunk, sg, o0, o1), wsum, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_chunk_apply(Tables T, const int32_t* offsets,
+                                                      int nvirt, int chunk, Chunk* out,
+                                                      const int32_t* part, int absolute,
+                                                      const unsigned int* gate,
+                                                      int threshold) {
+  if (gate_closed(gate, threshold)) return;
+  __shared__ int32_t wsum[17];
+  int sg[SCAN_PER], tl[SCAN_PER];
+  int32_t o0[SCAN_PER], o1[SCAN_PER];
+  slot_ranges(T, offsets, nvirt, blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER, absolute,
+              sg, tl, o0, o1);
+  int32_t total;
+  const int32_t pos = part[blockIdx.x] +
+                      block_exscan1024(chunk_count(chunk, sg, o0, o1), wsum, &total);
+  write_chunks(out, pos, chunk, sg, tl, o0, o1);
+}
+
+static void build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
+                         Chunk* out, int32_t* nchunks, int absolute, const unsigned int* gate,
+                         int threshold, int32_t* part, hipStream_t st) {
+  const int nparts = (nvirt + SCAN_TILE - 1) / SCAN_TILE;
+  if (!part || nparts <= 1) {
+    k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, nchunks, absolute, gate,
+                                       threshold);
+    return;
+  }
+  k_chunk_sums<<<nparts, 1024, 0, st>>>(T, offsets, nvirt, chunk, part, absolute, gate,
+                                        threshold);
+  k_scan_parts<<<1, 1024, 0, st>>>(part, nparts, nchunks, gate, threshold, 1);
+  k_chunk_apply<<<nparts, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, part, absolute, gate,
+                                         threshold);
 }
 
 // =======================================================================================
@@ -1877,9 +2039,9 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
 
 void launch_sort(const Tables& T, int prec, int dim, int nblocks, int32_t* counts,
                  int32_t* offsets, int32_t* cursor, int32_t* mult, int nbins, int spread,
-                 hipStream_t st) {
+                 hipStream_t st, int32_t* part) {
   LPIC_PD(prec, dim, (k_sort_count<R, D><<<nblocks, 256, 0, st>>>(T, counts)));
-  k_scan_bins<<<1, 1024, 0, st>>>(counts, offsets, cursor, mult, nbins, spread, nullptr, 0);
+  launch_scan(counts, offsets, cursor, mult, nbins, spread, nullptr, 0, part, st);
   LPIC_PD(prec, dim, (k_sort_scatter<R, D><<<nblocks, 256, 0, st>>>(T, cursor, offsets, mult,
                                                                      spread)));
 }
@@ -1900,20 +2062,20 @@ void launch_swap_segments(SegDesc* segs, int nsegs, hipStream_t st) {
 }
 
 void launch_build_chunks(const Tables& T, const int32_t* offsets, int nvirt, int chunk,
-                         Chunk* out, int32_t* nchunks, hipStream_t st) {
-  k_build_chunks<<<1, 1024, 0, st>>>(T, offsets, nvirt, chunk, out, nchunks, 0, nullptr, 0);
+                         Chunk* out, int32_t* nchunks, hipStream_t st, int32_t* part) {
+  build_chunks(T, offsets, nvirt, chunk, out, nchunks, 0, nullptr, 0, part, st);
 }
 
 void launch_rebin(const Tables& T, int prec, int dim, const EscapeList& esc, const Rebin& rb,
                   hipStream_t st) {
   LPIC_PD(prec, dim, (k_rebin_count<R, D><<<rb.count_blocks, 256, 0, st>>>(T, esc, rb.threshold,
                                                                           rb.counts)));
-  k_scan_bins<<<1, 1024, 0, st>>>(rb.counts, rb.offsets, rb.cursor, nullptr, rb.nbins, 0,
-                                  esc.count, rb.threshold);
+  launch_scan(rb.counts, rb.offsets, rb.cursor, nullptr, rb.nbins, 0, esc.count, rb.threshold,
+              rb.part, st);
   LPIC_PD(prec, dim, (k_rebin_scatter<R, D><<<rb.count_blocks, 256, 0, st>>>(
                          T, esc, rb.threshold, rb.cursor, rb.items, rb.rec)));
-  k_build_chunks<<<1, 1024, 0, st>>>(T, rb.offsets, rb.nvirt, rb.chunk, rb.chunks, rb.nchunks,
-                                     1, esc.count, rb.threshold);
+  build_chunks(T, rb.offsets, rb.nvirt, rb.chunk, rb.chunks, rb.nchunks, 1, esc.count,
+               rb.threshold, rb.part, st);
 }
 
 template <typename R, int DIM>
