@@ -780,17 +780,46 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
       }
     if (with_rho) {
       const R qw = k.q * fw;
+      if constexpr (Acc::kLinear) {
+        // each shape is non-zero on ORDER + 1 consecutive nodes of the window, from node 0
+        // or node 1 (the first node of a shape is never zero when it is in use): a base per
+        // shape and lane, and (ORDER + 1)^3 unconditional adds at fixed offsets from it
+        // instead of W^3 conditional ones
+        constexpr int N = ORDER + 1;
+        const int s0x = S0x[0] == R(0), s0y = S0y[0] == R(0), s0z = S0z[0] == R(0);
+        const int s1x = S1x[0] == R(0), s1y = S1y[0] == R(0), s1z = S1z[0] == R(0);
+        R a0[N], b0[N], c0[N], a1[N], b1[N], c1[N];
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc)
+        for (int i = 0; i < N; ++i) {
+          a0[i] = s0x ? S0x[i + 1] : S0x[i]; b0[i] = s0y ? S0y[i + 1] : S0y[i];
+          c0[i] = s0z ? S0z[i + 1] : S0z[i]; a1[i] = s1x ? S1x[i + 1] : S1x[i];
+          b1[i] = s1y ? S1y[i + 1] : S1y[i]; c1[i] = s1z ? S1z[i + 1] : S1z[i];
+        }
+        const int o0 = xo[0] + s0x + A.yo(s0y) + A.zo(s0z);
+        const int o1 = xo[0] + s1x + A.yo(s1y) + A.zo(s1z);
 #pragma unroll
-        for (int b = 0; b < W; ++b)
+        for (int cc = 0; cc < N; ++cc)
 #pragma unroll
-          for (int a = 0; a < W; ++a) {
-            if ((a == W - 1 && !lx) || (b == W - 1 && !ly) || (cc == W - 1 && !lz)) continue;
-            const int off = zo[cc] + yo[b] + xo[a];
-            A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
-            A.add(F_R1, off, qw * S1x[a] * S1y[b] * S1z[cc]);
-          }
+          for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+              const int off = A.zo(cc) + A.yo(b) + a;
+              A.add_core(F_R0, o0 + off, qw * a0[a] * b0[b] * c0[cc]);
+              A.add_core(F_R1, o1 + off, qw * a1[a] * b1[b] * c1[cc]);
+            }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc)
+#pragma unroll
+          for (int b = 0; b < W; ++b)
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+              if ((a == W - 1 && !lx) || (b == W - 1 && !ly) || (cc == W - 1 && !lz)) continue;
+              const int off = zo[cc] + yo[b] + xo[a];
+              A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
+              A.add(F_R1, off, qw * S1x[a] * S1y[b] * S1z[cc]);
+            }
+      }
     }
   }
 }
