@@ -711,14 +711,35 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
     }
     if (with_rho) {
       const R qw = k.q * fw;
+      if constexpr (Acc::kLinear) {
+        // each shape on its own ORDER + 1 nodes (as in 3D below)
+        constexpr int N = ORDER + 1;
+        const int s0x = S0x[0] == R(0), s0y = S0y[0] == R(0);
+        const int s1x = S1x[0] == R(0), s1y = S1y[0] == R(0);
+        R a0[N], b0[N], a1[N], b1[N];
 #pragma unroll
-      for (int b = 0; b < W; ++b)
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-          if ((a == W - 1 && !lx) || (b == W - 1 && !ly)) continue;
-          A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
-          A.add(F_R1, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
+        for (int i = 0; i < N; ++i) {
+          a0[i] = s0x ? S0x[i + 1] : S0x[i]; b0[i] = s0y ? S0y[i + 1] : S0y[i];
+          a1[i] = s1x ? S1x[i + 1] : S1x[i]; b1[i] = s1y ? S1y[i + 1] : S1y[i];
         }
+        const int o0 = xo[0] + s0x + A.yo(s0y), o1 = xo[0] + s1x + A.yo(s1y);
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            A.add_core(F_R0, o0 + A.yo(b) + a, qw * a0[a] * b0[b]);
+            A.add_core(F_R1, o1 + A.yo(b) + a, qw * a1[a] * b1[b]);
+          }
+      } else {
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            if ((a == W - 1 && !lx) || (b == W - 1 && !ly)) continue;
+            A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
+            A.add(F_R1, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
+          }
+      }
     }
   } else {
     const bool lz = __ballot(S0z[W - 1] != R(0) || S1z[W - 1] != R(0)) != 0;
