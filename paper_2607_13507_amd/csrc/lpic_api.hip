@@ -682,6 +682,7 @@ struct lpic_sim {
   unsigned long long* esc2_items = nullptr;   // the second pass's own escape list
   void* esc_rec = nullptr;                    // escape records of the list, and grouped
   void* rb_rec = nullptr;
+  int32_t* esc_keys = nullptr;                // the present bin of each escape-list entry
   unsigned int* esc2_count = nullptr;         // its counters (and a total)
   int blocks_per_cu = 1;       // fused workgroups resident per CU (without / with charge planes)
   int blocks_per_cu_rho = 1;
@@ -943,6 +944,7 @@ lpic_status configure(lpic_sim* s) {
         const size_t rec = 8 * (s->prec == LPIC_F32_CELLOFS ? 4 : 8);
         ALLOC(s->esc_rec, rec * s->esc_capacity);
         ALLOC(s->rb_rec, rec * s->esc_capacity);
+        if (s->prec == LPIC_F32_CELLOFS) ALLOC(s->esc_keys, sizeof(int32_t) * s->esc_capacity);
       }
       ALLOC(s->esc2_count, 256);
       HIPCHK(hipMemset(s->esc2_count, 0, 256));
@@ -1100,6 +1102,9 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       EscapeList esc;
       esc.items = s->esc_items;
       esc.rec = s->rebin && s->ndim == 3 ? s->esc_rec : nullptr;   // records: 3D only
+      // FP32: the fused pass writes each escapee's bin (a few shifts of the packed cell),
+      // so the re-binning kernels read 4 bytes per entry instead of its record
+      esc.keys = esc.rec && s->prec == LPIC_F32_CELLOFS ? s->esc_keys : nullptr;
       esc.count = s->esc_count;
       esc.total = s->escapes;
       esc.capacity = s->esc_capacity;
@@ -1267,7 +1272,7 @@ void lpic_sim_destroy(lpic_sim* s) {
   free_dev(s->rb.counts); free_dev(s->rb.offsets); free_dev(s->rb.cursor);
   free_dev(s->rb.chunks); free_dev(s->rb.nchunks);
   free_dev(s->rb_items); free_dev(s->esc2_items); free_dev(s->esc2_count);
-  free_dev(s->esc_rec); free_dev(s->rb_rec);
+  free_dev(s->esc_rec); free_dev(s->rb_rec); free_dev(s->esc_keys);
   free_dev(s->wmax); free_dev(s->jshift); free_dev(s->step_dev);
   free_dev(s->mid_pfx_d); free_dev(s->bands);
   free_dev(s->old_state);

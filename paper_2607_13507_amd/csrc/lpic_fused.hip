@@ -194,9 +194,24 @@ struct PassList {
 // Append the lanes that want it to the escape list (one reservation per wave), with their
 // escape records when the list keeps them (3D only: the 2D body has no registers to spare
 // for the record's words, and 2D particles rarely leave their regions).
+// Entry k of the escape list: the particle's record and the bin of the tile it is in.
+template <typename R, int DIM>
+__device__ __forceinline__ void escape_record(const EscapeList& esc, int64_t k,
+                                              const RunDesc& r, const SegDesc& s,
+                                              const PartPtrs<R>& q, int32_t p) {
+  const PWords<R> x = load_words<R, DIM>(q, p);
+  store_rec<R>(esc.rec, k, rec_of(x));
+  if (!esc.keys) return;   // (the list may carry records without keys)
+  int c[3];
+  esc.keys[k] = decode_cell<R, DIM>(q, x.cell, x.pos, c)
+                    ? s.bin_base + (((c[2] >> s.lz) * r.nty) + (c[1] >> s.ly)) * r.ntx + (c[0] >> s.lx)
+                    : s.bin_base + r.ntiles;
+}
+
 template <typename R, int DIM>
 __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, int seg,
-                                              int32_t p, const PartPtrs<R>& q) {
+                                              int32_t p, const PartPtrs<R>& q,
+                                              const RunDesc& r, const SegDesc& s) {
   const uint64_t mask = __ballot(want);
   if (!mask) return;
   const int lane = __lane_id();
@@ -209,7 +224,7 @@ __device__ __forceinline__ void escape_append(const EscapeList& esc, bool want, 
     if ((int64_t)k < esc.capacity) {
       esc.items[k] = ((unsigned long long)seg << 32) | (unsigned long long)p;
       if constexpr (DIM == 3)
-        if (esc.rec) store_rec<R>(esc.rec, k, rec_of(load_words<R, DIM>(q, p)));
+        if (esc.rec) escape_record<R, DIM>(esc, k, r, s, q, p);
     }
   }
 }
@@ -376,7 +391,7 @@ __device__ __forceinline__ double process_chunk_compact(
     for (int e = tid; e < n_esc; e += bd)
       if (ebase + e < esc.capacity) {
         esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)cesc[e];
-        if (esc.rec) store_rec<R>(esc.rec, ebase + e, rec_of(load_words<R, DIM>(q, cesc[e])));
+        if (esc.rec) escape_record<R, DIM>(esc, ebase + e, r, s, q, cesc[e]);
       }
     bool late = false;                 // on chip by its cell, not by its own path
     int32_t p = 0;
@@ -396,7 +411,7 @@ __device__ __forceinline__ double process_chunk_compact(
       late = !push_on_chip<R, DIM, ORDER>(r, g, L, n, b, ps, k, q, p, with_rho, want_ke, ke,
                                           true);
     }
-    escape_append<R, DIM>(esc, late, seg, p, q);
+    escape_append<R, DIM>(esc, late, seg, p, q, r, s);
   }
   return ke * s.m;
 }
@@ -450,7 +465,7 @@ __device__ __forceinline__ double process_chunk(const RunDesc& r, const SegDesc&
       if (in)
         done = push_on_chip<R, DIM, ORDER>(r, g, L, n, a, ps[b], k, q, pi[b], with_rho,
                                            want_ke, ke, check);
-      escape_append<R, DIM>(esc, live && !done, seg, pi[b], q);
+      escape_append<R, DIM>(esc, live && !done, seg, pi[b], q, r, s);
     }
   }
   return ke * s.m;

@@ -95,6 +95,8 @@ struct EscapeList {
   int64_t capacity;
   void* rec = nullptr;         // with the re-binned path: entry k's particle words as an
                                // escape record (EscRec, 8 values of the kernel precision)
+  int32_t* keys = nullptr;     // with records: entry k's (segment, tile) bin by the tile its
+                               // particle is in, written with the record
 };
 constexpr int ESCAPE_BLOCKS = 128;
 

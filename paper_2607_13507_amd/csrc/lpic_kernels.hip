@@ -1553,6 +1553,7 @@ __device__ __forceinline__ bool rebin_on(const unsigned int* esc_count, int thre
 template <typename R, int DIM>
 __device__ __forceinline__ int escapee_bin(const Tables& T, const EscapeList& esc, int64_t i,
                                            unsigned long long item) {
+  if (esc.keys) return esc.keys[i];   // written by the fused pass with the record
   const int seg = (int)(item >> 32);
   const int64_t p = (int64_t)(item & 0xffffffffull);
   const SegDesc& s = seg_of(T, seg);
@@ -1580,7 +1581,7 @@ __global__ __launch_bounds__(256) void k_rebin_count(Tables T, EscapeList esc, i
 #pragma unroll
     for (int it = 0; it < ESC_ITEMS; ++it) {
       const int64_t i = beg + it * 256 + threadIdx.x;
-      key[it] = i < n ? escapee_bin<R, DIM>(T, esc, i, esc.items[i]) : -1;
+      key[it] = i < n ? escapee_bin<R, DIM>(T, esc, i, esc.keys ? 0ull : esc.items[i]) : -1;
     }
 #pragma unroll
     for (int it = 0; it < ESC_ITEMS; ++it) {
@@ -1610,11 +1611,13 @@ __global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc,
     __syncthreads();
     int key[ESC_ITEMS];
     unsigned long long item[ESC_ITEMS];
+    EscRec<R> rec[ESC_ITEMS];   // (loaded with the entries: one memory latency per batch)
 #pragma unroll
     for (int it = 0; it < ESC_ITEMS; ++it) {
       const int64_t i = beg + it * 256 + threadIdx.x;
       item[it] = i < n ? esc.items[i] : 0ull;
       key[it] = i < n ? escapee_bin<R, DIM>(T, esc, i, item[it]) : -1;
+      if (esc.rec && i < n) rec[it] = load_rec<R>(esc.rec, i);
     }
     // ranks inside the workgroup for cached keys, straight from the bin cursor otherwise
     int32_t rank[ESC_ITEMS];
@@ -1647,7 +1650,7 @@ __global__ __launch_bounds__(256) void k_rebin_scatter(Tables T, EscapeList esc,
           (cached[it] ? (int64_t)C.base[key[it] & (SORT_SLOTS - 1)] : 0) + rank[it];
       out[slot] = item[it];
       if (esc.rec)
-        store_rec<R>(out_rec, slot, load_rec<R>(esc.rec, beg + it * 256 + threadIdx.x));
+        store_rec<R>(out_rec, slot, rec[it]);
     }
     __syncthreads();   // the cache is cleared for the next batch
   }
