@@ -533,6 +533,7 @@ lpic_status lpic_push_deposit_fused(const lpic_grid* grid, const lpic_fields* fi
                                     int32_t with_rho, double* kinetic, lpic_precision prec,
                                     hipStream_t stream) {
   CHK(check_grid(grid, prec));
+  if (with_rho != 0 && with_rho != 1) return fail(LPIC_EINVAL, "with_rho must be 0 or 1");
   CHK(check_fields(fields, with_rho != 0));
   CHK(check_species(sp, grid->ndim, prec));
   CHK(check_tiling(tiling, grid, prec));
@@ -653,6 +654,16 @@ struct lpic_sim {
   size_t smem = 0, smem_rho = 0;
   int geo = 0;
   int geo_rho = 0;                  // the geometry of diagnostic steps (charge planes)
+  // Chained charge (3D FP32, boxes periodic along x, 8 x 4 x 4 tiles with halo 3): the step
+  // before a diagnostic step accumulates the charge at the ends of its paths into rho0, and
+  // the diagnostic step only the charge at the ends of its own paths, into rho1.  A path
+  // ends half a step past the stored position (x^n + (dt/2) v^n) and the next step's path
+  // starts at the same point, so rho0 of the diagnostic step is that charge; each of the two
+  // steps then carries one 64-bit charge plane and keeps two workgroups per CU.
+  bool chain = false;
+  int geo_chain = 0;
+  size_t smem_chain = 0;
+  int blocks_per_cu_chain = 1;
   double* diag = nullptr;
   unsigned long long* escapes = nullptr;     // cumulative escape count
   unsigned int* esc_count = nullptr;         // per-step escape counters
@@ -700,7 +711,7 @@ struct lpic_sim {
   bool need_spread = true;   // the first sort after particles are loaded spreads tiles
   // captured steps keyed by (sort, diagnostics, first field updates already done by the
   // previous step, last field updates merged into the next step's)
-  static constexpr int NGRAPHS = 16;
+  static constexpr int NGRAPHS = 64;
   hipGraphExec_t gexec[NGRAPHS] = {};
   // timing
   bool timing = false;
@@ -891,12 +902,25 @@ lpic_status configure(lpic_sim* s) {
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
   // FP32 8 x 4 x 4 tiles with halo 3: the charge planes of diagnostic steps leave one
   // workgroup per CU, which then runs 1024 threads (geometry 8) instead of 512
-  s->geo_rho = (s->prec == LPIC_F32_CELLOFS && s->geo == 7) ? 8 : s->geo;
+  s->geo_rho = (s->prec == LPIC_F32_CELLOFS && s->geo == 7) ? 9 : s->geo;
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1, s->geo_rho);
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_rho, s->smem_rho, s->smem_rho,
                        &s->blocks_per_cu_rho));
   HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, std::max(s->smem, s->geo == s->geo_rho ? s->smem_rho : 0),
                        s->smem, &s->blocks_per_cu));
+  {
+    // (no particle leaves a box that is periodic along x, so the charge at the end of a
+    // step's paths is the charge at the start of the next step's paths)
+    bool periodic = true;
+    for (int r = 0; r < s->nruns; ++r) periodic = periodic && !s->runs_h[r].open_x;
+    s->chain = s->prec == LPIC_F32_CELLOFS && s->ndim == 3 && s->geo == 7 && periodic;
+    if (s->chain) {
+      s->geo_chain = 8;
+      s->smem_chain = fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 2, 8);
+      HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_chain, s->smem_chain, s->smem_chain,
+                           &s->blocks_per_cu_chain));
+    }
+  }
   HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
   // fused 2D field update between steps: the largest field tile dividing every box
   free_dev(s->mid_pfx_d);
@@ -973,16 +997,23 @@ lpic_status configure(lpic_sim* s) {
     // 8 x 4 x 4 tiling with halo 4 runs it on the halo-3 geometry, two workgroups per CU
     const bool small = s->prec == LPIC_F32_CELLOFS && s->ndim == 3 && s->geo == 5;
     rb.geo[0] = small ? fused_geometry(3, 8, 4, 4, 3) : s->geo;
-    rb.geo[1] = small ? 8 : s->geo_rho;
+    rb.geo[1] = small ? 9 : s->geo_rho;
     rb.smem[0] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 0) : s->smem;
-    rb.smem[1] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 1, 8) : s->smem_rho;
-    int bpc[2] = {1, 1};
+    rb.smem[1] = small ? fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 1, 9) : s->smem_rho;
+    // (the chained-charge steps' second pass: one charge plane, as their first pass)
+    rb.geo[2] = s->chain ? s->geo_chain : rb.geo[1];
+    rb.smem[2] = s->chain ? s->smem_chain : rb.smem[1];
+    int bpc[3] = {1, 1, 1};
     HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[1], rb.smem[1], rb.smem[1], &bpc[1]));
     HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[0],
                          std::max(rb.smem[0], rb.geo[0] == rb.geo[1] ? rb.smem[1] : 0),
                          rb.smem[0], &bpc[0]));
+    bpc[2] = bpc[1];
+    if (s->chain)
+      HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[2], rb.smem[2], rb.smem[2], &bpc[2]));
     rb.grid[0] = fused_grid(maxch, bpc[0]);
     rb.grid[1] = fused_grid(maxch, bpc[1]);
+    rb.grid[2] = fused_grid(maxch, bpc[2]);
     s->rebin = true;
   }
   s->need_sort = true;
@@ -1040,8 +1071,11 @@ FieldBands sim_bands(const lpic_sim* s) {
 // array, so E + (dt/2)(curl B - J) twice is E + dt (curl B - J).  With the fused 2D field
 // update the previous step already did all of it (its B half, this full E update and this
 // step's first B half), and this step only clears the sources.
+// rho: the charge this step accumulates (deposit's with_rho): 1 on a diagnostic step, or
+// with chained charge 2 on the step before one and 3 on the diagnostic step; 0 otherwise.
 lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread, bool diag,
-                         bool eager_hooks, bool capturing, bool first_full, bool skip_last) {
+                         bool eager_hooks, bool capturing, bool first_full, bool skip_last,
+                         int rho) {
   const Tables Tc = sim_tables(s, nullptr);
   const Tables Ts = sim_tables(s, s->seg_blk_sort_d);
   const bool mid = s->mid_tx > 0;
@@ -1050,14 +1084,16 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     launch_diag_clear(Tc, s->nruns, st);
     CHK(last_launch("diag clear"));
   }
-  // (the charge arrays are only written, and so only cleared, on diagnostic steps)
+  // (the charge arrays are only written, and so only cleared, by the steps that accumulate
+  // charge: both on a diagnostic step, rho0 before it and rho1 on it with chained charge)
   if (first_full && mid) {
-    launch_clear_sources(Tc, s->prec, s->ndim, s->nblk_cells, diag ? 1 : 0, bands.parity,
+    launch_clear_sources(Tc, s->prec, s->ndim, s->nblk_cells, rho == 1 ? 1 : 0, bands.parity,
                          s->laser_bpr > 0 ? s->step_dev : nullptr, st);
     CHK(last_launch("clear sources"));
   } else {
     // field half update t -> t + dt/2 (E first), clearing J for the deposit
-    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, diag ? 1 : 2,
+    const int zero = rho == 1 ? 1 : (rho == 2 ? 3 : (rho == 3 ? 4 : 2));
+    launch_yee(Tc, s->prec, s->ndim, s->nblk_cells, 0, first_full ? 1.0 : 0.5, zero,
                first_full ? 2 : 1, st);
     CHK(last_launch("yee E"));
     // a step whose last field updates go to the fused update publishes the tile edges
@@ -1108,10 +1144,13 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
       esc.count = s->esc_count;
       esc.total = s->escapes;
       esc.capacity = s->esc_capacity;
-      launch_fused(Tc, s->prec, s->ndim, diag ? s->geo_rho : s->geo,
-                   fused_grid(s->max_chunks, diag ? s->blocks_per_cu_rho : s->blocks_per_cu),
-                   diag ? s->smem_rho : s->smem, s->chunks, s->nchunks, diag ? 1 : 0, nullptr,
-                   diag ? 1 : 0, esc, s->jshift, st, s->rebin ? &s->rb : nullptr);
+      const int geo = rho == 0 ? s->geo : (rho == 1 ? s->geo_rho : s->geo_chain);
+      const int bpc = rho == 0 ? s->blocks_per_cu
+                    : (rho == 1 ? s->blocks_per_cu_rho : s->blocks_per_cu_chain);
+      const size_t smem = rho == 0 ? s->smem : (rho == 1 ? s->smem_rho : s->smem_chain);
+      launch_fused(Tc, s->prec, s->ndim, geo, fused_grid(s->max_chunks, bpc), smem, s->chunks,
+                   s->nchunks, rho, nullptr, diag ? 1 : 0, esc, s->jshift, st,
+                   s->rebin ? &s->rb : nullptr);
       CHK(last_launch("fused"));
       if (s->timing) {
         HIPCHK(hipEventRecord(e1, st));
@@ -1307,6 +1346,10 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
   CHK(run_hooks(s, LPIC_STAGE_START));
   if (nsteps > 0) CHK(enqueue_fixed_shift(s, s->stream));
   const bool hooks = any_hooks(s);
+  // chained charge inside this call (no hooks, so nothing looks at or moves the particles
+  // between the two steps of a chain)
+  const bool chain = s->chain && !hooks && !split && s->opt.diag_interval >= 2;
+  int prev_rho = 0;
   bool e_half_pending = false;
   for (int n = 0; n < nsteps; ++n) {
     CHK(run_hooks(s, LPIC_STAGE_LOOP_START));
@@ -1314,6 +1357,9 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
     const bool always_spread = (s->opt.tiling.flags & LPIC_SORT_SPREAD) != 0;
     const bool spread = do_sort && (s->need_spread || always_spread);
     const bool diag = s->opt.diag_interval > 0 && ((s->step + 1) % s->opt.diag_interval) == 0;
+    const bool pre_diag = chain && n + 1 < nsteps && ((s->step + 2) % s->opt.diag_interval) == 0;
+    const int rho = diag ? (prev_rho == 2 ? 3 : 1) : (pre_diag ? 2 : 0);
+    prev_rho = rho;
     // inside one call, with no hooks that could look at the fields between steps, a step
     // that ends without diagnostics leaves its last E half to the next step
     const bool first_full = e_half_pending;
@@ -1322,12 +1368,13 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
     // the one-off spreading sort runs eagerly; captured sort steps use the plain sort unless
     // every sort spreads
     if (use_graph && (!spread || always_spread)) {
-      const int gi = (do_sort ? 8 : 0) + (diag ? 4 : 0) + (first_full ? 2 : 0) + (skip_last ? 1 : 0);
+      const int gi = rho * 16 + (do_sort ? 8 : 0) + (diag ? 4 : 0) + (first_full ? 2 : 0) +
+                     (skip_last ? 1 : 0);
       if (!s->gexec[gi]) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
         lpic_status st = enqueue_step(s, s->cap_stream, do_sort, spread, diag, false, true,
-                                      first_full, skip_last);
+                                      first_full, skip_last, rho);
         hipError_t ee = hipStreamEndCapture(s->cap_stream, &g);
         if (st != LPIC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
         if (ee != hipSuccess) return fail(LPIC_EHIP, "graph capture: %s", hipGetErrorString(ee));
@@ -1338,7 +1385,8 @@ lpic_status lpic_step(lpic_sim* s, int32_t nsteps) {
       HIPCHK(hipGraphLaunch(s->gexec[gi], s->stream));
       if (do_sort && s->nsegs > 0) swap_host_buffers(s);
     } else {
-      CHK(enqueue_step(s, s->stream, do_sort, spread, diag, true, false, first_full, skip_last));
+      CHK(enqueue_step(s, s->stream, do_sort, spread, diag, true, false, first_full, skip_last,
+                       rho));
     }
     if (do_sort && s->nsegs > 0) {
       ++s->sorts;

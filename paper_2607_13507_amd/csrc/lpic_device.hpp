@@ -325,6 +325,11 @@ struct LdsAcc {
   }
 };
 
+// The charge planes a fused pass accumulates for a with_rho mode (see deposit).
+__host__ __device__ constexpr int charge_planes(int with_rho) {
+  return with_rho == 1 ? 2 : (with_rho >= 2 ? 1 : 0);
+}
+
 // ---------------------------------------------------------------------------------------
 // Interpolation (Sec. 3.1): every component from its own staggered nodes.
 // 2D:  Ex (h,i)  Ey (i,h)  Ez (i,i)  Bx (i,h)  By (h,i)  Bz (h,h)
@@ -633,9 +638,12 @@ __device__ __forceinline__ PushConst<R> push_const(const RunDesc& r, const SegDe
 // first W-1 nodes of every axis (and, along a running sum, before its last node) are the
 // ones a path that keeps its nearest node fills: they go through add_core; the others are
 // exactly zero for such a path and go through add, which skips zeros.
+// with_rho: 0 no charge; 1 the charge at both ends of the path (rho0 at x0, rho1 at x1);
+// 2 or 3 only the charge at the path's end, into rho0 (2) or rho1 (3) -- through the
+// on-chip accessor into its single charge plane, which sits in rho0's place (charge_planes).
 template <int DIM, int ORDER, typename R, class Acc>
 __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0, const R* x1,
-                                        R w, R vz_bar, const PushConst<R>& k, bool with_rho) {
+                                        R w, R vz_bar, const PushConst<R>& k, int with_rho) {
   constexpr int W = ORDER + 2;
   R S0x[W], S1x[W], S0y[W], S1y[W], S0z[W], S1z[W];
   int bx, by, bz = 0;
@@ -723,21 +731,23 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
           a1[i] = s1x ? S1x[i + 1] : S1x[i]; b1[i] = s1y ? S1y[i + 1] : S1y[i];
         }
         const int o0 = xo[0] + s0x + A.yo(s0y), o1 = xo[0] + s1x + A.yo(s1y);
+        const bool both = with_rho == 1;
 #pragma unroll
         for (int b = 0; b < N; ++b)
 #pragma unroll
           for (int a = 0; a < N; ++a) {
-            A.add_core(F_R0, o0 + A.yo(b) + a, qw * a0[a] * b0[b]);
-            A.add_core(F_R1, o1 + A.yo(b) + a, qw * a1[a] * b1[b]);
+            if (both) A.add_core(F_R0, o0 + A.yo(b) + a, qw * a0[a] * b0[b]);
+            A.add_core(both ? F_R1 : F_R0, o1 + A.yo(b) + a, qw * a1[a] * b1[b]);
           }
       } else {
+        const int end = with_rho == 2 ? F_R0 : F_R1;
 #pragma unroll
         for (int b = 0; b < W; ++b)
 #pragma unroll
           for (int a = 0; a < W; ++a) {
             if ((a == W - 1 && !lx) || (b == W - 1 && !ly)) continue;
-            A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
-            A.add(F_R1, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
+            if (with_rho == 1) A.add(F_R0, yo[b] + xo[a], qw * S0x[a] * S0y[b]);
+            A.add(end, yo[b] + xo[a], qw * S1x[a] * S1y[b]);
           }
       }
     }
@@ -818,6 +828,7 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
         }
         const int o0 = xo[0] + s0x + A.yo(s0y) + A.zo(s0z);
         const int o1 = xo[0] + s1x + A.yo(s1y) + A.zo(s1z);
+        const bool both = with_rho == 1;
 #pragma unroll
         for (int cc = 0; cc < N; ++cc)
 #pragma unroll
@@ -825,10 +836,11 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
 #pragma unroll
             for (int a = 0; a < N; ++a) {
               const int off = A.zo(cc) + A.yo(b) + a;
-              A.add_core(F_R0, o0 + off, qw * a0[a] * b0[b] * c0[cc]);
-              A.add_core(F_R1, o1 + off, qw * a1[a] * b1[b] * c1[cc]);
+              if (both) A.add_core(F_R0, o0 + off, qw * a0[a] * b0[b] * c0[cc]);
+              A.add_core(both ? F_R1 : F_R0, o1 + off, qw * a1[a] * b1[b] * c1[cc]);
             }
       } else {
+        const int end = with_rho == 2 ? F_R0 : F_R1;
 #pragma unroll
         for (int cc = 0; cc < W; ++cc)
 #pragma unroll
@@ -837,8 +849,8 @@ __device__ __forceinline__ void deposit(const Acc& A, const int* c, const R* x0,
             for (int a = 0; a < W; ++a) {
               if ((a == W - 1 && !lx) || (b == W - 1 && !ly) || (cc == W - 1 && !lz)) continue;
               const int off = zo[cc] + yo[b] + xo[a];
-              A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
-              A.add(F_R1, off, qw * S1x[a] * S1y[b] * S1z[cc]);
+              if (with_rho == 1) A.add(F_R0, off, qw * S0x[a] * S0y[b] * S0z[cc]);
+              A.add(end, off, qw * S1x[a] * S1y[b] * S1z[cc]);
             }
       }
     }

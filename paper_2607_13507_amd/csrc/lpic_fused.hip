@@ -22,18 +22,20 @@ namespace lpic {
 // region, charge planes included, still fits the LDS.  Geometry 7 (8 x 4 x 4 tiles, halo 3)
 // runs 512-thread workgroups, two per CU: it is also the second pass of the re-binned
 // escape path for 8 x 4 x 4 tilings with halo 4 (its particles lie inside their present
-// tile, so a halo of 3 always holds their stencils).  Geometry 8 is the same region with
-// 1024-thread workgroups, for FP32 diagnostic steps: their charge planes leave room for one
-// workgroup per CU, which then brings all sixteen waves by itself.
+// tile, so a halo of 3 always holds their stencils).  Geometry 8 is the same region without
+// the layer pad, for the FP32 steps that carry one charge plane (chained charge, see
+// k_fused): it still fits two 512-thread workgroups per CU (80.7 KB each).  Geometry 9 is
+// the padded region with 1024-thread workgroups, for FP32 steps with both charge planes:
+// they leave room for one workgroup per CU, which then brings all sixteen waves by itself.
 struct GeoFix { int tx, ty, tz, halo, pz; };
 __host__ __device__ constexpr GeoFix geo_table(int g) {
   return g == 1 ? GeoFix{16, 16, 1, 5, 0} : g == 2 ? GeoFix{8, 8, 1, 5, 0}
        : g == 3 ? GeoFix{32, 32, 1, 5, 0} : g == 4 ? GeoFix{16, 16, 1, 4, 0}
        : g == 5 ? GeoFix{8, 4, 4, 4, 4} : g == 6 ? GeoFix{8, 8, 4, 4, 8}
-       : g == 7 ? GeoFix{8, 4, 4, 3, 8} : g == 8 ? GeoFix{8, 4, 4, 3, 8}
-       : GeoFix{0, 0, 0, 0, 0};
+       : g == 7 ? GeoFix{8, 4, 4, 3, 8} : g == 8 ? GeoFix{8, 4, 4, 3, 0}
+       : g == 9 ? GeoFix{8, 4, 4, 3, 8} : GeoFix{0, 0, 0, 0, 0};
 }
-constexpr int NUM_GEO = 9;   // fused_geometry() returns the first match: 7, never 8
+constexpr int NUM_GEO = 10;   // fused_geometry() returns the first match: 7, never 8 or 9
 
 template <int DIM, int G>
 struct GeoStrides {
@@ -161,13 +163,16 @@ __device__ __forceinline__ void stage_region(const RunDesc& r, const Region& g, 
 }
 
 // Add the region's current (and charge) into the global arrays: one atomic per non-zero
-// entry, converted to the field precision (FP32 path: from fixed point, times 2^-S).
+// entry, converted to the field precision (FP32 path: from fixed point, times 2^-S).  With
+// a single charge plane (with_rho 2 or 3) it goes to rho0 or rho1.
 template <typename R, class S>
 __device__ __forceinline__ void flush_region(const RunDesc& r, const Region& g, const S& st,
-                                             int njplanes, const double* jm, double unscale) {
+                                             int njplanes, const double* jm, double unscale,
+                                             int with_rho) {
   gptr<R> F[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) F[c] = gp((R*)r.f[F_JX + c]);
+  if (with_rho == 3) F[3] = gp((R*)r.f[F_R1]);
   const int plane = st.plane();
   const int ncell = g.rw[0] * g.rw[1] * g.rw[2];
   const RegionWrap w = region_wrap(r, g);
@@ -244,16 +249,16 @@ constexpr int batch_of() { return DIM == 3 ? 1 : (sizeof(R) == 4 ? 4 : 1); }
 // 3D FP32 geometry fit 4 (at most 128 VGPRs), the others keep the compiler's choice.
 template <typename R, int DIM, int G>
 constexpr int fused_waves() {
-  return (sizeof(R) == 4 && (DIM == 2 || G == 7 || G == 8)) ? 4 : 1;
+  return (sizeof(R) == 4 && (DIM == 2 || G >= 7)) ? 4 : 1;
 }
 
 // Threads per workgroup: a 3D region (tile + halo on three axes) fills most of a CU's LDS,
 // so one workgroup per CU must bring enough waves by itself: 16 (four per SIMD) in FP32, whose
 // quadratic particle loop fits 128 VGPRs; 8 in FP64, which needs more registers per lane.
-// Geometry 7's smaller region lets two 512-thread workgroups share a CU.
+// The smaller regions of geometries 7 and 8 let two 512-thread workgroups share a CU.
 template <typename R, int DIM, int G>
 constexpr int fused_block() {
-  return DIM == 2 ? 256 : (sizeof(R) == 8 || G == 7 ? 512 : 1024);
+  return DIM == 2 ? 256 : (sizeof(R) == 8 || G == 7 || G == 8 ? 512 : 1024);
 }
 
 // pl.list != NULL (the second pass of the re-binned escape path): the chunk's range indexes
@@ -316,7 +321,7 @@ __device__ __forceinline__ bool push_on_chip(const RunDesc& r, const Region& g, 
   push_rest<DIM, ORDER>(L, pcell, po, xh, ps, k, pe, x1, vz1, g1);
   if (check) fit = deposit_fits<DIM, ORDER>(pcell, po, pe, lim);
   if (!fit) return false;
-  deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+  deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
   if (leaves_box(r, ps.c[0])) ps.alive = false;
@@ -334,7 +339,7 @@ __device__ __forceinline__ bool push_on_chip(const RunDesc& r, const Region& g, 
 // particles of the workgroup are then packed into the first threads (their slots pass
 // through LDS) and pushed there, so no wave carries idle lanes for escaped particles; the
 // escaped ones are appended to the escape list with one global reservation per round.
-// cbuf: 2 blockDim + 64 words of LDS.
+// cbuf: blockDim + 64 words of LDS.
 template <typename R, int DIM, int ORDER, class LA>
 __device__ __forceinline__ double process_chunk_compact(
     const RunDesc& r, const SegDesc& s, int seg, const Chunk& ch, const Region& g, const LA& L,
@@ -344,10 +349,10 @@ __device__ __forceinline__ double process_chunk_compact(
   const PartPtrs<R> q = part_ptrs<R>(s, r);
   const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
   const int lane = __lane_id(), wv = tid >> 6, nw = bd >> 6;
-  int32_t* cin = cbuf;                 // the on-chip particles (slots; list indexes when
-                                       // their records are read), packed
-  int32_t* cesc = cbuf + bd;           // slots of the escaped ones, packed
-  int32_t* wsum = cbuf + 2 * bd;       // per wave: on-chip and escaped counts -> bases;
+  // one list of bd entries: the on-chip particles (slots; list indexes when their records
+  // are read) packed from the front, the slots of the escaped ones from the back
+  int32_t* cin = cbuf;
+  int32_t* wsum = cbuf + bd;           // per wave: on-chip and escaped counts -> bases;
                                        // [2 nw], [2 nw + 1]: totals; [2 nw + 2]: list base
   double ke = 0.0;
   for (int32_t base = ch.beg; base < ch.end; base += bd) {
@@ -363,7 +368,7 @@ __device__ __forceinline__ double process_chunk_compact(
     const bool gone = alive && !inside;
     const uint64_t mi = __ballot(inside), me = __ballot(gone);
     const uint64_t below = (1ull << lane) - 1ull;
-    __syncthreads();                   // the previous round has read cin / cesc / wsum
+    __syncthreads();                   // the previous round has read the list and wsum
     if (lane == 0) {
       wsum[wv] = __popcll(mi);
       wsum[nw + wv] = __popcll(me);
@@ -384,14 +389,15 @@ __device__ __forceinline__ double process_chunk_compact(
     }
     __syncthreads();
     if (inside) cin[wsum[wv] + __popcll(mi & below)] = pl.rec ? lp : slot;
-    if (gone) cesc[wsum[nw + wv] + __popcll(me & below)] = slot;
+    if (gone) cbuf[bd - 1 - (wsum[nw + wv] + __popcll(me & below))] = slot;
     __syncthreads();
     const int n_in = wsum[2 * nw], n_esc = wsum[2 * nw + 1];
     const int64_t ebase = (int64_t)(uint32_t)wsum[2 * nw + 2];
     for (int e = tid; e < n_esc; e += bd)
       if (ebase + e < esc.capacity) {
-        esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)cesc[e];
-        if (esc.rec) escape_record<R, DIM>(esc, ebase + e, r, s, q, cesc[e]);
+        const int32_t es = cbuf[bd - 1 - e];
+        esc.items[ebase + e] = ((unsigned long long)seg << 32) | (unsigned long long)(uint32_t)es;
+        if (esc.rec) escape_record<R, DIM>(esc, ebase + e, r, s, q, es);
       }
     bool late = false;                 // on chip by its cell, not by its own path
     int32_t p = 0;
@@ -535,12 +541,12 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
     st.ey_ = rh;
   }
   const int plane = st.plane();
-  const int njplanes = 3 + (with_rho ? 2 : 0);
+  const int njplanes = 3 + charge_planes(with_rho);
   // the current planes follow the six field planes; 6 plane values of 4 or 8 bytes end on an
   // 8-byte boundary, as the 64-bit LDS atomics need
   double* jm = (double*)(sm + 6 * plane);
-  // 3D: the round compaction's slot lists after the current (and charge) planes
-  int32_t* cbuf = (int32_t*)(jm + (size_t)(3 + (with_rho ? 2 : 0)) * plane);
+  // 3D: the round compaction's slot list after the current (and charge) planes
+  int32_t* cbuf = (int32_t*)(jm + (size_t)njplanes * plane);
   LdsAcc<R, ST, DIM == 2> L;
   L.fbase = sm;
   L.jbase = jm;
@@ -562,7 +568,7 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
       if (cur_run >= 0) {
         const RunDesc& rp = run_of(T, cur_run);
         __syncthreads();
-        flush_region<R>(rp, g, st, njplanes, jm, unscale);
+        flush_region<R>(rp, g, st, njplanes, jm, unscale, with_rho);
         if (kinetic || ke_to_diag) {
           const double t = block_sum(ke, red);
           if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rp.diag + DIAG_UKIN : kinetic, t);
@@ -585,12 +591,12 @@ __global__ __launch_bounds__((fused_block<R, DIM, G>())) __attribute__((amdgpu_w
     const RunDesc r = run_of(T, s.run);
     const bool want_ke = kinetic || ke_to_diag;
     ke += s.order == 1
-              ? process_chunk<R, DIM, 1, G == 7 || G == 8>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
-              : process_chunk<R, DIM, 2, G == 7 || G == 8>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
+              ? process_chunk<R, DIM, 1, (G >= 7)>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf)
+              : process_chunk<R, DIM, 2, (G >= 7)>(r, s, ch.seg, ch, g, L, with_rho, want_ke, esc, pl, cbuf);
   }
   const RunDesc& rl = run_of(T, cur_run);
   __syncthreads();
-  flush_region<R>(rl, g, st, njplanes, jm, unscale);
+  flush_region<R>(rl, g, st, njplanes, jm, unscale, with_rho);
   if (kinetic || ke_to_diag) {
     const double t = block_sum(ke, red);
     if (threadIdx.x == 0) atomic_add_global(ke_to_diag ? rl.diag + DIAG_UKIN : kinetic, t);
@@ -610,7 +616,7 @@ __device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s,
   int pcell[3];
   R po[3], pe[3], x1[3], vz1, g1;
   push<DIM, ORDER>(G, ps.c, ps, k, pcell, po, pe, x1, vz1, g1);
-  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho != 0);
+  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho);
   const int n[3] = {r.nx, r.ny, r.nz};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
@@ -693,6 +699,7 @@ static void launch_fused_d(int geo, const Tables& T, int nblocks, size_t smem,
       case 6: LPIC_GEO(6); return;
       case 7: LPIC_GEO(7); return;
       case 8: LPIC_GEO(8); return;
+      case 9: LPIC_GEO(9); return;
       default: LPIC_GEO(0); return;
     }
   }
@@ -710,7 +717,7 @@ void launch_fused(const Tables& T, int prec, int dim, int geo, int nblocks, size
     // escapees by present tile, a second pass over them, then whatever that pass could not
     // place (normally nothing) through global memory
     launch_rebin(T, prec, dim, esc, *rb, st);
-    const int k = with_rho ? 1 : 0;
+    const int k = with_rho == 0 ? 0 : (with_rho == 1 ? 1 : 2);
     LPIC_PD(prec, dim, (launch_fused_d<R, D>(rb->geo[k], T, rb->grid[k], rb->smem[k], rb->chunks,
                                              rb->nchunks, with_rho, kinetic, ke_to_diag,
                                              rb->esc2, jshift,
@@ -754,6 +761,7 @@ hipError_t prepare_fused(int prec, int dim, int geo, size_t smem, size_t smem_oc
       case 6: e = prec == 0 ? set_smem<float, 3, 6>(smem, smem_occ, b) : set_smem<double, 3, 6>(smem, smem_occ, b); break;
       case 7: e = prec == 0 ? set_smem<float, 3, 7>(smem, smem_occ, b) : set_smem<double, 3, 7>(smem, smem_occ, b); break;
       case 8: e = prec == 0 ? set_smem<float, 3, 8>(smem, smem_occ, b) : set_smem<double, 3, 8>(smem, smem_occ, b); break;
+      case 9: e = prec == 0 ? set_smem<float, 3, 9>(smem, smem_occ, b) : set_smem<double, 3, 9>(smem, smem_occ, b); break;
       default: e = prec == 0 ? set_smem<float, 3, 0>(smem, smem_occ, b) : set_smem<double, 3, 0>(smem, smem_occ, b); break;
     }
   }
@@ -770,13 +778,13 @@ size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int
   // six field planes in the kernel precision (24 or 48 bytes per cell: the current planes
   // after them start 8-byte aligned), then 8-byte current planes (and, on diagnostic steps,
   // two charge planes)
-  const int jplanes = 3 + (with_rho ? 2 : 0);
+  const int jplanes = 3 + charge_planes(with_rho);
   static_assert((6 * sizeof(float)) % 8 == 0, "current planes must start 8-byte aligned");
-  // 3D: the round compaction's two slot lists and wave sums (process_chunk_compact)
-  const int block = geo == 7 ? fused_block<float, 3, 7>()
+  // 3D: the round compaction's slot list and wave sums (process_chunk_compact)
+  const int block = (geo == 7 || geo == 8) ? fused_block<float, 3, 7>()
                   : prec == 0 ? fused_block<float, 3, 0>() : fused_block<double, 3, 0>();
-  // (geometry 8 has the default 3D blocks: 1024 threads FP32, 512 FP64)
-  const size_t compact = dim == 3 ? (2 * (size_t)block + 64) * 4 : 0;
+  // (geometry 9 has the default 3D blocks: 1024 threads FP32, 512 FP64)
+  const size_t compact = dim == 3 ? ((size_t)block + 64) * 4 : 0;
   return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8 + compact;
 }
 

@@ -37,7 +37,8 @@ struct FieldBands {
 constexpr int MID_MAX_TX = 64, MID_MAX_TY = 16;
 inline int64_t band_values_per_tile(int tx, int ty) { return 6 * 3 * (int64_t)(tx + ty); }
 
-// which = 0: E update (zero_j = 1 also clears J and rho, 2 J only), 1: B update.  halves = 2: the E
+// which = 0: E update (zero_j = 1 also clears J and rho, 2 J only, 3 J and rho0, 4 J and
+// rho1), 1: B update.  halves = 2: the E
 // update stands for two equal half updates (open x ends apply their condition twice).
 // bands (B update in 2D only, may be NULL): also publish E and the new B of the tile edges
 // into the snapshot buffer named by *parity, for a fused update that follows.
@@ -117,9 +118,9 @@ struct Rebin {
   Chunk* chunks;
   int32_t* nchunks;
   EscapeList esc2;             // particles the second pass finds outside its regions
-  int geo[2];                  // the second pass's geometry (fused_geometry()), grid and
-  int grid[2];                 // dynamic LDS without / with the charge planes
-  size_t smem[2];
+  int geo[3];                  // the second pass's geometry (fused_geometry()), grid and
+  int grid[3];                 // dynamic LDS without charge, with both charge planes, and
+  size_t smem[3];              // with one (the with_rho modes of the first pass)
 };
 
 // geometry: 0 = runtime strides, else a compiled (tile, halo) shape (fused_geometry()).

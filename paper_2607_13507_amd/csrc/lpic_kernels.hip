@@ -193,12 +193,13 @@ __global__ __launch_bounds__(256) void k_yee_e(Tables T, double frac, int zero_j
     f[F_EY][x.c] += dey;
     f[F_EZ][x.c] += dez;
   }
-  if (zero_j) {   // 1: clear J (and the charge arrays when given); 2: J only
+  if (zero_j) {   // 1: clear J and the charge arrays (when given); 2: J only; 3: J and
+                  // rho0; 4: J and rho1
     f[F_JX][x.c] = R(0);
     f[F_JY][x.c] = R(0);
     f[F_JZ][x.c] = R(0);
-    if (zero_j == 1 && f[F_R0]) f[F_R0][x.c] = R(0);
-    if (zero_j == 1 && f[F_R1]) f[F_R1][x.c] = R(0);
+    if ((zero_j == 1 || zero_j == 3) && f[F_R0]) f[F_R0][x.c] = R(0);
+    if ((zero_j == 1 || zero_j == 4) && f[F_R1]) f[F_R1][x.c] = R(0);
   }
 }
 
@@ -859,7 +860,7 @@ __device__ __forceinline__ void deposit_one(const SegDesc& s, const RunDesc& r, 
 #pragma unroll
   for (int d = 0; d < 3; ++d) pe[d] = d < DIM ? o0[d] + R(2) * (hd[d] * now.u[d] * ig1) : R(0);
   const GlobalAcc<R> A = global_acc<R>(r);
-  deposit<DIM, ORDER>(A, c0, o0, pe, now.w, now.u[2] * ig1, k, with_rho);
+  deposit<DIM, ORDER>(A, c0, o0, pe, now.w, now.u[2] * ig1, k, with_rho ? 1 : 0);
   if (leaves_box(r, now.c[0])) {   // its new position is in an open end's margin
     now.alive = false;
     store_particle<R, DIM>(s, r, (int32_t)p, now);

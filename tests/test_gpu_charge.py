@@ -70,3 +70,42 @@ def test_charge_matches_oracle(ndim, prec, order, rebin):
     assert d["continuity"] < (1e-12 if prec == L.F64_ABS else 1e-5), d
     assert d["gauss"] == pytest.approx(np.abs(orc.gauss()).max(), rel=1e-8 if prec == L.F64_ABS else 1e-4)
     sim.close()
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("rebin", [False, True], ids=["escape", "rebin"])
+def test_chained_charge_matches_oracle(rebin, graph):
+    """3D FP32 in a periodic box with 8 x 4 x 4 tiles and halo 3: inside one call, the step
+    before a diagnostic step accumulates the charge at its paths' ends into rho0 and the
+    diagnostic step its own into rho1 (chained charge).  Against the oracle stepped from the
+    GPU's state through the same two steps, and against the same run taken one step per call
+    (no chain: the diagnostic step accumulates both planes)."""
+    banner(f"chained charge rebin={rebin} graph={graph}")
+    wl = W.thermal_3d(n=24, dx=0.1, ppc=4, T=0.5, order=2, seed=13)
+    kw = dict(prec=L.F32_CELLOFS, tiling=(8, 4, 4), halo=3, chunk=256, sort_interval=1000,
+              diag_interval=4, use_graph=graph, flags=L.ESCAPE_REBIN if rebin else 0)
+    sim = Simulation(wl, **kw)
+    one = Simulation(wl, **kw)
+    sim.step(10)                       # steps 0-9 (diagnostics after steps 3 and 7)
+    for _ in range(10):
+        one.step(1)
+    torch.cuda.synchronize()
+    orc = _oracle_from(sim, wl)
+    sim.step(2)                        # step 10 (before a diagnostic step) and step 11
+    for _ in range(2):
+        one.step(1)
+    orc.step(2)
+    torch.cuda.synchronize()
+    assert sim.diagnostics(0)["step"] == 12
+    compare_fields(sim.fields[0], orc, L.F32_CELLOFS, keys=("rho0", "rho1", "jx", "jy", "jz"),
+                   tol=2e-5, what="chained charge vs oracle")
+    d, d1 = sim.diagnostics(0), one.diagnostics(0)
+    assert d["continuity"] < 1e-5 and d1["continuity"] < 1e-5, (d, d1)
+    a, b = sim.fields[0].numpy(), one.fields[0].numpy()
+    for k in ("rho0", "rho1"):
+        err = np.abs(a[k].astype(np.float64) - b[k]).max() / np.abs(b[k]).max()
+        assert err < 1e-5, (k, err)
+    assert d["gauss"] == pytest.approx(d1["gauss"], rel=1e-4)
+    assert d["kinetic_energy"] == pytest.approx(d1["kinetic_energy"], rel=1e-6)
+    sim.close()
+    one.close()
