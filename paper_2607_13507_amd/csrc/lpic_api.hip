@@ -654,12 +654,14 @@ struct lpic_sim {
   size_t smem = 0, smem_rho = 0;
   int geo = 0;
   int geo_rho = 0;                  // the geometry of diagnostic steps (charge planes)
-  // Chained charge (3D FP32, boxes periodic along x, 8 x 4 x 4 tiles with halo 3): the step
-  // before a diagnostic step accumulates the charge at the ends of its paths into rho0, and
-  // the diagnostic step only the charge at the ends of its own paths, into rho1.  A path
-  // ends half a step past the stored position (x^n + (dt/2) v^n) and the next step's path
-  // starts at the same point, so rho0 of the diagnostic step is that charge; each of the two
-  // steps then carries one 64-bit charge plane and keeps two workgroups per CU.
+  // Chained charge (3D FP32 with 8 x 4 x 4 tiles and halo 3): the step before a
+  // diagnostic step accumulates the charge at the ends of its paths into rho0, leaving out
+  // the particles that leave the box, and the diagnostic step only the charge at the ends of
+  // its own paths, into rho1.  A path ends half a step past the stored position
+  // (x^n + (dt/2) v^n) and the next step's path starts at the same point, so rho0 of the
+  // diagnostic step is that charge; each of the two steps then carries one charge plane
+  // instead of two on one step, which keeps the occupancy of the other steps (3D FP32 on an
+  // unpadded geometry: two workgroups per CU).
   bool chain = false;
   int geo_chain = 0;
   size_t smem_chain = 0;
@@ -779,6 +781,8 @@ size_t pml_psi_bytes(const lpic_grid* g, int cells, int prec) {
   return (size_t)2 * 4 * g->ny * (g->ndim == 3 ? g->nz : 1) * 2 * cells *
          (prec == LPIC_F32_CELLOFS ? 4 : 8);
 }
+
+size_t lds_of_geometry(const lpic_sim* s, int g);
 
 lpic_status configure(lpic_sim* s) {
   drop_graphs(s);
@@ -904,23 +908,25 @@ lpic_status configure(lpic_sim* s) {
   // workgroup per CU, which then runs 1024 threads (geometry 8) instead of 512
   s->geo_rho = (s->prec == LPIC_F32_CELLOFS && s->geo == 7) ? 9 : s->geo;
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1, s->geo_rho);
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_rho, s->smem_rho, s->smem_rho,
-                       &s->blocks_per_cu_rho));
-  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, std::max(s->smem, s->geo == s->geo_rho ? s->smem_rho : 0),
-                       s->smem, &s->blocks_per_cu));
   {
-    // (no particle leaves a box that is periodic along x, so the charge at the end of a
-    // step's paths is the charge at the start of the next step's paths)
-    bool periodic = true;
-    for (int r = 0; r < s->nruns; ++r) periodic = periodic && !s->runs_h[r].open_x;
-    s->chain = s->prec == LPIC_F32_CELLOFS && s->ndim == 3 && s->geo == 7 && periodic;
-    if (s->chain) {
-      s->geo_chain = 8;
-      s->smem_chain = fused_smem_bytes(s->prec, 3, 8, 4, 4, 3, 2, 8);
-      HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_chain, s->smem_chain, s->smem_chain,
-                           &s->blocks_per_cu_chain));
-    }
+    // (FP32 only: FP64 positions are absolute, and the start of the next step's path,
+    // found again from the stored position, rounds at the scale of the box length -- about
+    // 1e-11 of a cell in a box of 65536 cells, above the FP64 continuity that the two planes
+    // of one step keep.  3D only: a 2D region keeps its occupancy with both planes less one
+    // workgroup per CU, and splitting the charge adds over two steps measured no faster.)
+    const bool f32_3d = s->prec == LPIC_F32_CELLOFS && s->ndim == 3;
+    s->chain = f32_3d && s->geo == 7;
+    s->geo_chain = f32_3d && s->geo == 7 ? 8 : s->geo;
+    s->smem_chain = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 2,
+                                     s->geo_chain);
   }
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_rho, lds_of_geometry(s, s->geo_rho),
+                       s->smem_rho, &s->blocks_per_cu_rho));
+  HIPCHK(prepare_fused(s->prec, s->ndim, s->geo, lds_of_geometry(s, s->geo), s->smem,
+                       &s->blocks_per_cu));
+  if (s->chain)
+    HIPCHK(prepare_fused(s->prec, s->ndim, s->geo_chain, lds_of_geometry(s, s->geo_chain),
+                         s->smem_chain, &s->blocks_per_cu_chain));
   HIPCHK(hipMemcpy(s->step_dev, &s->step, sizeof(int64_t), hipMemcpyHostToDevice));
   // fused 2D field update between steps: the largest field tile dividing every box
   free_dev(s->mid_pfx_d);
@@ -1004,13 +1010,9 @@ lpic_status configure(lpic_sim* s) {
     rb.geo[2] = s->chain ? s->geo_chain : rb.geo[1];
     rb.smem[2] = s->chain ? s->smem_chain : rb.smem[1];
     int bpc[3] = {1, 1, 1};
-    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[1], rb.smem[1], rb.smem[1], &bpc[1]));
-    HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[0],
-                         std::max(rb.smem[0], rb.geo[0] == rb.geo[1] ? rb.smem[1] : 0),
-                         rb.smem[0], &bpc[0]));
-    bpc[2] = bpc[1];
-    if (s->chain)
-      HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[2], rb.smem[2], rb.smem[2], &bpc[2]));
+    for (int k = 0; k < 3; ++k)
+      HIPCHK(prepare_fused(s->prec, s->ndim, rb.geo[k], lds_of_geometry(s, rb.geo[k]),
+                           rb.smem[k], &bpc[k]));
     rb.grid[0] = fused_grid(maxch, bpc[0]);
     rb.grid[1] = fused_grid(maxch, bpc[1]);
     rb.grid[2] = fused_grid(maxch, bpc[2]);
@@ -1087,7 +1089,8 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
   // (the charge arrays are only written, and so only cleared, by the steps that accumulate
   // charge: both on a diagnostic step, rho0 before it and rho1 on it with chained charge)
   if (first_full && mid) {
-    launch_clear_sources(Tc, s->prec, s->ndim, s->nblk_cells, rho == 1 ? 1 : 0, bands.parity,
+    const int zero = rho == 1 ? 1 : (rho == 2 ? 3 : (rho == 3 ? 4 : 0));
+    launch_clear_sources(Tc, s->prec, s->ndim, s->nblk_cells, zero, bands.parity,
                          s->laser_bpr > 0 ? s->step_dev : nullptr, st);
     CHK(last_launch("clear sources"));
   } else {
@@ -1212,6 +1215,18 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
     CHK(last_launch("reduce"));
   }
   return LPIC_OK;
+}
+
+// The largest dynamic LDS that any launch of fused geometry g asks for in this simulation:
+// the attribute belongs to the kernel instance, so it must cover every use of it.
+size_t lds_of_geometry(const lpic_sim* s, int g) {
+  size_t m = 0;
+  if (g == s->geo) m = std::max(m, s->smem);
+  if (g == s->geo_rho) m = std::max(m, s->smem_rho);
+  if (s->chain && g == s->geo_chain) m = std::max(m, s->smem_chain);
+  for (int k = 0; k < 3; ++k)
+    if (s->rb.smem[k] && g == s->rb.geo[k]) m = std::max(m, s->rb.smem[k]);
+  return m;
 }
 
 lpic_status ensure_old_state(lpic_sim* s) {

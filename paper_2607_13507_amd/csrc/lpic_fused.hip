@@ -321,10 +321,12 @@ __device__ __forceinline__ bool push_on_chip(const RunDesc& r, const Region& g, 
   push_rest<DIM, ORDER>(L, pcell, po, xh, ps, k, pe, x1, vz1, g1);
   if (check) fit = deposit_fits<DIM, ORDER>(pcell, po, pe, lim);
   if (!fit) return false;
-  deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
   if (leaves_box(r, ps.c[0])) ps.alive = false;
+  // (with_rho 2: the charge where the next step's paths start; a particle leaving the box
+  // has none there)
+  deposit<DIM, ORDER>(L, pcell, po, pe, ps.w, vz1, k, with_rho == 2 && !ps.alive ? 0 : with_rho);
   store_particle<R, DIM>(q, slot, ps);
   if (want_ke && ps.alive) {   // diagnostic steps only
     const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] +
@@ -616,11 +618,11 @@ __device__ __forceinline__ double escape_one(const RunDesc& r, const SegDesc& s,
   int pcell[3];
   R po[3], pe[3], x1[3], vz1, g1;
   push<DIM, ORDER>(G, ps.c, ps, k, pcell, po, pe, x1, vz1, g1);
-  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho);
   const int n[3] = {r.nx, r.ny, r.nz};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], x1[d], n[d]);
   if (leaves_box(r, ps.c[0])) ps.alive = false;
+  deposit<DIM, ORDER>(G, pcell, po, pe, ps.w, vz1, k, with_rho == 2 && !ps.alive ? 0 : with_rho);
   store_particle<R, DIM>(s, r, p, ps);
   if (!ps.alive) return 0.0;
   const double u2 = (double)ps.u[0] * ps.u[0] + (double)ps.u[1] * ps.u[1] + (double)ps.u[2] * ps.u[2];

@@ -60,6 +60,7 @@ void launch_yee_mid(const Tables& T, int prec, int ntiles, const FieldBands& ban
 // J := 0 (and the charge arrays when with_rho) over every cell of every run (nblocks: the
 // 256-cell blocks of T.run_blk).  flip != NULL: also *flip ^= 1 and, clock != NULL,
 // *clock += 1 (one thread).
+// with_rho: 1 also clears both charge arrays, 3 rho0 only, 4 rho1 only.
 void launch_clear_sources(const Tables& T, int prec, int dim, int nblocks, int with_rho,
                           int32_t* flip, int64_t* clock, hipStream_t st);
 // Laser antennas of the runs that have one (bpr workgroups of 256 (j, k) cells per run).

@@ -713,8 +713,9 @@ __global__ __launch_bounds__(256) void k_clear_sources(Tables T, int nblk, int w
   zero4((R*)r.f[F_JX], c, n);
   zero4((R*)r.f[F_JY], c, n);
   zero4((R*)r.f[F_JZ], c, n);
-  if (with_rho && r.f[F_R0]) zero4((R*)r.f[F_R0], c, n);
-  if (with_rho && r.f[F_R1]) zero4((R*)r.f[F_R1], c, n);
+  // with_rho: 1 both charge arrays, 3 rho0 only, 4 rho1 only (as k_yee_e's zero_j)
+  if ((with_rho == 1 || with_rho == 3) && r.f[F_R0]) zero4((R*)r.f[F_R0], c, n);
+  if ((with_rho == 1 || with_rho == 4) && r.f[F_R1]) zero4((R*)r.f[F_R1], c, n);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -74,15 +74,28 @@ def test_charge_matches_oracle(ndim, prec, order, rebin):
 
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
 @pytest.mark.parametrize("rebin", [False, True], ids=["escape", "rebin"])
-def test_chained_charge_matches_oracle(rebin, graph):
-    """3D FP32 in a periodic box with 8 x 4 x 4 tiles and halo 3: inside one call, the step
-    before a diagnostic step accumulates the charge at its paths' ends into rho0 and the
-    diagnostic step its own into rho1 (chained charge).  Against the oracle stepped from the
-    GPU's state through the same two steps, and against the same run taken one step per call
-    (no chain: the diagnostic step accumulates both planes)."""
-    banner(f"chained charge rebin={rebin} graph={graph}")
-    wl = W.thermal_3d(n=24, dx=0.1, ppc=4, T=0.5, order=2, seed=13)
-    kw = dict(prec=L.F32_CELLOFS, tiling=(8, 4, 4), halo=3, chunk=256, sort_interval=1000,
+@pytest.mark.parametrize("box,prec", [("3d", L.F32_CELLOFS), ("3d_open", L.F32_CELLOFS),
+                                      ("2d_open", L.F32_CELLOFS), ("2d_open", L.F64_ABS)],
+                         ids=["3d-f32", "3d_open-f32", "2d_open-f32", "2d_open-f64"])
+def test_chained_charge_matches_oracle(box, prec, rebin, graph):
+    """Inside one call, the step before a diagnostic step accumulates the charge at its
+    paths' ends into rho0, leaving out the particles that leave the box, and the diagnostic
+    step its own into rho1 (chained charge, 3D FP32 with 8 x 4 x 4 tiles and halo 3): a hot
+    periodic box, and a hot box with open x ends, where particles leave through the ends at
+    every step.  Against the oracle stepped from the GPU's state through the same two steps,
+    and against the same run taken one step per call (no chain: the diagnostic step
+    accumulates both planes).  The 2D cases (FP32 and FP64 keep both planes on the
+    diagnostic step) check the same quantities through the same calls."""
+    banner(f"chained charge box={box} prec={prec} rebin={rebin} graph={graph}")
+    if box.startswith("3d"):
+        wl = W.thermal_3d(n=24, dx=0.1, ppc=4, T=0.5, order=2, seed=13)
+        wl.open_x = box == "3d_open"
+        tiling = (8, 4, 4)
+    else:
+        wl = W.thermal_2d(nx=96, ny=80, dx=0.05, ppc=8, T=0.5, order=2, seed=13)
+        wl.open_x = True
+        tiling = (8, 8, 1)
+    kw = dict(prec=prec, tiling=tiling, halo=3, chunk=256, sort_interval=1000,
               diag_interval=4, use_graph=graph, flags=L.ESCAPE_REBIN if rebin else 0)
     sim = Simulation(wl, **kw)
     one = Simulation(wl, **kw)
@@ -91,21 +104,27 @@ def test_chained_charge_matches_oracle(rebin, graph):
         one.step(1)
     torch.cuda.synchronize()
     orc = _oracle_from(sim, wl)
+    alive0 = int((orc.species[0].x >= 0).sum())
     sim.step(2)                        # step 10 (before a diagnostic step) and step 11
     for _ in range(2):
         one.step(1)
     orc.step(2)
     torch.cuda.synchronize()
+    if box != "3d":                    # particles have left through the open ends
+        assert int((orc.species[0].x >= 0).sum()) < alive0
     assert sim.diagnostics(0)["step"] == 12
-    compare_fields(sim.fields[0], orc, L.F32_CELLOFS, keys=("rho0", "rho1", "jx", "jy", "jz"),
-                   tol=2e-5, what="chained charge vs oracle")
+    tol = 1e-10 if prec == L.F64_ABS else 2e-5
+    compare_fields(sim.fields[0], orc, prec, keys=("rho0", "rho1", "jx", "jy", "jz"), tol=tol,
+                   what="chained charge vs oracle")
     d, d1 = sim.diagnostics(0), one.diagnostics(0)
-    assert d["continuity"] < 1e-5 and d1["continuity"] < 1e-5, (d, d1)
+    cmax = 1e-12 if prec == L.F64_ABS else 1e-5
+    assert d["continuity"] < cmax and d1["continuity"] < cmax, (d, d1)
     a, b = sim.fields[0].numpy(), one.fields[0].numpy()
     for k in ("rho0", "rho1"):
         err = np.abs(a[k].astype(np.float64) - b[k]).max() / np.abs(b[k]).max()
-        assert err < 1e-5, (k, err)
-    assert d["gauss"] == pytest.approx(d1["gauss"], rel=1e-4)
-    assert d["kinetic_energy"] == pytest.approx(d1["kinetic_energy"], rel=1e-6)
+        assert err < (1e-12 if prec == L.F64_ABS else 1e-5), (k, err)
+    assert d["gauss"] == pytest.approx(d1["gauss"], rel=1e-8 if prec == L.F64_ABS else 1e-4)
+    assert d["kinetic_energy"] == pytest.approx(d1["kinetic_energy"],
+                                                rel=1e-12 if prec == L.F64_ABS else 1e-6)
     sim.close()
     one.close()
