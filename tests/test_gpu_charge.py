@@ -74,18 +74,23 @@ def test_charge_matches_oracle(ndim, prec, order, rebin):
 
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
 @pytest.mark.parametrize("rebin", [False, True], ids=["escape", "rebin"])
-@pytest.mark.parametrize("box,prec", [("3d", L.F32_CELLOFS), ("3d_open", L.F32_CELLOFS),
-                                      ("2d_open", L.F32_CELLOFS), ("2d_open", L.F64_ABS)],
-                         ids=["3d-f32", "3d_open-f32", "2d_open-f32", "2d_open-f64"])
-def test_chained_charge_matches_oracle(box, prec, rebin, graph):
+@pytest.mark.parametrize("box,prec,sort_interval",
+                         [("3d", L.F32_CELLOFS, 1000), ("3d", L.F32_CELLOFS, 10),
+                          ("3d", L.F32_CELLOFS, 11), ("3d_open", L.F32_CELLOFS, 1000),
+                          ("2d_open", L.F32_CELLOFS, 1000), ("2d_open", L.F64_ABS, 1000)],
+                         ids=["3d-f32", "3d-f32-sort_before", "3d-f32-sort_on_diag",
+                              "3d_open-f32", "2d_open-f32", "2d_open-f64"])
+def test_chained_charge_matches_oracle(box, prec, sort_interval, rebin, graph):
     """Inside one call, the step before a diagnostic step accumulates the charge at its
     paths' ends into rho0, leaving out the particles that leave the box, and the diagnostic
     step its own into rho1 (chained charge, 3D FP32 with 8 x 4 x 4 tiles and halo 3): a hot
     periodic box, and a hot box with open x ends, where particles leave through the ends at
     every step.  Against the oracle stepped from the GPU's state through the same two steps,
     and against the same run taken one step per call (no chain: the diagnostic step
-    accumulates both planes).  The 2D cases (FP32 and FP64 keep both planes on the
-    diagnostic step) check the same quantities through the same calls."""
+    accumulates both planes).  With a sort interval of 10 or 11 the particles are re-sorted
+    on the step before the diagnostic step or on the diagnostic step itself.  The 2D cases
+    (FP32 and FP64 keep both planes on the diagnostic step) check the same quantities
+    through the same calls."""
     banner(f"chained charge box={box} prec={prec} rebin={rebin} graph={graph}")
     if box.startswith("3d"):
         wl = W.thermal_3d(n=24, dx=0.1, ppc=4, T=0.5, order=2, seed=13)
@@ -95,7 +100,7 @@ def test_chained_charge_matches_oracle(box, prec, rebin, graph):
         wl = W.thermal_2d(nx=96, ny=80, dx=0.05, ppc=8, T=0.5, order=2, seed=13)
         wl.open_x = True
         tiling = (8, 8, 1)
-    kw = dict(prec=prec, tiling=tiling, halo=3, chunk=256, sort_interval=1000,
+    kw = dict(prec=prec, tiling=tiling, halo=3, chunk=256, sort_interval=sort_interval,
               diag_interval=4, use_graph=graph, flags=L.ESCAPE_REBIN if rebin else 0)
     sim = Simulation(wl, **kw)
     one = Simulation(wl, **kw)
