@@ -905,7 +905,7 @@ lpic_status configure(lpic_sim* s) {
   s->smem = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 0);
   s->geo = fused_geometry(s->ndim, t.tx, t.ty, t.tz, t.halo);
   // FP32 8 x 4 x 4 tiles with halo 3: the charge planes of diagnostic steps leave one
-  // workgroup per CU, which then runs 1024 threads (geometry 8) instead of 512
+  // workgroup per CU, which then runs 1024 threads (geometry 9) instead of 512
   s->geo_rho = (s->prec == LPIC_F32_CELLOFS && s->geo == 7) ? 9 : s->geo;
   s->smem_rho = fused_smem_bytes(s->prec, s->ndim, t.tx, t.ty, t.tz, t.halo, 1, s->geo_rho);
   {
