@@ -912,8 +912,8 @@ lpic_status configure(lpic_sim* s) {
     // (FP32 only: FP64 positions are absolute, and the start of the next step's path,
     // found again from the stored position, rounds at the scale of the box length -- about
     // 1e-11 of a cell in a box of 65536 cells, above the FP64 continuity that the two planes
-    // of one step keep.  3D only: a 2D region keeps its occupancy with both planes less one
-    // workgroup per CU, and splitting the charge adds over two steps measured no faster.)
+    // of one step keep.  3D only: in 2D both planes cost one workgroup of four per CU, and
+    // the chained 2D steps measured no faster.)
     const bool f32_3d = s->prec == LPIC_F32_CELLOFS && s->ndim == 3;
     s->chain = f32_3d && s->geo == 7;
     s->geo_chain = f32_3d && s->geo == 7 ? 8 : s->geo;
