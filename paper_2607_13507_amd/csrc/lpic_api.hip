@@ -711,8 +711,8 @@ struct lpic_sim {
   int64_t step = 0, sorts = 0, diag_step = -1;
   bool need_sort = true;
   bool need_spread = true;   // the first sort after particles are loaded spreads tiles
-  // captured steps keyed by (sort, diagnostics, first field updates already done by the
-  // previous step, last field updates merged into the next step's)
+  // captured steps keyed by (charge mode, sort, diagnostics, first field updates already
+  // done by the previous step, last field updates merged into the next step's)
   static constexpr int NGRAPHS = 64;
   hipGraphExec_t gexec[NGRAPHS] = {};
   // timing
