@@ -339,7 +339,10 @@ typedef struct {
 /* Create a simulation over nruns independent boxes.  species[s] belongs to box
  * species_run[s]; species_alt[s] holds same-sized arrays used as the sort's second buffer.
  * fields[r].rho0/rho1 must be non-NULL when diagnostics are on; they hold the charge of the
- * latest diagnostic step (steps without diagnostics neither write nor clear them).  All
+ * latest diagnostic step (other steps neither write nor clear them, except that in 3D FP32
+ * with 8x4x4 tiles and halo 3 the step before a diagnostic step inside the same lpic_step
+ * call writes rho0: the charge at the ends of its paths, which is where the diagnostic
+ * step's paths start, so that each step carries one charge plane in on-chip memory).  All
  * arrays stay owned by
  * the caller and must outlive the simulation; the library allocates only its own scratch
  * (sort workspace, tile and chunk tables, diagnostics) and frees it in lpic_sim_destroy. */
