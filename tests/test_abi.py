@@ -84,3 +84,10 @@ def test_error_path_without_gpu(lib):
     with pytest.raises(L.LpicError) as e:
         L.lpic_sort_tiles(g, s, s, t, 1, 1, 0, L.F32_CELLOFS, stream=0)
     assert "workspace" in str(e.value)
+    # the single fused call takes no charge mode but none (0) and both ends (1)
+    t = L.Tiling(16, 16, 1, 4, 256, 0)
+    for mode in (2, 3, -1):
+        with pytest.raises(L.LpicError) as e:
+            L.lpic_push_deposit_fused(g, f, s, t, 1, 1, 1 << 20, mode, None, L.F32_CELLOFS,
+                                      stream=0)
+        assert "with_rho" in str(e.value)
