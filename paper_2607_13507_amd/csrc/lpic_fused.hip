@@ -782,10 +782,11 @@ size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int
   // two charge planes)
   const int jplanes = 3 + charge_planes(with_rho);
   static_assert((6 * sizeof(float)) % 8 == 0, "current planes must start 8-byte aligned");
-  // 3D: the round compaction's slot list and wave sums (process_chunk_compact)
-  const int block = (geo == 7 || geo == 8) ? fused_block<float, 3, 7>()
-                  : prec == 0 ? fused_block<float, 3, 0>() : fused_block<double, 3, 0>();
-  // (geometry 9 has the default 3D blocks: 1024 threads FP32, 512 FP64)
+  // 3D: the round compaction's slot list and wave sums (process_chunk_compact), sized for
+  // the workgroup of this precision and geometry
+  const int block = geo == 7 || geo == 8
+                        ? (prec == 0 ? fused_block<float, 3, 7>() : fused_block<double, 3, 7>())
+                        : (prec == 0 ? fused_block<float, 3, 0>() : fused_block<double, 3, 0>());
   const size_t compact = dim == 3 ? ((size_t)block + 64) * 4 : 0;
   return plane * 6 * (prec == 0 ? 4 : 8) + plane * jplanes * 8 + compact;
 }
