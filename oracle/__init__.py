@@ -20,15 +20,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "qed.c"))
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc (IEEE semantics: no fast-math)."""
+    """Compile oracle.c and qed.c with gcc (IEEE semantics: no fast-math)."""
     if force or not os.path.exists(_SO):
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fopenmp", "-shared", "-fPIC",
-                               "-o", _SO + ".tmp", _SRC, "-lm"])
+                               "-o", _SO + ".tmp", *_SRCS, "-lm"])
         os.replace(_SO + ".tmp", _SO)
     return _SO
 
@@ -84,7 +85,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(f)
+                                          for f in _SRCS):
             build()
         L = ctypes.CDLL(_SO)
         L.orc_shape.restype = ctypes.c_double
