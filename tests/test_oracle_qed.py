@@ -137,7 +137,7 @@ def test_emission_statistics_and_conservation():
     x0 = s.x.copy()
     Q.qed_gather_push(sim, s, tau, hw, seed=5, step=1, photons=ph)
     g0 = math.sqrt(1 + ux * ux)
-    W = 7.2973525693e-3 * Q.compton_rate(chi) / (g0 * hw)
+    W = 7.2973525693e-3 * Q.compton_rate(0.5) / (g0 * hw)
     dtau = W * sim.grid.dt
     emit = tau0 - dtau <= 0
     n_ev = int(emit.sum())
