@@ -301,7 +301,7 @@ typedef enum {
   LPIC_STAGE_PUSH_POSITION_2 = 6,   /* Sec. 2.3); they fire per species, between the      */
                                     /* split gather-push and deposit calls                 */
   LPIC_STAGE_CURRENT_DEPOSITION = 7,/* after all species deposited */
-  LPIC_STAGE_QED_CREATE = 8,        /* reserved (no QED in this library) */
+  LPIC_STAGE_QED_CREATE = 8,        /* reserved (the QED calls run outside lpic_step) */
   LPIC_STAGE_MAXWELL_2 = 9,         /* after the second field half update */
   LPIC_STAGE_LOOP_END = 10,         /* end of every step */
   LPIC_STAGE_FINISH = 11,           /* once, after the last step of a call */
@@ -484,6 +484,101 @@ typedef struct {
  * when non-NULL; *report (optional) receives every trial. */
 lpic_status lpic_autotune_search(lpic_sim *sim, const lpic_tune_space *space,
                                  lpic_options *best, lpic_tune_report *report);
+
+/* =======================================================================================
+ * QED event Monte-Carlo -- Sec. 3.4: nonlinear Compton emission by leptons and
+ * Breit-Wheeler pair creation by photons in the locally-constant-field approximation, each
+ * particle carrying an optical depth that falls by (rate x dt) every step and triggers one
+ * event where it reaches zero or below (event-based Monte-Carlo).  Units as everywhere in
+ * this library (c = m_e = e = 1, time in 1/w_r, fields in m_e c w_r / e, momenta in m_e c);
+ * hbar_omega = hbar w_r / (m_e c^2) sets the Schwinger field 1 / hbar_omega.
+ *
+ *   chi_e = hbar_omega sqrt((gamma E + u x B)^2 - (u . E)^2)         (lepton, momentum u)
+ *   chi_g = hbar_omega sqrt((|k| E + k x B)^2 - (k . E)^2)           (photon, momentum k)
+ *   emission: rate alpha h(chi_e) / (gamma hbar_omega), photon energy fraction xi of the
+ *     spectrum F(chi, xi) = [(1 - xi + 1/(1 - xi)) K_{2/3}(y) - int_y^inf K_{1/3}] /
+ *     (sqrt3 pi), y = 2 xi / (3 chi (1 - xi)), h(chi) = int_0^1 F;
+ *   pairs: rate alpha T(chi_g) / (|k| hbar_omega), electron energy fraction xi of
+ *     G(chi, xi) = [(xi/(1 - xi) + (1 - xi)/xi) K_{2/3}(y) + int_y^inf K_{1/3}] / (sqrt3 pi),
+ *     y = 2 / (3 chi xi (1 - xi)), T(chi) = int_0^1 G.
+ * h, T and the inverse cumulative distributions of F and G are tabulated once per process
+ * (lpic_qed_tables_create) and interpolated: rates within ~1e-4 relative for chi in
+ * [1e-4, 1e3] (emission) and [1e-2, 1e3] (pairs; below 1e-2 the pair rate, under
+ * exp(-266) of the emission scale, is taken as zero); beyond 1e3 the tables extend with
+ * their end slope.  Every random number is a counter-based SplitMix64 draw (Steele, Lea
+ * and Flood 2014): output number ((step << 32) | slot) * 4 + draw of the generator seeded
+ * with `seed`, mapped to ((z >> 11) + 1/2) 2^-53 in (0, 1); results depend on the slot
+ * order, never on scheduling.  The event arithmetic runs in FP64 in both precisions.
+ * ======================================================================================= */
+typedef struct lpic_qed_tables lpic_qed_tables;
+
+/* Builds the tables on the host (a fraction of a second, on all host threads) and, with
+ * on_device != 0, copies them to the current device.  The same tables serve every later
+ * call; destroy releases both copies. */
+lpic_status lpic_qed_tables_create(int32_t on_device, lpic_qed_tables **out);
+lpic_status lpic_qed_tables_destroy(lpic_qed_tables *t);
+
+/* Host evaluation of the tabulated quantities with the device's interpolation (for
+ * checks): what = LPIC_QED_EMIT_RATE h(chi), LPIC_QED_EMIT_SAMPLE xi(chi, r),
+ * LPIC_QED_PAIR_RATE T(chi), LPIC_QED_PAIR_SAMPLE xi(chi, r); NaN for a bad `what`. */
+enum { LPIC_QED_EMIT_RATE = 0, LPIC_QED_EMIT_SAMPLE = 1, LPIC_QED_PAIR_RATE = 2,
+       LPIC_QED_PAIR_SAMPLE = 3 };
+double lpic_qed_table_eval(const lpic_qed_tables *t, int32_t what, double chi, double r);
+
+typedef struct {
+  double hbar_omega;     /* hbar w_r / (m_e c^2) > 0 */
+  uint64_t seed;
+  int64_t step;          /* the step number, part of every draw's counter (0 <= step < 2^30) */
+} lpic_qed_params;
+
+/* Event records, caller-owned device memory, FP64 absolute positions (z may be NULL in
+ * 2D) and momenta: photons (from emission; the photon population itself) or leptons (from
+ * pairs: the electron at an even index, the positron at the next).  *count (device) is the
+ * number of records; a call that creates records advances it atomically and writes a
+ * record only below capacity, so *count > capacity after a call reports an overflow (the
+ * records beyond capacity are lost).  tau is the record's optical depth, src the index of
+ * the particle or photon it came from.  A removed photon has x = -1. */
+typedef struct {
+  int64_t capacity;
+  int32_t *count;
+  double *x, *y, *z, *ux, *uy, *uz, *w, *tau;
+  int32_t *src;
+} lpic_qed_buffer;
+
+/* tau[i] = -ln U(seed, step, i, draw 2) for i < n: the optical depths of a fresh
+ * population (device array). */
+lpic_status lpic_qed_init_tau(double *tau, int64_t n, uint64_t seed, int64_t step,
+                              hipStream_t stream);
+
+/* lpic_gather_push with nonlinear Compton emission between the interpolation and the Boris
+ * push, as Algorithm 1 places the QED step: for every live lepton, x^{n+1/2} from u^n, E
+ * and B there, chi_e from u^n; tau (device, n doubles) falls by the emission rate x dt;
+ * where it reaches zero or below, xi = the inverse-cdf sample at draw 0, a photon of
+ * momentum xi gamma u/|u| is recorded in *photons at x^{n+1/2} (wrapped) with the lepton's
+ * weight, depth -ln(draw 2) and src = the lepton's slot, the lepton keeps u - xi gamma
+ * u/|u| and a new depth -ln(draw 1).  The rest (Boris, second half push, old_state for
+ * lpic_deposit_esirkepov) is lpic_gather_push's.  Photons created here are part of the
+ * next step's photon push (Algorithm 1 creates them after all species are pushed). */
+lpic_status lpic_qed_gather_push(const lpic_grid *grid, const lpic_fields *fields,
+                                 const lpic_species *sp, double *tau,
+                                 const lpic_qed_tables *tables, const lpic_qed_params *params,
+                                 const lpic_qed_buffer *photons, void *old_state,
+                                 size_t old_bytes, lpic_precision prec, hipStream_t stream);
+
+/* One step of the photons in *photons (records [0, min(*count, capacity)) as *count stands
+ * when the kernel starts; call it before the step's lpic_qed_gather_push): a photon moves
+ * at c along k; at x^{n+1/2} (shape `order` gather from the fields, precision prec) tau
+ * falls by the pair rate x dt; where it reaches zero or below, xi = the inverse-cdf sample
+ * at draw 0 and two records go to *pairs at x^{n+1/2}: the electron with energy xi |k|,
+ * the positron with (1 - xi) |k|, momenta along k (|u| = sqrt(gamma^2 - 1), zero below
+ * gamma = 1), the photon's weight, depths -ln(draw 2) and -ln(draw 3), src = the photon's
+ * index; the photon is removed (x = -1).  With open x ends a photon leaving
+ * [LPIC_OPEN_MARGIN dx, (nx - LPIC_OPEN_MARGIN) dx) is removed. */
+lpic_status lpic_qed_photon_push(const lpic_grid *grid, const lpic_fields *fields,
+                                 int32_t order, const lpic_qed_buffer *photons,
+                                 const lpic_qed_tables *tables, const lpic_qed_params *params,
+                                 const lpic_qed_buffer *pairs, lpic_precision prec,
+                                 hipStream_t stream);
 
 const char *lpic_last_error(void);
 const char *lpic_version(void);

@@ -1,6 +1,6 @@
 """Build the HIP library liblpic.so for gfx950 in-tree (hipcc, no JIT).
 
-The three translation units compile in parallel into objects in a temporary folder, then
+The translation units compile in parallel into objects in a temporary folder, then
 link into the shared library; the library is replaced only once the link succeeds."""
 import os
 import subprocess
@@ -10,7 +10,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblpic.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lpic_kernels.hip", "lpic_fused.hip", "lpic_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lpic_kernels.hip", "lpic_fused.hip", "lpic_qed.hip", "lpic_api.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("lpic_device.hpp", "lpic_internal.hpp")] + \
           [os.path.join(ROOT, "include", "lpic.h")]
 

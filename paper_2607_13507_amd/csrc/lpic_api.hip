@@ -380,6 +380,135 @@ lpic_status lpic_deposit_esirkepov(const lpic_grid* grid, const lpic_fields* fie
   return last_launch("deposit");
 }
 
+// ---- QED event Monte-Carlo (Sec. 3.4) -------------------------------------------------
+struct lpic_qed_tables {
+  QedTab host;
+  QedTab dev;
+  double* dev_base = nullptr;
+};
+
+static lpic_status check_qed_params(const lpic_qed_params* q) {
+  if (!q) return fail(LPIC_EINVAL, "qed params are NULL");
+  if (!(q->hbar_omega > 0.0) || !std::isfinite(q->hbar_omega))
+    return fail(LPIC_EINVAL, "hbar_omega must be positive (got %g)", q->hbar_omega);
+  if (q->step < 0 || q->step >= ((int64_t)1 << 30))
+    return fail(LPIC_EINVAL, "step must be in [0, 2^30) (got %lld)", (long long)q->step);
+  return LPIC_OK;
+}
+
+static lpic_status check_qed_buffer(const lpic_qed_buffer* b, int ndim, const char* what) {
+  if (!b) return fail(LPIC_EINVAL, "%s buffer is NULL", what);
+  if (b->capacity < 0 || b->capacity > ((int64_t)1 << 31) - 4)
+    return fail(LPIC_EINVAL, "%s capacity must be in [0, 2^31 - 4]", what);
+  if (!b->count) return fail(LPIC_EINVAL, "%s count is NULL", what);
+  if (b->capacity > 0 && (!b->x || !b->y || (ndim == 3 && !b->z) || !b->ux || !b->uy ||
+                          !b->uz || !b->w || !b->tau || !b->src))
+    return fail(LPIC_EINVAL, "%s arrays must not be NULL", what);
+  return LPIC_OK;
+}
+
+static QedBufDesc qed_desc(const lpic_qed_buffer* b) {
+  QedBufDesc d;
+  d.cap = b->capacity;
+  d.count = b->count;
+  d.x = b->x; d.y = b->y; d.z = b->z;
+  d.ux = b->ux; d.uy = b->uy; d.uz = b->uz;
+  d.w = b->w; d.tau = b->tau; d.src = b->src;
+  return d;
+}
+
+lpic_status lpic_qed_tables_create(int32_t on_device, lpic_qed_tables** out) {
+  if (!out) return fail(LPIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  const double* host = qed_host_tables();
+  lpic_qed_tables* t = new lpic_qed_tables;
+  t->host = qed_views(host);
+  t->dev = QedTab{nullptr, nullptr, nullptr, nullptr};
+  if (on_device) {
+    const size_t bytes = qed_table_doubles() * sizeof(double);
+    hipError_t e = hipMalloc((void**)&t->dev_base, bytes);
+    if (e == hipSuccess) e = hipMemcpy(t->dev_base, host, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (t->dev_base) (void)hipFree(t->dev_base);
+      delete t;
+      return fail(LPIC_EHIP, "QED tables: %s", hipGetErrorString(e));
+    }
+    t->dev = qed_views(t->dev_base);
+  }
+  *out = t;
+  return LPIC_OK;
+}
+
+lpic_status lpic_qed_tables_destroy(lpic_qed_tables* t) {
+  if (!t) return LPIC_OK;
+  if (t->dev_base) HIPCHK(hipFree(t->dev_base));
+  delete t;
+  return LPIC_OK;
+}
+
+double lpic_qed_table_eval(const lpic_qed_tables* t, int32_t what, double chi, double r) {
+  if (!t) return NAN;
+  switch (what) {
+    case LPIC_QED_EMIT_RATE: return qed_emit_rate(t->host, chi);
+    case LPIC_QED_EMIT_SAMPLE: return qed_emit_sample(t->host, chi, r);
+    case LPIC_QED_PAIR_RATE: return qed_pair_rate(t->host, chi);
+    case LPIC_QED_PAIR_SAMPLE: return qed_pair_sample(t->host, chi, r);
+    default: return NAN;
+  }
+}
+
+lpic_status lpic_qed_init_tau(double* tau, int64_t n, uint64_t seed, int64_t step,
+                              hipStream_t stream) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LPIC_EINVAL, "n must be in [0, 2^31)");
+  if (n > 0 && !tau) return fail(LPIC_EINVAL, "tau is NULL");
+  if (step < 0 || step >= ((int64_t)1 << 30)) return fail(LPIC_EINVAL, "step must be in [0, 2^30)");
+  launch_qed_tau(tau, n, seed, step, stream);
+  return last_launch("qed_init_tau");
+}
+
+lpic_status lpic_qed_gather_push(const lpic_grid* grid, const lpic_fields* fields,
+                                 const lpic_species* sp, double* tau,
+                                 const lpic_qed_tables* tables, const lpic_qed_params* params,
+                                 const lpic_qed_buffer* photons, void* old_state,
+                                 size_t old_bytes, lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, false));
+  CHK(check_species(sp, grid->ndim, prec));
+  CHK(check_qed_params(params));
+  CHK(check_qed_buffer(photons, grid->ndim, "photon"));
+  if (!tables || !tables->dev_base) return fail(LPIC_EINVAL, "QED tables without a device copy");
+  if (sp->n == 0) return LPIC_OK;
+  if (sp->n >= ((int64_t)1 << 31)) return fail(LPIC_EINVAL, "too many particles for the QED draws");
+  if (!tau) return fail(LPIC_EINVAL, "tau is NULL");
+  if (!old_state || old_bytes < old_state_bytes(grid->ndim, sp->n, prec))
+    return fail(LPIC_EINVAL, "old_state needs %zu bytes", old_state_bytes(grid->ndim, sp->n, prec));
+  RunDesc r = make_run(grid, fields, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  QedCall q{tables->dev, params->hbar_omega, params->seed, params->step, qed_desc(photons)};
+  launch_qed_push(T, prec, grid->ndim, (int)((sp->n + 255) / 256), old_state, tau, q, stream);
+  return last_launch("qed_gather_push");
+}
+
+lpic_status lpic_qed_photon_push(const lpic_grid* grid, const lpic_fields* fields,
+                                 int32_t order, const lpic_qed_buffer* photons,
+                                 const lpic_qed_tables* tables, const lpic_qed_params* params,
+                                 const lpic_qed_buffer* pairs, lpic_precision prec,
+                                 hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_fields(fields, false));
+  CHK(check_qed_params(params));
+  CHK(check_qed_buffer(photons, grid->ndim, "photon"));
+  CHK(check_qed_buffer(pairs, grid->ndim, "pair"));
+  if (order != 1 && order != 2) return fail(LPIC_EINVAL, "shape order must be 1 or 2");
+  if (!tables || !tables->dev_base) return fail(LPIC_EINVAL, "QED tables without a device copy");
+  if (photons->capacity == 0) return LPIC_OK;
+  RunDesc r = make_run(grid, fields, nullptr);
+  QedCall q{tables->dev, params->hbar_omega, params->seed, params->step, qed_desc(pairs)};
+  launch_qed_photons(r, prec, grid->ndim, order, qed_desc(photons), q, stream);
+  return last_launch("qed_photon_push");
+}
+
 int64_t lpic_num_tiles(const lpic_grid* grid, const lpic_tiling* tiling) {
   if (!grid || !tiling || tiling->tx <= 0 || tiling->ty <= 0) return -1;
   lpic_tiling t = *tiling;

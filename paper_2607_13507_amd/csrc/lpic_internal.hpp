@@ -6,6 +6,28 @@
 
 namespace lpic {
 
+// Split particle path: the start of each particle's deposit path (x^{n+1/2}), written by
+// the gather-push kernels and read by the deposit:
+//   FP32  cell[n] (packed, wrapped) o0[n] o1[n] (o2[n])     FP64  x[n] y[n] (z[n]) (wrapped)
+template <typename R, int DIM>
+struct OldState {
+  int32_t* cell;
+  R* o[3];
+  __device__ __forceinline__ OldState(void* base, int64_t n) {
+    char* b = (char*)base;
+    if (sizeof(R) == 4) {
+      cell = (int32_t*)b;
+      b += 4 * n;
+    } else {
+      cell = nullptr;
+    }
+    for (int d = 0; d < 3; ++d) {
+      if (d < DIM) { o[d] = (R*)b; b += sizeof(R) * n; } else { o[d] = nullptr; }
+    }
+  }
+};
+
+
 // Instantiate `call` with R (float / double) and D (2 / 3) from runtime values.
 #define LPIC_PD(prec, dim, call)                                  \
   do {                                                            \
@@ -174,5 +196,117 @@ void launch_store_positions(const Tables& T, int prec, int dim, int nblocks, dou
 // geo >= 0: the LDS of that geometry's launch (its workgroup size), else the tiling's own
 size_t fused_smem_bytes(int prec, int dim, int tx, int ty, int tz, int halo, int with_rho,
                         int geo = -1);
+
+// ---- QED event Monte-Carlo (Sec. 3.4) ------------------------------------------------------
+// Table geometry: emission rows at ln chi = QED_E_L0 + i QED_E_DL (chi from 1e-4, 40 per
+// decade, to 1e3), pair rows from chi = 1e-2 likewise, QED_NZ quantile levels z = QED_Z0 +
+// j QED_DZ, r = 1 / (1 + e^-z).  Layout of one table block (doubles): emission ln h[NE],
+// pair ln T + 8/(3 chi)[NP], emission v[NE][NZ], pair v[NP][NZ], v = ln(xi / (1 - xi)).
+constexpr int QED_NE = 281, QED_NP = 201, QED_NZ = 161;
+constexpr double QED_E_L0 = -9.210340371976184;    // ln 1e-4
+constexpr double QED_P_L0 = -4.605170185988091;    // ln 1e-2
+constexpr double QED_E_DL = 0.05756462732485115;   // ln 10 / 40
+constexpr double QED_P_DL = 0.05756462732485115;
+constexpr double QED_Z0 = -20.0, QED_DZ = 0.25;
+
+struct QedTab {
+  const double *emit_rate, *pair_rate, *emit_inv, *pair_inv;
+};
+
+struct QedBufDesc {
+  int64_t cap;
+  int32_t* count;
+  double *x, *y, *z, *ux, *uy, *uz, *w, *tau;
+  int32_t* src;
+};
+
+struct QedCall {
+  QedTab tab;
+  double hw;
+  uint64_t seed;
+  int64_t step;
+  QedBufDesc out;
+};
+
+size_t qed_table_doubles();
+const double* qed_host_tables();          // built once per process, on all host threads
+QedTab qed_views(const double* base);
+
+// Counter-based SplitMix64 draw in (0, 1): output number ((step << 32) | slot) * 4 + draw of
+// the generator seeded with `seed`.
+__host__ __device__ inline double qed_draw(uint64_t seed, int64_t step, int64_t slot,
+                                           int draw) {
+  const uint64_t k = ((((uint64_t)step) << 32) | (uint64_t)(uint32_t)slot) * 4u + (uint64_t)draw;
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// Row interpolation at quantile position fz = (z - Z0) / DZ: cubic through the four nearest
+// levels inside the table, linear with the end slopes beyond it.
+__host__ __device__ inline double qed_row(const double* row, double fz) {
+  if (fz < 0.0) return row[0] + fz * (row[1] - row[0]);
+  if (fz > QED_NZ - 1) return row[QED_NZ - 1] + (fz - (QED_NZ - 1)) * (row[QED_NZ - 1] - row[QED_NZ - 2]);
+  int j = (int)floor(fz);
+  j = j < 1 ? 1 : (j > QED_NZ - 3 ? QED_NZ - 3 : j);
+  const double t = fz - j;
+  const double wm = -t * (t - 1.0) * (t - 2.0) / 6.0, w0 = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+  const double w1 = -(t + 1.0) * t * (t - 2.0) / 2.0, w2 = (t + 1.0) * t * (t - 1.0) / 6.0;
+  return wm * row[j - 1] + w0 * row[j] + w1 * row[j + 1] + w2 * row[j + 2];
+}
+
+__host__ __device__ inline double qed_emit_rate(const QedTab& t, double chi) {
+  if (!(chi > 0.0)) return 0.0;
+  const double f = (log(chi) - QED_E_L0) / QED_E_DL;
+  if (f <= 0.0) return exp(t.emit_rate[0] + f * QED_E_DL);   // classical: h ~ chi
+  const int i = f < QED_NE - 2 ? (int)f : QED_NE - 2;
+  return exp(t.emit_rate[i] + (f - i) * (t.emit_rate[i + 1] - t.emit_rate[i]));
+}
+
+__host__ __device__ inline double qed_pair_rate(const QedTab& t, double chi) {
+  if (!(chi >= 1e-2)) return 0.0;
+  const double f = (log(chi) - QED_P_L0) / QED_P_DL;
+  const int i = f < QED_NP - 2 ? (int)f : QED_NP - 2;
+  return exp(t.pair_rate[i] + (f - i) * (t.pair_rate[i + 1] - t.pair_rate[i]) -
+             8.0 / (3.0 * chi));
+}
+
+__host__ __device__ inline double qed_sample(const double* inv, int nrows, double l0,
+                                             double dl, double chi, double r, double& scale) {
+  const double fz = (log(r) - log1p(-r) - QED_Z0) / QED_DZ;
+  double f = (log(chi) - l0) / dl;
+  scale = 1.0;
+  if (f < 0.0) {            // below the first row
+    scale = exp(f * dl);
+    f = 0.0;
+  }
+  int i = (int)f;
+  i = i > nrows - 2 ? nrows - 2 : i;
+  double a = f - i;
+  a = a > 1.0 ? 1.0 : a;    // beyond the last row: the last row
+  const double v = (1.0 - a) * qed_row(inv + (size_t)i * QED_NZ, fz) +
+                   a * qed_row(inv + (size_t)(i + 1) * QED_NZ, fz);
+  return 1.0 / (1.0 + exp(-v));
+}
+
+// Emission: below the first row the spectrum is the classical one, a function of xi / chi.
+__host__ __device__ inline double qed_emit_sample(const QedTab& t, double chi, double r) {
+  double scale;
+  const double xi = qed_sample(t.emit_inv, QED_NE, QED_E_L0, QED_E_DL, chi, r, scale);
+  return xi * scale;
+}
+
+__host__ __device__ inline double qed_pair_sample(const QedTab& t, double chi, double r) {
+  double scale;
+  return qed_sample(t.pair_inv, QED_NP, QED_P_L0, QED_P_DL, chi < 1e-2 ? 1e-2 : chi, r, scale);
+}
+
+void launch_qed_tau(double* tau, int64_t n, uint64_t seed, int64_t step, hipStream_t st);
+void launch_qed_push(const Tables& T, int prec, int dim, int nblocks, void* old, double* tau,
+                     const QedCall& q, hipStream_t st);
+void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,
+                        const QedCall& q, hipStream_t st);
 
 }  // namespace lpic

@@ -754,27 +754,8 @@ __global__ __launch_bounds__(256) void k_laser(Tables T, int nruns, int bpr, dou
 
 // =======================================================================================
 // Split particle path: gather + push, then deposit (used when a hook sits between them).
-// The old state holds the start of each particle's deposit path, the half-step position:
-//   FP32  cell[n] (packed, wrapped) o0[n] o1[n] (o2[n])     FP64  x[n] y[n] (z[n]) (wrapped)
+// The old state (OldState) holds the start of each particle's deposit path, x^{n+1/2}.
 // =======================================================================================
-template <typename R, int DIM>
-struct OldState {
-  int32_t* cell;
-  R* o[3];
-  __device__ __forceinline__ OldState(void* base, int64_t n) {
-    char* b = (char*)base;
-    if (sizeof(R) == 4) {
-      cell = (int32_t*)b;
-      b += 4 * n;
-    } else {
-      cell = nullptr;
-    }
-    for (int d = 0; d < 3; ++d) {
-      if (d < DIM) { o[d] = (R*)b; b += sizeof(R) * n; } else { o[d] = nullptr; }
-    }
-  }
-};
-
 template <typename R, int DIM, int ORDER>
 __device__ __forceinline__ void gather_push_one(const SegDesc& s, const RunDesc& r, int64_t p,
                                                 void* old) {

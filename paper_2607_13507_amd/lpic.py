@@ -112,6 +112,19 @@ class TuneReport(ctypes.Structure):
 HOOK_FN = ctypes.CFUNCTYPE(ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int64, _vp)
 
 
+class QedParams(ctypes.Structure):
+    _fields_ = [("hbar_omega", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("step", ctypes.c_int64)]
+
+
+class QedBuffer(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("count", _vp)] + \
+               [(k, _vp) for k in ("x", "y", "z", "ux", "uy", "uz", "w", "tau")] + [("src", _vp)]
+
+
+QED_EMIT_RATE, QED_EMIT_SAMPLE, QED_PAIR_RATE, QED_PAIR_SAMPLE = 0, 1, 2, 3
+
+
 class LpicError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
@@ -180,6 +193,20 @@ EXPORTS = {
                                      ctypes.POINTER(Options)]),
     "lpic_autotune_search": (ctypes.c_int, [_vp, ctypes.POINTER(TuneSpace),
                                             ctypes.POINTER(Options), ctypes.POINTER(TuneReport)]),
+    "lpic_qed_tables_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "lpic_qed_tables_destroy": (ctypes.c_int, [_vp]),
+    "lpic_qed_table_eval": (ctypes.c_double, [_vp, ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_double]),
+    "lpic_qed_init_tau": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64,
+                                         _vp]),
+    "lpic_qed_gather_push": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
+                                            ctypes.POINTER(Species), _vp, _vp,
+                                            ctypes.POINTER(QedParams), ctypes.POINTER(QedBuffer),
+                                            _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "lpic_qed_photon_push": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
+                                            ctypes.c_int32, ctypes.POINTER(QedBuffer), _vp,
+                                            ctypes.POINTER(QedParams), ctypes.POINTER(QedBuffer),
+                                            ctypes.c_int, _vp]),
 }
 
 _lib = None
@@ -408,3 +435,39 @@ def lpic_autotune_search(h, space):
                                                               ctypes.byref(best),
                                                               ctypes.byref(rep)))
     return best, rep
+
+
+# QED event Monte-Carlo (Sec. 3.4)
+def lpic_qed_tables_create(on_device=1):
+    h = _vp()
+    _check("lpic_qed_tables_create", lib().lpic_qed_tables_create(on_device, ctypes.byref(h)))
+    return h.value
+
+
+def lpic_qed_tables_destroy(h):
+    _check("lpic_qed_tables_destroy", lib().lpic_qed_tables_destroy(h))
+
+
+def lpic_qed_table_eval(h, what, chi, r=0.5):
+    return lib().lpic_qed_table_eval(h, what, chi, r)
+
+
+def lpic_qed_init_tau(tau, n, seed, step, stream=None):
+    _check("lpic_qed_init_tau", lib().lpic_qed_init_tau(tau, n, seed, step, _stream(stream)))
+
+
+def lpic_qed_gather_push(grid, fields, species, tau, tables, params, photons, old_state,
+                         old_bytes, prec, stream=None):
+    _check("lpic_qed_gather_push",
+           lib().lpic_qed_gather_push(ctypes.byref(grid), ctypes.byref(fields),
+                                      ctypes.byref(species), tau, tables, ctypes.byref(params),
+                                      ctypes.byref(photons), old_state, old_bytes, prec,
+                                      _stream(stream)))
+
+
+def lpic_qed_photon_push(grid, fields, order, photons, tables, params, pairs, prec,
+                         stream=None):
+    _check("lpic_qed_photon_push",
+           lib().lpic_qed_photon_push(ctypes.byref(grid), ctypes.byref(fields), order,
+                                      ctypes.byref(photons), tables, ctypes.byref(params),
+                                      ctypes.byref(pairs), prec, _stream(stream)))

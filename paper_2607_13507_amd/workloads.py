@@ -379,3 +379,50 @@ def deterministic_ensemble(steps=1000):
     s.ux, s.uy = np.zeros_like(s.ux), 5e-3 * np.sin(2 * math.pi * s.y / (16 * 0.05))
     members[-1].meta["perturbed_axis"] = "y"
     return members
+
+
+def _directions(rng, n):
+    """n isotropic unit vectors."""
+    v = rng.normal(size=(3, n))
+    return v / np.linalg.norm(v, axis=0)
+
+
+def qed_beam(ndim=2, n=24, dx=0.1, ppc=1, gamma=(500.0, 2000.0), b0=300.0, noise=0.2,
+             order=2, seed=7, eta=0.95, name="qed_beam") -> Workload:
+    """Electrons of Lorentz factor uniform in `gamma` with isotropic directions in a strong
+    uniform magnetic field b0 (along z) with a random perturbation of relative size `noise`
+    on every E and B component: quantum parameters ~0.1-3 at hbar_omega ~ 2e-6, the
+    regime where the emission of Sec. 3.4 happens within a few steps."""
+    rng = np.random.default_rng(seed)
+    if ndim == 2:
+        cx, cy = _cell_lists_2d(0, n, 0, n)
+        cz, nz = None, 1
+    else:
+        kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        cx, cy, cz, nz = ii.reshape(-1), jj.reshape(-1), kk.reshape(-1), n
+    x, y, z = _random_in_cells(rng, cx, cy, cz, ppc, dx, dx, dx)
+    L = n * dx
+    x, y = _fold(x, L), _fold(y, L)
+    z = _fold(z, L) if z is not None else None
+    m = x.shape[0]
+    g = rng.uniform(gamma[0], gamma[1], m)
+    u = _directions(rng, m) * np.sqrt(g * g - 1.0)
+    e = SpeciesInit("electron", -1.0, 1.0, order, x, y, z, u[0], u[1], u[2],
+                    rng.uniform(0.5, 1.5, m))
+    ncell = n * n * nz
+    f = random_fields(ncell, seed + 1, noise * b0)
+    f["bz"] = f["bz"] + b0
+    dt = cfl_dt(eta, dx, dx) if ndim == 2 else cfl_dt(eta, dx, dx, dx)
+    return Workload(name, ndim, n, n, nz, dx, dx, dx if ndim == 3 else 1.0, dt, 0.0, [e], f, 1,
+                    dict(ppc=ppc, gamma=gamma, b0=b0, noise=noise, order=order, seed=seed))
+
+
+def qed_photons(wl: Workload, n, k=(1000.0, 4000.0), seed=9):
+    """n photons uniform in the box of wl with momenta |k| uniform in `k` (units of m c)
+    and isotropic directions: positions x, y, z and momenta kx, ky, kz."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly, Lz = wl.box()
+    pos = [rng.uniform(0, Lx, n), rng.uniform(0, Ly, n),
+           rng.uniform(0, Lz, n) if wl.ndim == 3 else np.zeros(n)]
+    kv = _directions(rng, n) * rng.uniform(k[0], k[1], n)
+    return pos, kv, rng.uniform(0.5, 1.5, n)

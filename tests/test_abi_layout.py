@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PAIRS = [("lpic_grid", L.Grid), ("lpic_laser", L.Laser), ("lpic_fields", L.Fields),
          ("lpic_species", L.Species), ("lpic_tiling", L.Tiling), ("lpic_options", L.Options),
          ("lpic_stats", L.Stats), ("lpic_pml", L.Pml), ("lpic_plasma", L.Plasma),
-         ("lpic_tune_space", L.TuneSpace), ("lpic_tune_report", L.TuneReport)]
+         ("lpic_tune_space", L.TuneSpace), ("lpic_tune_report", L.TuneReport),
+         ("lpic_qed_params", L.QedParams), ("lpic_qed_buffer", L.QedBuffer)]
 
 
 def _layout(tmp_path, header, pairs, include_dirs):

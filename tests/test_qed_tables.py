@@ -1,0 +1,76 @@
+"""The library's QED tables (built on the host, interpolated exactly as the kernels do)
+against the oracle's integrals, and the host-side validation of the QED calls.  No GPU:
+the tables are built without a device copy.
+
+Tolerances come from the tables' resolution: 40 rows per decade of chi, linear in ln chi
+(second-order error ~ (ln10 / 40)^2 / 8 times the curvature of ln h, a few 1e-5), and a
+cubic in the quantile variable; measured worst cases 8e-5 (rates) and 5e-5 (samples)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import qed as Q
+from paper_2607_13507_amd import lpic as L
+
+
+@pytest.fixture(scope="module")
+def tabs():
+    h = L.lpic_qed_tables_create(0)
+    yield h
+    L.lpic_qed_tables_destroy(h)
+
+
+def ev(h, what, chi, r=0.5):
+    return L.lpic_qed_table_eval(h, what, chi, r)
+
+
+def test_rates_match_oracle(tabs):
+    rng = np.random.default_rng(5)
+    for chi in 10 ** rng.uniform(-5, 3, 24):
+        assert ev(tabs, L.QED_EMIT_RATE, chi) == pytest.approx(Q.compton_rate(chi), rel=2e-4)
+    for chi in 10 ** rng.uniform(-2, 3, 16):
+        assert ev(tabs, L.QED_PAIR_RATE, chi) == pytest.approx(Q.bw_rate(chi), rel=2e-4)
+    assert ev(tabs, L.QED_EMIT_RATE, 0.0) == 0.0
+    assert ev(tabs, L.QED_PAIR_RATE, 5e-3) == 0.0      # below the pair table: exp(-533)
+
+
+def test_samples_match_oracle(tabs):
+    rng = np.random.default_rng(6)
+    levels = [1e-6, 1e-3] + rng.uniform(0, 1, 4).tolist() + [0.999, 1 - 1e-6]
+    for chi in 10 ** rng.uniform(-4, 3, 6):
+        for r in levels:
+            assert ev(tabs, L.QED_EMIT_SAMPLE, chi, r) == pytest.approx(
+                Q.compton_sample(chi, r), rel=2e-4), (chi, r)
+    for chi in 10 ** rng.uniform(-2, 3, 5):
+        for r in levels:
+            assert ev(tabs, L.QED_PAIR_SAMPLE, chi, r) == pytest.approx(
+                Q.bw_sample(chi, r), abs=1e-4), (chi, r)
+    # below the emission table the classical spectrum, a function of xi / chi
+    for r in (0.1, 0.5, 0.9):
+        assert ev(tabs, L.QED_EMIT_SAMPLE, 1e-5, r) == pytest.approx(
+            Q.compton_sample(1e-5, r), rel=2e-3)
+    assert math.isnan(ev(tabs, 9, 1.0))
+
+
+def test_qed_calls_validate_on_the_host():
+    g = L.Grid(2, 16, 16, 1, 0.1, 0.1, 1.0, 0.05, 0.0)
+    f = L.Fields(*([1] * 9), None, None)
+    s = L.Species(10, -1.0, 1.0, 2, 0, *([1] * 11))
+    buf = L.QedBuffer(4, 1, *([1] * 9))
+    for params, tables, msg in ((L.QedParams(0.0, 1, 0), 1, "hbar_omega"),
+                                (L.QedParams(1e-6, 1, -1), 1, "step"),
+                                (L.QedParams(1e-6, 1, 0), None, "tables")):
+        with pytest.raises(L.LpicError) as e:
+            L.lpic_qed_gather_push(g, f, s, 1, tables, params, buf, 1, 1 << 20,
+                                   L.F32_CELLOFS, stream=0)
+        assert msg in str(e.value)
+    with pytest.raises(L.LpicError) as e:
+        L.lpic_qed_photon_push(g, f, 3, buf, 1, L.QedParams(1e-6, 1, 0), buf, L.F32_CELLOFS,
+                               stream=0)
+    assert "order" in str(e.value)
+    bad = L.QedBuffer(4, None, *([1] * 9))
+    with pytest.raises(L.LpicError) as e:
+        L.lpic_qed_photon_push(g, f, 2, bad, 1, L.QedParams(1e-6, 1, 0), buf, L.F32_CELLOFS,
+                               stream=0)
+    assert "count" in str(e.value)
