@@ -25,13 +25,15 @@ static double simpson_rec(orc_fn f, const void *c, double a, double b, double fa
 
 /* int_a^b f to a relative accuracy of about rel: P panels set the scale, then each panel
  * is refined adaptively. */
-static double integrate_p(orc_fn f, const void *c, double a, double b, double rel, int P) {
+static double integrate_p(orc_fn f, const void *c, double a, double b, double rel, int P,
+                          double abs_tol) {
   if (!(b > a)) return 0.0;
   double h = (b - a) / P, fx[2 * 64 + 1], coarse = 0.0;
   for (int i = 0; i <= 2 * P; ++i) fx[i] = f(a + 0.5 * h * i, c);
   for (int i = 0; i < P; ++i) coarse += h / 6.0 * (fx[2 * i] + 4.0 * fx[2 * i + 1] + fx[2 * i + 2]);
-  double eps = rel * fabs(coarse) / P;
-  if (eps == 0.0) return coarse;
+  /* below 1e-250 (and near the subnormal range) no refinement can improve anything */
+  double eps = fmax(rel * fabs(coarse), abs_tol) / P;
+  if (fabs(coarse) < 1e-250 || eps == 0.0) return coarse;
   double s = 0.0;
   for (int i = 0; i < P; ++i) {
     double pa = a + h * i, pb = pa + h;
@@ -42,7 +44,7 @@ static double integrate_p(orc_fn f, const void *c, double a, double b, double re
 }
 
 static double integrate(orc_fn f, const void *c, double a, double b, double rel) {
-  return integrate_p(f, c, a, b, rel, 64);
+  return integrate_p(f, c, a, b, rel, 64, 0.0);
 }
 
 /* ---- Bessel functions from their integral representations ----------------------------
@@ -142,7 +144,8 @@ static double sample(orc_fn f, const void *c, double lo, double hi, double total
   double target = r * total, flo = 0.0;
   for (int it = 0; it < 60 && hi - lo > 1e-14 * hi; ++it) {
     double mid = 0.5 * (lo + hi);
-    double fm = flo + integrate_p(f, c, lo, mid, 1e-10, 4);
+    /* pieces far out in a tail need no more than an absolute accuracy of the total's */
+    double fm = flo + integrate_p(f, c, lo, mid, 1e-10, 4, 1e-13 * total);
     if (fm < target) { lo = mid; flo = fm; } else { hi = mid; }
   }
   return 0.5 * (lo + hi);
