@@ -20,7 +20,14 @@ Also measured, each with its own roofline and CPU baseline (keys of "extra"):
                           path on and off, tried on a copy advanced to the same step);
   thermal_3d              3D3V periodic 256^3, 8 ppc (134,217,728), T = 0.05, quadratic, sort
                           every 20 steps as the configuration states;
-  wakefield               2D3V 8192x512, 0.01 n_c at 4 ppc, a0 = 2, window moving with light.
+  wakefield               2D3V 8192x512, 0.01 n_c at 4 ppc, a0 = 2, window moving with light;
+  qed                     the QED event Monte-Carlo of Sec. 3.4 at the laser-slab scale:
+                          16,777,216 electrons (gamma 500-2000, isotropic) on 2048x2048 cells
+                          in a 300 m_e w c / e magnetic field with 20% random E and B
+                          (quantum parameters ~0.1-3), one emission gather-push launch per
+                          step, and 16,777,216 photons (|k| 1000-4000 m_e c) in a 2000-unit
+                          field for the pair push; launches timed with HIP events, records
+                          written to caller buffers.
 
 Every configuration runs the FP32 cell+offset path (`value`) and the plain FP64 path beside
 it.  Timing: after the warmup steps (and alignment to a sort period), K steps run eagerly
@@ -405,6 +412,200 @@ def cpu_baseline(name, wls):
 
 
 # ------------------------------------------------------------------------------------------
+# QED event Monte-Carlo (Sec. 3.4)
+# ------------------------------------------------------------------------------------------
+QED_HW = 2e-6                  # hbar w_r / (m_e c^2)
+QED_PAIR_HW = 2.5e-6
+
+
+def qed_bytes(kind, events_per_push, per_cell):
+    """Algorithmic bytes of one push of the QED kernels (FP32 cell+offset leptons, FP64
+    records): particle words in and out, the optical depth in and out, E and B once per
+    cell (per_cell particles share a cell), and the records the events write (76 B each:
+    seven FP64 words and the source index)."""
+    fields = 6 * 4 / per_cell
+    if kind == "emit":   # read cell, 2 offsets, u, w; write cell, offsets, u, old state
+        return 28 + 24 + 12 + 16 + fields + 76 * events_per_push
+    # photons: read x, y, k, w, tau; write x, y, tau; two records per pair event
+    return 56 + 24 + fields + 2 * 76 * events_per_push
+
+
+class _QedBuf:
+    def __init__(self, cap):
+        import torch
+        self.cap = cap
+        self.t = {k: torch.zeros(cap, dtype=torch.float64, device="cuda")
+                  for k in ("x", "y", "ux", "uy", "uz", "w", "tau")}
+        self.src = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        self.count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def struct(self):
+        from paper_2607_13507_amd import lpic as L
+        t = self.t
+        return L.QedBuffer(self.cap, self.count.data_ptr(), t["x"].data_ptr(), t["y"].data_ptr(),
+                           None, t["ux"].data_ptr(), t["uy"].data_ptr(), t["uz"].data_ptr(),
+                           t["w"].data_ptr(), t["tau"].data_ptr(), self.src.data_ptr())
+
+
+def measure_qed(args, want_cpu):
+    import numpy as np
+    import torch
+    from paper_2607_13507_amd import lpic as L
+    from paper_2607_13507_amd import workloads as W
+    from paper_2607_13507_amd.simulation import DeviceFields, DeviceSpecies, grid_struct
+    print("[bench] qed: building inputs", file=sys.stderr, flush=True)
+    F32 = L.F32_CELLOFS
+    launches = max(3, min(args.steps, 10))
+    warm = 2
+    tabs = L.lpic_qed_tables_create(1)
+    stream = torch.cuda.current_stream()
+    st = stream.cuda_stream
+
+    def timed(launch, reset):
+        ms = []
+        for i in range(warm + launches):
+            reset()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            launch(i)
+            b.record(stream)
+            b.synchronize()
+            if i >= warm:
+                ms.append(a.elapsed_time(b))
+        return sum(ms) / len(ms)
+
+    # emission: electrons in the strong field
+    wl = W.qed_beam(ndim=2, n=2048, ppc=4, order=2, seed=11)
+    grid = grid_struct(wl)
+    F = DeviceFields(wl, F32, with_rho=False)
+    sp = DeviceSpecies.from_init(grid, wl.species[0], F32)
+    n = sp.n
+    tau = torch.empty(n, dtype=torch.float64, device="cuda")
+    L.lpic_qed_init_tau(tau.data_ptr(), n, 1, 0)
+    ph = _QedBuf(n)
+    old = torch.empty(L.lpic_old_state_bytes(2, n, F32), dtype=torch.uint8, device="cuda")
+    counts = []
+
+    def emit(i):
+        L.lpic_qed_gather_push(grid, F.struct(), sp.struct(), tau.data_ptr(), tabs,
+                               L.QedParams(QED_HW, 1, 1 + i), ph.struct(), old.data_ptr(),
+                               old.numel(), F32, stream=st)
+
+    def emit_reset():
+        if ph.count.item() > 0:
+            counts.append(int(ph.count.item()))
+        ph.count.zero_()
+
+    ms_emit = timed(emit, emit_reset)
+    emit_reset()
+    ev_emit = sum(counts[-launches:]) / launches / n
+
+    def plain(i):   # the same particles through the gather-push without QED, for context
+        L.lpic_gather_push(grid, F.struct(), sp.struct(), old.data_ptr(), old.numel(), F32,
+                           stream=st)
+
+    ms_plain = timed(plain, lambda: None)
+    fields_f = F
+    del ph, old, tau, sp
+    # pairs: photons in a stronger field
+    wl2 = W.qed_beam(ndim=2, n=2048, dx=0.5, b0=2000.0, ppc=1, order=2, seed=12)
+    wl2.species = []
+    grid2 = grid_struct(wl2)
+    F2 = DeviceFields(wl2, F32, with_rho=False)
+    m = n
+    pos, kv, w = W.qed_photons(wl2, m, seed=13)
+    phot = _QedBuf(m)
+    for k, v in (("x", pos[0]), ("y", pos[1]), ("ux", kv[0]), ("uy", kv[1]), ("uz", kv[2]),
+                 ("w", w)):
+        phot.t[k].copy_(torch.from_numpy(np.ascontiguousarray(v)))
+    phot.count.fill_(m)
+    L.lpic_qed_init_tau(phot.t["tau"].data_ptr(), m, 2, 0)
+    pairs = _QedBuf(m)
+    alive, pcounts = [], []
+
+    def pair(i):
+        L.lpic_qed_photon_push(grid2, F2.struct(), 2, phot.struct(), tabs,
+                               L.QedParams(QED_PAIR_HW, 2, 1 + i), pairs.struct(), F32,
+                               stream=st)
+
+    def pair_reset():
+        alive.append(int((phot.t["x"] >= 0).sum().item()))
+        if pairs.count.item() > 0:
+            pcounts.append(int(pairs.count.item()) // 2)
+        pairs.count.zero_()
+
+    ms_pair = timed(pair, pair_reset)
+    pair_reset()
+    live = sum(alive[warm:warm + launches]) / launches
+    ev_pair = sum(pcounts[-launches:]) / launches / live
+    del phot, pairs, F2, fields_f, F
+    L.lpic_qed_tables_destroy(tabs)
+
+    def roof(kind, npush, ms, ev, kernel):
+        b = qed_bytes(kind, ev, 4.0)
+        gbs = b * npush / (ms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    bytes_per_push=round(b, 3), avg_launch_ms=round(ms, 4), launches=launches)
+
+    out = dict(workload="qed_beam 2048x2048 f32, 16,777,216 electrons; 16,777,216 photons",
+               value=round(n / (ms_emit * 1e-3), 1), unit="particle-pushes/s",
+               emission=dict(pushes_per_s=round(n / (ms_emit * 1e-3), 1),
+                             avg_launch_ms=round(ms_emit, 4),
+                             events_per_push=round(ev_emit, 5), hbar_omega=QED_HW,
+                             plain_gather_push_ms=round(ms_plain, 4),
+                             roofline=roof("emit", n, ms_emit, ev_emit, "lpic::k_qed_push<float,2>")),
+               pairs=dict(pushes_per_s=round(live / (ms_pair * 1e-3), 1),
+                          avg_launch_ms=round(ms_pair, 4), live_photons=int(live),
+                          events_per_push=round(ev_pair, 5), hbar_omega=QED_PAIR_HW,
+                          roofline=roof("pair", live, ms_pair, ev_pair,
+                                        "lpic::k_qed_photons<float,2>")))
+    out["roofline"] = out["emission"]["roofline"]
+    if want_cpu:
+        out["cpu_baseline"] = qed_cpu_baseline(wl, wl2)
+    return out
+
+
+def qed_cpu_baseline(wl, wl2):
+    """The oracle's QED push (single-threaded, each rate and quantile from its integrals)
+    on the first 2000 electrons of the same workload and on 1000 photons."""
+    import numpy as np
+    import oracle
+    from oracle import qed as Q
+    from paper_2607_13507_amd import workloads as W
+    print("[bench] qed: CPU baseline (oracle)", file=sys.stderr, flush=True)
+    m = 2000
+    orc = oracle.OracleSim.from_workload(wl, with_rho=False)
+    s = orc.species[0]
+    for k in ("x", "y", "ux", "uy", "uz", "w"):
+        setattr(s, k, np.ascontiguousarray(getattr(s, k)[:m]))
+    tau = Q.init_tau(m, 1, 0)
+    buf = Q.QedBuf(m)
+    t0 = time.perf_counter()
+    Q.qed_gather_push(orc, s, tau, QED_HW, 1, 1, buf)
+    t_emit = time.perf_counter() - t0
+    del orc
+    orc2 = oracle.OracleSim.from_workload(wl2, with_rho=False)
+    k = 1000
+    pos, kv, w = W.qed_photons(wl2, k, seed=13)
+    ph = Q.QedBuf(k, count=k)
+    ph.x[:], ph.y[:] = pos[0], pos[1]
+    ph.ux[:], ph.uy[:], ph.uz[:] = kv
+    ph.w[:] = w
+    ph.tau[:] = Q.init_tau(k, 2, 0)
+    pairs = Q.QedBuf(2 * k)
+    t0 = time.perf_counter()
+    Q.qed_photon_push(orc2, 2, ph, QED_PAIR_HW, 2, 1, pairs)
+    t_pair = time.perf_counter() - t0
+    return dict(value=round(m / t_emit, 1), unit="particle-pushes/s", cores=1, kind="oracle",
+                sample=f"one emission gather-push of the first {m} electrons ({buf.count} "
+                       f"events), FP64, one thread of {host_cpu()}, {t_emit:.1f} s",
+                pairs=dict(value=round(k / t_pair, 1), cores=1,
+                           sample=f"one photon push of {k} photons ({pairs.count // 2} pairs), "
+                                  f"{t_pair:.1f} s"))
+
+
+# ------------------------------------------------------------------------------------------
 def roofline_of(name, ndim, wls, ppc_tot, res, launch_key="start"):
     """HBM roofline of the dominant kernel (k_fused, FP32) for one configuration."""
     w = res[launch_key]
@@ -502,7 +703,7 @@ def main():
     ap.add_argument("--workload", default=None, choices=WORKLOADS,
                     help="measure one configuration only (it becomes the headline); default: "
                          "the ensemble as headline and the others as extra keys")
-    ap.add_argument("--extra", default="laser_slab,thermal_3d,wakefield",
+    ap.add_argument("--extra", default="laser_slab,thermal_3d,wakefield,qed",
                     help="comma-separated configurations measured beside the headline")
     ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="T",
                     help="start (or, with --no-autotune, fixed) tile edges x y [z]")
@@ -519,6 +720,8 @@ def main():
                     help="laser_slab: skip the window timed from step 1200")
     ap.add_argument("--no-graph", action="store_true",
                     help="eager launches only (profiler passes)")
+    ap.add_argument("--qed-only", action="store_true",
+                    help="measure the QED kernels only and print their entry (profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain copy of this many MiB (profiler byte calibration)")
     args = ap.parse_args()
@@ -533,8 +736,16 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.qed_only:
+        out = dict(qed=measure_qed(args, not args.no_cpu_baseline))
+        if args.copy_calibration > 0:
+            out["copy_calibration"] = copy_calibration(args.copy_calibration)
+        print(json.dumps(out), flush=True)
+        return
     head_name = args.workload or "ensemble"
     extras = [] if args.workload else [e for e in args.extra.split(",") if e]
+    want_qed = "qed" in extras
+    extras = [e for e in extras if e != "qed"]
     copy_gbs = copy_bandwidth()
     results, pending_cpu = {}, []
     for name in [head_name] + extras:
@@ -581,6 +792,8 @@ def main():
     for name in extras:
         for key, e in results[name].items():
             extra[name if key == "start" else f"{name}_{key}"] = e
+    if want_qed:
+        extra["qed"] = measure_qed(args, not args.no_cpu_baseline)
     if extra:
         out["extra"] = extra
     if args.copy_calibration > 0:

@@ -508,7 +508,9 @@ lpic_status lpic_autotune_search(lpic_sim *sim, const lpic_tune_space *space,
  * their end slope.  Every random number is a counter-based SplitMix64 draw (Steele, Lea
  * and Flood 2014): output number ((step << 32) | slot) * 4 + draw of the generator seeded
  * with `seed`, mapped to ((z >> 11) + 1/2) 2^-53 in (0, 1); results depend on the slot
- * order, never on scheduling.  The event arithmetic runs in FP64 in both precisions.
+ * order, never on scheduling.  In both precisions the quantum parameters, rates x dt,
+ * optical depths, decisions and records are FP64; the table lookups and -ln(draw) take
+ * their logarithms and exponentials in FP32 (1e-7 relative, against the tables' 1e-4).
  * ======================================================================================= */
 typedef struct lpic_qed_tables lpic_qed_tables;
 

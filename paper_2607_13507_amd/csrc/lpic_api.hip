@@ -486,7 +486,7 @@ lpic_status lpic_qed_gather_push(const lpic_grid* grid, const lpic_fields* field
   SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
   Tables T = single_tables(r, &s);
   QedCall q{tables->dev, params->hbar_omega, params->seed, params->step, qed_desc(photons)};
-  launch_qed_push(T, prec, grid->ndim, (int)((sp->n + 255) / 256), old_state, tau, q, stream);
+  launch_qed_push(T, prec, grid->ndim, sp->n, old_state, tau, q, stream);
   return last_launch("qed_gather_push");
 }
 

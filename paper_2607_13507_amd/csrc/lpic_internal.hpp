@@ -257,29 +257,44 @@ __host__ __device__ inline double qed_row(const double* row, double fz) {
   return wm * row[j - 1] + w0 * row[j] + w1 * row[j + 1] + w2 * row[j + 2];
 }
 
+// The table lookups take their logarithms and exponentials in FP32 (a few instructions
+// against the long software sequences of FP64 ones): an index or weight off by 1e-7 and a value
+// off by 1e-7 relative are far below the tables' own 1e-4.  The decisions themselves
+// (optical depth minus rate x dt) stay in FP64.
+__host__ __device__ inline double qed_exp(double a) {
+  return a > -80.0 ? (double)expf((float)a) : exp(a);
+}
+
+// -ln u for a draw u in (0, 1) to 1e-7 relative: above 1/2 through log1p of 1 - u (exact in
+// FP64), so depths near zero keep their relative accuracy.
+__host__ __device__ inline double qed_neglog(double u) {
+  return u > 0.5 ? -(double)log1pf(-(float)(1.0 - u)) : -(double)logf((float)u);
+}
+
 __host__ __device__ inline double qed_emit_rate(const QedTab& t, double chi) {
   if (!(chi > 0.0)) return 0.0;
-  const double f = (log(chi) - QED_E_L0) / QED_E_DL;
-  if (f <= 0.0) return exp(t.emit_rate[0] + f * QED_E_DL);   // classical: h ~ chi
+  const double f = ((double)logf((float)chi) - QED_E_L0) / QED_E_DL;
+  if (f <= 0.0) return qed_exp(t.emit_rate[0] + f * QED_E_DL);   // classical: h ~ chi
   const int i = f < QED_NE - 2 ? (int)f : QED_NE - 2;
-  return exp(t.emit_rate[i] + (f - i) * (t.emit_rate[i + 1] - t.emit_rate[i]));
+  return qed_exp(t.emit_rate[i] + (f - i) * (t.emit_rate[i + 1] - t.emit_rate[i]));
 }
 
 __host__ __device__ inline double qed_pair_rate(const QedTab& t, double chi) {
   if (!(chi >= 1e-2)) return 0.0;
-  const double f = (log(chi) - QED_P_L0) / QED_P_DL;
+  const double f = ((double)logf((float)chi) - QED_P_L0) / QED_P_DL;
   const int i = f < QED_NP - 2 ? (int)f : QED_NP - 2;
-  return exp(t.pair_rate[i] + (f - i) * (t.pair_rate[i + 1] - t.pair_rate[i]) -
-             8.0 / (3.0 * chi));
+  return qed_exp(t.pair_rate[i] + (f - i) * (t.pair_rate[i + 1] - t.pair_rate[i]) -
+                 8.0 / (3.0 * chi));
 }
 
 __host__ __device__ inline double qed_sample(const double* inv, int nrows, double l0,
                                              double dl, double chi, double r, double& scale) {
-  const double fz = (log(r) - log1p(-r) - QED_Z0) / QED_DZ;
-  double f = (log(chi) - l0) / dl;
+  const double z = (double)(logf((float)r) - logf((float)(1.0 - r)));
+  const double fz = (z - QED_Z0) / QED_DZ;
+  double f = ((double)logf((float)chi) - l0) / dl;
   scale = 1.0;
   if (f < 0.0) {            // below the first row
-    scale = exp(f * dl);
+    scale = qed_exp(f * dl);
     f = 0.0;
   }
   int i = (int)f;
@@ -288,7 +303,7 @@ __host__ __device__ inline double qed_sample(const double* inv, int nrows, doubl
   a = a > 1.0 ? 1.0 : a;    // beyond the last row: the last row
   const double v = (1.0 - a) * qed_row(inv + (size_t)i * QED_NZ, fz) +
                    a * qed_row(inv + (size_t)(i + 1) * QED_NZ, fz);
-  return 1.0 / (1.0 + exp(-v));
+  return v < -80.0 ? exp(v) : 1.0 / (1.0 + qed_exp(-v));
 }
 
 // Emission: below the first row the spectrum is the classical one, a function of xi / chi.
@@ -304,7 +319,7 @@ __host__ __device__ inline double qed_pair_sample(const QedTab& t, double chi, d
 }
 
 void launch_qed_tau(double* tau, int64_t n, uint64_t seed, int64_t step, hipStream_t st);
-void launch_qed_push(const Tables& T, int prec, int dim, int nblocks, void* old, double* tau,
+void launch_qed_push(const Tables& T, int prec, int dim, int64_t n, void* old, double* tau,
                      const QedCall& q, hipStream_t st);
 void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,
                         const QedCall& q, hipStream_t st);

@@ -162,7 +162,39 @@ __device__ __forceinline__ double wrap_pos(double p, double L) {
   return p < 0.0 ? p + L : (p >= L ? p - L : p);
 }
 
-// Appends one record; the caller has taken index i with an atomic add on the count.
+// Record slots for the threads of a workgroup that want `per` records each: one atomic add
+// on the count per workgroup (same-address atomics serialise in the L2, one per wave cost
+// more than the rest of the kernel), each wanting thread's first slot from its rank in the
+// workgroup.  Every thread of the workgroup must call it.
+constexpr int QED_BLOCK = 1024;
+
+__device__ __forceinline__ int64_t block_slots(int32_t* count, bool want, int per) {
+  __shared__ int wcount[QED_BLOCK / 64];
+  __shared__ int bbase;
+  const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+  const uint64_t mask = __ballot(want);
+  if (lane == 0) wcount[wave] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      const int c = wcount[w];
+      wcount[w] = tot;
+      tot += c;
+    }
+    bbase = tot ? atomicAdd(count, per * tot) : 0;
+  }
+  __syncthreads();
+  const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+  return want ? (int64_t)bbase + (int64_t)per * (wcount[wave] + rank) : -1;
+}
+
+// One record's contents.
+struct QedRec {
+  double pos[3], u[3], w, tau;
+};
+
+// Writes one record at slot i (below capacity only).
 __device__ __forceinline__ void put_record(const QedBufDesc& b, int64_t i, const double pos[3],
                                            const double u[3], double w, double tau, int src) {
   if (i >= b.cap) return;
@@ -178,15 +210,16 @@ __device__ __forceinline__ void put_record(const QedBufDesc& b, int64_t i, const
 }
 
 template <typename R, int DIM, int ORDER>
-__device__ __forceinline__ void qed_push_one(const SegDesc& s, const RunDesc& r, int64_t p,
-                                             void* old, double* tau, const QedCall& q) {
+__device__ __forceinline__ bool qed_push_one(const SegDesc& s, const RunDesc& r, int64_t p,
+                                             void* old, double* tau, const QedCall& q,
+                                             QedRec& rec) {
   PState<R> ps;
   load_particle<R, DIM>(s, r, (int32_t)p, ps);
   OldState<R, DIM> os(old, s.n);
   if (!ps.alive) {
     if (os.cell) os.cell[p] = -1;
     else os.o[0][p] = R(-1);
-    return;
+    return false;
   }
   const GlobalAcc<R> A = global_acc<R>(r);
   const PushConst<R> k = push_const<R>(r, s);
@@ -206,10 +239,14 @@ __device__ __forceinline__ void qed_push_one(const SegDesc& s, const RunDesc& r,
   const double g0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const double chi = qed_chi(g0, u, Ed, Bd, q.hw);
   double t = tau[p] - kAlpha * qed_emit_rate(q.tab, chi) / (g0 * q.hw) * r.dt;
-  if (t <= 0.0) {
+  const bool fire = t <= 0.0;
+  double* kk = rec.u;
+  double* pos = rec.pos;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) kk[d] = pos[d] = 0.0;
+  if (fire) {
     const double xi = qed_emit_sample(q.tab, chi, qed_draw(q.seed, q.step, p, 0));
     const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    double kk[3] = {0.0, 0.0, 0.0};
     if (um > 0.0) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) kk[d] = xi * g0 * u[d] / um;
@@ -220,12 +257,11 @@ __device__ __forceinline__ void qed_push_one(const SegDesc& s, const RunDesc& r,
       ps.u[d] = (R)u[d];
     }
     const double h[3] = {r.dx, r.dy, r.dz};
-    double pos[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) pos[d] = ((double)wc[d] + (double)po[d]) * h[d];
-    const int64_t i = atomicAdd(q.out.count, 1);
-    put_record(q.out, i, pos, kk, (double)ps.w, -log(qed_draw(q.seed, q.step, p, 2)), (int)p);
-    t = -log(qed_draw(q.seed, q.step, p, 1));
+    t = qed_neglog(qed_draw(q.seed, q.step, p, 1));
+    rec.w = (double)ps.w;
+    rec.tau = qed_neglog(qed_draw(q.seed, q.step, p, 2));
   }
   tau[p] = t;
 
@@ -244,23 +280,32 @@ __device__ __forceinline__ void qed_push_one(const SegDesc& s, const RunDesc& r,
 #pragma unroll
   for (int d = 0; d < DIM; ++d) advance_cell<R>(ps.c[d], ps.o[d], xh[d] + hd[d] * ps.u[d] * ig1, n[d]);
   store_particle<R, DIM>(s, r, (int32_t)p, ps);
+  return fire;
 }
 
+// One species of a single run (the tables of lpic_qed_gather_push), QED_BLOCK particles per
+// workgroup; every thread reaches the slot reservation.
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_qed_push(Tables T, void* old, double* tau, QedCall q) {
-  int blk;
-  const SegDesc& s = seg_of(T, part_block(T, blk));
-  const int64_t p = (int64_t)blk * 256 + threadIdx.x;
-  if (p >= s.n) return;
-  const RunDesc& r = run_of(T, s.run);
-  if (s.order == 1) qed_push_one<R, DIM, 1>(s, r, p, old, tau, q);
-  else qed_push_one<R, DIM, 2>(s, r, p, old, tau, q);
+__global__ __launch_bounds__(QED_BLOCK) void k_qed_push(Tables T, void* old, double* tau,
+                                                        QedCall q) {
+  const SegDesc& s = seg_of(T, 0);
+  const int64_t p = (int64_t)blockIdx.x * QED_BLOCK + threadIdx.x;
+  QedRec rec;
+  bool fire = false;
+  if (p < s.n) {
+    const RunDesc& r = run_of(T, s.run);
+    fire = s.order == 1 ? qed_push_one<R, DIM, 1>(s, r, p, old, tau, q, rec)
+                        : qed_push_one<R, DIM, 2>(s, r, p, old, tau, q, rec);
+  }
+  const int64_t slot = block_slots(q.out.count, fire, 1);
+  if (fire) put_record(q.out, slot, rec.pos, rec.u, rec.w, rec.tau, (int)p);
 }
 
 template <typename R, int DIM, int ORDER>
-__device__ __forceinline__ void qed_photon_one(const RunDesc& r, const QedBufDesc& ph,
-                                               int64_t p, const QedCall& q) {
-  if (!(ph.x[p] >= 0.0)) return;
+__device__ __forceinline__ bool qed_photon_one(const RunDesc& r, const QedBufDesc& ph,
+                                               int64_t p, const QedCall& q, QedRec& re,
+                                               QedRec& rp) {
+  if (!(ph.x[p] >= 0.0)) return false;
   const double kv[3] = {ph.ux[p], ph.uy[p], ph.uz[p]};
   const double km = sqrt(kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]);
   double v[3] = {0.0, 0.0, 0.0};
@@ -289,22 +334,26 @@ __device__ __forceinline__ void qed_photon_one(const RunDesc& r, const QedBufDes
   const double chi = qed_chi(km, kv, Ed, Bd, q.hw);
   double t = ph.tau[p];
   if (km > 0.0) t -= kAlpha * qed_pair_rate(q.tab, chi) / (km * q.hw) * r.dt;
-  if (t <= 0.0) {
+  const bool fire = t <= 0.0;
+  double *ue = re.u, *up = rp.u;
+  if (fire) {
     const double xi = qed_pair_sample(q.tab, chi, qed_draw(q.seed, q.step, p, 0));
     const double ge = xi * km, gp = (1.0 - xi) * km;
     const double ae = ge > 1.0 ? sqrt(ge * ge - 1.0) : 0.0;
     const double ap = gp > 1.0 ? sqrt(gp * gp - 1.0) : 0.0;
-    const double ue[3] = {ae * v[0], ae * v[1], ae * v[2]};
-    const double up[3] = {ap * v[0], ap * v[1], ap * v[2]};
-    double wp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) wp[d] = wrap_pos(pos[d], L[d]);
-    const int64_t i = atomicAdd(q.out.count, 2);
-    put_record(q.out, i, wp, ue, ph.w[p], -log(qed_draw(q.seed, q.step, p, 2)), (int)p);
-    put_record(q.out, i + 1, wp, up, ph.w[p], -log(qed_draw(q.seed, q.step, p, 3)), (int)p);
+    for (int d = 0; d < 3; ++d) {
+      ue[d] = ae * v[d];
+      up[d] = ap * v[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) re.pos[d] = rp.pos[d] = d < DIM ? wrap_pos(pos[d], L[d]) : 0.0;
+    re.w = rp.w = ph.w[p];
+    re.tau = qed_neglog(qed_draw(q.seed, q.step, p, 2));
+    rp.tau = qed_neglog(qed_draw(q.seed, q.step, p, 3));
     ph.tau[p] = t;
     ph.x[p] = -1.0;
-    return;
+    return true;
   }
   ph.tau[p] = t;
   double x1[3];
@@ -315,22 +364,32 @@ __device__ __forceinline__ void qed_photon_one(const RunDesc& r, const QedBufDes
   if (DIM == 3) ph.z[p] = wrap_pos(x1[2], L[2]);
   if (r.open_x && (x1[0] < OPEN_MARGIN * r.dx || x1[0] >= (r.nx - OPEN_MARGIN) * r.dx))
     ph.x[p] = -1.0;
+  return false;
 }
 
 template <typename R, int DIM>
-__global__ __launch_bounds__(256) void k_qed_photons(RunDesc r, QedBufDesc ph, int order,
-                                                     QedCall q) {
+__global__ __launch_bounds__(QED_BLOCK) void k_qed_photons(RunDesc r, QedBufDesc ph, int order,
+                                                           QedCall q) {
   const int64_t n = min((int64_t)*ph.count, ph.cap);
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
-  if (order == 1) qed_photon_one<R, DIM, 1>(r, ph, p, q);
-  else qed_photon_one<R, DIM, 2>(r, ph, p, q);
+  const int64_t p = (int64_t)blockIdx.x * QED_BLOCK + threadIdx.x;
+  if ((int64_t)blockIdx.x * QED_BLOCK >= n) return;      // the whole workgroup
+  QedRec re, rp;
+  bool fire = false;
+  if (p < n) {
+    fire = order == 1 ? qed_photon_one<R, DIM, 1>(r, ph, p, q, re, rp)
+                      : qed_photon_one<R, DIM, 2>(r, ph, p, q, re, rp);
+  }
+  const int64_t slot = block_slots(q.out.count, fire, 2);
+  if (fire) {
+    put_record(q.out, slot, re.pos, re.u, re.w, re.tau, (int)p);
+    put_record(q.out, slot + 1, rp.pos, rp.u, rp.w, rp.tau, (int)p);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_qed_tau(double* tau, int64_t n, uint64_t seed,
                                                  int64_t step) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) tau[i] = -log(qed_draw(seed, step, i, 2));
+  if (i < n) tau[i] = qed_neglog(qed_draw(seed, step, i, 2));
 }
 
 }  // namespace
@@ -358,16 +417,18 @@ void launch_qed_tau(double* tau, int64_t n, uint64_t seed, int64_t step, hipStre
   k_qed_tau<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, n, seed, step);
 }
 
-void launch_qed_push(const Tables& T, int prec, int dim, int nblocks, void* old, double* tau,
+void launch_qed_push(const Tables& T, int prec, int dim, int64_t n, void* old, double* tau,
                      const QedCall& q, hipStream_t st) {
-  LPIC_PD(prec, dim, (k_qed_push<R, D><<<nblocks, 256, 0, st>>>(T, old, tau, q)));
+  if (n <= 0) return;
+  const unsigned nblocks = (unsigned)((n + QED_BLOCK - 1) / QED_BLOCK);
+  LPIC_PD(prec, dim, (k_qed_push<R, D><<<nblocks, QED_BLOCK, 0, st>>>(T, old, tau, q)));
 }
 
 void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,
                         const QedCall& q, hipStream_t st) {
   if (ph.cap <= 0) return;
-  const unsigned nb = (unsigned)((ph.cap + 255) / 256);
-  LPIC_PD(prec, dim, (k_qed_photons<R, D><<<nb, 256, 0, st>>>(r, ph, order, q)));
+  const unsigned nb = (unsigned)((ph.cap + QED_BLOCK - 1) / QED_BLOCK);
+  LPIC_PD(prec, dim, (k_qed_photons<R, D><<<nb, QED_BLOCK, 0, st>>>(r, ph, order, q)));
 }
 
 }  // namespace lpic

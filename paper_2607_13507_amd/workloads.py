@@ -418,11 +418,18 @@ def qed_beam(ndim=2, n=24, dx=0.1, ppc=1, gamma=(500.0, 2000.0), b0=300.0, noise
 
 
 def qed_photons(wl: Workload, n, k=(1000.0, 4000.0), seed=9):
-    """n photons uniform in the box of wl with momenta |k| uniform in `k` (units of m c)
-    and isotropic directions: positions x, y, z and momenta kx, ky, kz."""
+    """n photons spread over the box of wl cell by cell in storage order (as photons emitted
+    by tile-sorted leptons lie), with momenta |k| uniform in `k` (units of m c) and isotropic
+    directions: positions x, y, z, momenta kx, ky, kz and weights."""
     rng = np.random.default_rng(seed)
+    ncell = wl.ncell
+    cell = (np.arange(n, dtype=np.int64) * ncell) // n        # non-decreasing cell index
+    ix = cell % wl.nx
+    iy = (cell // wl.nx) % wl.ny
+    iz = cell // (wl.nx * wl.ny)
+    pos = [(ix + rng.random(n)) * wl.dx, (iy + rng.random(n)) * wl.dy,
+           (iz + rng.random(n)) * wl.dz if wl.ndim == 3 else np.zeros(n)]
     Lx, Ly, Lz = wl.box()
-    pos = [rng.uniform(0, Lx, n), rng.uniform(0, Ly, n),
-           rng.uniform(0, Lz, n) if wl.ndim == 3 else np.zeros(n)]
+    pos = [_fold(pos[0], Lx), _fold(pos[1], Ly), _fold(pos[2], Lz) if wl.ndim == 3 else pos[2]]
     kv = _directions(rng, n) * rng.uniform(k[0], k[1], n)
     return pos, kv, rng.uniform(0.5, 1.5, n)

@@ -10,7 +10,7 @@ integrals, tests/test_qed_tables.py); the oracle integrates.  So:
   - depths of particles without an event agree to the rate's error times dt;
   - records are matched by their source index: photon momenta to the sampled fraction's
     error (2e-4), pair energies to 1e-4 of the photon's; depths drawn from the counter-based
-    generator agree to a few ulps;
+    generator agree to the FP32 logarithm the kernels take of the draw (1e-6);
   - particles without an event follow the plain push (the tolerances of the split path);
     those with one carry the recoil's error (2e-4 of the momentum)."""
 import math
@@ -85,7 +85,7 @@ def test_compton_push_matches_oracle(tables, ndim, prec, order):
     tau = torch.empty(n, dtype=torch.float64, device="cuda")
     L.lpic_qed_init_tau(tau.data_ptr(), n, SEED, 0)
     torch.cuda.synchronize()
-    np.testing.assert_allclose(tau.cpu().numpy(), Q.init_tau(n, SEED, 0), rtol=1e-15)
+    np.testing.assert_allclose(tau.cpu().numpy(), Q.init_tau(n, SEED, 0), rtol=1e-6)
     # the step itself starts from seeded depths that both sides take as input
     tau0 = np.random.default_rng(50 + ndim).exponential(1.0, n)
     tau.copy_(torch.from_numpy(tau0))
@@ -124,8 +124,8 @@ def test_compton_push_matches_oracle(tables, ndim, prec, order):
         ko = np.array([oph.ux[b], oph.uy[b], oph.uz[b]])
         assert np.linalg.norm(kg - ko) <= 3e-4 * np.linalg.norm(ko) + 1e-9, (i, kg, ko)
         assert gph["w"][a] == oph.w[b]
-        assert gph["tau"][a] == pytest.approx(oph.tau[b], rel=1e-14)
-        assert gtau[i] == pytest.approx(otau[i], rel=1e-14)
+        assert gph["tau"][a] == pytest.approx(oph.tau[b], rel=1e-6)
+        assert gtau[i] == pytest.approx(otau[i], rel=1e-6)
         for d, key in enumerate(("x", "y", "z")[:ndim]):
             err = abs(periodic_diff(gph[key][a], getattr(oph, key)[b], Ls[d]))
             assert err <= (1e-5 if prec == F32 else 1e-12) * wl.dx, (i, key, err)
@@ -195,7 +195,7 @@ def test_pair_push_matches_oracle(tables, ndim, prec, order):
             ug = np.array([gp["ux"][a + off], gp["uy"][a + off], gp["uz"][a + off]])
             uo = np.array([opairs.ux[b + off], opairs.uy[b + off], opairs.uz[b + off]])
             assert np.linalg.norm(ug - uo) <= 2e-4 * km, (i, off)
-            assert gp["tau"][a + off] == pytest.approx(opairs.tau[b + off], rel=1e-14)
+            assert gp["tau"][a + off] == pytest.approx(opairs.tau[b + off], rel=1e-6)
             assert gp["w"][a + off] == opairs.w[b + off]
             for d, key in enumerate(("x", "y", "z")[:ndim]):
                 err = abs(periodic_diff(gp[key][a + off], getattr(opairs, key)[b + off], Ls[d]))
