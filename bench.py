@@ -415,6 +415,29 @@ def cpu_baseline(name, wls):
 # QED event Monte-Carlo (Sec. 3.4)
 # ------------------------------------------------------------------------------------------
 QED_HW = 2e-6                  # hbar w_r / (m_e c^2)
+QED_SOURCES = ("paper_2607_13507_amd/csrc/lpic_qed.hip", "paper_2607_13507_amd/csrc/lpic_internal.hpp",
+               "paper_2607_13507_amd/csrc/lpic_device.hpp")
+
+
+def qed_traffic(kernel):
+    """HBM bytes per launch of a QED kernel from the committed counter summary
+    (profiles/qed_beam_stats.md, already divided by the copy calibration), if it was taken
+    on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "qed_beam_stats.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in QED_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    text = open(path).read()
+    if f"qed_source_sha256: {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"- {kernel}: fetch "):
+            parts = line.split()
+            return int((float(parts[3]) + float(parts[6])) * 1e6)
+    return None
 QED_PAIR_HW = 2.5e-6
 
 
@@ -545,7 +568,8 @@ def measure_qed(args, want_cpu):
         b = qed_bytes(kind, ev, 4.0)
         gbs = b * npush / (ms * 1e-3) / 1e9
         return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    frac=round(gbs / HBM_PEAK_GBS, 4),
+                    traffic=qed_traffic(kernel.split("::")[1].split("<")[0]), kernel=kernel,
                     bytes_per_push=round(b, 3), avg_launch_ms=round(ms, 4), launches=launches)
 
     out = dict(workload="qed_beam 2048x2048 f32, 16,777,216 electrons; 16,777,216 photons",
