@@ -539,7 +539,10 @@ typedef struct {
  * number of records; a call that creates records advances it atomically and writes a
  * record only below capacity, so *count > capacity after a call reports an overflow (the
  * records beyond capacity are lost).  tau is the record's optical depth, src the index of
- * the particle or photon it came from.  A removed photon has x = -1. */
+ * the particle or photon it came from.  A removed photon has x = -1.  The order of the
+ * records a call appends is not specified (each workgroup of 1024 particles reserves one
+ * contiguous range with a single atomic add; the ranges follow the workgroups' finishing
+ * order); match records by src. */
 typedef struct {
   int64_t capacity;
   int32_t *count;
