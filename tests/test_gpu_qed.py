@@ -225,3 +225,51 @@ def test_event_buffer_overflow_is_reported(tables):
     assert count == n
     assert len(rec["src"]) == 5 and np.all(rec["src"] >= 0)
     assert np.all(tau.cpu().numpy() > 0)
+
+
+@pytest.mark.parametrize("ndim,prec,order", [(2, F32, 2), (3, F64, 1)])
+def test_compton_push_feeds_the_deposit(tables, ndim, prec, order):
+    """The old state the emission push leaves is the split path's: the deposit after it
+    traces x^{n+1/2} -> x^{n+1/2} + dt v^{n+1} with the recoiled momenta, and the charge it
+    lays down at both path ends satisfies continuity node by node."""
+    banner(f"qed push + deposit ndim={ndim} prec={prec} order={order}")
+    wl = W.qed_beam(ndim=ndim, n=24 if ndim == 2 else 8, order=order, seed=70 + ndim)
+    grid, F, S, orc = device_state(wl, prec)
+    sp = S[0]
+    n = sp.n
+    tau0 = np.random.default_rng(80 + ndim).exponential(1.0, n)
+    tau = torch.from_numpy(tau0.copy()).cuda()
+    ph = DevBuf(n)
+    old = torch.empty(L.lpic_old_state_bytes(ndim, n, prec), dtype=torch.uint8, device="cuda")
+    os_ = orc.species[0]
+    x0 = [os_.x.copy(), os_.y.copy(), os_.z.copy() if ndim == 3 else None]
+    u0 = np.stack([os_.ux.copy(), os_.uy.copy(), os_.uz.copy()])
+    L.lpic_qed_gather_push(grid, F.struct(), sp.struct(), tau.data_ptr(), tables,
+                           L.QedParams(HW, SEED, 2), ph.struct(), old.data_ptr(), old.numel(),
+                           prec)
+    L.lpic_deposit_esirkepov(grid, F.struct(), sp.struct(), old.data_ptr(), old.numel(), 1, prec)
+    torch.cuda.synchronize()
+    assert int(ph.count.item()) > 0
+    # the oracle: the same push, then the deposit of every particle's path from its own state
+    oph = Q.QedBuf(n)
+    Q.qed_gather_push(orc, os_, tau0.copy(), HW, SEED, 2, oph)
+    orc.zero_currents()
+    dt = wl.dt
+    g0 = np.sqrt(1 + (u0 ** 2).sum(axis=0))
+    u1 = np.stack([os_.ux, os_.uy, os_.uz])
+    g1 = np.sqrt(1 + (u1 ** 2).sum(axis=0))
+    for i in range(n):
+        ph_ = [x0[d][i] + 0.5 * dt * u0[d, i] / g0[i] if d < ndim else 0.0 for d in range(3)]
+        pe = [ph_[d] + dt * u1[d, i] / g1[i] if d < ndim else 0.0 for d in range(3)]
+        orc.deposit_particle(order, os_.q, os_.w[i], ph_, pe, u1[2, i] / g1[i])
+        orc.deposit_rho(orc.rho0, order, os_.q, os_.w[i], ph_)
+        orc.deposit_rho(orc.rho1, order, os_.q, os_.w[i], pe)
+    g = F.numpy()
+    for k in ("jx", "jy", "jz", "rho0", "rho1"):
+        o = orc.f[k] if k.startswith("j") else getattr(orc, k)
+        err = np.abs(g[k] - o).max() / np.abs(o).max()
+        assert err < (1e-4 if prec == F32 else 1e-5), (k, err)   # emitters: recoil within 3e-4
+    for k in ("jx", "jy", "jz"):
+        orc.f[k][:] = g[k]
+    orc.rho0[:], orc.rho1[:] = g["rho0"], g["rho1"]
+    assert orc.continuity() < (1e-5 if prec == F32 else 1e-12)
