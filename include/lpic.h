@@ -563,7 +563,11 @@ lpic_status lpic_qed_init_tau(double *tau, int64_t n, uint64_t seed, int64_t ste
  * weight, depth -ln(draw 2) and src = the lepton's slot, the lepton keeps u - xi gamma
  * u/|u| and a new depth -ln(draw 1).  The rest (Boris, second half push, old_state for
  * lpic_deposit_esirkepov) is lpic_gather_push's.  Photons created here are part of the
- * next step's photon push (Algorithm 1 creates them after all species are pushed). */
+ * next step's photon push (Algorithm 1 creates them after all species are pushed).
+ * tau is indexed by slot, and lpic_sort_tiles does not move it: after a sort, draw the
+ * depths afresh (lpic_qed_init_tau with a step number not used before).  That leaves the
+ * event statistics unchanged, since a depth drawn as -ln U is exponential and so
+ * memoryless: the remaining depth of a particle that has not fired is again -ln U. */
 lpic_status lpic_qed_gather_push(const lpic_grid *grid, const lpic_fields *fields,
                                  const lpic_species *sp, double *tau,
                                  const lpic_qed_tables *tables, const lpic_qed_params *params,
