@@ -273,3 +273,61 @@ def test_compton_push_feeds_the_deposit(tables, ndim, prec, order):
         orc.f[k][:] = g[k]
     orc.rho0[:], orc.rho1[:] = g["rho0"], g["rho1"]
     assert orc.continuity() < (1e-5 if prec == F32 else 1e-12)
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_compton_steps_follow_the_oracle(tables, prec):
+    """Four emission pushes in a row (step numbers 1-4, no sort, static fields): the draws of
+    a lepton depend on its slot and the step only, so both sides fire the same events step
+    after step; a particle whose decision fell inside the tables' error once is left out
+    from then on."""
+    banner(f"qed four steps prec={prec}")
+    wl = W.qed_beam(ndim=2, n=24, order=2, seed=91)
+    grid, F, S, orc = device_state(wl, prec)
+    sp = S[0]
+    n = sp.n
+    tau0 = np.random.default_rng(92).exponential(1.0, n)
+    tau = torch.from_numpy(tau0.copy()).cuda()
+    otau = tau0.copy()
+    old = torch.empty(L.lpic_old_state_bytes(2, n, prec), dtype=torch.uint8, device="cuda")
+    os_ = orc.species[0]
+    excluded = np.zeros(n, bool)
+    total = 0
+    for step in range(1, 5):
+        ph = DevBuf(n)
+        oph = Q.QedBuf(n)
+        before = tau.cpu().numpy()
+        L.lpic_qed_gather_push(grid, F.struct(), sp.struct(), tau.data_ptr(), tables,
+                               L.QedParams(HW, SEED, step), ph.struct(), old.data_ptr(),
+                               old.numel(), prec)
+        torch.cuda.synchronize()
+        obefore = otau.copy()
+        Q.qed_gather_push(orc, os_, otau, HW, SEED, step, oph)
+        count, gph = ph.host()
+        fg = np.zeros(n, bool)
+        fg[gph["src"]] = True
+        fo = np.zeros(n, bool)
+        fo[oph.src[:oph.count]] = True
+        gt = tau.cpu().numpy()
+        for i in np.nonzero((fg != fo) & ~excluded)[0]:
+            rest = gt[i] if not fg[i] else otau[i]
+            start = before[i] if not fg[i] else obefore[i]
+            assert rest < 1e-3 * (start - rest), (step, i)
+            excluded[i] = True
+        total += int((fg & fo).sum())
+        keep = ~excluded
+        assert np.array_equal(fg[keep], fo[keep]), step
+        quiet = keep & ~fg
+        np.testing.assert_allclose(gt[quiet], otau[quiet], rtol=0,
+                                   atol=1e-12 + 3e-4 * 4 * np.abs(obefore - otau)[quiet].max())
+    assert excluded.sum() <= 3 and total > 0.2 * n, (excluded.sum(), total)
+    keep = ~excluded
+    pos = sp.positions(grid)
+    Ls = wl.box()
+    for d in range(2):
+        err = np.abs(periodic_diff(pos[d], (os_.x, os_.y)[d], Ls[d]))[keep] / wl.dx
+        assert err.max() <= 1e-4, d
+    for key in ("ux", "uy", "uz"):
+        g = sp.numpy(key).astype(np.float64)
+        o = getattr(os_, key)
+        assert np.abs(g - o)[keep].max() <= 1e-3 * np.abs(o).max(), key
