@@ -331,3 +331,97 @@ def test_compton_steps_follow_the_oracle(tables, prec):
         g = sp.numpy(key).astype(np.float64)
         o = getattr(os_, key)
         assert np.abs(g - o)[keep].max() <= 1e-3 * np.abs(o).max(), key
+
+
+def _sort_new_records(buf, c0):
+    """Orders the records a call appended (from c0 on) by source index, the order in which
+    the oracle, looping over the slots, appends them."""
+    c1 = min(int(buf.count.item()), buf.cap)
+    if c1 <= c0:
+        return c1
+    idx = torch.argsort(buf.src[c0:c1].long()) + c0
+    for t in list(buf.t.values()) + [buf.src]:
+        t[c0:c1] = t[idx].clone()
+    return c1
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_qed_steps_of_algorithm_1(tables, prec):
+    """Three whole steps of Algorithm 1 with the QED module, through the C ABI: field half
+    updates, the photon push (pairs from the photons of earlier steps), the emission push
+    and the deposit of the recoiled paths, field half updates; against the oracle's pieces
+    in the same order.  The new photon records of each step are put in source order, the
+    oracle's, so that the photon draws (keyed by slot) agree at the next step."""
+    banner(f"qed algorithm-1 steps prec={prec}")
+    # a strong field and long steps: leptons emit at nearly every step (chi_e ~ 5) and a
+    # good share of their photons (chi_g ~ 1) turn into pairs within a step or two
+    wl = W.qed_beam(ndim=2, n=24, dx=0.5, b0=2000.0, order=2, seed=101)
+    grid, F, S, orc = device_state(wl, prec)
+    sp = S[0]
+    n = sp.n
+    hw = 2.5e-6
+    tau0 = np.random.default_rng(102).exponential(1.0, n)
+    tau = torch.from_numpy(tau0.copy()).cuda()
+    otau = tau0.copy()
+    old = torch.empty(L.lpic_old_state_bytes(2, n, prec), dtype=torch.uint8, device="cuda")
+    ph, pairs = DevBuf(4 * n), DevBuf(8 * n)
+    oph, opairs = Q.QedBuf(4 * n), Q.QedBuf(8 * n)
+    os_ = orc.species[0]
+    dt = wl.dt
+    fs = F.struct()
+    for step in range(1, 4):
+        L.lpic_yee_update_EB(grid, fs, 0, 0.5, 0, prec)
+        L.lpic_yee_update_EB(grid, fs, 1, 0.5, 0, prec)
+        for k in ("jx", "jy", "jz"):
+            F.t[k].zero_()
+        F.rho0.zero_()
+        F.rho1.zero_()
+        L.lpic_qed_photon_push(grid, fs, 2, ph.struct(), tables, L.QedParams(hw, SEED, step),
+                               pairs.struct(), prec)
+        c0 = min(int(ph.count.item()), ph.cap)
+        L.lpic_qed_gather_push(grid, fs, sp.struct(), tau.data_ptr(), tables,
+                               L.QedParams(hw, SEED, step), ph.struct(), old.data_ptr(),
+                               old.numel(), prec)
+        L.lpic_deposit_esirkepov(grid, fs, sp.struct(), old.data_ptr(), old.numel(), 1, prec)
+        L.lpic_yee_update_EB(grid, fs, 1, 0.5, 0, prec)
+        L.lpic_yee_update_EB(grid, fs, 0, 0.5, 0, prec)
+        torch.cuda.synchronize()
+        _sort_new_records(ph, c0)
+        # the oracle, piece by piece in the same order
+        orc.yee_e(0.5)
+        orc.yee_b(0.5)
+        orc.zero_currents()
+        Q.qed_photon_push(orc, 2, oph, hw, SEED, step, opairs)
+        x0 = [os_.x.copy(), os_.y.copy()]
+        u0 = np.stack([os_.ux.copy(), os_.uy.copy(), os_.uz.copy()])
+        Q.qed_gather_push(orc, os_, otau, hw, SEED, step, oph)
+        g0 = np.sqrt(1 + (u0 ** 2).sum(axis=0))
+        u1 = np.stack([os_.ux, os_.uy, os_.uz])
+        g1 = np.sqrt(1 + (u1 ** 2).sum(axis=0))
+        for i in range(n):
+            a = [x0[0][i] + 0.5 * dt * u0[0, i] / g0[i], x0[1][i] + 0.5 * dt * u0[1, i] / g0[i], 0.0]
+            b = [a[0] + dt * u1[0, i] / g1[i], a[1] + dt * u1[1, i] / g1[i], 0.0]
+            orc.deposit_particle(2, os_.q, os_.w[i], a, b, u1[2, i] / g1[i])
+            orc.deposit_rho(orc.rho0, 2, os_.q, os_.w[i], a)
+            orc.deposit_rho(orc.rho1, 2, os_.q, os_.w[i], b)
+        orc.yee_b(0.5)
+        orc.yee_e(0.5)
+        cnt, cnt_o = int(ph.count.item()), oph.count
+        pc, pc_o = int(pairs.count.item()), opairs.count
+        banner(f"step {step}: photons {cnt} / {cnt_o}, pair records {pc} / {pc_o}")
+        assert cnt == cnt_o and pc == pc_o, step
+        np.testing.assert_array_equal(ph.src[:cnt].cpu().numpy(), oph.src[:cnt])
+    assert oph.count > 0.2 * n and opairs.count > 0
+    # depths: fresh ones agree to 1e-6, decremented ones to the rates' 2e-4 of up to three
+    # decrements of rate x dt ~ 4
+    np.testing.assert_allclose(tau.cpu().numpy(), otau, rtol=1e-6, atol=3e-3)
+    # fields and currents: the sampled fractions' 5e-5 (tables) reach the emitters' paths
+    tol = 1e-4
+    g = F.numpy()
+    for k in ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz"):
+        err = np.abs(g[k] - orc.f[k]).max() / max(np.abs(orc.f[k]).max(), 1e-30)
+        assert err < tol, (k, err)
+    for k in ("jx", "jy", "jz"):
+        orc.f[k][:] = g[k]
+    orc.rho0[:], orc.rho1[:] = g["rho0"], g["rho1"]
+    assert orc.continuity() < (1e-5 if prec == F32 else 1e-12)
