@@ -589,6 +589,19 @@ lpic_status lpic_qed_photon_push(const lpic_grid *grid, const lpic_fields *field
                                  const lpic_qed_buffer *pairs, lpic_precision prec,
                                  hipStream_t stream);
 
+/* Inserts event records into a species (Sec. 3.4: the new particles of a pair go into the
+ * species arrays; Algorithm 1 does it after all species are pushed): record i of *records
+ * (i < min(*count, capacity) as the kernel starts) with i % 2 == parity (0: the electrons
+ * of a pair buffer, 1: the positrons), or every record with parity = -1, is written into
+ * slot first + i / 2 (first + i with parity -1) of *sp: its position in the species'
+ * representation (a record with x < 0 becomes a dead slot), momentum and weight.  Slots
+ * at or beyond sp->n are not written and counted in *dropped (device int32, may be NULL).
+ * The caller chooses `first`, e.g. the start of the dead block that lpic_sort_tiles
+ * reports (tile_offsets[ntiles]); what the slots held before is overwritten. */
+lpic_status lpic_qed_insert(const lpic_grid *grid, const lpic_species *sp, int64_t first,
+                            const lpic_qed_buffer *records, int32_t parity, int32_t *dropped,
+                            lpic_precision prec, hipStream_t stream);
+
 const char *lpic_last_error(void);
 const char *lpic_version(void);
 

@@ -509,6 +509,22 @@ lpic_status lpic_qed_photon_push(const lpic_grid* grid, const lpic_fields* field
   return last_launch("qed_photon_push");
 }
 
+lpic_status lpic_qed_insert(const lpic_grid* grid, const lpic_species* sp, int64_t first,
+                            const lpic_qed_buffer* records, int32_t parity, int32_t* dropped,
+                            lpic_precision prec, hipStream_t stream) {
+  CHK(check_grid(grid, prec));
+  CHK(check_species(sp, grid->ndim, prec));
+  CHK(check_qed_buffer(records, grid->ndim, "record"));
+  if (parity < -1 || parity > 1) return fail(LPIC_EINVAL, "parity must be -1, 0 or 1");
+  if (first < 0) return fail(LPIC_EINVAL, "first must be >= 0");
+  if (records->capacity == 0 || sp->n == 0) return LPIC_OK;
+  RunDesc r = make_run(grid, nullptr, nullptr);
+  SegDesc s = make_seg(sp, nullptr, 0, nullptr, 0, 0, prec);
+  Tables T = single_tables(r, &s);
+  launch_qed_insert(T, prec, grid->ndim, first, qed_desc(records), parity, dropped, stream);
+  return last_launch("qed_insert");
+}
+
 int64_t lpic_num_tiles(const lpic_grid* grid, const lpic_tiling* tiling) {
   if (!grid || !tiling || tiling->tx <= 0 || tiling->ty <= 0) return -1;
   lpic_tiling t = *tiling;

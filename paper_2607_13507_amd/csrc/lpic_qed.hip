@@ -392,6 +392,49 @@ __global__ __launch_bounds__(256) void k_qed_tau(double* tau, int64_t n, uint64_
   if (i < n) tau[i] = qed_neglog(qed_draw(seed, step, i, 2));
 }
 
+// Records into species slots: record i of the selected parity (or every record, parity < 0)
+// goes to slot first + i / 2 (or first + i); positions become the species' representation
+// (FP32: wrapped cell and offset; FP64: absolute), momenta and weight its precision.
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_qed_insert(Tables T, int64_t first, QedBufDesc b,
+                                                    int parity, int32_t* dropped) {
+  const SegDesc& s = seg_of(T, 0);
+  const RunDesc& r = run_of(T, s.run);
+  const int64_t nrec = min((int64_t)*b.count, b.cap);
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nrec || (parity >= 0 && (i & 1) != parity)) return;
+  const int64_t p = first + (parity >= 0 ? i >> 1 : i);
+  if (p >= s.n) {
+    if (dropped) atomicAdd(dropped, 1);
+    return;
+  }
+  const double src[3] = {b.x[i], b.y[i], DIM == 3 ? b.z[i] : 0.0};
+  if constexpr (sizeof(R) == 4) {
+    const double h[3] = {r.dx, r.dy, r.dz};
+    const int n[3] = {r.nx, r.ny, r.nz};
+    int c[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double X = src[d] / h[d];
+      const double f = floor(X);
+      int ci = (int)f;
+      float o = (float)(X - f);
+      if (o >= 1.0f) { o = 0.0f; ci += 1; }
+      ci = ci >= n[d] ? ci - n[d] : (ci < 0 ? ci + n[d] : ci);
+      c[d] = ci;
+      ((float*)s.p[P_OX + d])[p] = o;
+    }
+    ((int32_t*)s.p[P_CELL])[p] = b.x[i] >= 0.0 ? pack_cell(c, DIM) : -1;
+  } else {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ((double*)s.p[P_X + d])[p] = src[d];
+  }
+  ((R*)s.p[P_UX])[p] = (R)b.ux[i];
+  ((R*)s.p[P_UY])[p] = (R)b.uy[i];
+  ((R*)s.p[P_UZ])[p] = (R)b.uz[i];
+  ((R*)s.p[P_W])[p] = (R)b.w[i];
+}
+
 }  // namespace
 
 size_t qed_table_doubles() {
@@ -422,6 +465,13 @@ void launch_qed_push(const Tables& T, int prec, int dim, int64_t n, void* old, d
   if (n <= 0) return;
   const unsigned nblocks = (unsigned)((n + QED_BLOCK - 1) / QED_BLOCK);
   LPIC_PD(prec, dim, (k_qed_push<R, D><<<nblocks, QED_BLOCK, 0, st>>>(T, old, tau, q)));
+}
+
+void launch_qed_insert(const Tables& T, int prec, int dim, int64_t first, const QedBufDesc& b,
+                       int parity, int32_t* dropped, hipStream_t st) {
+  if (b.cap <= 0) return;
+  const unsigned nb = (unsigned)((b.cap + 255) / 256);
+  LPIC_PD(prec, dim, (k_qed_insert<R, D><<<nb, 256, 0, st>>>(T, first, b, parity, dropped)));
 }
 
 void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,

@@ -203,6 +203,9 @@ EXPORTS = {
                                             ctypes.POINTER(Species), _vp, _vp,
                                             ctypes.POINTER(QedParams), ctypes.POINTER(QedBuffer),
                                             _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "lpic_qed_insert": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Species),
+                                       ctypes.c_int64, ctypes.POINTER(QedBuffer), ctypes.c_int32,
+                                       _vp, ctypes.c_int, _vp]),
     "lpic_qed_photon_push": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Fields),
                                             ctypes.c_int32, ctypes.POINTER(QedBuffer), _vp,
                                             ctypes.POINTER(QedParams), ctypes.POINTER(QedBuffer),
@@ -471,3 +474,9 @@ def lpic_qed_photon_push(grid, fields, order, photons, tables, params, pairs, pr
            lib().lpic_qed_photon_push(ctypes.byref(grid), ctypes.byref(fields), order,
                                       ctypes.byref(photons), tables, ctypes.byref(params),
                                       ctypes.byref(pairs), prec, _stream(stream)))
+
+
+def lpic_qed_insert(grid, species, first, records, parity, dropped, prec, stream=None):
+    _check("lpic_qed_insert",
+           lib().lpic_qed_insert(ctypes.byref(grid), ctypes.byref(species), first,
+                                 ctypes.byref(records), parity, dropped, prec, _stream(stream)))

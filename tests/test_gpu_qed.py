@@ -425,3 +425,44 @@ def test_qed_steps_of_algorithm_1(tables, prec):
         orc.f[k][:] = g[k]
     orc.rho0[:], orc.rho1[:] = g["rho0"], g["rho1"]
     assert orc.continuity() < (1e-5 if prec == F32 else 1e-12)
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_pairs_go_into_species(tables, prec):
+    """The electrons (even records) and positrons (odd records) of a pair buffer into two
+    species: positions in the species' representation, momenta and weights; slots past the
+    species' end are counted as dropped."""
+    banner(f"qed insert prec={prec}")
+    from paper_2607_13507_amd.simulation import DeviceSpecies
+    wl = W.qed_beam(ndim=2, n=16, dx=0.5, b0=2000.0, order=2, seed=111)
+    wl.species = []
+    grid, F, S, orc = device_state(wl, prec)
+    n = 400
+    pos, kv, w = W.qed_photons(wl, n, seed=112)
+    ph = DevBuf(n, count=n)
+    for k, v in dict(x=pos[0], y=pos[1], z=pos[2], ux=kv[0], uy=kv[1], uz=kv[2], w=w,
+                     tau=np.random.default_rng(113).exponential(1.0, n)).items():
+        ph.t[k].copy_(torch.from_numpy(np.ascontiguousarray(v)))
+    pairs = DevBuf(2 * n)
+    L.lpic_qed_photon_push(grid, F.struct(), 2, ph.struct(), tables,
+                           L.QedParams(2.5e-6, SEED, 1), pairs.struct(), prec)
+    torch.cuda.synchronize()
+    m, rec = pairs.host()
+    assert m > 20
+    npairs = m // 2
+    room = npairs - 5                       # five pairs do not fit
+    dropped = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for parity, q in ((0, -1.0), (1, 1.0)):
+        sp = DeviceSpecies(2, room, q, 1.0, 2, prec)
+        L.lpic_qed_insert(grid, sp.struct(), 0, pairs.struct(), parity, dropped.data_ptr(), prec)
+        torch.cuda.synchronize()
+        got = sp.positions(grid)
+        sel = np.arange(parity, 2 * room, 2)
+        Ls = wl.box()
+        for d, key in enumerate(("x", "y")):
+            err = np.abs(periodic_diff(got[d], rec[key][sel], Ls[d])).max() / wl.dx
+            assert err <= (1e-6 if prec == F32 else 1e-13), (parity, key, err)
+        for key in ("ux", "uy", "uz", "w"):
+            np.testing.assert_allclose(sp.numpy(key), rec[key][sel],
+                                       rtol=1e-7 if prec == F32 else 0)
+    assert int(dropped.item()) == 2 * 5
