@@ -74,3 +74,9 @@ def test_qed_calls_validate_on_the_host():
         L.lpic_qed_photon_push(g, f, 2, bad, 1, L.QedParams(1e-6, 1, 0), buf, L.F32_CELLOFS,
                                stream=0)
     assert "count" in str(e.value)
+    with pytest.raises(L.LpicError) as e:
+        L.lpic_qed_insert(g, s, 0, buf, 2, None, L.F32_CELLOFS, stream=0)
+    assert "parity" in str(e.value)
+    with pytest.raises(L.LpicError) as e:
+        L.lpic_qed_insert(g, s, -1, buf, 0, None, L.F32_CELLOFS, stream=0)
+    assert "first" in str(e.value)
