@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <cmath>
 #include <string>
@@ -421,7 +422,9 @@ lpic_status lpic_qed_tables_create(int32_t on_device, lpic_qed_tables** out) {
   if (!out) return fail(LPIC_EINVAL, "out is NULL");
   *out = nullptr;
   const double* host = qed_host_tables();
-  lpic_qed_tables* t = new lpic_qed_tables;
+  if (!host) return fail(LPIC_ENOMEM, "QED tables: host memory");
+  lpic_qed_tables* t = new (std::nothrow) lpic_qed_tables;
+  if (!t) return fail(LPIC_ENOMEM, "QED tables: host memory");
   t->host = qed_views(host);
   t->dev = QedTab{nullptr, nullptr, nullptr, nullptr};
   if (on_device) {

@@ -140,10 +140,20 @@ void build_tables() {
       }
     }
   };
-  unsigned nt = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+  // rows are independent: spread them over the host threads; if no thread can be started
+  // the calling thread takes the rows of the threads that are missing
+  const unsigned nt = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
   std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, (int)t, (int)nt);
+  std::vector<int> orphan;
+  for (unsigned t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work, (int)t, (int)nt);
+    } catch (...) {
+      orphan.push_back((int)t);
+    }
+  }
   work(0, (int)nt);
+  for (int t : orphan) work(t, (int)nt);
   for (auto& t : th) t.join();
 }
 
@@ -441,9 +451,14 @@ size_t qed_table_doubles() {
   return (size_t)QED_NE + QED_NP + (size_t)(QED_NE + QED_NP) * QED_NZ;
 }
 
+// nullptr if the host memory for the tables could not be had
 const double* qed_host_tables() {
-  std::call_once(g_once, build_tables);
-  return g_host.data();
+  try {
+    std::call_once(g_once, build_tables);
+  } catch (...) {
+    return nullptr;
+  }
+  return g_host.size() == qed_table_doubles() ? g_host.data() : nullptr;
 }
 
 QedTab qed_views(const double* base) {
