@@ -589,6 +589,16 @@ lpic_status lpic_qed_photon_push(const lpic_grid *grid, const lpic_fields *field
                                  const lpic_qed_buffer *pairs, lpic_precision prec,
                                  hipStream_t stream);
 
+/* Stable compaction of a record buffer, out of place: the records of *in (i < min(*count,
+ * capacity)) that are alive (x >= 0; a converted photon is removed lazily by x = -1) are
+ * copied to the front of *out in their order and *out->count is set to their number.
+ * out->capacity >= in->capacity; ws: caller-owned device scratch of
+ * lpic_qed_compact_ws_bytes(in->capacity) bytes.  The compacted records keep their src;
+ * their slots (the counters of later photon draws) change. */
+size_t lpic_qed_compact_ws_bytes(int64_t capacity);
+lpic_status lpic_qed_compact(const lpic_qed_buffer *in, const lpic_qed_buffer *out, int32_t ndim,
+                             void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Inserts event records into a species (Sec. 3.4: the new particles of a pair go into the
  * species arrays; Algorithm 1 does it after all species are pushed): record i of *records
  * (i < min(*count, capacity) as the kernel starts) with i % 2 == parity (0: the electrons

@@ -512,6 +512,25 @@ lpic_status lpic_qed_photon_push(const lpic_grid* grid, const lpic_fields* field
   return last_launch("qed_photon_push");
 }
 
+size_t lpic_qed_compact_ws_bytes(int64_t capacity) {
+  return capacity <= 0 ? 0 : sizeof(int32_t) * ((size_t)qed_compact_blocks(capacity) + 1);
+}
+
+lpic_status lpic_qed_compact(const lpic_qed_buffer* in, const lpic_qed_buffer* out, int32_t ndim,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (ndim != 2 && ndim != 3) return fail(LPIC_EINVAL, "ndim must be 2 or 3");
+  CHK(check_qed_buffer(in, ndim, "input"));
+  CHK(check_qed_buffer(out, ndim, "output"));
+  if (in->capacity == 0) return LPIC_OK;
+  if (out->capacity < in->capacity)
+    return fail(LPIC_EINVAL, "the output buffer must hold the input's capacity");
+  if (in->x == out->x) return fail(LPIC_EINVAL, "compaction is out of place");
+  if (!ws || ws_bytes < lpic_qed_compact_ws_bytes(in->capacity))
+    return fail(LPIC_EINVAL, "ws needs %zu bytes", lpic_qed_compact_ws_bytes(in->capacity));
+  launch_qed_compact(qed_desc(in), qed_desc(out), (int32_t*)ws, stream);
+  return last_launch("qed_compact");
+}
+
 lpic_status lpic_qed_insert(const lpic_grid* grid, const lpic_species* sp, int64_t first,
                             const lpic_qed_buffer* records, int32_t parity, int32_t* dropped,
                             lpic_precision prec, hipStream_t stream) {

@@ -323,6 +323,9 @@ void launch_qed_push(const Tables& T, int prec, int dim, int64_t n, void* old, d
                      const QedCall& q, hipStream_t st);
 void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,
                         const QedCall& q, hipStream_t st);
+int qed_compact_blocks(int64_t cap);
+void launch_qed_compact(const QedBufDesc& in, const QedBufDesc& out, int32_t* blk,
+                        hipStream_t st);
 void launch_qed_insert(const Tables& T, int prec, int dim, int64_t first, const QedBufDesc& b,
                        int parity, int32_t* dropped, hipStream_t st);
 

@@ -402,6 +402,79 @@ __global__ __launch_bounds__(256) void k_qed_tau(double* tau, int64_t n, uint64_
   if (i < n) tau[i] = qed_neglog(qed_draw(seed, step, i, 2));
 }
 
+// Stable compaction of a record buffer (the lazily deleted records, x < 0, dropped):
+// per-workgroup live counts, one workgroup's exclusive scan of them, then a scatter that
+// keeps the records' order.
+__global__ __launch_bounds__(QED_BLOCK) void k_qed_live_counts(QedBufDesc b, int32_t* blk) {
+  __shared__ int wsum[QED_BLOCK / 64];
+  const int64_t n = min((int64_t)*b.count, b.cap);
+  const int64_t i = (int64_t)blockIdx.x * QED_BLOCK + threadIdx.x;
+  const bool live = i < n && b.x[i] >= 0.0;
+  const uint64_t m = __ballot(live);
+  if (__lane_id() == 0) wsum[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < QED_BLOCK / 64; ++w) t += wsum[w];
+    blk[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of nblk counts in place, the total into blk[nblk]: one workgroup walks the
+// counts QED_BLOCK at a time.
+__global__ __launch_bounds__(QED_BLOCK) void k_qed_scan_counts(int32_t* blk, int nblk) {
+  __shared__ int wsum[QED_BLOCK / 64];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+  for (int base = 0; base < nblk; base += QED_BLOCK) {
+    const int i = base + (int)threadIdx.x;
+    const int v = i < nblk ? blk[i] : 0;
+    int x = v;   // inclusive scan inside the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int before = carry;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (i < nblk) blk[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == QED_BLOCK - 1) carry = before + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk[nblk] = carry;
+}
+
+__global__ __launch_bounds__(QED_BLOCK) void k_qed_compact(QedBufDesc in, QedBufDesc out,
+                                                           const int32_t* blk, int nblk) {
+  __shared__ int wsum[QED_BLOCK / 64];
+  const int64_t n = min((int64_t)*in.count, in.cap);
+  const int64_t i = (int64_t)blockIdx.x * QED_BLOCK + threadIdx.x;
+  const bool live = i < n && in.x[i] >= 0.0;
+  const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+  const uint64_t m = __ballot(live);
+  if (lane == 0) wsum[wave] = __popcll(m);
+  __syncthreads();
+  int before = blk[blockIdx.x];
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  const int64_t j = (int64_t)before + __popcll(m & ((1ull << lane) - 1ull));
+  if (live && j < out.cap) {
+    out.x[j] = in.x[i];
+    out.y[j] = in.y[i];
+    if (out.z && in.z) out.z[j] = in.z[i];
+    out.ux[j] = in.ux[i];
+    out.uy[j] = in.uy[i];
+    out.uz[j] = in.uz[i];
+    out.w[j] = in.w[i];
+    out.tau[j] = in.tau[i];
+    out.src[j] = in.src[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out.count = blk[nblk];
+}
+
 // Records into species slots: record i of the selected parity (or every record, parity < 0)
 // goes to slot first + i / 2 (or first + i); positions become the species' representation
 // (FP32: wrapped cell and offset; FP64: absolute), momenta and weight its precision.
@@ -487,6 +560,17 @@ void launch_qed_insert(const Tables& T, int prec, int dim, int64_t first, const 
   if (b.cap <= 0) return;
   const unsigned nb = (unsigned)((b.cap + 255) / 256);
   LPIC_PD(prec, dim, (k_qed_insert<R, D><<<nb, 256, 0, st>>>(T, first, b, parity, dropped)));
+}
+
+int qed_compact_blocks(int64_t cap) { return (int)((cap + QED_BLOCK - 1) / QED_BLOCK); }
+
+void launch_qed_compact(const QedBufDesc& in, const QedBufDesc& out, int32_t* blk,
+                        hipStream_t st) {
+  const int nb = qed_compact_blocks(in.cap);
+  if (nb <= 0) return;
+  k_qed_live_counts<<<nb, QED_BLOCK, 0, st>>>(in, blk);
+  k_qed_scan_counts<<<1, QED_BLOCK, 0, st>>>(blk, nb);
+  k_qed_compact<<<nb, QED_BLOCK, 0, st>>>(in, out, blk, nb);
 }
 
 void launch_qed_photons(const RunDesc& r, int prec, int dim, int order, const QedBufDesc& ph,

@@ -203,6 +203,9 @@ EXPORTS = {
                                             ctypes.POINTER(Species), _vp, _vp,
                                             ctypes.POINTER(QedParams), ctypes.POINTER(QedBuffer),
                                             _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "lpic_qed_compact_ws_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "lpic_qed_compact": (ctypes.c_int, [ctypes.POINTER(QedBuffer), ctypes.POINTER(QedBuffer),
+                                        ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "lpic_qed_insert": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Species),
                                        ctypes.c_int64, ctypes.POINTER(QedBuffer), ctypes.c_int32,
                                        _vp, ctypes.c_int, _vp]),
@@ -480,3 +483,13 @@ def lpic_qed_insert(grid, species, first, records, parity, dropped, prec, stream
     _check("lpic_qed_insert",
            lib().lpic_qed_insert(ctypes.byref(grid), ctypes.byref(species), first,
                                  ctypes.byref(records), parity, dropped, prec, _stream(stream)))
+
+
+def lpic_qed_compact_ws_bytes(capacity):
+    return lib().lpic_qed_compact_ws_bytes(capacity)
+
+
+def lpic_qed_compact(inp, out, ndim, ws, ws_bytes, stream=None):
+    _check("lpic_qed_compact",
+           lib().lpic_qed_compact(ctypes.byref(inp), ctypes.byref(out), ndim, ws, ws_bytes,
+                                  _stream(stream)))

@@ -466,3 +466,30 @@ def test_pairs_go_into_species(tables, prec):
             np.testing.assert_allclose(sp.numpy(key), rec[key][sel],
                                        rtol=1e-7 if prec == F32 else 0)
     assert int(dropped.item()) == 2 * 5
+
+
+@pytest.mark.parametrize("cap,count", [(1000, 1000), (3_000_000, 2_900_000), (5000, 7000)])
+def test_record_compaction(cap, count):
+    """Dead records (x < 0) dropped, the rest in order, the count set: a small buffer, one
+    whose block counts take several passes of the scan, and one whose count overflowed its
+    capacity (only the capacity's records exist)."""
+    banner(f"qed compaction cap={cap} count={count}")
+    rng = np.random.default_rng(cap)
+    a = DevBuf(cap, count=count)
+    vals = {k: rng.uniform(0, 5, cap) for k in DevBuf.KEYS}
+    vals["x"][rng.random(cap) < 0.4] = -1.0
+    for k, v in vals.items():
+        a.t[k].copy_(torch.from_numpy(v))
+    src = np.arange(cap, dtype=np.int32)
+    a.src.copy_(torch.from_numpy(src))
+    b = DevBuf(cap)
+    ws = torch.empty(L.lpic_qed_compact_ws_bytes(cap), dtype=torch.uint8, device="cuda")
+    L.lpic_qed_compact(a.struct(), b.struct(), 2, ws.data_ptr(), ws.numel())
+    torch.cuda.synchronize()
+    n = min(count, cap)
+    keep = np.nonzero(vals["x"][:n] >= 0)[0]
+    m, rec = b.host()
+    assert m == len(keep)
+    np.testing.assert_array_equal(rec["src"], src[keep])
+    for k in DevBuf.KEYS:
+        np.testing.assert_array_equal(rec[k], vals[k][keep])
