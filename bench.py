@@ -26,7 +26,8 @@ Also measured, each with its own roofline and CPU baseline (keys of "extra"):
                           in a 300 m_e w c / e magnetic field with 20% random E and B
                           (quantum parameters ~0.1-3), one emission gather-push launch per
                           step, and 16,777,216 photons (|k| 1000-4000 m_e c) in a 2000-unit
-                          field for the pair push; launches timed with HIP events, records
+                          field for the pair push, the converted photons compacted out
+                          between launches; launches timed with HIP events, records
                           written to caller buffers.
 
 Every configuration runs the FP32 cell+offset path (`value`) and the plain FP64 path beside
@@ -544,15 +545,28 @@ def measure_qed(args, want_cpu):
     phot.count.fill_(m)
     L.lpic_qed_init_tau(phot.t["tau"].data_ptr(), m, 2, 0)
     pairs = _QedBuf(m)
-    alive, pcounts = [], []
+    spare = _QedBuf(m)
+    ws = torch.empty(L.lpic_qed_compact_ws_bytes(m), dtype=torch.uint8, device="cuda")
+    alive, pcounts, compact_ms = [], [], []
+    bufs = [phot, spare]
 
     def pair(i):
-        L.lpic_qed_photon_push(grid2, F2.struct(), 2, phot.struct(), tabs,
+        L.lpic_qed_photon_push(grid2, F2.struct(), 2, bufs[0].struct(), tabs,
                                L.QedParams(QED_PAIR_HW, 2, 1 + i), pairs.struct(), F32,
                                stream=st)
 
     def pair_reset():
-        alive.append(int((phot.t["x"] >= 0).sum().item()))
+        # the converted photons leave the buffer (stable compaction, timed on its own), so
+        # every launch pushes live photons only
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        L.lpic_qed_compact(bufs[0].struct(), bufs[1].struct(), 2, ws.data_ptr(), ws.numel(),
+                           stream=st)
+        b.record(stream)
+        b.synchronize()
+        compact_ms.append(a.elapsed_time(b))
+        bufs.reverse()
+        alive.append(int(bufs[0].count.item()))
         if pairs.count.item() > 0:
             pcounts.append(int(pairs.count.item()) // 2)
         pairs.count.zero_()
@@ -561,7 +575,8 @@ def measure_qed(args, want_cpu):
     pair_reset()
     live = sum(alive[warm:warm + launches]) / launches
     ev_pair = sum(pcounts[-launches:]) / launches / live
-    del phot, pairs, F2, fields_f, F
+    ms_compact = sum(compact_ms[warm:warm + launches]) / launches
+    del phot, spare, pairs, bufs, ws, F2, fields_f, F
     L.lpic_qed_tables_destroy(tabs)
 
     def roof(kind, npush, ms, ev, kernel):
@@ -581,6 +596,7 @@ def measure_qed(args, want_cpu):
                              roofline=roof("emit", n, ms_emit, ev_emit, "lpic::k_qed_push<float,2>")),
                pairs=dict(pushes_per_s=round(live / (ms_pair * 1e-3), 1),
                           avg_launch_ms=round(ms_pair, 4), live_photons=int(live),
+                          compaction_ms=round(ms_compact, 4),
                           events_per_push=round(ev_pair, 5), hbar_omega=QED_PAIR_HW,
                           roofline=roof("pair", live, ms_pair, ev_pair,
                                         "lpic::k_qed_photons<float,2>")))
