@@ -144,14 +144,17 @@ def test_compton_push_matches_oracle(tables, ndim, prec, order):
         assert np.abs(g - o)[both].max(initial=0) <= 3e-4 * scale, key
 
 
-@pytest.mark.parametrize("ndim,prec,order", [(2, F32, 2), (2, F64, 1), (3, F64, 2),
-                                             (3, F32, 1)])
-def test_pair_push_matches_oracle(tables, ndim, prec, order):
-    banner(f"qed pair push ndim={ndim} prec={prec} order={order}")
-    # strong field and long steps: pair creation in a good fraction of the photons
+@pytest.mark.parametrize("ndim,prec,order,open_x", [(2, F32, 2, False), (2, F64, 1, False),
+                                                    (3, F64, 2, False), (3, F32, 1, False),
+                                                    (2, F64, 2, True), (3, F32, 2, True)])
+def test_pair_push_matches_oracle(tables, ndim, prec, order, open_x):
+    banner(f"qed pair push ndim={ndim} prec={prec} order={order} open_x={open_x}")
+    # strong field and long steps: pair creation in a good fraction of the photons; with open
+    # x ends the photons crossing the margins are removed
     wl = W.qed_beam(ndim=ndim, n=16 if ndim == 2 else 8, dx=0.5, b0=2000.0, order=order,
                     seed=30 + ndim)
     wl.species = []
+    wl.open_x = open_x
     grid, F, S, orc = device_state(wl, prec)
     n = 600
     pos, kv, w = W.qed_photons(wl, n, seed=40 + ndim)
@@ -172,12 +175,19 @@ def test_pair_push_matches_oracle(tables, ndim, prec, order):
     Q.qed_photon_push(orc, order, oph, hw, SEED, 5, opairs)
     _, g = ph.host()
     m, gp = pairs.host()
-    fired_g = g["x"] < 0
-    fired_o = oph.x < 0
+    fired_g = np.zeros(n, bool)           # photons that turned into a pair
+    fired_g[gp["src"][0::2]] = True
+    fired_o = np.zeros(n, bool)
+    fired_o[opairs.src[:opairs.count:2]] = True
+    assert np.all(g["x"][fired_g] < 0) and np.all(oph.x[fired_o] < 0)
     banner(f"pairs: gpu {m // 2}, oracle {opairs.count // 2} of {n} photons")
     assert m % 2 == 0 and opairs.count > 0.05 * n
     both = _decisions(fired_g, fired_o, tau0, g["tau"], oph.tau)
-    quiet = ~fired_g & ~fired_o
+    if open_x:   # removed at an open end: the same photons on both sides
+        gone_o = (oph.x < 0) & ~fired_o
+        assert gone_o.sum() > 0
+        np.testing.assert_array_equal((g["x"] < 0) & ~fired_g, gone_o)
+    quiet = ~fired_g & ~fired_o & (oph.x >= 0)
     np.testing.assert_allclose(g["tau"][quiet], oph.tau[quiet], rtol=0,
                                atol=1e-12 + 3e-4 * np.abs(tau0 - oph.tau)[quiet].max())
     Ls = wl.box()
@@ -227,13 +237,21 @@ def test_event_buffer_overflow_is_reported(tables):
     assert np.all(tau.cpu().numpy() > 0)
 
 
-@pytest.mark.parametrize("ndim,prec,order", [(2, F32, 2), (3, F64, 1)])
-def test_compton_push_feeds_the_deposit(tables, ndim, prec, order):
+@pytest.mark.parametrize("ndim,prec,order,open_x", [(2, F32, 2, False), (3, F64, 1, False),
+                                                    (2, F64, 2, True), (3, F32, 1, True)])
+def test_compton_push_feeds_the_deposit(tables, ndim, prec, order, open_x):
     """The old state the emission push leaves is the split path's: the deposit after it
     traces x^{n+1/2} -> x^{n+1/2} + dt v^{n+1} with the recoiled momenta, and the charge it
     lays down at both path ends satisfies continuity node by node."""
     banner(f"qed push + deposit ndim={ndim} prec={prec} order={order}")
     wl = W.qed_beam(ndim=ndim, n=24 if ndim == 2 else 8, order=order, seed=70 + ndim)
+    wl.open_x = open_x
+    if open_x:   # keep the particles out of the margins at the start
+        s0 = wl.species[0]
+        inside = (s0.x >= 3 * wl.dx) & (s0.x < (wl.nx - 3) * wl.dx)
+        for k in ("x", "y", "z", "ux", "uy", "uz", "w"):
+            if getattr(s0, k) is not None:
+                setattr(s0, k, getattr(s0, k)[inside])
     grid, F, S, orc = device_state(wl, prec)
     sp = S[0]
     n = sp.n
@@ -273,6 +291,11 @@ def test_compton_push_feeds_the_deposit(tables, ndim, prec, order):
         orc.f[k][:] = g[k]
     orc.rho0[:], orc.rho1[:] = g["rho0"], g["rho1"]
     assert orc.continuity() < (1e-5 if prec == F32 else 1e-12)
+    # open ends: the leptons that left are removed after their deposit, on both sides
+    dead_g = sp.positions(grid)[0] < 0
+    np.testing.assert_array_equal(dead_g, os_.x < 0)
+    if open_x:
+        assert dead_g.sum() > 0
 
 
 @pytest.mark.parametrize("prec", [F32, F64])
