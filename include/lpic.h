@@ -301,7 +301,8 @@ typedef enum {
   LPIC_STAGE_PUSH_POSITION_2 = 6,   /* Sec. 2.3); they fire per species, between the      */
                                     /* split gather-push and deposit calls                 */
   LPIC_STAGE_CURRENT_DEPOSITION = 7,/* after all species deposited */
-  LPIC_STAGE_QED_CREATE = 8,        /* reserved (the QED calls run outside lpic_step) */
+  LPIC_STAGE_QED_CREATE = 8,        /* after the deposit stage, where Algorithm 1 creates
+                                       photons and pairs (e.g. lpic_qed_insert, compact) */
   LPIC_STAGE_MAXWELL_2 = 9,         /* after the second field half update */
   LPIC_STAGE_LOOP_END = 10,         /* end of every step */
   LPIC_STAGE_FINISH = 11,           /* once, after the last step of a call */

@@ -1358,7 +1358,11 @@ lpic_status enqueue_step(lpic_sim* s, hipStream_t st, bool do_sort, bool spread,
                  st);
     CHK(last_launch("laser"));
   }
-  if (eager_hooks) CHK(run_hooks(s, LPIC_STAGE_CURRENT_DEPOSITION));
+  if (eager_hooks) {
+    CHK(run_hooks(s, LPIC_STAGE_CURRENT_DEPOSITION));
+    // Algorithm 1 creates photons and pairs after every species is pushed and deposited
+    CHK(run_hooks(s, LPIC_STAGE_QED_CREATE));
+  }
   if (skip_last && mid) {
     // this step's last field halves and the next step's first ones, fused
     Tables Tm = Tc;
@@ -1505,7 +1509,6 @@ void lpic_sim_destroy(lpic_sim* s) {
 lpic_status lpic_register_hook(lpic_sim* s, int32_t stage, lpic_hook_fn fn, void* user) {
   if (!s || !fn) return fail(LPIC_EINVAL, "sim or hook is NULL");
   if (stage < 0 || stage >= LPIC_NUM_STAGES) return fail(LPIC_EINVAL, "bad stage %d", stage);
-  if (stage == LPIC_STAGE_QED_CREATE) return fail(LPIC_EUNSUPPORTED, "no QED stage in this library");
   s->hooks[stage].push_back({fn, user});
   drop_graphs(s);
   return LPIC_OK;

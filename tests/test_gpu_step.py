@@ -165,8 +165,6 @@ def test_split_path_and_hook_order():
                    diag_interval=2, use_graph=True)
     seen = []
     for st in L.STAGES:
-        if st == "QED_CREATE":
-            continue
         b.register_hook(st, lambda sim, stage, step: seen.append((step, stage)))
     a.step(4)
     b.step(4)
@@ -178,7 +176,7 @@ def test_split_path_and_hook_order():
     sa, sb = a.stats(), b.stats()
     assert sa["fused"] and sa["graph"] and not sb["fused"] and not sb["graph"]
     one_step = ["LOOP_START", "MAXWELL_1", "PUSH_POSITION_1", "INTERPOLATOR", "PUSH_MOMENTUM",
-                "PUSH_POSITION_2", "CURRENT_DEPOSITION", "MAXWELL_2", "LOOP_END"]
+                "PUSH_POSITION_2", "CURRENT_DEPOSITION", "QED_CREATE", "MAXWELL_2", "LOOP_END"]
     stages = [s for _, s in seen]
     assert stages[0] == "START" and stages[-1] == "FINISH"
     assert stages[1:-1] == one_step * 4
